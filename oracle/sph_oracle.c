@@ -1,0 +1,533 @@
+/*
+ * FP64 CPU oracle for the weakly-compressible SPH step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library includes, links
+ * or calls this file; only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark do.  It shares no header, helper or constant
+ * with the GPU path: both sides only share the canonical encoded input state.
+ *
+ * What it computes, and where the paper defines it (arXiv:2207.11328):
+ *   - cell grid, cell-relative positions, Moore-neighbourhood search:
+ *       section "Optimizing the neighbors search";
+ *   - sort by cell, then particle type, then particle id:
+ *       section "Changing perspective: from the particle to the cell";
+ *   - fluid neighbours from the front of the list, boundary ones from the
+ *       back: section "Efficient split neighbors list";
+ *   - Wendland kernel w(q) = (2q+1)(1-q/2)^4, f(q) = (q-2)^3 with
+ *       F = (1/r) dW/dr: listing l:ktemplate and eq. sph-field text;
+ *   - Cole equation of state: section "A lightning introduction to the
+ *       method";
+ *   - continuity and momentum in the golden-rule form: eq. mass-cont-sph1 and
+ *       eq. ns-sph1, with the sign, mass and viscosity readings documented in
+ *       the design notes (F <= 0, so the continuity sum carries a plus sign;
+ *       the pressure term carries m_j; viscosity is Monaghan's artificial term
+ *       or the Morris laminar term of section "Minimizing complexity");
+ *   - predictor/corrector integration with dt/2 then dt: section "Code
+ *       structure" (read as the explicit midpoint scheme).
+ *
+ * Floating point: everything physical is evaluated in double.  The one
+ * exception is the neighbour predicate, which the method defines on the
+ * float32 cell-relative encoding; it is evaluated here in genuine float
+ * arithmetic (compiled with -ffp-contract=off, no fast-math, SSE float) so
+ * that neighbour sets can be compared bit-exactly.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef struct {
+    double origin[3];
+    float cs[3];
+    int32_t n[3];
+    uint32_t periodic;
+    int32_t cell_base;
+} orc_grid;
+
+typedef struct {
+    double h, r_search, rho0, gamma, c0, alpha, eps_visc, nu;
+    double g[3];
+    double cfl;
+    int32_t visc_model; /* 0 artificial (Monaghan), 1 laminar (Morris) */
+} orc_params;
+
+#define ORC_TYPE_SHIFT 30
+#define ORC_BOUNDARY 1u
+
+static inline uint32_t ptype(uint32_t info) { return info >> ORC_TYPE_SHIFT; }
+
+static inline void cell_coords(const orc_grid *g, int32_t cell, int32_t c[3])
+{
+    int32_t lc = cell - g->cell_base;
+    c[0] = lc % g->n[0];
+    c[1] = (lc / g->n[0]) % g->n[1];
+    c[2] = lc / (g->n[0] * g->n[1]);
+}
+
+static inline int32_t cell_linear(const orc_grid *g, const int32_t c[3])
+{
+    return c[0] + g->n[0] * (c[1] + g->n[1] * c[2]) + g->cell_base;
+}
+
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+#else
+    (void)t;
+#endif
+}
+
+/* ------------------------------------------------------------------------
+ * Re-binning of cell-relative offsets (float32, as the encoding is float32).
+ * Offsets live in [-cs/2, cs/2).  A particle that drifted out of its cell is
+ * moved by whole cells (at most 4 per axis); periodic axes wrap the cell
+ * index; a particle that leaves a non-periodic grid, or whose offset is not
+ * finite, becomes invalid (cell = -1).  Returns the number of invalid ones.
+ * ------------------------------------------------------------------------ */
+int orc_rebin(const orc_grid *g, int n, int32_t *cell, float *pos4)
+{
+    int dropped = 0;
+    for (int i = 0; i < n; ++i) {
+        if (cell[i] < 0) { ++dropped; continue; }
+        int32_t c[3];
+        cell_coords(g, cell[i], c);
+        int ok = 1;
+        for (int d = 0; d < 3; ++d) {
+            float o = pos4[4 * i + d];
+            const float cs = g->cs[d];
+            const float half = 0.5f * cs;
+            for (int it = 0; it < 4; ++it) {
+                if (o >= half) { o = o - cs; c[d] += 1; }
+                else if (o < -half) { o = o + cs; c[d] -= 1; }
+                else break;
+            }
+            if (!(o >= -half && o < half)) ok = 0;
+            if ((g->periodic >> d) & 1u) {
+                c[d] %= g->n[d];
+                if (c[d] < 0) c[d] += g->n[d];
+            } else if (c[d] < 0 || c[d] >= g->n[d]) {
+                ok = 0;
+            }
+            pos4[4 * i + d] = o;
+        }
+        if (ok) cell[i] = cell_linear(g, c);
+        else { cell[i] = -1; ++dropped; }
+    }
+    return dropped;
+}
+
+/* The same re-binning rule on double offsets [n][3] (double rollouts). */
+int orc_rebin_f64(const orc_grid *g, int n, int32_t *cell, double *off3)
+{
+    int dropped = 0;
+    for (int i = 0; i < n; ++i) {
+        if (cell[i] < 0) { ++dropped; continue; }
+        int32_t c[3];
+        cell_coords(g, cell[i], c);
+        int ok = 1;
+        for (int d = 0; d < 3; ++d) {
+            double o = off3[3 * (size_t)i + d];
+            const double cs = (double)g->cs[d];
+            const double half = 0.5 * cs;
+            for (int it = 0; it < 4; ++it) {
+                if (o >= half) { o = o - cs; c[d] += 1; }
+                else if (o < -half) { o = o + cs; c[d] -= 1; }
+                else break;
+            }
+            if (!(o >= -half && o < half)) ok = 0;
+            if ((g->periodic >> d) & 1u) {
+                c[d] %= g->n[d];
+                if (c[d] < 0) c[d] += g->n[d];
+            } else if (c[d] < 0 || c[d] >= g->n[d]) {
+                ok = 0;
+            }
+            off3[3 * (size_t)i + d] = o;
+        }
+        if (ok) cell[i] = cell_linear(g, c);
+        else { cell[i] = -1; ++dropped; }
+    }
+    return dropped;
+}
+
+/* ------------------------------------------------------------------------
+ * Sort order: by cell, then type, then id (the info word is type<<30 | id).
+ * Invalid particles (cell < 0) go last, in (type, id) order.
+ * ------------------------------------------------------------------------ */
+typedef struct { uint64_t key; int32_t idx; } orc_kv;
+
+static int kv_cmp(const void *a, const void *b)
+{
+    const orc_kv *x = (const orc_kv *)a, *y = (const orc_kv *)b;
+    if (x->key < y->key) return -1;
+    if (x->key > y->key) return 1;
+    return 0;
+}
+
+void orc_sort_perm(int n, const int32_t *cell, const uint32_t *info, int32_t *perm)
+{
+    orc_kv *kv = (orc_kv *)malloc(sizeof(orc_kv) * (size_t)(n > 0 ? n : 1));
+    for (int i = 0; i < n; ++i) {
+        uint32_t hi = cell[i] < 0 ? 0xFFFFFFFFu : (uint32_t)cell[i];
+        kv[i].key = ((uint64_t)hi << 32) | (uint64_t)info[i];
+        kv[i].idx = i;
+    }
+    qsort(kv, (size_t)n, sizeof(orc_kv), kv_cmp);
+    for (int i = 0; i < n; ++i) perm[i] = kv[i].idx;
+    free(kv);
+}
+
+/* Cell ranges of a sorted particle array: start = exclusive prefix sum of the
+ * per-cell counts, end = start + count.  Cells are indexed from cell_base. */
+void orc_cell_ranges(const orc_grid *g, int n, const int32_t *cell_sorted,
+                     int32_t *start, int32_t *end)
+{
+    const int nc = g->n[0] * g->n[1] * g->n[2];
+    int32_t *cnt = (int32_t *)calloc((size_t)nc, sizeof(int32_t));
+    for (int i = 0; i < n; ++i)
+        if (cell_sorted[i] >= 0) cnt[cell_sorted[i] - g->cell_base] += 1;
+    int32_t acc = 0;
+    for (int c = 0; c < nc; ++c) { start[c] = acc; acc += cnt[c]; end[c] = acc; }
+    free(cnt);
+}
+
+/* ------------------------------------------------------------------------
+ * Neighbour lists.  For a central particle i every particle j != i in the 27
+ * cells around i's cell is a neighbour iff its separation, computed from the
+ * cell-relative encoding, is below the search radius:
+ *   per axis  k = c_i - c_j (one of -1, 0, 1),  t1 = o_i - o_j,  t2 = k cs,
+ *             x = t2 + t1;      r2 = (x*x + y*y) + z*z;   keep iff r2 < rs*rs
+ * evaluated in float on the float32 encoding pos4, or (pos4 == NULL) in
+ * double on double offsets off3 (used by double-precision rollouts).  A boundary
+ * particle only keeps fluid neighbours.  Output is particle-major:
+ * fl[i*max + a] / bl[i*max + b] hold the a-th fluid / b-th boundary
+ * neighbour, nf[i] / nb[i] their counts.  Returns the number of particles
+ * whose nf + nb exceeds max (their lists are truncated).
+ * ------------------------------------------------------------------------ */
+int orc_neighbors(const orc_grid *g, float r_search, int n,
+                  const int32_t *cell, const float *pos4, const double *off3,
+                  const uint32_t *info, const int32_t *start, const int32_t *end,
+                  int max_neibs, int32_t *nf, int32_t *nb, int32_t *fl, int32_t *bl)
+{
+    const int fp64 = pos4 == NULL;
+    const float rs2f = r_search * r_search;
+    const double rs2d = (double)r_search * (double)r_search;
+    int overflow = 0;
+#pragma omp parallel for schedule(static) reduction(+ : overflow)
+    for (int i = 0; i < n; ++i) {
+        nf[i] = 0;
+        nb[i] = 0;
+        if (cell[i] < 0) continue;
+        int32_t ci[3];
+        cell_coords(g, cell[i], ci);
+        const uint32_t ti = ptype(info[i]);
+        int cf = 0, cb = 0, wf = 0, wb = 0;
+        for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+            const int off[3] = {dx, dy, dz};
+            int32_t cj[3];
+            int inside = 1;
+            for (int d = 0; d < 3; ++d) {
+                cj[d] = ci[d] + off[d];
+                if ((g->periodic >> d) & 1u) {
+                    if (cj[d] < 0) cj[d] += g->n[d];
+                    if (cj[d] >= g->n[d]) cj[d] -= g->n[d];
+                } else if (cj[d] < 0 || cj[d] >= g->n[d]) {
+                    inside = 0;
+                }
+            }
+            if (!inside) continue;
+            const int32_t lc = cell_linear(g, cj) - g->cell_base;
+            for (int j = start[lc]; j < end[lc]; ++j) {
+                if (j == i) continue;
+                const uint32_t tj = ptype(info[j]);
+                if (ti == ORC_BOUNDARY && tj == ORC_BOUNDARY) continue;
+                int keep;
+                if (!fp64) {
+                    float x[3];
+                    for (int d = 0; d < 3; ++d) {
+                        const float t1 = pos4[4 * i + d] - pos4[4 * j + d];
+                        const float t2 = (float)(-off[d]) * g->cs[d];
+                        x[d] = t2 + t1;
+                    }
+                    const float xx = x[0] * x[0];
+                    const float yy = x[1] * x[1];
+                    const float zz = x[2] * x[2];
+                    const float s = xx + yy;
+                    const float r2 = s + zz;
+                    keep = r2 < rs2f;
+                } else {
+                    double r2 = 0.0;
+                    for (int d = 0; d < 3; ++d) {
+                        const double x = (double)(-off[d]) * (double)g->cs[d]
+                                       + (off3[3 * (size_t)i + d] - off3[3 * (size_t)j + d]);
+                        r2 += x * x;
+                    }
+                    keep = r2 < rs2d;
+                }
+                if (!keep) continue;
+                if (tj == ORC_BOUNDARY) {
+                    if (wf + wb < max_neibs) bl[(size_t)i * max_neibs + wb++] = j;
+                    ++cb;
+                } else {
+                    if (wf + wb < max_neibs) fl[(size_t)i * max_neibs + wf++] = j;
+                    ++cf;
+                }
+            }
+        }
+        if (cf + cb > max_neibs) ++overflow; /* truncated: only what fitted is kept */
+        nf[i] = wf;
+        nb[i] = wb;
+    }
+    return overflow;
+}
+
+/* ------------------------------------------------------------------------
+ * Kernel and equation of state, double precision.
+ * ------------------------------------------------------------------------ */
+
+/* 3D Wendland C2 with support 2h: W = aD (1 - q/2)^4 (2q + 1), aD = 21/(16 pi h^3)
+ * (from unit integral).  F = (1/r) dW/dr = fD (q - 2)^3, fD = 105/(128 pi h^5). */
+double orc_wendland_W(double r, double h)
+{
+    const double q = r / h;
+    if (q >= 2.0) return 0.0;
+    const double a = 1.0 - 0.5 * q;
+    return 21.0 / (16.0 * M_PI * h * h * h) * a * a * a * a * (2.0 * q + 1.0);
+}
+
+double orc_wendland_F(double r, double h)
+{
+    const double q = r / h;
+    if (q >= 2.0) return 0.0;
+    const double b = q - 2.0;
+    return 105.0 / (128.0 * M_PI * h * h * h * h * h) * b * b * b;
+}
+
+/* Cole's equation of state P = B ((rho/rho0)^gamma - 1), B = rho0 c0^2 / gamma,
+ * and the sound speed c = sqrt(dP/drho) = c0 (rho/rho0)^((gamma-1)/2). */
+double orc_pressure(const orc_params *p, double rho)
+{
+    const double B = p->rho0 * p->c0 * p->c0 / p->gamma;
+    return B * (pow(rho / p->rho0, p->gamma) - 1.0);
+}
+
+double orc_sound_speed(const orc_params *p, double rho)
+{
+    return p->c0 * pow(rho / p->rho0, 0.5 * (p->gamma - 1.0));
+}
+
+/* separation x_i - x_j from the cell-relative encoding, in double */
+static inline void separation(const orc_grid *g, int32_t cell_i, int32_t cell_j,
+                              const double *oi, const double *oj, double x[3])
+{
+    int32_t ci[3], cj[3];
+    cell_coords(g, cell_i, ci);
+    cell_coords(g, cell_j, cj);
+    for (int d = 0; d < 3; ++d) {
+        int k = ci[d] - cj[d];
+        if ((g->periodic >> d) & 1u) {
+            const int nd = g->n[d];
+            while (2 * k > nd) k -= nd;
+            while (2 * k < -nd) k += nd;
+        }
+        x[d] = (double)k * (double)g->cs[d] + (oi[d] - oj[d]);
+    }
+}
+
+/* ------------------------------------------------------------------------
+ * Time derivatives (the "forces").  For central particle i and every
+ * listed neighbour j with r_ij < 2h:
+ *   Drho_i/Dt = sum_j m_j (u_ij . x_ij) F_ij
+ *   a_i       = -sum_j m_j (P_i/rho_i^2 + P_j/rho_j^2 + Pi_ij) x_ij F_ij
+ *               [+ sum_j 4 nu m_j / (rho_i + rho_j) F_ij u_ij   (laminar)]
+ *   Pi_ij     = -alpha h cbar (u_ij . x_ij) / (rhobar (r^2 + eps h^2)) if u_ij.x_ij < 0
+ * Gravity is not included (the integrator adds it to fluid particles).
+ *
+ * Also returned, per particle and component, the sum of the magnitudes of
+ * the pair terms (every signed factor replaced by its absolute value, the dot
+ * product by the sum of absolute products): the scale against which the
+ * float32 result is compared.  n_inter receives the number of (i, j) pairs
+ * with r < 2h.
+ * ------------------------------------------------------------------------ */
+void orc_forces(const orc_params *p, const orc_grid *g, int n,
+                const int32_t *cell, const double *off, const double *mass,
+                const double *vel, const double *rho, const uint32_t *info,
+                const int32_t *nf, const int32_t *nb, const int32_t *fl, const int32_t *bl,
+                int max_neibs, double *acc, double *drho, double *s_acc, double *s_drho,
+                int64_t *n_inter)
+{
+    const double h = p->h, h2 = h * h, two_h = 2.0 * h;
+    int64_t inter = 0;
+#pragma omp parallel for schedule(static) reduction(+ : inter)
+    for (int i = 0; i < n; ++i) {
+        double a[3] = {0, 0, 0}, sa[3] = {0, 0, 0}, dr = 0.0, sdr = 0.0;
+        if (cell[i] >= 0) {
+            const double rhoi = rho[i];
+            const double Pi = orc_pressure(p, rhoi);
+            const double pi = Pi / (rhoi * rhoi);
+            const double ci = orc_sound_speed(p, rhoi);
+            const int total = nf[i] + nb[i];
+            for (int k = 0; k < total; ++k) {
+                const int j = k < nf[i] ? fl[(size_t)i * max_neibs + k]
+                                        : bl[(size_t)i * max_neibs + (k - nf[i])];
+                double x[3];
+                separation(g, cell[i], cell[j], off + 3 * (size_t)i, off + 3 * (size_t)j, x);
+                const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+                const double r = sqrt(r2);
+                if (!(r < two_h)) continue;
+                ++inter;
+                const double F = orc_wendland_F(r, h);
+                const double mj = mass[j];
+                const double rhoj = rho[j];
+                const double Pj = orc_pressure(p, rhoj);
+                const double pj = Pj / (rhoj * rhoj);
+                double u[3], ux = 0.0, uxabs = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    u[d] = vel[3 * (size_t)i + d] - vel[3 * (size_t)j + d];
+                    ux += u[d] * x[d];
+                    uxabs += fabs(u[d] * x[d]);
+                }
+                dr += mj * ux * F;
+                sdr += mj * uxabs * fabs(F);
+                const double cbar = 0.5 * (ci + orc_sound_speed(p, rhoj));
+                const double rhobar = 0.5 * (rhoi + rhoj);
+                const double visc_den = rhobar * (r2 + p->eps_visc * h2);
+                double Pi_ij = 0.0;
+                if (ux < 0.0) Pi_ij = -p->alpha * h * cbar * ux / visc_den;
+                const double Pi_abs = p->alpha * h * cbar * uxabs / visc_den;
+                const double coef = -mj * (pi + pj + Pi_ij) * F;
+                const double scoef = mj * (fabs(pi) + fabs(pj) + Pi_abs) * fabs(F);
+                for (int d = 0; d < 3; ++d) {
+                    a[d] += coef * x[d];
+                    sa[d] += scoef * fabs(x[d]);
+                }
+                if (p->visc_model == 1) {
+                    const double lam = 4.0 * p->nu * mj / (rhoi + rhoj) * F;
+                    for (int d = 0; d < 3; ++d) {
+                        a[d] += lam * u[d];
+                        sa[d] += fabs(lam * u[d]);
+                    }
+                }
+            }
+        }
+        for (int d = 0; d < 3; ++d) {
+            acc[3 * (size_t)i + d] = a[d];
+            s_acc[3 * (size_t)i + d] = sa[d];
+        }
+        drho[i] = dr;
+        s_drho[i] = sdr;
+    }
+    if (n_inter) *n_inter = inter;
+}
+
+/* Number of listed pairs whose float32 squared separation (evaluated as in
+ * the neighbour predicate) is below fl32(2h)^2: the interaction count the
+ * GPU uses for its masking decision. */
+int64_t orc_count_interactions_f32(const orc_grid *g, float h, int n, const int32_t *cell,
+                                   const float *pos4, const int32_t *nf, const int32_t *nb,
+                                   const int32_t *fl, const int32_t *bl, int max_neibs)
+{
+    const float two_h = 2.0f * h;
+    const float lim = two_h * two_h;
+    int64_t cnt = 0;
+#pragma omp parallel for schedule(static) reduction(+ : cnt)
+    for (int i = 0; i < n; ++i) {
+        if (cell[i] < 0) continue;
+        int32_t ci[3];
+        cell_coords(g, cell[i], ci);
+        const int total = nf[i] + nb[i];
+        for (int k = 0; k < total; ++k) {
+            const int j = k < nf[i] ? fl[(size_t)i * max_neibs + k]
+                                    : bl[(size_t)i * max_neibs + (k - nf[i])];
+            int32_t cj[3];
+            cell_coords(g, cell[j], cj);
+            float x[3];
+            for (int d = 0; d < 3; ++d) {
+                int kd = ci[d] - cj[d];
+                if ((g->periodic >> d) & 1u) {
+                    if (kd > 1) kd -= g->n[d];
+                    if (kd < -1) kd += g->n[d];
+                }
+                const float t1 = pos4[4 * i + d] - pos4[4 * j + d];
+                const float t2 = (float)kd * g->cs[d];
+                x[d] = t2 + t1;
+            }
+            const float xx = x[0] * x[0];
+            const float yy = x[1] * x[1];
+            const float zz = x[2] * x[2];
+            const float s = xx + yy;
+            const float r2 = s + zz;
+            if (r2 < lim) ++cnt;
+        }
+    }
+    return cnt;
+}
+
+/* ------------------------------------------------------------------------
+ * Explicit midpoint predictor / corrector.
+ *   stage 0: y* = y^n + dt/2 f(y^n)
+ *   stage 1: y^{n+1} = y^n + dt f(y*)   (positions advance with u*)
+ * f = (u, a + g, Drho/Dt) for fluid; boundary particles only advance rho.
+ * vel_star is the stage-0 result (used by stage 1 only).
+ * ------------------------------------------------------------------------ */
+void orc_integrate(const orc_params *p, int stage, double dt, int n,
+                   const int32_t *cell, const uint32_t *info,
+                   const double *off_n, const double *vel_n, const double *rho_n,
+                   const double *vel_star, const double *acc, const double *drho,
+                   double *off_out, double *vel_out, double *rho_out)
+{
+    const double tau = stage == 0 ? 0.5 * dt : dt;
+    const double *uadv = stage == 0 ? vel_n : vel_star;
+    for (int i = 0; i < n; ++i) {
+        const int fluid = ptype(info[i]) != ORC_BOUNDARY && cell[i] >= 0;
+        for (int d = 0; d < 3; ++d) {
+            const size_t q = 3 * (size_t)i + d;
+            if (fluid) {
+                off_out[q] = off_n[q] + tau * uadv[q];
+                vel_out[q] = vel_n[q] + tau * (acc[q] + p->g[d]);
+            } else {
+                off_out[q] = off_n[q];
+                vel_out[q] = vel_n[q];
+            }
+        }
+        rho_out[i] = cell[i] >= 0 ? rho_n[i] + tau * drho[i] : rho_n[i];
+    }
+}
+
+/* dt = CFL min(h / max c, sqrt(h / max |a + g|) [, 0.125 h^2 / nu]) over fluid. */
+double orc_dt(const orc_params *p, int n, const int32_t *cell, const uint32_t *info,
+              const double *rho, const double *acc)
+{
+    double cmax = 0.0, amax = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (cell[i] < 0 || ptype(info[i]) == ORC_BOUNDARY) continue;
+        const double c = orc_sound_speed(p, rho[i]);
+        if (c > cmax) cmax = c;
+        double s = 0.0;
+        for (int d = 0; d < 3; ++d) {
+            const double v = acc[3 * (size_t)i + d] + p->g[d];
+            s += v * v;
+        }
+        const double a = sqrt(s);
+        if (a > amax) amax = a;
+    }
+    double dt = INFINITY;
+    if (cmax > 0.0) dt = p->h / cmax;
+    if (amax > 0.0) { const double t = sqrt(p->h / amax); if (t < dt) dt = t; }
+    if (p->nu > 0.0) { const double t = 0.125 * p->h * p->h / p->nu; if (t < dt) dt = t; }
+    return p->cfl * dt;
+}

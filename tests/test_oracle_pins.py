@@ -1,0 +1,480 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these tests compares the oracle with itself: each checks a closed
+form, an invariant, a special case or a brute-force result, chosen so that a
+plausible slip (a dropped term, a wrong sign, a transposed operand, a wrong
+constant) fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import brute as B
+from oracle import oracle as O
+from workloads import scenes as S
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _lattice_vectors(R):
+    m = int(math.ceil(R)) + 1
+    r = np.arange(-m, m + 1)
+    a, b, c = np.meshgrid(r, r, r, indexing="ij")
+    v = np.stack([a.ravel(), b.ravel(), c.ravel()], axis=1)
+    s = (v * v).sum(axis=1)
+    return v[(s > 0) & (s < R * R)]
+
+
+def _golden_table(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                rows.append([float(t) for t in line.split()])
+    return rows
+
+
+# ------------------------------------------------------------------ kernel
+@pytest.mark.parametrize("h", [0.026, 1.0, 3.7e-3])
+def test_wendland_unit_integral(h):
+    """A smoothing kernel integrates to one (section 'A lightning introduction')."""
+    val, err = integrate.quad(lambda r: 4.0 * math.pi * r * r * O.wendland_W(r, h), 0.0, 2.0 * h,
+                              epsabs=1e-14, epsrel=1e-13, limit=200)
+    assert abs(val - 1.0) < 1e-10
+
+
+@pytest.mark.parametrize("q", [0.05, 0.3, 0.7, 1.0, 1.5, 1.9])
+def test_wendland_F_is_derivative_over_r(q):
+    """F = (1/r) dW/dr, by central differences of W."""
+    h = 0.026
+    r = q * h
+    e = 1e-6 * h
+    dW = (O.wendland_W(r + e, h) - O.wendland_W(r - e, h)) / (2 * e)
+    F = O.wendland_F(r, h)
+    assert F < 0
+    assert abs(F - dW / r) <= 1e-7 * abs(F)
+
+
+def test_wendland_support_and_shape():
+    """Compact support of radius 2h, a fourfold zero at q = 2 (C2 Wendland),
+    zero slope at the origin."""
+    h = 0.5
+    for q in (2.0, 2.0 + 1e-9, 2.5, 10.0):
+        assert O.wendland_W(q * h, h) == 0.0
+        assert O.wendland_F(q * h, h) == 0.0
+    # W(2h - eps) ~ C eps^4: ratio of two samples gives the order
+    e1, e2 = 1e-2, 5e-3
+    w1 = O.wendland_W((2 - e1) * h, h)
+    w2 = O.wendland_W((2 - e2) * h, h)
+    order = math.log(w1 / w2) / math.log(e1 / e2)
+    assert abs(order - 4.0) < 1e-2
+    e = 1e-6
+    assert abs(O.wendland_W(e * h, h) - O.wendland_W(0.0, h)) < 1e-9 * O.wendland_W(0.0, h)
+
+
+# ------------------------------------------------------------------ EOS
+def test_eos_rest_and_binomial():
+    """Cole EOS: P(rho0) = 0 and P = B((1+d)^7 - 1) expanded by the binomial theorem."""
+    p = S.sph_params(0.02)
+    rho0 = O.f32(p.rho0)
+    c0 = O.f32(p.c0)
+    Bc = rho0 * c0 * c0 / 7.0
+    assert O.pressure(p, rho0) == 0.0
+    for d in (-0.03, -1e-3, 1e-5, 2e-3, 0.02, 0.1):
+        expect = Bc * sum(math.comb(7, k) * d ** k for k in range(1, 8))
+        got = O.pressure(p, rho0 * (1 + d))
+        assert abs(got - expect) <= 1e-12 * abs(expect) + 1e-9
+
+
+def test_eos_sound_speed_is_sqrt_dP_drho():
+    p = S.sph_params(0.02)
+    for rho in (980.0, 1000.0, 1013.0):
+        e = 1e-4
+        dP = (O.pressure(p, rho + e) - O.pressure(p, rho - e)) / (2 * e)
+        c = O.sound_speed(p, rho)
+        assert abs(c * c - dP) < 1e-7 * dP
+
+
+def test_eos_hydrostatic_initial_state():
+    """The generator's hydrostatic density (written independently from the
+    inverse of Cole's law) gives P = rho0 g (H - z) through the oracle's EOS."""
+    sc = S.still_water()
+    x = S.decode_positions(sc.grid, sc.cell, sc.pos[:, :3])
+    H = sc.meta["H"]
+    p = sc.params
+    rho = sc.vel[:, 3].astype(np.float64)
+    fluid = (sc.info >> 30) == 0
+    for i in np.nonzero(fluid)[0][::97]:
+        P = O.pressure(p, rho[i])
+        expect = O.f32(p.rho0) * 9.81 * (H - x[i, 2])
+        # float32 storage of rho: relative error 6e-8 of rho -> 7*B*6e-8 absolute in P
+        assert abs(P - expect) < 7 * (1000 * 400 / 7) * 1.2e-7 + 1e-6 * expect
+
+
+# ------------------------------------------------------------------ neighbour sets
+def test_golden_lattice_counts():
+    for R, count in _golden_table("lattice_counts.txt"):
+        assert len(_lattice_vectors(R)) == int(count)
+
+
+def test_lattice_neighbour_counts_periodic():
+    """Every particle of a periodic lattice lists 92 neighbours within
+    r_s = 2.86 dp and interacts with 80 within 2h = 2.6 dp."""
+    sc = S.periodic_box(n=10, dp=0.02)
+    b = O.build_f32(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info)
+    L = b["lists"]
+    rows = dict((R, int(c)) for R, c in _golden_table("lattice_counts.txt"))
+    assert np.all(L.nf == rows[2.86]) and np.all(L.nb == 0)
+    st = O.State.lift(b["cell"], b["pos"], b["vel"], b["info"])
+    _, _, _, _, ninter = O.forces(sc.grid, sc.params, st, L)
+    assert ninter == rows[2.6] * sc.n
+    assert O.count_interactions_f32(sc.grid, sc.params, b["cell"], b["pos"], L) == rows[2.6] * sc.n
+
+
+def _check_sets_vs_brute(sc, max_neibs=128):
+    b = O.build_f32(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, max_neibs)
+    L = b["lists"]
+    ref = B.neighbor_sets(sc.grid, sc.params.r_search, b["cell"], b["pos"], b["info"])
+    for i in range(sc.n):
+        f = np.sort(L.fluid(i))
+        bb = np.sort(L.boundary(i))
+        assert np.array_equal(f, ref[i][0]), i
+        assert np.array_equal(bb, ref[i][1]), i
+    return b
+
+
+@pytest.mark.parametrize("seed,periodic", [(0, 0), (1, 0b111), (2, 0b010), (3, 0b101)])
+def test_neighbour_sets_match_brute_force(seed, periodic):
+    sc = S.random_cloud(n=700, box=(0.24, 0.2, 0.18), dp=0.02, periodic=periodic, seed=seed)
+    _check_sets_vs_brute(sc)
+
+
+def test_neighbour_sets_jittered_lattice_with_walls():
+    sc = S.still_water(dp=0.05, side=0.4)
+    sc = S.shuffled(sc, seed=7)
+    _check_sets_vs_brute(sc)
+
+
+def test_neighbour_predicate_adversarial_pairs():
+    """Pairs placed at r_s (1 +/- k 2^-23) along oblique directions: the
+    cell scan and the brute force take the same float32 decision."""
+    rng = np.random.default_rng(11)
+    dp = 0.02
+    p = S.sph_params(dp, g=(0, 0, 0))
+    grid = S.make_grid((0, 0, 0), (0.6, 0.6, 0.6), p.r_search)
+    rs = float(np.float32(p.r_search))
+    xs = []
+    for k in range(60):
+        c = rng.uniform(0.15, 0.45, size=3)
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        r = rs * (1.0 + (k % 7 - 3) * 2.0 ** -23)
+        xs.append(c)
+        xs.append(c + r * d)
+    x = np.array(xs)
+    cell, off = S.encode_positions(grid, x)
+    n = x.shape[0]
+    pos = np.zeros((n, 4), np.float32)
+    pos[:, :3] = off
+    pos[:, 3] = 1.0
+    vel = np.zeros((n, 4), np.float32)
+    vel[:, 3] = 1000.0
+    info = np.arange(n, dtype=np.uint32)
+    sc = S.Scene("adv", grid, p, cell, pos, vel, info, n, 0)
+    b = _check_sets_vs_brute(sc)
+    # the double predicate may disagree only inside a narrow band around r_s
+    r2_32 = B.pair_r2(grid, b["cell"], b["pos"])
+    r2_64 = B.pair_r2(grid, b["cell"], b["pos"], fp64=True)
+    in32 = r2_32 < np.float32(np.float32(rs) * np.float32(rs))
+    in64 = r2_64 < rs * rs
+    np.fill_diagonal(in32, False)
+    np.fill_diagonal(in64, False)
+    diff = in32 != in64
+    assert np.all(np.abs(r2_64[diff] - rs * rs) < 2.0 ** -20 * rs * rs)
+
+
+def test_neighbour_sets_symmetric_and_typed():
+    sc = S.random_cloud(n=900, box=(0.2, 0.2, 0.2), dp=0.02, periodic=0b011, seed=5)
+    b = O.build_f32(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info)
+    L = b["lists"]
+    typ = b["info"] >> 30
+    pairs = set()
+    for i in range(sc.n):
+        for j in L.fluid(i):
+            assert typ[j] == 0
+            pairs.add((i, int(j)))
+        for j in L.boundary(i):
+            assert typ[j] == 1 and typ[i] == 0
+            pairs.add((i, int(j)))
+    for (i, j) in pairs:
+        assert (j, i) in pairs
+
+
+def test_list_overflow_is_reported():
+    sc = S.periodic_box(n=9, dp=0.02)
+    b = O.build_f32(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, max_neibs=50)
+    assert b["lists"].overflow == sc.n
+    assert np.all(b["lists"].nf == 50)
+
+
+# ------------------------------------------------------------------ sort / cells
+def test_sort_order_and_cell_ranges():
+    sc = S.shuffled(S.random_cloud(n=1500, box=(0.3, 0.2, 0.2), dp=0.02, seed=9), seed=3)
+    b = O.build_f32(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info)
+    perm = b["perm"]
+    assert np.array_equal(np.sort(perm), np.arange(sc.n))
+    key = (b["cell"].astype(np.int64) << 32) | b["info"].astype(np.int64)
+    assert np.all(np.diff(key) > 0)
+    cover = np.zeros(sc.n, dtype=np.int32)
+    for c in range(sc.grid.n_cells):
+        s, e = b["start"][c], b["end"][c]
+        assert np.all(b["cell"][s:e] == c)
+        cover[s:e] += 1
+    assert np.all(cover == 1)
+
+
+def test_rebin_moves_offsets_back_into_cells_and_drops_escapees():
+    sc = S.random_cloud(n=300, box=(0.2, 0.2, 0.2), dp=0.02, seed=4)
+    x0 = S.decode_positions(sc.grid, sc.cell, sc.pos[:, :3])
+    rng = np.random.default_rng(1)
+    pos = sc.pos.copy()
+    pos[:, :3] += rng.uniform(-0.06, 0.06, size=(sc.n, 3)).astype(np.float32)
+    xm = S.decode_positions(sc.grid, sc.cell, pos[:, :3])
+    cell, pos2, dropped = O.rebin_f32(sc.grid, sc.cell, pos)
+    ok = cell >= 0
+    cs = sc.grid.cell_size
+    assert np.all(np.abs(pos2[ok, :3]) <= cs[None, :] / 2)
+    x1 = S.decode_positions(sc.grid, cell[ok], pos2[ok, :3])
+    assert np.allclose(x1, xm[ok], atol=1e-7)
+    outside = np.any((xm < 0) | (xm >= (sc.grid.ncell * cs)[None, :]), axis=1)
+    assert dropped == int(outside.sum()) and np.array_equal(~ok, outside)
+    del x0
+
+
+# ------------------------------------------------------------------ forces
+def _forces(sc):
+    b = O.build_f32(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info)
+    st = O.State.lift(b["cell"], b["pos"], b["vel"], b["info"])
+    acc, drho, sa, sd, ni = O.forces(sc.grid, sc.params, st, b["lists"])
+    return b, st, acc, drho, sa, sd, ni
+
+
+@pytest.mark.parametrize("visc", [0, 1])
+def test_momentum_antisymmetry(visc):
+    """Pair forces are antisymmetric: sum_i m_i a_i = 0 (fluid-boundary pairs
+    counted from both sides, boundary-boundary pairs from neither)."""
+    sc = S.random_cloud(n=1200, box=(0.25, 0.2, 0.2), dp=0.02, seed=21, boundary_frac=0.3,
+                        visc_model=visc, nu=1e-3)
+    b, st, acc, drho, sa, sd, ni = _forces(sc)
+    m = st.mass[:, None]
+    tot = np.abs((m * acc).sum(axis=0))
+    scale = (m * sa).sum(axis=0)
+    assert np.all(tot <= 1e-13 * scale)
+    assert ni > 10 * sc.n
+
+
+def test_angular_momentum_of_central_forces():
+    """Pressure and artificial viscosity act along x_ij: sum m x x a = 0."""
+    sc = S.random_cloud(n=1000, box=(0.2, 0.2, 0.2), dp=0.02, seed=22, boundary_frac=0.2)
+    b, st, acc, drho, sa, sd, ni = _forces(sc)
+    x = O.positions(sc.grid, st)
+    L = (st.mass[:, None] * np.cross(x, acc)).sum(axis=0)
+    scale = (st.mass * np.linalg.norm(x, axis=1) * np.linalg.norm(sa, axis=1)).sum()
+    assert np.all(np.abs(L) <= 1e-13 * scale)
+
+
+@pytest.mark.parametrize("visc", [0, 1])
+def test_viscous_dissipation(visc):
+    """With pressure off (uniform rest density), viscosity never adds kinetic
+    energy: sum_i m_i u_i . a_i <= 0, and it is strictly negative here."""
+    sc = S.random_cloud(n=1000, box=(0.2, 0.2, 0.2), dp=0.02, seed=23, boundary_frac=0.2,
+                        rho_sigma=0.0, u_sigma=0.1, visc_model=visc, nu=1e-2, alpha=0.1)
+    sc.vel[:, 3] = np.float32(1000.0)
+    b, st, acc, drho, sa, sd, ni = _forces(sc)
+    power = (st.mass[:, None] * st.vel * acc).sum()
+    assert power < 0
+    assert abs(power) > 1e-6 * (st.mass[:, None] * np.abs(st.vel) * sa).sum()
+
+
+def test_compression_raises_density():
+    """u = -eps x (uniform compression): every particle with neighbours has
+    Drho/Dt > 0 (fixes the sign of the continuity sum)."""
+    dp = 0.02
+    p = S.sph_params(dp, g=(0, 0, 0))
+    xf = S.lattice(9, 8, 7, dp, lo=(0.1, 0.1, 0.1))
+    grid = S.make_grid((0, 0, 0), (0.4, 0.4, 0.4), p.r_search)
+    centre = xf.mean(axis=0)
+    sc = S._assemble("block", grid, p, xf, np.zeros((0, 3)), H=0.0, vel_f=-0.1 * (xf - centre))
+    b, st, acc, drho, sa, sd, ni = _forces(sc)
+    assert np.all(b["lists"].nf > 0)
+    assert np.all(drho > 0)
+    # and expansion lowers it
+    sc.vel[:, :3] *= -1
+    b, st, acc, drho, sa, sd, ni = _forces(sc)
+    assert np.all(drho < 0)
+
+
+def test_uniform_periodic_lattice_is_at_rest():
+    """Uniform density and uniform velocity on a complete periodic lattice:
+    zero acceleration (by symmetry) and zero density rate (u_ij = 0)."""
+    sc = S.periodic_box(n=9, dp=0.02)
+    sc.vel[:, :3] = np.float32([0.3, -0.2, 0.1])
+    sc.vel[:, 3] = np.float32(1010.0)
+    b, st, acc, drho, sa, sd, ni = _forces(sc)
+    # the float32 cell-relative encoding perturbs the lattice by ~1e-8 relative
+    assert np.all(np.abs(acc) <= 1e-6 * sa)
+    assert np.all(drho == 0.0)
+
+
+def test_small_g_hydrostatic_lattice():
+    """Still water at small g: a bulk particle's SPH acceleration equals
+    -M_zz g, where M_zz = sum_j dp^3 x_z^2 F_ij is the lattice second moment
+    of the kernel gradient (-> -1 in the continuum).  This pins the pressure
+    gradient term: its mass factor, sign and the P_i/rho_i^2 + P_j/rho_j^2 form."""
+    dp = 0.02
+    g = 1e-3
+    sc = S.still_water(dp=dp, side=0.4, g=(0.0, 0.0, -g))
+    h = O.f32(sc.params.h)
+    v = _lattice_vectors(2.6) * dp
+    r = np.linalg.norm(v, axis=1)
+    Mzz = sum(dp ** 3 * v[k, 2] ** 2 * O.wendland_F(r[k], h) for k in range(len(v)))
+    assert abs(Mzz - (-0.978896)) < 2e-6
+    b = O.build_f32(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info)
+    st = O.State.lift(b["cell"], b["pos"], b["vel"], b["info"])
+    x = O.positions(sc.grid, st)
+    H = sc.meta["H"]
+    # the density signal rho0 g dp / B ~ 3e-7 is below float32 resolution:
+    # take the hydrostatic density in double for this pin
+    st.rho = S.hydrostatic_density(x[:, 2], H, sc.params)
+    acc, drho, sa, sd, ni = O.forces(sc.grid, sc.params, st, b["lists"])
+    bulk = st.is_fluid & (x[:, 2] > 3 * h) & (x[:, 2] < H - 3 * h)
+    assert bulk.sum() > 1000
+    az = acc[bulk, 2]
+    assert np.all(np.abs(az / g - (-Mzz)) < 1e-3)
+    assert np.all(np.abs(acc[bulk, :2]) < 1e-5 * g)
+
+
+@pytest.mark.parametrize("visc,lam", [(0, 2.0), (0, 0.25), (1, 4.0)])
+def test_change_of_length_unit(visc, lam):
+    """Dimensional consistency: measuring lengths in a unit lam times smaller
+    (positions, h, r_s, cell sizes, u, c0, g scale by lam, masses by lam^3,
+    nu by lam^2) multiplies accelerations by lam and leaves Drho/Dt unchanged.
+    lam is a power of two, so the float32 encoding scales exactly."""
+    sc = S.random_cloud(n=800, box=(0.2, 0.2, 0.2), dp=0.02, seed=31, boundary_frac=0.25,
+                        u_sigma=0.2, rho_sigma=0.01, visc_model=visc, nu=2e-3, alpha=0.3)
+    b, st, acc, drho, sa, sd, ni = _forces(sc)
+    import copy
+    g2 = copy.deepcopy(sc.grid)
+    g2.origin = sc.grid.origin * lam
+    g2.cell_size = (sc.grid.cell_size * np.float32(lam)).astype(np.float32)
+    p2 = copy.deepcopy(sc.params)
+    p2.h, p2.r_search, p2.c0 = sc.params.h * lam, sc.params.r_search * lam, sc.params.c0 * lam
+    p2.g = tuple(v * lam for v in sc.params.g)
+    p2.nu = sc.params.nu * lam * lam
+    assert O.f32(p2.h) == O.f32(sc.params.h) * lam
+    st2 = st.copy()
+    st2.off = st.off * lam
+    st2.vel = st.vel * lam
+    st2.mass = st.mass * lam ** 3
+    acc2, drho2, sa2, sd2, ni2 = O.forces(g2, p2, st2, b["lists"])
+    assert ni2 == ni
+    assert np.all(np.abs(acc2 - lam * acc) <= 1e-12 * lam * sa)
+    assert np.all(np.abs(drho2 - drho) <= 1e-12 * sd)
+
+
+# ------------------------------------------------------------------ integrator
+def test_free_fall_is_exact():
+    """An isolated particle under constant g: midpoint predictor/corrector is
+    exact for constant acceleration, x = x0 + u0 t + g t^2/2, u = u0 + g t."""
+    p = S.sph_params(0.02, g=(0.1, -0.2, -9.81))
+    grid = S.make_grid((0, 0, 0), (1, 1, 1), p.r_search)
+    x0 = np.array([[0.5, 0.5, 0.5]])
+    cell, off = S.encode_positions(grid, x0)
+    u0 = np.array([[0.3, 0.0, 1.0]])
+    st = O.State(cell, off.astype(np.float64), np.ones(1), u0, np.full(1, 1000.0), np.zeros(1, np.uint32))
+    lists = O.Lists(np.zeros(1, np.int32), np.zeros(1, np.int32), np.zeros((1, 4), np.int32),
+                    np.zeros((1, 4), np.int32), 4, 0)
+    t = 0.0
+    gv = np.array([O.f32(v) for v in p.g])
+    for k in range(25):
+        st, h = O.step(grid, p, st, lists, dt_fixed=1e-3 * (1 + 0.1 * k))
+        t += h
+    xe = x0 + u0 * t + 0.5 * gv[None, :] * t * t
+    ue = u0 + gv[None, :] * t
+    assert np.allclose(O.positions(grid, st), xe, atol=1e-14, rtol=0)
+    assert np.allclose(st.vel, ue, atol=1e-14, rtol=0)
+
+
+def test_boundary_particles_only_advance_density():
+    sc = S.still_water(dp=0.05, side=0.4)
+    b, st, acc, drho, sa, sd, ni = _forces(sc)
+    acc2 = acc + 1.0
+    for stage in (0, 1):
+        out = O.integrate(sc.params, stage, 1e-3, st, acc2, drho + 3.0, vel_star=st.vel + 1.0)
+        bd = ~st.is_fluid
+        assert np.array_equal(out.off[bd], st.off[bd]) and np.array_equal(out.vel[bd], st.vel[bd])
+        tau = 0.5e-3 if stage == 0 else 1e-3
+        assert np.allclose(out.rho - st.rho, tau * (drho + 3.0), rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------------------ rollout invariants
+@pytest.mark.slow
+def test_still_water_rollout_invariants():
+    """Still-water tank, 100 predictor/corrector steps, rebuild every 10:
+    particle count and mass exact, |rho/rho0 - 1| < 2%, and the layer
+    pressure within 10% of rho0 g (H - z) away from floor and surface.  The
+    lattice start is not in discrete equilibrium (the lattice pressure
+    gradient is 2.1% short, see the small-g pin), so the column rings
+    acoustically with a period of about 0.1 s and a pressure amplitude of
+    about 5%: a tighter band at one instant would test the transient."""
+    sc = S.still_water()
+    st = O.State.lift(sc.cell, sc.pos, sc.vel, sc.info)
+    m0 = st.mass.sum()
+    st, t = O.rollout(sc.grid, sc.params, st, 100, rebuild_every=10)
+    assert st.n == sc.n and np.all(st.cell >= 0)
+    assert st.mass.sum() == m0
+    rho0 = O.f32(sc.params.rho0)
+    assert np.abs(st.rho / rho0 - 1).max() < 0.02
+    x = O.positions(sc.grid, st)
+    H = sc.meta["H"]
+    h = O.f32(sc.params.h)
+    f = st.is_fluid
+    P = np.array([O.pressure(sc.params, r) for r in st.rho])
+    z = x[:, 2]
+    layers = np.round((z[f] - 0.01) / 0.02).astype(int)
+    for lay in np.unique(layers):
+        zc = 0.01 + 0.02 * lay
+        if not (3 * h < zc < H - 3 * h):
+            continue
+        sel = layers == lay
+        Pm = P[f][sel].mean()
+        expect = rho0 * 9.81 * (H - zc)
+        assert abs(Pm - expect) < 0.10 * expect, (lay, Pm, expect)
+    assert t > 0
+
+
+def test_momentum_conserved_in_periodic_rollout():
+    """No gravity, no walls: total momentum is conserved to round-off."""
+    sc = S.periodic_box(n=9, dp=0.02, jitter=0.1, u_sigma=0.05, rho_sigma=0.002, seed=3)
+    st = O.State.lift(sc.cell, sc.pos, sc.vel, sc.info)
+    P0 = (st.mass[:, None] * st.vel).sum(axis=0)
+    st, t = O.rollout(sc.grid, sc.params, st, 20, rebuild_every=10)
+    P1 = (st.mass[:, None] * st.vel).sum(axis=0)
+    scale = (st.mass[:, None] * np.abs(st.vel)).sum(axis=0)
+    assert np.all(np.abs(P1 - P0) < 1e-12 * scale.max())
+
+
+def test_dam_break_geometry_golden():
+    (row,) = _golden_table("dam_break_geometry.txt")
+    dp, cx, cy, cz, nf = row
+    sc = S.dam_break(dp=dp, box=(1.6, 0.67, 0.6), column=(cx, cy, cz))
+    # the column spans the full tank width in the generator; count the paper's 52 dp width
+    nx = int(math.floor(cx / dp + 1e-9))
+    ny = int(math.floor(cy / dp + 1e-9))
+    nz = int(math.floor(cz / dp + 1e-9))
+    assert nx * ny * nz == int(nf)
+    assert sc.n_fluid == nx * int(math.floor(0.67 / dp + 1e-9)) * nz
