@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the WCSPH step on one MI355X.
+
+Workload: the 3D dam break of ~1M fluid particles (1.6 x 0.67 x 0.6 m box,
+0.4 x 0.67 x 0.3 m water column, dp = 4.3 mm, 994,635 fluid + 627,096 wall
+particles), Wendland kernel h = 1.3 dp, Cole EOS, artificial viscosity
+alpha = 0.01, CFL 0.3, lists rebuilt every 10 steps.  Synthetic, seeded
+lattice input; nothing is read from disk.
+
+One step = one predictor/corrector step of the hot path: neighbour search
+(every 10th step), derivatives twice, device dt, integrator twice.  The
+metric is particle interactions evaluated by sph_forces per second of whole
+step time (interactions = listed pairs with r < 2h, counted exactly by
+replaying the same deterministic trajectory with sph_count_interactions).
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz, one fp32 op per lane per cycle
+# (packed fp32 excluded): 39.3e12 lane-ops/s.
+VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="dam_break_1m", choices=["dam_break_1m", "dam_break_64k", "still_water_8k"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def make_scene(name):
+    from workloads import scenes as S
+    return S.CONFIGS[name]()
+
+
+def cpu_baseline(sc, budget_s):
+    """The FP64 oracle's derivative evaluation on the host cores, on the same
+    step-0 state: time repeated calls until the budget is used."""
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    ob = O.build_f32(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info)
+    t_build = time.perf_counter() - t0
+    st = O.State.lift(ob["cell"], ob["pos"], ob["vel"], ob["info"])
+    calls, inter, spent = 0, 0, 0.0
+    while spent < budget_s or calls == 0:
+        t0 = time.perf_counter()
+        _, _, _, _, ni = O.forces(sc.grid, sc.params, st, ob["lists"])
+        spent += time.perf_counter() - t0
+        inter += ni
+        calls += 1
+    return {
+        "value": inter / spent,
+        "unit": "interactions/s",
+        "cores": O.threads(),
+        "kind": "oracle",
+        "sample": "%d FP64 oracle derivative call(s) on the full step-0 state (%d particles, %d interactions "
+                  "per call; oracle list build %.1f s not included)" % (calls, sc.n, inter // calls, t_build),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the step shards by slabs of "
+              "cells with halo exchange, which is not implemented); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2207_11328_amd.sim import Simulation
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    sc = make_scene(args.workload)
+    K, W = args.steps, args.warmup
+
+    def new_sim():
+        return Simulation(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0")
+
+    sim = new_sim()
+    for _ in range(W):
+        sim.step()
+    torch.cuda.synchronize()
+    sim.check_status()
+
+    ev = []  # (start, end) around each sph_forces launch
+    t_forces_events = []
+
+    def timed_step():
+        rebuild = sim.steps_done % sim.rebuild_every == 0
+        if rebuild:
+            sim.build()
+        for star in (False, True):
+            if star:
+                sim.integrate(0)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            sim.forces(star)
+            b.record()
+            ev.append((a, b))
+            if not star and sim.dt_fixed is None:
+                sim.step_dt()
+        sim.integrate(1)
+        sim.steps_done += 1
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        timed_step()
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    for a, b in ev:
+        t_forces_events.append(a.elapsed_time(b) * 1e-3)
+    sim.check_status()
+
+    # replay the same deterministic trajectory to count interactions per call
+    rep = new_sim()
+    for _ in range(W):
+        rep.step()
+    inter = 0
+    listed = 0
+    for _ in range(K):
+        if rep.steps_done % rep.rebuild_every == 0:
+            rep.build()
+        for star in (False, True):
+            if star:
+                rep.integrate(0)
+            rep.forces(star)
+            parts_n = rep.parts_star if star else rep.parts
+            from paper_2207_11328_amd import abi
+            abi.sph_count_interactions(rep.g, rep.p, parts_n, rep.neibs, rep.neib_count, rep.max_neibs, rep.count)
+            inter += int(rep.count.item())
+            if not star:
+                rep.step_dt()
+        cnt = rep.neib_count[: rep.n]
+        listed += 2 * int(((cnt & 0xFFFF) + (cnt >> 16)).sum().item())
+        rep.integrate(1)
+        rep.steps_done += 1
+    torch.cuda.synchronize()
+    same = torch.equal(rep.pos, sim.pos) and torch.equal(rep.vel, sim.vel)
+
+    n = sc.n
+    calls = len(t_forces_events)
+    t_forces = float(np.sum(t_forces_events))
+    t_forces_avg = t_forces / calls
+    # algorithmic bytes of one sph_forces launch: pos, vel (16 B each), count
+    # (4 B), the listed entries (4 B each) and the float4 output per particle
+    bytes_per_launch = n * (16 + 16 + 4 + 16) + 4 * (listed / calls)
+    achieved_gbs = bytes_per_launch / t_forces_avg / 1e9
+    ms_per_step = t_total / K * 1e3
+    value = inter / t_total
+    out = {
+        "metric": "particle-interactions/s in sph_forces; fwd+bwd steps/s vs plain fwd at 1e-5 rel err",
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "dam_break_%s" % ("1m" if args.workload == "dam_break_1m" else args.workload),
+            "particles": n, "fluid": sc.n_fluid, "boundary": sc.n_boundary,
+            "dp": sc.params.dp, "h_over_dp": 1.3, "max_neibs": sim.max_neibs, "rebuild_every": sim.rebuild_every,
+        },
+        "forces_interactions_per_s": inter / t_forces,
+        "forces_ms_avg": t_forces_avg * 1e3,
+        "interactions_per_forces_call": inter / calls,
+        "listed_per_forces_call": listed / calls,
+        "steps_per_s": K / t_total,
+        "replay_bitwise_identical": bool(same),
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved_gbs,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved_gbs / HBM_PEAK_GBS,
+            "traffic": None,
+            "kernel": "k_forces (sph_forces)",
+            "bytes_per_launch": bytes_per_launch,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,217 @@
+/*
+ * sph.h — C ABI of the MI355X weakly-compressible SPH step library (libsph.so).
+ *
+ * The library implements the step that dominates a WCSPH run, as stated in
+ * arXiv:2207.11328 (section "From theory to implementation"): a neighbour
+ * search (re-bin, sort by cell, cell ranges, per-particle neighbour list), the
+ * time derivatives ("forces": continuity, Cole equation of state, golden-rule
+ * pressure gradient plus artificial or laminar viscosity, Wendland kernel) and
+ * a predictor/corrector integrator; plus the adjoint of the derivatives.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All particle arrays, lists and scalars marked "device" are device
+ *   pointers on the current HIP device; the caller allocates and owns them.
+ *   The library never allocates on these paths and keeps no state between
+ *   calls.
+ * - `stream` is a hipStream_t passed as void*; NULL means the default
+ *   stream.  Every call only enqueues work on that stream (asynchronous);
+ *   calls on distinct streams with distinct buffers may overlap.
+ * - Argument and shape errors are reported synchronously by the return code
+ *   and nothing is launched.  Conditions discovered on the device (neighbour
+ *   overflow, particles leaving the grid) are written to a device status
+ *   word and are visible after the caller synchronises the stream.  No call
+ *   aborts or throws.
+ * - Particle state is structure-of-arrays (section "From theory to
+ *   implementation"): positions are cell-relative (section "Optimizing the
+ *   neighbors search"): a linear cell index plus a float32 offset from the
+ *   cell centre, so float32 keeps uniform accuracy over large domains.
+ *     cell[i]  int32  cx + ncell[0]*(cy + ncell[1]*cz) + cell_base; -1 after
+ *                     a build for a particle that left the grid
+ *     pos[i]   float4 xyz: offset from the cell centre [m], w: mass [kg]
+ *     vel[i]   float4 xyz: velocity [m/s], w: density [kg/m^3]
+ *     info[i]  uint32 type << 30 | id; type 0 = fluid, 1 = fixed ("dynamic")
+ *                     boundary particle; ids unique
+ * - After sph_build_neighbors the particles are stored sorted by
+ *   (cell, type, id), and neighbour indices refer to that order.
+ *
+ * Neighbour list (sections "Efficient split neighbors list" and
+ * "Changing perspective: from the particle to the cell")
+ * -----------------------------------------------------
+ * Fixed size, `max_neibs` slots per particle, neighbour-major: slot k of
+ * particle i is neibs[k * capacity + i].  Fluid neighbours fill slots
+ * 0, 1, ... upwards, boundary neighbours fill max_neibs-1, max_neibs-2, ...
+ * downwards.  neib_count[i] = n_fluid | n_boundary << 16 replaces the paper's
+ * end-of-list marker.  A boundary particle lists fluid neighbours only.  Each
+ * entry packs the neighbour's sorted index j (bits 0..25, so capacity is at
+ * most 2^26) and the cell difference k_d = c_i,d - c_j,d + 1 in {0, 1, 2} of
+ * each axis d (bits 26+2d .. 27+2d), periodic images already resolved.  The
+ * separation is then x_ij = (k - 1) * cell_size + (o_i - o_j).
+ *
+ * A pair is listed iff, in float32 with every operation rounded,
+ *   x_d = (k_d * cs_d) + (o_i,d - o_j,d),   r2 = (x*x + y*y) + z*z,
+ *   r2 < r_search * r_search.
+ */
+#ifndef SPH_H
+#define SPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SPH_OK = 0,
+    SPH_ERR_ARG = 1,        /* invalid argument or shape; nothing launched */
+    SPH_ERR_WORKSPACE = 2,  /* workspace missing or smaller than required */
+    SPH_ERR_HIP = 3         /* a HIP runtime call or launch failed */
+} sph_status;
+
+/* Device status word written by sph_build_neighbors: int32[4]. */
+enum {
+    SPH_STATUS_N_ACTIVE = 0,   /* particles inside the grid (sorted first)  */
+    SPH_STATUS_MAX_NEIBS = 1,  /* largest n_fluid + n_boundary found        */
+    SPH_STATUS_OVERFLOW = 2,   /* particles whose list did not fit          */
+    SPH_STATUS_DROPPED = 3     /* particles that left the grid (sorted last) */
+};
+
+#define SPH_NEIB_INDEX_BITS 26
+#define SPH_MAX_CAPACITY (1 << SPH_NEIB_INDEX_BITS)
+
+/* One scene's uniform cell grid (section "Optimizing the neighbors search"):
+ * origin, extents and spacing.  cell_size[d] must be >= r_search; a
+ * periodic axis (bit d of `periodic`) has ncell[d] >= 3 and period
+ * ncell[d] * cell_size[d]. */
+typedef struct {
+    double origin[3];
+    float cell_size[3];
+    int32_t ncell[3];
+    uint32_t periodic;
+    int32_t cell_base;
+} sph_grid;
+
+/* Physical and numerical parameters.
+ *   h          smoothing length; the Wendland kernel has support 2h
+ *   r_search   neighbour search radius (>= 2h; the excess is the skin that
+ *              lets the list be reused for several steps)
+ *   rho0, gamma, c0   Cole equation of state P = B((rho/rho0)^gamma - 1),
+ *              B = rho0 c0^2 / gamma (gamma = 7 only)
+ *   alpha, eps_visc   Monaghan artificial viscosity
+ *              Pi_ij = -alpha h cbar (u_ij.x_ij) / (rhobar (r^2 + eps h^2))
+ *              for approaching pairs (visc_model 0)
+ *   nu         kinematic viscosity of the Morris laminar term
+ *              sum_j 4 nu m_j / (rho_i + rho_j) F_ij u_ij (visc_model 1)
+ *   g          body acceleration added to fluid particles by the integrator
+ *   cfl        time-step safety factor */
+typedef struct {
+    float h, r_search, rho0, gamma, c0, alpha, eps_visc, nu;
+    float g[3];
+    float cfl;
+    int32_t visc_model;
+} sph_params;
+
+/* Particle arrays (device pointers), see the conventions above. */
+typedef struct {
+    int32_t n;          /* particles stored */
+    int32_t capacity;   /* allocated length of every per-particle array */
+    int32_t *cell;
+    float *pos;         /* [capacity][4] */
+    float *vel;         /* [capacity][4] */
+    uint32_t *info;
+} sph_particles;
+
+/* Human-readable name of a status code (static storage). */
+const char *sph_status_string(sph_status s);
+
+/* ABI revision of this header (incremented on incompatible changes). */
+int32_t sph_abi_version(void);
+
+/* Bytes of device workspace sph_build_neighbors needs. */
+size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells);
+
+/* Neighbour search (sections "Optimizing the neighbors search", "Efficient
+ * split neighbors list", "Changing perspective: from the particle to the
+ * cell"): in one call on `stream`,
+ *   1. re-bin: offsets that drifted out of [-cs/2, cs/2) move by whole cells
+ *      (at most 4 per axis, float32, periodic axes wrap); particles leaving
+ *      the grid or with non-finite offsets get cell = -1;
+ *   2. sort particles by (cell, type, id), dropped ones last, and reorder
+ *      cell/pos/vel/info in place (parts is in/out; parts->n is unchanged);
+ *   3. cell ranges: particles of linear cell c (relative to cell_base) are
+ *      [cell_start[c], cell_end[c]) (device int32[n_cells] each);
+ *   4. build the split neighbour list described above into
+ *      neibs (device uint32[max_neibs * capacity]) and
+ *      neib_count (device uint32[capacity]); dropped particles get count 0;
+ *   5. d_status (device int32[4], see SPH_STATUS_*) is overwritten.
+ * A particle whose neighbours exceed max_neibs keeps the first max_neibs
+ * found (scan order: cells z, y, x outer to inner, then sorted index) and is
+ * counted in SPH_STATUS_OVERFLOW; the lists are then unusable for physics.
+ * workspace: device buffer of at least sph_build_workspace_bytes bytes.
+ * Errors: SPH_ERR_ARG for null pointers, n > capacity, capacity > 2^26,
+ * max_neibs outside [1, 65535], bad grid; SPH_ERR_WORKSPACE. */
+sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
+                               sph_particles *parts, uint32_t *neibs, uint32_t *neib_count,
+                               int32_t max_neibs, int32_t *cell_start, int32_t *cell_end,
+                               int32_t *d_status, void *workspace, size_t workspace_bytes,
+                               void *stream);
+
+/* Time derivatives (eq. mass-cont-sph1 and eq. ns-sph1 with the readings of
+ * the design notes; Wendland kernel of listing l:ktemplate).  For every
+ * particle i < parts->n and every listed neighbour j with r_ij < 2h:
+ *   Drho_i/Dt = sum_j m_j (u_ij . x_ij) F_ij
+ *   a_i = -sum_j m_j (P_i/rho_i^2 + P_j/rho_j^2 + Pi_ij) x_ij F_ij
+ *         [+ sum_j 4 nu m_j/(rho_i + rho_j) F_ij u_ij  for visc_model 1]
+ * with F = (105 / (128 pi h^5)) (q - 2)^3, q = r/h.  Gravity is excluded.
+ * forces: device float[capacity][4], xyz = a_i [m/s^2], w = Drho_i/Dt,
+ * fully overwritten for i < n.  Particles are read in the order of the last
+ * build; positions may have drifted since (lists are reused).
+ * Errors: SPH_ERR_ARG. */
+sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
+                      const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
+                      float *forces, void *stream);
+
+/* Explicit midpoint predictor/corrector (section "Code structure": phases
+ * with dt/2 and dt).  d_dt: device double, the step.
+ *   stage 0: out = state_n + dt/2 * (u_n, a_n + g, Drho_n)
+ *   stage 1: out = state_n + dt   * (u*,  a*  + g, Drho*), vel_star = u*
+ *            (device float[capacity][4], the stage-0 velocities); if
+ *            d_time is not NULL the corrector adds dt to it (device double).
+ * Offsets advance with the velocity; boundary particles only advance
+ * density; dropped particles (cell < 0) are left unchanged.  `out` may
+ * alias `state_n` (elementwise update).  Only out->pos and out->vel are
+ * written; cell and info are read from state_n.
+ * Errors: SPH_ERR_ARG. */
+sph_status sph_integrate(const sph_params *params, int32_t stage, const double *d_dt,
+                         const sph_particles *state_n, const float *vel_star,
+                         const float *forces, sph_particles *out, double *d_time,
+                         void *stream);
+
+/* Bytes of device workspace sph_step_dt needs. */
+size_t sph_dt_workspace_bytes(void);
+
+/* Adaptive time step kept on the device (section "The GPU in GPUSPH": the
+ * step is a device reduction):
+ *   dt = cfl * min(h / max c_i, sqrt(h / max |a_i + g|) [, 0.125 h^2 / nu])
+ * over fluid particles i < n with cell >= 0, c_i the sound speed at rho_i,
+ * evaluated in double from float32 maxima and written to d_dt (device
+ * double).  forces: the derivatives of this state.
+ * Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
+sph_status sph_step_dt(const sph_params *params, const sph_particles *parts, const float *forces,
+                       double *d_dt, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Number of listed pairs (i, j), i < n, whose float32 squared separation
+ * (evaluated as in the neighbour predicate) is below (2h)^2 in float32:
+ * the interactions sph_forces evaluates.  d_count: device uint64,
+ * overwritten.  Errors: SPH_ERR_ARG. */
+sph_status sph_count_interactions(const sph_grid *grid, const sph_params *params,
+                                  const sph_particles *parts, const uint32_t *neibs,
+                                  const uint32_t *neib_count, int32_t max_neibs,
+                                  unsigned long long *d_count, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPH_H */

@@ -1,0 +1,167 @@
+"""ctypes binding of libsph.so (argument marshalling only).
+
+Every entry point of include/sph.h is exposed under the same name.  Device
+buffers are torch tensors (PyTorch is used for device memory and streams);
+this module only turns them into raw pointers and forwards the call.  There is
+no fallback: if the HIP library is missing or fails to load, importing this
+module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsph.so")
+
+SPH_OK, SPH_ERR_ARG, SPH_ERR_WORKSPACE, SPH_ERR_HIP = 0, 1, 2, 3
+STATUS_N_ACTIVE, STATUS_MAX_NEIBS, STATUS_OVERFLOW, STATUS_DROPPED = 0, 1, 2, 3
+NEIB_INDEX_BITS = 26
+MAX_CAPACITY = 1 << NEIB_INDEX_BITS
+
+EXPORTS = [
+    "sph_status_string", "sph_abi_version", "sph_build_workspace_bytes", "sph_build_neighbors",
+    "sph_forces", "sph_integrate", "sph_dt_workspace_bytes", "sph_step_dt", "sph_count_interactions",
+]
+
+
+class SphGrid(C.Structure):
+    _fields_ = [("origin", C.c_double * 3), ("cell_size", C.c_float * 3), ("ncell", C.c_int32 * 3),
+                ("periodic", C.c_uint32), ("cell_base", C.c_int32)]
+
+
+class SphParams(C.Structure):
+    _fields_ = [("h", C.c_float), ("r_search", C.c_float), ("rho0", C.c_float), ("gamma", C.c_float),
+                ("c0", C.c_float), ("alpha", C.c_float), ("eps_visc", C.c_float), ("nu", C.c_float),
+                ("g", C.c_float * 3), ("cfl", C.c_float), ("visc_model", C.c_int32)]
+
+
+class SphParticles(C.Structure):
+    _fields_ = [("n", C.c_int32), ("capacity", C.c_int32), ("cell", C.c_void_p), ("pos", C.c_void_p),
+                ("vel", C.c_void_p), ("info", C.c_void_p)]
+
+
+class SphError(RuntimeError):
+    pass
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libsph.so is not built (%s): run `python -m paper_2207_11328_amd.build`" % LIB_PATH)
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    i32 = C.c_int32
+    st = C.c_int
+    L.sph_status_string.argtypes = [st]
+    L.sph_status_string.restype = C.c_char_p
+    L.sph_abi_version.argtypes = []
+    L.sph_abi_version.restype = i32
+    L.sph_build_workspace_bytes.argtypes = [i32, i32]
+    L.sph_build_workspace_bytes.restype = C.c_size_t
+    L.sph_build_neighbors.argtypes = [P, P, P, P, P, i32, P, P, P, P, C.c_size_t, P]
+    L.sph_build_neighbors.restype = st
+    L.sph_forces.argtypes = [P, P, P, P, P, i32, P, P]
+    L.sph_forces.restype = st
+    L.sph_integrate.argtypes = [P, i32, P, P, P, P, P, P, P]
+    L.sph_integrate.restype = st
+    L.sph_dt_workspace_bytes.argtypes = []
+    L.sph_dt_workspace_bytes.restype = C.c_size_t
+    L.sph_step_dt.argtypes = [P, P, P, P, P, C.c_size_t, P]
+    L.sph_step_dt.restype = st
+    L.sph_count_interactions.argtypes = [P, P, P, P, P, i32, P, P]
+    L.sph_count_interactions.restype = st
+    return L
+
+
+lib = _load()
+
+
+def check(code: int, what: str):
+    if code != SPH_OK:
+        raise SphError("%s: %s" % (what, lib.sph_status_string(code).decode()))
+
+
+def ptr(t) -> int | None:
+    if t is None:
+        return None
+    assert t.is_contiguous(), "device buffers must be contiguous"
+    return t.data_ptr()
+
+
+def stream_ptr(stream=None) -> int | None:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def grid_struct(grid) -> SphGrid:
+    g = SphGrid()
+    for d in range(3):
+        g.origin[d] = float(grid.origin[d])
+        g.cell_size[d] = float(grid.cell_size[d])
+        g.ncell[d] = int(grid.ncell[d])
+    g.periodic = int(grid.periodic)
+    g.cell_base = int(grid.cell_base)
+    return g
+
+
+def params_struct(p, alpha=None) -> SphParams:
+    q = SphParams()
+    q.h, q.r_search, q.rho0, q.gamma = p.h, p.r_search, p.rho0, p.gamma
+    q.c0 = p.c0
+    q.alpha = p.alpha if alpha is None else alpha
+    q.eps_visc, q.nu = p.eps_visc, p.nu
+    for d in range(3):
+        q.g[d] = float(p.g[d])
+    q.cfl = p.cfl
+    q.visc_model = int(p.visc_model)
+    return q
+
+
+def particles_struct(n: int, cell, pos, vel, info) -> SphParticles:
+    cap = cell.shape[0]
+    assert pos.shape == (cap, 4) and vel.shape == (cap, 4) and info.shape == (cap,)
+    assert cell.dtype == torch.int32 and pos.dtype == torch.float32 and vel.dtype == torch.float32
+    assert info.dtype == torch.int32, "info is stored as int32 bits of the uint32 word"
+    return SphParticles(int(n), int(cap), ptr(cell), ptr(pos), ptr(vel), ptr(info))
+
+
+def sph_build_workspace_bytes(capacity: int, n_cells: int) -> int:
+    return int(lib.sph_build_workspace_bytes(int(capacity), int(n_cells)))
+
+
+def sph_dt_workspace_bytes() -> int:
+    return int(lib.sph_dt_workspace_bytes())
+
+
+def sph_build_neighbors(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count,
+                        max_neibs: int, cell_start, cell_end, d_status, workspace, stream=None):
+    check(lib.sph_build_neighbors(C.byref(grid), C.byref(params), C.byref(parts), ptr(neibs), ptr(neib_count),
+                                  int(max_neibs), ptr(cell_start), ptr(cell_end), ptr(d_status),
+                                  ptr(workspace), workspace.numel() * workspace.element_size(),
+                                  stream_ptr(stream)), "sph_build_neighbors")
+
+
+def sph_forces(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count, max_neibs: int,
+               forces, stream=None):
+    check(lib.sph_forces(C.byref(grid), C.byref(params), C.byref(parts), ptr(neibs), ptr(neib_count),
+                         int(max_neibs), ptr(forces), stream_ptr(stream)), "sph_forces")
+
+
+def sph_integrate(params: SphParams, stage: int, d_dt, state_n: SphParticles, vel_star, forces,
+                  out: SphParticles, d_time=None, stream=None):
+    check(lib.sph_integrate(C.byref(params), int(stage), ptr(d_dt), C.byref(state_n), ptr(vel_star),
+                            ptr(forces), C.byref(out), ptr(d_time), stream_ptr(stream)), "sph_integrate")
+
+
+def sph_step_dt(params: SphParams, parts: SphParticles, forces, d_dt, workspace, stream=None):
+    check(lib.sph_step_dt(C.byref(params), C.byref(parts), ptr(forces), ptr(d_dt), ptr(workspace),
+                          workspace.numel() * workspace.element_size(), stream_ptr(stream)), "sph_step_dt")
+
+
+def sph_count_interactions(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count,
+                           max_neibs: int, d_count, stream=None):
+    check(lib.sph_count_interactions(C.byref(grid), C.byref(params), C.byref(parts), ptr(neibs),
+                                     ptr(neib_count), int(max_neibs), ptr(d_count), stream_ptr(stream)),
+          "sph_count_interactions")

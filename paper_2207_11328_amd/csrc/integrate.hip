@@ -1,0 +1,171 @@
+// Explicit midpoint predictor/corrector and the device-side adaptive time
+// step (arXiv:2207.11328, section "Code structure": predictor and corrector
+// phases with dt/2 and dt; section "The GPU in GPUSPH": dt from a device
+// reduction, kept on the device here so a whole step can be enqueued with
+// no host round trip).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "sph_device.h"
+
+using namespace sph;
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kDtBlocks = 1024;
+
+__global__ __launch_bounds__(kThreads) void k_integrate(int n, int stage, const double *__restrict__ d_dt,
+                                                        const int32_t *__restrict__ cell,
+                                                        const uint32_t *__restrict__ info,
+                                                        const float4 *pos_n, const float4 *vel_n,
+                                                        const float4 *__restrict__ vel_star,
+                                                        const float4 *__restrict__ forces, float4 *pos_out,
+                                                        float4 *vel_out, float gx, float gy, float gz,
+                                                        double *__restrict__ d_time)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    const double dt = *d_dt;
+    if (stage == 1 && d_time && i == 0) *d_time += dt;
+    if (i >= n) return;
+    const float tau = (float)(stage == 0 ? 0.5 * dt : dt);
+    float4 p = pos_n[i];
+    float4 v = vel_n[i];
+    if (cell[i] >= 0) {
+        const float4 f = forces[i];
+        if (ptype(info[i]) != kBoundary) {
+            const float4 ua = stage == 0 ? v : vel_star[i];
+            p.x = fmaf(tau, ua.x, p.x);
+            p.y = fmaf(tau, ua.y, p.y);
+            p.z = fmaf(tau, ua.z, p.z);
+            v.x = fmaf(tau, f.x + gx, v.x);
+            v.y = fmaf(tau, f.y + gy, v.y);
+            v.z = fmaf(tau, f.z + gz, v.z);
+        }
+        v.w = fmaf(tau, f.w, v.w);
+    }
+    pos_out[i] = p;
+    vel_out[i] = v;
+}
+
+// Per-block maxima of the sound speed and of |a + g| over fluid particles.
+__global__ __launch_bounds__(kThreads) void k_dt_partial(int n, const int32_t *__restrict__ cell,
+                                                         const uint32_t *__restrict__ info,
+                                                         const float4 *__restrict__ vel,
+                                                         const float4 *__restrict__ forces, float rho0,
+                                                         float inv_rho0, float c0, float gx, float gy, float gz,
+                                                         float2 *__restrict__ partial)
+{
+    float cmax = 0.0f, amax = 0.0f;
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+        if (cell[i] < 0 || ptype(info[i]) == kBoundary) continue;
+        const float d = (vel[i].w - rho0) * inv_rho0;
+        const float a = 1.0f + d;
+        cmax = fmaxf(cmax, c0 * a * a * a);
+        const float4 f = forces[i];
+        const float fx = f.x + gx, fy = f.y + gy, fz = f.z + gz;
+        amax = fmaxf(amax, __builtin_sqrtf(fx * fx + fy * fy + fz * fz));
+    }
+    cmax = wave_max(cmax);
+    amax = wave_max(amax);
+    __shared__ float2 w[kThreads / kWave];
+    if (threadIdx.x % kWave == 0) w[threadIdx.x / kWave] = make_float2(cmax, amax);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float2 r = w[0];
+        for (int k = 1; k < kThreads / kWave; ++k) {
+            r.x = fmaxf(r.x, w[k].x);
+            r.y = fmaxf(r.y, w[k].y);
+        }
+        partial[blockIdx.x] = r;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_dt_final(int np, const float2 *__restrict__ partial, double h,
+                                                       double nu, double cfl, double *__restrict__ d_dt)
+{
+    float cmax = 0.0f, amax = 0.0f;
+    for (int k = threadIdx.x; k < np; k += kThreads) {
+        cmax = fmaxf(cmax, partial[k].x);
+        amax = fmaxf(amax, partial[k].y);
+    }
+    cmax = wave_max(cmax);
+    amax = wave_max(amax);
+    __shared__ float2 w[kThreads / kWave];
+    if (threadIdx.x % kWave == 0) w[threadIdx.x / kWave] = make_float2(cmax, amax);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double c = 0.0, a = 0.0;
+        for (int k = 0; k < kThreads / kWave; ++k) {
+            c = fmax(c, (double)w[k].x);
+            a = fmax(a, (double)w[k].y);
+        }
+        double dt = INFINITY;
+        if (c > 0.0) dt = h / c;
+        if (a > 0.0) dt = fmin(dt, sqrt(h / a));
+        if (nu > 0.0) dt = fmin(dt, 0.125 * h * h / nu);
+        *d_dt = cfl * dt;
+    }
+}
+
+}  // namespace
+
+extern "C" sph_status sph_integrate(const sph_params *params, int32_t stage, const double *d_dt,
+                                    const sph_particles *state_n, const float *vel_star, const float *forces,
+                                    sph_particles *out, double *d_time, void *stream)
+{
+    if (!params || !d_dt || !state_n || !out || (stage != 0 && stage != 1)) return SPH_ERR_ARG;
+    const int n = state_n->n;
+    if (n < 0 || state_n->capacity < n || out->capacity < n) return SPH_ERR_ARG;
+    if (n > 0) {
+        if (!state_n->cell || !state_n->pos || !state_n->vel || !state_n->info || !forces) return SPH_ERR_ARG;
+        if (!out->pos || !out->vel) return SPH_ERR_ARG;
+        if (stage == 1 && !vel_star) return SPH_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned blocks = n > 0 ? sph_blocks(n, kThreads) : 1;
+    k_integrate<<<blocks, kThreads, 0, s>>>(n, stage, d_dt, state_n->cell, state_n->info,
+                                            (const float4 *)state_n->pos, (const float4 *)state_n->vel,
+                                            (const float4 *)vel_star, (const float4 *)forces,
+                                            (float4 *)out->pos, (float4 *)out->vel, params->g[0], params->g[1],
+                                            params->g[2], d_time);
+    SPH_CHECK_LAUNCH();
+    return SPH_OK;
+}
+
+extern "C" size_t sph_dt_workspace_bytes(void) { return sizeof(float2) * kDtBlocks; }
+
+extern "C" sph_status sph_step_dt(const sph_params *params, const sph_particles *parts, const float *forces,
+                                  double *d_dt, void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!params || !parts || !d_dt) return SPH_ERR_ARG;
+    const int n = parts->n;
+    if (n < 0 || parts->capacity < n) return SPH_ERR_ARG;
+    if (n > 0 && (!parts->cell || !parts->vel || !parts->info || !forces)) return SPH_ERR_ARG;
+    if (!(params->h > 0.0f) || !(params->rho0 > 0.0f) || params->gamma != 7.0f) return SPH_ERR_ARG;
+    if (!workspace || workspace_bytes < sph_dt_workspace_bytes()) return SPH_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned want = n > 0 ? sph_blocks(n, kThreads) : 1;
+    const int blocks = (int)(want < (unsigned)kDtBlocks ? want : (unsigned)kDtBlocks);
+    float2 *partial = (float2 *)workspace;
+    k_dt_partial<<<blocks, kThreads, 0, s>>>(n, parts->cell, parts->info, (const float4 *)parts->vel,
+                                             (const float4 *)forces, params->rho0,
+                                             (float)(1.0 / (double)params->rho0), params->c0, params->g[0],
+                                             params->g[1], params->g[2], partial);
+    k_dt_final<<<1, kThreads, 0, s>>>(blocks, partial, params->h, params->nu, params->cfl, d_dt);
+    SPH_CHECK_LAUNCH();
+    return SPH_OK;
+}
+
+extern "C" const char *sph_status_string(sph_status st)
+{
+    switch (st) {
+    case SPH_OK: return "SPH_OK";
+    case SPH_ERR_ARG: return "SPH_ERR_ARG: invalid argument or shape";
+    case SPH_ERR_WORKSPACE: return "SPH_ERR_WORKSPACE: workspace missing or too small";
+    case SPH_ERR_HIP: return "SPH_ERR_HIP: HIP launch or runtime failure";
+    }
+    return "SPH: unknown status";
+}
+
+extern "C" int32_t sph_abi_version(void) { return 1; }

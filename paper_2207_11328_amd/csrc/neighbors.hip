@@ -1,0 +1,447 @@
+// Neighbour search: re-bin, counting sort by cell with an in-cell sort by
+// (type, id), reorder, cell ranges and split neighbour lists.
+//
+// Sort order is cell, then particle type, then particle id (section
+// "Changing perspective: from the particle to the cell").  Instead of a
+// multi-pass radix sort of 64-bit keys, the cell index is used directly as
+// a single radix digit: a histogram over cells, an exclusive scan (which is
+// also the cell-start array) and an atomic scatter put every particle in its
+// cell's range; one wave per cell then ranks the cell's few particles by
+// their (type, id) word, which makes the permutation unique.
+//
+// Lists are split (fluid from the front, boundary from the back) and stored
+// neighbour-major (section "Efficient split neighbors list").
+#include <hip/hip_runtime.h>
+
+#include "sph_device.h"
+
+using namespace sph;
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kScanItems = 4;                       // per thread
+constexpr int kScanTile = kThreads * kScanItems;    // elements per block
+
+struct BuildLayout {
+    size_t cnt, cursor, start, partials, perm_a, perm_b, t_cell, t_pos, t_vel, t_info, total;
+};
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+BuildLayout build_layout(int64_t capacity, int64_t n_cells)
+{
+    const int64_t nb = n_cells + 1;  // one extra bucket for dropped particles
+    const int64_t nparts = (nb + kScanTile - 1) / kScanTile;
+    BuildLayout L;
+    size_t o = 0;
+    L.cnt = o;      o = align_up(o + sizeof(int32_t) * nb);
+    L.cursor = o;   o = align_up(o + sizeof(int32_t) * nb);
+    L.start = o;    o = align_up(o + sizeof(int32_t) * (nb + 1));
+    L.partials = o; o = align_up(o + sizeof(int32_t) * (nparts + 1));
+    L.perm_a = o;   o = align_up(o + sizeof(uint32_t) * capacity);
+    L.perm_b = o;   o = align_up(o + sizeof(uint32_t) * capacity);
+    L.t_cell = o;   o = align_up(o + sizeof(int32_t) * capacity);
+    L.t_pos = o;    o = align_up(o + sizeof(float4) * capacity);
+    L.t_vel = o;    o = align_up(o + sizeof(float4) * capacity);
+    L.t_info = o;   o = align_up(o + sizeof(uint32_t) * capacity);
+    L.total = o;
+    return L;
+}
+
+__global__ void k_fill(int32_t *__restrict__ p, int64_t n, int32_t v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Re-bin offsets into [-cs/2, cs/2) (float32, at most 4 cells per axis) and
+// count particles per cell.  Particles that leave a non-periodic axis, or
+// whose offsets are not finite, become dropped (cell = -1, last bucket).
+__global__ __launch_bounds__(kThreads) void k_rebin_count(
+    int n, int32_t *__restrict__ cell, float4 *__restrict__ pos, CellDims dims, float csx, float csy,
+    float csz, int cell_base, int n_cells, int32_t *__restrict__ cnt)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    int c = cell[i];
+    int bucket = n_cells;
+    if (c >= 0) {
+        int cc[3];
+        cell_coords(c - cell_base, dims, cc[0], cc[1], cc[2]);
+        float4 p = pos[i];
+        float o[3] = {p.x, p.y, p.z};
+        const float cs[3] = {csx, csy, csz};
+        const int nd[3] = {dims.nx, dims.ny, dims.nz};
+        bool ok = true;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            const float half = 0.5f * cs[d];
+            float v = o[d];
+            for (int it = 0; it < 4; ++it) {
+                if (v >= half) { v = v - cs[d]; cc[d] += 1; }
+                else if (v < -half) { v = v + cs[d]; cc[d] -= 1; }
+                else break;
+            }
+            if (!(v >= -half && v < half)) ok = false;
+            if ((dims.periodic >> d) & 1u) {
+                cc[d] %= nd[d];
+                if (cc[d] < 0) cc[d] += nd[d];
+            } else if (cc[d] < 0 || cc[d] >= nd[d]) {
+                ok = false;
+            }
+            o[d] = v;
+        }
+        pos[i] = make_float4(o[0], o[1], o[2], p.w);
+        if (ok) {
+            const int lc = cc[0] + dims.nx * (cc[1] + dims.ny * cc[2]);
+            cell[i] = lc + cell_base;
+            bucket = lc;
+        } else {
+            cell[i] = -1;
+        }
+    }
+    atomicAdd(&cnt[bucket], 1);
+}
+
+// ---- exclusive scan of cnt[0..m) into start[0..m], start[m] = total --------
+__device__ __forceinline__ int block_exclusive_scan(int v, int &total)
+{
+    __shared__ int wsum[kThreads / kWave];
+    const int lane = threadIdx.x % kWave;
+    const int w = threadIdx.x / kWave;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        int t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    if (lane == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    int off = 0;
+    total = 0;
+#pragma unroll
+    for (int k = 0; k < kThreads / kWave; ++k) {
+        if (k < w) off += wsum[k];
+        total += wsum[k];
+    }
+    __syncthreads();
+    return off + inc - v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const int32_t *__restrict__ in, int m,
+                                                          int32_t *__restrict__ partials)
+{
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k)
+        if (base + k < m) s += in[base + k];
+    int total;
+    (void)block_exclusive_scan(s, total);
+    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_partials(int32_t *__restrict__ partials, int np,
+                                                            int32_t *__restrict__ grand_total)
+{
+    int carry = 0;
+    for (int base = 0; base < np; base += kThreads) {
+        const int i = base + threadIdx.x;
+        const int v = i < np ? partials[i] : 0;
+        int total;
+        const int ex = block_exclusive_scan(v, total);
+        if (i < np) partials[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) *grand_total = carry;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_apply(const int32_t *__restrict__ in, int m,
+                                                         const int32_t *__restrict__ partials,
+                                                         int32_t *__restrict__ out)
+{
+    const int base = blockIdx.x * kScanTile + threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = base + k < m ? in[base + k] : 0;
+        s += v[k];
+    }
+    int total;
+    int ex = block_exclusive_scan(s, total) + partials[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (base + k < m) out[base + k] = ex;
+        ex += v[k];
+    }
+}
+
+// Place every particle in its bucket's range (order inside a bucket is
+// arbitrary at this point).
+__global__ __launch_bounds__(kThreads) void k_scatter(int n, const int32_t *__restrict__ cell,
+                                                      int cell_base, int n_cells,
+                                                      const int32_t *__restrict__ start,
+                                                      int32_t *__restrict__ cursor,
+                                                      uint32_t *__restrict__ perm)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const int c = cell[i];
+    const int b = c >= 0 ? c - cell_base : n_cells;
+    const int slot = start[b] + atomicAdd(&cursor[b], 1);
+    perm[slot] = (uint32_t)i;
+}
+
+// One wave per bucket: rank each particle of the bucket by its info word
+// (type << 30 | id) and write it to its final position.  Ids are unique;
+// equal words (invalid input) are ranked by their slot so the result is a
+// permutation in every case.
+__global__ __launch_bounds__(kThreads) void k_cell_sort(int n_buckets, const int32_t *__restrict__ start,
+                                                        const uint32_t *__restrict__ perm_in,
+                                                        const uint32_t *__restrict__ info,
+                                                        uint32_t *__restrict__ perm_out)
+{
+    const int b = blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+    if (b >= n_buckets) return;
+    const int lane = threadIdx.x % kWave;
+    const int s = start[b];
+    const int m = start[b + 1] - s;
+    for (int mb = 0; mb < m; mb += kWave) {
+        const int me = mb + lane;
+        const bool valid = me < m;
+        const uint32_t idx = valid ? perm_in[s + me] : 0u;
+        const uint32_t key = valid ? info[idx] : 0xFFFFFFFFu;
+        int rank = 0;
+        for (int tb = 0; tb < m; tb += kWave) {
+            const int t = tb + lane;
+            const uint32_t kt_lane = t < m ? info[perm_in[s + t]] : 0xFFFFFFFFu;
+            const int cnt = min(kWave, m - tb);
+            for (int u = 0; u < cnt; ++u) {
+                const uint32_t kt = __shfl(kt_lane, u);
+                rank += (kt < key || (kt == key && tb + u < me)) ? 1 : 0;
+            }
+        }
+        if (valid) perm_out[s + rank] = idx;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_gather(int n, const uint32_t *__restrict__ perm,
+                                                     const int32_t *__restrict__ cell,
+                                                     const float4 *__restrict__ pos,
+                                                     const float4 *__restrict__ vel,
+                                                     const uint32_t *__restrict__ info,
+                                                     int32_t *__restrict__ o_cell,
+                                                     float4 *__restrict__ o_pos,
+                                                     float4 *__restrict__ o_vel,
+                                                     uint32_t *__restrict__ o_info)
+{
+    const int k = blockIdx.x * kThreads + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t src = perm[k];
+    o_cell[k] = cell[src];
+    o_pos[k] = pos[src];
+    o_vel[k] = vel[src];
+    o_info[k] = info[src];
+}
+
+__global__ __launch_bounds__(kThreads) void k_copy_state(int n, const int32_t *__restrict__ cell,
+                                                         const float4 *__restrict__ pos,
+                                                         const float4 *__restrict__ vel,
+                                                         const uint32_t *__restrict__ info,
+                                                         int32_t *__restrict__ o_cell,
+                                                         float4 *__restrict__ o_pos,
+                                                         float4 *__restrict__ o_vel,
+                                                         uint32_t *__restrict__ o_info)
+{
+    const int k = blockIdx.x * kThreads + threadIdx.x;
+    if (k >= n) return;
+    o_cell[k] = cell[k];
+    o_pos[k] = pos[k];
+    o_vel[k] = vel[k];
+    o_info[k] = info[k];
+}
+
+__global__ __launch_bounds__(kThreads) void k_cell_ranges(int n_cells, const int32_t *__restrict__ start,
+                                                          int32_t *__restrict__ cell_start,
+                                                          int32_t *__restrict__ cell_end)
+{
+    const int c = blockIdx.x * kThreads + threadIdx.x;
+    if (c >= n_cells) return;
+    cell_start[c] = start[c];
+    cell_end[c] = start[c + 1];
+}
+
+__global__ void k_status(int n, int n_cells, const int32_t *__restrict__ start, int32_t *__restrict__ status)
+{
+    const int n_active = start[n_cells];
+    status[SPH_STATUS_N_ACTIVE] = n_active;
+    status[SPH_STATUS_DROPPED] = n - n_active;
+}
+
+// Per-particle neighbour list: one lane per central particle scans the 27
+// cells of its Moore neighbourhood (z, y, x from -1 to +1) in sorted order.
+// Inside a cell fluid particles precede boundary ones, so a boundary centre
+// stops at the first boundary neighbour of each cell.
+__global__ __launch_bounds__(kThreads) void k_build_lists(
+    int n, int capacity, int max_neibs, const int32_t *__restrict__ cell, const float4 *__restrict__ pos,
+    const uint32_t *__restrict__ info, const int32_t *__restrict__ start, CellDims dims, float csx,
+    float csy, float csz, int cell_base, float rs2, uint32_t *__restrict__ neibs,
+    uint32_t *__restrict__ neib_count, int32_t *__restrict__ status)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const int ci = cell[i];
+    if (ci < 0) {
+        neib_count[i] = 0u;
+        return;
+    }
+    int cx, cy, cz;
+    cell_coords(ci - cell_base, dims, cx, cy, cz);
+    const float4 pi = pos[i];
+    const bool central_boundary = ptype(info[i]) == kBoundary;
+    int nf = 0, nb = 0, wf = 0, wb = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+        int jz = cz + dz;
+        if ((dims.periodic >> 2) & 1u) jz = jz < 0 ? jz + dims.nz : (jz >= dims.nz ? jz - dims.nz : jz);
+        else if (jz < 0 || jz >= dims.nz) continue;
+        const float t2z = cell_shift(-dz, csz);
+        for (int dy = -1; dy <= 1; ++dy) {
+            int jy = cy + dy;
+            if ((dims.periodic >> 1) & 1u) jy = jy < 0 ? jy + dims.ny : (jy >= dims.ny ? jy - dims.ny : jy);
+            else if (jy < 0 || jy >= dims.ny) continue;
+            const float t2y = cell_shift(-dy, csy);
+            for (int dx = -1; dx <= 1; ++dx) {
+                int jx = cx + dx;
+                if (dims.periodic & 1u) jx = jx < 0 ? jx + dims.nx : (jx >= dims.nx ? jx - dims.nx : jx);
+                else if (jx < 0 || jx >= dims.nx) continue;
+                const float t2x = cell_shift(-dx, csx);
+                const int lc = jx + dims.nx * (jy + dims.ny * jz);
+                const int s = start[lc];
+                const int e = start[lc + 1];
+                for (int j = s; j < e; ++j) {
+                    if (j == i) continue;
+                    const bool nb_boundary = ptype(info[j]) == kBoundary;
+                    if (central_boundary && nb_boundary) break;
+                    const float4 pj = pos[j];
+                    const float r2 = predicate_r2(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, t2x, t2y, t2z);
+                    if (!(r2 < rs2)) continue;
+                    const uint32_t entry = pack_neib((uint32_t)j, -dx, -dy, -dz);
+                    if (nb_boundary) {
+                        if (wf + wb < max_neibs) {
+                            neibs[(size_t)(max_neibs - 1 - wb) * capacity + i] = entry;
+                            ++wb;
+                        }
+                        ++nb;
+                    } else {
+                        if (wf + wb < max_neibs) {
+                            neibs[(size_t)wf * capacity + i] = entry;
+                            ++wf;
+                        }
+                        ++nf;
+                    }
+                }
+            }
+        }
+    }
+    neib_count[i] = (uint32_t)wf | (uint32_t)wb << 16;
+    const int total = nf + nb;
+    atomicMax(&status[SPH_STATUS_MAX_NEIBS], total);
+    if (total > max_neibs) atomicAdd(&status[SPH_STATUS_OVERFLOW], 1);
+}
+
+bool grid_ok(const sph_grid *g, float r_search)
+{
+    for (int d = 0; d < 3; ++d) {
+        if (g->ncell[d] < 1) return false;
+        if (!(g->cell_size[d] >= r_search)) return false;
+        if (((g->periodic >> d) & 1u) && g->ncell[d] < 3) return false;
+    }
+    const int64_t nc = (int64_t)g->ncell[0] * g->ncell[1] * g->ncell[2];
+    if (nc + 2 > INT32_MAX || g->cell_base < 0 || nc + g->cell_base > INT32_MAX) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells)
+{
+    if (capacity < 0 || n_cells < 0) return 0;
+    return build_layout(capacity, n_cells).total;
+}
+
+extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
+                                          sph_particles *parts, uint32_t *neibs, uint32_t *neib_count,
+                                          int32_t max_neibs, int32_t *cell_start, int32_t *cell_end,
+                                          int32_t *d_status, void *workspace, size_t workspace_bytes,
+                                          void *stream)
+{
+    if (!grid || !params || !parts || !neibs || !neib_count || !cell_start || !cell_end || !d_status)
+        return SPH_ERR_ARG;
+    if (parts->n < 0 || parts->capacity < parts->n || parts->capacity > SPH_MAX_CAPACITY) return SPH_ERR_ARG;
+    if (parts->capacity > 0 && (!parts->cell || !parts->pos || !parts->vel || !parts->info)) return SPH_ERR_ARG;
+    if (max_neibs < 1 || max_neibs > 65535) return SPH_ERR_ARG;
+    if (!(params->r_search > 0.0f) || !grid_ok(grid, params->r_search)) return SPH_ERR_ARG;
+    const int n = parts->n;
+    const int cap = parts->capacity;
+    const int n_cells = grid->ncell[0] * grid->ncell[1] * grid->ncell[2];
+    const BuildLayout L = build_layout(cap, n_cells);
+    if (!workspace || workspace_bytes < L.total) return SPH_ERR_WORKSPACE;
+
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    int32_t *cnt = (int32_t *)(ws + L.cnt);
+    int32_t *cursor = (int32_t *)(ws + L.cursor);
+    int32_t *start = (int32_t *)(ws + L.start);
+    int32_t *partials = (int32_t *)(ws + L.partials);
+    uint32_t *perm_a = (uint32_t *)(ws + L.perm_a);
+    uint32_t *perm_b = (uint32_t *)(ws + L.perm_b);
+    int32_t *t_cell = (int32_t *)(ws + L.t_cell);
+    float4 *t_pos = (float4 *)(ws + L.t_pos);
+    float4 *t_vel = (float4 *)(ws + L.t_vel);
+    uint32_t *t_info = (uint32_t *)(ws + L.t_info);
+    float4 *pos = (float4 *)parts->pos;
+    float4 *vel = (float4 *)parts->vel;
+
+    const CellDims dims{grid->ncell[0], grid->ncell[1], grid->ncell[2], grid->periodic};
+    const int nbk = n_cells + 1;
+
+    const unsigned fill_blocks = sph_blocks(nbk, kThreads) < 4096u ? sph_blocks(nbk, kThreads) : 4096u;
+    k_fill<<<fill_blocks, kThreads, 0, s>>>(cnt, nbk, 0);
+    k_fill<<<fill_blocks, kThreads, 0, s>>>(cursor, nbk, 0);
+    k_fill<<<1, 64, 0, s>>>(d_status, 4, 0);
+    SPH_CHECK_LAUNCH();
+    if (n > 0) {
+        k_rebin_count<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(
+            n, parts->cell, pos, dims, grid->cell_size[0], grid->cell_size[1], grid->cell_size[2],
+            grid->cell_base, n_cells, cnt);
+        SPH_CHECK_LAUNCH();
+    }
+    const int np = (nbk + kScanTile - 1) / kScanTile;
+    k_scan_reduce<<<np, kThreads, 0, s>>>(cnt, nbk, partials);
+    k_scan_partials<<<1, kThreads, 0, s>>>(partials, np, start + nbk);
+    k_scan_apply<<<np, kThreads, 0, s>>>(cnt, nbk, partials, start);
+    SPH_CHECK_LAUNCH();
+    k_status<<<1, 1, 0, s>>>(n, n_cells, start, d_status);
+    k_cell_ranges<<<sph_blocks(n_cells, kThreads), kThreads, 0, s>>>(n_cells, start, cell_start, cell_end);
+    SPH_CHECK_LAUNCH();
+    if (n > 0) {
+        k_scatter<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, parts->cell, grid->cell_base, n_cells,
+                                                                start, cursor, perm_a);
+        k_cell_sort<<<sph_blocks(nbk, kThreads / kWave), kThreads, 0, s>>>(nbk, start, perm_a, parts->info,
+                                                                              perm_b);
+        k_gather<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, perm_b, parts->cell, pos, vel, parts->info,
+                                                               t_cell, t_pos, t_vel, t_info);
+        SPH_CHECK_LAUNCH();
+        const float rs2 = params->r_search * params->r_search;
+        k_build_lists<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(
+            n, cap, max_neibs, t_cell, t_pos, t_info, start, dims, grid->cell_size[0], grid->cell_size[1],
+            grid->cell_size[2], grid->cell_base, rs2, neibs, neib_count, d_status);
+        k_copy_state<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, t_cell, t_pos, t_vel, t_info, parts->cell,
+                                                                   pos, vel, parts->info);
+        SPH_CHECK_LAUNCH();
+    }
+    return SPH_OK;
+}

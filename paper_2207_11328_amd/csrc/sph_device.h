@@ -1,0 +1,89 @@
+// Device-side helpers shared by the HIP translation units of libsph.so.
+// gfx950 (CDNA4): wave64, 256 CUs in 8 XCDs, 160 KB LDS per CU.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sph.h"
+
+namespace sph {
+
+constexpr int kWave = 64;
+constexpr uint32_t kTypeShift = 30;
+constexpr uint32_t kBoundary = 1;
+constexpr uint32_t kIndexMask = (1u << SPH_NEIB_INDEX_BITS) - 1u;
+
+__device__ __forceinline__ uint32_t ptype(uint32_t info) { return info >> kTypeShift; }
+
+// Linear cell index (relative to the scene's cell base) -> integer coordinates.
+struct CellDims {
+    int nx, ny, nz;
+    uint32_t periodic;
+};
+
+__device__ __forceinline__ void cell_coords(int lc, const CellDims &d, int &cx, int &cy, int &cz)
+{
+    cx = lc % d.nx;
+    int t = lc / d.nx;
+    cy = t % d.ny;
+    cz = t / d.ny;
+}
+
+// Squared separation of the neighbour predicate, in float32 with every
+// operation rounded separately (no contraction), so that the decision is
+// reproducible bit for bit:  x_d = t2_d + (o_i,d - o_j,d),  r2 = (xx + yy) + zz.
+__device__ __forceinline__ float predicate_r2(float oix, float oiy, float oiz, float ojx, float ojy,
+                                              float ojz, float t2x, float t2y, float t2z)
+{
+#pragma clang fp contract(off)
+    const float x = t2x + (oix - ojx);
+    const float y = t2y + (oiy - ojy);
+    const float z = t2z + (oiz - ojz);
+    const float xx = x * x;
+    const float yy = y * y;
+    const float zz = z * z;
+    const float s = xx + yy;
+    return s + zz;
+}
+
+// k * cs for k in {-1, 0, 1}, exact.
+__device__ __forceinline__ float cell_shift(int k, float cs)
+{
+    return k == 0 ? 0.0f : (k > 0 ? cs : -cs);
+}
+
+// Neighbour entry: sorted index plus (c_i - c_j + 1) per axis in 2-bit fields.
+__device__ __forceinline__ uint32_t pack_neib(uint32_t j, int kx, int ky, int kz)
+{
+    return j | (uint32_t)(kx + 1) << 26 | (uint32_t)(ky + 1) << 28 | (uint32_t)(kz + 1) << 30;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+}  // namespace sph
+
+// Host-side launch helpers.
+#define SPH_CHECK_LAUNCH()                                  \
+    do {                                                    \
+        if (hipGetLastError() != hipSuccess) return SPH_ERR_HIP; \
+    } while (0)
+
+static inline unsigned sph_blocks(long long n, int threads)
+{
+    return (unsigned)((n + threads - 1) / threads);
+}

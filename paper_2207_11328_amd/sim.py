@@ -1,0 +1,171 @@
+"""Step driver over the C ABI: device buffers (torch), rebuild cadence, the
+predictor/corrector step with the time step kept on the device.
+
+One step (section "Code structure"; the rebuild cadence of section "Too much
+of a good thing?": lists rebuilt every 10 steps by default):
+
+    every K steps: sph_build_neighbors        (re-bin, sort, lists)
+    sph_forces(state n)      -> forces_n
+    sph_step_dt(state n)     -> dt   (device double)
+    sph_integrate(stage 0)   -> state *
+    sph_forces(state *)      -> forces_*
+    sph_integrate(stage 1)   -> state n+1 (in place), t += dt
+
+Nothing is synchronised with the host inside a step.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import abi
+
+
+def _i32(a: np.ndarray) -> np.ndarray:
+    return np.ascontiguousarray(a).view(np.int32) if a.dtype == np.uint32 else np.ascontiguousarray(a, np.int32)
+
+
+class Simulation:
+    """Device state of one scene and the step sequence over the C ABI."""
+
+    def __init__(self, grid, params, cell, pos, vel, info, max_neibs: int = 128, capacity: int | None = None,
+                 rebuild_every: int = 10, device: str = "cuda", dt_fixed: float | None = None):
+        n = int(np.asarray(cell).shape[0])
+        cap = int(capacity or n)
+        if cap < n or cap > abi.MAX_CAPACITY:
+            raise ValueError("capacity must be in [n, 2^26]")
+        self.n = n
+        self.capacity = cap
+        self.max_neibs = int(max_neibs)
+        self.rebuild_every = int(rebuild_every)
+        self.grid = grid
+        self.params = params
+        self.n_cells = int(np.prod(np.asarray(grid.ncell, dtype=np.int64)))
+        self.device = torch.device(device)
+        dev = self.device
+
+        def z(shape, dtype):
+            return torch.zeros(shape, dtype=dtype, device=dev)
+
+        self.cell = z(cap, torch.int32)
+        self.info = z(cap, torch.int32)
+        self.pos = z((cap, 4), torch.float32)
+        self.vel = z((cap, 4), torch.float32)
+        self.pos_star = z((cap, 4), torch.float32)
+        self.vel_star = z((cap, 4), torch.float32)
+        self.forces_n = z((cap, 4), torch.float32)
+        self.forces_star = z((cap, 4), torch.float32)
+        self.neibs = z(self.max_neibs * cap, torch.int32)
+        self.neib_count = z(cap, torch.int32)
+        self.cell_start = z(max(self.n_cells, 1), torch.int32)
+        self.cell_end = z(max(self.n_cells, 1), torch.int32)
+        self.status = z(4, torch.int32)
+        self.ws_build = z(abi.sph_build_workspace_bytes(cap, self.n_cells), torch.uint8)
+        self.ws_dt = z(abi.sph_dt_workspace_bytes(), torch.uint8)
+        self.d_dt = z(1, torch.float64)
+        self.d_time = z(1, torch.float64)
+        self.count = z(1, torch.int64)
+        self.dt_fixed = dt_fixed
+        if dt_fixed is not None:
+            self.d_dt.fill_(float(dt_fixed))
+
+        self.cell[:n] = torch.from_numpy(_i32(cell))
+        self.info[:n] = torch.from_numpy(_i32(np.asarray(info, np.uint32)))
+        self.pos[:n] = torch.from_numpy(np.ascontiguousarray(pos, np.float32))
+        self.vel[:n] = torch.from_numpy(np.ascontiguousarray(vel, np.float32))
+
+        self.g = abi.grid_struct(grid)
+        self.p = abi.params_struct(params)
+        self.parts = abi.particles_struct(n, self.cell, self.pos, self.vel, self.info)
+        self.parts_star = abi.particles_struct(n, self.cell, self.pos_star, self.vel_star, self.info)
+        self.steps_done = 0
+
+    # ------------------------------------------------------------ primitives
+    def build(self, stream=None):
+        abi.sph_build_neighbors(self.g, self.p, self.parts, self.neibs, self.neib_count, self.max_neibs,
+                                self.cell_start, self.cell_end, self.status, self.ws_build, stream)
+
+    def forces(self, star: bool = False, stream=None):
+        parts = self.parts_star if star else self.parts
+        out = self.forces_star if star else self.forces_n
+        abi.sph_forces(self.g, self.p, parts, self.neibs, self.neib_count, self.max_neibs, out, stream)
+        return out
+
+    def step_dt(self, stream=None):
+        abi.sph_step_dt(self.p, self.parts, self.forces_n, self.d_dt, self.ws_dt, stream)
+
+    def integrate(self, stage: int, stream=None):
+        if stage == 0:
+            abi.sph_integrate(self.p, 0, self.d_dt, self.parts, None, self.forces_n, self.parts_star,
+                              None, stream)
+        else:
+            abi.sph_integrate(self.p, 1, self.d_dt, self.parts, self.vel_star, self.forces_star, self.parts,
+                              self.d_time, stream)
+
+    def count_interactions(self, stream=None) -> torch.Tensor:
+        abi.sph_count_interactions(self.g, self.p, self.parts, self.neibs, self.neib_count, self.max_neibs,
+                                   self.count, stream)
+        return self.count
+
+    # ------------------------------------------------------------ step
+    def step(self, stream=None):
+        if self.steps_done % self.rebuild_every == 0:
+            self.build(stream)
+        self.forces(False, stream)
+        if self.dt_fixed is None:
+            self.step_dt(stream)
+        self.integrate(0, stream)
+        self.forces(True, stream)
+        self.integrate(1, stream)
+        self.steps_done += 1
+
+    def run(self, steps: int, stream=None):
+        for _ in range(steps):
+            self.step(stream)
+
+    # ------------------------------------------------------------ host views
+    def status_host(self) -> dict:
+        s = self.status.cpu().numpy()
+        return {"n_active": int(s[0]), "max_neibs": int(s[1]), "overflow": int(s[2]), "dropped": int(s[3])}
+
+    def check_status(self):
+        st = self.status_host()
+        if st["overflow"] > 0:
+            raise abi.SphError("neighbour list overflow: %d particles need more than %d slots (max %d)"
+                               % (st["overflow"], self.max_neibs, st["max_neibs"]))
+        return st
+
+    def state_host(self) -> dict:
+        n = self.n
+        return {
+            "cell": self.cell[:n].cpu().numpy(),
+            "pos": self.pos[:n].cpu().numpy(),
+            "vel": self.vel[:n].cpu().numpy(),
+            "info": self.info[:n].cpu().numpy().view(np.uint32),
+        }
+
+    def lists_host(self):
+        """(neibs [max_neibs, capacity] uint32, neib_count [n] uint32)."""
+        nb = self.neibs.view(self.max_neibs, self.capacity).cpu().numpy().view(np.uint32)
+        cnt = self.neib_count[: self.n].cpu().numpy().view(np.uint32)
+        return nb, cnt
+
+    @property
+    def time(self) -> float:
+        return float(self.d_time.item())
+
+
+def decode_lists(neibs: np.ndarray, count: np.ndarray, max_neibs: int):
+    """Split neighbour-major lists -> (fluid index arrays, boundary index arrays,
+    fluid codes, boundary codes) per particle, in list order."""
+    mask = (1 << abi.NEIB_INDEX_BITS) - 1
+    n = count.shape[0]
+    nf = (count & 0xFFFF).astype(np.int64)
+    nb = (count >> 16).astype(np.int64)
+    fl, bl = [], []
+    for i in range(n):
+        fe = neibs[: nf[i], i]
+        be = neibs[max_neibs - nb[i]:, i][::-1] if nb[i] > 0 else neibs[:0, i]
+        fl.append(fe)
+        bl.append(be)
+    return fl, bl, mask

@@ -1,0 +1,170 @@
+"""Helpers shared by the GPU parity tests: run the HIP path through the C ABI
+and the oracle on the same canonical inputs, and compare.
+
+Tolerances are derived from the arithmetic (float32 unit roundoff
+u = 2^-24) and written where they are used:
+
+* sorted state, cell ranges, neighbour sets, counts, status: bit-exact;
+* derivatives: per particle and component, |f_gpu - f_oracle| <= 1e-5 S,
+  where S is the oracle's sum of the magnitudes of the pair terms (the
+  condition scale of the sum; a plain relative error would measure the
+  cancellation of the still-water balance, not the implementation);
+* integrator: one rounding per operand of y + tau f on top of the
+  derivative tolerance: |dy| <= 4 u (|y| + tau |f|) + tau 1e-5 S.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+from oracle import oracle as O
+from workloads import scenes as S
+
+U32 = 2.0 ** -24
+FORCE_TOL = 1e-5
+SENT = np.iinfo(np.int64).max
+
+
+def log(msg: str):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def make_sim(sc, max_neibs=128, capacity=None, **kw):
+    from paper_2207_11328_amd.sim import Simulation
+    return Simulation(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, max_neibs=max_neibs,
+                      capacity=capacity, **kw)
+
+
+def gpu_lists_padded(sim):
+    """GPU split lists -> (fluid idx [n,max] sorted, boundary idx sorted,
+    fluid codes, boundary codes) with SENT padding; codes follow the index sort."""
+    nb, cnt = sim.lists_host()
+    n = sim.n
+    M = sim.max_neibs
+    E = nb[:, :n].T.astype(np.int64)  # [n, M]
+    nf = (cnt & 0xFFFF).astype(np.int64)
+    nbd = (cnt >> 16).astype(np.int64)
+    col = np.arange(M)[None, :]
+    fmask = col < nf[:, None]
+    bmask = col >= (M - nbd)[:, None]
+    idx = E & ((1 << 26) - 1)
+    code = E >> 26
+    fi = np.where(fmask, idx, SENT)
+    bi = np.where(bmask, idx, SENT)
+    fo = np.argsort(fi, axis=1, kind="stable")
+    bo = np.argsort(bi, axis=1, kind="stable")
+    fi = np.take_along_axis(fi, fo, 1)
+    bi = np.take_along_axis(bi, bo, 1)
+    fc = np.take_along_axis(np.where(fmask, code, -1), fo, 1)
+    bc = np.take_along_axis(np.where(bmask, code, -1), bo, 1)
+    return fi, bi, fc, bc, nf, nbd
+
+
+def oracle_lists_padded(lists, max_neibs):
+    n = lists.nf.shape[0]
+    col = np.arange(max_neibs)[None, :]
+    fi = np.where(col < lists.nf[:, None], lists.fl.astype(np.int64), SENT)
+    bi = np.where(col < lists.nb[:, None], lists.bl.astype(np.int64), SENT)
+    return np.sort(fi, axis=1), np.sort(bi, axis=1)
+
+
+def expected_codes(grid, cell, idx_sorted):
+    """Cell-difference codes (k_d + 1 per axis, 2 bits each) for padded
+    neighbour index rows of a sorted state."""
+    nx, ny, nz = (int(v) for v in grid.ncell)
+    lc = cell.astype(np.int64) - int(grid.cell_base)
+    c = np.stack([lc % nx, (lc // nx) % ny, lc // (nx * ny)], axis=1)
+    valid = idx_sorted != SENT
+    j = np.where(valid, idx_sorted, 0)
+    code = np.zeros(idx_sorted.shape, dtype=np.int64)
+    for d, nd in enumerate((nx, ny, nz)):
+        k = c[:, d][:, None] - c[:, d][j]
+        if (grid.periodic >> d) & 1:
+            k = np.where(k > 1, k - nd, k)
+            k = np.where(k < -1, k + nd, k)
+        code |= (k + 1) << (2 * d)
+    return np.where(valid, code, -1)
+
+
+def compare_build(sc, sim, max_neibs=128, rows=None):
+    """Bit-exact comparison of a GPU build with the oracle's float32 build.
+    rows: optional subset of particle indices for the list comparison."""
+    ob = O.build_f32(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, max_neibs)
+    gs = sim.state_host()
+    n = sc.n
+    assert np.array_equal(gs["info"], ob["info"]), "sort order"
+    assert np.array_equal(gs["cell"], ob["cell"]), "cells"
+    assert np.array_equal(gs["pos"].view(np.uint32), ob["pos"].view(np.uint32)), "re-binned offsets"
+    assert np.array_equal(gs["vel"].view(np.uint32), np.ascontiguousarray(ob["vel"]).view(np.uint32)), "vel"
+    nc = sc.grid.n_cells
+    assert np.array_equal(sim.cell_start[:nc].cpu().numpy(), ob["start"]), "cell_start"
+    assert np.array_equal(sim.cell_end[:nc].cpu().numpy(), ob["end"]), "cell_end"
+    st = sim.status_host()
+    assert st["n_active"] == ob["n_active"] and st["dropped"] == ob["dropped"], (st, ob["n_active"])
+    assert st["overflow"] == ob["lists"].overflow, (st, ob["lists"].overflow)
+    fi, bi, fc, bc, nf, nbd = gpu_lists_padded(sim)
+    ofi, obi = oracle_lists_padded(ob["lists"], max_neibs)
+    if rows is not None:
+        fi, bi, fc, bc, ofi, obi = fi[rows], bi[rows], fc[rows], bc[rows], ofi[rows], obi[rows]
+        cells = ob["cell"]
+    else:
+        cells = ob["cell"]
+    assert np.array_equal(fi, ofi), "fluid neighbour sets"
+    assert np.array_equal(bi, obi), "boundary neighbour sets"
+    if st["overflow"] == 0:
+        sel = rows if rows is not None else slice(None)
+        ec_f = expected_codes_rows(sc.grid, cells, fi, sel)
+        ec_b = expected_codes_rows(sc.grid, cells, bi, sel)
+        assert np.array_equal(fc, ec_f), "fluid cell codes"
+        assert np.array_equal(bc, ec_b), "boundary cell codes"
+    return ob
+
+
+def expected_codes_rows(grid, cell, idx_rows, sel):
+    nx, ny, nz = (int(v) for v in grid.ncell)
+    lc = cell.astype(np.int64) - int(grid.cell_base)
+    c = np.stack([lc % nx, (lc // nx) % ny, lc // (nx * ny)], axis=1)
+    ci = c[sel]
+    valid = idx_rows != SENT
+    j = np.where(valid, idx_rows, 0)
+    code = np.zeros(idx_rows.shape, dtype=np.int64)
+    for d, nd in enumerate((nx, ny, nz)):
+        k = ci[:, d][:, None] - c[:, d][j]
+        if (grid.periodic >> d) & 1:
+            k = np.where(k > 1, k - nd, k)
+            k = np.where(k < -1, k + nd, k)
+        code |= (k + 1) << (2 * d)
+    return np.where(valid, code, -1)
+
+
+def oracle_forces_of(sc, ob, state_pos=None, state_vel=None, alpha=None):
+    pos = ob["pos"] if state_pos is None else state_pos
+    vel = ob["vel"] if state_vel is None else state_vel
+    st = O.State.lift(ob["cell"], pos, vel, ob["info"])
+    return st, O.forces(sc.grid, sc.params, st, ob["lists"], alpha)
+
+
+def check_forces(gpu_f, acc, drho, s_acc, s_drho, tol=FORCE_TOL, label=""):
+    """Returns the max normalised errors (acc, drho); asserts <= tol."""
+    ga = gpu_f[:, :3].astype(np.float64)
+    gd = gpu_f[:, 3].astype(np.float64)
+    ea = np.abs(ga - acc)
+    ed = np.abs(gd - drho)
+    za = s_acc == 0
+    zd = s_drho == 0
+    assert np.all(ga[za] == 0.0), label + ": nonzero acceleration with no interaction"
+    assert np.all(gd[zd] == 0.0), label + ": nonzero density rate with no interaction"
+    na = np.where(za, 0.0, ea / np.where(za, 1.0, s_acc))
+    nd = np.where(zd, 0.0, ed / np.where(zd, 1.0, s_drho))
+    worst_a, worst_d = float(na.max(initial=0.0)), float(nd.max(initial=0.0))
+    log("%s forces: max |da|/S = %.3e, max |dDrho|/S = %.3e" % (label, worst_a, worst_d))
+    assert worst_a <= tol, (label, worst_a, np.unravel_index(np.argmax(na), na.shape))
+    assert worst_d <= tol, (label, worst_d, int(np.argmax(nd)))
+    return worst_a, worst_d
+
+
+def torch_sync():
+    torch.cuda.synchronize()

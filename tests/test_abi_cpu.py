@@ -1,0 +1,85 @@
+"""Host-side checks of the C ABI (no GPU needed, no compute launched): the
+library loads, exports every function include/sph.h declares, and the
+ctypes structures match the C layout of the header."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sph.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sph_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def abi():
+    from paper_2207_11328_amd import abi as A
+    return A
+
+
+def test_every_declared_symbol_is_exported(abi):
+    names = _declared()
+    assert len(names) >= 9
+    for nm in names:
+        assert hasattr(abi.lib, nm), nm
+    assert sorted(abi.EXPORTS) == names
+
+
+def test_struct_layout_matches_header(abi, tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "sph.h"
+int main(void) {
+  printf("%zu %zu %zu %zu\\n", sizeof(sph_grid), offsetof(sph_grid, cell_size), offsetof(sph_grid, periodic), offsetof(sph_grid, cell_base));
+  printf("%zu %zu %zu\\n", sizeof(sph_params), offsetof(sph_params, g), offsetof(sph_params, visc_model));
+  printf("%zu %zu %zu %zu\\n", sizeof(sph_particles), offsetof(sph_particles, cell), offsetof(sph_particles, vel), offsetof(sph_particles, info));
+  return 0;
+}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I" + os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    g = [int(v) for v in out[0].split()]
+    assert g == [C.sizeof(abi.SphGrid), abi.SphGrid.cell_size.offset, abi.SphGrid.periodic.offset,
+                 abi.SphGrid.cell_base.offset]
+    p = [int(v) for v in out[1].split()]
+    assert p == [C.sizeof(abi.SphParams), abi.SphParams.g.offset, abi.SphParams.visc_model.offset]
+    q = [int(v) for v in out[2].split()]
+    assert q == [C.sizeof(abi.SphParticles), abi.SphParticles.cell.offset, abi.SphParticles.vel.offset,
+                 abi.SphParticles.info.offset]
+
+
+def test_host_only_entry_points(abi):
+    assert abi.lib.sph_abi_version() == 1
+    for code in range(4):
+        assert abi.lib.sph_status_string(code)
+    a = abi.sph_build_workspace_bytes(1000, 500)
+    b = abi.sph_build_workspace_bytes(2000, 500)
+    c = abi.sph_build_workspace_bytes(1000, 5000)
+    assert 0 < a < b and a < c
+    assert a % 256 == 0
+    assert abi.sph_dt_workspace_bytes() > 0
+
+
+def test_argument_errors_return_before_any_launch(abi):
+    """Null or inconsistent arguments are rejected synchronously."""
+    g = abi.SphGrid()
+    p = abi.SphParams()
+    parts = abi.SphParticles(10, 5, None, None, None, None)  # n > capacity
+    assert abi.lib.sph_forces(C.byref(g), C.byref(p), C.byref(parts), None, None, 128, None, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_forces(None, None, None, None, None, 128, None, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_build_neighbors(None, None, None, None, None, 128, None, None, None, None, 0,
+                                       None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_integrate(None, 0, None, None, None, None, None, None, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_integrate(C.byref(p), 2, None, None, None, None, None, None, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_step_dt(None, None, None, None, None, 0, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_count_interactions(None, None, None, None, None, 128, None, None) == abi.SPH_ERR_ARG

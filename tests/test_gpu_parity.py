@@ -1,0 +1,216 @@
+"""GPU parity of every C-ABI entry point against the FP64 oracle.
+
+Inputs are seeded and synthetic (workloads.scenes); both sides start from the
+same canonical float32 state.  See tests/parity.py for the tolerances.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from workloads import scenes as S
+
+from parity import (FORCE_TOL, U32, check_forces, compare_build, log, make_sim, oracle_forces_of,
+                    torch_sync)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _scenes():
+    return {
+        "still_water": lambda: S.still_water(),
+        "cloud_periodic_xyz": lambda: S.shuffled(S.random_cloud(n=3000, box=(0.3, 0.24, 0.2), dp=0.02,
+                                                                  periodic=0b111, seed=1), seed=2),
+        "cloud_open": lambda: S.shuffled(S.random_cloud(n=2500, box=(0.3, 0.2, 0.25), dp=0.02, seed=3,
+                                                        boundary_frac=0.35), seed=4),
+        "channel_small": lambda: S.channel(dp=0.02, length=0.6, width=0.3, depth=0.2, seed=6),
+        "laminar_cloud": lambda: S.random_cloud(n=2000, box=(0.2, 0.2, 0.2), dp=0.02, seed=7,
+                                                visc_model=1, nu=1e-3, u_sigma=0.3),
+        "dam_break_64k": lambda: S.dam_break_64k(),
+    }
+
+
+SCENES = _scenes()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+
+
+@pytest.mark.parametrize("name", list(SCENES))
+def test_build_and_forces_parity(name):
+    sc = SCENES[name]()
+    log("case %s: n=%d cells=%s" % (name, sc.n, list(sc.grid.ncell)))
+    sim = make_sim(sc)
+    sim.build()
+    sim.forces()
+    sim.count_interactions()
+    torch_sync()
+    ob = compare_build(sc, sim)
+    st, (acc, drho, sa, sd, ni) = oracle_forces_of(sc, ob)
+    gf = sim.forces_n[: sc.n].cpu().numpy()
+    check_forces(gf, acc, drho, sa, sd, label=name)
+    n32 = O.count_interactions_f32(sc.grid, sc.params, ob["cell"], ob["pos"], ob["lists"])
+    assert int(sim.count.item()) == n32
+    # the float32 mask and the double r < 2h may differ only at r ~ 2h, where F ~ 0
+    assert abs(n32 - ni) <= max(2, ni // 100000)
+
+
+@pytest.mark.parametrize("name", ["still_water", "cloud_open", "laminar_cloud"])
+def test_integrate_and_dt_parity(name):
+    sc = SCENES[name]()
+    log("case %s integrate" % name)
+    sim = make_sim(sc)
+    sim.build()
+    sim.forces()
+    sim.step_dt()
+    torch_sync()
+    ob = compare_build(sc, sim)
+    st, (acc, drho, sa, sd, ni) = oracle_forces_of(sc, ob)
+    dt_o = O.dt(sc.params, st, acc)
+    dt_g = float(sim.d_dt.item())
+    log("dt gpu %.9e oracle %.9e" % (dt_g, dt_o))
+    assert abs(dt_g - dt_o) <= 1e-5 * dt_o
+    # predictor with the oracle's dt fed to both sides
+    sim.d_dt.fill_(dt_o)
+    sim.integrate(0)
+    torch_sync()
+    star_o = O.integrate(sc.params, 0, dt_o, st, acc, drho)
+    tau = 0.5 * dt_o
+    _check_stage(sim, st, star_o, acc, drho, sa, sd, tau, sc.params, star=True)
+    # corrector: both sides evaluate the derivatives at the same predicted
+    # state (the oracle's, rounded to float32 and uploaded); in still water
+    # u* is a small residual of a ~ -g, so two independently predicted states
+    # differ by far more than the derivative kernel's own error
+    star32 = O.State.lift(ob["cell"], np.concatenate([star_o.off, star_o.mass[:, None]], 1).astype(np.float32),
+                          np.concatenate([star_o.vel, star_o.rho[:, None]], 1).astype(np.float32), ob["info"])
+    sim.pos_star[: sc.n] = torch.from_numpy(np.concatenate([star32.off, star32.mass[:, None]], 1).astype(np.float32)).cuda()
+    sim.vel_star[: sc.n] = torch.from_numpy(np.concatenate([star32.vel, star32.rho[:, None]], 1).astype(np.float32)).cuda()
+    sim.forces(star=True)
+    torch_sync()
+    acc2, drho2, sa2, sd2, _ = O.forces(sc.grid, sc.params, star32, ob["lists"])
+    gf2 = sim.forces_star[: sc.n].cpu().numpy()
+    check_forces(gf2, acc2, drho2, sa2, sd2, label=name + " stage1")
+    sim.integrate(1)
+    torch_sync()
+    new_o = O.integrate(sc.params, 1, dt_o, st, acc2, drho2, vel_star=star32.vel)
+    _check_stage(sim, st, new_o, acc2, drho2, sa2, sd2, dt_o, sc.params, star=False, uadv=star32.vel)
+    assert abs(sim.time - dt_o) <= 1e-15
+
+
+def _check_stage(sim, st, ref, acc, drho, sa, sd, tau, params, star, uadv=None):
+    n = st.n
+    pos = (sim.pos_star if star else sim.pos)[:n].cpu().numpy().astype(np.float64)
+    vel = (sim.vel_star if star else sim.vel)[:n].cpu().numpy().astype(np.float64)
+    g = np.array([O.f32(v) for v in params.g])
+    ua = st.vel if uadv is None else uadv
+    # one rounding of o + tau u (the advecting velocity is an exact input)
+    tol_o = 4 * U32 * (np.abs(st.off) + tau * np.abs(ua))
+    assert np.all(np.abs(pos[:, :3] - ref.off) <= tol_o + 1e-30), "offsets"
+    tol_u = 4 * U32 * (np.abs(st.vel) + tau * (np.abs(acc) + np.abs(g))) + tau * FORCE_TOL * 2 * sa
+    assert np.all(np.abs(vel[:, :3] - ref.vel) <= tol_u + 1e-30), "velocities"
+    tol_r = 4 * U32 * (np.abs(st.rho) + tau * np.abs(drho)) + tau * FORCE_TOL * 2 * sd
+    assert np.all(np.abs(vel[:, 3] - ref.rho) <= tol_r + 1e-30), "densities"
+    assert np.array_equal(pos[:, 3], st.mass), "mass untouched"
+
+
+def test_edge_empty_and_single():
+    sc = S.random_cloud(n=1, box=(0.2, 0.2, 0.2), dp=0.02, seed=1, boundary_frac=0.0)
+    sim = make_sim(sc, capacity=300)
+    sim.step()
+    torch_sync()
+    st = sim.status_host()
+    assert st == {"n_active": 1, "max_neibs": 0, "overflow": 0, "dropped": 0}
+    # free fall of the lone particle: midpoint is exact for constant g
+    sc0 = S.random_cloud(n=1, box=(0.2, 0.2, 0.2), dp=0.02, seed=1, boundary_frac=0.0)
+    dt = sim.time
+    gz = O.f32(sc0.params.g[2])
+    u0 = float(sc0.vel[0, 2])
+    assert abs(sim.vel[0, 2].item() - (u0 + gz * dt)) < 1e-6
+    # zero particles
+    sc2 = S.random_cloud(n=1, box=(0.2, 0.2, 0.2), dp=0.02, seed=1)
+    sim2 = make_sim(sc2, capacity=8)
+    sim2.n = 0
+    sim2.parts.n = 0
+    sim2.parts_star.n = 0
+    sim2.build()
+    sim2.forces()
+    torch_sync()
+    assert sim2.status_host() == {"n_active": 0, "max_neibs": 0, "overflow": 0, "dropped": 0}
+
+
+def test_dropped_particles_and_ragged_capacity():
+    sc = S.shuffled(S.random_cloud(n=2000, box=(0.3, 0.2, 0.2), dp=0.02, seed=12, boundary_frac=0.2), seed=1)
+    rng = np.random.default_rng(5)
+    # push some particles out of the (non-periodic) grid and one to NaN
+    k = rng.choice(sc.n, size=37, replace=False)
+    sc.pos[k[:30], 0] += np.float32(0.35)
+    sc.pos[k[30:36], 2] -= np.float32(0.3)
+    sc.pos[k[36], 1] = np.float32(np.nan)
+    sim = make_sim(sc, capacity=sc.n + 77)
+    sim.build()
+    sim.forces()
+    torch_sync()
+    ob = compare_build(sc, sim)
+    assert sim.status_host()["dropped"] == ob["dropped"] > 0
+    st, (acc, drho, sa, sd, ni) = oracle_forces_of(sc, ob)
+    check_forces(sim.forces_n[: sc.n].cpu().numpy(), acc, drho, sa, sd, label="dropped")
+    assert np.all(sim.neib_count[ob["n_active"]: sc.n].cpu().numpy() == 0)
+
+
+def test_neighbour_overflow_reported():
+    sc = S.periodic_box(n=9, dp=0.02, jitter=0.05, seed=3)
+    sim = make_sim(sc, max_neibs=60)
+    sim.build()
+    torch_sync()
+    ob = compare_build(sc, sim, max_neibs=60)
+    st = sim.status_host()
+    assert st["overflow"] == sc.n == ob["lists"].overflow
+    assert st["max_neibs"] >= 80
+    with pytest.raises(Exception):
+        sim.check_status()
+
+
+def test_deterministic_rebuild_and_forces():
+    sc = S.shuffled(S.dam_break(dp=0.02), seed=9)
+    a = make_sim(sc)
+    b = make_sim(sc)
+    for s in (a, b):
+        s.build()
+        s.forces()
+    torch_sync()
+    assert torch.equal(a.neibs, b.neibs) and torch.equal(a.neib_count, b.neib_count)
+    assert torch.equal(a.forces_n, b.forces_n)
+    # rebuilding a sorted state is the identity on the state and the lists
+    nb0 = a.neibs.clone()
+    p0 = a.pos.clone()
+    a.build()
+    torch_sync()
+    assert torch.equal(a.pos, p0) and torch.equal(a.neibs, nb0)
+
+
+def test_step_sequence_matches_oracle_rollout():
+    """Ten full steps (one rebuild) of the still-water tank: per-field error
+    against the double-precision oracle rollout stays at float32 level."""
+    sc = S.still_water()
+    sim = make_sim(sc)
+    sim.run(10)
+    torch_sync()
+    st = O.State.lift(sc.cell, sc.pos, sc.vel, sc.info)
+    st, t = O.rollout(sc.grid, sc.params, st, 10, rebuild_every=10)
+    g = sim.state_host()
+    order = np.argsort(g["info"])
+    oo = np.argsort(st.info)
+    assert np.array_equal(g["info"][order], st.info[oo])
+    assert np.array_equal(g["cell"][order], st.cell[oo])
+    dpos = np.abs(g["pos"][order, :3].astype(np.float64) - st.off[oo]).max()
+    dvel = np.abs(g["vel"][order, :3].astype(np.float64) - st.vel[oo]).max()
+    drho = np.abs(g["vel"][order, 3].astype(np.float64) - st.rho[oo]).max()
+    log("10-step rollout: max |dx| %.3e m  |du| %.3e m/s  |drho| %.3e kg/m3  t gpu %.9e oracle %.9e"
+        % (dpos, dvel, drho, sim.time, t))
+    assert abs(sim.time - t) <= 1e-5 * t
+    assert dpos < 1e-6 and dvel < 1e-4 and drho < 1e-2
