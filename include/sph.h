@@ -38,15 +38,20 @@
  * Neighbour list (sections "Efficient split neighbors list" and
  * "Changing perspective: from the particle to the cell")
  * -----------------------------------------------------
- * Fixed size, `max_neibs` slots per particle, neighbour-major: slot k of
- * particle i is neibs[k * capacity + i].  Fluid neighbours fill slots
+ * Fixed size, `max_neibs` slots per particle, neighbour-major inside tiles of
+ * 64 particles (one wave64):
+ *     slot k of particle i is neibs[(i / 64) * (64 * max_neibs) + 64 * k + i % 64]
+ * so slot k of 64 consecutive particles is one contiguous 256-byte row and
+ * every offset inside a tile fits 32 bits.  The array holds
+ * sph_neib_list_entries(capacity, max_neibs) entries.  Fluid neighbours fill slots
  * 0, 1, ... upwards, boundary neighbours fill max_neibs-1, max_neibs-2, ...
  * downwards.  neib_count[i] = n_fluid | n_boundary << 16 replaces the paper's
  * end-of-list marker.  A boundary particle lists fluid neighbours only.  Each
  * entry packs the neighbour's sorted index j (bits 0..25, so capacity is at
- * most 2^26) and the cell difference k_d = c_i,d - c_j,d + 1 in {0, 1, 2} of
- * each axis d (bits 26+2d .. 27+2d), periodic images already resolved.  The
- * separation is then x_ij = (k - 1) * cell_size + (o_i - o_j).
+ * most 2^26) and the cell difference k_d = c_i,d - c_j,d in {-1, 0, 1} of
+ * each axis d as a two's-complement 2-bit field (bits 26+2d .. 27+2d),
+ * periodic images already resolved.  The separation is then
+ * x_ij = k * cell_size + (o_i - o_j).
  *
  * A pair is listed iff, in float32 with every operation rounded,
  *   x_d = (k_d * cs_d) + (o_i,d - o_j,d),   r2 = (x*x + y*y) + z*z,
@@ -100,9 +105,11 @@ typedef struct {
  *              B = rho0 c0^2 / gamma (gamma = 7 only)
  *   alpha, eps_visc   Monaghan artificial viscosity
  *              Pi_ij = -alpha h cbar (u_ij.x_ij) / (rhobar (r^2 + eps h^2))
- *              for approaching pairs (visc_model 0)
+ *              for approaching pairs, cbar and rhobar arithmetic means
+ *              (always applied; alpha = 0 disables it)
  *   nu         kinematic viscosity of the Morris laminar term
- *              sum_j 4 nu m_j / (rho_i + rho_j) F_ij u_ij (visc_model 1)
+ *              sum_j 4 nu m_j / (rho_i + rho_j) F_ij u_ij, added when
+ *              visc_model = 1 (visc_model 0: no laminar term)
  *   g          body acceleration added to fluid particles by the integrator
  *   cfl        time-step safety factor */
 typedef struct {
@@ -128,6 +135,10 @@ const char *sph_status_string(sph_status s);
 /* ABI revision of this header (incremented on incompatible changes). */
 int32_t sph_abi_version(void);
 
+/* Number of uint32 entries of a neighbour list for `capacity` particles:
+ * ceil(capacity / 64) * 64 * max_neibs. */
+size_t sph_neib_list_entries(int32_t capacity, int32_t max_neibs);
+
 /* Bytes of device workspace sph_build_neighbors needs. */
 size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells);
 
@@ -142,7 +153,7 @@ size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells);
  *   3. cell ranges: particles of linear cell c (relative to cell_base) are
  *      [cell_start[c], cell_end[c]) (device int32[n_cells] each);
  *   4. build the split neighbour list described above into
- *      neibs (device uint32[max_neibs * capacity]) and
+ *      neibs (device uint32[sph_neib_list_entries(capacity, max_neibs)]) and
  *      neib_count (device uint32[capacity]); dropped particles get count 0;
  *   5. d_status (device int32[4], see SPH_STATUS_*) is overwritten.
  * A particle whose neighbours exceed max_neibs keeps the first max_neibs
@@ -167,10 +178,15 @@ sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
  * forces: device float[capacity][4], xyz = a_i [m/s^2], w = Drho_i/Dt,
  * fully overwritten for i < n.  Particles are read in the order of the last
  * build; positions may have drifted since (lists are reused).
- * Errors: SPH_ERR_ARG. */
+ * workspace: device buffer of sph_forces_workspace_bytes(capacity) bytes
+ * (per-particle equation-of-state terms, recomputed by every call).
+ * Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
 sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
                       const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
-                      float *forces, void *stream);
+                      float *forces, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Bytes of device workspace sph_forces needs. */
+size_t sph_forces_workspace_bytes(int32_t capacity);
 
 /* Explicit midpoint predictor/corrector (section "Code structure": phases
  * with dt/2 and dt).  d_dt: device double, the step.

@@ -14,7 +14,8 @@ import os
 import torch
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libsph.so")
+# SPH_LIB may name another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("SPH_LIB") or os.path.join(PKG, "libsph.so")
 
 SPH_OK, SPH_ERR_ARG, SPH_ERR_WORKSPACE, SPH_ERR_HIP = 0, 1, 2, 3
 STATUS_N_ACTIVE, STATUS_MAX_NEIBS, STATUS_OVERFLOW, STATUS_DROPPED = 0, 1, 2, 3
@@ -22,8 +23,9 @@ NEIB_INDEX_BITS = 26
 MAX_CAPACITY = 1 << NEIB_INDEX_BITS
 
 EXPORTS = [
-    "sph_status_string", "sph_abi_version", "sph_build_workspace_bytes", "sph_build_neighbors",
-    "sph_forces", "sph_integrate", "sph_dt_workspace_bytes", "sph_step_dt", "sph_count_interactions",
+    "sph_status_string", "sph_abi_version", "sph_neib_list_entries", "sph_build_workspace_bytes",
+    "sph_build_neighbors", "sph_forces", "sph_forces_workspace_bytes", "sph_integrate",
+    "sph_dt_workspace_bytes", "sph_step_dt", "sph_count_interactions",
 ]
 
 
@@ -58,11 +60,15 @@ def _load():
     L.sph_status_string.restype = C.c_char_p
     L.sph_abi_version.argtypes = []
     L.sph_abi_version.restype = i32
+    L.sph_neib_list_entries.argtypes = [i32, i32]
+    L.sph_neib_list_entries.restype = C.c_size_t
+    L.sph_forces_workspace_bytes.argtypes = [i32]
+    L.sph_forces_workspace_bytes.restype = C.c_size_t
     L.sph_build_workspace_bytes.argtypes = [i32, i32]
     L.sph_build_workspace_bytes.restype = C.c_size_t
     L.sph_build_neighbors.argtypes = [P, P, P, P, P, i32, P, P, P, P, C.c_size_t, P]
     L.sph_build_neighbors.restype = st
-    L.sph_forces.argtypes = [P, P, P, P, P, i32, P, P]
+    L.sph_forces.argtypes = [P, P, P, P, P, i32, P, P, C.c_size_t, P]
     L.sph_forces.restype = st
     L.sph_integrate.argtypes = [P, i32, P, P, P, P, P, P, P]
     L.sph_integrate.restype = st
@@ -131,6 +137,14 @@ def sph_build_workspace_bytes(capacity: int, n_cells: int) -> int:
     return int(lib.sph_build_workspace_bytes(int(capacity), int(n_cells)))
 
 
+def sph_neib_list_entries(capacity: int, max_neibs: int) -> int:
+    return int(lib.sph_neib_list_entries(int(capacity), int(max_neibs)))
+
+
+def sph_forces_workspace_bytes(capacity: int) -> int:
+    return int(lib.sph_forces_workspace_bytes(int(capacity)))
+
+
 def sph_dt_workspace_bytes() -> int:
     return int(lib.sph_dt_workspace_bytes())
 
@@ -144,9 +158,10 @@ def sph_build_neighbors(grid: SphGrid, params: SphParams, parts: SphParticles, n
 
 
 def sph_forces(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count, max_neibs: int,
-               forces, stream=None):
+               forces, workspace, stream=None):
     check(lib.sph_forces(C.byref(grid), C.byref(params), C.byref(parts), ptr(neibs), ptr(neib_count),
-                         int(max_neibs), ptr(forces), stream_ptr(stream)), "sph_forces")
+                         int(max_neibs), ptr(forces), ptr(workspace), workspace.numel() * workspace.element_size(),
+                         stream_ptr(stream)), "sph_forces")
 
 
 def sph_integrate(params: SphParams, stage: int, d_dt, state_n: SphParticles, vel_star, forces,

@@ -1,14 +1,22 @@
 // Time derivatives of the WCSPH step ("forces"): continuity, Cole equation
-// of state, golden-rule pressure gradient with Monaghan artificial or Morris
-// laminar viscosity, Wendland C2 kernel (arXiv:2207.11328, eq. mass-cont-sph1,
-// eq. ns-sph1, section "Minimizing complexity", listing l:ktemplate).
+// of state, golden-rule pressure gradient with Monaghan artificial viscosity
+// and the optional Morris laminar term, Wendland C2 kernel (arXiv:2207.11328,
+// eq. mass-cont-sph1, eq. ns-sph1, section "Minimizing complexity", listing
+// l:ktemplate).
 //
-// One lane per central particle gathers over its split neighbour list.  The
-// list is neighbour-major, so slot k of 64 consecutive centres is one
-// coalesced 256-byte load; the neighbours' pos/vel gathers hit L2 because
-// particles are sorted by cell.  Fluid and boundary segments are walked in a
-// single loop (slot k < nf from the front, the rest from the back) so lanes
-// with different fluid/boundary splits stay converged.
+// Layout of the work on gfx950:
+// * A prologue pass evaluates the equation of state once per particle
+//   (P/rho^2 and alpha h c), so the pair loop gathers 8 bytes instead of
+//   recomputing a 6th-order polynomial and a reciprocal per pair.
+// * One lane per central particle; the list is neighbour-major inside tiles
+//   of 64 particles, so slot k of a wave is one contiguous 256-byte row and
+//   its address is one 32-bit offset from the lane's tile base.
+// * The trip count is the wave's largest list (a scalar), lanes past their
+//   own count are masked, and fluid and boundary segments are walked in one
+//   loop (slot k < nf from the front, the rest from the back), so there is
+//   no divergent control flow in the pair loop.
+// * Loads are software-pipelined: list entries two pairs ahead, neighbour
+//   data one pair ahead, so each wave keeps several gathers in flight.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -30,14 +38,18 @@ struct ForceConst {
     float eps_h2;    // eps * h^2
     float four_nu;   // 4 nu
     int max_neibs;
-    int cap;
 };
 
 // Cole EOS for gamma = 7 in the expanded form P = B d (7 + 21d + 35d^2 +
-// 35d^3 + 21d^4 + 7d^5 + d^6), d = (rho - rho0)/rho0, which keeps full
-// relative accuracy near rho0; returns P/rho^2 and c = c0 (1 + d)^3.
-__device__ __forceinline__ void eos(float rho, const ForceConst &C, float &p_over_rho2, float &c)
+// 35d^3 + 21d^4 + 7d^5 + d^6), d = (rho - rho0)/rho0 (exact expansion of
+// (1 + d)^7 - 1, full relative accuracy near rho0).  aux = (P/rho^2, alpha h c)
+// with c = c0 (1 + d)^3.
+__global__ __launch_bounds__(kThreads) void k_eos(int n, const float4 *__restrict__ vel, float2 *__restrict__ aux,
+                                                  ForceConst C)
 {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const float rho = vel[i].w;
     const float d = (rho - C.rho0) * C.inv_rho0;
     float poly = 7.0f + d;
     poly = fmaf(poly, d, 21.0f);
@@ -46,86 +58,126 @@ __device__ __forceinline__ void eos(float rho, const ForceConst &C, float &p_ove
     poly = fmaf(poly, d, 21.0f);
     poly = fmaf(poly, d, 7.0f);
     const float P = C.B * d * poly;
-    const float inv_rho = __builtin_amdgcn_rcpf(rho);
-    p_over_rho2 = P * inv_rho * inv_rho;
+    const float inv_rho = 1.0f / rho;
     const float a = 1.0f + d;
-    c = C.c0 * a * a * a;
+    aux[i] = make_float2(P * inv_rho * inv_rho, C.alpha_h * (C.c0 * a * a * a));
 }
 
-__device__ __forceinline__ float unpack_shift(uint32_t e, int axis, float cs)
+// Cell difference k_d in {-1, 0, 1} of axis d, stored as a two's-complement
+// 2-bit field at bit 26 + 2d of a list entry.
+__device__ __forceinline__ float entry_k(uint32_t e, int axis)
 {
-    const float b = (float)((e >> (26 + 2 * axis)) & 3u);
-    return fmaf(b, cs, -cs);  // (b - 1) * cs, exact
+    return (float)((int32_t)(e << (4 - 2 * axis)) >> 30);
+}
+
+__device__ __forceinline__ int list_slot(int k, int nf, int last, int M)
+{
+    const int kk = min(k, last);
+    return kk < nf ? kk : M - 1 + nf - kk;
+}
+
+struct PairAcc {
+    float ax, ay, az, dr;
+};
+
+// One pair (i, j) of the derivative sums, branch-free; contributes only when
+// `valid` (slot inside i's list) and r < 2h.
+template <int VISC>
+__device__ __forceinline__ void pair_terms(PairAcc &A, uint32_t e, const float4 &pi, const float4 &vi,
+                                           const float2 &ai, const float4 &pj, const float4 &vj, const float2 &aj,
+                                           bool valid, const ForceConst &C)
+{
+    // separation, bit-identical to the list predicate: x = k cs + (o_i - o_j)
+    const float xx = fmaf(entry_k(e, 0), C.csx, pi.x - pj.x);
+    const float xy = fmaf(entry_k(e, 1), C.csy, pi.y - pj.y);
+    const float xz = fmaf(entry_k(e, 2), C.csz, pi.z - pj.z);
+    float r2;
+    {
+#pragma clang fp contract(off)
+        r2 = (xx * xx + xy * xy) + xz * xz;
+    }
+    const bool inter = valid && (r2 < C.lim2);
+    const float r = __builtin_amdgcn_sqrtf(r2);
+    const float qm2 = fmaf(r, C.inv_h, -2.0f);
+    const float mF = (qm2 * qm2) * (qm2 * C.fcoeff) * pj.w;  // m_j F_ij
+    const float ux = vi.x - vj.x;
+    const float uy = vi.y - vj.y;
+    const float uz = vi.z - vj.z;
+    const float udx = fmaf(ux, xx, fmaf(uy, xy, uz * xz));
+    A.dr = inter ? fmaf(mF, udx, A.dr) : A.dr;
+    // Monaghan: Pi = -alpha h (c_i + c_j)/2 min(u.x, 0) / ((rho_i + rho_j)/2 (r^2 + eps h^2))
+    const float den = (vi.w + vj.w) * (r2 + C.eps_h2);
+    const float visc = -(ai.y + aj.y) * fminf(udx, 0.0f) * __builtin_amdgcn_rcpf(den);
+    const float coef = inter ? -mF * (ai.x + aj.x + visc) : 0.0f;
+    A.ax = fmaf(coef, xx, A.ax);
+    A.ay = fmaf(coef, xy, A.ay);
+    A.az = fmaf(coef, xz, A.az);
+    if (VISC == 1) {
+        const float lam = inter ? C.four_nu * mF * __builtin_amdgcn_rcpf(vi.w + vj.w) : 0.0f;
+        A.ax = fmaf(lam, ux, A.ax);
+        A.ay = fmaf(lam, uy, A.ay);
+        A.az = fmaf(lam, uz, A.az);
+    }
 }
 
 template <int VISC>
 __global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__restrict__ pos,
                                                      const float4 *__restrict__ vel,
+                                                     const float2 *__restrict__ aux,
                                                      const uint32_t *__restrict__ neibs,
                                                      const uint32_t *__restrict__ count,
                                                      float4 *__restrict__ out, ForceConst C)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t cnt = count[i];
-    // counts and indices are clamped so that a stale or foreign list can give
-    // wrong numbers but never an out-of-bounds access
-    const int nf = min((int)(cnt & 0xFFFFu), C.max_neibs);
-    const int nt = min(nf + (int)(cnt >> 16), C.max_neibs);
-    const uint32_t jmax = (uint32_t)(n - 1);
-    const float4 pi = pos[i];
-    const float4 vi = vel[i];
-    const float rhoi = vi.w;
-    float pri, ci;
-    eos(rhoi, C, pri, ci);
-    float ax = 0.0f, ay = 0.0f, az = 0.0f, dr = 0.0f;
-    const uint32_t *col = neibs + i;
-    for (int k = 0; k < nt; ++k) {
-        const int slot = k < nf ? k : C.max_neibs - 1 + nf - k;
-        const uint32_t e = col[(size_t)slot * C.cap];
-        const uint32_t j = min(e & kIndexMask, jmax);
-        const float tx = unpack_shift(e, 0, C.csx);
-        const float ty = unpack_shift(e, 1, C.csy);
-        const float tz = unpack_shift(e, 2, C.csz);
-        const float4 pj = pos[j];
-        const float4 vj = vel[j];
-        const float r2 = predicate_r2(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, tx, ty, tz);
-        if (r2 < C.lim2) {
-            const float xx = tx + (pi.x - pj.x);
-            const float xy = ty + (pi.y - pj.y);
-            const float xz = tz + (pi.z - pj.z);
-            const float r = __builtin_amdgcn_sqrtf(r2);
-            const float qm2 = fmaf(r, C.inv_h, -2.0f);
-            const float F = C.fcoeff * qm2 * qm2 * qm2;
-            const float ux = vi.x - vj.x;
-            const float uy = vi.y - vj.y;
-            const float uz = vi.z - vj.z;
-            const float udx = fmaf(ux, xx, fmaf(uy, xy, uz * xz));
-            const float mF = pj.w * F;
-            dr = fmaf(mF, udx, dr);
-            const float rhoj = vj.w;
-            float prj, cj;
-            eos(rhoj, C, prj, cj);
-            float visc = 0.0f;
-            if (udx < 0.0f) {
-                // -alpha h cbar udx / (rhobar (r2 + eps h^2)) with the two
-                // halves of the averages cancelling
-                const float den = (rhoi + rhoj) * (r2 + C.eps_h2);
-                visc = -C.alpha_h * (ci + cj) * udx * __builtin_amdgcn_rcpf(den);
-            }
-            const float coef = -mF * (pri + prj + visc);
-            ax = fmaf(coef, xx, ax);
-            ay = fmaf(coef, xy, ay);
-            az = fmaf(coef, xz, az);
-            if (VISC == 1) {
-                const float lam = C.four_nu * mF * __builtin_amdgcn_rcpf(rhoi + rhoj);
-                ax = fmaf(lam, ux, ax);
-                ay = fmaf(lam, uy, ay);
-                az = fmaf(lam, uz, az);
-            }
-        }
+    const int lane = threadIdx.x % kWave;
+    const int ii = min(i, n - 1);  // lanes past the end load in bounds and store nothing
+    const int M = C.max_neibs;
+    const uint32_t cnt = i < n ? count[i] : 0u;
+    // counts and indices are clamped: a stale or foreign list gives wrong
+    // numbers but never an out-of-bounds access
+    const int nf = min((int)(cnt & 0xFFFFu), M);
+    const int nt = min(nf + (int)(cnt >> 16), M);
+    const int last = max(nt - 1, 0);
+    const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
+    if (ntw == 0) {
+        if (i < n) out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        return;
     }
-    out[i] = make_float4(ax, ay, az, dr);
+    // a wave is exactly one 64-particle tile of the list (wave-uniform base)
+    const int tile_id = __builtin_amdgcn_readfirstlane(i / kWave);
+    const uint32_t *tile = neibs + (size_t)tile_id * (kWave * M);
+    const uint32_t jmax = (uint32_t)(n - 1);
+
+    const float4 pi = pos[ii];
+    const float4 vi = vel[ii];
+    const float2 ai = aux[ii];
+    PairAcc A = {0.0f, 0.0f, 0.0f, 0.0f};
+
+    // Software pipeline, unrolled by two.  Entry k+2 is requested before pair k
+    // is evaluated and the neighbour data of pair k+1 while pair k is being
+    // evaluated; the data registers of set A are only ever written by loads,
+    // so the loop carries no copy of an in-flight value.
+    uint32_t eA = tile[list_slot(0, nf, last, M) * kWave + lane];
+    uint32_t eNext = tile[list_slot(1, nf, last, M) * kWave + lane];
+    uint32_t jA = min(eA & kIndexMask, jmax);
+    float4 pA = pos[jA], vA = vel[jA];
+    float2 xA = aux[jA];
+    for (int k = 0; k < ntw; k += 2) {
+        const uint32_t eN2 = tile[list_slot(k + 2, nf, last, M) * kWave + lane];
+        const uint32_t eB = eNext;
+        const uint32_t jB = min(eB & kIndexMask, jmax);
+        const float4 pB = pos[jB], vB = vel[jB];
+        const float2 xB = aux[jB];
+        pair_terms<VISC>(A, eA, pi, vi, ai, pA, vA, xA, k < nt, C);
+        eNext = tile[list_slot(k + 3, nf, last, M) * kWave + lane];
+        eA = eN2;
+        jA = min(eA & kIndexMask, jmax);
+        pA = pos[jA];
+        vA = vel[jA];
+        xA = aux[jA];
+        pair_terms<VISC>(A, eB, pi, vi, ai, pB, vB, xB, k + 1 < nt, C);
+    }
+    if (i < n) out[i] = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 __global__ __launch_bounds__(kThreads) void k_count_interactions(int n, const float4 *__restrict__ pos,
@@ -137,17 +189,18 @@ __global__ __launch_bounds__(kThreads) void k_count_interactions(int n, const fl
     const int i = blockIdx.x * kThreads + threadIdx.x;
     unsigned long long c = 0;
     if (i < n) {
+        const int M = C.max_neibs;
         const uint32_t cnt = count[i];
-        const int nf = min((int)(cnt & 0xFFFFu), C.max_neibs);
-        const int nt = min(nf + (int)(cnt >> 16), C.max_neibs);
+        const int nf = min((int)(cnt & 0xFFFFu), M);
+        const int nt = min(nf + (int)(cnt >> 16), M);
         const uint32_t jmax = (uint32_t)(n - 1);
+        const uint32_t *tile = neibs + (size_t)(i / kWave) * (kWave * M) + (i % kWave);
         const float4 pi = pos[i];
         for (int k = 0; k < nt; ++k) {
-            const int slot = k < nf ? k : C.max_neibs - 1 + nf - k;
-            const uint32_t e = neibs[(size_t)slot * C.cap + i];
+            const uint32_t e = tile[list_slot(k, nf, nt - 1, M) * kWave];
             const float4 pj = pos[min(e & kIndexMask, jmax)];
-            const float r2 = predicate_r2(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, unpack_shift(e, 0, C.csx),
-                                          unpack_shift(e, 1, C.csy), unpack_shift(e, 2, C.csz));
+            const float r2 = predicate_r2(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, entry_k(e, 0) * C.csx,
+                                          entry_k(e, 1) * C.csy, entry_k(e, 2) * C.csz);
             c += r2 < C.lim2 ? 1ull : 0ull;
         }
     }
@@ -157,8 +210,7 @@ __global__ __launch_bounds__(kThreads) void k_count_interactions(int n, const fl
 
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
 
-bool make_const(const sph_grid *g, const sph_params *p, const sph_particles *parts, int max_neibs,
-                ForceConst &C)
+bool make_const(const sph_grid *g, const sph_params *p, int max_neibs, ForceConst &C)
 {
     if (!(p->h > 0.0f) || !(p->rho0 > 0.0f) || !(p->c0 > 0.0f) || p->gamma != 7.0f) return false;
     if (p->visc_model != 0 && p->visc_model != 1) return false;
@@ -180,7 +232,6 @@ bool make_const(const sph_grid *g, const sph_params *p, const sph_particles *par
     C.eps_h2 = (float)((double)p->eps_visc * h * h);
     C.four_nu = (float)(4.0 * (double)p->nu);
     C.max_neibs = max_neibs;
-    C.cap = parts->capacity;
     return true;
 }
 
@@ -194,26 +245,37 @@ bool common_args(const sph_grid *g, const sph_params *p, const sph_particles *pa
     return true;
 }
 
+size_t aux_bytes(int64_t capacity) { return (size_t)((sizeof(float2) * capacity + 255) & ~(int64_t)255); }
+
 }  // namespace
+
+extern "C" size_t sph_forces_workspace_bytes(int32_t capacity)
+{
+    if (capacity < 0) return 0;
+    return aux_bytes(capacity > 0 ? capacity : 1);
+}
 
 extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
                                  const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
-                                 float *forces, void *stream)
+                                 float *forces, void *workspace, size_t workspace_bytes, void *stream)
 {
     if (!common_args(grid, params, parts, neibs, neib_count, max_neibs)) return SPH_ERR_ARG;
     if (parts->n > 0 && !forces) return SPH_ERR_ARG;
     ForceConst C;
-    if (!make_const(grid, params, parts, max_neibs, C)) return SPH_ERR_ARG;
+    if (!make_const(grid, params, max_neibs, C)) return SPH_ERR_ARG;
+    if (!workspace || workspace_bytes < sph_forces_workspace_bytes(parts->capacity)) return SPH_ERR_WORKSPACE;
     const int n = parts->n;
     if (n == 0) return SPH_OK;
     hipStream_t s = (hipStream_t)stream;
     const float4 *pos = (const float4 *)parts->pos;
     const float4 *vel = (const float4 *)parts->vel;
+    float2 *aux = (float2 *)workspace;
     float4 *out = (float4 *)forces;
+    k_eos<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, vel, aux, C);
     if (params->visc_model == 0)
-        k_forces<0><<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, pos, vel, neibs, neib_count, out, C);
+        k_forces<0><<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, pos, vel, aux, neibs, neib_count, out, C);
     else
-        k_forces<1><<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, pos, vel, neibs, neib_count, out, C);
+        k_forces<1><<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, pos, vel, aux, neibs, neib_count, out, C);
     SPH_CHECK_LAUNCH();
     return SPH_OK;
 }
@@ -225,7 +287,7 @@ extern "C" sph_status sph_count_interactions(const sph_grid *grid, const sph_par
 {
     if (!common_args(grid, params, parts, neibs, neib_count, max_neibs) || !d_count) return SPH_ERR_ARG;
     ForceConst C;
-    if (!make_const(grid, params, parts, max_neibs, C)) return SPH_ERR_ARG;
+    if (!make_const(grid, params, max_neibs, C)) return SPH_ERR_ARG;
     hipStream_t s = (hipStream_t)stream;
     k_zero_u64<<<1, 1, 0, s>>>(d_count);
     SPH_CHECK_LAUNCH();

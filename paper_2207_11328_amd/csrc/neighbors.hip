@@ -286,7 +286,7 @@ __global__ void k_status(int n, int n_cells, const int32_t *__restrict__ start, 
 // Inside a cell fluid particles precede boundary ones, so a boundary centre
 // stops at the first boundary neighbour of each cell.
 __global__ __launch_bounds__(kThreads) void k_build_lists(
-    int n, int capacity, int max_neibs, const int32_t *__restrict__ cell, const float4 *__restrict__ pos,
+    int n, int max_neibs, const int32_t *__restrict__ cell, const float4 *__restrict__ pos,
     const uint32_t *__restrict__ info, const int32_t *__restrict__ start, CellDims dims, float csx,
     float csy, float csz, int cell_base, float rs2, uint32_t *__restrict__ neibs,
     uint32_t *__restrict__ neib_count, int32_t *__restrict__ status)
@@ -302,6 +302,7 @@ __global__ __launch_bounds__(kThreads) void k_build_lists(
     cell_coords(ci - cell_base, dims, cx, cy, cz);
     const float4 pi = pos[i];
     const bool central_boundary = ptype(info[i]) == kBoundary;
+    uint32_t *tile = neibs + (size_t)(i / kWave) * kWave * max_neibs + (i % kWave);
     int nf = 0, nb = 0, wf = 0, wb = 0;
     for (int dz = -1; dz <= 1; ++dz) {
         int jz = cz + dz;
@@ -331,13 +332,13 @@ __global__ __launch_bounds__(kThreads) void k_build_lists(
                     const uint32_t entry = pack_neib((uint32_t)j, -dx, -dy, -dz);
                     if (nb_boundary) {
                         if (wf + wb < max_neibs) {
-                            neibs[(size_t)(max_neibs - 1 - wb) * capacity + i] = entry;
+                            tile[(max_neibs - 1 - wb) * kWave] = entry;
                             ++wb;
                         }
                         ++nb;
                     } else {
                         if (wf + wb < max_neibs) {
-                            neibs[(size_t)wf * capacity + i] = entry;
+                            tile[wf * kWave] = entry;
                             ++wf;
                         }
                         ++nf;
@@ -365,6 +366,12 @@ bool grid_ok(const sph_grid *g, float r_search)
 }
 
 }  // namespace
+
+extern "C" size_t sph_neib_list_entries(int32_t capacity, int32_t max_neibs)
+{
+    if (capacity < 0 || max_neibs < 0) return 0;
+    return (size_t)((capacity + kWave - 1) / kWave) * kWave * (size_t)max_neibs;
+}
 
 extern "C" size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells)
 {
@@ -437,7 +444,7 @@ extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params
         SPH_CHECK_LAUNCH();
         const float rs2 = params->r_search * params->r_search;
         k_build_lists<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(
-            n, cap, max_neibs, t_cell, t_pos, t_info, start, dims, grid->cell_size[0], grid->cell_size[1],
+            n, max_neibs, t_cell, t_pos, t_info, start, dims, grid->cell_size[0], grid->cell_size[1],
             grid->cell_size[2], grid->cell_base, rs2, neibs, neib_count, d_status);
         k_copy_state<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, t_cell, t_pos, t_vel, t_info, parts->cell,
                                                                    pos, vel, parts->info);

@@ -53,10 +53,11 @@ __device__ __forceinline__ float cell_shift(int k, float cs)
     return k == 0 ? 0.0f : (k > 0 ? cs : -cs);
 }
 
-// Neighbour entry: sorted index plus (c_i - c_j + 1) per axis in 2-bit fields.
+// Neighbour entry: sorted index plus k_d = c_i,d - c_j,d in {-1, 0, 1} per
+// axis as two's-complement 2-bit fields at bits 26, 28, 30.
 __device__ __forceinline__ uint32_t pack_neib(uint32_t j, int kx, int ky, int kz)
 {
-    return j | (uint32_t)(kx + 1) << 26 | (uint32_t)(ky + 1) << 28 | (uint32_t)(kz + 1) << 30;
+    return j | ((uint32_t)kx & 3u) << 26 | ((uint32_t)ky & 3u) << 28 | ((uint32_t)kz & 3u) << 30;
 }
 
 template <typename T>

@@ -55,13 +55,14 @@ class Simulation:
         self.vel_star = z((cap, 4), torch.float32)
         self.forces_n = z((cap, 4), torch.float32)
         self.forces_star = z((cap, 4), torch.float32)
-        self.neibs = z(self.max_neibs * cap, torch.int32)
+        self.neibs = z(abi.sph_neib_list_entries(cap, self.max_neibs), torch.int32)
         self.neib_count = z(cap, torch.int32)
         self.cell_start = z(max(self.n_cells, 1), torch.int32)
         self.cell_end = z(max(self.n_cells, 1), torch.int32)
         self.status = z(4, torch.int32)
         self.ws_build = z(abi.sph_build_workspace_bytes(cap, self.n_cells), torch.uint8)
         self.ws_dt = z(abi.sph_dt_workspace_bytes(), torch.uint8)
+        self.ws_forces = z(abi.sph_forces_workspace_bytes(cap), torch.uint8)
         self.d_dt = z(1, torch.float64)
         self.d_time = z(1, torch.float64)
         self.count = z(1, torch.int64)
@@ -88,7 +89,8 @@ class Simulation:
     def forces(self, star: bool = False, stream=None):
         parts = self.parts_star if star else self.parts
         out = self.forces_star if star else self.forces_n
-        abi.sph_forces(self.g, self.p, parts, self.neibs, self.neib_count, self.max_neibs, out, stream)
+        abi.sph_forces(self.g, self.p, parts, self.neibs, self.neib_count, self.max_neibs, out, self.ws_forces,
+                       stream)
         return out
 
     def step_dt(self, stream=None):
@@ -145,27 +147,13 @@ class Simulation:
         }
 
     def lists_host(self):
-        """(neibs [max_neibs, capacity] uint32, neib_count [n] uint32)."""
-        nb = self.neibs.view(self.max_neibs, self.capacity).cpu().numpy().view(np.uint32)
+        """(neibs [max_neibs, n] uint32 in slot-major order, neib_count [n] uint32)."""
+        M = self.max_neibs
+        t = self.neibs.view(-1, M, 64).cpu().numpy().view(np.uint32)  # [tile, slot, lane]
+        nb = t.transpose(1, 0, 2).reshape(M, -1)[:, : self.n]
         cnt = self.neib_count[: self.n].cpu().numpy().view(np.uint32)
-        return nb, cnt
+        return np.ascontiguousarray(nb), cnt
 
     @property
     def time(self) -> float:
         return float(self.d_time.item())
-
-
-def decode_lists(neibs: np.ndarray, count: np.ndarray, max_neibs: int):
-    """Split neighbour-major lists -> (fluid index arrays, boundary index arrays,
-    fluid codes, boundary codes) per particle, in list order."""
-    mask = (1 << abi.NEIB_INDEX_BITS) - 1
-    n = count.shape[0]
-    nf = (count & 0xFFFF).astype(np.int64)
-    nb = (count >> 16).astype(np.int64)
-    fl, bl = [], []
-    for i in range(n):
-        fe = neibs[: nf[i], i]
-        be = neibs[max_neibs - nb[i]:, i][::-1] if nb[i] > 0 else neibs[:0, i]
-        fl.append(fe)
-        bl.append(be)
-    return fl, bl, mask

@@ -85,7 +85,7 @@ def expected_codes(grid, cell, idx_sorted):
         if (grid.periodic >> d) & 1:
             k = np.where(k > 1, k - nd, k)
             k = np.where(k < -1, k + nd, k)
-        code |= (k + 1) << (2 * d)
+        code |= (k & 3) << (2 * d)
     return np.where(valid, code, -1)
 
 
@@ -136,7 +136,7 @@ def expected_codes_rows(grid, cell, idx_rows, sel):
         if (grid.periodic >> d) & 1:
             k = np.where(k > 1, k - nd, k)
             k = np.where(k < -1, k + nd, k)
-        code |= (k + 1) << (2 * d)
+        code |= (k & 3) << (2 * d)
     return np.where(valid, code, -1)
 
 
