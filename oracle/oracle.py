@@ -102,18 +102,21 @@ def grid_struct(grid) -> OrcGrid:
 
 
 def params_struct(p, alpha=None) -> OrcParams:
+    """Parameters as the GPU receives them (float32 values lifted to double),
+    unless p.exact_values is set (finite-difference checks of the oracle)."""
+    rnd = float if getattr(p, "exact_values", False) else f32
     q = OrcParams()
-    q.h = f32(p.h)
-    q.r_search = f32(p.r_search)
-    q.rho0 = f32(p.rho0)
-    q.gamma = f32(p.gamma)
-    q.c0 = f32(p.c0)
-    q.alpha = f32(p.alpha if alpha is None else alpha)
-    q.eps_visc = f32(p.eps_visc)
-    q.nu = f32(p.nu)
+    q.h = rnd(p.h)
+    q.r_search = rnd(p.r_search)
+    q.rho0 = rnd(p.rho0)
+    q.gamma = rnd(p.gamma)
+    q.c0 = rnd(p.c0)
+    q.alpha = rnd(p.alpha if alpha is None else alpha)
+    q.eps_visc = rnd(p.eps_visc)
+    q.nu = rnd(p.nu)
     for d in range(3):
-        q.g[d] = f32(p.g[d])
-    q.cfl = f32(p.cfl)
+        q.g[d] = rnd(p.g[d])
+    q.cfl = rnd(p.cfl)
     q.visc_model = int(p.visc_model)
     return q
 
@@ -347,3 +350,133 @@ def positions(grid, st: State) -> np.ndarray:
     c = np.stack([lc % nx, (lc // nx) % ny, lc // (nx * ny)], axis=1).astype(np.float64)
     cs = np.asarray(grid.cell_size, dtype=np.float32).astype(np.float64)
     return np.asarray(grid.origin, dtype=np.float64)[None, :] + (c + 0.5) * cs[None, :] + st.off
+
+
+# ---------------------------------------------------------------- reverse mode
+def _setup_reverse():
+    L = lib()
+    if getattr(L, "_rev_ready", False):
+        return L
+    P = C.c_void_p
+    i32 = C.c_int
+    L.orc_forces_reverse.argtypes = [P, P, i32, P, P, P, P, P, P, P, P, P, P, i32, P, P, P, P, P, P]
+    L.orc_forces_reverse.restype = None
+    L.orc_integrate_reverse.argtypes = [i32, C.c_double, i32, P, P, P, P, P, P, P, P, P, P, P]
+    L.orc_integrate_reverse.restype = None
+    L._rev_ready = True
+    return L
+
+
+class Adj:
+    """Adjoint of a double state: offsets, velocities, densities."""
+
+    def __init__(self, go, gu, grho):
+        self.go = np.ascontiguousarray(go, dtype=np.float64)
+        self.gu = np.ascontiguousarray(gu, dtype=np.float64)
+        self.grho = np.ascontiguousarray(grho, dtype=np.float64)
+
+    @staticmethod
+    def zeros(n):
+        return Adj(np.zeros((n, 3)), np.zeros((n, 3)), np.zeros(n))
+
+    def copy(self):
+        return Adj(self.go.copy(), self.gu.copy(), self.grho.copy())
+
+    def __add__(self, o):
+        return Adj(self.go + o.go, self.gu + o.gu, self.grho + o.grho)
+
+
+def forces_reverse(grid, params, st: State, lists: Lists, abar, dbar, into: Adj | None = None, alpha=None):
+    """Adds the reverse of forces() for upstream (abar, dbar) to `into` (or a
+    new zero adjoint).  Returns (adjoint, gparams[alpha, c0, nu])."""
+    L = _setup_reverse()
+    adj = Adj.zeros(st.n) if into is None else into
+    gp = np.zeros(3)
+    g = grid_struct(grid)
+    ps = params_struct(params, alpha)
+    abar = np.ascontiguousarray(abar, dtype=np.float64)
+    dbar = np.ascontiguousarray(dbar, dtype=np.float64)
+    L.orc_forces_reverse(C.byref(ps), C.byref(g), st.n, _p(st.cell), _p(st.off), _p(st.mass), _p(st.vel),
+                         _p(st.rho), _p(st.info), _p(lists.nf), _p(lists.nb), _p(lists.fl), _p(lists.bl),
+                         lists.max_neibs, _p(abar), _p(dbar), _p(adj.go), _p(adj.gu), _p(adj.grho), _p(gp))
+    return adj, gp
+
+
+def integrate_reverse(stage, dt, st_n: State, adj_out: Adj):
+    """Returns (adjoint of stage inputs without the derivative terms,
+    gu_star (stage 1 only, else None), abar, dbar)."""
+    L = _setup_reverse()
+    n = st_n.n
+    out = Adj.zeros(n)
+    gu_star = np.zeros((n, 3)) if stage == 1 else None
+    abar = np.zeros((n, 3))
+    dbar = np.zeros(n)
+    L.orc_integrate_reverse(int(stage), float(dt), n, _p(st_n.cell), _p(st_n.info), _p(adj_out.go),
+                            _p(adj_out.gu), _p(adj_out.grho), _p(out.go), _p(out.gu), _p(out.grho),
+                            _p(gu_star) if gu_star is not None else None, _p(abar), _p(dbar))
+    return out, gu_star, abar, dbar
+
+
+def step_reverse(grid, params, st_n: State, star: State, lists: Lists, dt, adj_next: Adj, alpha=None):
+    """Reverse of step() with fixed dt: adjoint of state n and gparams."""
+    gp = np.zeros(3)
+    base1, gu_star, abar1, dbar1 = integrate_reverse(1, dt, st_n, adj_next)
+    adj_star = Adj(np.zeros((st_n.n, 3)), gu_star, np.zeros(st_n.n))
+    adj_star, g1 = forces_reverse(grid, params, star, lists, abar1, dbar1, into=adj_star, alpha=alpha)
+    base0, _, abar0, dbar0 = integrate_reverse(0, dt, st_n, adj_star)
+    adj_n = base1 + base0
+    adj_n, g0 = forces_reverse(grid, params, st_n, lists, abar0, dbar0, into=adj_n, alpha=alpha)
+    return adj_n, g0 + g1
+
+
+def rollout_adjoint(grid, params, st0: State, steps: int, dt: float, loss_and_grad, rebuild_every: int = 10,
+                    max_neibs: int = 128):
+    """Double-precision rollout with a fixed time step and its reverse.
+
+    loss_and_grad(final_state) -> (L, Adj of the final state).  Returns
+    (L, Adj of st0 in st0's particle order, gparams[alpha, c0, nu], final state).
+    Every state is kept (test sizes only)."""
+    tape = []
+    st = st0
+    lists = None
+    for s in range(steps):
+        if s % rebuild_every == 0 or lists is None:
+            st, lists, perm, _ = rebuild_f64(grid, params, st, max_neibs)
+            tape.append(("perm", perm))
+        acc, drho, _, _, _ = forces(grid, params, st, lists)
+        star = integrate(params, 0, dt, st, acc, drho)
+        acc2, drho2, _, _, _ = forces(grid, params, star, lists)
+        new = integrate(params, 1, dt, st, acc2, drho2, vel_star=star.vel)
+        tape.append(("step", st, star, lists))
+        st = new
+    Lval, adj = loss_and_grad(st)
+    gp = np.zeros(3)
+    for rec in reversed(tape):
+        if rec[0] == "step":
+            _, st_n, star, lists = rec
+            adj, g = step_reverse(grid, params, st_n, star, lists, dt, adj)
+            gp += g
+        else:
+            perm = rec[1]
+            back = Adj.zeros(adj.go.shape[0])
+            back.go[perm] = adj.go
+            back.gu[perm] = adj.gu
+            back.grho[perm] = adj.grho
+            adj = back
+    return Lval, adj, gp, st
+
+
+def front_loss(grid, front_ids):
+    """L = mean x of the particles whose ids are front_ids; returns a
+    loss_and_grad callable for rollout_adjoint."""
+    ids = np.asarray(front_ids, dtype=np.int64)
+
+    def f(st: State):
+        x = positions(grid, st)
+        pid = (st.info & np.uint32((1 << TYPE_SHIFT) - 1)).astype(np.int64)
+        sel = np.isin(pid, ids)
+        L = x[sel, 0].mean()
+        adj = Adj.zeros(st.n)
+        adj.go[sel, 0] = 1.0 / sel.sum()
+        return L, adj
+    return f

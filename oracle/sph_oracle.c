@@ -531,3 +531,142 @@ double orc_dt(const orc_params *p, int n, const int32_t *cell, const uint32_t *i
     if (p->nu > 0.0) { const double t = 0.125 * p->h * p->h / p->nu; if (t < dt) dt = t; }
     return p->cfl * dt;
 }
+
+/* ------------------------------------------------------------------------
+ * Reverse (adjoint) of orc_forces with the lists held fixed.
+ *
+ * Forward pair term of central c and neighbour n (r < 2h):
+ *   a_c += G x + Lm u,   Drho_c += m_n F w,
+ *   G = -m_n (p_c + p_n + Pi) F,  Lm = 4 nu m_n F / (rho_c + rho_n) (laminar),
+ *   w = u . x,  Pi = K min(w, 0) / (r^2 + eps h^2),  K = -alpha h (c_c + c_n)/(rho_c + rho_n).
+ * Given the upstream adjoints abar_c (3) and dbar_c of every central, the
+ * derivative of T = abar_c . (G x + Lm u) + dbar_c m_n F w with respect to
+ * x = x_c - x_n, u = u_c - u_n, rho_c, rho_n and (alpha, c0, nu) is formed and
+ * scattered: +x/+u to the central, -x/-u to the neighbour.  The switch of Pi at
+ * w = 0 takes the derivative of the active branch (zero at w = 0).
+ * Results are ADDED to go [n,3], gu [n,3], grho [n] and gparams[3].
+ * ------------------------------------------------------------------------ */
+void orc_forces_reverse(const orc_params *p, const orc_grid *g, int n,
+                        const int32_t *cell, const double *off, const double *mass,
+                        const double *vel, const double *rho, const uint32_t *info,
+                        const int32_t *nf, const int32_t *nb, const int32_t *fl, const int32_t *bl,
+                        int max_neibs, const double *abar, const double *dbar,
+                        double *go, double *gu, double *grho, double *gparams)
+{
+    const double h = p->h, two_h = 2.0 * h, eh2 = p->eps_visc * h * h;
+    const double fD = 105.0 / (128.0 * M_PI * h * h * h * h * h);
+    const double B = p->rho0 * p->c0 * p->c0 / p->gamma;
+    double galpha = 0.0, gc0 = 0.0, gnu = 0.0;
+    for (int c = 0; c < n; ++c) {
+        if (cell[c] < 0) continue;
+        const double rc = rho[c];
+        const double Pc = orc_pressure(p, rc);
+        const double pc = Pc / (rc * rc);
+        const double cc = orc_sound_speed(p, rc);
+        /* dP/drho = c^2; d(P/rho^2)/drho = c^2/rho^2 - 2P/rho^3; dc/drho = (gamma-1)/2 c/rho */
+        const double dpc = cc * cc / (rc * rc) - 2.0 * Pc / (rc * rc * rc);
+        const double dcc = 0.5 * (p->gamma - 1.0) * cc / rc;
+        const double *ab = abar + 3 * (size_t)c;
+        const double db = dbar[c];
+        const int total = nf[c] + nb[c];
+        (void)B;
+        for (int k = 0; k < total; ++k) {
+            const int m = k < nf[c] ? fl[(size_t)c * max_neibs + k]
+                                    : bl[(size_t)c * max_neibs + (k - nf[c])];
+            double x[3], u[3];
+            separation(g, cell[c], cell[m], off + 3 * (size_t)c, off + 3 * (size_t)m, x);
+            const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+            const double r = sqrt(r2);
+            if (!(r < two_h)) continue;
+            for (int d = 0; d < 3; ++d) u[d] = vel[3 * (size_t)c + d] - vel[3 * (size_t)m + d];
+            const double w = u[0] * x[0] + u[1] * x[1] + u[2] * x[2];
+            const double q = r / h;
+            const double F = fD * (q - 2.0) * (q - 2.0) * (q - 2.0);
+            const double dFdr = 3.0 * fD * (q - 2.0) * (q - 2.0) / h;
+            const double mn = mass[m];
+            const double rn = rho[m];
+            const double Pn = orc_pressure(p, rn);
+            const double pn = Pn / (rn * rn);
+            const double cn = orc_sound_speed(p, rn);
+            const double dpn = cn * cn / (rn * rn) - 2.0 * Pn / (rn * rn * rn);
+            const double dcn = 0.5 * (p->gamma - 1.0) * cn / rn;
+            const double rs = rc + rn;
+            const double dd = r2 + eh2;
+            const int act = w < 0.0;
+            const double mw = act ? w : 0.0;
+            const double K = -p->alpha * h * (cc + cn) / rs;
+            const double Pi = K * mw / dd;
+            const double S = pc + pn + Pi;
+            const double G = -mn * S * F;
+            const double Lm = p->visc_model == 1 ? 4.0 * p->nu * mn * F / rs : 0.0;
+            const double A = ab[0] * x[0] + ab[1] * x[1] + ab[2] * x[2];
+            const double Bu = ab[0] * u[0] + ab[1] * u[1] + ab[2] * u[2];
+            double gx[3], gv[3];
+            for (int d = 0; d < 3; ++d) {
+                const double dFdx = dFdr * x[d] / r;
+                const double dPidx = act ? K * (u[d] / dd - 2.0 * w * x[d] / (dd * dd)) : 0.0;
+                const double dPidu = act ? K * x[d] / dd : 0.0;
+                const double dGdx = -mn * (S * dFdx + F * dPidx);
+                const double dGdu = -mn * F * dPidu;
+                const double dLdx = p->visc_model == 1 ? 4.0 * p->nu * mn * dFdx / rs : 0.0;
+                gx[d] = G * ab[d] + A * dGdx + Bu * dLdx + db * mn * (F * u[d] + w * dFdx);
+                gv[d] = Lm * ab[d] + A * dGdu + db * mn * F * x[d];
+            }
+            const double dPi_drc = act ? -p->alpha * h * mw / dd * (dcc / rs - (cc + cn) / (rs * rs)) : 0.0;
+            const double dPi_drn = act ? -p->alpha * h * mw / dd * (dcn / rs - (cc + cn) / (rs * rs)) : 0.0;
+            const double dL_drho = p->visc_model == 1 ? -4.0 * p->nu * mn * F / (rs * rs) : 0.0;
+            const double grc = A * (-mn * F * (dpc + dPi_drc)) + Bu * dL_drho;
+            const double grn = A * (-mn * F * (dpn + dPi_drn)) + Bu * dL_drho;
+            for (int d = 0; d < 3; ++d) {
+                go[3 * (size_t)c + d] += gx[d];
+                go[3 * (size_t)m + d] -= gx[d];
+                gu[3 * (size_t)c + d] += gv[d];
+                gu[3 * (size_t)m + d] -= gv[d];
+            }
+            grho[c] += grc;
+            grho[m] += grn;
+            /* Pi is proportional to alpha and to c0; P/rho^2 to c0^2 */
+            const double Pi_over_alpha = -h * (cc + cn) / rs * mw / dd;
+            galpha += A * (-mn * F) * Pi_over_alpha;
+            gc0 += A * (-mn * F) * (2.0 * pc + 2.0 * pn + Pi) / p->c0;
+            if (p->visc_model == 1) gnu += Bu * 4.0 * mn * F / rs;
+        }
+    }
+    gparams[0] += galpha;
+    gparams[1] += gc0;
+    gparams[2] += gnu;
+}
+
+/* Reverse of orc_integrate.  Given the adjoint of the stage output
+ * (go_out, gu_out, grho_out), return the adjoint of the stage inputs:
+ *   stage 0 (y* = y + tau f(y), tau = dt/2):
+ *       go_n = go_out, gu_n = gu_out + tau go_out (fluid), grho_n = grho_out,
+ *       abar = tau gu_out (fluid), dbar = tau grho_out;
+ *   stage 1 (y^{n+1} = y^n + dt (u*, a* + g, D*)):
+ *       go_n = go_out, gu_n = gu_out, grho_n = grho_out,
+ *       gu_star = dt go_out (fluid), abar = dt gu_out (fluid), dbar = dt grho_out.
+ * The derivative contributions through abar/dbar are added by the caller via
+ * orc_forces_reverse.  Outputs are overwritten. */
+void orc_integrate_reverse(int stage, double dt, int n, const int32_t *cell, const uint32_t *info,
+                           const double *go_out, const double *gu_out, const double *grho_out,
+                           double *go_n, double *gu_n, double *grho_n, double *gu_star,
+                           double *abar, double *dbar)
+{
+    const double tau = stage == 0 ? 0.5 * dt : dt;
+    for (int i = 0; i < n; ++i) {
+        const int fluid = ptype(info[i]) != ORC_BOUNDARY && cell[i] >= 0;
+        for (int d = 0; d < 3; ++d) {
+            const size_t q = 3 * (size_t)i + d;
+            go_n[q] = go_out[q];
+            if (stage == 0) {
+                gu_n[q] = gu_out[q] + (fluid ? tau * go_out[q] : 0.0);
+            } else {
+                gu_n[q] = gu_out[q];
+                if (gu_star) gu_star[q] = fluid ? dt * go_out[q] : 0.0;
+            }
+            abar[q] = fluid ? tau * gu_out[q] : 0.0;
+        }
+        grho_n[i] = grho_out[i];
+        dbar[i] = cell[i] >= 0 ? tau * grho_out[i] : 0.0;
+    }
+}
