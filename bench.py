@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="dam_break_1m", choices=["dam_break_1m", "dam_break_64k", "still_water_8k"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fwd-bwd", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
@@ -74,6 +75,58 @@ def cpu_baseline(sc, budget_s):
         "sample": "%d FP64 oracle derivative call(s) on the full step-0 state (%d particles, %d interactions "
                   "per call; oracle list build %.1f s not included)" % (calls, sc.n, inter // calls, t_build),
     }
+
+
+def fwd_bwd(sc, dt, K=10, reps=3):
+    """Cost of the reverse relative to the forward on one K-step block of the
+    same workload (fixed dt): t_fwd = K plain steps (one rebuild); t_bwd = the
+    reverse of those K steps from stored stage states (sph_integrate_backward
+    and sph_forces_backward twice per step, plus the rebuild permutation).
+    Also the end-to-end ratio with the checkpoint recomputation included."""
+    import torch
+    from paper_2207_11328_amd import abi
+    from paper_2207_11328_amd.adjoint import AdjointRollout
+    run = AdjointRollout(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, steps=K, dt=dt, rebuild_every=K,
+                         checkpoint_every=K)
+    n = run.n
+    g = torch.Generator(device=run.sim.device).manual_seed(0)
+    seed_p = torch.randn((n, 4), device=run.sim.device, generator=g)
+    seed_v = torch.randn((n, 4), device=run.sim.device, generator=g)
+    t_f, t_b, t_e2e = [], [], []
+    for _ in range(reps):
+        run.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run.forward()
+        torch.cuda.synchronize()
+        t_f.append(time.perf_counter() - t0)
+        # stage states of the block (the recomputation the checkpointing does)
+        run.reset()
+        run.sim.build(perm_out=run.perm)
+        stored = []
+        for _k in range(K):
+            run._advance(stored)
+        run.gpos[:n] = seed_p
+        run.gvel[:n] = seed_v
+        run.grad_params.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run.reverse_block(stored)
+        abi.sph_unpermute(n, run.perm, run.gpos, run.tmp_p)
+        abi.sph_unpermute(n, run.perm, run.gvel, run.tmp_v)
+        torch.cuda.synchronize()
+        t_b.append(time.perf_counter() - t0)
+        del stored
+        run.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run.forward()
+        run.backward(seed_p, seed_v)
+        torch.cuda.synchronize()
+        t_e2e.append(time.perf_counter() - t0)
+    tf, tb, te = min(t_f), min(t_b), min(t_e2e)
+    return {"block_steps": K, "fwd_ms": tf * 1e3, "bwd_ms": tb * 1e3, "fwd_bwd_ratio": (tf + tb) / tf,
+            "fwd_bwd_ratio_with_recompute": te / tf, "fwd_bwd_steps_per_s": K / (tf + tb)}
 
 
 def main():
@@ -200,6 +253,10 @@ def main():
             "bytes_per_launch": bytes_per_launch,
         },
     }
+    if not args.no_fwd_bwd:
+        dt_now = float(sim.d_dt.item())
+        del rep
+        out["adjoint"] = fwd_bwd(sc, dt_now)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -155,7 +155,11 @@ size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells);
  *   4. build the split neighbour list described above into
  *      neibs (device uint32[sph_neib_list_entries(capacity, max_neibs)]) and
  *      neib_count (device uint32[capacity]); dropped particles get count 0;
- *   5. d_status (device int32[4], see SPH_STATUS_*) is overwritten.
+ *   5. d_status (device int32[4], see SPH_STATUS_*) is overwritten;
+ *   6. if perm_out (device uint32[capacity]) is not NULL, perm_out[k] is the
+ *      index before the call of the particle now stored at k (k < n); the
+ *      adjoint of the rebuild is dL/dy_before[perm_out[k]] = dL/dy_after[k]
+ *      (sph_unpermute), since re-binning does not move a particle.
  * A particle whose neighbours exceed max_neibs keeps the first max_neibs
  * found (scan order: cells z, y, x outer to inner, then sorted index) and is
  * counted in SPH_STATUS_OVERFLOW; the lists are then unusable for physics.
@@ -165,8 +169,8 @@ size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells);
 sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
                                sph_particles *parts, uint32_t *neibs, uint32_t *neib_count,
                                int32_t max_neibs, int32_t *cell_start, int32_t *cell_end,
-                               int32_t *d_status, void *workspace, size_t workspace_bytes,
-                               void *stream);
+                               int32_t *d_status, uint32_t *perm_out, void *workspace,
+                               size_t workspace_bytes, void *stream);
 
 /* Time derivatives (eq. mass-cont-sph1 and eq. ns-sph1 with the readings of
  * the design notes; Wendland kernel of listing l:ktemplate).  For every
@@ -203,6 +207,54 @@ sph_status sph_integrate(const sph_params *params, int32_t stage, const double *
                          const sph_particles *state_n, const float *vel_star,
                          const float *forces, sph_particles *out, double *d_time,
                          void *stream);
+
+/* Reverse of sph_integrate (the transpose of its linear update; dt is held
+ * fixed).  All grad arrays are device float[capacity][4] laid out like the
+ * state: grad_pos xyz = dL/d(offset), grad_vel xyz = dL/du, w = dL/drho;
+ * grad_forces xyz = dL/da, w = dL/d(Drho/Dt).  One reverse step is
+ *   sph_integrate_backward(stage 1)   grad_pos/grad_vel = dL/dy^{n+1} on entry
+ *   sph_forces_backward(y*, accumulate into grad_pos_star/grad_vel_star)
+ *   sph_integrate_backward(stage 0)
+ *   sph_forces_backward(y^n, accumulate into grad_pos/grad_vel)
+ * after which grad_pos/grad_vel hold dL/dy^n.
+ *   stage 1: writes grad_forces = (dt dL/du^{n+1} (fluid), dt dL/drho^{n+1})
+ *            and initialises grad_pos_star = 0, grad_vel_star = (dt dL/do^{n+1}
+ *            (fluid), 0); grad_pos/grad_vel are left as they are.
+ *   stage 0: adds dL/dy* (grad_pos_star/grad_vel_star) to grad_pos/grad_vel,
+ *            plus dt/2 dL/do* to the fluid velocity adjoint, and writes
+ *            grad_forces = (dt/2 dL/du* (fluid), dt/2 dL/drho*).
+ * Boundary particles carry no velocity update; dropped particles (cell < 0)
+ * get a zero upstream.  Errors: SPH_ERR_ARG. */
+sph_status sph_integrate_backward(const sph_params *params, int32_t stage, const double *d_dt,
+                                  const sph_particles *state_n, float *grad_pos, float *grad_vel,
+                                  float *grad_pos_star, float *grad_vel_star, float *grad_forces,
+                                  void *stream);
+
+/* Bytes of device workspace sph_forces_backward needs. */
+size_t sph_forces_backward_workspace_bytes(int32_t capacity);
+
+/* Adjoint of sph_forces with the lists held fixed.  Given grad_forces
+ * (xyz = dL/da_i, w = dL/d(Drho_i/Dt)), computes dL/d(offset_i) into
+ * grad_pos (xyz; w is left unchanged), dL/du_i and dL/drho_i into grad_vel,
+ * and dL/d(alpha, c0, nu) into grad_params (device double[3]).  With
+ * accumulate != 0 every output is added to, otherwise overwritten.
+ * Atomic-free and deterministic: each particle gathers over its own list the
+ * terms of the pairs where it is the central and where it is the neighbour
+ * (the list is symmetric); parameter sums are reduced in double in a fixed
+ * order.  The derivative of the artificial-viscosity switch at u.x = 0 is
+ * that of the active branch.  workspace: sph_forces_backward_workspace_bytes.
+ * Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
+sph_status sph_forces_backward(const sph_grid *grid, const sph_params *params,
+                               const sph_particles *parts, const uint32_t *neibs,
+                               const uint32_t *neib_count, int32_t max_neibs,
+                               const float *grad_forces, float *grad_pos, float *grad_vel,
+                               double *grad_params, int32_t accumulate, void *workspace,
+                               size_t workspace_bytes, void *stream);
+
+/* dst[perm[k]] = src[k] for k < n, float4 records (carries an adjoint back
+ * across a rebuild, see sph_build_neighbors).  src and dst must differ.
+ * Errors: SPH_ERR_ARG. */
+sph_status sph_unpermute(int32_t n, const uint32_t *perm, const float *src, float *dst, void *stream);
 
 /* Bytes of device workspace sph_step_dt needs. */
 size_t sph_dt_workspace_bytes(void);

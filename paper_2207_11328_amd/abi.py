@@ -25,7 +25,8 @@ MAX_CAPACITY = 1 << NEIB_INDEX_BITS
 EXPORTS = [
     "sph_status_string", "sph_abi_version", "sph_neib_list_entries", "sph_build_workspace_bytes",
     "sph_build_neighbors", "sph_forces", "sph_forces_workspace_bytes", "sph_integrate",
-    "sph_dt_workspace_bytes", "sph_step_dt", "sph_count_interactions",
+    "sph_dt_workspace_bytes", "sph_step_dt", "sph_count_interactions", "sph_integrate_backward",
+    "sph_forces_backward_workspace_bytes", "sph_forces_backward", "sph_unpermute",
 ]
 
 
@@ -66,7 +67,7 @@ def _load():
     L.sph_forces_workspace_bytes.restype = C.c_size_t
     L.sph_build_workspace_bytes.argtypes = [i32, i32]
     L.sph_build_workspace_bytes.restype = C.c_size_t
-    L.sph_build_neighbors.argtypes = [P, P, P, P, P, i32, P, P, P, P, C.c_size_t, P]
+    L.sph_build_neighbors.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, C.c_size_t, P]
     L.sph_build_neighbors.restype = st
     L.sph_forces.argtypes = [P, P, P, P, P, i32, P, P, C.c_size_t, P]
     L.sph_forces.restype = st
@@ -78,6 +79,14 @@ def _load():
     L.sph_step_dt.restype = st
     L.sph_count_interactions.argtypes = [P, P, P, P, P, i32, P, P]
     L.sph_count_interactions.restype = st
+    L.sph_integrate_backward.argtypes = [P, i32, P, P, P, P, P, P, P, P]
+    L.sph_integrate_backward.restype = st
+    L.sph_forces_backward_workspace_bytes.argtypes = [i32]
+    L.sph_forces_backward_workspace_bytes.restype = C.c_size_t
+    L.sph_forces_backward.argtypes = [P, P, P, P, P, i32, P, P, P, P, i32, P, C.c_size_t, P]
+    L.sph_forces_backward.restype = st
+    L.sph_unpermute.argtypes = [i32, P, P, P, P]
+    L.sph_unpermute.restype = st
     return L
 
 
@@ -150,9 +159,9 @@ def sph_dt_workspace_bytes() -> int:
 
 
 def sph_build_neighbors(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count,
-                        max_neibs: int, cell_start, cell_end, d_status, workspace, stream=None):
+                        max_neibs: int, cell_start, cell_end, d_status, workspace, stream=None, perm_out=None):
     check(lib.sph_build_neighbors(C.byref(grid), C.byref(params), C.byref(parts), ptr(neibs), ptr(neib_count),
-                                  int(max_neibs), ptr(cell_start), ptr(cell_end), ptr(d_status),
+                                  int(max_neibs), ptr(cell_start), ptr(cell_end), ptr(d_status), ptr(perm_out),
                                   ptr(workspace), workspace.numel() * workspace.element_size(),
                                   stream_ptr(stream)), "sph_build_neighbors")
 
@@ -180,3 +189,27 @@ def sph_count_interactions(grid: SphGrid, params: SphParams, parts: SphParticles
     check(lib.sph_count_interactions(C.byref(grid), C.byref(params), C.byref(parts), ptr(neibs),
                                      ptr(neib_count), int(max_neibs), ptr(d_count), stream_ptr(stream)),
           "sph_count_interactions")
+
+
+def sph_forces_backward_workspace_bytes(capacity: int) -> int:
+    return int(lib.sph_forces_backward_workspace_bytes(int(capacity)))
+
+
+def sph_integrate_backward(params: SphParams, stage: int, d_dt, state_n: SphParticles, grad_pos, grad_vel,
+                           grad_pos_star, grad_vel_star, grad_forces, stream=None):
+    check(lib.sph_integrate_backward(C.byref(params), int(stage), ptr(d_dt), C.byref(state_n), ptr(grad_pos),
+                                     ptr(grad_vel), ptr(grad_pos_star), ptr(grad_vel_star), ptr(grad_forces),
+                                     stream_ptr(stream)), "sph_integrate_backward")
+
+
+def sph_forces_backward(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count, max_neibs: int,
+                        grad_forces, grad_pos, grad_vel, grad_params, accumulate: bool, workspace, stream=None):
+    check(lib.sph_forces_backward(C.byref(grid), C.byref(params), C.byref(parts), ptr(neibs), ptr(neib_count),
+                                  int(max_neibs), ptr(grad_forces), ptr(grad_pos), ptr(grad_vel), ptr(grad_params),
+                                  1 if accumulate else 0, ptr(workspace),
+                                  workspace.numel() * workspace.element_size(), stream_ptr(stream)),
+          "sph_forces_backward")
+
+
+def sph_unpermute(n: int, perm, src, dst, stream=None):
+    check(lib.sph_unpermute(int(n), ptr(perm), ptr(src), ptr(dst), stream_ptr(stream)), "sph_unpermute")

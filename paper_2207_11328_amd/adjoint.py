@@ -1,0 +1,212 @@
+"""Differentiable fixed-dt rollouts over the C ABI.
+
+The forward rollout keeps a checkpoint of the full particle state every
+`checkpoint_every` steps (a multiple of the rebuild interval K).  The reverse
+walks the checkpoint segments backwards; inside a segment it re-runs the
+forward once to recover the state before each rebuild, then for every K-step
+block (last to first): restores the pre-rebuild state, rebuilds (the same
+lists and the same sort permutation as the forward, the build being
+deterministic), re-runs the K steps keeping the stage states y^n and y*, and
+applies the reverse step
+
+    sph_integrate_backward(1) -> sph_forces_backward(y*) ->
+    sph_integrate_backward(0) -> sph_forces_backward(y^n)
+
+K times, then carries the adjoint back across the rebuild with
+sph_unpermute.  The time step is frozen (treated as a constant), so the
+reverse differentiates exactly the function the forward evaluates.
+
+`SPHRollout` wraps a rollout as a torch.autograd.Function of the initial
+velocities and of (alpha, c0).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import abi
+from .sim import Simulation
+
+
+class AdjointRollout:
+    def __init__(self, grid, params, cell, pos, vel, info, steps: int, dt: float, rebuild_every: int = 10,
+                 checkpoint_every: int = 20, max_neibs: int = 128, device: str = "cuda"):
+        if checkpoint_every % rebuild_every != 0:
+            raise ValueError("checkpoint_every must be a multiple of rebuild_every")
+        self.steps = int(steps)
+        self.K = int(rebuild_every)
+        self.C = int(checkpoint_every)
+        self.dt = float(dt)
+        self.sim = Simulation(grid, params, cell, pos, vel, info, max_neibs=max_neibs, rebuild_every=rebuild_every,
+                              device=device, dt_fixed=dt)
+        s = self.sim
+        n, cap, dev = s.n, s.capacity, s.device
+
+        def z(shape, dtype=torch.float32):
+            return torch.zeros(shape, dtype=dtype, device=dev)
+
+        self.gpos, self.gvel = z((cap, 4)), z((cap, 4))
+        self.gpos_s, self.gvel_s = z((cap, 4)), z((cap, 4))
+        self.gforce = z((cap, 4))
+        self.tmp_p, self.tmp_v = z((cap, 4)), z((cap, 4))
+        self.perm = z(cap, torch.int32)
+        self.ws_back = z(abi.sph_forces_backward_workspace_bytes(cap), torch.uint8)
+        self.grad_params = z(3, torch.float64)
+        self.initial = self._snapshot()
+        self.checkpoints = {}
+        self.n = n
+
+    # ------------------------------------------------------------ state helpers
+    def _snapshot(self):
+        s = self.sim
+        return tuple(t.clone() for t in (s.cell, s.pos, s.vel, s.info))
+
+    def _restore(self, snap):
+        s = self.sim
+        for dst, src in zip((s.cell, s.pos, s.vel, s.info), snap):
+            dst.copy_(src)
+
+    def _advance(self, store=None):
+        """One predictor/corrector step on the current lists (no rebuild)."""
+        s = self.sim
+        if store is not None:
+            store.append([s.pos.clone(), s.vel.clone(), None, None])
+        s.forces(False)
+        s.integrate(0)
+        if store is not None:
+            store[-1][2] = s.pos_star.clone()
+            store[-1][3] = s.vel_star.clone()
+        s.forces(True)
+        s.integrate(1)
+
+    def reset(self, vel0=None, alpha=None, c0=None):
+        """Back to the initial state, optionally with new initial velocities
+        (device float[n][3], initial particle order) and parameters."""
+        self._restore(self.initial)
+        if vel0 is not None:
+            self.sim.vel[: self.n, :3] = vel0.to(self.sim.vel.dtype)
+        kw = {}
+        if alpha is not None:
+            kw["alpha"] = float(alpha)
+        if c0 is not None:
+            kw["c0"] = float(c0)
+        if kw:
+            self.sim.set_params(**kw)
+        self.sim.d_time.zero_()
+        self.checkpoints = {}
+
+    # ------------------------------------------------------------ forward
+    def forward(self):
+        s = self.sim
+        for k in range(self.steps):
+            if k % self.C == 0:
+                self.checkpoints[k] = self._snapshot()
+            if k % self.K == 0:
+                s.build()
+            self._advance()
+        return s
+
+    # ------------------------------------------------------------ reverse
+    def _reverse_step(self, pos_n, vel_n, pos_s, vel_s):
+        s = self.sim
+        pn = abi.particles_struct(s.n, s.cell, pos_n, vel_n, s.info)
+        ps = abi.particles_struct(s.n, s.cell, pos_s, vel_s, s.info)
+        abi.sph_integrate_backward(s.p, 1, s.d_dt, pn, self.gpos, self.gvel, self.gpos_s, self.gvel_s, self.gforce)
+        abi.sph_forces_backward(s.g, s.p, ps, s.neibs, s.neib_count, s.max_neibs, self.gforce, self.gpos_s,
+                                self.gvel_s, self.grad_params, True, self.ws_back)
+        abi.sph_integrate_backward(s.p, 0, s.d_dt, pn, self.gpos, self.gvel, self.gpos_s, self.gvel_s, self.gforce)
+        abi.sph_forces_backward(s.g, s.p, pn, s.neibs, s.neib_count, s.max_neibs, self.gforce, self.gpos,
+                                self.gvel, self.grad_params, True, self.ws_back)
+
+    def reverse_block(self, stored):
+        """Reverse the steps of one block given their stored stage states."""
+        for pos_n, vel_n, pos_s, vel_s in reversed(stored):
+            self._reverse_step(pos_n, vel_n, pos_s, vel_s)
+
+    def backward(self, gpos_final, gvel_final):
+        """Adjoint of the final state (device float[n][4] each, final sorted
+        order; grad_pos xyz = dL/d(offset), grad_vel = (dL/du, dL/drho)) ->
+        adjoint of the initial state (initial particle order) and
+        dL/d(alpha, c0, nu) (device double[3])."""
+        s = self.sim
+        n = s.n
+        self.gpos.zero_()
+        self.gvel.zero_()
+        self.gpos[:n] = gpos_final
+        self.gvel[:n] = gvel_final
+        self.grad_params.zero_()
+        for c in sorted(self.checkpoints, reverse=True):
+            end = min(c + self.C, self.steps)
+            blocks = list(range(c, end, self.K))
+            self._restore(self.checkpoints[c])
+            pre = {}
+            for b in blocks:
+                pre[b] = self._snapshot()
+                if b != blocks[-1]:
+                    s.build()
+                    for _ in range(self.K):
+                        self._advance()
+            for b in reversed(blocks):
+                self._restore(pre[b])
+                s.build(perm_out=self.perm)
+                stored = []
+                for _ in range(b, min(b + self.K, end)):
+                    self._advance(stored)
+                self.reverse_block(stored)
+                abi.sph_unpermute(n, self.perm, self.gpos, self.tmp_p)
+                abi.sph_unpermute(n, self.perm, self.gvel, self.tmp_v)
+                self.gpos, self.tmp_p = self.tmp_p, self.gpos
+                self.gvel, self.tmp_v = self.tmp_v, self.gvel
+        return self.gpos[:n], self.gvel[:n], self.grad_params
+
+    # ------------------------------------------------------------ outputs
+    def outputs_by_id(self):
+        """Final positions (double, physical), velocities and densities in
+        particle-id order, and the id order of the sorted state."""
+        s = self.sim
+        n = s.n
+        g = s.grid
+        ids = (s.info[:n].long() & ((1 << 30) - 1))
+        nx, ny = int(g.ncell[0]), int(g.ncell[1])
+        lc = s.cell[:n].long() - int(g.cell_base)
+        c = torch.stack([lc % nx, (lc // nx) % ny, lc // (nx * ny)], dim=1).double()
+        cs = torch.tensor(np.asarray(g.cell_size, np.float32).astype(np.float64), device=s.device)
+        org = torch.tensor(np.asarray(g.origin, np.float64), device=s.device)
+        x = org[None, :] + (c + 0.5) * cs[None, :] + s.pos[:n, :3].double()
+        order = torch.argsort(ids)
+        return x[order], s.vel[:n, :3][order], s.vel[:n, 3][order], order
+
+
+class SPHRollout(torch.autograd.Function):
+    """(initial velocities [n,3] in id order, alpha, c0) -> final (x, u, rho)
+    in id order.  Backward runs the checkpointed adjoint."""
+
+    @staticmethod
+    def forward(ctx, vel0, alpha, c0, runner: AdjointRollout):
+        runner.reset(vel0.detach(), float(alpha), float(c0))
+        runner.forward()
+        x, u, rho, order = runner.outputs_by_id()
+        ctx.runner = runner
+        ctx.order = order
+        ctx.param_like = (alpha, c0)
+        return x, u.clone(), rho.clone()
+
+    @staticmethod
+    def backward(ctx, gx, gu, grho):
+        runner = ctx.runner
+        order = ctx.order
+        n = runner.n
+        dev = runner.sim.device
+        gp = torch.zeros((n, 4), dtype=torch.float32, device=dev)
+        gv = torch.zeros((n, 4), dtype=torch.float32, device=dev)
+        if gx is not None:
+            gp[order, :3] = gx.float()
+        if gu is not None:
+            gv[order, :3] = gu.float()
+        if grho is not None:
+            gv[order, 3] = grho.float()
+        g0p, g0v, gparams = runner.backward(gp, gv)
+        a, c = ctx.param_like
+        ga = gparams[0].to(device=a.device, dtype=a.dtype) if torch.is_tensor(a) else None
+        gc = gparams[1].to(device=c.device, dtype=c.dtype) if torch.is_tensor(c) else None
+        return g0v[:, :3].clone(), ga, gc, None

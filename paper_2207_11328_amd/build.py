@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsph.so")
-SOURCES = ["neighbors.hip", "forces.hip", "integrate.hip"]
+SOURCES = ["neighbors.hip", "forces.hip", "forces_backward.hip", "integrate.hip"]
 ARCH = "gfx950"
 
 

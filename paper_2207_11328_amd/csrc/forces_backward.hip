@@ -1,0 +1,347 @@
+// Adjoint of the derivative sums (sph_forces) with the neighbour lists held
+// fixed, and the permutation helper used to carry adjoints across a rebuild.
+//
+// Forward pair term of central c and neighbour n (r < 2h), x = x_c - x_n,
+// u = u_c - u_n, w = u.x:
+//   a_c    += G x + Lm u,   G = -m_n (p_c + p_n + Pi) F,  Lm = 4 nu m_n F/(rho_c + rho_n)
+//   Drho_c += m_n F w
+//   Pi = K min(w, 0) / (r^2 + eps h^2),  K = -alpha h (c_c + c_n)/(rho_c + rho_n)
+// (eq. mass-cont-sph1 and eq. ns-sph1 with the readings of the design notes).
+//
+// Atomic-free gather: the list is symmetric (the float32 predicate gives
+// x_ji = -x_ij bit for bit), so particle i visits each partner j once and
+// collects both its role as central (upstream abar_i, dbar_i) and its role as
+// neighbour of j (upstream abar_j, dbar_j).  With
+//   da = m_j abar_i - m_i abar_j,  dA = da.x,  dU = da.u,  sD = m_j dbar_i + m_i dbar_j
+// the two roles combine into
+//   dL/do_i   += -S F da - dA (S F'/r x + F act K (u/d - 2 w x/d^2)) + sD (F u + w F'/r x)
+//                [+ 4 nu F'/(rs r) dU x]
+//   dL/du_i   += -F act K/d dA x + sD F x                       [+ 4 nu F/rs da]
+//   dL/drho_i += -F (p_i' + dPi/drho_i) dA                      [- 4 nu F/rs^2 dU]
+// with S = p_i + p_j + Pi, d = r^2 + eps h^2, rs = rho_i + rho_j, act = (w < 0).
+// Parameter derivatives are taken from the central role only:
+//   dL/dalpha += abar_i.x (-m_j F) Pi/alpha,  dL/dc0 += abar_i.x (-m_j F)(2p_i + 2p_j + Pi)/c0,
+//   dL/dnu    += abar_i.u 4 m_j F/rs.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "sph_device.h"
+
+using namespace sph;
+
+namespace {
+
+constexpr int kThreads = 256;
+
+struct BackConst {
+    float csx, csy, csz;
+    float rho0, inv_rho0, B, c0;
+    float lim2, inv_h, fcoeff;
+    float alpha_h, h, eps_h2, four_nu, inv_c0;
+    int max_neibs;
+};
+
+// aux = (P/rho^2, c, d(P/rho^2)/drho, dc/drho) for gamma = 7
+__global__ __launch_bounds__(kThreads) void k_eos_grad(int n, const float4 *__restrict__ vel,
+                                                       float4 *__restrict__ aux, BackConst C)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const float rho = vel[i].w;
+    const float d = (rho - C.rho0) * C.inv_rho0;
+    float poly = 7.0f + d;
+    poly = fmaf(poly, d, 21.0f);
+    poly = fmaf(poly, d, 35.0f);
+    poly = fmaf(poly, d, 35.0f);
+    poly = fmaf(poly, d, 21.0f);
+    poly = fmaf(poly, d, 7.0f);
+    const float P = C.B * d * poly;
+    const float inv_rho = 1.0f / rho;
+    const float a = 1.0f + d;
+    const float c = C.c0 * a * a * a;
+    const float p = P * inv_rho * inv_rho;
+    aux[i] = make_float4(p, c, (c * c * inv_rho - 2.0f * P * inv_rho * inv_rho) * inv_rho, 3.0f * c * inv_rho);
+}
+
+__device__ __forceinline__ float entry_k(uint32_t e, int axis)
+{
+    return (float)((int32_t)(e << (4 - 2 * axis)) >> 30);
+}
+
+__device__ __forceinline__ int list_slot(int k, int nf, int last, int M)
+{
+    const int kk = min(k, last);
+    return kk < nf ? kk : M - 1 + nf - kk;
+}
+
+struct BackAcc {
+    float ox, oy, oz, ux, uy, uz, r;
+    float galpha, gc0, gnu;
+};
+
+template <int VISC>
+__device__ __forceinline__ void pair_adjoint(BackAcc &G, uint32_t e, const float4 &pi, const float4 &vi,
+                                             const float4 &xi, const float4 &gi, const float4 &pj,
+                                             const float4 &vj, const float4 &xj, const float4 &gj, bool valid,
+                                             const BackConst &C)
+{
+    const float xx = fmaf(entry_k(e, 0), C.csx, pi.x - pj.x);
+    const float xy = fmaf(entry_k(e, 1), C.csy, pi.y - pj.y);
+    const float xz = fmaf(entry_k(e, 2), C.csz, pi.z - pj.z);
+    float r2;
+    {
+#pragma clang fp contract(off)
+        r2 = (xx * xx + xy * xy) + xz * xz;
+    }
+    const bool inter = valid && (r2 < C.lim2);
+    const float r = __builtin_amdgcn_sqrtf(r2);
+    const float inv_r = __builtin_amdgcn_rcpf(r);
+    const float qm2 = fmaf(r, C.inv_h, -2.0f);
+    const float F = C.fcoeff * qm2 * qm2 * qm2;
+    const float Fp_r = 3.0f * C.fcoeff * qm2 * qm2 * C.inv_h * inv_r;  // F'(r)/r
+    const float ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
+    const float w = fmaf(ux, xx, fmaf(uy, xy, uz * xz));
+    const float mi = pi.w, mj = pj.w;
+    const float rs = vi.w + vj.w;
+    const float inv_rs = __builtin_amdgcn_rcpf(rs);
+    const float dd = r2 + C.eps_h2;
+    const float inv_d = __builtin_amdgcn_rcpf(dd);
+    const float csum = xi.y + xj.y;
+    const float mw = fminf(w, 0.0f);
+    const float actK = w < 0.0f ? -C.alpha_h * csum * inv_rs : 0.0f;
+    const float Pi = -C.alpha_h * csum * inv_rs * mw * inv_d;
+    const float S = xi.x + xj.x + Pi;
+    // combined upstream of the two roles
+    const float dax = mj * gi.x - mi * gj.x;
+    const float day = mj * gi.y - mi * gj.y;
+    const float daz = mj * gi.z - mi * gj.z;
+    const float dA = fmaf(dax, xx, fmaf(day, xy, daz * xz));
+    const float sD = fmaf(mj, gi.w, mi * gj.w);
+    // d/do_i
+    const float cx = S * Fp_r + F * actK * (-2.0f * w * inv_d * inv_d);
+    const float cu = F * actK * inv_d;
+    float kx = -dA * cx + sD * w * Fp_r;  // coefficient of x
+    float ku = -dA * cu + sD * F;         // coefficient of u
+    const float ka = -S * F;              // coefficient of da
+    if (VISC == 1) kx = fmaf(C.four_nu * Fp_r * inv_rs, fmaf(dax, ux, fmaf(day, uy, daz * uz)), kx);
+    float ox = fmaf(ka, dax, fmaf(kx, xx, ku * ux));
+    float oy = fmaf(ka, day, fmaf(kx, xy, ku * uy));
+    float oz = fmaf(ka, daz, fmaf(kx, xz, ku * uz));
+    // d/du_i
+    const float lx = -dA * cu + sD * F;  // coefficient of x
+    float vx = lx * xx, vy = lx * xy, vz = lx * xz;
+    if (VISC == 1) {
+        const float la = C.four_nu * F * inv_rs;
+        vx = fmaf(la, dax, vx);
+        vy = fmaf(la, day, vy);
+        vz = fmaf(la, daz, vz);
+    }
+    // d/drho_i
+    const float dPi_dri = w < 0.0f ? -C.alpha_h * mw * inv_d * (xi.w * inv_rs - csum * inv_rs * inv_rs) : 0.0f;
+    float gr = -F * (xi.z + dPi_dri) * dA;
+    if (VISC == 1) gr = fmaf(-C.four_nu * F * inv_rs * inv_rs, fmaf(dax, ux, fmaf(day, uy, daz * uz)), gr);
+    // parameters (central role)
+    const float Axi = fmaf(gi.x, xx, fmaf(gi.y, xy, gi.z * xz));
+    const float mF = -mj * F;
+    float ga = Axi * mF * (-C.h * csum * inv_rs * mw * inv_d);
+    float gc = Axi * mF * (2.0f * (xi.x + xj.x) + Pi) * C.inv_c0;
+    float gn = 0.0f;
+    if (VISC == 1) gn = fmaf(gi.x, ux, fmaf(gi.y, uy, gi.z * uz)) * 4.0f * mj * F * inv_rs;
+    if (inter) {
+        G.ox += ox;
+        G.oy += oy;
+        G.oz += oz;
+        G.ux += vx;
+        G.uy += vy;
+        G.uz += vz;
+        G.r += gr;
+        G.galpha += ga;
+        G.gc0 += gc;
+        G.gnu += gn;
+    }
+}
+
+template <int VISC>
+__global__ __launch_bounds__(kThreads) void k_forces_backward(
+    int n, const float4 *__restrict__ pos, const float4 *__restrict__ vel, const float4 *__restrict__ aux,
+    const float4 *__restrict__ gforce, const uint32_t *__restrict__ neibs, const uint32_t *__restrict__ count,
+    float4 *__restrict__ gpos, float4 *__restrict__ gvel, double *__restrict__ partial, int accumulate,
+    BackConst C)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    const int lane = threadIdx.x % kWave;
+    const int ii = min(i, n - 1);
+    const int M = C.max_neibs;
+    const uint32_t cnt = i < n ? count[i] : 0u;
+    const int nf = min((int)(cnt & 0xFFFFu), M);
+    const int nt = min(nf + (int)(cnt >> 16), M);
+    const int last = max(nt - 1, 0);
+    const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
+    const uint32_t jmax = (uint32_t)(n - 1);
+    BackAcc G = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (ntw > 0) {
+        const int tile_id = __builtin_amdgcn_readfirstlane(i / kWave);
+        const uint32_t *tile = neibs + (size_t)tile_id * (kWave * M);
+        const float4 pi = pos[ii], vi = vel[ii], xi = aux[ii], gi = gforce[ii];
+        uint32_t eA = tile[list_slot(0, nf, last, M) * kWave + lane];
+        uint32_t eNext = tile[list_slot(1, nf, last, M) * kWave + lane];
+        uint32_t jA = min(eA & kIndexMask, jmax);
+        float4 pA = pos[jA], vA = vel[jA], xA = aux[jA], gA = gforce[jA];
+        for (int k = 0; k < ntw; k += 2) {
+            const uint32_t eN2 = tile[list_slot(k + 2, nf, last, M) * kWave + lane];
+            const uint32_t eB = eNext;
+            const uint32_t jB = min(eB & kIndexMask, jmax);
+            const float4 pB = pos[jB], vB = vel[jB], xB = aux[jB], gB = gforce[jB];
+            pair_adjoint<VISC>(G, eA, pi, vi, xi, gi, pA, vA, xA, gA, k < nt, C);
+            eNext = tile[list_slot(k + 3, nf, last, M) * kWave + lane];
+            eA = eN2;
+            jA = min(eA & kIndexMask, jmax);
+            pA = pos[jA];
+            vA = vel[jA];
+            xA = aux[jA];
+            gA = gforce[jA];
+            pair_adjoint<VISC>(G, eB, pi, vi, xi, gi, pB, vB, xB, gB, k + 1 < nt, C);
+        }
+    }
+    if (i < n) {
+        float4 po = make_float4(G.ox, G.oy, G.oz, 0.0f);
+        float4 vo = make_float4(G.ux, G.uy, G.uz, G.r);
+        if (nt == 0) po = vo = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (accumulate) {
+            const float4 p0 = gpos[i], v0 = gvel[i];
+            po = make_float4(p0.x + po.x, p0.y + po.y, p0.z + po.z, p0.w);
+            vo = make_float4(v0.x + vo.x, v0.y + vo.y, v0.z + vo.z, v0.w + vo.w);
+        } else {
+            po.w = gpos[i].w;
+        }
+        gpos[i] = po;
+        gvel[i] = vo;
+    }
+    // parameter derivatives: per-block partial sums in double, fixed order
+    double a = nt > 0 ? (double)G.galpha : 0.0, c = nt > 0 ? (double)G.gc0 : 0.0,
+           v = nt > 0 ? (double)G.gnu : 0.0;
+    if (i >= n) a = c = v = 0.0;
+    a = wave_sum(a);
+    c = wave_sum(c);
+    v = wave_sum(v);
+    __shared__ double red[3][kThreads / kWave];
+    const int w = threadIdx.x / kWave;
+    if (lane == 0) {
+        red[0][w] = a;
+        red[1][w] = c;
+        red[2][w] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double s = 0.0;
+        for (int k = 0; k < kThreads / kWave; ++k) s += red[threadIdx.x][k];
+        partial[3 * (size_t)blockIdx.x + threadIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_param_reduce(int nblocks, const double *__restrict__ partial,
+                                                           double *__restrict__ out, int accumulate)
+{
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += kThreads)
+        for (int k = 0; k < 3; ++k) s[k] += partial[3 * (size_t)b + k];
+    __shared__ double red[3][kThreads / kWave];
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    for (int k = 0; k < 3; ++k) {
+        const double t = wave_sum(s[k]);
+        if (lane == 0) red[k][w] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        double t = 0.0;
+        for (int k = 0; k < kThreads / kWave; ++k) t += red[threadIdx.x][k];
+        out[threadIdx.x] = accumulate ? out[threadIdx.x] + t : t;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_unpermute(int n, const uint32_t *__restrict__ perm,
+                                                        const float4 *__restrict__ src, float4 *__restrict__ dst)
+{
+    const int k = blockIdx.x * kThreads + threadIdx.x;
+    if (k >= n) return;
+    const uint32_t d = perm[k];
+    if (d < (uint32_t)n) dst[d] = src[k];
+}
+
+size_t aux_bytes(int64_t cap) { return (size_t)((16 * cap + 255) & ~(int64_t)255); }
+size_t partial_bytes(int64_t cap) { return (size_t)(3 * 8 * ((cap + kThreads - 1) / kThreads) + 256); }
+
+}  // namespace
+
+extern "C" size_t sph_forces_backward_workspace_bytes(int32_t capacity)
+{
+    if (capacity < 0) return 0;
+    const int64_t cap = capacity > 0 ? capacity : 1;
+    return aux_bytes(cap) + partial_bytes(cap);
+}
+
+extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params *p, const sph_particles *parts,
+                                          const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
+                                          const float *grad_forces, float *grad_pos, float *grad_vel,
+                                          double *grad_params, int32_t accumulate, void *workspace,
+                                          size_t workspace_bytes, void *stream)
+{
+    if (!grid || !p || !parts || !grad_params) return SPH_ERR_ARG;
+    if (parts->n < 0 || parts->capacity < parts->n || parts->capacity > SPH_MAX_CAPACITY) return SPH_ERR_ARG;
+    if (max_neibs < 1 || max_neibs > 65535) return SPH_ERR_ARG;
+    if (parts->n > 0 && (!parts->pos || !parts->vel || !neibs || !neib_count || !grad_forces || !grad_pos ||
+                         !grad_vel))
+        return SPH_ERR_ARG;
+    if (!(p->h > 0.0f) || !(p->rho0 > 0.0f) || !(p->c0 > 0.0f) || p->gamma != 7.0f) return SPH_ERR_ARG;
+    if (p->visc_model != 0 && p->visc_model != 1) return SPH_ERR_ARG;
+    if (!workspace || workspace_bytes < sph_forces_backward_workspace_bytes(parts->capacity))
+        return SPH_ERR_WORKSPACE;
+    BackConst C;
+    C.csx = grid->cell_size[0];
+    C.csy = grid->cell_size[1];
+    C.csz = grid->cell_size[2];
+    C.rho0 = p->rho0;
+    C.inv_rho0 = (float)(1.0 / (double)p->rho0);
+    C.B = (float)((double)p->rho0 * (double)p->c0 * (double)p->c0 / (double)p->gamma);
+    C.c0 = p->c0;
+    const float two_h = 2.0f * p->h;
+    C.lim2 = two_h * two_h;
+    C.inv_h = (float)(1.0 / (double)p->h);
+    const double h = p->h;
+    C.fcoeff = (float)(105.0 / (128.0 * M_PI * h * h * h * h * h));
+    C.alpha_h = (float)((double)p->alpha * h);
+    C.h = p->h;
+    C.eps_h2 = (float)((double)p->eps_visc * h * h);
+    C.four_nu = (float)(4.0 * (double)p->nu);
+    C.inv_c0 = (float)(1.0 / (double)p->c0);
+    C.max_neibs = max_neibs;
+    const int n = parts->n;
+    hipStream_t s = (hipStream_t)stream;
+    float4 *aux = (float4 *)workspace;
+    double *partial = (double *)((char *)workspace + aux_bytes(parts->capacity > 0 ? parts->capacity : 1));
+    const int nblocks = n > 0 ? (int)sph_blocks(n, kThreads) : 0;
+    if (n > 0) {
+        k_eos_grad<<<nblocks, kThreads, 0, s>>>(n, (const float4 *)parts->vel, aux, C);
+        if (p->visc_model == 0)
+            k_forces_backward<0><<<nblocks, kThreads, 0, s>>>(
+                n, (const float4 *)parts->pos, (const float4 *)parts->vel, aux, (const float4 *)grad_forces, neibs,
+                neib_count, (float4 *)grad_pos, (float4 *)grad_vel, partial, accumulate, C);
+        else
+            k_forces_backward<1><<<nblocks, kThreads, 0, s>>>(
+                n, (const float4 *)parts->pos, (const float4 *)parts->vel, aux, (const float4 *)grad_forces, neibs,
+                neib_count, (float4 *)grad_pos, (float4 *)grad_vel, partial, accumulate, C);
+    }
+    k_param_reduce<<<1, kThreads, 0, s>>>(nblocks, partial, grad_params, accumulate);
+    SPH_CHECK_LAUNCH();
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_unpermute(int32_t n, const uint32_t *perm, const float *src, float *dst, void *stream)
+{
+    if (n < 0 || (n > 0 && (!perm || !src || !dst || src == dst))) return SPH_ERR_ARG;
+    if (n == 0) return SPH_OK;
+    k_unpermute<<<sph_blocks(n, kThreads), kThreads, 0, (hipStream_t)stream>>>(n, perm, (const float4 *)src,
+                                                                              (float4 *)dst);
+    SPH_CHECK_LAUNCH();
+    return SPH_OK;
+}

@@ -108,7 +108,72 @@ __global__ __launch_bounds__(kThreads) void k_dt_final(int np, const float2 *__r
     }
 }
 
+// Reverse of the midpoint stages (the transpose of the linear updates).
+//   stage 1:  gpos/gvel hold dL/dy^{n+1}; they stay as the direct part of
+//             dL/dy^n.  Writes the upstream of the derivatives at y*
+//             gforce = (dt dL/du^{n+1} (fluid), dt dL/drho^{n+1}) and initialises
+//             dL/dy* = (0, dt dL/do^{n+1} (fluid), 0) in gpos_s/gvel_s.
+//   stage 0:  gpos_s/gvel_s hold the complete dL/dy*.  Adds it to dL/dy^n
+//             (plus tau dL/do* to the fluid velocity) and writes the upstream
+//             of the derivatives at y^n: gforce = (tau dL/du* (fluid), tau dL/drho*).
+__global__ __launch_bounds__(kThreads) void k_integrate_backward(int n, int stage, const double *__restrict__ d_dt,
+                                                                 const int32_t *__restrict__ cell,
+                                                                 const uint32_t *__restrict__ info,
+                                                                 float4 *__restrict__ gpos, float4 *__restrict__ gvel,
+                                                                 float4 *__restrict__ gpos_s,
+                                                                 float4 *__restrict__ gvel_s,
+                                                                 float4 *__restrict__ gforce)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const double dt = *d_dt;
+    const bool valid = cell[i] >= 0;
+    const bool fluid = valid && ptype(info[i]) != kBoundary;
+    if (stage == 1) {
+        const float t = (float)dt;
+        const float4 go = gpos[i], gv = gvel[i];
+        gforce[i] = make_float4(fluid ? t * gv.x : 0.0f, fluid ? t * gv.y : 0.0f, fluid ? t * gv.z : 0.0f,
+                                valid ? t * gv.w : 0.0f);
+        gpos_s[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        gvel_s[i] = make_float4(fluid ? t * go.x : 0.0f, fluid ? t * go.y : 0.0f, fluid ? t * go.z : 0.0f, 0.0f);
+    } else {
+        const float tau = (float)(0.5 * dt);
+        const float4 so = gpos_s[i], sv = gvel_s[i];
+        float4 go = gpos[i], gv = gvel[i];
+        go.x += so.x;
+        go.y += so.y;
+        go.z += so.z;
+        gv.x += sv.x + (fluid ? tau * so.x : 0.0f);
+        gv.y += sv.y + (fluid ? tau * so.y : 0.0f);
+        gv.z += sv.z + (fluid ? tau * so.z : 0.0f);
+        gv.w += sv.w;
+        gpos[i] = go;
+        gvel[i] = gv;
+        gforce[i] = make_float4(fluid ? tau * sv.x : 0.0f, fluid ? tau * sv.y : 0.0f, fluid ? tau * sv.z : 0.0f,
+                                valid ? tau * sv.w : 0.0f);
+    }
+}
+
 }  // namespace
+
+extern "C" sph_status sph_integrate_backward(const sph_params *params, int32_t stage, const double *d_dt,
+                                             const sph_particles *state_n, float *grad_pos, float *grad_vel,
+                                             float *grad_pos_star, float *grad_vel_star, float *grad_forces,
+                                             void *stream)
+{
+    if (!params || !d_dt || !state_n || (stage != 0 && stage != 1)) return SPH_ERR_ARG;
+    const int n = state_n->n;
+    if (n < 0 || state_n->capacity < n) return SPH_ERR_ARG;
+    if (n == 0) return SPH_OK;
+    if (!state_n->cell || !state_n->info || !grad_pos || !grad_vel || !grad_pos_star || !grad_vel_star ||
+        !grad_forces)
+        return SPH_ERR_ARG;
+    k_integrate_backward<<<sph_blocks(n, kThreads), kThreads, 0, (hipStream_t)stream>>>(
+        n, stage, d_dt, state_n->cell, state_n->info, (float4 *)grad_pos, (float4 *)grad_vel,
+        (float4 *)grad_pos_star, (float4 *)grad_vel_star, (float4 *)grad_forces);
+    SPH_CHECK_LAUNCH();
+    return SPH_OK;
+}
 
 extern "C" sph_status sph_integrate(const sph_params *params, int32_t stage, const double *d_dt,
                                     const sph_particles *state_n, const float *vel_star, const float *forces,

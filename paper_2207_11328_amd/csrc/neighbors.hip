@@ -236,11 +236,13 @@ __global__ __launch_bounds__(kThreads) void k_gather(int n, const uint32_t *__re
                                                      int32_t *__restrict__ o_cell,
                                                      float4 *__restrict__ o_pos,
                                                      float4 *__restrict__ o_vel,
-                                                     uint32_t *__restrict__ o_info)
+                                                     uint32_t *__restrict__ o_info,
+                                                     uint32_t *__restrict__ perm_out)
 {
     const int k = blockIdx.x * kThreads + threadIdx.x;
     if (k >= n) return;
     const uint32_t src = perm[k];
+    if (perm_out) perm_out[k] = src;
     o_cell[k] = cell[src];
     o_pos[k] = pos[src];
     o_vel[k] = vel[src];
@@ -382,8 +384,8 @@ extern "C" size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells)
 extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
                                           sph_particles *parts, uint32_t *neibs, uint32_t *neib_count,
                                           int32_t max_neibs, int32_t *cell_start, int32_t *cell_end,
-                                          int32_t *d_status, void *workspace, size_t workspace_bytes,
-                                          void *stream)
+                                          int32_t *d_status, uint32_t *perm_out, void *workspace,
+                                          size_t workspace_bytes, void *stream)
 {
     if (!grid || !params || !parts || !neibs || !neib_count || !cell_start || !cell_end || !d_status)
         return SPH_ERR_ARG;
@@ -440,7 +442,7 @@ extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params
         k_cell_sort<<<sph_blocks(nbk, kThreads / kWave), kThreads, 0, s>>>(nbk, start, perm_a, parts->info,
                                                                               perm_b);
         k_gather<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, perm_b, parts->cell, pos, vel, parts->info,
-                                                               t_cell, t_pos, t_vel, t_info);
+                                                               t_cell, t_pos, t_vel, t_info, perm_out);
         SPH_CHECK_LAUNCH();
         const float rs2 = params->r_search * params->r_search;
         k_build_lists<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(

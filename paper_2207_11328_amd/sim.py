@@ -82,9 +82,14 @@ class Simulation:
         self.steps_done = 0
 
     # ------------------------------------------------------------ primitives
-    def build(self, stream=None):
+    def build(self, stream=None, perm_out=None):
         abi.sph_build_neighbors(self.g, self.p, self.parts, self.neibs, self.neib_count, self.max_neibs,
-                                self.cell_start, self.cell_end, self.status, self.ws_build, stream)
+                                self.cell_start, self.cell_end, self.status, self.ws_build, stream, perm_out)
+
+    def set_params(self, **kw):
+        """Change scalar parameters (e.g. alpha, c0) between calls."""
+        for k, v in kw.items():
+            setattr(self.p, k, float(v))
 
     def forces(self, star: bool = False, stream=None):
         parts = self.parts_star if star else self.parts

@@ -78,8 +78,14 @@ def test_argument_errors_return_before_any_launch(abi):
     assert abi.lib.sph_forces(C.byref(g), C.byref(p), C.byref(parts), None, None, 128, None, None, 0,
                               None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_forces(None, None, None, None, None, 128, None, None, 0, None) == abi.SPH_ERR_ARG
-    assert abi.lib.sph_build_neighbors(None, None, None, None, None, 128, None, None, None, None, 0,
+    assert abi.lib.sph_build_neighbors(None, None, None, None, None, 128, None, None, None, None, None, 0,
                                        None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_forces_backward(None, None, None, None, None, 128, None, None, None, None, 0, None, 0,
+                                       None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_integrate_backward(None, 0, None, None, None, None, None, None, None,
+                                          None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_unpermute(-1, None, None, None, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_unpermute(0, None, None, None, None) == abi.SPH_OK
     assert abi.lib.sph_integrate(None, 0, None, None, None, None, None, None, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_integrate(C.byref(p), 2, None, None, None, None, None, None, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_step_dt(None, None, None, None, None, 0, None) == abi.SPH_ERR_ARG
