@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--workload", default="dam_break_1m", choices=["dam_break_1m", "dam_break_64k", "still_water_8k"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fwd-bwd", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
@@ -127,6 +128,30 @@ def fwd_bwd(sc, dt, K=10, reps=3):
     tf, tb, te = min(t_f), min(t_b), min(t_e2e)
     return {"block_steps": K, "fwd_ms": tf * 1e3, "bwd_ms": tb * 1e3, "fwd_bwd_ratio": (tf + tb) / tf,
             "fwd_bwd_ratio_with_recompute": te / tf, "fwd_bwd_steps_per_s": K / (tf + tb)}
+
+
+def batched(units=5, warm_units=1):
+    """128 independent tanks (fluid counts log-uniform in [2k, 60k], column
+    aspect 0.3-2, alpha 0.005-0.05) stacked in one grid, advanced by replays
+    of a HIP graph holding one rebuild unit (10 steps, adaptive dt)."""
+    import torch
+    from paper_2207_11328_amd.sim import Simulation
+    from workloads import scenes as S
+    tanks = S.batched_tanks()
+    st, alpha, _, _ = S.stack_scenes(tanks)
+    sim = Simulation(st.grid, st.params, st.cell, st.pos, st.vel, st.info, cell_alpha=alpha, device="cuda:0")
+    sim.capture_unit()
+    sim.replay_units(warm_units)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.replay_units(units)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    sim.check_status()
+    steps = units * sim.rebuild_every
+    return {"scenes": len(tanks), "particles": st.n, "fluid": st.n_fluid, "steps": steps,
+            "ms_per_step": t / steps * 1e3, "particle_steps_per_s": st.n * steps / t,
+            "fluid_particle_steps_per_s": st.n_fluid * steps / t, "graph_units": units}
 
 
 def main():
@@ -253,6 +278,8 @@ def main():
             "bytes_per_launch": bytes_per_launch,
         },
     }
+    if not args.no_batched:
+        out["batched"] = batched()
     if not args.no_fwd_bwd:
         dt_now = float(sim.d_dt.item())
         del rep

@@ -85,16 +85,23 @@ enum {
 #define SPH_NEIB_INDEX_BITS 26
 #define SPH_MAX_CAPACITY (1 << SPH_NEIB_INDEX_BITS)
 
-/* One scene's uniform cell grid (section "Optimizing the neighbors search"):
- * origin, extents and spacing.  cell_size[d] must be >= r_search; a
- * periodic axis (bit d of `periodic`) has ncell[d] >= 3 and period
- * ncell[d] * cell_size[d]. */
+/* Uniform cell grid (section "Optimizing the neighbors search"): origin,
+ * extents and spacing.  cell_size[d] must be >= r_search; a periodic axis
+ * (bit d of `periodic`) has ncell[d] >= 3 and period ncell[d] * cell_size[d].
+ * Several independent scenes can share one grid (one neighbour search, one
+ * launch per step for all of them): place them in disjoint regions separated
+ * by at least one empty cell layer, so no pair across scenes is ever listed,
+ * and give each region its own artificial-viscosity coefficient through
+ * cell_alpha (device float[n_cells], indexed by cell - cell_base; NULL means
+ * params->alpha everywhere; the coefficient of a pair is that of the central
+ * particle's cell, equal for both members within one scene). */
 typedef struct {
     double origin[3];
     float cell_size[3];
     int32_t ncell[3];
     uint32_t periodic;
     int32_t cell_base;
+    const float *cell_alpha;
 } sph_grid;
 
 /* Physical and numerical parameters.
@@ -243,7 +250,8 @@ size_t sph_forces_backward_workspace_bytes(int32_t capacity);
  * (the list is symmetric); parameter sums are reduced in double in a fixed
  * order.  The derivative of the artificial-viscosity switch at u.x = 0 is
  * that of the active branch.  workspace: sph_forces_backward_workspace_bytes.
- * Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
+ * Errors: SPH_ERR_ARG (also for a grid with a per-cell alpha table),
+ * SPH_ERR_WORKSPACE. */
 sph_status sph_forces_backward(const sph_grid *grid, const sph_params *params,
                                const sph_particles *parts, const uint32_t *neibs,
                                const uint32_t *neib_count, int32_t max_neibs,

@@ -32,7 +32,7 @@ EXPORTS = [
 
 class SphGrid(C.Structure):
     _fields_ = [("origin", C.c_double * 3), ("cell_size", C.c_float * 3), ("ncell", C.c_int32 * 3),
-                ("periodic", C.c_uint32), ("cell_base", C.c_int32)]
+                ("periodic", C.c_uint32), ("cell_base", C.c_int32), ("cell_alpha", C.c_void_p)]
 
 
 class SphParams(C.Structure):
@@ -110,8 +110,10 @@ def stream_ptr(stream=None) -> int | None:
     return s.cuda_stream
 
 
-def grid_struct(grid) -> SphGrid:
+def grid_struct(grid, cell_alpha=None) -> SphGrid:
+    """cell_alpha: optional device float tensor [n_cells] (per-cell alpha)."""
     g = SphGrid()
+    g.cell_alpha = ptr(cell_alpha)
     for d in range(3):
         g.origin[d] = float(grid.origin[d])
         g.cell_size[d] = float(grid.cell_size[d])

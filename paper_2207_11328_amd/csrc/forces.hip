@@ -45,10 +45,17 @@ struct ForceConst {
 // (1 + d)^7 - 1, full relative accuracy near rho0).  aux = (P/rho^2, alpha h c)
 // with c = c0 (1 + d)^3.
 __global__ __launch_bounds__(kThreads) void k_eos(int n, const float4 *__restrict__ vel, float2 *__restrict__ aux,
+                                                  const int32_t *__restrict__ cell,
+                                                  const float *__restrict__ cell_alpha, int cell_base, float h,
                                                   ForceConst C)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
+    float alpha_h = C.alpha_h;
+    if (cell_alpha) {
+        const int c = cell[i];
+        if (c >= 0) alpha_h = cell_alpha[c - cell_base] * h;
+    }
     const float rho = vel[i].w;
     const float d = (rho - C.rho0) * C.inv_rho0;
     float poly = 7.0f + d;
@@ -60,7 +67,7 @@ __global__ __launch_bounds__(kThreads) void k_eos(int n, const float4 *__restric
     const float P = C.B * d * poly;
     const float inv_rho = 1.0f / rho;
     const float a = 1.0f + d;
-    aux[i] = make_float2(P * inv_rho * inv_rho, C.alpha_h * (C.c0 * a * a * a));
+    aux[i] = make_float2(P * inv_rho * inv_rho, alpha_h * (C.c0 * a * a * a));
 }
 
 // Cell difference k_d in {-1, 0, 1} of axis d, stored as a two's-complement
@@ -271,7 +278,9 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
     const float4 *vel = (const float4 *)parts->vel;
     float2 *aux = (float2 *)workspace;
     float4 *out = (float4 *)forces;
-    k_eos<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, vel, aux, C);
+    if (grid->cell_alpha && !parts->cell) return SPH_ERR_ARG;
+    k_eos<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, vel, aux, parts->cell, grid->cell_alpha, grid->cell_base,
+                                                       params->h, C);
     if (params->visc_model == 0)
         k_forces<0><<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, pos, vel, aux, neibs, neib_count, out, C);
     else

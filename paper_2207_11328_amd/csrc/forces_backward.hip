@@ -286,7 +286,7 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
                                           double *grad_params, int32_t accumulate, void *workspace,
                                           size_t workspace_bytes, void *stream)
 {
-    if (!grid || !p || !parts || !grad_params) return SPH_ERR_ARG;
+    if (!grid || !p || !parts || !grad_params || grid->cell_alpha) return SPH_ERR_ARG;
     if (parts->n < 0 || parts->capacity < parts->n || parts->capacity > SPH_MAX_CAPACITY) return SPH_ERR_ARG;
     if (max_neibs < 1 || max_neibs > 65535) return SPH_ERR_ARG;
     if (parts->n > 0 && (!parts->pos || !parts->vel || !neibs || !neib_count || !grad_forces || !grad_pos ||

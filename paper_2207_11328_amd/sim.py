@@ -29,7 +29,7 @@ class Simulation:
     """Device state of one scene and the step sequence over the C ABI."""
 
     def __init__(self, grid, params, cell, pos, vel, info, max_neibs: int = 128, capacity: int | None = None,
-                 rebuild_every: int = 10, device: str = "cuda", dt_fixed: float | None = None):
+                 rebuild_every: int = 10, device: str = "cuda", dt_fixed: float | None = None, cell_alpha=None):
         n = int(np.asarray(cell).shape[0])
         cap = int(capacity or n)
         if cap < n or cap > abi.MAX_CAPACITY:
@@ -75,7 +75,10 @@ class Simulation:
         self.pos[:n] = torch.from_numpy(np.ascontiguousarray(pos, np.float32))
         self.vel[:n] = torch.from_numpy(np.ascontiguousarray(vel, np.float32))
 
-        self.g = abi.grid_struct(grid)
+        self.cell_alpha = None
+        if cell_alpha is not None:
+            self.cell_alpha = torch.from_numpy(np.ascontiguousarray(cell_alpha, np.float32)).to(dev)
+        self.g = abi.grid_struct(grid, self.cell_alpha)
         self.p = abi.params_struct(params)
         self.parts = abi.particles_struct(n, self.cell, self.pos, self.vel, self.info)
         self.parts_star = abi.particles_struct(n, self.cell, self.pos_star, self.vel_star, self.info)
@@ -129,6 +132,38 @@ class Simulation:
     def run(self, steps: int, stream=None):
         for _ in range(steps):
             self.step(stream)
+
+    # ------------------------------------------------------------ HIP graph
+    def capture_unit(self):
+        """Record one rebuild unit (the neighbour search plus rebuild_every
+        steps, about 6 + 5 K launches) into a HIP graph.  Nothing is
+        executed while capturing; replay_units() then advances K steps per
+        graph launch with no per-kernel launch overhead.  Must be called on a
+        rebuild boundary.  The graph reads and writes this object's buffers,
+        so it stays valid for the object's lifetime."""
+        if self.steps_done % self.rebuild_every != 0:
+            raise RuntimeError("capture_unit must start on a rebuild step")
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream(device=self.device)
+        side.wait_stream(torch.cuda.current_stream(self.device))
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(graph, stream=side):
+                self.build()
+                for _ in range(self.rebuild_every):
+                    self.forces(False)
+                    if self.dt_fixed is None:
+                        self.step_dt()
+                    self.integrate(0)
+                    self.forces(True)
+                    self.integrate(1)
+        torch.cuda.current_stream(self.device).wait_stream(side)
+        self.graph = graph
+        return graph
+
+    def replay_units(self, units: int):
+        for _ in range(units):
+            self.graph.replay()
+            self.steps_done += self.rebuild_every
 
     # ------------------------------------------------------------ host views
     def status_host(self) -> dict:

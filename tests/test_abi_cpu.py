@@ -39,7 +39,7 @@ def test_struct_layout_matches_header(abi, tmp_path):
 #include <stddef.h>
 #include "sph.h"
 int main(void) {
-  printf("%zu %zu %zu %zu\\n", sizeof(sph_grid), offsetof(sph_grid, cell_size), offsetof(sph_grid, periodic), offsetof(sph_grid, cell_base));
+  printf("%zu %zu %zu %zu %zu\\n", sizeof(sph_grid), offsetof(sph_grid, cell_size), offsetof(sph_grid, periodic), offsetof(sph_grid, cell_base), offsetof(sph_grid, cell_alpha));
   printf("%zu %zu %zu\\n", sizeof(sph_params), offsetof(sph_params, g), offsetof(sph_params, visc_model));
   printf("%zu %zu %zu %zu\\n", sizeof(sph_particles), offsetof(sph_particles, cell), offsetof(sph_particles, vel), offsetof(sph_particles, info));
   return 0;
@@ -50,7 +50,7 @@ int main(void) {
     out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
     g = [int(v) for v in out[0].split()]
     assert g == [C.sizeof(abi.SphGrid), abi.SphGrid.cell_size.offset, abi.SphGrid.periodic.offset,
-                 abi.SphGrid.cell_base.offset]
+                 abi.SphGrid.cell_base.offset, abi.SphGrid.cell_alpha.offset]
     p = [int(v) for v in out[1].split()]
     assert p == [C.sizeof(abi.SphParams), abi.SphParams.g.offset, abi.SphParams.visc_model.offset]
     q = [int(v) for v in out[2].split()]

@@ -372,3 +372,84 @@ CONFIGS = {
     "dam_break_64k": dam_break_64k,
     "channel_16m": channel_16m,
 }
+
+
+def stack_scenes(scenes, gap_cells: int = 2):
+    """Lay independent scenes out in one grid, stacked along z, so that one
+    neighbour search and one set of launches covers all of them.
+
+    Every scene must use the same particle spacing (hence the same search
+    radius).  The common cell side is the float32 search radius on all axes;
+    each scene keeps its particles' positions relative to its own lower
+    corner, placed at an integer number of cells, so its cell-relative
+    encoding is identical to the one it has alone on its own sub-grid
+    (returned as `sub_grids`).  `gap_cells` empty cell layers separate
+    consecutive scenes, so no pair of particles of different scenes is ever
+    listed.  Returns (combined Scene, per-cell alpha float32[n_cells],
+    sub_grids, per-scene (first particle, count) in the combined input)."""
+    rs = float(np.float32(scenes[0].params.r_search))
+    for s in scenes:
+        if float(np.float32(s.params.r_search)) != rs:
+            raise ValueError("stacked scenes need a common search radius")
+    cs = np.float32(rs)
+    csd = float(cs)
+    # each scene's extent in cells (its own grid rounded up to whole cells)
+    ext = []
+    for s in scenes:
+        L = s.grid.ncell.astype(np.float64) * s.grid.cell_size.astype(np.float64)
+        ext.append(np.ceil(L / csd - 1e-9).astype(np.int64))
+    nx = int(max(e[0] for e in ext))
+    ny = int(max(e[1] for e in ext))
+    z0 = []
+    z = 0
+    for e in ext:
+        z0.append(z)
+        z += int(e[2]) + gap_cells
+    nz = z - gap_cells
+    grid = Grid(origin=np.zeros(3), cell_size=np.full(3, cs, np.float32),
+                ncell=np.array([nx, ny, nz], np.int32), periodic=0, cell_base=0)
+    xs, types, rho, vel, mass = [], [], [], [], []
+    sub_grids, ranges = [], []
+    first = 0
+    alpha = np.zeros(grid.n_cells, np.float32)
+    for s, e, zz in zip(scenes, ext, z0):
+        x = decode_positions(s.grid, s.cell, s.pos[:, :3]) - s.grid.origin[None, :]
+        x[:, 2] += zz * csd
+        xs.append(x)
+        types.append((s.info >> np.uint32(TYPE_SHIFT)).astype(np.uint32))
+        vel.append(s.vel)
+        mass.append(s.pos[:, 3])
+        sub = Grid(origin=np.array([0.0, 0.0, zz * csd]), cell_size=grid.cell_size.copy(),
+                   ncell=np.array([nx, ny, int(e[2])], np.int32), periodic=0, cell_base=0)
+        sub_grids.append(sub)
+        ranges.append((first, s.n))
+        first += s.n
+        a = np.float32(s.params.alpha)
+        alpha[zz * nx * ny:(zz + int(e[2])) * nx * ny] = a
+    x = np.concatenate(xs)
+    cell, off = encode_positions(grid, x)
+    n = x.shape[0]
+    pos = np.zeros((n, 4), np.float32)
+    pos[:, :3] = off
+    pos[:, 3] = np.concatenate(mass)
+    info = (np.concatenate(types) << np.uint32(TYPE_SHIFT)) | np.arange(n, dtype=np.uint32)
+    p0 = scenes[0].params
+    params = Params(**{k: getattr(p0, k) for k in p0.__dataclass_fields__})
+    sc = Scene("stacked", grid, params, cell, pos, np.concatenate(vel).astype(np.float32), info,
+               sum(s.n_fluid for s in scenes), sum(s.n_boundary for s in scenes),
+               {"scenes": len(scenes), "z0": z0})
+    return sc, alpha, sub_grids, ranges
+
+
+def scene_on_subgrid(stacked: Scene, sub_grid: Grid, rng):
+    """The particles [first, first + count) of a stacked scene re-encoded on
+    their own sub-grid (same offsets, local cells), with their own ids."""
+    first, count = rng
+    x = decode_positions(stacked.grid, stacked.cell[first:first + count], stacked.pos[first:first + count, :3])
+    cell, off = encode_positions(sub_grid, x)
+    pos = stacked.pos[first:first + count].copy()
+    pos[:, :3] = off
+    info = stacked.info[first:first + count].copy()
+    return Scene("sub", sub_grid, stacked.params, cell, pos, stacked.vel[first:first + count].copy(), info,
+                 int(((info >> np.uint32(TYPE_SHIFT)) == FLUID).sum()),
+                 int(((info >> np.uint32(TYPE_SHIFT)) == BOUNDARY).sum()))
