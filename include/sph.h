@@ -264,6 +264,23 @@ sph_status sph_forces_backward(const sph_grid *grid, const sph_params *params,
  * Errors: SPH_ERR_ARG. */
 sph_status sph_unpermute(int32_t n, const uint32_t *perm, const float *src, float *dst, void *stream);
 
+/* Bytes of device workspace sph_reduce_diagnostics needs. */
+size_t sph_diagnostics_workspace_bytes(void);
+
+/* Global conservation diagnostics in double precision (the step itself is
+ * float32; only these sums and the time accumulator are double), over
+ * particles i < n with cell >= 0, written to d_out (device double[12]):
+ *   [0] sum m            [1..3] sum m u (fluid)   [4..6] sum m a (forces xyz,
+ *   all particles; the raw pair sums are antisymmetric, so without boundary
+ *   particles this is zero up to float32 rounding of the terms)
+ *   [7] sum m / rho      [8] fluid count           [9] boundary count
+ *   [10] max |rho/rho0 - 1| over fluid               [11] sum m |u|^2 / 2 (fluid)
+ * forces may be NULL (then [4..6] = 0).  Fixed-order reduction: the result
+ * is reproducible bit for bit.  Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
+sph_status sph_reduce_diagnostics(const sph_params *params, const sph_particles *parts,
+                                  const float *forces, double *d_out, void *workspace,
+                                  size_t workspace_bytes, void *stream);
+
 /* Bytes of device workspace sph_step_dt needs. */
 size_t sph_dt_workspace_bytes(void);
 

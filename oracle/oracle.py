@@ -480,3 +480,76 @@ def front_loss(grid, front_ids):
         adj.go[sel, 0] = 1.0 / sel.sum()
         return L, adj
     return f
+
+
+# ---------------------------------------------------------------- very large inputs
+def _setup_rows():
+    L = lib()
+    if getattr(L, "_rows_ready", False):
+        return L
+    P = C.c_void_p
+    i32 = C.c_int
+    L.orc_neighbors_rows.argtypes = [P, C.c_float, P, P, P, P, P, i32, P, i32, P, P, P, P]
+    L.orc_neighbors_rows.restype = i32
+    L.orc_forces_rows.argtypes = [P, P, P, P, P, P, P, P, i32, P, P, P, P, i32, P, P, P, P]
+    L.orc_forces_rows.restype = None
+    L.orc_count_interactions_rows.argtypes = [P, C.c_float, P, P, P, i32, P, P, P, P, i32]
+    L.orc_count_interactions_rows.restype = C.c_int64
+    L._rows_ready = True
+    return L
+
+
+def sorted_f32(grid, cell, pos, vel, info):
+    """Re-bin, sort and cell ranges of a float32 encoded state (no lists)."""
+    cell, pos, dropped = rebin_f32(grid, cell, pos)
+    perm = sort_perm(cell, info)
+    cell, pos, vel, info = cell[perm], pos[perm], np.asarray(vel)[perm], np.asarray(info)[perm]
+    start, end = cell_ranges(grid, cell)
+    return dict(cell=np.ascontiguousarray(cell), pos=np.ascontiguousarray(pos), vel=np.ascontiguousarray(vel),
+                info=np.ascontiguousarray(info), perm=perm, start=start, end=end,
+                n_active=int((cell >= 0).sum()), dropped=dropped)
+
+
+def neighbors_rows(grid, params, sorted_state, rows, max_neibs=128) -> Lists:
+    """Float32-predicate lists of the sorted particles `rows` (row-indexed)."""
+    L = _setup_rows()
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    m = rows.shape[0]
+    nf = np.zeros(m, np.int32)
+    nb = np.zeros(m, np.int32)
+    fl = np.zeros((m, max_neibs), np.int32)
+    bl = np.zeros((m, max_neibs), np.int32)
+    g = grid_struct(grid)
+    ss = sorted_state
+    ov = L.orc_neighbors_rows(C.byref(g), C.c_float(f32(params.r_search)), _p(ss["cell"]), _p(ss["pos"]),
+                              _p(ss["info"]), _p(ss["start"]), _p(ss["end"]), max_neibs, _p(rows), m,
+                              _p(nf), _p(nb), _p(fl), _p(bl))
+    return Lists(nf, nb, fl, bl, max_neibs, int(ov))
+
+
+def forces_rows(grid, params, st: State, rows, lists: Lists):
+    """Derivatives of the particles `rows` of a double state, from
+    row-indexed lists.  Returns (acc, drho, s_acc, s_drho), row-indexed."""
+    L = _setup_rows()
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    m = rows.shape[0]
+    acc = np.zeros((m, 3))
+    drho = np.zeros(m)
+    s_acc = np.zeros((m, 3))
+    s_drho = np.zeros(m)
+    g = grid_struct(grid)
+    ps = params_struct(params)
+    L.orc_forces_rows(C.byref(ps), C.byref(g), _p(st.cell), _p(st.off), _p(st.mass), _p(st.vel), _p(st.rho),
+                      _p(rows), m, _p(lists.nf), _p(lists.nb), _p(lists.fl), _p(lists.bl), lists.max_neibs,
+                      _p(acc), _p(drho), _p(s_acc), _p(s_drho))
+    return acc, drho, s_acc, s_drho
+
+
+def count_interactions_rows(grid, params, sorted_state, rows, lists: Lists) -> int:
+    L = _setup_rows()
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    g = grid_struct(grid)
+    ss = sorted_state
+    return int(L.orc_count_interactions_rows(C.byref(g), C.c_float(f32(params.h)), _p(ss["cell"]), _p(ss["pos"]),
+                                             _p(rows), rows.shape[0], _p(lists.nf), _p(lists.nb), _p(lists.fl),
+                                             _p(lists.bl), lists.max_neibs))

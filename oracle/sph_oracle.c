@@ -216,82 +216,105 @@ void orc_cell_ranges(const orc_grid *g, int n, const int32_t *cell_sorted,
  * neighbour, nf[i] / nb[i] their counts.  Returns the number of particles
  * whose nf + nb exceeds max (their lists are truncated).
  * ------------------------------------------------------------------------ */
+/* Neighbours of one particle i; fl_row / bl_row receive its fluid / boundary
+ * lists, *nf / *nb the numbers kept.  Returns 1 if the list overflowed. */
+static int neighbors_of(const orc_grid *g, float r_search, int i, const int32_t *cell, const float *pos4,
+                        const double *off3, const uint32_t *info, const int32_t *start, const int32_t *end,
+                        int max_neibs, int32_t *nf, int32_t *nb, int32_t *fl_row, int32_t *bl_row)
+{
+    const float rs2f = r_search * r_search;
+    const double rs2d = (double)r_search * (double)r_search;
+    *nf = 0;
+    *nb = 0;
+    if (cell[i] < 0) return 0;
+    int32_t ci[3];
+    cell_coords(g, cell[i], ci);
+    const uint32_t ti = ptype(info[i]);
+    int cf = 0, cb = 0, wf = 0, wb = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+    for (int dx = -1; dx <= 1; ++dx) {
+        const int off[3] = {dx, dy, dz};
+        int32_t cj[3];
+        int inside = 1;
+        for (int d = 0; d < 3; ++d) {
+            cj[d] = ci[d] + off[d];
+            if ((g->periodic >> d) & 1u) {
+                if (cj[d] < 0) cj[d] += g->n[d];
+                if (cj[d] >= g->n[d]) cj[d] -= g->n[d];
+            } else if (cj[d] < 0 || cj[d] >= g->n[d]) {
+                inside = 0;
+            }
+        }
+        if (!inside) continue;
+        const int32_t lc = cell_linear(g, cj) - g->cell_base;
+        for (int j = start[lc]; j < end[lc]; ++j) {
+            if (j == i) continue;
+            const uint32_t tj = ptype(info[j]);
+            if (ti == ORC_BOUNDARY && tj == ORC_BOUNDARY) continue;
+            int keep;
+            if (pos4) {
+                float x[3];
+                for (int d = 0; d < 3; ++d) {
+                    const float t1 = pos4[4 * (size_t)i + d] - pos4[4 * (size_t)j + d];
+                    const float t2 = (float)(-off[d]) * g->cs[d];
+                    x[d] = t2 + t1;
+                }
+                const float xx = x[0] * x[0];
+                const float yy = x[1] * x[1];
+                const float zz = x[2] * x[2];
+                const float s = xx + yy;
+                const float r2 = s + zz;
+                keep = r2 < rs2f;
+            } else {
+                double r2 = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    const double x = (double)(-off[d]) * (double)g->cs[d]
+                                   + (off3[3 * (size_t)i + d] - off3[3 * (size_t)j + d]);
+                    r2 += x * x;
+                }
+                keep = r2 < rs2d;
+            }
+            if (!keep) continue;
+            if (tj == ORC_BOUNDARY) {
+                if (wf + wb < max_neibs) bl_row[wb++] = j;
+                ++cb;
+            } else {
+                if (wf + wb < max_neibs) fl_row[wf++] = j;
+                ++cf;
+            }
+        }
+    }
+    *nf = wf;
+    *nb = wb;
+    return cf + cb > max_neibs; /* truncated: only what fitted is kept */
+}
+
 int orc_neighbors(const orc_grid *g, float r_search, int n,
                   const int32_t *cell, const float *pos4, const double *off3,
                   const uint32_t *info, const int32_t *start, const int32_t *end,
                   int max_neibs, int32_t *nf, int32_t *nb, int32_t *fl, int32_t *bl)
 {
-    const int fp64 = pos4 == NULL;
-    const float rs2f = r_search * r_search;
-    const double rs2d = (double)r_search * (double)r_search;
     int overflow = 0;
 #pragma omp parallel for schedule(static) reduction(+ : overflow)
-    for (int i = 0; i < n; ++i) {
-        nf[i] = 0;
-        nb[i] = 0;
-        if (cell[i] < 0) continue;
-        int32_t ci[3];
-        cell_coords(g, cell[i], ci);
-        const uint32_t ti = ptype(info[i]);
-        int cf = 0, cb = 0, wf = 0, wb = 0;
-        for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-            const int off[3] = {dx, dy, dz};
-            int32_t cj[3];
-            int inside = 1;
-            for (int d = 0; d < 3; ++d) {
-                cj[d] = ci[d] + off[d];
-                if ((g->periodic >> d) & 1u) {
-                    if (cj[d] < 0) cj[d] += g->n[d];
-                    if (cj[d] >= g->n[d]) cj[d] -= g->n[d];
-                } else if (cj[d] < 0 || cj[d] >= g->n[d]) {
-                    inside = 0;
-                }
-            }
-            if (!inside) continue;
-            const int32_t lc = cell_linear(g, cj) - g->cell_base;
-            for (int j = start[lc]; j < end[lc]; ++j) {
-                if (j == i) continue;
-                const uint32_t tj = ptype(info[j]);
-                if (ti == ORC_BOUNDARY && tj == ORC_BOUNDARY) continue;
-                int keep;
-                if (!fp64) {
-                    float x[3];
-                    for (int d = 0; d < 3; ++d) {
-                        const float t1 = pos4[4 * i + d] - pos4[4 * j + d];
-                        const float t2 = (float)(-off[d]) * g->cs[d];
-                        x[d] = t2 + t1;
-                    }
-                    const float xx = x[0] * x[0];
-                    const float yy = x[1] * x[1];
-                    const float zz = x[2] * x[2];
-                    const float s = xx + yy;
-                    const float r2 = s + zz;
-                    keep = r2 < rs2f;
-                } else {
-                    double r2 = 0.0;
-                    for (int d = 0; d < 3; ++d) {
-                        const double x = (double)(-off[d]) * (double)g->cs[d]
-                                       + (off3[3 * (size_t)i + d] - off3[3 * (size_t)j + d]);
-                        r2 += x * x;
-                    }
-                    keep = r2 < rs2d;
-                }
-                if (!keep) continue;
-                if (tj == ORC_BOUNDARY) {
-                    if (wf + wb < max_neibs) bl[(size_t)i * max_neibs + wb++] = j;
-                    ++cb;
-                } else {
-                    if (wf + wb < max_neibs) fl[(size_t)i * max_neibs + wf++] = j;
-                    ++cf;
-                }
-            }
-        }
-        if (cf + cb > max_neibs) ++overflow; /* truncated: only what fitted is kept */
-        nf[i] = wf;
-        nb[i] = wb;
-    }
+    for (int i = 0; i < n; ++i)
+        overflow += neighbors_of(g, r_search, i, cell, pos4, off3, info, start, end, max_neibs, nf + i, nb + i,
+                                 fl + (size_t)i * max_neibs, bl + (size_t)i * max_neibs);
+    return overflow;
+}
+
+/* The same for the particles rows[0..nrows) only (float32 predicate); row r
+ * of the outputs belongs to particle rows[r].  For inputs too large to list
+ * every particle. */
+int orc_neighbors_rows(const orc_grid *g, float r_search, const int32_t *cell, const float *pos4,
+                       const uint32_t *info, const int32_t *start, const int32_t *end, int max_neibs,
+                       const int32_t *rows, int nrows, int32_t *nf, int32_t *nb, int32_t *fl, int32_t *bl)
+{
+    int overflow = 0;
+#pragma omp parallel for schedule(static) reduction(+ : overflow)
+    for (int r = 0; r < nrows; ++r)
+        overflow += neighbors_of(g, r_search, rows[r], cell, pos4, NULL, info, start, end, max_neibs, nf + r,
+                                 nb + r, fl + (size_t)r * max_neibs, bl + (size_t)r * max_neibs);
     return overflow;
 }
 
@@ -363,6 +386,71 @@ static inline void separation(const orc_grid *g, int32_t cell_i, int32_t cell_j,
  * float32 result is compared.  n_inter receives the number of (i, j) pairs
  * with r < 2h.
  * ------------------------------------------------------------------------ */
+/* Derivatives of one particle i from its lists (fl_row, bl_row with nfi,
+ * nbi entries): a[3], drho, the magnitude scales sa[3], sdr; returns the
+ * number of pairs with r < 2h. */
+static int forces_of(const orc_params *p, const orc_grid *g, int i, const int32_t *cell, const double *off,
+                     const double *mass, const double *vel, const double *rho, int nfi, int nbi,
+                     const int32_t *fl_row, const int32_t *bl_row, double a[3], double sa[3], double *dr_out,
+                     double *sdr_out)
+{
+    const double h = p->h, h2 = h * h, two_h = 2.0 * h;
+    double dr = 0.0, sdr = 0.0;
+    int inter = 0;
+    for (int d = 0; d < 3; ++d) a[d] = sa[d] = 0.0;
+    if (cell[i] >= 0) {
+        const double rhoi = rho[i];
+        const double Pi = orc_pressure(p, rhoi);
+        const double pi = Pi / (rhoi * rhoi);
+        const double ci = orc_sound_speed(p, rhoi);
+        const int total = nfi + nbi;
+        for (int k = 0; k < total; ++k) {
+            const int j = k < nfi ? fl_row[k] : bl_row[k - nfi];
+            double x[3];
+            separation(g, cell[i], cell[j], off + 3 * (size_t)i, off + 3 * (size_t)j, x);
+            const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+            const double r = sqrt(r2);
+            if (!(r < two_h)) continue;
+            ++inter;
+            const double F = orc_wendland_F(r, h);
+            const double mj = mass[j];
+            const double rhoj = rho[j];
+            const double Pj = orc_pressure(p, rhoj);
+            const double pj = Pj / (rhoj * rhoj);
+            double u[3], ux = 0.0, uxabs = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                u[d] = vel[3 * (size_t)i + d] - vel[3 * (size_t)j + d];
+                ux += u[d] * x[d];
+                uxabs += fabs(u[d] * x[d]);
+            }
+            dr += mj * ux * F;
+            sdr += mj * uxabs * fabs(F);
+            const double cbar = 0.5 * (ci + orc_sound_speed(p, rhoj));
+            const double rhobar = 0.5 * (rhoi + rhoj);
+            const double visc_den = rhobar * (r2 + p->eps_visc * h2);
+            double Pi_ij = 0.0;
+            if (ux < 0.0) Pi_ij = -p->alpha * h * cbar * ux / visc_den;
+            const double Pi_abs = p->alpha * h * cbar * uxabs / visc_den;
+            const double coef = -mj * (pi + pj + Pi_ij) * F;
+            const double scoef = mj * (fabs(pi) + fabs(pj) + Pi_abs) * fabs(F);
+            for (int d = 0; d < 3; ++d) {
+                a[d] += coef * x[d];
+                sa[d] += scoef * fabs(x[d]);
+            }
+            if (p->visc_model == 1) {
+                const double lam = 4.0 * p->nu * mj / (rhoi + rhoj) * F;
+                for (int d = 0; d < 3; ++d) {
+                    a[d] += lam * u[d];
+                    sa[d] += fabs(lam * u[d]);
+                }
+            }
+        }
+    }
+    *dr_out = dr;
+    *sdr_out = sdr;
+    return inter;
+}
+
 void orc_forces(const orc_params *p, const orc_grid *g, int n,
                 const int32_t *cell, const double *off, const double *mass,
                 const double *vel, const double *rho, const uint32_t *info,
@@ -370,110 +458,89 @@ void orc_forces(const orc_params *p, const orc_grid *g, int n,
                 int max_neibs, double *acc, double *drho, double *s_acc, double *s_drho,
                 int64_t *n_inter)
 {
-    const double h = p->h, h2 = h * h, two_h = 2.0 * h;
     int64_t inter = 0;
+    (void)info;
 #pragma omp parallel for schedule(static) reduction(+ : inter)
-    for (int i = 0; i < n; ++i) {
-        double a[3] = {0, 0, 0}, sa[3] = {0, 0, 0}, dr = 0.0, sdr = 0.0;
-        if (cell[i] >= 0) {
-            const double rhoi = rho[i];
-            const double Pi = orc_pressure(p, rhoi);
-            const double pi = Pi / (rhoi * rhoi);
-            const double ci = orc_sound_speed(p, rhoi);
-            const int total = nf[i] + nb[i];
-            for (int k = 0; k < total; ++k) {
-                const int j = k < nf[i] ? fl[(size_t)i * max_neibs + k]
-                                        : bl[(size_t)i * max_neibs + (k - nf[i])];
-                double x[3];
-                separation(g, cell[i], cell[j], off + 3 * (size_t)i, off + 3 * (size_t)j, x);
-                const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
-                const double r = sqrt(r2);
-                if (!(r < two_h)) continue;
-                ++inter;
-                const double F = orc_wendland_F(r, h);
-                const double mj = mass[j];
-                const double rhoj = rho[j];
-                const double Pj = orc_pressure(p, rhoj);
-                const double pj = Pj / (rhoj * rhoj);
-                double u[3], ux = 0.0, uxabs = 0.0;
-                for (int d = 0; d < 3; ++d) {
-                    u[d] = vel[3 * (size_t)i + d] - vel[3 * (size_t)j + d];
-                    ux += u[d] * x[d];
-                    uxabs += fabs(u[d] * x[d]);
-                }
-                dr += mj * ux * F;
-                sdr += mj * uxabs * fabs(F);
-                const double cbar = 0.5 * (ci + orc_sound_speed(p, rhoj));
-                const double rhobar = 0.5 * (rhoi + rhoj);
-                const double visc_den = rhobar * (r2 + p->eps_visc * h2);
-                double Pi_ij = 0.0;
-                if (ux < 0.0) Pi_ij = -p->alpha * h * cbar * ux / visc_den;
-                const double Pi_abs = p->alpha * h * cbar * uxabs / visc_den;
-                const double coef = -mj * (pi + pj + Pi_ij) * F;
-                const double scoef = mj * (fabs(pi) + fabs(pj) + Pi_abs) * fabs(F);
-                for (int d = 0; d < 3; ++d) {
-                    a[d] += coef * x[d];
-                    sa[d] += scoef * fabs(x[d]);
-                }
-                if (p->visc_model == 1) {
-                    const double lam = 4.0 * p->nu * mj / (rhoi + rhoj) * F;
-                    for (int d = 0; d < 3; ++d) {
-                        a[d] += lam * u[d];
-                        sa[d] += fabs(lam * u[d]);
-                    }
-                }
-            }
-        }
-        for (int d = 0; d < 3; ++d) {
-            acc[3 * (size_t)i + d] = a[d];
-            s_acc[3 * (size_t)i + d] = sa[d];
-        }
-        drho[i] = dr;
-        s_drho[i] = sdr;
-    }
+    for (int i = 0; i < n; ++i)
+        inter += forces_of(p, g, i, cell, off, mass, vel, rho, nf[i], nb[i], fl + (size_t)i * max_neibs,
+                           bl + (size_t)i * max_neibs, acc + 3 * (size_t)i, s_acc + 3 * (size_t)i, drho + i,
+                           s_drho + i);
     if (n_inter) *n_inter = inter;
+}
+
+/* The same for particles rows[0..nrows) with row-indexed lists (as produced
+ * by orc_neighbors_rows) and row-indexed outputs. */
+void orc_forces_rows(const orc_params *p, const orc_grid *g, const int32_t *cell, const double *off,
+                     const double *mass, const double *vel, const double *rho, const int32_t *rows, int nrows,
+                     const int32_t *nf, const int32_t *nb, const int32_t *fl, const int32_t *bl, int max_neibs,
+                     double *acc, double *drho, double *s_acc, double *s_drho)
+{
+#pragma omp parallel for schedule(static)
+    for (int r = 0; r < nrows; ++r)
+        (void)forces_of(p, g, rows[r], cell, off, mass, vel, rho, nf[r], nb[r], fl + (size_t)r * max_neibs,
+                        bl + (size_t)r * max_neibs, acc + 3 * (size_t)r, s_acc + 3 * (size_t)r, drho + r,
+                        s_drho + r);
 }
 
 /* Number of listed pairs whose float32 squared separation (evaluated as in
  * the neighbour predicate) is below fl32(2h)^2: the interaction count the
- * GPU uses for its masking decision. */
-int64_t orc_count_interactions_f32(const orc_grid *g, float h, int n, const int32_t *cell,
-                                   const float *pos4, const int32_t *nf, const int32_t *nb,
-                                   const int32_t *fl, const int32_t *bl, int max_neibs)
+ * GPU uses for its masking decision.  One particle: */
+static int64_t count_of(const orc_grid *g, float h, int i, const int32_t *cell, const float *pos4, int nfi,
+                        int nbi, const int32_t *fl_row, const int32_t *bl_row)
 {
     const float two_h = 2.0f * h;
     const float lim = two_h * two_h;
     int64_t cnt = 0;
-#pragma omp parallel for schedule(static) reduction(+ : cnt)
-    for (int i = 0; i < n; ++i) {
-        if (cell[i] < 0) continue;
-        int32_t ci[3];
-        cell_coords(g, cell[i], ci);
-        const int total = nf[i] + nb[i];
-        for (int k = 0; k < total; ++k) {
-            const int j = k < nf[i] ? fl[(size_t)i * max_neibs + k]
-                                    : bl[(size_t)i * max_neibs + (k - nf[i])];
-            int32_t cj[3];
-            cell_coords(g, cell[j], cj);
-            float x[3];
-            for (int d = 0; d < 3; ++d) {
-                int kd = ci[d] - cj[d];
-                if ((g->periodic >> d) & 1u) {
-                    if (kd > 1) kd -= g->n[d];
-                    if (kd < -1) kd += g->n[d];
-                }
-                const float t1 = pos4[4 * i + d] - pos4[4 * j + d];
-                const float t2 = (float)kd * g->cs[d];
-                x[d] = t2 + t1;
+    if (cell[i] < 0) return 0;
+    int32_t ci[3];
+    cell_coords(g, cell[i], ci);
+    const int total = nfi + nbi;
+    for (int k = 0; k < total; ++k) {
+        const int j = k < nfi ? fl_row[k] : bl_row[k - nfi];
+        int32_t cj[3];
+        cell_coords(g, cell[j], cj);
+        float x[3];
+        for (int d = 0; d < 3; ++d) {
+            int kd = ci[d] - cj[d];
+            if ((g->periodic >> d) & 1u) {
+                if (kd > 1) kd -= g->n[d];
+                if (kd < -1) kd += g->n[d];
             }
-            const float xx = x[0] * x[0];
-            const float yy = x[1] * x[1];
-            const float zz = x[2] * x[2];
-            const float s = xx + yy;
-            const float r2 = s + zz;
-            if (r2 < lim) ++cnt;
+            const float t1 = pos4[4 * (size_t)i + d] - pos4[4 * (size_t)j + d];
+            const float t2 = (float)kd * g->cs[d];
+            x[d] = t2 + t1;
         }
+        const float xx = x[0] * x[0];
+        const float yy = x[1] * x[1];
+        const float zz = x[2] * x[2];
+        const float s = xx + yy;
+        const float r2 = s + zz;
+        if (r2 < lim) ++cnt;
     }
+    return cnt;
+}
+
+int64_t orc_count_interactions_f32(const orc_grid *g, float h, int n, const int32_t *cell,
+                                   const float *pos4, const int32_t *nf, const int32_t *nb,
+                                   const int32_t *fl, const int32_t *bl, int max_neibs)
+{
+    int64_t cnt = 0;
+#pragma omp parallel for schedule(static) reduction(+ : cnt)
+    for (int i = 0; i < n; ++i)
+        cnt += count_of(g, h, i, cell, pos4, nf[i], nb[i], fl + (size_t)i * max_neibs, bl + (size_t)i * max_neibs);
+    return cnt;
+}
+
+/* The same over particles rows[0..nrows) with row-indexed lists. */
+int64_t orc_count_interactions_rows(const orc_grid *g, float h, const int32_t *cell, const float *pos4,
+                                    const int32_t *rows, int nrows, const int32_t *nf, const int32_t *nb,
+                                    const int32_t *fl, const int32_t *bl, int max_neibs)
+{
+    int64_t cnt = 0;
+#pragma omp parallel for schedule(static) reduction(+ : cnt)
+    for (int r = 0; r < nrows; ++r)
+        cnt += count_of(g, h, rows[r], cell, pos4, nf[r], nb[r], fl + (size_t)r * max_neibs,
+                        bl + (size_t)r * max_neibs);
     return cnt;
 }
 

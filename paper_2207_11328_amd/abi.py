@@ -27,6 +27,7 @@ EXPORTS = [
     "sph_build_neighbors", "sph_forces", "sph_forces_workspace_bytes", "sph_integrate",
     "sph_dt_workspace_bytes", "sph_step_dt", "sph_count_interactions", "sph_integrate_backward",
     "sph_forces_backward_workspace_bytes", "sph_forces_backward", "sph_unpermute",
+    "sph_diagnostics_workspace_bytes", "sph_reduce_diagnostics",
 ]
 
 
@@ -87,6 +88,10 @@ def _load():
     L.sph_forces_backward.restype = st
     L.sph_unpermute.argtypes = [i32, P, P, P, P]
     L.sph_unpermute.restype = st
+    L.sph_diagnostics_workspace_bytes.argtypes = []
+    L.sph_diagnostics_workspace_bytes.restype = C.c_size_t
+    L.sph_reduce_diagnostics.argtypes = [P, P, P, P, P, C.c_size_t, P]
+    L.sph_reduce_diagnostics.restype = st
     return L
 
 
@@ -215,3 +220,13 @@ def sph_forces_backward(grid: SphGrid, params: SphParams, parts: SphParticles, n
 
 def sph_unpermute(n: int, perm, src, dst, stream=None):
     check(lib.sph_unpermute(int(n), ptr(perm), ptr(src), ptr(dst), stream_ptr(stream)), "sph_unpermute")
+
+
+def sph_diagnostics_workspace_bytes() -> int:
+    return int(lib.sph_diagnostics_workspace_bytes())
+
+
+def sph_reduce_diagnostics(params: SphParams, parts: SphParticles, forces, d_out, workspace, stream=None):
+    check(lib.sph_reduce_diagnostics(C.byref(params), C.byref(parts), ptr(forces), ptr(d_out), ptr(workspace),
+                                     workspace.numel() * workspace.element_size(), stream_ptr(stream)),
+          "sph_reduce_diagnostics")

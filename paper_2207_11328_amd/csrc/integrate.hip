@@ -154,7 +154,104 @@ __global__ __launch_bounds__(kThreads) void k_integrate_backward(int n, int stag
     }
 }
 
+// FP64 conservation diagnostics, two-level fixed-order reduction (the
+// result does not depend on scheduling).  Per particle i < n with cell >= 0:
+//   [0] m   [1..3] m u (fluid)   [4..6] m a (forces xyz; all particles)
+//   [7] m / rho   [8] n fluid   [9] n boundary   [10] max |rho/rho0 - 1| (fluid)
+//   [11] 1/2 m |u|^2 (fluid)
+constexpr int kDiag = 12;
+constexpr int kDiagBlocks = 1024;
+
+__global__ __launch_bounds__(kThreads) void k_diag_partial(int n, const int32_t *__restrict__ cell,
+                                                           const uint32_t *__restrict__ info,
+                                                           const float4 *__restrict__ pos,
+                                                           const float4 *__restrict__ vel,
+                                                           const float4 *__restrict__ forces, float rho0,
+                                                           double *__restrict__ partial)
+{
+    double acc[kDiag];
+#pragma unroll
+    for (int k = 0; k < kDiag; ++k) acc[k] = 0.0;
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
+        if (cell[i] < 0) continue;
+        const float4 p = pos[i], v = vel[i];
+        const double m = p.w;
+        const bool fluid = ptype(info[i]) != kBoundary;
+        acc[0] += m;
+        if (fluid) {
+            acc[1] += m * v.x;
+            acc[2] += m * v.y;
+            acc[3] += m * v.z;
+            acc[8] += 1.0;
+            acc[10] = fmax(acc[10], fabs((double)v.w / rho0 - 1.0));
+            acc[11] += 0.5 * m * ((double)v.x * v.x + (double)v.y * v.y + (double)v.z * v.z);
+        } else {
+            acc[9] += 1.0;
+        }
+        if (forces) {
+            const float4 f = forces[i];
+            acc[4] += m * f.x;
+            acc[5] += m * f.y;
+            acc[6] += m * f.z;
+        }
+        acc[7] += m / (double)v.w;
+    }
+    __shared__ double red[kDiag][kThreads / kWave];
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < kDiag; ++k) {
+        const double t = k == 10 ? wave_max(acc[k]) : wave_sum(acc[k]);
+        if (lane == 0) red[k][w] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < kDiag) {
+        const int k = threadIdx.x;
+        double t = red[k][0];
+        for (int q = 1; q < kThreads / kWave; ++q) t = k == 10 ? fmax(t, red[k][q]) : t + red[k][q];
+        partial[(size_t)blockIdx.x * kDiag + k] = t;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_diag_final(int np, const double *__restrict__ partial,
+                                                         double *__restrict__ out)
+{
+    // one thread per quantity, blocks in a fixed order
+    if (threadIdx.x < kDiag) {
+        const int k = threadIdx.x;
+        double t = 0.0;
+        for (int b = 0; b < np; ++b) {
+            const double v = partial[(size_t)b * kDiag + k];
+            t = k == 10 ? fmax(t, v) : t + v;
+        }
+        out[k] = t;
+    }
+}
+
 }  // namespace
+
+extern "C" size_t sph_diagnostics_workspace_bytes(void) { return sizeof(double) * kDiag * kDiagBlocks; }
+
+extern "C" sph_status sph_reduce_diagnostics(const sph_params *params, const sph_particles *parts,
+                                             const float *forces, double *d_out, void *workspace,
+                                             size_t workspace_bytes, void *stream)
+{
+    if (!params || !parts || !d_out) return SPH_ERR_ARG;
+    const int n = parts->n;
+    if (n < 0 || parts->capacity < n) return SPH_ERR_ARG;
+    if (n > 0 && (!parts->cell || !parts->pos || !parts->vel || !parts->info)) return SPH_ERR_ARG;
+    if (!(params->rho0 > 0.0f)) return SPH_ERR_ARG;
+    if (!workspace || workspace_bytes < sph_diagnostics_workspace_bytes()) return SPH_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    const unsigned want = n > 0 ? sph_blocks(n, kThreads) : 1;
+    const int blocks = (int)(want < (unsigned)kDiagBlocks ? want : (unsigned)kDiagBlocks);
+    double *partial = (double *)workspace;
+    k_diag_partial<<<blocks, kThreads, 0, s>>>(n, parts->cell, parts->info, (const float4 *)parts->pos,
+                                               (const float4 *)parts->vel, (const float4 *)forces, params->rho0,
+                                               partial);
+    k_diag_final<<<1, 64, 0, s>>>(blocks, partial, d_out);
+    SPH_CHECK_LAUNCH();
+    return SPH_OK;
+}
 
 extern "C" sph_status sph_integrate_backward(const sph_params *params, int32_t stage, const double *d_dt,
                                              const sph_particles *state_n, float *grad_pos, float *grad_vel,

@@ -112,6 +112,19 @@ class Simulation:
             abi.sph_integrate(self.p, 1, self.d_dt, self.parts, self.vel_star, self.forces_star, self.parts,
                               self.d_time, stream)
 
+    DIAG_NAMES = ("mass", "mom_x", "mom_y", "mom_z", "force_x", "force_y", "force_z", "volume", "n_fluid",
+                  "n_boundary", "max_rel_density", "kinetic")
+
+    def diagnostics(self, with_forces: bool = True, stream=None) -> dict:
+        """FP64 conservation sums of the current state (host dict; syncs)."""
+        if not hasattr(self, "_diag_out"):
+            self._diag_out = torch.zeros(12, dtype=torch.float64, device=self.device)
+            self._diag_ws = torch.zeros(abi.sph_diagnostics_workspace_bytes(), dtype=torch.uint8,
+                                        device=self.device)
+        abi.sph_reduce_diagnostics(self.p, self.parts, self.forces_n if with_forces else None, self._diag_out,
+                                   self._diag_ws, stream)
+        return dict(zip(self.DIAG_NAMES, self._diag_out.cpu().numpy().tolist()))
+
     def count_interactions(self, stream=None) -> torch.Tensor:
         abi.sph_count_interactions(self.g, self.p, self.parts, self.neibs, self.neib_count, self.max_neibs,
                                    self.count, stream)

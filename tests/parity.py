@@ -63,6 +63,30 @@ def gpu_lists_padded(sim):
     return fi, bi, fc, bc, nf, nbd
 
 
+def gpu_lists_rows(sim, rows):
+    """As gpu_lists_padded, for the particles `rows` only (gathered on the
+    device from the tiled list, so very large lists are never copied whole)."""
+    M = sim.max_neibs
+    r = torch.as_tensor(np.asarray(rows, np.int64), device=sim.device)
+    k = torch.arange(M, device=sim.device, dtype=torch.int64)
+    idx = (r // 64)[:, None] * (64 * M) + k[None, :] * 64 + (r % 64)[:, None]
+    E = sim.neibs[idx].cpu().numpy().view(np.uint32).astype(np.int64)  # [m, M]
+    cnt = sim.neib_count[r].cpu().numpy().view(np.uint32)
+    nf = (cnt & 0xFFFF).astype(np.int64)
+    nbd = (cnt >> 16).astype(np.int64)
+    col = np.arange(M)[None, :]
+    fmask = col < nf[:, None]
+    bmask = col >= (M - nbd)[:, None]
+    idxv = E & ((1 << 26) - 1)
+    code = E >> 26
+    fi = np.where(fmask, idxv, SENT)
+    bi = np.where(bmask, idxv, SENT)
+    fo = np.argsort(fi, axis=1, kind="stable")
+    bo = np.argsort(bi, axis=1, kind="stable")
+    return (np.take_along_axis(fi, fo, 1), np.take_along_axis(bi, bo, 1),
+            np.take_along_axis(np.where(fmask, code, -1), fo, 1), np.take_along_axis(np.where(bmask, code, -1), bo, 1))
+
+
 def oracle_lists_padded(lists, max_neibs):
     n = lists.nf.shape[0]
     col = np.arange(max_neibs)[None, :]

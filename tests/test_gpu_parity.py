@@ -222,3 +222,38 @@ def test_step_sequence_matches_oracle_rollout():
         % (dpos, dvel, drho, sim.time, t))
     assert abs(sim.time - t) <= 1e-5 * t
     assert dpos < 1e-6 and dvel < 1e-4 and drho < 1e-2
+
+
+def test_fp64_diagnostics():
+    """The FP64 conservation sums against float64 sums of the lifted state,
+    and the momentum balance of the raw pair sums on a wall-free periodic box."""
+    sc = S.shuffled(S.dam_break(dp=0.02, u0_sigma=0.05), seed=3)
+    sim = make_sim(sc)
+    sim.build()
+    sim.forces()
+    d = sim.diagnostics()
+    st = sim.state_host()
+    f = sim.forces_n[: sc.n].cpu().numpy().astype(np.float64)
+    m = st["pos"][:, 3].astype(np.float64)
+    u = st["vel"][:, :3].astype(np.float64)
+    rho = st["vel"][:, 3].astype(np.float64)
+    fl = (st["info"] >> 30) == 0
+    ref = {"mass": m.sum(), "mom_x": (m * u[:, 0])[fl].sum(), "volume": (m / rho).sum(),
+           "n_fluid": fl.sum(), "n_boundary": (~fl).sum(), "force_z": (m * f[:, 2]).sum(),
+           "kinetic": 0.5 * (m * (u * u).sum(1))[fl].sum(),
+           "max_rel_density": np.abs(rho[fl] / O.f32(sc.params.rho0) - 1).max()}
+    # double sums in another order: compare against the sum of magnitudes
+    scale = {"mom_x": np.abs(m * u[:, 0])[fl].sum(), "force_z": np.abs(m * f[:, 2]).sum()}
+    for k, v in ref.items():
+        assert abs(d[k] - v) <= 1e-12 * max(abs(v), scale.get(k, 0.0), 1e-300), (k, d[k], v)
+    box = S.periodic_box(n=12, dp=0.02, jitter=0.1, u_sigma=0.1, rho_sigma=0.003, seed=4)
+    sim2 = make_sim(box)
+    sim2.build()
+    sim2.forces()
+    d2 = sim2.diagnostics()
+    f2 = sim2.forces_n[: box.n].cpu().numpy().astype(np.float64)
+    m2 = box.pos[:, 3].astype(np.float64)
+    scale = (m2[:, None] * np.abs(f2)).sum(0)
+    for k, name in enumerate(("force_x", "force_y", "force_z")):
+        assert abs(d2[name]) <= 1e-6 * scale[k], (name, d2[name], scale[k])
+    log("momentum balance of the raw pair sums: %s (scale %s)" % ([d2[k] for k in ("force_x", "force_y", "force_z")], scale))
