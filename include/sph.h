@@ -189,15 +189,22 @@ sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
  * forces: device float[capacity][4], xyz = a_i [m/s^2], w = Drho_i/Dt,
  * fully overwritten for i < n.  Particles are read in the order of the last
  * build; positions may have drifted since (lists are reused).
- * workspace: device buffer of sph_forces_workspace_bytes(capacity) bytes
- * (per-particle equation-of-state terms, recomputed by every call).
+ * cell_start / cell_end: the cell ranges written by that build (device
+ * int32[n_cells] each), or both NULL.  With them the derivatives are computed
+ * brick by brick of cells, the particles of a brick and of its one-cell halo
+ * staged in LDS; without them one lane per particle gathers its neighbours
+ * from global memory.  Both give the same result bit for bit.
+ * workspace: device buffer of sph_forces_workspace_bytes(capacity, n_cells)
+ * bytes (per-particle equation-of-state terms and the list of bricks that
+ * hold particles, both recomputed by every call).
  * Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
 sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
                       const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
+                      const int32_t *cell_start, const int32_t *cell_end,
                       float *forces, void *workspace, size_t workspace_bytes, void *stream);
 
-/* Bytes of device workspace sph_forces needs. */
-size_t sph_forces_workspace_bytes(int32_t capacity);
+/* Bytes of device workspace sph_forces needs (n_cells: cells of the grid). */
+size_t sph_forces_workspace_bytes(int32_t capacity, int32_t n_cells);
 
 /* Explicit midpoint predictor/corrector (section "Code structure": phases
  * with dt/2 and dt).  d_dt: device double, the step.

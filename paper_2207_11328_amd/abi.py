@@ -64,13 +64,13 @@ def _load():
     L.sph_abi_version.restype = i32
     L.sph_neib_list_entries.argtypes = [i32, i32]
     L.sph_neib_list_entries.restype = C.c_size_t
-    L.sph_forces_workspace_bytes.argtypes = [i32]
+    L.sph_forces_workspace_bytes.argtypes = [i32, i32]
     L.sph_forces_workspace_bytes.restype = C.c_size_t
     L.sph_build_workspace_bytes.argtypes = [i32, i32]
     L.sph_build_workspace_bytes.restype = C.c_size_t
     L.sph_build_neighbors.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, C.c_size_t, P]
     L.sph_build_neighbors.restype = st
-    L.sph_forces.argtypes = [P, P, P, P, P, i32, P, P, C.c_size_t, P]
+    L.sph_forces.argtypes = [P, P, P, P, P, i32, P, P, P, P, C.c_size_t, P]
     L.sph_forces.restype = st
     L.sph_integrate.argtypes = [P, i32, P, P, P, P, P, P, P]
     L.sph_integrate.restype = st
@@ -157,8 +157,8 @@ def sph_neib_list_entries(capacity: int, max_neibs: int) -> int:
     return int(lib.sph_neib_list_entries(int(capacity), int(max_neibs)))
 
 
-def sph_forces_workspace_bytes(capacity: int) -> int:
-    return int(lib.sph_forces_workspace_bytes(int(capacity)))
+def sph_forces_workspace_bytes(capacity: int, n_cells: int) -> int:
+    return int(lib.sph_forces_workspace_bytes(int(capacity), int(n_cells)))
 
 
 def sph_dt_workspace_bytes() -> int:
@@ -174,10 +174,10 @@ def sph_build_neighbors(grid: SphGrid, params: SphParams, parts: SphParticles, n
 
 
 def sph_forces(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count, max_neibs: int,
-               forces, workspace, stream=None):
+               forces, workspace, stream=None, cell_start=None, cell_end=None):
     check(lib.sph_forces(C.byref(grid), C.byref(params), C.byref(parts), ptr(neibs), ptr(neib_count),
-                         int(max_neibs), ptr(forces), ptr(workspace), workspace.numel() * workspace.element_size(),
-                         stream_ptr(stream)), "sph_forces")
+                         int(max_neibs), ptr(cell_start), ptr(cell_end), ptr(forces), ptr(workspace),
+                         workspace.numel() * workspace.element_size(), stream_ptr(stream)), "sph_forces")
 
 
 def sph_integrate(params: SphParams, stage: int, d_dt, state_n: SphParticles, vel_star, forces,

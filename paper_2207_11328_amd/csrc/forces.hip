@@ -27,6 +27,11 @@ using namespace sph;
 namespace {
 
 constexpr int kThreads = 256;
+// pairs in flight per lane in the derivative loop
+#ifndef SPH_FORCES_DEPTH
+#define SPH_FORCES_DEPTH 4
+#endif
+constexpr int kDepth = SPH_FORCES_DEPTH;
 
 struct ForceConst {
     float csx, csy, csz;
@@ -160,31 +165,307 @@ __global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__rest
     const float2 ai = aux[ii];
     PairAcc A = {0.0f, 0.0f, 0.0f, 0.0f};
 
-    // Software pipeline, unrolled by two.  Entry k+2 is requested before pair k
-    // is evaluated and the neighbour data of pair k+1 while pair k is being
-    // evaluated; the data registers of set A are only ever written by loads,
-    // so the loop carries no copy of an in-flight value.
-    uint32_t eA = tile[list_slot(0, nf, last, M) * kWave + lane];
-    uint32_t eNext = tile[list_slot(1, nf, last, M) * kWave + lane];
-    uint32_t jA = min(eA & kIndexMask, jmax);
-    float4 pA = pos[jA], vA = vel[jA];
-    float2 xA = aux[jA];
-    for (int k = 0; k < ntw; k += 2) {
-        const uint32_t eN2 = tile[list_slot(k + 2, nf, last, M) * kWave + lane];
-        const uint32_t eB = eNext;
-        const uint32_t jB = min(eB & kIndexMask, jmax);
-        const float4 pB = pos[jB], vB = vel[jB];
-        const float2 xB = aux[jB];
-        pair_terms<VISC>(A, eA, pi, vi, ai, pA, vA, xA, k < nt, C);
-        eNext = tile[list_slot(k + 3, nf, last, M) * kWave + lane];
-        eA = eN2;
-        jA = min(eA & kIndexMask, jmax);
-        pA = pos[jA];
-        vA = vel[jA];
-        xA = aux[jA];
-        pair_terms<VISC>(A, eB, pi, vi, ai, pB, vB, xB, k + 1 < nt, C);
+    // Software pipeline over a ring of kDepth pair slots, unrolled by kDepth:
+    // slot s holds the neighbour data of pair k + s (requested kDepth pairs
+    // before it is used) and the list entry of pair k + s + kDepth (requested
+    // 2 kDepth pairs ahead).  Neighbour data registers are only ever written
+    // by loads, so the loop carries no copy of an in-flight value.
+    uint32_t e[kDepth], en[kDepth];
+    float4 P[kDepth], V[kDepth];
+    float2 X[kDepth];
+#pragma unroll
+    for (int s = 0; s < kDepth; ++s) {
+        e[s] = tile[list_slot(s, nf, last, M) * kWave + lane];
+        en[s] = tile[list_slot(s + kDepth, nf, last, M) * kWave + lane];
+    }
+#pragma unroll
+    for (int s = 0; s < kDepth; ++s) {
+        const uint32_t j = min(e[s] & kIndexMask, jmax);
+        P[s] = pos[j];
+        V[s] = vel[j];
+        X[s] = aux[j];
+    }
+    for (int k = 0; k < ntw; k += kDepth) {
+#pragma unroll
+        for (int s = 0; s < kDepth; ++s) {
+            pair_terms<VISC>(A, e[s], pi, vi, ai, P[s], V[s], X[s], k + s < nt, C);
+            e[s] = en[s];
+            const uint32_t j = min(e[s] & kIndexMask, jmax);
+            P[s] = pos[j];
+            V[s] = vel[j];
+            X[s] = aux[j];
+            en[s] = tile[list_slot(k + s + 2 * kDepth, nf, last, M) * kWave + lane];
+        }
     }
     if (i < n) out[i] = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// ---------------------------------------------------------------------------
+// Cell-brick variant of the derivative kernel.  A workgroup owns a brick of
+// BX x BY x BZ cells; it first copies the particles of the brick and of its
+// one-cell halo (every possible neighbour of its particles) from HBM/L2 into
+// LDS with coalesced loads, one contiguous cell range after another, then
+// each lane walks the list of one central particle of the brick exactly as
+// k_forces does, but reads the neighbour data from LDS.  This is the
+// cell-centred perspective the paper applies to the list construction,
+// applied to the derivatives: the 64 lanes of a wave read neighbours that are
+// scattered over dozens of cache lines, which the global-gather kernel pays
+// in L1/L2 request throughput.  The arithmetic and its order are those of
+// k_forces, so the result is bit for bit the same.  A brick whose halo does
+// not fit the LDS capacity falls back to global reads (same loop).
+struct BrickGrid {
+    int nx, ny, nz;
+    uint32_t periodic;
+    int nbx, nby, nbz;
+};
+
+__device__ __forceinline__ bool wrap_axis(int &c, int n, uint32_t periodic)
+{
+    if (periodic) {
+        if (c < 0) c += n;
+        if (c >= n) c -= n;
+        return true;
+    }
+    return c >= 0 && c < n;
+}
+
+// exclusive scan of one int per thread over a block of NT threads
+template <int NT>
+__device__ __forceinline__ int block_scan(int v, int &total, int *wsum)
+{
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    if (lane == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    int off = 0;
+    total = 0;
+#pragma unroll
+    for (int k = 0; k < NT / kWave; ++k) {
+        off += k < w ? wsum[k] : 0;
+        total += wsum[k];
+    }
+    __syncthreads();
+    return off + inc - v;
+}
+
+// List the bricks that hold at least one particle (order is irrelevant: each
+// brick writes only its own particles).  active[0] must be zero on entry.
+template <int BX, int BY, int BZ>
+__global__ __launch_bounds__(256) void k_active_bricks(const int32_t *__restrict__ cell_start,
+                                                       const int32_t *__restrict__ cell_end, BrickGrid G,
+                                                       int32_t *__restrict__ active)
+{
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    const int nb = G.nbx * G.nby * G.nbz;
+    int cnt = 0;
+    if (b < nb) {
+        const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
+        const int cx1 = min(cx0 + BX, G.nx) - 1;
+        for (int z = cz0; z < min(cz0 + BZ, G.nz); ++z)
+            for (int y = cy0; y < min(cy0 + BY, G.ny); ++y) {
+                const int row = G.nx * (y + G.ny * z);
+                cnt += cell_end[row + cx1] - cell_start[row + cx0];
+            }
+    }
+    const bool has = cnt > 0;
+    // wave-aggregated append
+    const unsigned long long ballot = __ballot(has);
+    const int lane = threadIdx.x % kWave;
+    const int before = __popcll(ballot & ((1ull << lane) - 1ull));
+    int base = 0;
+    if (lane == 0 && ballot) base = atomicAdd(&active[0], (int)__popcll(ballot));
+    base = __shfl(base, 0);
+    if (has) active[1 + base + before] = b;
+}
+
+__global__ void k_zero_i32(int32_t *p) { *p = 0; }
+
+#ifndef SPH_BRICK_DEPTH
+#define SPH_BRICK_DEPTH 6
+#endif
+constexpr int kBrickDepth = SPH_BRICK_DEPTH;
+
+template <int VISC, int NT, bool LDS>
+__device__ __forceinline__ void brick_pairs(PairAcc &A, const uint32_t *tile, int lane_in_tile, int nf, int nt,
+                                            int ntw, int M, uint32_t jmax, int total, int dbase,
+                                            const int *__restrict__ dtab, const float4 *__restrict__ sP,
+                                            const float4 *__restrict__ sV, const float2 *__restrict__ sA,
+                                            const float4 *__restrict__ pos, const float4 *__restrict__ vel,
+                                            const float2 *__restrict__ aux, const float4 &pi, const float4 &vi,
+                                            const float2 &ai, const ForceConst &C)
+{
+    const int last = max(nt - 1, 0);
+    uint32_t e[kBrickDepth], en[kBrickDepth];
+    float4 P[kBrickDepth], V[kBrickDepth];
+    float2 X[kBrickDepth];
+    auto fetch = [&](uint32_t ee, float4 &p, float4 &v, float2 &x) {
+        const uint32_t j = min(ee & kIndexMask, jmax);
+        if (LDS) {
+            int slot = (int)j + dtab[dbase + (int)(ee >> 26)];
+            slot = min(max(slot, 0), total - 1);
+            p = sP[slot];
+            v = sV[slot];
+            x = sA[slot];
+        } else {
+            p = pos[j];
+            v = vel[j];
+            x = aux[j];
+        }
+    };
+#pragma unroll
+    for (int s = 0; s < kBrickDepth; ++s) {
+        e[s] = tile[list_slot(s, nf, last, M) * kWave + lane_in_tile];
+        en[s] = tile[list_slot(s + kBrickDepth, nf, last, M) * kWave + lane_in_tile];
+    }
+#pragma unroll
+    for (int s = 0; s < kBrickDepth; ++s) fetch(e[s], P[s], V[s], X[s]);
+    for (int k = 0; k < ntw; k += kBrickDepth) {
+#pragma unroll
+        for (int s = 0; s < kBrickDepth; ++s) {
+            pair_terms<VISC>(A, e[s], pi, vi, ai, P[s], V[s], X[s], k + s < nt, C);
+            e[s] = en[s];
+            fetch(e[s], P[s], V[s], X[s]);
+            en[s] = tile[list_slot(k + s + 2 * kBrickDepth, nf, last, M) * kWave + lane_in_tile];
+        }
+    }
+}
+
+template <int VISC, int BX, int BY, int BZ, int NT, int CAP>
+__global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__restrict__ pos,
+                                                     const float4 *__restrict__ vel,
+                                                     const float2 *__restrict__ aux,
+                                                     const uint32_t *__restrict__ neibs,
+                                                     const uint32_t *__restrict__ count,
+                                                     const int32_t *__restrict__ cell_start,
+                                                     const int32_t *__restrict__ cell_end,
+                                                     const int32_t *__restrict__ active,
+                                                     float4 *__restrict__ out, ForceConst C, BrickGrid G)
+{
+    constexpr int SX = BX + 2, SY = BY + 2, SZ = BZ + 2;
+    constexpr int S = SX * SY * SZ;  // staged cells
+    constexpr int NI = BX * BY * BZ; // inner cells
+    static_assert(S <= NT && NI <= NT, "one thread per cell");
+    __shared__ float4 sP[CAP];
+    __shared__ float4 sV[CAP];
+    __shared__ float2 sA[CAP];
+    __shared__ int cBase[S + 1];
+    __shared__ int cDelta[S];
+    __shared__ int iBase[NI + 1];
+    __shared__ int iStart[NI];
+    __shared__ int dtab[NI * 64];  // [inner cell][entry code] -> LDS slot - particle index
+    __shared__ int wsum[NT / kWave];
+
+    const int tid = threadIdx.x;
+    // active[0] = number of bricks holding particles, active[1 + k] = brick id
+    if ((int)blockIdx.x >= active[0]) return;
+    const int b = active[1 + blockIdx.x];
+    const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
+
+    // 1. ranges of the staged cells and their LDS bases
+    int st = 0, cnt = 0;
+    if (tid < S) {
+        int gx = cx0 - 1 + tid % SX, gy = cy0 - 1 + (tid / SX) % SY, gz = cz0 - 1 + tid / (SX * SY);
+        const bool ok = wrap_axis(gx, G.nx, G.periodic & 1u) && wrap_axis(gy, G.ny, (G.periodic >> 1) & 1u) &&
+                        wrap_axis(gz, G.nz, (G.periodic >> 2) & 1u);
+        if (ok) {
+            const int lin = gx + G.nx * (gy + G.ny * gz);
+            st = cell_start[lin];
+            cnt = cell_end[lin] - st;
+        }
+    }
+    int total;
+    const int ex = block_scan<NT>(cnt, total, wsum);
+    if (tid < S) {
+        cBase[tid] = ex;
+        cDelta[tid] = ex - st;
+    }
+    if (tid == 0) cBase[S] = total;
+    __syncthreads();
+    // inner cells (x fastest: each inner row is one contiguous particle range)
+    int icnt = 0, ist = 0;
+    if (tid < NI) {
+        const int t = (tid % BX + 1) + SX * ((tid / BX) % BY + 1) + SX * SY * (tid / (BX * BY) + 1);
+        icnt = cBase[t + 1] - cBase[t];
+        ist = cBase[t] - cDelta[t];
+    }
+    int nc;
+    const int iex = block_scan<NT>(icnt, nc, wsum);
+    if (tid < NI) {
+        iBase[tid] = iex;
+        iStart[tid] = ist;
+    }
+    if (tid == 0) iBase[NI] = nc;
+    if (nc == 0) return;  // uniform: no particle in the brick
+    const bool use_lds = total <= CAP;
+    if (use_lds) {
+        // slot offsets per (inner cell, entry code): the neighbour of a particle
+        // of inner cell u with cell difference k lives in staged cell t(u) - k
+        for (int q = tid; q < NI * 64; q += NT) {
+            const int u = q / 64, code = q % 64;
+            const int kx = (int32_t)((uint32_t)code << 30) >> 30;
+            const int ky = (int32_t)((uint32_t)code << 28) >> 30;
+            const int kz = (int32_t)((uint32_t)code << 26) >> 30;
+            const int sx = u % BX + 1 - kx, sy = (u / BX) % BY + 1 - ky, sz = u / (BX * BY) + 1 - kz;
+            const bool valid = kx >= -1 && kx <= 1 && ky >= -1 && ky <= 1 && kz >= -1 && kz <= 1;
+            dtab[q] = valid ? cDelta[sx + SX * (sy + SY * sz)] : 0;
+        }
+        // 2. stage the brick and its halo (slot -> cell by binary search)
+        for (int s2 = tid; s2 < total; s2 += NT) {
+            int lo = 0, hi = S - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (cBase[mid] <= s2) lo = mid;
+                else hi = mid - 1;
+            }
+            const int j = s2 - cDelta[lo];
+            sP[s2] = pos[j];
+            sV[s2] = vel[j];
+            sA[s2] = aux[j];
+        }
+    }
+    __syncthreads();
+
+    // 3. one lane per central particle of the brick
+    const int M = C.max_neibs;
+    const uint32_t jmax = (uint32_t)(n - 1);
+    for (int q0 = 0; q0 < nc; q0 += NT) {
+        const int q = q0 + tid;
+        const bool act = q < nc;
+        int u = 0;
+        {
+            int lo = 0, hi = NI - 1;
+            const int qq = act ? q : nc - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (iBase[mid] <= qq) lo = mid;
+                else hi = mid - 1;
+            }
+            u = lo;
+        }
+        const int i = iStart[u] + ((act ? q : nc - 1) - iBase[u]);
+        const uint32_t cntw = act ? count[i] : 0u;
+        const int nf = min((int)(cntw & 0xFFFFu), M);
+        const int nt = min(nf + (int)(cntw >> 16), M);
+        const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
+        PairAcc A = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (ntw > 0) {
+            const uint32_t *tile = neibs + (size_t)(i / kWave) * (kWave * M);
+            const float4 pi = pos[i], vi = vel[i];
+            const float2 ai = aux[i];
+            if (use_lds)
+                brick_pairs<VISC, NT, true>(A, tile, i % kWave, nf, nt, ntw, M, jmax, total, u * 64, dtab, sP, sV, sA,
+                                            pos, vel, aux, pi, vi, ai, C);
+            else
+                brick_pairs<VISC, NT, false>(A, tile, i % kWave, nf, nt, ntw, M, jmax, total, u * 64, dtab, sP, sV,
+                                             sA, pos, vel, aux, pi, vi, ai, C);
+        }
+        if (act) out[i] = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
 }
 
 __global__ __launch_bounds__(kThreads) void k_count_interactions(int n, const float4 *__restrict__ pos,
@@ -216,6 +497,13 @@ __global__ __launch_bounds__(kThreads) void k_count_interactions(int n, const fl
 }
 
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
+
+__global__ __launch_bounds__(kThreads) void k_zero_dropped(int n, const int32_t *__restrict__ cell,
+                                                           float4 *__restrict__ out)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n && cell[i] < 0) out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
 
 bool make_const(const sph_grid *g, const sph_params *p, int max_neibs, ForceConst &C)
 {
@@ -256,35 +544,85 @@ size_t aux_bytes(int64_t capacity) { return (size_t)((sizeof(float2) * capacity 
 
 }  // namespace
 
-extern "C" size_t sph_forces_workspace_bytes(int32_t capacity)
+extern "C" size_t sph_forces_workspace_bytes(int32_t capacity, int32_t n_cells)
 {
-    if (capacity < 0) return 0;
-    return aux_bytes(capacity > 0 ? capacity : 1);
+    if (capacity < 0 || n_cells < 0) return 0;
+    // per-particle EOS terms, then the active-brick list (at most one brick per cell)
+    return aux_bytes(capacity > 0 ? capacity : 1) + sizeof(int32_t) * ((size_t)n_cells + 1) + 256;
+}
+
+// brick shape of the LDS kernel: 3 x 3 x 3 cells (about 620 particles at the
+// h = 1.3 dp, r_s = 2.86 dp lattice density, 10 waves), halo of 5^3 cells
+// (about 2900 particles, 3700 fit in 148 KB of the 160 KB of LDS)
+#ifndef SPH_BRICK
+#define SPH_BRICK 3
+#define SPH_BRICK_THREADS 640
+#define SPH_BRICK_CAP 3700
+#endif
+constexpr int kBrick = SPH_BRICK;
+constexpr int kBrickThreads = SPH_BRICK_THREADS;
+constexpr int kBrickCap = SPH_BRICK_CAP;
+
+template <int VISC>
+void launch_brick(const sph_grid *grid, int n, const float4 *pos, const float4 *vel, const float2 *aux,
+                  const uint32_t *neibs, const uint32_t *count, const int32_t *cell_start, const int32_t *cell_end,
+                  int32_t *active, float4 *out, const ForceConst &C, hipStream_t s)
+{
+    BrickGrid G;
+    G.nx = grid->ncell[0];
+    G.ny = grid->ncell[1];
+    G.nz = grid->ncell[2];
+    G.periodic = grid->periodic;
+    G.nbx = (G.nx + kBrick - 1) / kBrick;
+    G.nby = (G.ny + kBrick - 1) / kBrick;
+    G.nbz = (G.nz + kBrick - 1) / kBrick;
+    const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
+    k_zero_i32<<<1, 1, 0, s>>>(active);
+    k_active_bricks<kBrick, kBrick, kBrick><<<sph_blocks(blocks, 256), 256, 0, s>>>(cell_start, cell_end, G, active);
+    k_forces_brick<VISC, kBrick, kBrick, kBrick, kBrickThreads, kBrickCap><<<blocks, kBrickThreads, 0, s>>>(
+        n, pos, vel, aux, neibs, count, cell_start, cell_end, active, out, C, G);
 }
 
 extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
                                  const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
+                                 const int32_t *cell_start, const int32_t *cell_end,
                                  float *forces, void *workspace, size_t workspace_bytes, void *stream)
 {
     if (!common_args(grid, params, parts, neibs, neib_count, max_neibs)) return SPH_ERR_ARG;
     if (parts->n > 0 && !forces) return SPH_ERR_ARG;
     ForceConst C;
     if (!make_const(grid, params, max_neibs, C)) return SPH_ERR_ARG;
-    if (!workspace || workspace_bytes < sph_forces_workspace_bytes(parts->capacity)) return SPH_ERR_WORKSPACE;
+    const int64_t n_cells = (int64_t)grid->ncell[0] * grid->ncell[1] * grid->ncell[2];
+    if (n_cells <= 0 || n_cells > INT32_MAX - 1) return SPH_ERR_ARG;
+    if (!workspace || workspace_bytes < sph_forces_workspace_bytes(parts->capacity, (int32_t)n_cells))
+        return SPH_ERR_WORKSPACE;
     const int n = parts->n;
     if (n == 0) return SPH_OK;
     hipStream_t s = (hipStream_t)stream;
     const float4 *pos = (const float4 *)parts->pos;
     const float4 *vel = (const float4 *)parts->vel;
     float2 *aux = (float2 *)workspace;
+    int32_t *active = (int32_t *)((char *)workspace + aux_bytes(parts->capacity > 0 ? parts->capacity : 1));
     float4 *out = (float4 *)forces;
     if (grid->cell_alpha && !parts->cell) return SPH_ERR_ARG;
     k_eos<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, vel, aux, parts->cell, grid->cell_alpha, grid->cell_base,
                                                        params->h, C);
-    if (params->visc_model == 0)
+    if (cell_start && cell_end) {
+        // cell ranges of the last build: LDS cell-brick kernel (it writes the
+        // derivatives of every particle that lies in a cell; particles dropped
+        // by the build have none)
+        if (params->visc_model == 0)
+            launch_brick<0>(grid, n, pos, vel, aux, neibs, neib_count, cell_start, cell_end, active, out, C, s);
+        else
+            launch_brick<1>(grid, n, pos, vel, aux, neibs, neib_count, cell_start, cell_end, active, out, C, s);
+        SPH_CHECK_LAUNCH();
+        // dropped particles (cell < 0) are in no cell: zero their derivatives
+        k_zero_dropped<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, parts->cell, out);
+    } else if (params->visc_model == 0) {
         k_forces<0><<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, pos, vel, aux, neibs, neib_count, out, C);
-    else
+    } else {
         k_forces<1><<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, pos, vel, aux, neibs, neib_count, out, C);
+    }
     SPH_CHECK_LAUNCH();
     return SPH_OK;
 }

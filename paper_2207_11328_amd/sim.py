@@ -62,7 +62,7 @@ class Simulation:
         self.status = z(4, torch.int32)
         self.ws_build = z(abi.sph_build_workspace_bytes(cap, self.n_cells), torch.uint8)
         self.ws_dt = z(abi.sph_dt_workspace_bytes(), torch.uint8)
-        self.ws_forces = z(abi.sph_forces_workspace_bytes(cap), torch.uint8)
+        self.ws_forces = z(abi.sph_forces_workspace_bytes(cap, self.n_cells), torch.uint8)
         self.d_dt = z(1, torch.float64)
         self.d_time = z(1, torch.float64)
         self.count = z(1, torch.int64)
@@ -94,11 +94,15 @@ class Simulation:
         for k, v in kw.items():
             setattr(self.p, k, float(v))
 
-    def forces(self, star: bool = False, stream=None):
+    def forces(self, star: bool = False, stream=None, bricks: bool = True):
+        """Derivatives of the state n (or *).  bricks: the LDS cell-brick
+        kernel (uses the cell ranges of the last build); False: the
+        per-particle global-gather kernel.  Same result bit for bit."""
         parts = self.parts_star if star else self.parts
         out = self.forces_star if star else self.forces_n
+        cs, ce = (self.cell_start, self.cell_end) if bricks else (None, None)
         abi.sph_forces(self.g, self.p, parts, self.neibs, self.neib_count, self.max_neibs, out, self.ws_forces,
-                       stream)
+                       stream, cs, ce)
         return out
 
     def step_dt(self, stream=None):

@@ -75,9 +75,10 @@ def test_argument_errors_return_before_any_launch(abi):
     g = abi.SphGrid()
     p = abi.SphParams()
     parts = abi.SphParticles(10, 5, None, None, None, None)  # n > capacity
-    assert abi.lib.sph_forces(C.byref(g), C.byref(p), C.byref(parts), None, None, 128, None, None, 0,
+    assert abi.lib.sph_forces(C.byref(g), C.byref(p), C.byref(parts), None, None, 128, None, None, None, None,
+                              0, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_forces(None, None, None, None, None, 128, None, None, None, None, 0,
                               None) == abi.SPH_ERR_ARG
-    assert abi.lib.sph_forces(None, None, None, None, None, 128, None, None, 0, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_build_neighbors(None, None, None, None, None, 128, None, None, None, None, None, 0,
                                        None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_forces_backward(None, None, None, None, None, 128, None, None, None, None, 0, None, 0,
