@@ -213,78 +213,6 @@ __global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__rest
 // in L1/L2 request throughput.  The arithmetic and its order are those of
 // k_forces, so the result is bit for bit the same.  A brick whose halo does
 // not fit the LDS capacity falls back to global reads (same loop).
-struct BrickGrid {
-    int nx, ny, nz;
-    uint32_t periodic;
-    int nbx, nby, nbz;
-};
-
-__device__ __forceinline__ bool wrap_axis(int &c, int n, uint32_t periodic)
-{
-    if (periodic) {
-        if (c < 0) c += n;
-        if (c >= n) c -= n;
-        return true;
-    }
-    return c >= 0 && c < n;
-}
-
-// exclusive scan of one int per thread over a block of NT threads
-template <int NT>
-__device__ __forceinline__ int block_scan(int v, int &total, int *wsum)
-{
-    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-    int inc = v;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const int t = __shfl_up(inc, o);
-        if (lane >= o) inc += t;
-    }
-    if (lane == kWave - 1) wsum[w] = inc;
-    __syncthreads();
-    int off = 0;
-    total = 0;
-#pragma unroll
-    for (int k = 0; k < NT / kWave; ++k) {
-        off += k < w ? wsum[k] : 0;
-        total += wsum[k];
-    }
-    __syncthreads();
-    return off + inc - v;
-}
-
-// List the bricks that hold at least one particle (order is irrelevant: each
-// brick writes only its own particles).  active[0] must be zero on entry.
-template <int BX, int BY, int BZ>
-__global__ __launch_bounds__(256) void k_active_bricks(const int32_t *__restrict__ cell_start,
-                                                       const int32_t *__restrict__ cell_end, BrickGrid G,
-                                                       int32_t *__restrict__ active)
-{
-    const int b = blockIdx.x * 256 + threadIdx.x;
-    const int nb = G.nbx * G.nby * G.nbz;
-    int cnt = 0;
-    if (b < nb) {
-        const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
-        const int cx1 = min(cx0 + BX, G.nx) - 1;
-        for (int z = cz0; z < min(cz0 + BZ, G.nz); ++z)
-            for (int y = cy0; y < min(cy0 + BY, G.ny); ++y) {
-                const int row = G.nx * (y + G.ny * z);
-                cnt += cell_end[row + cx1] - cell_start[row + cx0];
-            }
-    }
-    const bool has = cnt > 0;
-    // wave-aggregated append
-    const unsigned long long ballot = __ballot(has);
-    const int lane = threadIdx.x % kWave;
-    const int before = __popcll(ballot & ((1ull << lane) - 1ull));
-    int base = 0;
-    if (lane == 0 && ballot) base = atomicAdd(&active[0], (int)__popcll(ballot));
-    base = __shfl(base, 0);
-    if (has) active[1 + base + before] = b;
-}
-
-__global__ void k_zero_i32(int32_t *p) { *p = 0; }
-
 #ifndef SPH_BRICK_DEPTH
 #define SPH_BRICK_DEPTH 6
 #endif
@@ -388,7 +316,9 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     __syncthreads();
     // inner cells (x fastest: each inner row is one contiguous particle range)
     int icnt = 0, ist = 0;
-    if (tid < NI) {
+    // inner cells past the grid edge hold no centrals (on a periodic axis the
+    // staged copy would be the wrapped cell, owned by another brick)
+    if (tid < NI && cx0 + tid % BX < G.nx && cy0 + (tid / BX) % BY < G.ny && cz0 + tid / (BX * BY) < G.nz) {
         const int t = (tid % BX + 1) + SX * ((tid / BX) % BY + 1) + SX * SY * (tid / (BX * BY) + 1);
         icnt = cBase[t + 1] - cBase[t];
         ist = cBase[t] - cDelta[t];
@@ -577,7 +507,7 @@ void launch_brick(const sph_grid *grid, int n, const float4 *pos, const float4 *
     G.nby = (G.ny + kBrick - 1) / kBrick;
     G.nbz = (G.nz + kBrick - 1) / kBrick;
     const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
-    k_zero_i32<<<1, 1, 0, s>>>(active);
+    k_zero_one<int32_t><<<1, 1, 0, s>>>(active);
     k_active_bricks<kBrick, kBrick, kBrick><<<sph_blocks(blocks, 256), 256, 0, s>>>(cell_start, cell_end, G, active);
     k_forces_brick<VISC, kBrick, kBrick, kBrick, kBrickThreads, kBrickCap><<<blocks, kBrickThreads, 0, s>>>(
         n, pos, vel, aux, neibs, count, cell_start, cell_end, active, out, C, G);

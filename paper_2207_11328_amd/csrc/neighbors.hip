@@ -24,7 +24,7 @@ constexpr int kScanItems = 4;                       // per thread
 constexpr int kScanTile = kThreads * kScanItems;    // elements per block
 
 struct BuildLayout {
-    size_t cnt, cursor, start, partials, perm_a, perm_b, t_cell, t_pos, t_vel, t_info, total;
+    size_t cnt, cursor, start, partials, perm_a, perm_b, t_cell, t_pos, t_vel, t_info, active, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -45,6 +45,7 @@ BuildLayout build_layout(int64_t capacity, int64_t n_cells)
     L.t_pos = o;    o = align_up(o + sizeof(float4) * capacity);
     L.t_vel = o;    o = align_up(o + sizeof(float4) * capacity);
     L.t_info = o;   o = align_up(o + sizeof(uint32_t) * capacity);
+    L.active = o;   o = align_up(o + sizeof(int32_t) * (n_cells + 1));
     L.total = o;
     return L;
 }
@@ -355,6 +356,200 @@ __global__ __launch_bounds__(kThreads) void k_build_lists(
     if (total > max_neibs) atomicAdd(&status[SPH_STATUS_OVERFLOW], 1);
 }
 
+// Cell-brick list build (section "Changing perspective: from the particle to
+// the cell": a group of work-items per cell, neighbour data shared through
+// on-chip memory).  A workgroup owns a brick of BX x BY x BZ cells and stages
+// the offsets and type words of the particles of the brick and its one-cell
+// halo in LDS (16 bytes per particle); each lane then scans the 27 cells
+// around one central particle in the order k_build_lists uses (same cell
+// order, same predicate, same truncation), reading candidates from LDS, so
+// the lists are identical to k_build_lists'.  Lanes of the same cell read the
+// same candidate at the same time (an LDS broadcast).
+//
+// Particles inside a cell are sorted fluid first, so the boundary-boundary
+// exclusion is a shorter candidate range (the fluid prefix of the cell, from
+// a per-cell table) rather than a test per candidate, and the candidate loop
+// has no data-dependent branch: one predicated store per listed pair.  A
+// brick whose halo does not fit reads the candidates from global memory
+// instead (same loop).
+template <int BX, int BY, int BZ, bool LDS>
+__device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float4 &pi, bool central_boundary,
+                                               const int *cBase, const int *cDelta, const int *cFluidEnd,
+                                               const float4 *sPos, const float4 *__restrict__ gpos,
+                                               const uint32_t *__restrict__ ginfo, float csx, float csy, float csz,
+                                               float rs2, uint32_t *tile, int &total_found)
+{
+    constexpr int SX = BX + 2, SY = BY + 2;
+    int nf = 0, nb = 0, wf = 0, wb = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+        const float t2z = cell_shift(-dz, csz);
+        for (int dy = -1; dy <= 1; ++dy) {
+            const float t2y = cell_shift(-dy, csy);
+            for (int dx = -1; dx <= 1; ++dx) {
+                const float t2x = cell_shift(-dx, csx);
+                const int t = tc + dx + SX * (dy + SY * dz);
+                const int s0 = cBase[t];
+                const int s1 = central_boundary ? cFluidEnd[t] : cBase[t + 1];
+                const int delta = cDelta[t];
+                const uint32_t code = pack_neib(0u, -dx, -dy, -dz);
+                // two candidates in flight per lane (the LDS read latency)
+#pragma unroll 2
+                for (int sl = s0; sl < s1; ++sl) {
+                    const int j = sl - delta;
+                    float4 pj;
+                    uint32_t inf;
+                    if (LDS) {
+                        pj = sPos[sl];
+                        inf = __float_as_uint(pj.w);
+                    } else {
+                        pj = gpos[j];
+                        inf = ginfo[j];
+                    }
+                    const bool nb_boundary = ptype(inf) == kBoundary;
+                    const float r2 = predicate_r2(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, t2x, t2y, t2z);
+                    const bool hit = (r2 < rs2) & (j != i);
+                    const bool keep = hit & (wf + wb < M);
+                    const int slot = nb_boundary ? M - 1 - wb : wf;
+                    if (keep) tile[slot * kWave] = (uint32_t)j | code;
+                    const int kb = (int)(keep & nb_boundary), hb = (int)(hit & nb_boundary);
+                    wb += kb;
+                    wf += (int)keep - kb;
+                    nb += hb;
+                    nf += (int)hit - hb;
+                }
+            }
+        }
+    }
+    total_found = nf + nb;
+    return (uint32_t)wf | (uint32_t)wb << 16;
+}
+
+template <int BX, int BY, int BZ, int NT, int CAP>
+__global__ __launch_bounds__(NT) void k_build_brick(int n, int max_neibs, const float4 *__restrict__ pos,
+                                                    const uint32_t *__restrict__ info,
+                                                    const int32_t *__restrict__ start, BrickGrid G, float csx,
+                                                    float csy, float csz, float rs2,
+                                                    const int32_t *__restrict__ active,
+                                                    uint32_t *__restrict__ neibs,
+                                                    uint32_t *__restrict__ neib_count,
+                                                    int32_t *__restrict__ status)
+{
+    constexpr int SX = BX + 2, SY = BY + 2, SZ = BZ + 2;
+    constexpr int S = SX * SY * SZ;
+    constexpr int NI = BX * BY * BZ;
+    static_assert(S <= NT && NI <= NT, "one thread per cell");
+    __shared__ float4 sPos[CAP];  // xyz offset, w = type/id word
+    __shared__ int cBase[S + 1];
+    __shared__ int cDelta[S];
+    __shared__ int cFluidEnd[S];  // end of the fluid prefix of each staged cell (slot)
+    __shared__ int iBase[NI + 1];
+    __shared__ int iStart[NI];
+    __shared__ int wsum[NT / kWave];
+
+    const int tid = threadIdx.x;
+    if ((int)blockIdx.x >= active[0]) return;
+    const int b = active[1 + blockIdx.x];
+    const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
+
+    // 1. ranges of the staged cells and their LDS bases
+    int st = 0, cnt = 0;
+    if (tid < S) {
+        int gx = cx0 - 1 + tid % SX, gy = cy0 - 1 + (tid / SX) % SY, gz = cz0 - 1 + tid / (SX * SY);
+        const bool ok = wrap_axis(gx, G.nx, G.periodic & 1u) && wrap_axis(gy, G.ny, (G.periodic >> 1) & 1u) &&
+                        wrap_axis(gz, G.nz, (G.periodic >> 2) & 1u);
+        if (ok) {
+            const int lin = gx + G.nx * (gy + G.ny * gz);
+            st = start[lin];
+            cnt = start[lin + 1] - st;
+        }
+    }
+    int total;
+    const int ex = block_scan<NT>(cnt, total, wsum);
+    if (tid < S) {
+        cBase[tid] = ex;
+        cDelta[tid] = ex - st;
+        cFluidEnd[tid] = ex + cnt;  // lowered below where the cell holds boundary particles
+    }
+    if (tid == 0) cBase[S] = total;
+    __syncthreads();
+    int icnt = 0, ist = 0;
+    // inner cells past the grid edge hold no centrals (on a periodic axis the
+    // staged copy would be the wrapped cell, owned by another brick)
+    if (tid < NI && cx0 + tid % BX < G.nx && cy0 + (tid / BX) % BY < G.ny && cz0 + tid / (BX * BY) < G.nz) {
+        const int t = (tid % BX + 1) + SX * ((tid / BX) % BY + 1) + SX * SY * (tid / (BX * BY) + 1);
+        icnt = cBase[t + 1] - cBase[t];
+        ist = cBase[t] - cDelta[t];
+    }
+    int nc;
+    const int iex = block_scan<NT>(icnt, nc, wsum);
+    if (tid < NI) {
+        iBase[tid] = iex;
+        iStart[tid] = ist;
+    }
+    if (tid == 0) iBase[NI] = nc;
+    if (nc == 0) return;  // uniform: no particle in the brick
+    const bool use_lds = total <= CAP;
+
+    // 2. stage the brick and its halo (slot -> cell by binary search) and mark
+    //    the first boundary particle of each cell
+    for (int s2 = tid; s2 < total; s2 += NT) {
+        int lo = 0, hi = S - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (cBase[mid] <= s2) lo = mid;
+            else hi = mid - 1;
+        }
+        const int j = s2 - cDelta[lo];
+        const uint32_t inf = info[j];
+        if (use_lds) {
+            float4 p = pos[j];
+            p.w = __uint_as_float(inf);
+            sPos[s2] = p;
+        }
+        if (ptype(inf) == kBoundary && (s2 == cBase[lo] || ptype(info[j - 1]) != kBoundary)) cFluidEnd[lo] = s2;
+    }
+    __syncthreads();
+
+    // 3. one lane per central particle of the brick
+    for (int q0 = 0; q0 < nc; q0 += NT) {
+        const int q = q0 + tid;
+        if (q >= nc) break;
+        int lo = 0, hi = NI - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (iBase[mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        const int u = lo;
+        const int i = iStart[u] + (q - iBase[u]);
+        const int tc = (u % BX + 1) + SX * ((u / BX) % BY + 1) + SX * SY * (u / (BX * BY) + 1);
+        const float4 pi = pos[i];
+        const bool central_boundary = ptype(info[i]) == kBoundary;
+        uint32_t *tile = neibs + (size_t)(i / kWave) * kWave * max_neibs + (i % kWave);
+        int found;
+        const uint32_t cw =
+            use_lds ? brick_scan<BX, BY, BZ, true>(i, tc, max_neibs, pi, central_boundary, cBase, cDelta, cFluidEnd,
+                                                   sPos, pos, info, csx, csy, csz, rs2, tile, found)
+                    : brick_scan<BX, BY, BZ, false>(i, tc, max_neibs, pi, central_boundary, cBase, cDelta,
+                                                    cFluidEnd, sPos, pos, info, csx, csy, csz, rs2, tile, found);
+        neib_count[i] = cw;
+        atomicMax(&status[SPH_STATUS_MAX_NEIBS], found);
+        if (found > max_neibs) atomicAdd(&status[SPH_STATUS_OVERFLOW], 1);
+    }
+}
+
+// particles dropped by the build are in no brick: no neighbours
+__global__ __launch_bounds__(kThreads) void k_zero_dropped_counts(int n, const int32_t *__restrict__ cell,
+                                                                  uint32_t *__restrict__ neib_count)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n && cell[i] < 0) neib_count[i] = 0u;
+}
+
+constexpr int kBuildBrick = 3;
+constexpr int kBuildThreads = 640;
+constexpr int kBuildCap = 4800;  // 75 KB of LDS for the halo: two workgroups per CU
+
 bool grid_ok(const sph_grid *g, float r_search)
 {
     for (int d = 0; d < 3; ++d) {
@@ -445,9 +640,25 @@ extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params
                                                                t_cell, t_pos, t_vel, t_info, perm_out);
         SPH_CHECK_LAUNCH();
         const float rs2 = params->r_search * params->r_search;
-        k_build_lists<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(
-            n, max_neibs, t_cell, t_pos, t_info, start, dims, grid->cell_size[0], grid->cell_size[1],
-            grid->cell_size[2], grid->cell_base, rs2, neibs, neib_count, d_status);
+        BrickGrid G;
+        G.nx = dims.nx;
+        G.ny = dims.ny;
+        G.nz = dims.nz;
+        G.periodic = dims.periodic;
+        G.nbx = (G.nx + kBuildBrick - 1) / kBuildBrick;
+        G.nby = (G.ny + kBuildBrick - 1) / kBuildBrick;
+        G.nbz = (G.nz + kBuildBrick - 1) / kBuildBrick;
+        const unsigned bricks = (unsigned)G.nbx * G.nby * G.nbz;
+        int32_t *active = (int32_t *)(ws + L.active);
+        k_zero_one<int32_t><<<1, 1, 0, s>>>(active);
+        // brick activity from the (exclusive-scan) cell starts: start[c + 1] is the end of cell c
+        k_active_bricks<kBuildBrick, kBuildBrick, kBuildBrick><<<sph_blocks(bricks, 256), 256, 0, s>>>(
+            start, start + 1, G, active);
+        k_build_brick<kBuildBrick, kBuildBrick, kBuildBrick, kBuildThreads, kBuildCap>
+            <<<bricks, kBuildThreads, 0, s>>>(n, max_neibs, t_pos, t_info, start, G, grid->cell_size[0],
+                                              grid->cell_size[1], grid->cell_size[2], rs2, active, neibs,
+                                              neib_count, d_status);
+        k_zero_dropped_counts<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, t_cell, neib_count);
         k_copy_state<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, t_cell, t_pos, t_vel, t_info, parts->cell,
                                                                    pos, vel, parts->info);
         SPH_CHECK_LAUNCH();

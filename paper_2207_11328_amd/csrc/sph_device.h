@@ -76,6 +76,88 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+// ---------------------------------------------------------------------------
+// Cell bricks: blocks of cells processed by one workgroup with the particles
+// of the brick and of its one-cell halo staged in LDS (used by the list build
+// and by the derivative kernel).
+struct BrickGrid {
+    int nx, ny, nz;
+    uint32_t periodic;
+    int nbx, nby, nbz;
+};
+
+__device__ __forceinline__ bool wrap_axis(int &c, int n, uint32_t periodic)
+{
+    if (periodic) {
+        if (c < 0) c += n;
+        if (c >= n) c -= n;
+        return true;
+    }
+    return c >= 0 && c < n;
+}
+
+// exclusive scan of one int per thread over a block of NT threads
+template <int NT>
+__device__ __forceinline__ int block_scan(int v, int &total, int *wsum)
+{
+    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int t = __shfl_up(inc, o);
+        if (lane >= o) inc += t;
+    }
+    if (lane == kWave - 1) wsum[w] = inc;
+    __syncthreads();
+    int off = 0;
+    total = 0;
+#pragma unroll
+    for (int k = 0; k < NT / kWave; ++k) {
+        off += k < w ? wsum[k] : 0;
+        total += wsum[k];
+    }
+    __syncthreads();
+    return off + inc - v;
+}
+
+// List the bricks that hold at least one particle (order is irrelevant: each
+// brick writes only its own particles).  active[0] must be zero on entry.
+template <int BX, int BY, int BZ>
+__global__ __launch_bounds__(256) void k_active_bricks(const int32_t *__restrict__ cell_start,
+                                                       const int32_t *__restrict__ cell_end, BrickGrid G,
+                                                       int32_t *__restrict__ active)
+{
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    const int nb = G.nbx * G.nby * G.nbz;
+    int cnt = 0;
+    if (b < nb) {
+        const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
+        const int cx1 = min(cx0 + BX, G.nx) - 1;
+        for (int z = cz0; z < min(cz0 + BZ, G.nz); ++z)
+            for (int y = cy0; y < min(cy0 + BY, G.ny); ++y) {
+                const int row = G.nx * (y + G.ny * z);
+                cnt += cell_end[row + cx1] - cell_start[row + cx0];
+            }
+    }
+    const bool has = cnt > 0;
+    // wave-aggregated append
+    const unsigned long long ballot = __ballot(has);
+    const int lane = threadIdx.x % kWave;
+    const int before = __popcll(ballot & ((1ull << lane) - 1ull));
+    int base = 0;
+    if (lane == 0 && ballot) base = atomicAdd(&active[0], (int)__popcll(ballot));
+    base = __shfl(base, 0);
+    if (has) active[1 + base + before] = b;
+}
+
+
+// A counter zeroed by a kernel (graph-capturable, no memset node).
+template <typename T>
+__global__ void k_zero_one(T *p)
+{
+    *p = T(0);
+}
+
 }  // namespace sph
 
 // Host-side launch helpers.
