@@ -284,94 +284,23 @@ __global__ void k_status(int n, int n_cells, const int32_t *__restrict__ start, 
     status[SPH_STATUS_DROPPED] = n - n_active;
 }
 
-// Per-particle neighbour list: one lane per central particle scans the 27
-// cells of its Moore neighbourhood (z, y, x from -1 to +1) in sorted order.
-// Inside a cell fluid particles precede boundary ones, so a boundary centre
-// stops at the first boundary neighbour of each cell.
-__global__ __launch_bounds__(kThreads) void k_build_lists(
-    int n, int max_neibs, const int32_t *__restrict__ cell, const float4 *__restrict__ pos,
-    const uint32_t *__restrict__ info, const int32_t *__restrict__ start, CellDims dims, float csx,
-    float csy, float csz, int cell_base, float rs2, uint32_t *__restrict__ neibs,
-    uint32_t *__restrict__ neib_count, int32_t *__restrict__ status)
-{
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
-    const int ci = cell[i];
-    if (ci < 0) {
-        neib_count[i] = 0u;
-        return;
-    }
-    int cx, cy, cz;
-    cell_coords(ci - cell_base, dims, cx, cy, cz);
-    const float4 pi = pos[i];
-    const bool central_boundary = ptype(info[i]) == kBoundary;
-    uint32_t *tile = neibs + (size_t)(i / kWave) * kWave * max_neibs + (i % kWave);
-    int nf = 0, nb = 0, wf = 0, wb = 0;
-    for (int dz = -1; dz <= 1; ++dz) {
-        int jz = cz + dz;
-        if ((dims.periodic >> 2) & 1u) jz = jz < 0 ? jz + dims.nz : (jz >= dims.nz ? jz - dims.nz : jz);
-        else if (jz < 0 || jz >= dims.nz) continue;
-        const float t2z = cell_shift(-dz, csz);
-        for (int dy = -1; dy <= 1; ++dy) {
-            int jy = cy + dy;
-            if ((dims.periodic >> 1) & 1u) jy = jy < 0 ? jy + dims.ny : (jy >= dims.ny ? jy - dims.ny : jy);
-            else if (jy < 0 || jy >= dims.ny) continue;
-            const float t2y = cell_shift(-dy, csy);
-            for (int dx = -1; dx <= 1; ++dx) {
-                int jx = cx + dx;
-                if (dims.periodic & 1u) jx = jx < 0 ? jx + dims.nx : (jx >= dims.nx ? jx - dims.nx : jx);
-                else if (jx < 0 || jx >= dims.nx) continue;
-                const float t2x = cell_shift(-dx, csx);
-                const int lc = jx + dims.nx * (jy + dims.ny * jz);
-                const int s = start[lc];
-                const int e = start[lc + 1];
-                for (int j = s; j < e; ++j) {
-                    if (j == i) continue;
-                    const bool nb_boundary = ptype(info[j]) == kBoundary;
-                    if (central_boundary && nb_boundary) break;
-                    const float4 pj = pos[j];
-                    const float r2 = predicate_r2(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, t2x, t2y, t2z);
-                    if (!(r2 < rs2)) continue;
-                    const uint32_t entry = pack_neib((uint32_t)j, -dx, -dy, -dz);
-                    if (nb_boundary) {
-                        if (wf + wb < max_neibs) {
-                            tile[(max_neibs - 1 - wb) * kWave] = entry;
-                            ++wb;
-                        }
-                        ++nb;
-                    } else {
-                        if (wf + wb < max_neibs) {
-                            tile[wf * kWave] = entry;
-                            ++wf;
-                        }
-                        ++nf;
-                    }
-                }
-            }
-        }
-    }
-    neib_count[i] = (uint32_t)wf | (uint32_t)wb << 16;
-    const int total = nf + nb;
-    atomicMax(&status[SPH_STATUS_MAX_NEIBS], total);
-    if (total > max_neibs) atomicAdd(&status[SPH_STATUS_OVERFLOW], 1);
-}
-
-// Cell-brick list build (section "Changing perspective: from the particle to
-// the cell": a group of work-items per cell, neighbour data shared through
-// on-chip memory).  A workgroup owns a brick of BX x BY x BZ cells and stages
-// the offsets and type words of the particles of the brick and its one-cell
-// halo in LDS (16 bytes per particle); each lane then scans the 27 cells
-// around one central particle in the order k_build_lists uses (same cell
-// order, same predicate, same truncation), reading candidates from LDS, so
-// the lists are identical to k_build_lists'.  Lanes of the same cell read the
-// same candidate at the same time (an LDS broadcast).
+// Neighbour lists, cell-brick form (section "Changing perspective: from the
+// particle to the cell": a group of work-items per cell, neighbour data shared
+// through on-chip memory).  A workgroup owns a brick of BX x BY x BZ cells and
+// stages the offsets and type words of the particles of the brick and its
+// one-cell halo in LDS (16 bytes per particle).  Each lane then takes one
+// central particle and scans the 27 cells of its Moore neighbourhood (z, y, x
+// from -1 to +1), each cell in sorted order, reading candidates from LDS;
+// lanes of the same cell read the same candidate at the same time (an LDS
+// broadcast).  Fluid entries fill the list from the front and boundary
+// entries from the back, in scan order, until M entries are written.
 //
-// Particles inside a cell are sorted fluid first, so the boundary-boundary
-// exclusion is a shorter candidate range (the fluid prefix of the cell, from
-// a per-cell table) rather than a test per candidate, and the candidate loop
-// has no data-dependent branch: one predicated store per listed pair.  A
-// brick whose halo does not fit reads the candidates from global memory
-// instead (same loop).
+// Inside a cell fluid particles precede boundary ones, so the exclusion of
+// boundary-boundary pairs is a shorter candidate range for a boundary centre
+// (the fluid prefix of each cell, from a per-cell table) rather than a test per
+// candidate, and the candidate loop has no data-dependent branch: one
+// predicated store per listed pair.  A brick whose halo does not fit in LDS
+// runs the same loop on global memory.
 template <int BX, int BY, int BZ, bool LDS>
 __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float4 &pi, bool central_boundary,
                                                const int *cBase, const int *cDelta, const int *cFluidEnd,
