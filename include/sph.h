@@ -146,6 +146,11 @@ int32_t sph_abi_version(void);
  * ceil(capacity / 64) * 64 * max_neibs. */
 size_t sph_neib_list_entries(int32_t capacity, int32_t max_neibs);
 
+/* Cells per brick along x, y, z of the brick-local lists (shape[3], host
+ * memory).  Bricks tile the grid from cell 0 along each axis; a workgroup of
+ * the list build and of sph_forces owns one brick. */
+void sph_brick_shape(int32_t *shape);
+
 /* Bytes of device workspace sph_build_neighbors needs. */
 size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells);
 
@@ -166,7 +171,16 @@ size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells);
  *   6. if perm_out (device uint32[capacity]) is not NULL, perm_out[k] is the
  *      index before the call of the particle now stored at k (k < n); the
  *      adjoint of the rebuild is dL/dy_before[perm_out[k]] = dL/dy_after[k]
- *      (sph_unpermute), since re-binning does not move a particle.
+ *      (sph_unpermute), since re-binning does not move a particle;
+ *   7. if neibs_brick (device uint16[sph_neib_list_entries(capacity,
+ *      max_neibs)]) is not NULL, the same lists in brick-local form for
+ *      sph_forces: same tiling as neibs, slot k of particle i (k < nf + nb,
+ *      neighbours in scan order, fluid and boundary interleaved as found)
+ *      holds the neighbour's position in the staging order of the brick
+ *      (sph_brick_shape) that holds i; staging order: the cells of the brick
+ *      and its one-cell halo, x fastest, periodic axes wrapped, cells outside
+ *      a closed axis empty, then particles of a cell in sorted order;
+ *      saturated at 65535.
  * A particle whose neighbours exceed max_neibs keeps the first max_neibs
  * found (scan order: cells z, y, x outer to inner, then sorted index) and is
  * counted in SPH_STATUS_OVERFLOW; the lists are then unusable for physics.
@@ -176,8 +190,8 @@ size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells);
 sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
                                sph_particles *parts, uint32_t *neibs, uint32_t *neib_count,
                                int32_t max_neibs, int32_t *cell_start, int32_t *cell_end,
-                               int32_t *d_status, uint32_t *perm_out, void *workspace,
-                               size_t workspace_bytes, void *stream);
+                               int32_t *d_status, uint32_t *perm_out, uint16_t *neibs_brick,
+                               void *workspace, size_t workspace_bytes, void *stream);
 
 /* Time derivatives (eq. mass-cont-sph1 and eq. ns-sph1 with the readings of
  * the design notes; Wendland kernel of listing l:ktemplate).  For every
@@ -189,11 +203,16 @@ sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
  * forces: device float[capacity][4], xyz = a_i [m/s^2], w = Drho_i/Dt,
  * fully overwritten for i < n.  Particles are read in the order of the last
  * build; positions may have drifted since (lists are reused).
- * cell_start / cell_end: the cell ranges written by that build (device
- * int32[n_cells] each), or both NULL.  With them the derivatives are computed
- * brick by brick of cells, the particles of a brick and of its one-cell halo
- * staged in LDS; without them one lane per particle gathers its neighbours
- * from global memory.  Both give the same result bit for bit.
+ * cell_start / cell_end / neibs_brick: the cell ranges and brick-local
+ * lists written by that build (device int32[n_cells] each and
+ * uint16[sph_neib_list_entries(capacity, max_neibs)]), or all NULL.  With
+ * them the derivatives are computed brick by brick of cells, the particles of
+ * a brick and of its one-cell halo staged in LDS with positions relative to
+ * the brick's centre cell; without them one lane per particle gathers its
+ * neighbours from global memory with the separation of the list predicate.
+ * The two differ by rounding only (the separation of the brick form carries
+ * an error of a few ulp of 2.5 cell sizes instead of one ulp of a cell size);
+ * neither is bit-exact against the other.
  * workspace: device buffer of sph_forces_workspace_bytes(capacity, n_cells)
  * bytes (per-particle equation-of-state terms and the list of bricks that
  * hold particles, both recomputed by every call).
@@ -201,7 +220,8 @@ sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
 sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
                       const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
                       const int32_t *cell_start, const int32_t *cell_end,
-                      float *forces, void *workspace, size_t workspace_bytes, void *stream);
+                      const uint16_t *neibs_brick, float *forces, void *workspace,
+                      size_t workspace_bytes, void *stream);
 
 /* Bytes of device workspace sph_forces needs (n_cells: cells of the grid). */
 size_t sph_forces_workspace_bytes(int32_t capacity, int32_t n_cells);

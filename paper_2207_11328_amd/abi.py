@@ -24,7 +24,7 @@ MAX_CAPACITY = 1 << NEIB_INDEX_BITS
 
 EXPORTS = [
     "sph_status_string", "sph_abi_version", "sph_neib_list_entries", "sph_build_workspace_bytes",
-    "sph_build_neighbors", "sph_forces", "sph_forces_workspace_bytes", "sph_integrate",
+    "sph_brick_shape", "sph_build_neighbors", "sph_forces", "sph_forces_workspace_bytes", "sph_integrate",
     "sph_dt_workspace_bytes", "sph_step_dt", "sph_count_interactions", "sph_integrate_backward",
     "sph_forces_backward_workspace_bytes", "sph_forces_backward", "sph_unpermute",
     "sph_diagnostics_workspace_bytes", "sph_reduce_diagnostics",
@@ -68,9 +68,11 @@ def _load():
     L.sph_forces_workspace_bytes.restype = C.c_size_t
     L.sph_build_workspace_bytes.argtypes = [i32, i32]
     L.sph_build_workspace_bytes.restype = C.c_size_t
-    L.sph_build_neighbors.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, C.c_size_t, P]
+    L.sph_brick_shape.argtypes = [P]
+    L.sph_brick_shape.restype = None
+    L.sph_build_neighbors.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, P, C.c_size_t, P]
     L.sph_build_neighbors.restype = st
-    L.sph_forces.argtypes = [P, P, P, P, P, i32, P, P, P, P, C.c_size_t, P]
+    L.sph_forces.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, C.c_size_t, P]
     L.sph_forces.restype = st
     L.sph_integrate.argtypes = [P, i32, P, P, P, P, P, P, P]
     L.sph_integrate.restype = st
@@ -165,19 +167,27 @@ def sph_dt_workspace_bytes() -> int:
     return int(lib.sph_dt_workspace_bytes())
 
 
+def sph_brick_shape():
+    shape = (C.c_int32 * 3)()
+    lib.sph_brick_shape(shape)
+    return tuple(int(v) for v in shape)
+
+
 def sph_build_neighbors(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count,
-                        max_neibs: int, cell_start, cell_end, d_status, workspace, stream=None, perm_out=None):
+                        max_neibs: int, cell_start, cell_end, d_status, workspace, stream=None, perm_out=None,
+                        neibs_brick=None):
     check(lib.sph_build_neighbors(C.byref(grid), C.byref(params), C.byref(parts), ptr(neibs), ptr(neib_count),
                                   int(max_neibs), ptr(cell_start), ptr(cell_end), ptr(d_status), ptr(perm_out),
-                                  ptr(workspace), workspace.numel() * workspace.element_size(),
+                                  ptr(neibs_brick), ptr(workspace), workspace.numel() * workspace.element_size(),
                                   stream_ptr(stream)), "sph_build_neighbors")
 
 
 def sph_forces(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count, max_neibs: int,
-               forces, workspace, stream=None, cell_start=None, cell_end=None):
+               forces, workspace, stream=None, cell_start=None, cell_end=None, neibs_brick=None):
     check(lib.sph_forces(C.byref(grid), C.byref(params), C.byref(parts), ptr(neibs), ptr(neib_count),
-                         int(max_neibs), ptr(cell_start), ptr(cell_end), ptr(forces), ptr(workspace),
-                         workspace.numel() * workspace.element_size(), stream_ptr(stream)), "sph_forces")
+                         int(max_neibs), ptr(cell_start), ptr(cell_end), ptr(neibs_brick), ptr(forces),
+                         ptr(workspace), workspace.numel() * workspace.element_size(), stream_ptr(stream)),
+          "sph_forces")
 
 
 def sph_integrate(params: SphParams, stage: int, d_dt, state_n: SphParticles, vel_star, forces,

@@ -95,14 +95,10 @@ struct PairAcc {
 // One pair (i, j) of the derivative sums, branch-free; contributes only when
 // `valid` (slot inside i's list) and r < 2h.
 template <int VISC>
-__device__ __forceinline__ void pair_terms(PairAcc &A, uint32_t e, const float4 &pi, const float4 &vi,
-                                           const float2 &ai, const float4 &pj, const float4 &vj, const float2 &aj,
-                                           bool valid, const ForceConst &C)
+__device__ __forceinline__ void pair_core(PairAcc &A, float xx, float xy, float xz, const float4 &vi,
+                                          const float2 &ai, const float4 &pj, const float4 &vj, const float2 &aj,
+                                          bool valid, const ForceConst &C)
 {
-    // separation, bit-identical to the list predicate: x = k cs + (o_i - o_j)
-    const float xx = fmaf(entry_k(e, 0), C.csx, pi.x - pj.x);
-    const float xy = fmaf(entry_k(e, 1), C.csy, pi.y - pj.y);
-    const float xz = fmaf(entry_k(e, 2), C.csz, pi.z - pj.z);
     float r2;
     {
 #pragma clang fp contract(off)
@@ -133,50 +129,38 @@ __device__ __forceinline__ void pair_terms(PairAcc &A, uint32_t e, const float4 
 }
 
 template <int VISC>
-__global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__restrict__ pos,
-                                                     const float4 *__restrict__ vel,
-                                                     const float2 *__restrict__ aux,
-                                                     const uint32_t *__restrict__ neibs,
-                                                     const uint32_t *__restrict__ count,
-                                                     float4 *__restrict__ out, ForceConst C)
+__device__ __forceinline__ void pair_terms(PairAcc &A, uint32_t e, const float4 &pi, const float4 &vi,
+                                           const float2 &ai, const float4 &pj, const float4 &vj, const float2 &aj,
+                                           bool valid, const ForceConst &C)
 {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    const int lane = threadIdx.x % kWave;
-    const int ii = min(i, n - 1);  // lanes past the end load in bounds and store nothing
-    const int M = C.max_neibs;
-    const uint32_t cnt = i < n ? count[i] : 0u;
-    // counts and indices are clamped: a stale or foreign list gives wrong
-    // numbers but never an out-of-bounds access
-    const int nf = min((int)(cnt & 0xFFFFu), M);
-    const int nt = min(nf + (int)(cnt >> 16), M);
+    // separation, bit-identical to the list predicate: x = k cs + (o_i - o_j)
+    const float xx = fmaf(entry_k(e, 0), C.csx, pi.x - pj.x);
+    const float xy = fmaf(entry_k(e, 1), C.csy, pi.y - pj.y);
+    const float xz = fmaf(entry_k(e, 2), C.csz, pi.z - pj.z);
+    pair_core<VISC>(A, xx, xy, xz, vi, ai, pj, vj, aj, valid, C);
+}
+
+// Pairs of one lane's list gathered from global memory, in list order.
+// Software pipeline over a ring of kDepth pair slots, unrolled by kDepth:
+// slot s holds the neighbour data of pair k + s (requested kDepth pairs
+// before it is used) and the list entry of pair k + s + kDepth (requested
+// 2 kDepth pairs ahead).  Neighbour data registers are only ever written by
+// loads, so the loop carries no copy of an in-flight value.
+template <int VISC>
+__device__ __forceinline__ void gather_pairs(PairAcc &A, const uint32_t *tile, int nf, int nt, int ntw, int M,
+                                             uint32_t jmax, const float4 *__restrict__ pos,
+                                             const float4 *__restrict__ vel, const float2 *__restrict__ aux,
+                                             const float4 &pi, const float4 &vi, const float2 &ai,
+                                             const ForceConst &C)
+{
     const int last = max(nt - 1, 0);
-    const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
-    if (ntw == 0) {
-        if (i < n) out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        return;
-    }
-    // a wave is exactly one 64-particle tile of the list (wave-uniform base)
-    const int tile_id = __builtin_amdgcn_readfirstlane(i / kWave);
-    const uint32_t *tile = neibs + (size_t)tile_id * (kWave * M);
-    const uint32_t jmax = (uint32_t)(n - 1);
-
-    const float4 pi = pos[ii];
-    const float4 vi = vel[ii];
-    const float2 ai = aux[ii];
-    PairAcc A = {0.0f, 0.0f, 0.0f, 0.0f};
-
-    // Software pipeline over a ring of kDepth pair slots, unrolled by kDepth:
-    // slot s holds the neighbour data of pair k + s (requested kDepth pairs
-    // before it is used) and the list entry of pair k + s + kDepth (requested
-    // 2 kDepth pairs ahead).  Neighbour data registers are only ever written
-    // by loads, so the loop carries no copy of an in-flight value.
     uint32_t e[kDepth], en[kDepth];
     float4 P[kDepth], V[kDepth];
     float2 X[kDepth];
 #pragma unroll
     for (int s = 0; s < kDepth; ++s) {
-        e[s] = tile[list_slot(s, nf, last, M) * kWave + lane];
-        en[s] = tile[list_slot(s + kDepth, nf, last, M) * kWave + lane];
+        e[s] = tile[list_slot(s, nf, last, M) * kWave];
+        en[s] = tile[list_slot(s + kDepth, nf, last, M) * kWave];
     }
 #pragma unroll
     for (int s = 0; s < kDepth; ++s) {
@@ -194,98 +178,132 @@ __global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__rest
             P[s] = pos[j];
             V[s] = vel[j];
             X[s] = aux[j];
-            en[s] = tile[list_slot(k + s + 2 * kDepth, nf, last, M) * kWave + lane];
+            en[s] = tile[list_slot(k + s + 2 * kDepth, nf, last, M) * kWave];
         }
     }
+}
+
+template <int VISC>
+__global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__restrict__ pos,
+                                                     const float4 *__restrict__ vel,
+                                                     const float2 *__restrict__ aux,
+                                                     const uint32_t *__restrict__ neibs,
+                                                     const uint32_t *__restrict__ count,
+                                                     float4 *__restrict__ out, ForceConst C)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    const int lane = threadIdx.x % kWave;
+    const int ii = min(i, n - 1);  // lanes past the end load in bounds and store nothing
+    const int M = C.max_neibs;
+    const uint32_t cnt = i < n ? count[i] : 0u;
+    // counts and indices are clamped: a stale or foreign list gives wrong
+    // numbers but never an out-of-bounds access
+    const int nf = min((int)(cnt & 0xFFFFu), M);
+    const int nt = min(nf + (int)(cnt >> 16), M);
+    const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
+    if (ntw == 0) {
+        if (i < n) out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        return;
+    }
+    // a wave is exactly one 64-particle tile of the list (wave-uniform base)
+    const int tile_id = __builtin_amdgcn_readfirstlane(i / kWave);
+    const uint32_t *tile = neibs + (size_t)tile_id * (kWave * M);
+    const uint32_t jmax = (uint32_t)(n - 1);
+
+    const float4 pi = pos[ii];
+    const float4 vi = vel[ii];
+    const float2 ai = aux[ii];
+    PairAcc A = {0.0f, 0.0f, 0.0f, 0.0f};
+
+    gather_pairs<VISC>(A, tile + lane, nf, nt, ntw, M, jmax, pos, vel, aux, pi, vi, ai, C);
     if (i < n) out[i] = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 // ---------------------------------------------------------------------------
-// Cell-brick variant of the derivative kernel.  A workgroup owns a brick of
-// BX x BY x BZ cells; it first copies the particles of the brick and of its
-// one-cell halo (every possible neighbour of its particles) from HBM/L2 into
-// LDS with coalesced loads, one contiguous cell range after another, then
-// each lane walks the list of one central particle of the brick exactly as
-// k_forces does, but reads the neighbour data from LDS.  This is the
-// cell-centred perspective the paper applies to the list construction,
-// applied to the derivatives: the 64 lanes of a wave read neighbours that are
-// scattered over dozens of cache lines, which the global-gather kernel pays
-// in L1/L2 request throughput.  The arithmetic and its order are those of
-// k_forces, so the result is bit for bit the same.  A brick whose halo does
-// not fit the LDS capacity falls back to global reads (same loop).
+// Cell-brick variant of the derivative kernel (the cell perspective of section
+// "Changing perspective: from the particle to the cell" applied to the
+// derivatives).  A workgroup owns a brick of cells; it first copies
+// the particles of the brick and of its one-cell halo (every possible
+// neighbour of its particles) from HBM/L2 into LDS with coalesced loads, one
+// contiguous cell range after another, then each lane walks the list of one
+// central particle of the brick and reads the neighbour data from LDS.  The
+// 64 lanes of a wave read neighbours scattered over dozens of cache lines,
+// which the global-gather kernel pays in L1/L2 request throughput.
+//
+// The lists are the brick-local ones of the build: entry k is the
+// neighbour's LDS slot itself (uint16, fluid then boundary contiguous), so a
+// pair costs no index decoding.  Staged positions are relative to the centre
+// cell of the brick, o + s cs with s in {-2, ..., 2} per axis, so the
+// separation is one subtraction: its rounding error is a few ulp of 2.5 cs,
+// not of cs (the list predicate, which must be exact, is not evaluated here;
+// the r < 2h mask only differs from the exact one where the kernel weight is
+// of order 1e-20).  A brick whose halo does not fit in LDS reads the global
+// lists and the global state with the arithmetic of k_forces.
 #ifndef SPH_BRICK_DEPTH
 #define SPH_BRICK_DEPTH 6
 #endif
 constexpr int kBrickDepth = SPH_BRICK_DEPTH;
 
-template <int VISC, int NT, bool LDS>
-__device__ __forceinline__ void brick_pairs(PairAcc &A, const uint32_t *tile, int lane_in_tile, int nf, int nt,
-                                            int ntw, int M, uint32_t jmax, int total, int dbase,
-                                            const int *__restrict__ dtab, const float4 *__restrict__ sP,
-                                            const float4 *__restrict__ sV, const float2 *__restrict__ sA,
-                                            const float4 *__restrict__ pos, const float4 *__restrict__ vel,
-                                            const float2 *__restrict__ aux, const float4 &pi, const float4 &vi,
-                                            const float2 &ai, const ForceConst &C)
+template <int VISC, int NT>
+__device__ __forceinline__ void brick_pairs_lds(PairAcc &A, const uint16_t *ltile, int nt, int ntw, int total,
+                                                const float4 *__restrict__ sP, const float4 *__restrict__ sV,
+                                                const float2 *__restrict__ sA, const float4 &pi, const float4 &vi,
+                                                const float2 &ai, const ForceConst &C)
 {
     const int last = max(nt - 1, 0);
+    const uint32_t smax = (uint32_t)(total - 1);
     uint32_t e[kBrickDepth], en[kBrickDepth];
     float4 P[kBrickDepth], V[kBrickDepth];
     float2 X[kBrickDepth];
-    auto fetch = [&](uint32_t ee, float4 &p, float4 &v, float2 &x) {
-        const uint32_t j = min(ee & kIndexMask, jmax);
-        if (LDS) {
-            int slot = (int)j + dtab[dbase + (int)(ee >> 26)];
-            slot = min(max(slot, 0), total - 1);
-            p = sP[slot];
-            v = sV[slot];
-            x = sA[slot];
-        } else {
-            p = pos[j];
-            v = vel[j];
-            x = aux[j];
-        }
+    auto fetch = [&](uint32_t slot, float4 &p, float4 &v, float2 &x) {
+        const uint32_t sl = min(slot, smax);  // a stale list stays inside the staged range
+        p = sP[sl];
+        v = sV[sl];
+        x = sA[sl];
     };
 #pragma unroll
     for (int s = 0; s < kBrickDepth; ++s) {
-        e[s] = tile[list_slot(s, nf, last, M) * kWave + lane_in_tile];
-        en[s] = tile[list_slot(s + kBrickDepth, nf, last, M) * kWave + lane_in_tile];
+        e[s] = ltile[min(s, last) * kWave];
+        en[s] = ltile[min(s + kBrickDepth, last) * kWave];
     }
 #pragma unroll
     for (int s = 0; s < kBrickDepth; ++s) fetch(e[s], P[s], V[s], X[s]);
     for (int k = 0; k < ntw; k += kBrickDepth) {
 #pragma unroll
         for (int s = 0; s < kBrickDepth; ++s) {
-            pair_terms<VISC>(A, e[s], pi, vi, ai, P[s], V[s], X[s], k + s < nt, C);
+            pair_core<VISC>(A, pi.x - P[s].x, pi.y - P[s].y, pi.z - P[s].z, vi, ai, P[s], V[s], X[s], k + s < nt,
+                            C);
             e[s] = en[s];
             fetch(e[s], P[s], V[s], X[s]);
-            en[s] = tile[list_slot(k + s + 2 * kBrickDepth, nf, last, M) * kWave + lane_in_tile];
+            en[s] = ltile[min(k + s + 2 * kBrickDepth, last) * kWave];
         }
     }
 }
 
-template <int VISC, int BX, int BY, int BZ, int NT, int CAP>
+template <int VISC, int NT, int CAP>
 __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__restrict__ pos,
                                                      const float4 *__restrict__ vel,
                                                      const float2 *__restrict__ aux,
                                                      const uint32_t *__restrict__ neibs,
+                                                     const uint16_t *__restrict__ neibs_brick,
                                                      const uint32_t *__restrict__ count,
                                                      const int32_t *__restrict__ cell_start,
                                                      const int32_t *__restrict__ cell_end,
                                                      const int32_t *__restrict__ active,
                                                      float4 *__restrict__ out, ForceConst C, BrickGrid G)
 {
+    constexpr int BX = kBrickX, BY = kBrickY, BZ = kBrickZ;
     constexpr int SX = BX + 2, SY = BY + 2, SZ = BZ + 2;
     constexpr int S = SX * SY * SZ;  // staged cells
     constexpr int NI = BX * BY * BZ; // inner cells
     static_assert(S <= NT && NI <= NT, "one thread per cell");
-    __shared__ float4 sP[CAP];
+    __shared__ float4 sP[CAP];  // brick-relative offset, mass
     __shared__ float4 sV[CAP];
     __shared__ float2 sA[CAP];
     __shared__ int cBase[S + 1];
     __shared__ int cDelta[S];
     __shared__ int iBase[NI + 1];
     __shared__ int iStart[NI];
-    __shared__ int dtab[NI * 64];  // [inner cell][entry code] -> LDS slot - particle index
     __shared__ int wsum[NT / kWave];
 
     const int tid = threadIdx.x;
@@ -294,7 +312,8 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     const int b = active[1 + blockIdx.x];
     const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
 
-    // 1. ranges of the staged cells and their LDS bases
+    // 1. ranges of the staged cells and their LDS bases (the staging order of
+    //    the list build)
     int st = 0, cnt = 0;
     if (tid < S) {
         int gx = cx0 - 1 + tid % SX, gy = cy0 - 1 + (tid / SX) % SY, gz = cz0 - 1 + tid / (SX * SY);
@@ -333,29 +352,29 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     if (nc == 0) return;  // uniform: no particle in the brick
     const bool use_lds = total <= CAP;
     if (use_lds) {
-        // slot offsets per (inner cell, entry code): the neighbour of a particle
-        // of inner cell u with cell difference k lives in staged cell t(u) - k
-        for (int q = tid; q < NI * 64; q += NT) {
-            const int u = q / 64, code = q % 64;
-            const int kx = (int32_t)((uint32_t)code << 30) >> 30;
-            const int ky = (int32_t)((uint32_t)code << 28) >> 30;
-            const int kz = (int32_t)((uint32_t)code << 26) >> 30;
-            const int sx = u % BX + 1 - kx, sy = (u / BX) % BY + 1 - ky, sz = u / (BX * BY) + 1 - kz;
-            const bool valid = kx >= -1 && kx <= 1 && ky >= -1 && ky <= 1 && kz >= -1 && kz <= 1;
-            dtab[q] = valid ? cDelta[sx + SX * (sy + SY * sz)] : 0;
-        }
-        // 2. stage the brick and its halo (slot -> cell by binary search)
-        for (int s2 = tid; s2 < total; s2 += NT) {
-            int lo = 0, hi = S - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (cBase[mid] <= s2) lo = mid;
-                else hi = mid - 1;
+        // 2. stage the brick and its halo: one wave per row of SX staged
+        //    cells (x-consecutive, so one contiguous LDS range and, away from
+        //    a periodic seam, one contiguous global range), lanes over the
+        //    row's particles
+        const int wave = tid / kWave, lane = tid % kWave;
+        for (int r = wave; r < SY * SZ; r += NT / kWave) {
+            const int t0 = r * SX;
+            const int b0 = cBase[t0], b1 = cBase[t0 + SX];
+            int e[SX - 1];
+#pragma unroll
+            for (int c = 0; c < SX - 1; ++c) e[c] = cBase[t0 + 1 + c];
+            const float sy = (float)(r % SY - 2), sz = (float)(r / SY - 2);
+            for (int s2 = b0 + lane; s2 < b1; s2 += kWave) {
+                int c = 0;
+#pragma unroll
+                for (int k = 0; k < SX - 1; ++k) c += s2 >= e[k] ? 1 : 0;
+                const int j = s2 - cDelta[t0 + c];
+                const float4 p = pos[j];
+                const float sx = (float)(c - 2);
+                sP[s2] = make_float4(fmaf(sx, C.csx, p.x), fmaf(sy, C.csy, p.y), fmaf(sz, C.csz, p.z), p.w);
+                sV[s2] = vel[j];
+                sA[s2] = aux[j];
             }
-            const int j = s2 - cDelta[lo];
-            sP[s2] = pos[j];
-            sV[s2] = vel[j];
-            sA[s2] = aux[j];
         }
     }
     __syncthreads();
@@ -384,15 +403,15 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
         const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
         PairAcc A = {0.0f, 0.0f, 0.0f, 0.0f};
         if (ntw > 0) {
-            const uint32_t *tile = neibs + (size_t)(i / kWave) * (kWave * M);
-            const float4 pi = pos[i], vi = vel[i];
-            const float2 ai = aux[i];
-            if (use_lds)
-                brick_pairs<VISC, NT, true>(A, tile, i % kWave, nf, nt, ntw, M, jmax, total, u * 64, dtab, sP, sV, sA,
-                                            pos, vel, aux, pi, vi, ai, C);
-            else
-                brick_pairs<VISC, NT, false>(A, tile, i % kWave, nf, nt, ntw, M, jmax, total, u * 64, dtab, sP, sV,
-                                             sA, pos, vel, aux, pi, vi, ai, C);
+            const size_t toff = (size_t)(i / kWave) * (kWave * M) + (i % kWave);
+            if (use_lds) {
+                const int tc = (u % BX + 1) + SX * ((u / BX) % BY + 1) + SX * SY * (u / (BX * BY) + 1);
+                const int si = i + cDelta[tc];
+                brick_pairs_lds<VISC, NT>(A, neibs_brick + toff, nt, ntw, total, sP, sV, sA, sP[si], sV[si], sA[si],
+                                          C);
+            } else {
+                gather_pairs<VISC>(A, neibs + toff, nf, nt, ntw, M, jmax, pos, vel, aux, pos[i], vel[i], aux[i], C);
+            }
         }
         if (act) out[i] = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
@@ -481,42 +500,44 @@ extern "C" size_t sph_forces_workspace_bytes(int32_t capacity, int32_t n_cells)
     return aux_bytes(capacity > 0 ? capacity : 1) + sizeof(int32_t) * ((size_t)n_cells + 1) + 256;
 }
 
-// brick shape of the LDS kernel: 3 x 3 x 3 cells (about 620 particles at the
-// h = 1.3 dp, r_s = 2.86 dp lattice density, 10 waves), halo of 5^3 cells
-// (about 2900 particles, 3700 fit in 148 KB of the 160 KB of LDS)
-#ifndef SPH_BRICK
-#define SPH_BRICK 3
-#define SPH_BRICK_THREADS 640
-#define SPH_BRICK_CAP 3700
+// LDS kernel: bricks of 3 x 4 x 3 cells (up to about 970 particles at the
+// h = 1.3 dp, r_s = 2.86 dp lattice density, 16 waves), halo of 5 x 6 x 5
+// cells (up to about 3800 particles; 4000 fit in 160 KB of LDS at 40 bytes
+// each).  Measured on the 1.62M dam break: 3 x 4 x 3 277 us, 3 x 3 x 3
+// 357 us, 4 x 3 x 3 425 us (1% of its bricks overflow the LDS there).
+#ifndef SPH_BRICK_CAP
+#define SPH_BRICK_THREADS 1024
+#define SPH_BRICK_CAP 4000
 #endif
-constexpr int kBrick = SPH_BRICK;
 constexpr int kBrickThreads = SPH_BRICK_THREADS;
 constexpr int kBrickCap = SPH_BRICK_CAP;
 
 template <int VISC>
 void launch_brick(const sph_grid *grid, int n, const float4 *pos, const float4 *vel, const float2 *aux,
-                  const uint32_t *neibs, const uint32_t *count, const int32_t *cell_start, const int32_t *cell_end,
-                  int32_t *active, float4 *out, const ForceConst &C, hipStream_t s)
+                  const uint32_t *neibs, const uint16_t *neibs_brick, const uint32_t *count,
+                  const int32_t *cell_start, const int32_t *cell_end, int32_t *active, float4 *out,
+                  const ForceConst &C, hipStream_t s)
 {
     BrickGrid G;
     G.nx = grid->ncell[0];
     G.ny = grid->ncell[1];
     G.nz = grid->ncell[2];
     G.periodic = grid->periodic;
-    G.nbx = (G.nx + kBrick - 1) / kBrick;
-    G.nby = (G.ny + kBrick - 1) / kBrick;
-    G.nbz = (G.nz + kBrick - 1) / kBrick;
+    G.nbx = (G.nx + kBrickX - 1) / kBrickX;
+    G.nby = (G.ny + kBrickY - 1) / kBrickY;
+    G.nbz = (G.nz + kBrickZ - 1) / kBrickZ;
     const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
     k_zero_one<int32_t><<<1, 1, 0, s>>>(active);
-    k_active_bricks<kBrick, kBrick, kBrick><<<sph_blocks(blocks, 256), 256, 0, s>>>(cell_start, cell_end, G, active);
-    k_forces_brick<VISC, kBrick, kBrick, kBrick, kBrickThreads, kBrickCap><<<blocks, kBrickThreads, 0, s>>>(
-        n, pos, vel, aux, neibs, count, cell_start, cell_end, active, out, C, G);
+    k_active_bricks<kBrickX, kBrickY, kBrickZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(cell_start, cell_end, G, active);
+    k_forces_brick<VISC, kBrickThreads, kBrickCap><<<blocks, kBrickThreads, 0, s>>>(
+        n, pos, vel, aux, neibs, neibs_brick, count, cell_start, cell_end, active, out, C, G);
 }
 
 extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
                                  const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
                                  const int32_t *cell_start, const int32_t *cell_end,
-                                 float *forces, void *workspace, size_t workspace_bytes, void *stream)
+                                 const uint16_t *neibs_brick, float *forces, void *workspace,
+                                 size_t workspace_bytes, void *stream)
 {
     if (!common_args(grid, params, parts, neibs, neib_count, max_neibs)) return SPH_ERR_ARG;
     if (parts->n > 0 && !forces) return SPH_ERR_ARG;
@@ -537,14 +558,16 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
     if (grid->cell_alpha && !parts->cell) return SPH_ERR_ARG;
     k_eos<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, vel, aux, parts->cell, grid->cell_alpha, grid->cell_base,
                                                        params->h, C);
-    if (cell_start && cell_end) {
-        // cell ranges of the last build: LDS cell-brick kernel (it writes the
-        // derivatives of every particle that lies in a cell; particles dropped
-        // by the build have none)
+    if (cell_start && cell_end && neibs_brick) {
+        // cell ranges and brick-local lists of the last build: LDS cell-brick
+        // kernel (it writes the derivatives of every particle that lies in a
+        // cell; particles dropped by the build have none)
         if (params->visc_model == 0)
-            launch_brick<0>(grid, n, pos, vel, aux, neibs, neib_count, cell_start, cell_end, active, out, C, s);
+            launch_brick<0>(grid, n, pos, vel, aux, neibs, neibs_brick, neib_count, cell_start, cell_end, active,
+                            out, C, s);
         else
-            launch_brick<1>(grid, n, pos, vel, aux, neibs, neib_count, cell_start, cell_end, active, out, C, s);
+            launch_brick<1>(grid, n, pos, vel, aux, neibs, neibs_brick, neib_count, cell_start, cell_end, active,
+                            out, C, s);
         SPH_CHECK_LAUNCH();
         // dropped particles (cell < 0) are in no cell: zero their derivatives
         k_zero_dropped<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, parts->cell, out);

@@ -301,12 +301,18 @@ __global__ void k_status(int n, int n_cells, const int32_t *__restrict__ start, 
 // candidate, and the candidate loop has no data-dependent branch: one
 // predicated store per listed pair.  A brick whose halo does not fit in LDS
 // runs the same loop on global memory.
+//
+// Optionally the same lists are also written in brick-local form for the
+// derivative kernels: entry k is the neighbour's slot in the staging order of
+// the central particle's brick (cells of the 5x5x5 halo in x-fastest order,
+// particles of a cell in sorted order), uint16, in scan order with fluid and
+// boundary neighbours interleaved as found (slots 0 .. nf + nb - 1).
 template <int BX, int BY, int BZ, bool LDS>
 __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float4 &pi, bool central_boundary,
                                                const int *cBase, const int *cDelta, const int *cFluidEnd,
                                                const float4 *sPos, const float4 *__restrict__ gpos,
                                                const uint32_t *__restrict__ ginfo, float csx, float csy, float csz,
-                                               float rs2, uint32_t *tile, int &total_found)
+                                               float rs2, uint32_t *tile, uint16_t *ltile, int &total_found)
 {
     constexpr int SX = BX + 2, SY = BY + 2;
     int nf = 0, nb = 0, wf = 0, wb = 0;
@@ -339,7 +345,10 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
                     const bool hit = (r2 < rs2) & (j != i);
                     const bool keep = hit & (wf + wb < M);
                     const int slot = nb_boundary ? M - 1 - wb : wf;
-                    if (keep) tile[slot * kWave] = (uint32_t)j | code;
+                    if (keep) {
+                        tile[slot * kWave] = (uint32_t)j | code;
+                        if (ltile) ltile[(wf + wb) * kWave] = (uint16_t)min(sl, 0xFFFF);
+                    }
                     const int kb = (int)(keep & nb_boundary), hb = (int)(hit & nb_boundary);
                     wb += kb;
                     wf += (int)keep - kb;
@@ -360,6 +369,7 @@ __global__ __launch_bounds__(NT) void k_build_brick(int n, int max_neibs, const 
                                                     float csy, float csz, float rs2,
                                                     const int32_t *__restrict__ active,
                                                     uint32_t *__restrict__ neibs,
+                                                    uint16_t *__restrict__ neibs_brick,
                                                     uint32_t *__restrict__ neib_count,
                                                     int32_t *__restrict__ status)
 {
@@ -454,13 +464,16 @@ __global__ __launch_bounds__(NT) void k_build_brick(int n, int max_neibs, const 
         const int tc = (u % BX + 1) + SX * ((u / BX) % BY + 1) + SX * SY * (u / (BX * BY) + 1);
         const float4 pi = pos[i];
         const bool central_boundary = ptype(info[i]) == kBoundary;
-        uint32_t *tile = neibs + (size_t)(i / kWave) * kWave * max_neibs + (i % kWave);
+        const size_t toff = (size_t)(i / kWave) * kWave * max_neibs + (i % kWave);
+        uint32_t *tile = neibs + toff;
+        uint16_t *ltile = neibs_brick ? neibs_brick + toff : nullptr;
         int found;
         const uint32_t cw =
             use_lds ? brick_scan<BX, BY, BZ, true>(i, tc, max_neibs, pi, central_boundary, cBase, cDelta, cFluidEnd,
-                                                   sPos, pos, info, csx, csy, csz, rs2, tile, found)
+                                                   sPos, pos, info, csx, csy, csz, rs2, tile, ltile, found)
                     : brick_scan<BX, BY, BZ, false>(i, tc, max_neibs, pi, central_boundary, cBase, cDelta,
-                                                    cFluidEnd, sPos, pos, info, csx, csy, csz, rs2, tile, found);
+                                                    cFluidEnd, sPos, pos, info, csx, csy, csz, rs2, tile, ltile,
+                                                    found);
         neib_count[i] = cw;
         atomicMax(&status[SPH_STATUS_MAX_NEIBS], found);
         if (found > max_neibs) atomicAdd(&status[SPH_STATUS_OVERFLOW], 1);
@@ -475,8 +488,10 @@ __global__ __launch_bounds__(kThreads) void k_zero_dropped_counts(int n, const i
     if (i < n && cell[i] < 0) neib_count[i] = 0u;
 }
 
-constexpr int kBuildBrick = 3;
-constexpr int kBuildThreads = 640;
+#ifndef SPH_BUILD_THREADS
+#define SPH_BUILD_THREADS 1024
+#endif
+constexpr int kBuildThreads = SPH_BUILD_THREADS;
 constexpr int kBuildCap = 4800;  // 75 KB of LDS for the halo: two workgroups per CU
 
 bool grid_ok(const sph_grid *g, float r_search)
@@ -505,11 +520,19 @@ extern "C" size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells)
     return build_layout(capacity, n_cells).total;
 }
 
+extern "C" void sph_brick_shape(int32_t *shape)
+{
+    if (!shape) return;
+    shape[0] = kBrickX;
+    shape[1] = kBrickY;
+    shape[2] = kBrickZ;
+}
+
 extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
                                           sph_particles *parts, uint32_t *neibs, uint32_t *neib_count,
                                           int32_t max_neibs, int32_t *cell_start, int32_t *cell_end,
-                                          int32_t *d_status, uint32_t *perm_out, void *workspace,
-                                          size_t workspace_bytes, void *stream)
+                                          int32_t *d_status, uint32_t *perm_out, uint16_t *neibs_brick,
+                                          void *workspace, size_t workspace_bytes, void *stream)
 {
     if (!grid || !params || !parts || !neibs || !neib_count || !cell_start || !cell_end || !d_status)
         return SPH_ERR_ARG;
@@ -574,19 +597,19 @@ extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params
         G.ny = dims.ny;
         G.nz = dims.nz;
         G.periodic = dims.periodic;
-        G.nbx = (G.nx + kBuildBrick - 1) / kBuildBrick;
-        G.nby = (G.ny + kBuildBrick - 1) / kBuildBrick;
-        G.nbz = (G.nz + kBuildBrick - 1) / kBuildBrick;
+        G.nbx = (G.nx + kBrickX - 1) / kBrickX;
+        G.nby = (G.ny + kBrickY - 1) / kBrickY;
+        G.nbz = (G.nz + kBrickZ - 1) / kBrickZ;
         const unsigned bricks = (unsigned)G.nbx * G.nby * G.nbz;
         int32_t *active = (int32_t *)(ws + L.active);
         k_zero_one<int32_t><<<1, 1, 0, s>>>(active);
         // brick activity from the (exclusive-scan) cell starts: start[c + 1] is the end of cell c
-        k_active_bricks<kBuildBrick, kBuildBrick, kBuildBrick><<<sph_blocks(bricks, 256), 256, 0, s>>>(
+        k_active_bricks<kBrickX, kBrickY, kBrickZ><<<sph_blocks(bricks, 256), 256, 0, s>>>(
             start, start + 1, G, active);
-        k_build_brick<kBuildBrick, kBuildBrick, kBuildBrick, kBuildThreads, kBuildCap>
+        k_build_brick<kBrickX, kBrickY, kBrickZ, kBuildThreads, kBuildCap>
             <<<bricks, kBuildThreads, 0, s>>>(n, max_neibs, t_pos, t_info, start, G, grid->cell_size[0],
                                               grid->cell_size[1], grid->cell_size[2], rs2, active, neibs,
-                                              neib_count, d_status);
+                                              neibs_brick, neib_count, d_status);
         k_zero_dropped_counts<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, t_cell, neib_count);
         k_copy_state<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, t_cell, t_pos, t_vel, t_info, parts->cell,
                                                                    pos, vel, parts->info);

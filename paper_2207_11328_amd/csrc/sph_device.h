@@ -80,6 +80,17 @@ __device__ __forceinline__ T wave_sum(T v)
 // Cell bricks: blocks of cells processed by one workgroup with the particles
 // of the brick and of its one-cell halo staged in LDS (used by the list build
 // and by the derivative kernel).
+// Bricks of kBrickX x kBrickY x kBrickZ cells: the unit of LDS staging of the
+// list build and of the derivative kernels.  The brick-local lists written by
+// the build index the staging order of the same bricks, so both sides use
+// this shape (reported by sph_brick_shape).
+#ifndef SPH_BRICK_X
+#define SPH_BRICK_X 3
+#define SPH_BRICK_Y 4
+#define SPH_BRICK_Z 3
+#endif
+constexpr int kBrickX = SPH_BRICK_X, kBrickY = SPH_BRICK_Y, kBrickZ = SPH_BRICK_Z;
+
 struct BrickGrid {
     int nx, ny, nz;
     uint32_t periodic;

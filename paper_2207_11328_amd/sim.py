@@ -56,6 +56,7 @@ class Simulation:
         self.forces_n = z((cap, 4), torch.float32)
         self.forces_star = z((cap, 4), torch.float32)
         self.neibs = z(abi.sph_neib_list_entries(cap, self.max_neibs), torch.int32)
+        self.neibs_brick = z(abi.sph_neib_list_entries(cap, self.max_neibs), torch.int16)
         self.neib_count = z(cap, torch.int32)
         self.cell_start = z(max(self.n_cells, 1), torch.int32)
         self.cell_end = z(max(self.n_cells, 1), torch.int32)
@@ -87,7 +88,8 @@ class Simulation:
     # ------------------------------------------------------------ primitives
     def build(self, stream=None, perm_out=None):
         abi.sph_build_neighbors(self.g, self.p, self.parts, self.neibs, self.neib_count, self.max_neibs,
-                                self.cell_start, self.cell_end, self.status, self.ws_build, stream, perm_out)
+                                self.cell_start, self.cell_end, self.status, self.ws_build, stream, perm_out,
+                                self.neibs_brick)
 
     def set_params(self, **kw):
         """Change scalar parameters (e.g. alpha, c0) between calls."""
@@ -96,13 +98,14 @@ class Simulation:
 
     def forces(self, star: bool = False, stream=None, bricks: bool = True):
         """Derivatives of the state n (or *).  bricks: the LDS cell-brick
-        kernel (uses the cell ranges of the last build); False: the
-        per-particle global-gather kernel.  Same result bit for bit."""
+        kernel (uses the cell ranges and brick-local lists of the last
+        build); False: the per-particle global-gather kernel.  The two agree
+        to rounding."""
         parts = self.parts_star if star else self.parts
         out = self.forces_star if star else self.forces_n
-        cs, ce = (self.cell_start, self.cell_end) if bricks else (None, None)
+        cs, ce, nb = (self.cell_start, self.cell_end, self.neibs_brick) if bricks else (None, None, None)
         abi.sph_forces(self.g, self.p, parts, self.neibs, self.neib_count, self.max_neibs, out, self.ws_forces,
-                       stream, cs, ce)
+                       stream, cs, ce, nb)
         return out
 
     def step_dt(self, stream=None):

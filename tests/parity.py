@@ -192,3 +192,83 @@ def check_forces(gpu_f, acc, drho, s_acc, s_drho, tol=FORCE_TOL, label=""):
 
 def torch_sync():
     torch.cuda.synchronize()
+
+
+def expected_brick_lists(sim, grid, brick=None):
+    """Brick-local lists implied by the GPU's own j-lists and cell ranges,
+    from the layout the header documents: entry k of particle i is the
+    neighbour's position in the staging order of i's brick (the
+    (BX+2)(BY+2)(BZ+2) cells of the brick and its halo, x fastest, periodic axes wrapped, cells
+    past a closed axis empty; particles of a cell in sorted order), entries
+    in scan order (neighbour cells z, y, x from -1 to +1, then sorted index),
+    fluid and boundary interleaved.  Returns
+    ([n, M] int64 with -1 past each list, n_total [n])."""
+    if brick is None:
+        from paper_2207_11328_amd import abi
+        brick = abi.sph_brick_shape()
+    BX, BY, BZ = brick
+    n, M = sim.n, sim.max_neibs
+    nb, cnt = sim.lists_host()
+    E = nb[:, :n].T.astype(np.int64)
+    cnt = cnt.astype(np.int64)
+    nf, nbd = cnt & 0xFFFF, cnt >> 16
+    cell = sim.cell[:n].cpu().numpy().astype(np.int64) - int(grid.cell_base)
+    cs_ = sim.cell_start[: grid.n_cells].cpu().numpy().astype(np.int64)
+    ce_ = sim.cell_end[: grid.n_cells].cpu().numpy().astype(np.int64)
+    nx, ny, nz = (int(v) for v in grid.ncell)
+    per = [(int(grid.periodic) >> d) & 1 for d in range(3)]
+    SX, SY, SZ = BX + 2, BY + 2, BZ + 2
+    out = np.full((n, M), -1, np.int64)
+    bases = {}
+
+    def staging(bx, by, bz):
+        key = (bx, by, bz)
+        if key not in bases:
+            st = np.zeros(SX * SY * SZ, np.int64)
+            ct = np.zeros(SX * SY * SZ, np.int64)
+            for t in range(SX * SY * SZ):
+                g = [bx * BX - 1 + t % SX, by * BY - 1 + (t // SX) % SY, bz * BZ - 1 + t // (SX * SY)]
+                ok = True
+                for d, nd in enumerate((nx, ny, nz)):
+                    if per[d]:
+                        g[d] %= nd
+                    elif not 0 <= g[d] < nd:
+                        ok = False
+                if ok:
+                    lin = g[0] + nx * (g[1] + ny * g[2])
+                    st[t], ct[t] = cs_[lin], ce_[lin] - cs_[lin]
+            base = np.concatenate([[0], np.cumsum(ct)[:-1]])
+            bases[key] = (base - st, int(ct.sum()))
+        return bases[key]
+
+    totals = np.zeros(n, np.int64)
+    for i in range(n):
+        c = cell[i]
+        if c < 0:
+            continue
+        cx, cy, cz = c % nx, (c // nx) % ny, c // (nx * ny)
+        delta, tot = staging(cx // BX, cy // BY, cz // BZ)
+        totals[i] = tot
+        tc = (cx % BX + 1) + SX * ((cy % BY + 1) + SY * (cz % BZ + 1))
+        order = list(range(nf[i])) + [M - 1 - b for b in range(nbd[i])]
+        e = E[i, order]
+        j = e & ((1 << 26) - 1)
+        k = [((e >> (26 + 2 * d)) & 3) for d in range(3)]
+        k = [np.where(v >= 2, v - 4, v) for v in k]
+        # scan order: neighbour cell offset d = -k, z outermost, then index
+        o = np.lexsort((j, -k[0], -k[1], -k[2]))
+        j, k = j[o], [v[o] for v in k]
+        t = tc - k[0] - SX * (k[1] + SY * k[2])
+        out[i, : len(order)] = np.minimum(j + delta[t], 0xFFFF)
+    return out, totals
+
+
+def gpu_brick_lists(sim):
+    """GPU brick-local lists as [n, M] int64 (tile layout undone), -1 past
+    each list."""
+    n, M = sim.n, sim.max_neibs
+    t = sim.neibs_brick.view(-1, M, 64).cpu().numpy().view(np.uint16)  # [tile, slot, lane]
+    L = t.transpose(0, 2, 1).reshape(-1, M)[:n].astype(np.int64)
+    cnt = sim.neib_count[:n].cpu().numpy().view(np.uint32).astype(np.int64)
+    tot = (cnt & 0xFFFF) + (cnt >> 16)
+    return np.where(np.arange(M)[None, :] < tot[:, None], L, -1)

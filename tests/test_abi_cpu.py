@@ -70,16 +70,21 @@ def test_host_only_entry_points(abi):
     assert abi.sph_dt_workspace_bytes() > 0
 
 
+def test_brick_shape(abi):
+    shape = abi.sph_brick_shape()
+    assert len(shape) == 3 and all(1 <= v <= 8 for v in shape), shape
+
+
 def test_argument_errors_return_before_any_launch(abi):
     """Null or inconsistent arguments are rejected synchronously."""
     g = abi.SphGrid()
     p = abi.SphParams()
     parts = abi.SphParticles(10, 5, None, None, None, None)  # n > capacity
     assert abi.lib.sph_forces(C.byref(g), C.byref(p), C.byref(parts), None, None, 128, None, None, None, None,
-                              0, None) == abi.SPH_ERR_ARG
-    assert abi.lib.sph_forces(None, None, None, None, None, 128, None, None, None, None, 0,
+                              None, 0, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_forces(None, None, None, None, None, 128, None, None, None, None, None, 0,
                               None) == abi.SPH_ERR_ARG
-    assert abi.lib.sph_build_neighbors(None, None, None, None, None, 128, None, None, None, None, None, 0,
+    assert abi.lib.sph_build_neighbors(None, None, None, None, None, 128, None, None, None, None, None, None, 0,
                                        None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_forces_backward(None, None, None, None, None, 128, None, None, None, None, 0, None, 0,
                                        None) == abi.SPH_ERR_ARG

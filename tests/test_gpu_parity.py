@@ -9,8 +9,8 @@ import pytest
 from oracle import oracle as O
 from workloads import scenes as S
 
-from parity import (FORCE_TOL, U32, check_forces, compare_build, log, make_sim, oracle_forces_of,
-                    torch_sync)
+from parity import (FORCE_TOL, U32, check_forces, compare_build, expected_brick_lists, gpu_brick_lists, log,
+                    make_sim, oracle_forces_of, torch_sync)
 
 pytestmark = pytest.mark.gpu
 
@@ -59,6 +59,10 @@ def test_build_and_forces_parity(name):
     torch_sync()
     ob = compare_build(sc, sim, max_neibs=_slots(name))
     assert ob["lists"].overflow == 0
+    if sc.n <= 20000:
+        # brick-local lists: bit-exact against the documented layout
+        exp, tot = expected_brick_lists(sim, sc.grid)
+        assert np.array_equal(gpu_brick_lists(sim), exp), "brick-local lists"
     st, (acc, drho, sa, sd, ni) = oracle_forces_of(sc, ob)
     gf = sim.forces_n[: sc.n].cpu().numpy()
     check_forces(gf, acc, drho, sa, sd, label=name)
@@ -261,17 +265,22 @@ def test_fp64_diagnostics():
 
 @pytest.mark.parametrize("name", ["still_water", "cloud_periodic_xyz", "channel_small", "dam_break_64k",
                                   "dense_overflow"])
-def test_brick_kernel_equals_gather_kernel(name):
-    """The LDS cell-brick derivative kernel and the per-particle global-gather
-    kernel give the same derivatives bit for bit (same arithmetic, same
-    order), including bricks whose halo overflows the LDS capacity and fall
-    back to global reads (the dense case: three times the lattice density)."""
+def test_brick_kernel_matches_gather_kernel(name):
+    """The LDS cell-brick derivative kernel (brick-local lists, separations
+    from brick-relative positions) and the per-particle global-gather kernel
+    (separations as in the list predicate) both meet the oracle tolerance and
+    differ from each other by rounding only.  Bricks whose halo overflows the
+    LDS capacity read the global lists with the gather kernel's arithmetic, so
+    there the two agree bit for bit (the dense case: 3 times the lattice
+    density, at least 5,200 particles in every brick with its halo, beyond the
+    LDS capacity of both the list build and the derivative kernel)."""
     if name == "dense_overflow":
-        sc = S.random_cloud(n=13000, box=(0.4, 0.4, 0.4), dp=0.02, seed=21, boundary_frac=0.2, u_sigma=0.2)
-        M = 256
+        sc = S.random_cloud(n=24000, box=(0.4, 0.4, 0.4), dp=0.02, seed=21, boundary_frac=0.2, u_sigma=0.2)
+        M = 416
     else:
         sc = SCENES[name]()
         M = _slots(name)
+    log("case %s brick vs gather: n=%d" % (name, sc.n))
     sim = make_sim(sc, max_neibs=M)
     sim.build()
     a = sim.forces(bricks=True).clone()
@@ -279,8 +288,17 @@ def test_brick_kernel_equals_gather_kernel(name):
     b = sim.forces(bricks=False).clone()
     torch_sync()
     assert sim.status_host()["overflow"] == 0
-    assert torch.equal(a[: sc.n], b[: sc.n]), name
     if name == "dense_overflow":
-        ob = compare_build(sc, sim, max_neibs=M)
-        st, (acc, drho, sa, sd, ni) = oracle_forces_of(sc, ob)
-        check_forces(a[: sc.n].cpu().numpy(), acc, drho, sa, sd, label="dense (LDS overflow)")
+        _, totals = expected_brick_lists(sim, sc.grid)
+        assert totals.min() > 5000, totals.min()
+        assert torch.equal(a[: sc.n], b[: sc.n]), name
+    ob = compare_build(sc, sim, max_neibs=M)
+    st, (acc, drho, sa, sd, ni) = oracle_forces_of(sc, ob)
+    ea = check_forces(a[: sc.n].cpu().numpy(), acc, drho, sa, sd, label=name + " brick")
+    eb = check_forces(b[: sc.n].cpu().numpy(), acc, drho, sa, sd, label=name + " gather")
+    # mutual difference, on the oracle's scale
+    d = (a[: sc.n] - b[: sc.n]).abs().double().cpu().numpy()
+    scale = np.concatenate([sa, sd[:, None]], 1)
+    rel = np.where(scale > 0, d / np.where(scale > 0, scale, 1.0), d)
+    log("%s brick - gather: max |d|/S = %.3e" % (name, float(rel.max(initial=0.0))))
+    assert float(rel.max(initial=0.0)) <= FORCE_TOL, name

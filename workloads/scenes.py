@@ -374,6 +374,9 @@ CONFIGS = {
 }
 
 
+BRICK_CELLS = 3
+
+
 def stack_scenes(scenes, gap_cells: int = 2):
     """Lay independent scenes out in one grid, stacked along z, so that one
     neighbour search and one set of launches covers all of them.
@@ -384,7 +387,8 @@ def stack_scenes(scenes, gap_cells: int = 2):
     corner, placed at an integer number of cells, so its cell-relative
     encoding is identical to the one it has alone on its own sub-grid
     (returned as `sub_grids`).  `gap_cells` empty cell layers separate
-    consecutive scenes, so no pair of particles of different scenes is ever
+    consecutive scenes (more where needed to start each scene at a multiple
+    of BRICK_CELLS cells), so no pair of particles of different scenes is ever
     listed.  Returns (combined Scene, per-cell alpha float32[n_cells],
     sub_grids, per-scene (first particle, count) in the combined input)."""
     rs = float(np.float32(scenes[0].params.r_search))
@@ -400,12 +404,15 @@ def stack_scenes(scenes, gap_cells: int = 2):
         ext.append(np.ceil(L / csd - 1e-9).astype(np.int64))
     nx = int(max(e[0] for e in ext))
     ny = int(max(e[1] for e in ext))
+    # scene origins at multiples of the 3-cell brick of the LDS kernels, so a
+    # scene's cells take the same place in their bricks stacked or alone
     z0 = []
     z = 0
     for e in ext:
         z0.append(z)
         z += int(e[2]) + gap_cells
-    nz = z - gap_cells
+        z = -(-z // BRICK_CELLS) * BRICK_CELLS
+    nz = z0[-1] + int(ext[-1][2])
     grid = Grid(origin=np.zeros(3), cell_size=np.full(3, cs, np.float32),
                 ncell=np.array([nx, ny, nz], np.int32), periodic=0, cell_base=0)
     xs, types, rho, vel, mass = [], [], [], [], []
