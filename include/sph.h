@@ -146,6 +146,10 @@ int32_t sph_abi_version(void);
  * ceil(capacity / 64) * 64 * max_neibs. */
 size_t sph_neib_list_entries(int32_t capacity, int32_t max_neibs);
 
+/* Entries (uint16) of a brick-local neighbour list for `capacity`
+ * particles: ceil(capacity / 64) * 64 * 8 * ceil(max_neibs / 8). */
+size_t sph_neib_brick_entries(int32_t capacity, int32_t max_neibs);
+
 /* Cells per brick along x, y, z of the brick-local lists (shape[3], host
  * memory).  Bricks tile the grid from cell 0 along each axis; a workgroup of
  * the list build and of sph_forces owns one brick. */
@@ -172,11 +176,14 @@ size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells);
  *      index before the call of the particle now stored at k (k < n); the
  *      adjoint of the rebuild is dL/dy_before[perm_out[k]] = dL/dy_after[k]
  *      (sph_unpermute), since re-binning does not move a particle;
- *   7. if neibs_brick (device uint16[sph_neib_list_entries(capacity,
+ *   7. if neibs_brick (device uint16[sph_neib_brick_entries(capacity,
  *      max_neibs)]) is not NULL, the same lists in brick-local form for
- *      sph_forces: same tiling as neibs, slot k of particle i (k < nf + nb,
- *      neighbours in scan order, fluid and boundary interleaved as found)
- *      holds the neighbour's position in the staging order of the brick
+ *      sph_forces: entry k of particle i (k < nf + nb, neighbours in scan
+ *      order, fluid and boundary interleaved as found) is stored at
+ *        ((i / 64) * G + k / 8) * 512 + (i % 64) * 8 + k % 8,
+ *      G = ceil(max_neibs / 8) (groups of 8 entries, one 16-byte load per
+ *      particle and group), and holds the neighbour's position in the staging
+ *      order of the brick
  *      (sph_brick_shape) that holds i; staging order: the cells of the brick
  *      and its one-cell halo, x fastest, periodic axes wrapped, cells outside
  *      a closed axis empty, then particles of a cell in sorted order;
@@ -205,7 +212,7 @@ sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
  * build; positions may have drifted since (lists are reused).
  * cell_start / cell_end / neibs_brick: the cell ranges and brick-local
  * lists written by that build (device int32[n_cells] each and
- * uint16[sph_neib_list_entries(capacity, max_neibs)]), or all NULL.  With
+ * uint16[sph_neib_brick_entries(capacity, max_neibs)]), or all NULL.  With
  * them the derivatives are computed brick by brick of cells, the particles of
  * a brick and of its one-cell halo staged in LDS with positions relative to
  * the brick's centre cell; without them one lane per particle gathers its

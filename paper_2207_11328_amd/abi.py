@@ -24,7 +24,7 @@ MAX_CAPACITY = 1 << NEIB_INDEX_BITS
 
 EXPORTS = [
     "sph_status_string", "sph_abi_version", "sph_neib_list_entries", "sph_build_workspace_bytes",
-    "sph_brick_shape", "sph_build_neighbors", "sph_forces", "sph_forces_workspace_bytes", "sph_integrate",
+    "sph_brick_shape", "sph_neib_brick_entries", "sph_build_neighbors", "sph_forces", "sph_forces_workspace_bytes", "sph_integrate",
     "sph_dt_workspace_bytes", "sph_step_dt", "sph_count_interactions", "sph_integrate_backward",
     "sph_forces_backward_workspace_bytes", "sph_forces_backward", "sph_unpermute",
     "sph_diagnostics_workspace_bytes", "sph_reduce_diagnostics",
@@ -68,6 +68,8 @@ def _load():
     L.sph_forces_workspace_bytes.restype = C.c_size_t
     L.sph_build_workspace_bytes.argtypes = [i32, i32]
     L.sph_build_workspace_bytes.restype = C.c_size_t
+    L.sph_neib_brick_entries.argtypes = [i32, i32]
+    L.sph_neib_brick_entries.restype = C.c_size_t
     L.sph_brick_shape.argtypes = [P]
     L.sph_brick_shape.restype = None
     L.sph_build_neighbors.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, P, C.c_size_t, P]
@@ -165,6 +167,10 @@ def sph_forces_workspace_bytes(capacity: int, n_cells: int) -> int:
 
 def sph_dt_workspace_bytes() -> int:
     return int(lib.sph_dt_workspace_bytes())
+
+
+def sph_neib_brick_entries(capacity: int, max_neibs: int) -> int:
+    return int(lib.sph_neib_brick_entries(int(capacity), int(max_neibs)))
 
 
 def sph_brick_shape():

@@ -141,12 +141,12 @@ __device__ __forceinline__ void pair_terms(PairAcc &A, uint32_t e, const float4 
 }
 
 // Pairs of one lane's list gathered from global memory, in list order.
-// Software pipeline over a ring of kDepth pair slots, unrolled by kDepth:
-// slot s holds the neighbour data of pair k + s (requested kDepth pairs
-// before it is used) and the list entry of pair k + s + kDepth (requested
-// 2 kDepth pairs ahead).  Neighbour data registers are only ever written by
-// loads, so the loop carries no copy of an in-flight value.
-template <int VISC>
+// Software pipeline over a ring of D pair slots, unrolled by D: slot s holds
+// the neighbour data of pair k + s (requested D pairs before it is used) and
+// the list entry of pair k + s + D (requested 2 D pairs ahead).  Neighbour
+// data registers are only ever written by loads, so the loop carries no copy
+// of an in-flight value.
+template <int VISC, int D>
 __device__ __forceinline__ void gather_pairs(PairAcc &A, const uint32_t *tile, int nf, int nt, int ntw, int M,
                                              uint32_t jmax, const float4 *__restrict__ pos,
                                              const float4 *__restrict__ vel, const float2 *__restrict__ aux,
@@ -154,31 +154,31 @@ __device__ __forceinline__ void gather_pairs(PairAcc &A, const uint32_t *tile, i
                                              const ForceConst &C)
 {
     const int last = max(nt - 1, 0);
-    uint32_t e[kDepth], en[kDepth];
-    float4 P[kDepth], V[kDepth];
-    float2 X[kDepth];
+    uint32_t e[D], en[D];
+    float4 P[D], V[D];
+    float2 X[D];
 #pragma unroll
-    for (int s = 0; s < kDepth; ++s) {
+    for (int s = 0; s < D; ++s) {
         e[s] = tile[list_slot(s, nf, last, M) * kWave];
-        en[s] = tile[list_slot(s + kDepth, nf, last, M) * kWave];
+        en[s] = tile[list_slot(s + D, nf, last, M) * kWave];
     }
 #pragma unroll
-    for (int s = 0; s < kDepth; ++s) {
+    for (int s = 0; s < D; ++s) {
         const uint32_t j = min(e[s] & kIndexMask, jmax);
         P[s] = pos[j];
         V[s] = vel[j];
         X[s] = aux[j];
     }
-    for (int k = 0; k < ntw; k += kDepth) {
+    for (int k = 0; k < ntw; k += D) {
 #pragma unroll
-        for (int s = 0; s < kDepth; ++s) {
+        for (int s = 0; s < D; ++s) {
             pair_terms<VISC>(A, e[s], pi, vi, ai, P[s], V[s], X[s], k + s < nt, C);
             e[s] = en[s];
             const uint32_t j = min(e[s] & kIndexMask, jmax);
             P[s] = pos[j];
             V[s] = vel[j];
             X[s] = aux[j];
-            en[s] = tile[list_slot(k + s + 2 * kDepth, nf, last, M) * kWave];
+            en[s] = tile[list_slot(k + s + 2 * D, nf, last, M) * kWave];
         }
     }
 }
@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__rest
     const float2 ai = aux[ii];
     PairAcc A = {0.0f, 0.0f, 0.0f, 0.0f};
 
-    gather_pairs<VISC>(A, tile + lane, nf, nt, ntw, M, jmax, pos, vel, aux, pi, vi, ai, C);
+    gather_pairs<VISC, kDepth>(A, tile + lane, nf, nt, ntw, M, jmax, pos, vel, aux, pi, vi, ai, C);
     if (i < n) out[i] = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
@@ -239,44 +239,57 @@ __global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__rest
 // the r < 2h mask only differs from the exact one where the kernel weight is
 // of order 1e-20).  A brick whose halo does not fit in LDS reads the global
 // lists and the global state with the arithmetic of k_forces.
-#ifndef SPH_BRICK_DEPTH
-#define SPH_BRICK_DEPTH 6
+
+// Pairs of one lane's brick-local list, read from LDS.  The list arrives in
+// 16-byte groups of 8 entries (one load per 8 pairs), requested two groups
+// ahead; the staged data of pair k + R is requested while pair k is computed
+// (a ring of R slots, R dividing 8 so the ring phase is the same in every
+// group).
+#ifndef SPH_BRICK_RING
+#define SPH_BRICK_RING 2
 #endif
-constexpr int kBrickDepth = SPH_BRICK_DEPTH;
+constexpr int kRing = SPH_BRICK_RING;
+static_assert(kBrickGroup % kRing == 0, "ring must divide the group");
+
+__device__ __forceinline__ uint32_t group_entry(const uint4 &g, int s)
+{
+    const uint32_t w = (s >> 1) == 0 ? g.x : (s >> 1) == 1 ? g.y : (s >> 1) == 2 ? g.z : g.w;
+    return (s & 1) ? (w >> 16) : (w & 0xFFFFu);
+}
 
 template <int VISC, int NT>
-__device__ __forceinline__ void brick_pairs_lds(PairAcc &A, const uint16_t *ltile, int nt, int ntw, int total,
+__device__ __forceinline__ void brick_pairs_lds(PairAcc &A, const uint4 *lg, int nt, int ntw, int total,
                                                 const float4 *__restrict__ sP, const float4 *__restrict__ sV,
                                                 const float2 *__restrict__ sA, const float4 &pi, const float4 &vi,
                                                 const float2 &ai, const ForceConst &C)
 {
-    const int last = max(nt - 1, 0);
+    constexpr int GS = kWave;  // uint4 stride between groups of one lane
+    const int lastg = max(nt - 1, 0) / kBrickGroup;
     const uint32_t smax = (uint32_t)(total - 1);
-    uint32_t e[kBrickDepth], en[kBrickDepth];
-    float4 P[kBrickDepth], V[kBrickDepth];
-    float2 X[kBrickDepth];
+    float4 P[kRing], V[kRing];
+    float2 X[kRing];
     auto fetch = [&](uint32_t slot, float4 &p, float4 &v, float2 &x) {
         const uint32_t sl = min(slot, smax);  // a stale list stays inside the staged range
         p = sP[sl];
         v = sV[sl];
         x = sA[sl];
     };
+    uint4 gc = lg[0];
+    uint4 gn = lg[min(1, lastg) * GS];
 #pragma unroll
-    for (int s = 0; s < kBrickDepth; ++s) {
-        e[s] = ltile[min(s, last) * kWave];
-        en[s] = ltile[min(s + kBrickDepth, last) * kWave];
-    }
+    for (int r = 0; r < kRing; ++r) fetch(group_entry(gc, r), P[r], V[r], X[r]);
+    for (int k = 0; k < ntw; k += kBrickGroup) {
+        const uint4 gnn = lg[min(k / kBrickGroup + 2, lastg) * GS];
 #pragma unroll
-    for (int s = 0; s < kBrickDepth; ++s) fetch(e[s], P[s], V[s], X[s]);
-    for (int k = 0; k < ntw; k += kBrickDepth) {
-#pragma unroll
-        for (int s = 0; s < kBrickDepth; ++s) {
-            pair_core<VISC>(A, pi.x - P[s].x, pi.y - P[s].y, pi.z - P[s].z, vi, ai, P[s], V[s], X[s], k + s < nt,
+        for (int s = 0; s < kBrickGroup; ++s) {
+            const int r = s % kRing;
+            pair_core<VISC>(A, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, vi, ai, P[r], V[r], X[r], k + s < nt,
                             C);
-            e[s] = en[s];
-            fetch(e[s], P[s], V[s], X[s]);
-            en[s] = ltile[min(k + s + 2 * kBrickDepth, last) * kWave];
+            const int s2 = s + kRing;
+            fetch(s2 < kBrickGroup ? group_entry(gc, s2) : group_entry(gn, s2 - kBrickGroup), P[r], V[r], X[r]);
         }
+        gc = gn;
+        gn = gnn;
     }
 }
 
@@ -407,10 +420,13 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
             if (use_lds) {
                 const int tc = (u % BX + 1) + SX * ((u / BX) % BY + 1) + SX * SY * (u / (BX * BY) + 1);
                 const int si = i + cDelta[tc];
-                brick_pairs_lds<VISC, NT>(A, neibs_brick + toff, nt, ntw, total, sP, sV, sA, sP[si], sV[si], sA[si],
-                                          C);
+                const uint4 *lg = (const uint4 *)(neibs_brick + brick_entry(i, 0, brick_groups(M)));
+                brick_pairs_lds<VISC, NT>(A, lg, nt, ntw, total, sP, sV, sA, sP[si], sV[si], sA[si], C);
             } else {
-                gather_pairs<VISC>(A, neibs + toff, nf, nt, ntw, M, jmax, pos, vel, aux, pos[i], vel[i], aux[i], C);
+                // (a shallow pipeline: this path shares the register budget of
+                // the LDS path and runs only where a halo overflows)
+                gather_pairs<VISC, 2>(A, neibs + toff, nf, nt, ntw, M, jmax, pos, vel, aux, pos[i], vel[i], aux[i],
+                                      C);
             }
         }
         if (act) out[i] = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);

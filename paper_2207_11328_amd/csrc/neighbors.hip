@@ -304,9 +304,10 @@ __global__ void k_status(int n, int n_cells, const int32_t *__restrict__ start, 
 //
 // Optionally the same lists are also written in brick-local form for the
 // derivative kernels: entry k is the neighbour's slot in the staging order of
-// the central particle's brick (cells of the 5x5x5 halo in x-fastest order,
-// particles of a cell in sorted order), uint16, in scan order with fluid and
-// boundary neighbours interleaved as found (slots 0 .. nf + nb - 1).
+// the central particle's brick (cells of the brick and its halo in x-fastest
+// order, particles of a cell in sorted order), uint16, in scan order with
+// fluid and boundary neighbours interleaved as found (entries 0 .. nf+nb-1),
+// stored in groups of 8 per particle (brick_entry).
 template <int BX, int BY, int BZ, bool LDS>
 __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float4 &pi, bool central_boundary,
                                                const int *cBase, const int *cDelta, const int *cFluidEnd,
@@ -347,7 +348,11 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
                     const int slot = nb_boundary ? M - 1 - wb : wf;
                     if (keep) {
                         tile[slot * kWave] = (uint32_t)j | code;
-                        if (ltile) ltile[(wf + wb) * kWave] = (uint16_t)min(sl, 0xFFFF);
+                        if (ltile) {
+                            const int p = wf + wb;
+                            ltile[(p / kBrickGroup) * (kWave * kBrickGroup) + p % kBrickGroup] =
+                                (uint16_t)min(sl, 0xFFFF);
+                        }
                     }
                     const int kb = (int)(keep & nb_boundary), hb = (int)(hit & nb_boundary);
                     wb += kb;
@@ -466,7 +471,7 @@ __global__ __launch_bounds__(NT) void k_build_brick(int n, int max_neibs, const 
         const bool central_boundary = ptype(info[i]) == kBoundary;
         const size_t toff = (size_t)(i / kWave) * kWave * max_neibs + (i % kWave);
         uint32_t *tile = neibs + toff;
-        uint16_t *ltile = neibs_brick ? neibs_brick + toff : nullptr;
+        uint16_t *ltile = neibs_brick ? neibs_brick + brick_entry(i, 0, brick_groups(max_neibs)) : nullptr;
         int found;
         const uint32_t cw =
             use_lds ? brick_scan<BX, BY, BZ, true>(i, tc, max_neibs, pi, central_boundary, cBase, cDelta, cFluidEnd,
@@ -512,6 +517,12 @@ extern "C" size_t sph_neib_list_entries(int32_t capacity, int32_t max_neibs)
 {
     if (capacity < 0 || max_neibs < 0) return 0;
     return (size_t)((capacity + kWave - 1) / kWave) * kWave * (size_t)max_neibs;
+}
+
+extern "C" size_t sph_neib_brick_entries(int32_t capacity, int32_t max_neibs)
+{
+    if (capacity < 0 || max_neibs < 0) return 0;
+    return (size_t)((capacity + kWave - 1) / kWave) * kWave * (size_t)brick_groups(max_neibs) * kBrickGroup;
 }
 
 extern "C" size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells)

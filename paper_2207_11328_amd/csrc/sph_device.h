@@ -91,6 +91,17 @@ __device__ __forceinline__ T wave_sum(T v)
 #endif
 constexpr int kBrickX = SPH_BRICK_X, kBrickY = SPH_BRICK_Y, kBrickZ = SPH_BRICK_Z;
 
+// Brick-local lists: uint16 entries in groups of 8 per particle (one 16-byte
+// load), tiles of 64 particles, group-major inside a tile: entry p of
+// particle i is at brick_entry(i, p, groups), groups = ceil(max_neibs / 8).
+constexpr int kBrickGroup = 8;
+__host__ __device__ inline int brick_groups(int max_neibs) { return (max_neibs + kBrickGroup - 1) / kBrickGroup; }
+__host__ __device__ inline size_t brick_entry(int i, int p, int groups)
+{
+    return ((size_t)(i / kWave) * groups + (size_t)(p / kBrickGroup)) * (kWave * kBrickGroup) +
+           (size_t)(i % kWave) * kBrickGroup + (size_t)(p % kBrickGroup);
+}
+
 struct BrickGrid {
     int nx, ny, nz;
     uint32_t periodic;

@@ -56,7 +56,7 @@ class Simulation:
         self.forces_n = z((cap, 4), torch.float32)
         self.forces_star = z((cap, 4), torch.float32)
         self.neibs = z(abi.sph_neib_list_entries(cap, self.max_neibs), torch.int32)
-        self.neibs_brick = z(abi.sph_neib_list_entries(cap, self.max_neibs), torch.int16)
+        self.neibs_brick = z(abi.sph_neib_brick_entries(cap, self.max_neibs), torch.int16)
         self.neib_count = z(cap, torch.int32)
         self.cell_start = z(max(self.n_cells, 1), torch.int32)
         self.cell_end = z(max(self.n_cells, 1), torch.int32)

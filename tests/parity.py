@@ -264,11 +264,12 @@ def expected_brick_lists(sim, grid, brick=None):
 
 
 def gpu_brick_lists(sim):
-    """GPU brick-local lists as [n, M] int64 (tile layout undone), -1 past
-    each list."""
+    """GPU brick-local lists as [n, M] int64 (tile and group layout undone),
+    -1 past each list."""
     n, M = sim.n, sim.max_neibs
-    t = sim.neibs_brick.view(-1, M, 64).cpu().numpy().view(np.uint16)  # [tile, slot, lane]
-    L = t.transpose(0, 2, 1).reshape(-1, M)[:n].astype(np.int64)
+    G = -(-M // 8)
+    t = sim.neibs_brick.view(-1, G, 64, 8).cpu().numpy().view(np.uint16)  # [tile, group, lane, 8]
+    L = t.transpose(0, 2, 1, 3).reshape(-1, G * 8)[:n, :M].astype(np.int64)
     cnt = sim.neib_count[:n].cpu().numpy().view(np.uint32).astype(np.int64)
     tot = (cnt & 0xFFFF) + (cnt >> 16)
     return np.where(np.arange(M)[None, :] < tot[:, None], L, -1)
