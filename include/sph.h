@@ -185,8 +185,9 @@ size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells);
  *      particle and group), and holds the neighbour's position in the staging
  *      order of the brick
  *      (sph_brick_shape) that holds i; staging order: the cells of the brick
- *      and its one-cell halo, x fastest, periodic axes wrapped, cells outside
- *      a closed axis empty, then particles of a cell in sorted order;
+ *      and its one-cell halo, x fastest, then z, then y, periodic axes
+ *      wrapped, cells outside a closed axis empty, then particles of a cell
+ *      in sorted order;
  *      saturated at 65535.
  * A particle whose neighbours exceed max_neibs keeps the first max_neibs
  * found (scan order: cells z, y, x outer to inner, then sorted index) and is
@@ -271,8 +272,9 @@ sph_status sph_integrate_backward(const sph_params *params, int32_t stage, const
                                   float *grad_pos_star, float *grad_vel_star, float *grad_forces,
                                   void *stream);
 
-/* Bytes of device workspace sph_forces_backward needs. */
-size_t sph_forces_backward_workspace_bytes(int32_t capacity);
+/* Bytes of device workspace sph_forces_backward needs (n_cells: cells of
+ * the grid). */
+size_t sph_forces_backward_workspace_bytes(int32_t capacity, int32_t n_cells);
 
 /* Adjoint of sph_forces with the lists held fixed.  Given grad_forces
  * (xyz = dL/da_i, w = dL/d(Drho_i/Dt)), computes dL/d(offset_i) into
@@ -283,14 +285,20 @@ size_t sph_forces_backward_workspace_bytes(int32_t capacity);
  * terms of the pairs where it is the central and where it is the neighbour
  * (the list is symmetric); parameter sums are reduced in double in a fixed
  * order.  The derivative of the artificial-viscosity switch at u.x = 0 is
- * that of the active branch.  workspace: sph_forces_backward_workspace_bytes.
- * Errors: SPH_ERR_ARG (also for a grid with a per-cell alpha table),
- * SPH_ERR_WORKSPACE. */
+ * that of the active branch.
+ * cell_start / cell_end / neibs_brick: as for sph_forces (all three from the
+ * build of the lists, or all NULL).  With them the adjoint is computed brick
+ * by brick of cells from LDS (each brick in two halves along y); without them
+ * one lane per particle gathers from global memory.  The two agree to
+ * rounding.  workspace: sph_forces_backward_workspace_bytes(capacity,
+ * n_cells).  Errors: SPH_ERR_ARG (also for a grid with a per-cell alpha
+ * table), SPH_ERR_WORKSPACE. */
 sph_status sph_forces_backward(const sph_grid *grid, const sph_params *params,
                                const sph_particles *parts, const uint32_t *neibs,
                                const uint32_t *neib_count, int32_t max_neibs,
-                               const float *grad_forces, float *grad_pos, float *grad_vel,
-                               double *grad_params, int32_t accumulate, void *workspace,
+                               const int32_t *cell_start, const int32_t *cell_end,
+                               const uint16_t *neibs_brick, const float *grad_forces, float *grad_pos,
+                               float *grad_vel, double *grad_params, int32_t accumulate, void *workspace,
                                size_t workspace_bytes, void *stream);
 
 /* dst[perm[k]] = src[k] for k < n, float4 records (carries an adjoint back

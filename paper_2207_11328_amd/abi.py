@@ -86,9 +86,9 @@ def _load():
     L.sph_count_interactions.restype = st
     L.sph_integrate_backward.argtypes = [P, i32, P, P, P, P, P, P, P, P]
     L.sph_integrate_backward.restype = st
-    L.sph_forces_backward_workspace_bytes.argtypes = [i32]
+    L.sph_forces_backward_workspace_bytes.argtypes = [i32, i32]
     L.sph_forces_backward_workspace_bytes.restype = C.c_size_t
-    L.sph_forces_backward.argtypes = [P, P, P, P, P, i32, P, P, P, P, i32, P, C.c_size_t, P]
+    L.sph_forces_backward.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, P, P, i32, P, C.c_size_t, P]
     L.sph_forces_backward.restype = st
     L.sph_unpermute.argtypes = [i32, P, P, P, P]
     L.sph_unpermute.restype = st
@@ -214,8 +214,8 @@ def sph_count_interactions(grid: SphGrid, params: SphParams, parts: SphParticles
           "sph_count_interactions")
 
 
-def sph_forces_backward_workspace_bytes(capacity: int) -> int:
-    return int(lib.sph_forces_backward_workspace_bytes(int(capacity)))
+def sph_forces_backward_workspace_bytes(capacity: int, n_cells: int) -> int:
+    return int(lib.sph_forces_backward_workspace_bytes(int(capacity), int(n_cells)))
 
 
 def sph_integrate_backward(params: SphParams, stage: int, d_dt, state_n: SphParticles, grad_pos, grad_vel,
@@ -226,9 +226,11 @@ def sph_integrate_backward(params: SphParams, stage: int, d_dt, state_n: SphPart
 
 
 def sph_forces_backward(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count, max_neibs: int,
-                        grad_forces, grad_pos, grad_vel, grad_params, accumulate: bool, workspace, stream=None):
+                        grad_forces, grad_pos, grad_vel, grad_params, accumulate: bool, workspace, stream=None,
+                        cell_start=None, cell_end=None, neibs_brick=None):
     check(lib.sph_forces_backward(C.byref(grid), C.byref(params), C.byref(parts), ptr(neibs), ptr(neib_count),
-                                  int(max_neibs), ptr(grad_forces), ptr(grad_pos), ptr(grad_vel), ptr(grad_params),
+                                  int(max_neibs), ptr(cell_start), ptr(cell_end), ptr(neibs_brick),
+                                  ptr(grad_forces), ptr(grad_pos), ptr(grad_vel), ptr(grad_params),
                                   1 if accumulate else 0, ptr(workspace),
                                   workspace.numel() * workspace.element_size(), stream_ptr(stream)),
           "sph_forces_backward")

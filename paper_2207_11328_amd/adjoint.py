@@ -50,7 +50,7 @@ class AdjointRollout:
         self.gforce = z((cap, 4))
         self.tmp_p, self.tmp_v = z((cap, 4)), z((cap, 4))
         self.perm = z(cap, torch.int32)
-        self.ws_back = z(abi.sph_forces_backward_workspace_bytes(cap), torch.uint8)
+        self.ws_back = z(abi.sph_forces_backward_workspace_bytes(cap, s.n_cells), torch.uint8)
         self.grad_params = z(3, torch.float64)
         self.initial = self._snapshot()
         self.checkpoints = {}
@@ -112,11 +112,12 @@ class AdjointRollout:
         pn = abi.particles_struct(s.n, s.cell, pos_n, vel_n, s.info)
         ps = abi.particles_struct(s.n, s.cell, pos_s, vel_s, s.info)
         abi.sph_integrate_backward(s.p, 1, s.d_dt, pn, self.gpos, self.gvel, self.gpos_s, self.gvel_s, self.gforce)
+        bk = dict(cell_start=s.cell_start, cell_end=s.cell_end, neibs_brick=s.neibs_brick)
         abi.sph_forces_backward(s.g, s.p, ps, s.neibs, s.neib_count, s.max_neibs, self.gforce, self.gpos_s,
-                                self.gvel_s, self.grad_params, True, self.ws_back)
+                                self.gvel_s, self.grad_params, True, self.ws_back, **bk)
         abi.sph_integrate_backward(s.p, 0, s.d_dt, pn, self.gpos, self.gvel, self.gpos_s, self.gvel_s, self.gforce)
         abi.sph_forces_backward(s.g, s.p, pn, s.neibs, s.neib_count, s.max_neibs, self.gforce, self.gpos,
-                                self.gvel, self.grad_params, True, self.ws_back)
+                                self.gvel, self.grad_params, True, self.ws_back, **bk)
 
     def reverse_block(self, stored):
         """Reverse the steps of one block given their stored stage states."""

@@ -306,6 +306,7 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
                                                      float4 *__restrict__ out, ForceConst C, BrickGrid G)
 {
     constexpr int BX = kBrickX, BY = kBrickY, BZ = kBrickZ;
+    using St = Staging<BX, BY, BZ>;
     constexpr int SX = BX + 2, SY = BY + 2, SZ = BZ + 2;
     constexpr int S = SX * SY * SZ;  // staged cells
     constexpr int NI = BX * BY * BZ; // inner cells
@@ -329,7 +330,7 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     //    the list build)
     int st = 0, cnt = 0;
     if (tid < S) {
-        int gx = cx0 - 1 + tid % SX, gy = cy0 - 1 + (tid / SX) % SY, gz = cz0 - 1 + tid / (SX * SY);
+        int gx = cx0 - 1 + St::sx_of(tid), gy = cy0 - 1 + St::sy_of(tid), gz = cz0 - 1 + St::sz_of(tid);
         const bool ok = wrap_axis(gx, G.nx, G.periodic & 1u) && wrap_axis(gy, G.ny, (G.periodic >> 1) & 1u) &&
                         wrap_axis(gz, G.nz, (G.periodic >> 2) & 1u);
         if (ok) {
@@ -350,8 +351,8 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     int icnt = 0, ist = 0;
     // inner cells past the grid edge hold no centrals (on a periodic axis the
     // staged copy would be the wrapped cell, owned by another brick)
-    if (tid < NI && cx0 + tid % BX < G.nx && cy0 + (tid / BX) % BY < G.ny && cz0 + tid / (BX * BY) < G.nz) {
-        const int t = (tid % BX + 1) + SX * ((tid / BX) % BY + 1) + SX * SY * (tid / (BX * BY) + 1);
+    if (tid < NI && cx0 + St::ix_of(tid) < G.nx && cy0 + St::iy_of(tid) < G.ny && cz0 + St::iz_of(tid) < G.nz) {
+        const int t = St::inner(tid);
         icnt = cBase[t + 1] - cBase[t];
         ist = cBase[t] - cDelta[t];
     }
@@ -376,7 +377,7 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
             int e[SX - 1];
 #pragma unroll
             for (int c = 0; c < SX - 1; ++c) e[c] = cBase[t0 + 1 + c];
-            const float sy = (float)(r % SY - 2), sz = (float)(r / SY - 2);
+            const float sy = (float)(r / SZ - 2), sz = (float)(r % SZ - 2);
             for (int s2 = b0 + lane; s2 < b1; s2 += kWave) {
                 int c = 0;
 #pragma unroll
@@ -418,7 +419,7 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
         if (ntw > 0) {
             const size_t toff = (size_t)(i / kWave) * (kWave * M) + (i % kWave);
             if (use_lds) {
-                const int tc = (u % BX + 1) + SX * ((u / BX) % BY + 1) + SX * SY * (u / (BX * BY) + 1);
+                const int tc = St::inner(u);
                 const int si = i + cDelta[tc];
                 const uint4 *lg = (const uint4 *)(neibs_brick + brick_entry(i, 0, brick_groups(M)));
                 brick_pairs_lds<VISC, NT>(A, lg, nt, ntw, total, sP, sV, sA, sP[si], sV[si], sA[si], C);

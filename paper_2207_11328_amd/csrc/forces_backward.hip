@@ -80,14 +80,11 @@ struct BackAcc {
 };
 
 template <int VISC>
-__device__ __forceinline__ void pair_adjoint(BackAcc &G, uint32_t e, const float4 &pi, const float4 &vi,
-                                             const float4 &xi, const float4 &gi, const float4 &pj,
-                                             const float4 &vj, const float4 &xj, const float4 &gj, bool valid,
-                                             const BackConst &C)
+__device__ __forceinline__ void pair_adjoint_core(BackAcc &G, float xx, float xy, float xz, float mi,
+                                                  const float4 &vi, const float4 &xi, const float4 &gi, float mj,
+                                                  const float4 &vj, const float2 &xj, const float4 &gj, bool valid,
+                                                  const BackConst &C)
 {
-    const float xx = fmaf(entry_k(e, 0), C.csx, pi.x - pj.x);
-    const float xy = fmaf(entry_k(e, 1), C.csy, pi.y - pj.y);
-    const float xz = fmaf(entry_k(e, 2), C.csz, pi.z - pj.z);
     float r2;
     {
 #pragma clang fp contract(off)
@@ -101,7 +98,6 @@ __device__ __forceinline__ void pair_adjoint(BackAcc &G, uint32_t e, const float
     const float Fp_r = 3.0f * C.fcoeff * qm2 * qm2 * C.inv_h * inv_r;  // F'(r)/r
     const float ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
     const float w = fmaf(ux, xx, fmaf(uy, xy, uz * xz));
-    const float mi = pi.w, mj = pj.w;
     const float rs = vi.w + vj.w;
     const float inv_rs = __builtin_amdgcn_rcpf(rs);
     const float dd = r2 + C.eps_h2;
@@ -159,6 +155,18 @@ __device__ __forceinline__ void pair_adjoint(BackAcc &G, uint32_t e, const float
         G.gc0 += gc;
         G.gnu += gn;
     }
+}
+
+template <int VISC>
+__device__ __forceinline__ void pair_adjoint(BackAcc &G, uint32_t e, const float4 &pi, const float4 &vi,
+                                             const float4 &xi, const float4 &gi, const float4 &pj,
+                                             const float4 &vj, const float4 &xj, const float4 &gj, bool valid,
+                                             const BackConst &C)
+{
+    const float xx = fmaf(entry_k(e, 0), C.csx, pi.x - pj.x);
+    const float xy = fmaf(entry_k(e, 1), C.csy, pi.y - pj.y);
+    const float xz = fmaf(entry_k(e, 2), C.csz, pi.z - pj.z);
+    pair_adjoint_core<VISC>(G, xx, xy, xz, pi.w, vi, xi, gi, pj.w, vj, make_float2(xj.x, xj.y), gj, valid, C);
 }
 
 template <int VISC>
@@ -239,6 +247,268 @@ __global__ __launch_bounds__(kThreads) void k_forces_backward(
     }
 }
 
+// Output of one particle's adjoint (overwrite or accumulate; grad_pos.w is
+// left as it is).
+__device__ __forceinline__ void store_adjoint(int i, int nt, const BackAcc &G, float4 *__restrict__ gpos,
+                                              float4 *__restrict__ gvel, int accumulate)
+{
+    float4 po = make_float4(G.ox, G.oy, G.oz, 0.0f);
+    float4 vo = make_float4(G.ux, G.uy, G.uz, G.r);
+    if (nt == 0) po = vo = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const float4 p0 = gpos[i];
+    if (accumulate) {
+        const float4 v0 = gvel[i];
+        po = make_float4(p0.x + po.x, p0.y + po.y, p0.z + po.z, p0.w);
+        vo = make_float4(v0.x + vo.x, v0.y + vo.y, v0.z + vo.z, v0.w + vo.w);
+    } else {
+        po.w = p0.w;
+    }
+    gpos[i] = po;
+    gvel[i] = vo;
+}
+
+// ---------------------------------------------------------------------------
+// Cell-brick form of the adjoint (the cell perspective of section "Changing
+// perspective: from the particle to the cell", as in sph_forces).  A brick of
+// cells is processed in its lower and its upper half along y: the staging
+// order puts y outermost, so the staged cells of a half (its inner rows and
+// one halo row on each side) are one contiguous range of staging slots, and
+// the brick-local list entries of its particles index into that range.  Per
+// staged particle 56 bytes go to LDS (brick-relative position and mass,
+// velocity and density, P/rho^2 and c, the upstream adjoint), which holds the
+// halo of a half brick at the lattice density; a half that does not fit reads
+// the global lists and arrays as k_forces_backward does.  The sums per pair
+// are those of k_forces_backward; the separation is taken from brick-relative
+// positions (rounding differs from the gather kernel at the ulp level).
+constexpr int kBackBrickThreads = 512;
+constexpr int kBackBrickCap = 2880;
+
+__device__ __forceinline__ uint32_t group_entry(const uint4 &g, int s)
+{
+    const uint32_t w = (s >> 1) == 0 ? g.x : (s >> 1) == 1 ? g.y : (s >> 1) == 2 ? g.z : g.w;
+    return (s & 1) ? (w >> 16) : (w & 0xFFFFu);
+}
+
+template <int VISC>
+__device__ __forceinline__ void brick_adjoint_lds(BackAcc &G, const uint4 *lg, int nt, int ntw, int s_lo, int span,
+                                                  const float4 *__restrict__ sP, const float4 *__restrict__ sV,
+                                                  const float2 *__restrict__ sX, const float4 *__restrict__ sG,
+                                                  const float4 &pi, const float4 &vi, const float4 &xi,
+                                                  const float4 &gi, const BackConst &C)
+{
+    constexpr int R = 2;  // pairs of staged data in flight
+    const int lastg = max(nt - 1, 0) / kBrickGroup;
+    const uint32_t smax = (uint32_t)(span - 1);
+    float4 P[R], V[R], Gj[R];
+    float2 X[R];
+    auto fetch = [&](uint32_t slot, int r) {
+        const uint32_t sl = min(slot - (uint32_t)s_lo, smax);  // stays inside the staged range
+        P[r] = sP[sl];
+        V[r] = sV[sl];
+        X[r] = sX[sl];
+        Gj[r] = sG[sl];
+    };
+    uint4 gc = lg[0];
+    uint4 gn = lg[min(1, lastg) * kWave];
+#pragma unroll
+    for (int r = 0; r < R; ++r) fetch(group_entry(gc, r), r);
+    for (int k = 0; k < ntw; k += kBrickGroup) {
+        const uint4 gnn = lg[min(k / kBrickGroup + 2, lastg) * kWave];
+#pragma unroll
+        for (int s = 0; s < kBrickGroup; ++s) {
+            const int r = s % R;
+            pair_adjoint_core<VISC>(G, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, pi.w, vi, xi, gi, P[r].w, V[r],
+                                    X[r], Gj[r], k + s < nt, C);
+            const int s2 = s + R;
+            fetch(s2 < kBrickGroup ? group_entry(gc, s2) : group_entry(gn, s2 - kBrickGroup), r);
+        }
+        gc = gn;
+        gn = gnn;
+    }
+}
+
+template <int VISC, int NT, int CAP>
+__global__ __launch_bounds__(NT) void k_forces_backward_brick(
+    int n, const float4 *__restrict__ pos, const float4 *__restrict__ vel, const float4 *__restrict__ aux,
+    const float4 *__restrict__ gforce, const uint32_t *__restrict__ neibs, const uint16_t *__restrict__ neibs_brick,
+    const uint32_t *__restrict__ count, const int32_t *__restrict__ cell_start, const int32_t *__restrict__ cell_end,
+    const int32_t *__restrict__ active, float4 *__restrict__ gpos, float4 *__restrict__ gvel,
+    double *__restrict__ partial, int accumulate, BackConst C, BrickGrid G)
+{
+    constexpr int BX = kBrickX, BY = kBrickY, BZ = kBrickZ;
+    using St = Staging<BX, BY, BZ>;
+    constexpr int SX = St::SX, SZ = St::SZ, S = St::S, NI = St::NI;
+    constexpr int ROW = SX * SZ;       // staged cells per y row
+    constexpr int IROW = BX * BZ;      // inner cells per y row
+    constexpr int HALF = BY / 2;       // inner y rows per half
+    static_assert(BY % 2 == 0, "halves of equal height");
+    static_assert(S <= NT, "one thread per staged cell");
+    __shared__ float4 sP[CAP];
+    __shared__ float4 sV[CAP];
+    __shared__ float2 sX[CAP];
+    __shared__ float4 sG[CAP];
+    __shared__ int cBase[S + 1];
+    __shared__ int cDelta[S];
+    __shared__ int iBase[NI + 1];
+    __shared__ int iStart[NI];
+    __shared__ int wsum[NT / kWave];
+    __shared__ double red[3][NT / kWave];
+
+    const int tid = threadIdx.x;
+    if ((int)blockIdx.x >= active[0]) return;
+    const int b = active[1 + blockIdx.x];
+    const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
+
+    // 1. staged cell ranges and LDS bases, inner cells and their centrals
+    int st = 0, cnt = 0;
+    if (tid < S) {
+        int gx = cx0 - 1 + St::sx_of(tid), gy = cy0 - 1 + St::sy_of(tid), gz = cz0 - 1 + St::sz_of(tid);
+        const bool ok = wrap_axis(gx, G.nx, G.periodic & 1u) && wrap_axis(gy, G.ny, (G.periodic >> 1) & 1u) &&
+                        wrap_axis(gz, G.nz, (G.periodic >> 2) & 1u);
+        if (ok) {
+            const int lin = gx + G.nx * (gy + G.ny * gz);
+            st = cell_start[lin];
+            cnt = cell_end[lin] - st;
+        }
+    }
+    int total;
+    const int ex = block_scan<NT>(cnt, total, wsum);
+    if (tid < S) {
+        cBase[tid] = ex;
+        cDelta[tid] = ex - st;
+    }
+    if (tid == 0) cBase[S] = total;
+    __syncthreads();
+    int icnt = 0, ist = 0;
+    if (tid < NI && cx0 + St::ix_of(tid) < G.nx && cy0 + St::iy_of(tid) < G.ny && cz0 + St::iz_of(tid) < G.nz) {
+        const int t = St::inner(tid);
+        icnt = cBase[t + 1] - cBase[t];
+        ist = cBase[t] - cDelta[t];
+    }
+    int nc;
+    const int iex = block_scan<NT>(icnt, nc, wsum);
+    if (tid < NI) {
+        iBase[tid] = iex;
+        iStart[tid] = ist;
+    }
+    if (tid == 0) iBase[NI] = nc;
+    __syncthreads();
+
+    const int M = C.max_neibs;
+    const int groups = brick_groups(M);
+    const uint32_t jmax = (uint32_t)(n - 1);
+    double pa = 0.0, pc = 0.0, pn = 0.0;
+    for (int half = 0; half < 2; ++half) {
+        // staged rows [half HALF, half HALF + HALF + 2), inner rows [half HALF, (half + 1) HALF)
+        const int s_lo = cBase[half * HALF * ROW];
+        const int s_hi = cBase[(half * HALF + HALF + 2) * ROW];
+        const int q_lo = iBase[half * HALF * IROW];
+        const int q_hi = iBase[(half + 1) * HALF * IROW];
+        const int span = s_hi - s_lo;
+        const bool use_lds = span <= CAP;
+        if (q_hi == q_lo) continue;  // uniform
+        if (use_lds) {
+            // stage the half: one wave per row of SX cells (contiguous in LDS)
+            const int wave = tid / kWave, lane = tid % kWave;
+            for (int r = half * HALF * SZ + wave; r < (half * HALF + HALF + 2) * SZ; r += NT / kWave) {
+                const int t0 = r * SX;
+                const int b0 = cBase[t0], b1 = cBase[t0 + SX];
+                int e[SX - 1];
+#pragma unroll
+                for (int c = 0; c < SX - 1; ++c) e[c] = cBase[t0 + 1 + c];
+                const float sy = (float)(r / SZ - 2), sz = (float)(r % SZ - 2);
+                for (int s2 = b0 + lane; s2 < b1; s2 += kWave) {
+                    int c = 0;
+#pragma unroll
+                    for (int kk = 0; kk < SX - 1; ++kk) c += s2 >= e[kk] ? 1 : 0;
+                    const int j = s2 - cDelta[t0 + c];
+                    const float4 p = pos[j];
+                    const float sx = (float)(c - 2);
+                    const float4 a4 = aux[j];
+                    const int l = s2 - s_lo;
+                    sP[l] = make_float4(fmaf(sx, C.csx, p.x), fmaf(sy, C.csy, p.y), fmaf(sz, C.csz, p.z), p.w);
+                    sV[l] = vel[j];
+                    sX[l] = make_float2(a4.x, a4.y);
+                    sG[l] = gforce[j];
+                }
+            }
+        }
+        __syncthreads();
+        // one lane per central particle of the half
+        for (int q0 = q_lo; q0 < q_hi; q0 += NT) {
+            const int q = q0 + tid;
+            const bool act = q < q_hi;
+            int u;
+            {
+                int lo = 0, hi = NI - 1;
+                const int qq = act ? q : q_hi - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (iBase[mid] <= qq) lo = mid;
+                    else hi = mid - 1;
+                }
+                u = lo;
+            }
+            const int i = iStart[u] + ((act ? q : q_hi - 1) - iBase[u]);
+            const uint32_t cntw = act ? count[i] : 0u;
+            const int nf = min((int)(cntw & 0xFFFFu), M);
+            const int nt = min(nf + (int)(cntw >> 16), M);
+            const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
+            BackAcc A = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+            if (ntw > 0) {
+                const float4 xi = aux[i];
+                if (use_lds) {
+                    const int si = i + cDelta[St::inner(u)] - s_lo;
+                    const uint4 *lg = (const uint4 *)(neibs_brick + brick_entry(i, 0, groups));
+                    brick_adjoint_lds<VISC>(A, lg, nt, ntw, s_lo, span, sP, sV, sX, sG, sP[si], sV[si], xi, sG[si],
+                                            C);
+                } else {
+                    const uint32_t *tile = neibs + (size_t)(i / kWave) * (kWave * M) + (i % kWave);
+                    const float4 pi = pos[i], vi = vel[i], gi = gforce[i];
+                    const int last = max(nt - 1, 0);
+                    for (int k = 0; k < ntw; ++k) {
+                        const uint32_t e = tile[list_slot(k, nf, last, M) * kWave];
+                        const uint32_t j = min(e & kIndexMask, jmax);
+                        pair_adjoint<VISC>(A, e, pi, vi, xi, gi, pos[j], vel[j], aux[j], gforce[j], k < nt, C);
+                    }
+                }
+            }
+            if (act) {
+                store_adjoint(i, nt, A, gpos, gvel, accumulate);
+                if (nt > 0) {
+                    pa += (double)A.galpha;
+                    pc += (double)A.gc0;
+                    pn += (double)A.gnu;
+                }
+            }
+        }
+        __syncthreads();  // the next half reuses LDS
+    }
+    // parameter partial sums of the brick, fixed order, stored by brick id
+    pa = wave_sum(pa);
+    pc = wave_sum(pc);
+    pn = wave_sum(pn);
+    const int lane = tid % kWave, w = tid / kWave;
+    if (lane == 0) {
+        red[0][w] = pa;
+        red[1][w] = pc;
+        red[2][w] = pn;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        double sum = 0.0;
+        for (int k = 0; k < NT / kWave; ++k) sum += red[tid][k];
+        partial[3 * (size_t)b + tid] = sum;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero_f64(int n, double *__restrict__ p)
+{
+    for (int k = blockIdx.x * kThreads + threadIdx.x; k < n; k += gridDim.x * kThreads) p[k] = 0.0;
+}
+
+__global__ void k_zero_i32(int32_t *p) { *p = 0; }
+
 __global__ __launch_bounds__(kThreads) void k_param_reduce(int nblocks, const double *__restrict__ partial,
                                                            double *__restrict__ out, int accumulate)
 {
@@ -270,21 +540,60 @@ __global__ __launch_bounds__(kThreads) void k_unpermute(int n, const uint32_t *_
 
 size_t aux_bytes(int64_t cap) { return (size_t)((16 * cap + 255) & ~(int64_t)255); }
 size_t partial_bytes(int64_t cap) { return (size_t)(3 * 8 * ((cap + kThreads - 1) / kThreads) + 256); }
+// per-brick parameter partials (at most one brick per cell) and the active-brick list
+size_t brick_bytes(int64_t n_cells) { return (size_t)(3 * 8 * (n_cells + 1) + 4 * (n_cells + 2) + 256); }
+
+__global__ __launch_bounds__(kThreads) void k_zero_dropped_adjoint(int n, const int32_t *__restrict__ cell,
+                                                                   float4 *__restrict__ gpos,
+                                                                   float4 *__restrict__ gvel)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i < n && cell[i] < 0) {
+        gpos[i] = make_float4(0.0f, 0.0f, 0.0f, gpos[i].w);
+        gvel[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+}
+
+template <int VISC>
+void launch_backward_brick(const sph_grid *grid, int n, const float4 *pos, const float4 *vel, const float4 *aux,
+                           const float4 *gforce, const uint32_t *neibs, const uint16_t *neibs_brick,
+                           const uint32_t *count, const int32_t *cell_start, const int32_t *cell_end,
+                           int32_t *active, float4 *gpos, float4 *gvel, double *partial, int accumulate,
+                           const BackConst &C, hipStream_t s)
+{
+    BrickGrid G;
+    G.nx = grid->ncell[0];
+    G.ny = grid->ncell[1];
+    G.nz = grid->ncell[2];
+    G.periodic = grid->periodic;
+    G.nbx = (G.nx + kBrickX - 1) / kBrickX;
+    G.nby = (G.ny + kBrickY - 1) / kBrickY;
+    G.nbz = (G.nz + kBrickZ - 1) / kBrickZ;
+    const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
+    k_zero_i32<<<1, 1, 0, s>>>(active);
+    k_zero_f64<<<sph_blocks(3 * blocks, kThreads) < 1024u ? sph_blocks(3 * blocks, kThreads) : 1024u, kThreads, 0,
+                 s>>>(3 * (int)blocks, partial);
+    k_active_bricks<kBrickX, kBrickY, kBrickZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(cell_start, cell_end, G, active);
+    k_forces_backward_brick<VISC, kBackBrickThreads, kBackBrickCap><<<blocks, kBackBrickThreads, 0, s>>>(
+        n, pos, vel, aux, gforce, neibs, neibs_brick, count, cell_start, cell_end, active, gpos, gvel, partial,
+        accumulate, C, G);
+}
 
 }  // namespace
 
-extern "C" size_t sph_forces_backward_workspace_bytes(int32_t capacity)
+extern "C" size_t sph_forces_backward_workspace_bytes(int32_t capacity, int32_t n_cells)
 {
-    if (capacity < 0) return 0;
+    if (capacity < 0 || n_cells < 0) return 0;
     const int64_t cap = capacity > 0 ? capacity : 1;
-    return aux_bytes(cap) + partial_bytes(cap);
+    return aux_bytes(cap) + partial_bytes(cap) + brick_bytes(n_cells);
 }
 
 extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params *p, const sph_particles *parts,
                                           const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
-                                          const float *grad_forces, float *grad_pos, float *grad_vel,
-                                          double *grad_params, int32_t accumulate, void *workspace,
-                                          size_t workspace_bytes, void *stream)
+                                          const int32_t *cell_start, const int32_t *cell_end,
+                                          const uint16_t *neibs_brick, const float *grad_forces, float *grad_pos,
+                                          float *grad_vel, double *grad_params, int32_t accumulate,
+                                          void *workspace, size_t workspace_bytes, void *stream)
 {
     if (!grid || !p || !parts || !grad_params || grid->cell_alpha) return SPH_ERR_ARG;
     if (parts->n < 0 || parts->capacity < parts->n || parts->capacity > SPH_MAX_CAPACITY) return SPH_ERR_ARG;
@@ -294,7 +603,11 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
         return SPH_ERR_ARG;
     if (!(p->h > 0.0f) || !(p->rho0 > 0.0f) || !(p->c0 > 0.0f) || p->gamma != 7.0f) return SPH_ERR_ARG;
     if (p->visc_model != 0 && p->visc_model != 1) return SPH_ERR_ARG;
-    if (!workspace || workspace_bytes < sph_forces_backward_workspace_bytes(parts->capacity))
+    const int64_t n_cells = (int64_t)grid->ncell[0] * grid->ncell[1] * grid->ncell[2];
+    if (n_cells <= 0 || n_cells > INT32_MAX - 2) return SPH_ERR_ARG;
+    const bool bricks = cell_start && cell_end && neibs_brick;
+    if (bricks && parts->n > 0 && !parts->cell) return SPH_ERR_ARG;
+    if (!workspace || workspace_bytes < sph_forces_backward_workspace_bytes(parts->capacity, (int32_t)n_cells))
         return SPH_ERR_WORKSPACE;
     BackConst C;
     C.csx = grid->cell_size[0];
@@ -317,9 +630,34 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
     C.max_neibs = max_neibs;
     const int n = parts->n;
     hipStream_t s = (hipStream_t)stream;
+    const int64_t cap1 = parts->capacity > 0 ? parts->capacity : 1;
     float4 *aux = (float4 *)workspace;
-    double *partial = (double *)((char *)workspace + aux_bytes(parts->capacity > 0 ? parts->capacity : 1));
+    double *partial = (double *)((char *)workspace + aux_bytes(cap1));
+    double *bpartial = (double *)((char *)workspace + aux_bytes(cap1) + partial_bytes(cap1));
+    int32_t *active = (int32_t *)(bpartial + 3 * (n_cells + 1));
     const int nblocks = n > 0 ? (int)sph_blocks(n, kThreads) : 0;
+    if (n > 0 && bricks) {
+        // cell ranges and brick-local lists of the last build: LDS bricks
+        const int nb = ((grid->ncell[0] + kBrickX - 1) / kBrickX) * ((grid->ncell[1] + kBrickY - 1) / kBrickY) *
+                       ((grid->ncell[2] + kBrickZ - 1) / kBrickZ);
+        k_eos_grad<<<nblocks, kThreads, 0, s>>>(n, (const float4 *)parts->vel, aux, C);
+        if (p->visc_model == 0)
+            launch_backward_brick<0>(grid, n, (const float4 *)parts->pos, (const float4 *)parts->vel, aux,
+                                     (const float4 *)grad_forces, neibs, neibs_brick, neib_count, cell_start,
+                                     cell_end, active, (float4 *)grad_pos, (float4 *)grad_vel, bpartial, accumulate,
+                                     C, s);
+        else
+            launch_backward_brick<1>(grid, n, (const float4 *)parts->pos, (const float4 *)parts->vel, aux,
+                                     (const float4 *)grad_forces, neibs, neibs_brick, neib_count, cell_start,
+                                     cell_end, active, (float4 *)grad_pos, (float4 *)grad_vel, bpartial, accumulate,
+                                     C, s);
+        if (!accumulate)
+            k_zero_dropped_adjoint<<<nblocks, kThreads, 0, s>>>(n, parts->cell, (float4 *)grad_pos,
+                                                                 (float4 *)grad_vel);
+        k_param_reduce<<<1, kThreads, 0, s>>>(nb, bpartial, grad_params, accumulate);
+        SPH_CHECK_LAUNCH();
+        return SPH_OK;
+    }
     if (n > 0) {
         k_eos_grad<<<nblocks, kThreads, 0, s>>>(n, (const float4 *)parts->vel, aux, C);
         if (p->visc_model == 0)

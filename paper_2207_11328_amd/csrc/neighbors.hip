@@ -304,8 +304,8 @@ __global__ void k_status(int n, int n_cells, const int32_t *__restrict__ start, 
 //
 // Optionally the same lists are also written in brick-local form for the
 // derivative kernels: entry k is the neighbour's slot in the staging order of
-// the central particle's brick (cells of the brick and its halo in x-fastest
-// order, particles of a cell in sorted order), uint16, in scan order with
+// the central particle's brick (cells of the brick and its halo in the
+// Staging order, particles of a cell in sorted order), uint16, in scan order with
 // fluid and boundary neighbours interleaved as found (entries 0 .. nf+nb-1),
 // stored in groups of 8 per particle (brick_entry).
 template <int BX, int BY, int BZ, bool LDS>
@@ -315,7 +315,6 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
                                                const uint32_t *__restrict__ ginfo, float csx, float csy, float csz,
                                                float rs2, uint32_t *tile, uint16_t *ltile, int &total_found)
 {
-    constexpr int SX = BX + 2, SY = BY + 2;
     int nf = 0, nb = 0, wf = 0, wb = 0;
     for (int dz = -1; dz <= 1; ++dz) {
         const float t2z = cell_shift(-dz, csz);
@@ -323,7 +322,7 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
             const float t2y = cell_shift(-dy, csy);
             for (int dx = -1; dx <= 1; ++dx) {
                 const float t2x = cell_shift(-dx, csx);
-                const int t = tc + dx + SX * (dy + SY * dz);
+                const int t = tc + Staging<BX, BY, BZ>::step(dx, dy, dz);
                 const int s0 = cBase[t];
                 const int s1 = central_boundary ? cFluidEnd[t] : cBase[t + 1];
                 const int delta = cDelta[t];
@@ -398,7 +397,8 @@ __global__ __launch_bounds__(NT) void k_build_brick(int n, int max_neibs, const 
     // 1. ranges of the staged cells and their LDS bases
     int st = 0, cnt = 0;
     if (tid < S) {
-        int gx = cx0 - 1 + tid % SX, gy = cy0 - 1 + (tid / SX) % SY, gz = cz0 - 1 + tid / (SX * SY);
+        using St = Staging<BX, BY, BZ>;
+        int gx = cx0 - 1 + St::sx_of(tid), gy = cy0 - 1 + St::sy_of(tid), gz = cz0 - 1 + St::sz_of(tid);
         const bool ok = wrap_axis(gx, G.nx, G.periodic & 1u) && wrap_axis(gy, G.ny, (G.periodic >> 1) & 1u) &&
                         wrap_axis(gz, G.nz, (G.periodic >> 2) & 1u);
         if (ok) {
@@ -419,8 +419,9 @@ __global__ __launch_bounds__(NT) void k_build_brick(int n, int max_neibs, const 
     int icnt = 0, ist = 0;
     // inner cells past the grid edge hold no centrals (on a periodic axis the
     // staged copy would be the wrapped cell, owned by another brick)
-    if (tid < NI && cx0 + tid % BX < G.nx && cy0 + (tid / BX) % BY < G.ny && cz0 + tid / (BX * BY) < G.nz) {
-        const int t = (tid % BX + 1) + SX * ((tid / BX) % BY + 1) + SX * SY * (tid / (BX * BY) + 1);
+    using St = Staging<BX, BY, BZ>;
+    if (tid < NI && cx0 + St::ix_of(tid) < G.nx && cy0 + St::iy_of(tid) < G.ny && cz0 + St::iz_of(tid) < G.nz) {
+        const int t = St::inner(tid);
         icnt = cBase[t + 1] - cBase[t];
         ist = cBase[t] - cDelta[t];
     }
@@ -466,7 +467,7 @@ __global__ __launch_bounds__(NT) void k_build_brick(int n, int max_neibs, const 
         }
         const int u = lo;
         const int i = iStart[u] + (q - iBase[u]);
-        const int tc = (u % BX + 1) + SX * ((u / BX) % BY + 1) + SX * SY * (u / (BX * BY) + 1);
+        const int tc = St::inner(u);
         const float4 pi = pos[i];
         const bool central_boundary = ptype(info[i]) == kBoundary;
         const size_t toff = (size_t)(i / kWave) * kWave * max_neibs + (i % kWave);

@@ -91,6 +91,27 @@ __device__ __forceinline__ T wave_sum(T v)
 #endif
 constexpr int kBrickX = SPH_BRICK_X, kBrickY = SPH_BRICK_Y, kBrickZ = SPH_BRICK_Z;
 
+// Staging geometry of a brick of BX x BY x BZ cells: the brick and its
+// one-cell halo, SX x SY x SZ staged cells numbered x fastest, then z, then y
+// (y outermost, so the staged cells of the lower and of the upper half of the
+// brick's y extent are two contiguous ranges of the staging order).  Inner
+// cells u = ix + BX (iz + BZ iy) follow the same order.
+template <int BX, int BY, int BZ>
+struct Staging {
+    static constexpr int SX = BX + 2, SY = BY + 2, SZ = BZ + 2;
+    static constexpr int S = SX * SY * SZ, NI = BX * BY * BZ;
+    __host__ __device__ static int cell(int sx, int sy, int sz) { return sx + SX * (sz + SZ * sy); }
+    __host__ __device__ static int sx_of(int t) { return t % SX; }
+    __host__ __device__ static int sz_of(int t) { return (t / SX) % SZ; }
+    __host__ __device__ static int sy_of(int t) { return t / (SX * SZ); }
+    __host__ __device__ static int ix_of(int u) { return u % BX; }
+    __host__ __device__ static int iz_of(int u) { return (u / BX) % BZ; }
+    __host__ __device__ static int iy_of(int u) { return u / (BX * BZ); }
+    // staged cell of inner cell u, and the step to a neighbour cell
+    __host__ __device__ static int inner(int u) { return cell(ix_of(u) + 1, iy_of(u) + 1, iz_of(u) + 1); }
+    __host__ __device__ static int step(int dx, int dy, int dz) { return dx + SX * (dz + SZ * dy); }
+};
+
 // Brick-local lists: uint16 entries in groups of 8 per particle (one 16-byte
 // load), tiles of 64 particles, group-major inside a tile: entry p of
 // particle i is at brick_entry(i, p, groups), groups = ceil(max_neibs / 8).

@@ -198,7 +198,8 @@ def expected_brick_lists(sim, grid, brick=None):
     """Brick-local lists implied by the GPU's own j-lists and cell ranges,
     from the layout the header documents: entry k of particle i is the
     neighbour's position in the staging order of i's brick (the
-    (BX+2)(BY+2)(BZ+2) cells of the brick and its halo, x fastest, periodic axes wrapped, cells
+    (BX+2)(BY+2)(BZ+2) cells of the brick and its halo, x fastest, then z,
+    then y, periodic axes wrapped, cells
     past a closed axis empty; particles of a cell in sorted order), entries
     in scan order (neighbour cells z, y, x from -1 to +1, then sorted index),
     fluid and boundary interleaved.  Returns
@@ -227,7 +228,7 @@ def expected_brick_lists(sim, grid, brick=None):
             st = np.zeros(SX * SY * SZ, np.int64)
             ct = np.zeros(SX * SY * SZ, np.int64)
             for t in range(SX * SY * SZ):
-                g = [bx * BX - 1 + t % SX, by * BY - 1 + (t // SX) % SY, bz * BZ - 1 + t // (SX * SY)]
+                g = [bx * BX - 1 + t % SX, by * BY - 1 + t // (SX * SZ), bz * BZ - 1 + (t // SX) % SZ]
                 ok = True
                 for d, nd in enumerate((nx, ny, nz)):
                     if per[d]:
@@ -249,7 +250,7 @@ def expected_brick_lists(sim, grid, brick=None):
         cx, cy, cz = c % nx, (c // nx) % ny, c // (nx * ny)
         delta, tot = staging(cx // BX, cy // BY, cz // BZ)
         totals[i] = tot
-        tc = (cx % BX + 1) + SX * ((cy % BY + 1) + SY * (cz % BZ + 1))
+        tc = (cx % BX + 1) + SX * ((cz % BZ + 1) + SZ * (cy % BY + 1))
         order = list(range(nf[i])) + [M - 1 - b for b in range(nbd[i])]
         e = E[i, order]
         j = e & ((1 << 26) - 1)
@@ -258,7 +259,7 @@ def expected_brick_lists(sim, grid, brick=None):
         # scan order: neighbour cell offset d = -k, z outermost, then index
         o = np.lexsort((j, -k[0], -k[1], -k[2]))
         j, k = j[o], [v[o] for v in k]
-        t = tc - k[0] - SX * (k[1] + SY * k[2])
+        t = tc - k[0] - SX * (k[2] + SZ * k[1])
         out[i, : len(order)] = np.minimum(j + delta[t], 0xFFFF)
     return out, totals
 

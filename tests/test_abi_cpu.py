@@ -86,8 +86,8 @@ def test_argument_errors_return_before_any_launch(abi):
                               None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_build_neighbors(None, None, None, None, None, 128, None, None, None, None, None, None, 0,
                                        None) == abi.SPH_ERR_ARG
-    assert abi.lib.sph_forces_backward(None, None, None, None, None, 128, None, None, None, None, 0, None, 0,
-                                       None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_forces_backward(None, None, None, None, None, 128, None, None, None, None, None, None, None,
+                                       0, None, 0, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_integrate_backward(None, 0, None, None, None, None, None, None, None,
                                           None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_unpermute(-1, None, None, None, None) == abi.SPH_ERR_ARG

@@ -53,11 +53,14 @@ SCENES = {
 }
 
 
+@pytest.mark.parametrize("bricks", [True, False], ids=["bricks", "gather"])
 @pytest.mark.parametrize("name", list(SCENES))
-def test_forces_backward_parity(name):
+def test_forces_backward_parity(name, bricks):
+    """Both forms of the adjoint (LDS bricks in two halves, per-particle
+    gather) against the FP64 oracle reverse."""
     make, M = SCENES[name]
     sc = make()
-    log("case %s n=%d" % (name, sc.n))
+    log("case %s n=%d bricks=%s" % (name, sc.n, bricks))
     sim = make_sim(sc, max_neibs=M)
     sim.build()
     torch_sync()
@@ -76,9 +79,11 @@ def test_forces_backward_parity(name):
     gpos = torch.full((sim.capacity, 4), 7.0, device=dev)
     gvel = torch.zeros((sim.capacity, 4), device=dev)
     gparams = torch.zeros(3, dtype=torch.float64, device=dev)
-    ws = torch.zeros(abi.sph_forces_backward_workspace_bytes(sim.capacity), dtype=torch.uint8, device=dev)
+    ws = torch.zeros(abi.sph_forces_backward_workspace_bytes(sim.capacity, sim.n_cells), dtype=torch.uint8,
+                     device=dev)
+    bk = dict(cell_start=sim.cell_start, cell_end=sim.cell_end, neibs_brick=sim.neibs_brick) if bricks else {}
     abi.sph_forces_backward(sim.g, sim.p, sim.parts, sim.neibs, sim.neib_count, sim.max_neibs, gforce, gpos, gvel,
-                            gparams, False, ws)
+                            gparams, False, ws, **bk)
     torch_sync()
     gp_gpu = gpos[: sc.n].cpu().numpy()
     gv_gpu = gvel[: sc.n].cpu().numpy()
@@ -95,12 +100,12 @@ def test_forces_backward_parity(name):
     gvel2 = gvel.clone()
     gparams2 = gparams.clone()
     abi.sph_forces_backward(sim.g, sim.p, sim.parts, sim.neibs, sim.neib_count, sim.max_neibs, gforce, gpos2,
-                            gvel2, gparams2, True, ws)
+                            gvel2, gparams2, True, ws, **bk)
     torch_sync()
     assert torch.allclose(gvel2, 2 * gvel, rtol=1e-6, atol=0)
     assert torch.allclose(gparams2, 2 * gparams, rtol=1e-12, atol=0)
     abi.sph_forces_backward(sim.g, sim.p, sim.parts, sim.neibs, sim.neib_count, sim.max_neibs, gforce, gpos2,
-                            gvel2, gparams2, False, ws)
+                            gvel2, gparams2, False, ws, **bk)
     torch_sync()
     assert torch.equal(gvel2, gvel) and torch.equal(gparams2, gparams)
 
