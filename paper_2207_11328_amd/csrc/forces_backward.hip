@@ -280,7 +280,10 @@ __device__ __forceinline__ void store_adjoint(int i, int nt, const BackAcc &G, f
 // the global lists and arrays as k_forces_backward does.  The sums per pair
 // are those of k_forces_backward; the separation is taken from brick-relative
 // positions (rounding differs from the gather kernel at the ulp level).
-constexpr int kBackBrickThreads = 512;
+#ifndef SPH_BACK_RING
+#define SPH_BACK_RING 2
+#endif
+constexpr int kBackBrickThreads = 1024;
 constexpr int kBackBrickCap = 2880;
 
 __device__ __forceinline__ uint32_t group_entry(const uint4 &g, int s)
@@ -289,14 +292,17 @@ __device__ __forceinline__ uint32_t group_entry(const uint4 &g, int s)
     return (s & 1) ? (w >> 16) : (w & 0xFFFFu);
 }
 
+// Pairs of one central's brick-local list, read from LDS, shared by two
+// lanes: lane h of the pair takes the groups of 8 entries h, h + 2, h + 4, ...
+// (list groups requested two iterations ahead, staged data R pairs ahead).
 template <int VISC>
-__device__ __forceinline__ void brick_adjoint_lds(BackAcc &G, const uint4 *lg, int nt, int ntw, int s_lo, int span,
-                                                  const float4 *__restrict__ sP, const float4 *__restrict__ sV,
-                                                  const float2 *__restrict__ sX, const float4 *__restrict__ sG,
-                                                  const float4 &pi, const float4 &vi, const float4 &xi,
-                                                  const float4 &gi, const BackConst &C)
+__device__ __forceinline__ void brick_adjoint_lds(BackAcc &G, const uint4 *lg, int h, int nt, int ntw, int s_lo,
+                                                  int span, const float4 *__restrict__ sP,
+                                                  const float4 *__restrict__ sV, const float2 *__restrict__ sX,
+                                                  const float4 *__restrict__ sG, const float4 &pi, const float4 &vi,
+                                                  const float4 &xi, const float4 &gi, const BackConst &C)
 {
-    constexpr int R = 2;  // pairs of staged data in flight
+    constexpr int R = SPH_BACK_RING;  // pairs of staged data in flight
     const int lastg = max(nt - 1, 0) / kBrickGroup;
     const uint32_t smax = (uint32_t)(span - 1);
     float4 P[R], V[R], Gj[R];
@@ -308,23 +314,38 @@ __device__ __forceinline__ void brick_adjoint_lds(BackAcc &G, const uint4 *lg, i
         X[r] = sX[sl];
         Gj[r] = sG[sl];
     };
-    uint4 gc = lg[0];
-    uint4 gn = lg[min(1, lastg) * kWave];
+    uint4 gc = lg[min(h, lastg) * kWave];
+    uint4 gn = lg[min(h + 2, lastg) * kWave];
 #pragma unroll
     for (int r = 0; r < R; ++r) fetch(group_entry(gc, r), r);
-    for (int k = 0; k < ntw; k += kBrickGroup) {
-        const uint4 gnn = lg[min(k / kBrickGroup + 2, lastg) * kWave];
+    for (int k = 0; k < ntw; k += 2 * kBrickGroup) {
+        const int g0 = k / kBrickGroup + h;  // this lane's group
+        const uint4 gnn = lg[min(g0 + 4, lastg) * kWave];
 #pragma unroll
         for (int s = 0; s < kBrickGroup; ++s) {
             const int r = s % R;
             pair_adjoint_core<VISC>(G, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, pi.w, vi, xi, gi, P[r].w, V[r],
-                                    X[r], Gj[r], k + s < nt, C);
+                                    X[r], Gj[r], g0 * kBrickGroup + s < nt, C);
             const int s2 = s + R;
             fetch(s2 < kBrickGroup ? group_entry(gc, s2) : group_entry(gn, s2 - kBrickGroup), r);
         }
         gc = gn;
         gn = gnn;
     }
+}
+
+__device__ __forceinline__ void add_partner(BackAcc &A)
+{
+    A.ox += __shfl_xor(A.ox, 1);
+    A.oy += __shfl_xor(A.oy, 1);
+    A.oz += __shfl_xor(A.oz, 1);
+    A.ux += __shfl_xor(A.ux, 1);
+    A.uy += __shfl_xor(A.uy, 1);
+    A.uz += __shfl_xor(A.uz, 1);
+    A.r += __shfl_xor(A.r, 1);
+    A.galpha += __shfl_xor(A.galpha, 1);
+    A.gc0 += __shfl_xor(A.gc0, 1);
+    A.gnu += __shfl_xor(A.gnu, 1);
 }
 
 template <int VISC, int NT, int CAP>
@@ -434,9 +455,10 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
             }
         }
         __syncthreads();
-        // one lane per central particle of the half
-        for (int q0 = q_lo; q0 < q_hi; q0 += NT) {
-            const int q = q0 + tid;
+        // two lanes per central particle of the half (lane pairs 2q', 2q'+1)
+        const int h = tid & 1;
+        for (int q0 = q_lo; q0 < q_hi; q0 += NT / 2) {
+            const int q = q0 + tid / 2;
             const bool act = q < q_hi;
             int u;
             {
@@ -460,20 +482,22 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
                 if (use_lds) {
                     const int si = i + cDelta[St::inner(u)] - s_lo;
                     const uint4 *lg = (const uint4 *)(neibs_brick + brick_entry(i, 0, groups));
-                    brick_adjoint_lds<VISC>(A, lg, nt, ntw, s_lo, span, sP, sV, sX, sG, sP[si], sV[si], xi, sG[si],
-                                            C);
+                    brick_adjoint_lds<VISC>(A, lg, h, nt, ntw, s_lo, span, sP, sV, sX, sG, sP[si], sV[si], xi,
+                                            sG[si], C);
                 } else {
+                    // the lane pair splits the list by parity of the entry
                     const uint32_t *tile = neibs + (size_t)(i / kWave) * (kWave * M) + (i % kWave);
                     const float4 pi = pos[i], vi = vel[i], gi = gforce[i];
                     const int last = max(nt - 1, 0);
-                    for (int k = 0; k < ntw; ++k) {
+                    for (int k = h; k < ntw; k += 2) {
                         const uint32_t e = tile[list_slot(k, nf, last, M) * kWave];
                         const uint32_t j = min(e & kIndexMask, jmax);
                         pair_adjoint<VISC>(A, e, pi, vi, xi, gi, pos[j], vel[j], aux[j], gforce[j], k < nt, C);
                     }
                 }
             }
-            if (act) {
+            add_partner(A);
+            if (act && h == 0) {
                 store_adjoint(i, nt, A, gpos, gvel, accumulate);
                 if (nt > 0) {
                     pa += (double)A.galpha;
@@ -509,22 +533,32 @@ __global__ __launch_bounds__(kThreads) void k_zero_f64(int n, double *__restrict
 
 __global__ void k_zero_i32(int32_t *p) { *p = 0; }
 
-__global__ __launch_bounds__(kThreads) void k_param_reduce(int nblocks, const double *__restrict__ partial,
-                                                           double *__restrict__ out, int accumulate)
+// Sum of the per-block (or per-brick) parameter partials in a fixed order:
+// thread t adds partials t, t + 1024, ... (four running sums, combined in a
+// fixed order), then a fixed tree over the threads.
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void k_param_reduce(int nblocks, const double *__restrict__ partial,
+                                                                 double *__restrict__ out, int accumulate)
 {
-    double s[3] = {0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nblocks; b += kThreads)
-        for (int k = 0; k < 3; ++k) s[k] += partial[3 * (size_t)b + k];
-    __shared__ double red[3][kThreads / kWave];
+    double s[3][4] = {};
+    int b = threadIdx.x;
+    for (; b + 3 * kReduceThreads < nblocks; b += 4 * kReduceThreads)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s[k][u] += partial[3 * (size_t)(b + u * kReduceThreads) + k];
+    for (; b < nblocks; b += kReduceThreads)
+        for (int k = 0; k < 3; ++k) s[k][0] += partial[3 * (size_t)b + k];
+    __shared__ double red[3][kReduceThreads / kWave];
     const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
     for (int k = 0; k < 3; ++k) {
-        const double t = wave_sum(s[k]);
+        const double t = wave_sum((s[k][0] + s[k][1]) + (s[k][2] + s[k][3]));
         if (lane == 0) red[k][w] = t;
     }
     __syncthreads();
     if (threadIdx.x < 3) {
         double t = 0.0;
-        for (int k = 0; k < kThreads / kWave; ++k) t += red[threadIdx.x][k];
+        for (int k = 0; k < kReduceThreads / kWave; ++k) t += red[threadIdx.x][k];
         out[threadIdx.x] = accumulate ? out[threadIdx.x] + t : t;
     }
 }
@@ -654,7 +688,7 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
         if (!accumulate)
             k_zero_dropped_adjoint<<<nblocks, kThreads, 0, s>>>(n, parts->cell, (float4 *)grad_pos,
                                                                  (float4 *)grad_vel);
-        k_param_reduce<<<1, kThreads, 0, s>>>(nb, bpartial, grad_params, accumulate);
+        k_param_reduce<<<1, kReduceThreads, 0, s>>>(nb, bpartial, grad_params, accumulate);
         SPH_CHECK_LAUNCH();
         return SPH_OK;
     }
@@ -669,7 +703,7 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
                 n, (const float4 *)parts->pos, (const float4 *)parts->vel, aux, (const float4 *)grad_forces, neibs,
                 neib_count, (float4 *)grad_pos, (float4 *)grad_vel, partial, accumulate, C);
     }
-    k_param_reduce<<<1, kThreads, 0, s>>>(nblocks, partial, grad_params, accumulate);
+    k_param_reduce<<<1, kReduceThreads, 0, s>>>(nblocks, partial, grad_params, accumulate);
     SPH_CHECK_LAUNCH();
     return SPH_OK;
 }
