@@ -93,7 +93,7 @@ def cpu_baseline(sc, budget_s):
     }
 
 
-def fwd_bwd(sc, dt, K=10, reps=3):
+def fwd_bwd(sc, dt, K=10, reps=3, brick=None, use_bricks=True):
     """Cost of the reverse relative to the forward on one K-step block of the
     same workload (fixed dt): t_fwd = K plain steps (one rebuild); t_bwd = the
     reverse of those K steps from stored stage states (sph_integrate_backward
@@ -103,7 +103,7 @@ def fwd_bwd(sc, dt, K=10, reps=3):
     from paper_2207_11328_amd import abi
     from paper_2207_11328_amd.adjoint import AdjointRollout
     run = AdjointRollout(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, steps=K, dt=dt, rebuild_every=K,
-                         checkpoint_every=K)
+                         checkpoint_every=K, brick=brick, use_bricks=use_bricks)
     n = run.n
     g = torch.Generator(device=run.sim.device).manual_seed(0)
     seed_p = torch.randn((n, 4), device=run.sim.device, generator=g)
@@ -141,8 +141,9 @@ def fwd_bwd(sc, dt, K=10, reps=3):
         torch.cuda.synchronize()
         t_e2e.append(time.perf_counter() - t0)
     tf, tb, te = min(t_f), min(t_b), min(t_e2e)
-    return {"block_steps": K, "fwd_ms": tf * 1e3, "bwd_ms": tb * 1e3, "fwd_bwd_ratio": (tf + tb) / tf,
-            "fwd_bwd_ratio_with_recompute": te / tf, "fwd_bwd_steps_per_s": K / (tf + tb)}
+    return {"workload": sc.name, "particles": sc.n, "block_steps": K, "fwd_ms": tf * 1e3, "bwd_ms": tb * 1e3,
+            "fwd_bwd_ratio": (tf + tb) / tf, "fwd_bwd_ratio_with_recompute": te / tf,
+            "fwd_bwd_steps_per_s": K / (tf + tb)}
 
 
 def batched(units=5, warm_units=1):
@@ -150,11 +151,12 @@ def batched(units=5, warm_units=1):
     aspect 0.3-2, alpha 0.005-0.05) stacked in one grid, advanced by replays
     of a HIP graph holding one rebuild unit (10 steps, adaptive dt)."""
     import torch
-    from paper_2207_11328_amd.sim import Simulation
+    from paper_2207_11328_amd import tune
     from workloads import scenes as S
     tanks = S.batched_tanks()
     st, alpha, _, _ = S.stack_scenes(tanks)
-    sim = Simulation(st.grid, st.params, st.cell, st.pos, st.vel, st.info, cell_alpha=alpha, device="cuda:0")
+    sim, choice = tune.tuned_simulation(st.grid, st.params, st.cell, st.pos, st.vel, st.info, cell_alpha=alpha,
+                                        device="cuda:0")
     sim.capture_unit()
     sim.replay_units(warm_units)
     torch.cuda.synchronize()
@@ -166,7 +168,9 @@ def batched(units=5, warm_units=1):
     steps = units * sim.rebuild_every
     return {"scenes": len(tanks), "particles": st.n, "fluid": st.n_fluid, "steps": steps,
             "ms_per_step": t / steps * 1e3, "particle_steps_per_s": st.n * steps / t,
-            "fluid_particle_steps_per_s": st.n_fluid * steps / t, "graph_units": units}
+            "fluid_particle_steps_per_s": st.n_fluid * steps / t, "graph_units": units,
+            "tuned": {"brick": list(choice["brick"]), "bricks": choice["bricks"],
+                      "per_step_ms": {k: v * 1e3 for k, v in choice["per_step_s"].items()}}}
 
 
 def main():
@@ -179,14 +183,17 @@ def main():
               "cells with halo exchange, which is not implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
+    from paper_2207_11328_amd import tune
     from paper_2207_11328_amd.sim import Simulation
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     sc = make_scene(args.workload)
     K, W = args.steps, args.warmup
+    choice = tune.autotune(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0")
 
     def new_sim():
-        return Simulation(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0")
+        return Simulation(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0",
+                          brick=choice["brick"], use_bricks=choice["bricks"])
 
     sim = new_sim()
     for _ in range(W):
@@ -256,8 +263,11 @@ def main():
     t_forces = float(np.sum(t_forces_events))
     t_forces_avg = t_forces / calls
     # algorithmic bytes of one sph_forces launch: pos, vel (16 B each), count
-    # (4 B), the listed entries (4 B each) and the float4 output per particle
-    bytes_per_launch = n * (16 + 16 + 4 + 16) + 4 * (listed / calls)
+    # (4 B) and the float4 output per particle, and the listed entries (2 B
+    # each in the brick-local lists the LDS kernel reads, 4 B in the global
+    # lists of the gather kernel)
+    entry_bytes = 2 if choice["bricks"] else 4
+    bytes_per_launch = n * (16 + 16 + 4 + 16) + entry_bytes * (listed / calls)
     achieved_gbs = bytes_per_launch / t_forces_avg / 1e9
     ms_per_step = t_total / K * 1e3
     value = inter / t_total
@@ -278,7 +288,9 @@ def main():
             "workload": "dam_break_%s" % ("1m" if args.workload == "dam_break_1m" else args.workload),
             "particles": n, "fluid": sc.n_fluid, "boundary": sc.n_boundary,
             "dp": sc.params.dp, "h_over_dp": 1.3, "max_neibs": sim.max_neibs, "rebuild_every": sim.rebuild_every,
+            "brick": list(choice["brick"]), "kernel": "lds_bricks" if choice["bricks"] else "gather",
         },
+        "tuning": {"cached": choice["cached"], "per_step_ms": {k: v * 1e3 for k, v in choice["per_step_s"].items()}},
         "forces_interactions_per_s": inter / t_forces,
         "forces_ms_avg": t_forces_avg * 1e3,
         "interactions_per_forces_call": inter / calls,
@@ -292,7 +304,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved_gbs / HBM_PEAK_GBS,
             "traffic": None,
-            "kernel": "k_forces (sph_forces)",
+            "kernel": "k_forces_brick (sph_forces)" if choice["bricks"] else "k_forces (sph_forces)",
             "bytes_per_launch": bytes_per_launch,
         },
     }
@@ -301,7 +313,19 @@ def main():
     if not args.no_fwd_bwd:
         dt_now = float(sim.d_dt.item())
         del rep
-        out["adjoint"] = fwd_bwd(sc, dt_now)
+        out["adjoint"] = fwd_bwd(sc, dt_now, brick=choice["brick"], use_bricks=choice["bricks"])
+        # the differentiable dam break of ~64k fluid particles (the configuration
+        # the fwd+bwd cost ratio is quoted on), at its own step-0 dt
+        sc64 = make_scene("dam_break_64k")
+        c64 = tune.autotune(sc64.grid, sc64.params, sc64.cell, sc64.pos, sc64.vel, sc64.info, device="cuda:0")
+        s64 = Simulation(sc64.grid, sc64.params, sc64.cell, sc64.pos, sc64.vel, sc64.info, device="cuda:0",
+                         brick=c64["brick"], use_bricks=c64["bricks"])
+        s64.build()
+        s64.forces()
+        s64.step_dt()
+        dt64 = float(s64.d_dt.item())
+        del s64
+        out["adjoint_64k"] = fwd_bwd(sc64, dt64, brick=c64["brick"], use_bricks=c64["bricks"])
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
     print(json.dumps(out), flush=True)

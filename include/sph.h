@@ -94,7 +94,10 @@ enum {
  * and give each region its own artificial-viscosity coefficient through
  * cell_alpha (device float[n_cells], indexed by cell - cell_base; NULL means
  * params->alpha everywhere; the coefficient of a pair is that of the central
- * particle's cell, equal for both members within one scene). */
+ * particle's cell, equal for both members within one scene).
+ * brick: cells per brick along x, y, z of the LDS kernels (list build,
+ * sph_forces, sph_forces_backward), one of sph_brick_shapes; {0, 0, 0} is
+ * the default shape.  Lists built with one shape are read with the same. */
 typedef struct {
     double origin[3];
     float cell_size[3];
@@ -102,6 +105,7 @@ typedef struct {
     uint32_t periodic;
     int32_t cell_base;
     const float *cell_alpha;
+    int32_t brick[3];
 } sph_grid;
 
 /* Physical and numerical parameters.
@@ -150,10 +154,12 @@ size_t sph_neib_list_entries(int32_t capacity, int32_t max_neibs);
  * particles: ceil(capacity / 64) * 64 * 8 * ceil(max_neibs / 8). */
 size_t sph_neib_brick_entries(int32_t capacity, int32_t max_neibs);
 
-/* Cells per brick along x, y, z of the brick-local lists (shape[3], host
- * memory).  Bricks tile the grid from cell 0 along each axis; a workgroup of
- * the list build and of sph_forces owns one brick. */
-void sph_brick_shape(int32_t *shape);
+/* Brick shapes the LDS kernels support: writes up to max_shapes triples
+ * (cells along x, y, z; host memory shapes[3 * max_shapes], may be NULL) and
+ * returns how many there are.  The first is the default.  Bricks tile the
+ * grid from cell 0 along each axis; a workgroup of the list build and of
+ * the derivative kernels owns one brick. */
+int32_t sph_brick_shapes(int32_t *shapes, int32_t max_shapes);
 
 /* Bytes of device workspace sph_build_neighbors needs. */
 size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells);
@@ -184,7 +190,7 @@ size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells);
  *      G = ceil(max_neibs / 8) (groups of 8 entries, one 16-byte load per
  *      particle and group), and holds the neighbour's position in the staging
  *      order of the brick
- *      (sph_brick_shape) that holds i; staging order: the cells of the brick
+ *      (grid->brick) that holds i; staging order: the cells of the brick
  *      and its one-cell halo, x fastest, then z, then y, periodic axes
  *      wrapped, cells outside a closed axis empty, then particles of a cell
  *      in sorted order;
@@ -194,7 +200,7 @@ size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells);
  * counted in SPH_STATUS_OVERFLOW; the lists are then unusable for physics.
  * workspace: device buffer of at least sph_build_workspace_bytes bytes.
  * Errors: SPH_ERR_ARG for null pointers, n > capacity, capacity > 2^26,
- * max_neibs outside [1, 65535], bad grid; SPH_ERR_WORKSPACE. */
+ * max_neibs outside [1, 65535], bad grid or brick shape; SPH_ERR_WORKSPACE. */
 sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
                                sph_particles *parts, uint32_t *neibs, uint32_t *neib_count,
                                int32_t max_neibs, int32_t *cell_start, int32_t *cell_end,

@@ -24,7 +24,7 @@ MAX_CAPACITY = 1 << NEIB_INDEX_BITS
 
 EXPORTS = [
     "sph_status_string", "sph_abi_version", "sph_neib_list_entries", "sph_build_workspace_bytes",
-    "sph_brick_shape", "sph_neib_brick_entries", "sph_build_neighbors", "sph_forces", "sph_forces_workspace_bytes", "sph_integrate",
+    "sph_brick_shapes", "sph_neib_brick_entries", "sph_build_neighbors", "sph_forces", "sph_forces_workspace_bytes", "sph_integrate",
     "sph_dt_workspace_bytes", "sph_step_dt", "sph_count_interactions", "sph_integrate_backward",
     "sph_forces_backward_workspace_bytes", "sph_forces_backward", "sph_unpermute",
     "sph_diagnostics_workspace_bytes", "sph_reduce_diagnostics",
@@ -33,7 +33,8 @@ EXPORTS = [
 
 class SphGrid(C.Structure):
     _fields_ = [("origin", C.c_double * 3), ("cell_size", C.c_float * 3), ("ncell", C.c_int32 * 3),
-                ("periodic", C.c_uint32), ("cell_base", C.c_int32), ("cell_alpha", C.c_void_p)]
+                ("periodic", C.c_uint32), ("cell_base", C.c_int32), ("cell_alpha", C.c_void_p),
+                ("brick", C.c_int32 * 3)]
 
 
 class SphParams(C.Structure):
@@ -70,8 +71,8 @@ def _load():
     L.sph_build_workspace_bytes.restype = C.c_size_t
     L.sph_neib_brick_entries.argtypes = [i32, i32]
     L.sph_neib_brick_entries.restype = C.c_size_t
-    L.sph_brick_shape.argtypes = [P]
-    L.sph_brick_shape.restype = None
+    L.sph_brick_shapes.argtypes = [P, i32]
+    L.sph_brick_shapes.restype = i32
     L.sph_build_neighbors.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, P, C.c_size_t, P]
     L.sph_build_neighbors.restype = st
     L.sph_forces.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, C.c_size_t, P]
@@ -119,10 +120,13 @@ def stream_ptr(stream=None) -> int | None:
     return s.cuda_stream
 
 
-def grid_struct(grid, cell_alpha=None) -> SphGrid:
-    """cell_alpha: optional device float tensor [n_cells] (per-cell alpha)."""
+def grid_struct(grid, cell_alpha=None, brick=None) -> SphGrid:
+    """cell_alpha: optional device float tensor [n_cells] (per-cell alpha);
+    brick: (bx, by, bz) of the LDS kernels, None for the default."""
     g = SphGrid()
     g.cell_alpha = ptr(cell_alpha)
+    for d in range(3):
+        g.brick[d] = 0 if brick is None else int(brick[d])
     for d in range(3):
         g.origin[d] = float(grid.origin[d])
         g.cell_size[d] = float(grid.cell_size[d])
@@ -173,10 +177,12 @@ def sph_neib_brick_entries(capacity: int, max_neibs: int) -> int:
     return int(lib.sph_neib_brick_entries(int(capacity), int(max_neibs)))
 
 
-def sph_brick_shape():
-    shape = (C.c_int32 * 3)()
-    lib.sph_brick_shape(shape)
-    return tuple(int(v) for v in shape)
+def sph_brick_shapes():
+    """Supported brick shapes [(bx, by, bz), ...]; the first is the default."""
+    k = int(lib.sph_brick_shapes(None, 0))
+    buf = (C.c_int32 * (3 * k))()
+    lib.sph_brick_shapes(buf, k)
+    return [tuple(int(buf[3 * i + d]) for d in range(3)) for i in range(k)]
 
 
 def sph_build_neighbors(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count,

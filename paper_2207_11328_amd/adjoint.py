@@ -30,7 +30,8 @@ from .sim import Simulation
 
 class AdjointRollout:
     def __init__(self, grid, params, cell, pos, vel, info, steps: int, dt: float, rebuild_every: int = 10,
-                 checkpoint_every: int = 20, max_neibs: int = 128, device: str = "cuda"):
+                 checkpoint_every: int = 20, max_neibs: int = 128, device: str = "cuda", brick=None,
+                 use_bricks: bool = True):
         if checkpoint_every % rebuild_every != 0:
             raise ValueError("checkpoint_every must be a multiple of rebuild_every")
         self.steps = int(steps)
@@ -38,7 +39,7 @@ class AdjointRollout:
         self.C = int(checkpoint_every)
         self.dt = float(dt)
         self.sim = Simulation(grid, params, cell, pos, vel, info, max_neibs=max_neibs, rebuild_every=rebuild_every,
-                              device=device, dt_fixed=dt)
+                              device=device, dt_fixed=dt, brick=brick, use_bricks=use_bricks)
         s = self.sim
         n, cap, dev = s.n, s.capacity, s.device
 
@@ -112,7 +113,8 @@ class AdjointRollout:
         pn = abi.particles_struct(s.n, s.cell, pos_n, vel_n, s.info)
         ps = abi.particles_struct(s.n, s.cell, pos_s, vel_s, s.info)
         abi.sph_integrate_backward(s.p, 1, s.d_dt, pn, self.gpos, self.gvel, self.gpos_s, self.gvel_s, self.gforce)
-        bk = dict(cell_start=s.cell_start, cell_end=s.cell_end, neibs_brick=s.neibs_brick)
+        cs, ce, nb = s.brick_args()
+        bk = dict(cell_start=cs, cell_end=ce, neibs_brick=nb)
         abi.sph_forces_backward(s.g, s.p, ps, s.neibs, s.neib_count, s.max_neibs, self.gforce, self.gpos_s,
                                 self.gvel_s, self.grad_params, True, self.ws_back, **bk)
         abi.sph_integrate_backward(s.p, 0, s.d_dt, pn, self.gpos, self.gvel, self.gpos_s, self.gvel_s, self.gforce)

@@ -27,7 +27,7 @@ def hipcc() -> str:
 
 def flags() -> list:
     return [
-        "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
+        "--offload-arch=" + ARCH, "-O3", "-std=c++20", "-fPIC",
         # packed FP32 instructions are disabled for correctness on this target
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I" + INCLUDE, "-I" + CSRC,

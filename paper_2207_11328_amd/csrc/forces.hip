@@ -293,7 +293,7 @@ __device__ __forceinline__ void brick_pairs_lds(PairAcc &A, const uint4 *lg, int
     }
 }
 
-template <int VISC, int NT, int CAP>
+template <int VISC, int BX, int BY, int BZ, int NT, int CAP>
 __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__restrict__ pos,
                                                      const float4 *__restrict__ vel,
                                                      const float2 *__restrict__ aux,
@@ -305,7 +305,6 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
                                                      const int32_t *__restrict__ active,
                                                      float4 *__restrict__ out, ForceConst C, BrickGrid G)
 {
-    constexpr int BX = kBrickX, BY = kBrickY, BZ = kBrickZ;
     using St = Staging<BX, BY, BZ>;
     constexpr int SX = BX + 2, SY = BY + 2, SZ = BZ + 2;
     constexpr int S = SX * SY * SZ;  // staged cells
@@ -517,37 +516,30 @@ extern "C" size_t sph_forces_workspace_bytes(int32_t capacity, int32_t n_cells)
     return aux_bytes(capacity > 0 ? capacity : 1) + sizeof(int32_t) * ((size_t)n_cells + 1) + 256;
 }
 
-// LDS kernel: bricks of 3 x 4 x 3 cells (up to about 970 particles at the
-// h = 1.3 dp, r_s = 2.86 dp lattice density, 16 waves), halo of 5 x 6 x 5
-// cells (up to about 3800 particles; 4000 fit in 160 KB of LDS at 40 bytes
-// each).  Measured on the 1.62M dam break: 3 x 4 x 3 277 us, 3 x 3 x 3
-// 357 us, 4 x 3 x 3 425 us (1% of its bricks overflow the LDS there).
-#ifndef SPH_BRICK_CAP
-#define SPH_BRICK_THREADS 1024
-#define SPH_BRICK_CAP 4000
-#endif
-constexpr int kBrickThreads = SPH_BRICK_THREADS;
-constexpr int kBrickCap = SPH_BRICK_CAP;
+// LDS capacity (staged particles, 40 bytes each) per brick shape: the halo
+// of a brick at the h = 1.3 dp, r_s = 2.86 dp lattice density holds up to
+// about 27 particles per staged cell (3 x 4 x 3: 150 cells, 3825 at most in
+// the 1.62M dam break; 3 x 3 x 3: 125 cells, 3375; 3 x 2 x 3: 100 cells).
+// Measured on the 1.62M dam break (one workgroup per CU in every case):
+// 3 x 4 x 3 277 us, 3 x 3 x 3 357 us, 4 x 3 x 3 425 us (1% of its bricks
+// overflow the LDS there).
+constexpr int brick_cap(int BX, int BY, int BZ) { return BX * BY * BZ >= 36 ? 4000 : (BX * BY * BZ >= 27 ? 3400 : 2750); }
 
 template <int VISC>
-void launch_brick(const sph_grid *grid, int n, const float4 *pos, const float4 *vel, const float2 *aux,
+void launch_brick(const sph_grid *grid, int shape, int n, const float4 *pos, const float4 *vel, const float2 *aux,
                   const uint32_t *neibs, const uint16_t *neibs_brick, const uint32_t *count,
                   const int32_t *cell_start, const int32_t *cell_end, int32_t *active, float4 *out,
                   const ForceConst &C, hipStream_t s)
 {
-    BrickGrid G;
-    G.nx = grid->ncell[0];
-    G.ny = grid->ncell[1];
-    G.nz = grid->ncell[2];
-    G.periodic = grid->periodic;
-    G.nbx = (G.nx + kBrickX - 1) / kBrickX;
-    G.nby = (G.ny + kBrickY - 1) / kBrickY;
-    G.nbz = (G.nz + kBrickZ - 1) / kBrickZ;
-    const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
-    k_zero_one<int32_t><<<1, 1, 0, s>>>(active);
-    k_active_bricks<kBrickX, kBrickY, kBrickZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(cell_start, cell_end, G, active);
-    k_forces_brick<VISC, kBrickThreads, kBrickCap><<<blocks, kBrickThreads, 0, s>>>(
-        n, pos, vel, aux, neibs, neibs_brick, count, cell_start, cell_end, active, out, C, G);
+    with_shape(shape, [&]<int BX, int BY, int BZ>() {
+        const BrickGrid G = brick_grid<BX, BY, BZ>(grid->ncell, grid->periodic);
+        const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
+        constexpr int NT = brick_threads(BX * BY * BZ);
+        k_zero_one<int32_t><<<1, 1, 0, s>>>(active);
+        k_active_bricks<BX, BY, BZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(cell_start, cell_end, G, active);
+        k_forces_brick<VISC, BX, BY, BZ, NT, brick_cap(BX, BY, BZ)><<<blocks, NT, 0, s>>>(
+            n, pos, vel, aux, neibs, neibs_brick, count, cell_start, cell_end, active, out, C, G);
+    });
 }
 
 extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
@@ -560,6 +552,8 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
     if (parts->n > 0 && !forces) return SPH_ERR_ARG;
     ForceConst C;
     if (!make_const(grid, params, max_neibs, C)) return SPH_ERR_ARG;
+    const int shape = brick_shape_index(grid->brick);
+    if (shape < 0) return SPH_ERR_ARG;
     const int64_t n_cells = (int64_t)grid->ncell[0] * grid->ncell[1] * grid->ncell[2];
     if (n_cells <= 0 || n_cells > INT32_MAX - 1) return SPH_ERR_ARG;
     if (!workspace || workspace_bytes < sph_forces_workspace_bytes(parts->capacity, (int32_t)n_cells))
@@ -580,11 +574,11 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
         // kernel (it writes the derivatives of every particle that lies in a
         // cell; particles dropped by the build have none)
         if (params->visc_model == 0)
-            launch_brick<0>(grid, n, pos, vel, aux, neibs, neibs_brick, neib_count, cell_start, cell_end, active,
-                            out, C, s);
+            launch_brick<0>(grid, shape, n, pos, vel, aux, neibs, neibs_brick, neib_count, cell_start, cell_end,
+                            active, out, C, s);
         else
-            launch_brick<1>(grid, n, pos, vel, aux, neibs, neibs_brick, neib_count, cell_start, cell_end, active,
-                            out, C, s);
+            launch_brick<1>(grid, shape, n, pos, vel, aux, neibs, neibs_brick, neib_count, cell_start, cell_end,
+                            active, out, C, s);
         SPH_CHECK_LAUNCH();
         // dropped particles (cell < 0) are in no cell: zero their derivatives
         k_zero_dropped<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, parts->cell, out);

@@ -348,7 +348,7 @@ __device__ __forceinline__ void add_partner(BackAcc &A)
     A.gnu += __shfl_xor(A.gnu, 1);
 }
 
-template <int VISC, int NT, int CAP>
+template <int VISC, int BX, int BY, int BZ, int NT, int CAP>
 __global__ __launch_bounds__(NT) void k_forces_backward_brick(
     int n, const float4 *__restrict__ pos, const float4 *__restrict__ vel, const float4 *__restrict__ aux,
     const float4 *__restrict__ gforce, const uint32_t *__restrict__ neibs, const uint16_t *__restrict__ neibs_brick,
@@ -356,13 +356,11 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
     const int32_t *__restrict__ active, float4 *__restrict__ gpos, float4 *__restrict__ gvel,
     double *__restrict__ partial, int accumulate, BackConst C, BrickGrid G)
 {
-    constexpr int BX = kBrickX, BY = kBrickY, BZ = kBrickZ;
     using St = Staging<BX, BY, BZ>;
     constexpr int SX = St::SX, SZ = St::SZ, S = St::S, NI = St::NI;
     constexpr int ROW = SX * SZ;       // staged cells per y row
     constexpr int IROW = BX * BZ;      // inner cells per y row
-    constexpr int HALF = BY / 2;       // inner y rows per half
-    static_assert(BY % 2 == 0, "halves of equal height");
+    constexpr int HALF = BY / 2;       // inner y rows of the lower half
     static_assert(S <= NT, "one thread per staged cell");
     __shared__ float4 sP[CAP];
     __shared__ float4 sV[CAP];
@@ -420,18 +418,18 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
     const uint32_t jmax = (uint32_t)(n - 1);
     double pa = 0.0, pc = 0.0, pn = 0.0;
     for (int half = 0; half < 2; ++half) {
-        // staged rows [half HALF, half HALF + HALF + 2), inner rows [half HALF, (half + 1) HALF)
-        const int s_lo = cBase[half * HALF * ROW];
-        const int s_hi = cBase[(half * HALF + HALF + 2) * ROW];
-        const int q_lo = iBase[half * HALF * IROW];
-        const int q_hi = iBase[(half + 1) * HALF * IROW];
+        // inner rows [y0, y1), staged rows [y0, y1 + 2)
+        const int y0 = half ? HALF : 0, y1 = half ? BY : HALF;
+        const int s_lo = cBase[y0 * ROW];
+        const int s_hi = cBase[(y1 + 2) * ROW];
+        const int q_lo = iBase[y0 * IROW];
+        const int q_hi = iBase[y1 * IROW];
         const int span = s_hi - s_lo;
         const bool use_lds = span <= CAP;
-        if (q_hi == q_lo) continue;  // uniform
-        if (use_lds) {
+        if (use_lds && q_hi > q_lo) {
             // stage the half: one wave per row of SX cells (contiguous in LDS)
             const int wave = tid / kWave, lane = tid % kWave;
-            for (int r = half * HALF * SZ + wave; r < (half * HALF + HALF + 2) * SZ; r += NT / kWave) {
+            for (int r = y0 * SZ + wave; r < (y1 + 2) * SZ; r += NT / kWave) {
                 const int t0 = r * SX;
                 const int b0 = cBase[t0], b1 = cBase[t0 + SX];
                 int e[SX - 1];
@@ -457,6 +455,7 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
         __syncthreads();
         // two lanes per central particle of the half (lane pairs 2q', 2q'+1)
         const int h = tid & 1;
+        if (q_hi == q_lo) continue;  // uniform
         for (int q0 = q_lo; q0 < q_hi; q0 += NT / 2) {
             const int q = q0 + tid / 2;
             const bool act = q < q_hi;
@@ -589,28 +588,25 @@ __global__ __launch_bounds__(kThreads) void k_zero_dropped_adjoint(int n, const 
 }
 
 template <int VISC>
-void launch_backward_brick(const sph_grid *grid, int n, const float4 *pos, const float4 *vel, const float4 *aux,
-                           const float4 *gforce, const uint32_t *neibs, const uint16_t *neibs_brick,
-                           const uint32_t *count, const int32_t *cell_start, const int32_t *cell_end,
-                           int32_t *active, float4 *gpos, float4 *gvel, double *partial, int accumulate,
-                           const BackConst &C, hipStream_t s)
+void launch_backward_brick(const sph_grid *grid, int shape, int n, const float4 *pos, const float4 *vel,
+                           const float4 *aux, const float4 *gforce, const uint32_t *neibs,
+                           const uint16_t *neibs_brick, const uint32_t *count, const int32_t *cell_start,
+                           const int32_t *cell_end, int32_t *active, float4 *gpos, float4 *gvel, double *partial,
+                           int accumulate, const BackConst &C, hipStream_t s, int &n_bricks)
 {
-    BrickGrid G;
-    G.nx = grid->ncell[0];
-    G.ny = grid->ncell[1];
-    G.nz = grid->ncell[2];
-    G.periodic = grid->periodic;
-    G.nbx = (G.nx + kBrickX - 1) / kBrickX;
-    G.nby = (G.ny + kBrickY - 1) / kBrickY;
-    G.nbz = (G.nz + kBrickZ - 1) / kBrickZ;
-    const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
-    k_zero_i32<<<1, 1, 0, s>>>(active);
-    k_zero_f64<<<sph_blocks(3 * blocks, kThreads) < 1024u ? sph_blocks(3 * blocks, kThreads) : 1024u, kThreads, 0,
-                 s>>>(3 * (int)blocks, partial);
-    k_active_bricks<kBrickX, kBrickY, kBrickZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(cell_start, cell_end, G, active);
-    k_forces_backward_brick<VISC, kBackBrickThreads, kBackBrickCap><<<blocks, kBackBrickThreads, 0, s>>>(
-        n, pos, vel, aux, gforce, neibs, neibs_brick, count, cell_start, cell_end, active, gpos, gvel, partial,
-        accumulate, C, G);
+    with_shape(shape, [&]<int BX, int BY, int BZ>() {
+        const BrickGrid G = brick_grid<BX, BY, BZ>(grid->ncell, grid->periodic);
+        const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
+        n_bricks = (int)blocks;
+        k_zero_i32<<<1, 1, 0, s>>>(active);
+        k_zero_f64<<<sph_blocks(3 * blocks, kThreads) < 1024u ? sph_blocks(3 * blocks, kThreads) : 1024u, kThreads,
+                     0, s>>>(3 * (int)blocks, partial);
+        k_active_bricks<BX, BY, BZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(cell_start, cell_end, G, active);
+        k_forces_backward_brick<VISC, BX, BY, BZ, kBackBrickThreads, kBackBrickCap><<<blocks, kBackBrickThreads, 0,
+                                                                                      s>>>(
+            n, pos, vel, aux, gforce, neibs, neibs_brick, count, cell_start, cell_end, active, gpos, gvel, partial,
+            accumulate, C, G);
+    });
 }
 
 }  // namespace
@@ -640,6 +636,8 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
     const int64_t n_cells = (int64_t)grid->ncell[0] * grid->ncell[1] * grid->ncell[2];
     if (n_cells <= 0 || n_cells > INT32_MAX - 2) return SPH_ERR_ARG;
     const bool bricks = cell_start && cell_end && neibs_brick;
+    const int shape = brick_shape_index(grid->brick);
+    if (shape < 0) return SPH_ERR_ARG;
     if (bricks && parts->n > 0 && !parts->cell) return SPH_ERR_ARG;
     if (!workspace || workspace_bytes < sph_forces_backward_workspace_bytes(parts->capacity, (int32_t)n_cells))
         return SPH_ERR_WORKSPACE;
@@ -672,19 +670,18 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
     const int nblocks = n > 0 ? (int)sph_blocks(n, kThreads) : 0;
     if (n > 0 && bricks) {
         // cell ranges and brick-local lists of the last build: LDS bricks
-        const int nb = ((grid->ncell[0] + kBrickX - 1) / kBrickX) * ((grid->ncell[1] + kBrickY - 1) / kBrickY) *
-                       ((grid->ncell[2] + kBrickZ - 1) / kBrickZ);
+        int nb = 0;
         k_eos_grad<<<nblocks, kThreads, 0, s>>>(n, (const float4 *)parts->vel, aux, C);
         if (p->visc_model == 0)
-            launch_backward_brick<0>(grid, n, (const float4 *)parts->pos, (const float4 *)parts->vel, aux,
+            launch_backward_brick<0>(grid, shape, n, (const float4 *)parts->pos, (const float4 *)parts->vel, aux,
                                      (const float4 *)grad_forces, neibs, neibs_brick, neib_count, cell_start,
                                      cell_end, active, (float4 *)grad_pos, (float4 *)grad_vel, bpartial, accumulate,
-                                     C, s);
+                                     C, s, nb);
         else
-            launch_backward_brick<1>(grid, n, (const float4 *)parts->pos, (const float4 *)parts->vel, aux,
+            launch_backward_brick<1>(grid, shape, n, (const float4 *)parts->pos, (const float4 *)parts->vel, aux,
                                      (const float4 *)grad_forces, neibs, neibs_brick, neib_count, cell_start,
                                      cell_end, active, (float4 *)grad_pos, (float4 *)grad_vel, bpartial, accumulate,
-                                     C, s);
+                                     C, s, nb);
         if (!accumulate)
             k_zero_dropped_adjoint<<<nblocks, kThreads, 0, s>>>(n, parts->cell, (float4 *)grad_pos,
                                                                  (float4 *)grad_vel);

@@ -494,10 +494,6 @@ __global__ __launch_bounds__(kThreads) void k_zero_dropped_counts(int n, const i
     if (i < n && cell[i] < 0) neib_count[i] = 0u;
 }
 
-#ifndef SPH_BUILD_THREADS
-#define SPH_BUILD_THREADS 1024
-#endif
-constexpr int kBuildThreads = SPH_BUILD_THREADS;
 constexpr int kBuildCap = 4800;  // 75 KB of LDS for the halo: two workgroups per CU
 
 bool grid_ok(const sph_grid *g, float r_search)
@@ -532,12 +528,12 @@ extern "C" size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells)
     return build_layout(capacity, n_cells).total;
 }
 
-extern "C" void sph_brick_shape(int32_t *shape)
+extern "C" int32_t sph_brick_shapes(int32_t *shapes, int32_t max_shapes)
 {
-    if (!shape) return;
-    shape[0] = kBrickX;
-    shape[1] = kBrickY;
-    shape[2] = kBrickZ;
+    if (shapes)
+        for (int k = 0; k < kShapes && k < max_shapes; ++k)
+            for (int d = 0; d < 3; ++d) shapes[3 * k + d] = kShapeTable[k][d];
+    return kShapes;
 }
 
 extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
@@ -552,6 +548,8 @@ extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params
     if (parts->capacity > 0 && (!parts->cell || !parts->pos || !parts->vel || !parts->info)) return SPH_ERR_ARG;
     if (max_neibs < 1 || max_neibs > 65535) return SPH_ERR_ARG;
     if (!(params->r_search > 0.0f) || !grid_ok(grid, params->r_search)) return SPH_ERR_ARG;
+    const int shape = brick_shape_index(grid->brick);
+    if (shape < 0) return SPH_ERR_ARG;
     const int n = parts->n;
     const int cap = parts->capacity;
     const int n_cells = grid->ncell[0] * grid->ncell[1] * grid->ncell[2];
@@ -604,24 +602,18 @@ extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params
                                                                t_cell, t_pos, t_vel, t_info, perm_out);
         SPH_CHECK_LAUNCH();
         const float rs2 = params->r_search * params->r_search;
-        BrickGrid G;
-        G.nx = dims.nx;
-        G.ny = dims.ny;
-        G.nz = dims.nz;
-        G.periodic = dims.periodic;
-        G.nbx = (G.nx + kBrickX - 1) / kBrickX;
-        G.nby = (G.ny + kBrickY - 1) / kBrickY;
-        G.nbz = (G.nz + kBrickZ - 1) / kBrickZ;
-        const unsigned bricks = (unsigned)G.nbx * G.nby * G.nbz;
         int32_t *active = (int32_t *)(ws + L.active);
-        k_zero_one<int32_t><<<1, 1, 0, s>>>(active);
-        // brick activity from the (exclusive-scan) cell starts: start[c + 1] is the end of cell c
-        k_active_bricks<kBrickX, kBrickY, kBrickZ><<<sph_blocks(bricks, 256), 256, 0, s>>>(
-            start, start + 1, G, active);
-        k_build_brick<kBrickX, kBrickY, kBrickZ, kBuildThreads, kBuildCap>
-            <<<bricks, kBuildThreads, 0, s>>>(n, max_neibs, t_pos, t_info, start, G, grid->cell_size[0],
-                                              grid->cell_size[1], grid->cell_size[2], rs2, active, neibs,
-                                              neibs_brick, neib_count, d_status);
+        with_shape(shape, [&]<int BX, int BY, int BZ>() {
+            const BrickGrid G = brick_grid<BX, BY, BZ>(grid->ncell, grid->periodic);
+            const unsigned bricks = (unsigned)G.nbx * G.nby * G.nbz;
+            constexpr int NT = brick_threads(BX * BY * BZ);
+            k_zero_one<int32_t><<<1, 1, 0, s>>>(active);
+            // brick activity from the (exclusive-scan) cell starts: start[c + 1] is the end of cell c
+            k_active_bricks<BX, BY, BZ><<<sph_blocks(bricks, 256), 256, 0, s>>>(start, start + 1, G, active);
+            k_build_brick<BX, BY, BZ, NT, kBuildCap><<<bricks, NT, 0, s>>>(
+                n, max_neibs, t_pos, t_info, start, G, grid->cell_size[0], grid->cell_size[1], grid->cell_size[2],
+                rs2, active, neibs, neibs_brick, neib_count, d_status);
+        });
         k_zero_dropped_counts<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, t_cell, neib_count);
         k_copy_state<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, t_cell, t_pos, t_vel, t_info, parts->cell,
                                                                    pos, vel, parts->info);

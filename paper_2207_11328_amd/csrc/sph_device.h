@@ -80,16 +80,37 @@ __device__ __forceinline__ T wave_sum(T v)
 // Cell bricks: blocks of cells processed by one workgroup with the particles
 // of the brick and of its one-cell halo staged in LDS (used by the list build
 // and by the derivative kernel).
-// Bricks of kBrickX x kBrickY x kBrickZ cells: the unit of LDS staging of the
-// list build and of the derivative kernels.  The brick-local lists written by
-// the build index the staging order of the same bricks, so both sides use
-// this shape (reported by sph_brick_shape).
-#ifndef SPH_BRICK_X
-#define SPH_BRICK_X 3
-#define SPH_BRICK_Y 4
-#define SPH_BRICK_Z 3
-#endif
-constexpr int kBrickX = SPH_BRICK_X, kBrickY = SPH_BRICK_Y, kBrickZ = SPH_BRICK_Z;
+// Bricks of cells: the unit of LDS staging of the list build and of the
+// derivative kernels.  The brick-local lists written by the build index the
+// staging order of the same bricks, so the build and its consumers take the
+// shape from the same grid description (sph_grid.brick).  Supported shapes,
+// the first being the default (zero shape):
+constexpr int kShapes = 3;
+constexpr int kShapeTable[kShapes][3] = {{3, 4, 3}, {3, 3, 3}, {3, 2, 3}};
+
+// index into kShapeTable of a grid's brick shape, -1 if unsupported
+inline int brick_shape_index(const int32_t b[3])
+{
+    if (b[0] == 0 && b[1] == 0 && b[2] == 0) return 0;
+    for (int k = 0; k < kShapes; ++k)
+        if (b[0] == kShapeTable[k][0] && b[1] == kShapeTable[k][1] && b[2] == kShapeTable[k][2]) return k;
+    return -1;
+}
+
+// Calls f.template operator()<BX, BY, BZ>() for the shape of index k.
+template <typename F>
+inline void with_shape(int k, F &&f)
+{
+    switch (k) {
+    case 1: f.template operator()<3, 3, 3>(); break;
+    case 2: f.template operator()<3, 2, 3>(); break;
+    default: f.template operator()<3, 4, 3>(); break;
+    }
+}
+
+// Threads of a workgroup for bricks of `cells` cells: one lane per central
+// particle up to 27 per cell (the densest lattice alignment), in whole waves.
+constexpr int brick_threads(int cells) { return ((27 * cells + 63) / 64) * 64 > 1024 ? 1024 : ((27 * cells + 63) / 64) * 64; }
 
 // Staging geometry of a brick of BX x BY x BZ cells: the brick and its
 // one-cell halo, SX x SY x SZ staged cells numbered x fastest, then z, then y
@@ -128,6 +149,20 @@ struct BrickGrid {
     uint32_t periodic;
     int nbx, nby, nbz;
 };
+
+template <int BX, int BY, int BZ>
+inline BrickGrid brick_grid(const int32_t ncell[3], uint32_t periodic)
+{
+    BrickGrid G;
+    G.nx = ncell[0];
+    G.ny = ncell[1];
+    G.nz = ncell[2];
+    G.periodic = periodic;
+    G.nbx = (G.nx + BX - 1) / BX;
+    G.nby = (G.ny + BY - 1) / BY;
+    G.nbz = (G.nz + BZ - 1) / BZ;
+    return G;
+}
 
 __device__ __forceinline__ bool wrap_axis(int &c, int n, uint32_t periodic)
 {

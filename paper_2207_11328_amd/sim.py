@@ -29,7 +29,8 @@ class Simulation:
     """Device state of one scene and the step sequence over the C ABI."""
 
     def __init__(self, grid, params, cell, pos, vel, info, max_neibs: int = 128, capacity: int | None = None,
-                 rebuild_every: int = 10, device: str = "cuda", dt_fixed: float | None = None, cell_alpha=None):
+                 rebuild_every: int = 10, device: str = "cuda", dt_fixed: float | None = None, cell_alpha=None,
+                 brick=None, use_bricks: bool = True):
         n = int(np.asarray(cell).shape[0])
         cap = int(capacity or n)
         if cap < n or cap > abi.MAX_CAPACITY:
@@ -79,7 +80,12 @@ class Simulation:
         self.cell_alpha = None
         if cell_alpha is not None:
             self.cell_alpha = torch.from_numpy(np.ascontiguousarray(cell_alpha, np.float32)).to(dev)
-        self.g = abi.grid_struct(grid, self.cell_alpha)
+        self.use_bricks = bool(use_bricks)
+        shapes = abi.sph_brick_shapes()
+        self.brick_shape = shapes[0] if brick is None else tuple(int(v) for v in brick)
+        if self.brick_shape not in shapes:
+            raise ValueError("brick shape %s not supported (%s)" % (self.brick_shape, shapes))
+        self.g = abi.grid_struct(grid, self.cell_alpha, self.brick_shape)
         self.p = abi.params_struct(params)
         self.parts = abi.particles_struct(n, self.cell, self.pos, self.vel, self.info)
         self.parts_star = abi.particles_struct(n, self.cell, self.pos_star, self.vel_star, self.info)
@@ -91,19 +97,36 @@ class Simulation:
                                 self.cell_start, self.cell_end, self.status, self.ws_build, stream, perm_out,
                                 self.neibs_brick)
 
+    def set_brick(self, brick):
+        """Change the brick shape of the LDS kernels; the lists must be
+        rebuilt before the next derivative call."""
+        shapes = abi.sph_brick_shapes()
+        shape = tuple(int(v) for v in brick)
+        if shape not in shapes:
+            raise ValueError("brick shape %s not supported (%s)" % (shape, shapes))
+        self.brick_shape = shape
+        for d in range(3):
+            self.g.brick[d] = shape[d]
+
     def set_params(self, **kw):
         """Change scalar parameters (e.g. alpha, c0) between calls."""
         for k, v in kw.items():
             setattr(self.p, k, float(v))
 
-    def forces(self, star: bool = False, stream=None, bricks: bool = True):
+    def brick_args(self, bricks=None):
+        """(cell_start, cell_end, neibs_brick) for the LDS brick kernels, or
+        Nones for the per-particle gather kernels."""
+        use = self.use_bricks if bricks is None else bricks
+        return (self.cell_start, self.cell_end, self.neibs_brick) if use else (None, None, None)
+
+    def forces(self, star: bool = False, stream=None, bricks: bool | None = None):
         """Derivatives of the state n (or *).  bricks: the LDS cell-brick
         kernel (uses the cell ranges and brick-local lists of the last
-        build); False: the per-particle global-gather kernel.  The two agree
-        to rounding."""
+        build); False: the per-particle global-gather kernel; None: the
+        simulation's choice (use_bricks).  The two agree to rounding."""
         parts = self.parts_star if star else self.parts
         out = self.forces_star if star else self.forces_n
-        cs, ce, nb = (self.cell_start, self.cell_end, self.neibs_brick) if bricks else (None, None, None)
+        cs, ce, nb = self.brick_args(bricks)
         abi.sph_forces(self.g, self.p, parts, self.neibs, self.neib_count, self.max_neibs, out, self.ws_forces,
                        stream, cs, ce, nb)
         return out

@@ -205,8 +205,7 @@ def expected_brick_lists(sim, grid, brick=None):
     fluid and boundary interleaved.  Returns
     ([n, M] int64 with -1 past each list, n_total [n])."""
     if brick is None:
-        from paper_2207_11328_amd import abi
-        brick = abi.sph_brick_shape()
+        brick = sim.brick_shape
     BX, BY, BZ = brick
     n, M = sim.n, sim.max_neibs
     nb, cnt = sim.lists_host()

@@ -70,9 +70,10 @@ def test_host_only_entry_points(abi):
     assert abi.sph_dt_workspace_bytes() > 0
 
 
-def test_brick_shape(abi):
-    shape = abi.sph_brick_shape()
-    assert len(shape) == 3 and all(1 <= v <= 8 for v in shape), shape
+def test_brick_shapes(abi):
+    shapes = abi.sph_brick_shapes()
+    assert len(shapes) >= 1 and len(set(shapes)) == len(shapes), shapes
+    assert all(len(s) == 3 and all(1 <= v <= 8 for v in s) for s in shapes), shapes
 
 
 def test_argument_errors_return_before_any_launch(abi):

@@ -53,15 +53,21 @@ SCENES = {
 }
 
 
-@pytest.mark.parametrize("bricks", [True, False], ids=["bricks", "gather"])
-@pytest.mark.parametrize("name", list(SCENES))
-def test_forces_backward_parity(name, bricks):
-    """Both forms of the adjoint (LDS bricks in two halves, per-particle
-    gather) against the FP64 oracle reverse."""
+CASES = [(name, "bricks", None) for name in SCENES] + [(name, "gather", None) for name in SCENES] + \
+    [("cloud_laminar_periodic", "bricks", (3, 3, 3)), ("cloud_av", "bricks", (3, 2, 3))]
+
+
+@pytest.mark.parametrize("name,form,shape", CASES,
+                         ids=["%s-%s%s" % (c[0], c[1], "" if c[2] is None else "-" + "x".join(map(str, c[2])))
+                              for c in CASES])
+def test_forces_backward_parity(name, form, shape):
+    """Both forms of the adjoint (LDS bricks in two halves along y, also for
+    odd brick heights; per-particle gather) against the FP64 oracle reverse."""
+    bricks = form == "bricks"
     make, M = SCENES[name]
     sc = make()
-    log("case %s n=%d bricks=%s" % (name, sc.n, bricks))
-    sim = make_sim(sc, max_neibs=M)
+    log("case %s n=%d bricks=%s shape=%s" % (name, sc.n, bricks, shape))
+    sim = make_sim(sc, max_neibs=M, brick=shape)
     sim.build()
     torch_sync()
     ob = compare_build(sc, sim, max_neibs=M)

@@ -302,3 +302,46 @@ def test_brick_kernel_matches_gather_kernel(name):
     rel = np.where(scale > 0, d / np.where(scale > 0, scale, 1.0), d)
     log("%s brick - gather: max |d|/S = %.3e" % (name, float(rel.max(initial=0.0))))
     assert float(rel.max(initial=0.0)) <= FORCE_TOL, name
+
+
+@pytest.mark.parametrize("shape", [(3, 4, 3), (3, 3, 3), (3, 2, 3)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("name", ["still_water", "cloud_periodic_xyz", "channel_small"])
+def test_brick_shapes(name, shape):
+    """Every supported brick shape: brick-local lists bit-exact against the
+    documented layout, derivatives within the oracle tolerance."""
+    from paper_2207_11328_amd import abi
+    assert shape in abi.sph_brick_shapes()
+    sc = SCENES[name]()
+    M = _slots(name)
+    log("case %s shape %s" % (name, shape))
+    sim = make_sim(sc, max_neibs=M, brick=shape)
+    sim.build()
+    a = sim.forces(bricks=True)
+    torch_sync()
+    ob = compare_build(sc, sim, max_neibs=M)
+    exp, _ = expected_brick_lists(sim, sc.grid)
+    assert np.array_equal(gpu_brick_lists(sim), exp), "brick-local lists"
+    st, (acc, drho, sa, sd, ni) = oracle_forces_of(sc, ob)
+    check_forces(a[: sc.n].cpu().numpy(), acc, drho, sa, sd, label="%s %s" % (name, shape))
+
+
+def test_autotune_choice_and_cache(tmp_path, monkeypatch):
+    """The autotuner times every shape and the gather kernel, caches its
+    choice, and a simulation built from the choice matches the oracle."""
+    from paper_2207_11328_amd import tune
+    monkeypatch.setenv(tune.CACHE_ENV, str(tmp_path / "tune.json"))
+    sc = SCENES["still_water"]()
+    c1 = tune.autotune(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, reps=3)
+    log("autotune: %s" % c1)
+    assert not c1["cached"] and set(c1["per_step_s"]) == {"3x4x3", "3x3x3", "3x2x3", "gather"}
+    assert all(v > 0 for v in c1["per_step_s"].values())
+    c2 = tune.autotune(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, reps=3)
+    assert c2["cached"] and c2["brick"] == c1["brick"] and c2["bricks"] == c1["bricks"]
+    sim, choice = tune.tuned_simulation(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info)
+    assert choice["cached"] and sim.brick_shape == c1["brick"] and sim.use_bricks == c1["bricks"]
+    sim.build()
+    f = sim.forces()
+    torch_sync()
+    ob = compare_build(sc, sim)
+    st, (acc, drho, sa, sd, ni) = oracle_forces_of(sc, ob)
+    check_forces(f[: sc.n].cpu().numpy(), acc, drho, sa, sd, label="tuned")
