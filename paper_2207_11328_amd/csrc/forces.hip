@@ -47,19 +47,24 @@ struct ForceConst {
 
 // Cole EOS for gamma = 7 in the expanded form P = B d (7 + 21d + 35d^2 +
 // 35d^3 + 21d^4 + 7d^5 + d^6), d = (rho - rho0)/rho0 (exact expansion of
-// (1 + d)^7 - 1, full relative accuracy near rho0).  aux = (P/rho^2, alpha h c)
-// with c = c0 (1 + d)^3.
+// (1 + d)^7 - 1, full relative accuracy near rho0).  aux = (P/rho^2,
+// alpha h c / 2) with c = c0 (1 + d)^3.
+// Also (brick form): zeroes the active-brick counter and the derivatives of
+// particles the last build dropped (cell < 0), which no brick visits.
 __global__ __launch_bounds__(kThreads) void k_eos(int n, const float4 *__restrict__ vel, float2 *__restrict__ aux,
                                                   const int32_t *__restrict__ cell,
                                                   const float *__restrict__ cell_alpha, int cell_base, float h,
-                                                  ForceConst C)
+                                                  ForceConst C, int32_t *__restrict__ active,
+                                                  float4 *__restrict__ out)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (active && i == 0) active[0] = 0;
     if (i >= n) return;
     float alpha_h = C.alpha_h;
-    if (cell_alpha) {
+    if (cell_alpha || out) {
         const int c = cell[i];
-        if (c >= 0) alpha_h = cell_alpha[c - cell_base] * h;
+        if (cell_alpha && c >= 0) alpha_h = cell_alpha[c - cell_base] * h;
+        if (out && c < 0) out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     const float rho = vel[i].w;
     const float d = (rho - C.rho0) * C.inv_rho0;
@@ -72,7 +77,7 @@ __global__ __launch_bounds__(kThreads) void k_eos(int n, const float4 *__restric
     const float P = C.B * d * poly;
     const float inv_rho = 1.0f / rho;
     const float a = 1.0f + d;
-    aux[i] = make_float2(P * inv_rho * inv_rho, alpha_h * (C.c0 * a * a * a));
+    aux[i] = make_float2(P * inv_rho * inv_rho, 0.5f * alpha_h * (C.c0 * a * a * a));
 }
 
 // Cell difference k_d in {-1, 0, 1} of axis d, stored as a two's-complement
@@ -93,21 +98,20 @@ struct PairAcc {
 };
 
 // One pair (i, j) of the derivative sums, branch-free; contributes only when
-// `valid` (slot inside i's list) and r < 2h.
+// `valid` (slot inside i's list) and r < 2h.  mfj = m_j times the Wendland
+// coefficient 105/(128 pi h^5); ai.y, aj.y = alpha h c / 2 (so the mean of
+// the sound speeds and the min(u.x, 0) of Monaghan's term come out of one
+// sum and one subtraction: (ai.y + aj.y)(w - |w|) = alpha h (c_i + c_j) min(w, 0)).
 template <int VISC>
 __device__ __forceinline__ void pair_core(PairAcc &A, float xx, float xy, float xz, const float4 &vi,
-                                          const float2 &ai, const float4 &pj, const float4 &vj, const float2 &aj,
+                                          const float2 &ai, float mfj, const float4 &vj, const float2 &aj,
                                           bool valid, const ForceConst &C)
 {
-    float r2;
-    {
-#pragma clang fp contract(off)
-        r2 = (xx * xx + xy * xy) + xz * xz;
-    }
+    const float r2 = fmaf(xx, xx, fmaf(xy, xy, xz * xz));
     const bool inter = valid && (r2 < C.lim2);
     const float r = __builtin_amdgcn_sqrtf(r2);
     const float qm2 = fmaf(r, C.inv_h, -2.0f);
-    const float mF = (qm2 * qm2) * (qm2 * C.fcoeff) * pj.w;  // m_j F_ij
+    const float mF = (qm2 * qm2) * (qm2 * mfj);  // m_j F_ij
     const float ux = vi.x - vj.x;
     const float uy = vi.y - vj.y;
     const float uz = vi.z - vj.z;
@@ -115,7 +119,7 @@ __device__ __forceinline__ void pair_core(PairAcc &A, float xx, float xy, float 
     A.dr = inter ? fmaf(mF, udx, A.dr) : A.dr;
     // Monaghan: Pi = -alpha h (c_i + c_j)/2 min(u.x, 0) / ((rho_i + rho_j)/2 (r^2 + eps h^2))
     const float den = (vi.w + vj.w) * (r2 + C.eps_h2);
-    const float visc = -(ai.y + aj.y) * fminf(udx, 0.0f) * __builtin_amdgcn_rcpf(den);
+    const float visc = -(ai.y + aj.y) * (udx - fabsf(udx)) * __builtin_amdgcn_rcpf(den);
     const float coef = inter ? -mF * (ai.x + aj.x + visc) : 0.0f;
     A.ax = fmaf(coef, xx, A.ax);
     A.ay = fmaf(coef, xy, A.ay);
@@ -137,7 +141,7 @@ __device__ __forceinline__ void pair_terms(PairAcc &A, uint32_t e, const float4 
     const float xx = fmaf(entry_k(e, 0), C.csx, pi.x - pj.x);
     const float xy = fmaf(entry_k(e, 1), C.csy, pi.y - pj.y);
     const float xz = fmaf(entry_k(e, 2), C.csz, pi.z - pj.z);
-    pair_core<VISC>(A, xx, xy, xz, vi, ai, pj, vj, aj, valid, C);
+    pair_core<VISC>(A, xx, xy, xz, vi, ai, pj.w * C.fcoeff, vj, aj, valid, C);
 }
 
 // Pairs of one lane's list gathered from global memory, in list order.
@@ -283,7 +287,7 @@ __device__ __forceinline__ void brick_pairs_lds(PairAcc &A, const uint4 *lg, int
 #pragma unroll
         for (int s = 0; s < kBrickGroup; ++s) {
             const int r = s % kRing;
-            pair_core<VISC>(A, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, vi, ai, P[r], V[r], X[r], k + s < nt,
+            pair_core<VISC>(A, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, vi, ai, P[r].w, V[r], X[r], k + s < nt,
                             C);
             const int s2 = s + kRing;
             fetch(s2 < kBrickGroup ? group_entry(gc, s2) : group_entry(gn, s2 - kBrickGroup), P[r], V[r], X[r]);
@@ -310,7 +314,7 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     constexpr int S = SX * SY * SZ;  // staged cells
     constexpr int NI = BX * BY * BZ; // inner cells
     static_assert(S <= NT && NI <= NT, "one thread per cell");
-    __shared__ float4 sP[CAP];  // brick-relative offset, mass
+    __shared__ float4 sP[CAP];  // brick-relative offset, mass x Wendland coefficient
     __shared__ float4 sV[CAP];
     __shared__ float2 sA[CAP];
     __shared__ int cBase[S + 1];
@@ -363,7 +367,24 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     }
     if (tid == 0) iBase[NI] = nc;
     if (nc == 0) return;  // uniform: no particle in the brick
+    __syncthreads();
     const bool use_lds = total <= CAP;
+    // central particle of lane q (binary search over the inner cells)
+    auto central = [&](int q, int &u, int &i) {
+        int lo = 0, hi = NI - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (iBase[mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        u = lo;
+        i = iStart[u] + (q - iBase[u]);
+    };
+    // the list count of the first pass is requested before the staging loads
+    // so the two latencies overlap
+    int u0, i0;
+    central(min(tid, nc - 1), u0, i0);
+    const uint32_t cnt0 = tid < nc ? count[i0] : 0u;
     if (use_lds) {
         // 2. stage the brick and its halo: one wave per row of SX staged
         //    cells (x-consecutive, so one contiguous LDS range and, away from
@@ -384,7 +405,8 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
                 const int j = s2 - cDelta[t0 + c];
                 const float4 p = pos[j];
                 const float sx = (float)(c - 2);
-                sP[s2] = make_float4(fmaf(sx, C.csx, p.x), fmaf(sy, C.csy, p.y), fmaf(sz, C.csz, p.z), p.w);
+                sP[s2] = make_float4(fmaf(sx, C.csx, p.x), fmaf(sy, C.csy, p.y), fmaf(sz, C.csz, p.z),
+                                     p.w * C.fcoeff);
                 sV[s2] = vel[j];
                 sA[s2] = aux[j];
             }
@@ -398,19 +420,12 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     for (int q0 = 0; q0 < nc; q0 += NT) {
         const int q = q0 + tid;
         const bool act = q < nc;
-        int u = 0;
-        {
-            int lo = 0, hi = NI - 1;
-            const int qq = act ? q : nc - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (iBase[mid] <= qq) lo = mid;
-                else hi = mid - 1;
-            }
-            u = lo;
+        int u = u0, i = i0;
+        uint32_t cntw = cnt0;
+        if (q0 > 0) {
+            central(act ? q : nc - 1, u, i);
+            cntw = act ? count[i] : 0u;
         }
-        const int i = iStart[u] + ((act ? q : nc - 1) - iBase[u]);
-        const uint32_t cntw = act ? count[i] : 0u;
         const int nf = min((int)(cntw & 0xFFFFu), M);
         const int nt = min(nf + (int)(cntw >> 16), M);
         const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
@@ -462,13 +477,6 @@ __global__ __launch_bounds__(kThreads) void k_count_interactions(int n, const fl
 }
 
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
-
-__global__ __launch_bounds__(kThreads) void k_zero_dropped(int n, const int32_t *__restrict__ cell,
-                                                           float4 *__restrict__ out)
-{
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i < n && cell[i] < 0) out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-}
 
 bool make_const(const sph_grid *g, const sph_params *p, int max_neibs, ForceConst &C)
 {
@@ -535,7 +543,7 @@ void launch_brick(const sph_grid *grid, int shape, int n, const float4 *pos, con
         const BrickGrid G = brick_grid<BX, BY, BZ>(grid->ncell, grid->periodic);
         const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
         constexpr int NT = brick_threads(BX * BY * BZ);
-        k_zero_one<int32_t><<<1, 1, 0, s>>>(active);
+        // (active[0] was zeroed by k_eos)
         k_active_bricks<BX, BY, BZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(cell_start, cell_end, G, active);
         k_forces_brick<VISC, BX, BY, BZ, NT, brick_cap(BX, BY, BZ)><<<blocks, NT, 0, s>>>(
             n, pos, vel, aux, neibs, neibs_brick, count, cell_start, cell_end, active, out, C, G);
@@ -567,9 +575,12 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
     int32_t *active = (int32_t *)((char *)workspace + aux_bytes(parts->capacity > 0 ? parts->capacity : 1));
     float4 *out = (float4 *)forces;
     if (grid->cell_alpha && !parts->cell) return SPH_ERR_ARG;
+    const bool bricks = cell_start && cell_end && neibs_brick;
+    if (bricks && !parts->cell) return SPH_ERR_ARG;
     k_eos<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, vel, aux, parts->cell, grid->cell_alpha, grid->cell_base,
-                                                       params->h, C);
-    if (cell_start && cell_end && neibs_brick) {
+                                                       params->h, C, bricks ? active : nullptr,
+                                                       bricks ? out : nullptr);
+    if (bricks) {
         // cell ranges and brick-local lists of the last build: LDS cell-brick
         // kernel (it writes the derivatives of every particle that lies in a
         // cell; particles dropped by the build have none)
@@ -579,9 +590,6 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
         else
             launch_brick<1>(grid, shape, n, pos, vel, aux, neibs, neibs_brick, neib_count, cell_start, cell_end,
                             active, out, C, s);
-        SPH_CHECK_LAUNCH();
-        // dropped particles (cell < 0) are in no cell: zero their derivatives
-        k_zero_dropped<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, parts->cell, out);
     } else if (params->visc_model == 0) {
         k_forces<0><<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, pos, vel, aux, neibs, neib_count, out, C);
     } else {
