@@ -31,7 +31,7 @@ class OrcParams(C.Structure):
     _fields_ = [("h", C.c_double), ("r_search", C.c_double), ("rho0", C.c_double),
                 ("gamma", C.c_double), ("c0", C.c_double), ("alpha", C.c_double),
                 ("eps_visc", C.c_double), ("nu", C.c_double), ("g", C.c_double * 3),
-                ("cfl", C.c_double), ("visc_model", C.c_int32)]
+                ("cfl", C.c_double), ("visc_model", C.c_int32), ("delta", C.c_double)]
 
 
 _lib = None
@@ -118,6 +118,7 @@ def params_struct(p, alpha=None) -> OrcParams:
         q.g[d] = rnd(p.g[d])
     q.cfl = rnd(p.cfl)
     q.visc_model = int(p.visc_model)
+    q.delta = rnd(getattr(p, "delta", 0.0))
     return q
 
 
@@ -389,6 +390,8 @@ class Adj:
 def forces_reverse(grid, params, st: State, lists: Lists, abar, dbar, into: Adj | None = None, alpha=None):
     """Adds the reverse of forces() for upstream (abar, dbar) to `into` (or a
     new zero adjoint).  Returns (adjoint, gparams[alpha, c0, nu])."""
+    if getattr(params, "delta", 0.0) != 0.0:
+        raise NotImplementedError("the reverse of the density diffusion term is not part of the oracle")
     L = _setup_reverse()
     adj = Adj.zeros(st.n) if into is None else into
     gp = np.zeros(3)
@@ -491,7 +494,7 @@ def _setup_rows():
     i32 = C.c_int
     L.orc_neighbors_rows.argtypes = [P, C.c_float, P, P, P, P, P, i32, P, i32, P, P, P, P]
     L.orc_neighbors_rows.restype = i32
-    L.orc_forces_rows.argtypes = [P, P, P, P, P, P, P, P, i32, P, P, P, P, i32, P, P, P, P]
+    L.orc_forces_rows.argtypes = [P, P, P, P, P, P, P, P, P, i32, P, P, P, P, i32, P, P, P, P]
     L.orc_forces_rows.restype = None
     L.orc_count_interactions_rows.argtypes = [P, C.c_float, P, P, P, i32, P, P, P, P, i32]
     L.orc_count_interactions_rows.restype = C.c_int64
@@ -540,7 +543,7 @@ def forces_rows(grid, params, st: State, rows, lists: Lists):
     g = grid_struct(grid)
     ps = params_struct(params)
     L.orc_forces_rows(C.byref(ps), C.byref(g), _p(st.cell), _p(st.off), _p(st.mass), _p(st.vel), _p(st.rho),
-                      _p(rows), m, _p(lists.nf), _p(lists.nb), _p(lists.fl), _p(lists.bl), lists.max_neibs,
+                      _p(st.info), _p(rows), m, _p(lists.nf), _p(lists.nb), _p(lists.fl), _p(lists.bl), lists.max_neibs,
                       _p(acc), _p(drho), _p(s_acc), _p(s_drho))
     return acc, drho, s_acc, s_drho
 

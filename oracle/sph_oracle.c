@@ -52,6 +52,7 @@ typedef struct {
     double g[3];
     double cfl;
     int32_t visc_model; /* 0 artificial (Monaghan), 1 laminar (Morris) */
+    double delta;       /* Molteni-Colagrossi density diffusion coefficient (0: off) */
 } orc_params;
 
 #define ORC_TYPE_SHIFT 30
@@ -378,6 +379,13 @@ static inline void separation(const orc_grid *g, int32_t cell_i, int32_t cell_j,
  *   a_i       = -sum_j m_j (P_i/rho_i^2 + P_j/rho_j^2 + Pi_ij) x_ij F_ij
  *               [+ sum_j 4 nu m_j / (rho_i + rho_j) F_ij u_ij   (laminar)]
  *   Pi_ij     = -alpha h cbar (u_ij . x_ij) / (rhobar (r^2 + eps h^2)) if u_ij.x_ij < 0
+ * and, with delta > 0, for a fluid i and fluid j the density diffusion of
+ * Molteni and Colagrossi (named among the dissipative terms of section "A
+ * lightning introduction to the method" and the options of "The SPH in
+ * GPUSPH", used by the dam break of "Clang: the better compiler?" and the
+ * wave basin of "An industrial test case"; the formula is that
+ * publication's, the paper does not print it):
+ *   Drho_i/Dt += -2 delta h c0 sum_j (rho_j - rho_i) F_ij r^2 / (r^2 + eps h^2) m_j / rho_j
  * Gravity is not included (the integrator adds it to fluid particles).
  *
  * Also returned, per particle and component, the sum of the magnitudes of
@@ -390,7 +398,8 @@ static inline void separation(const orc_grid *g, int32_t cell_i, int32_t cell_j,
  * nbi entries): a[3], drho, the magnitude scales sa[3], sdr; returns the
  * number of pairs with r < 2h. */
 static int forces_of(const orc_params *p, const orc_grid *g, int i, const int32_t *cell, const double *off,
-                     const double *mass, const double *vel, const double *rho, int nfi, int nbi,
+                     const double *mass, const double *vel, const double *rho, const uint32_t *info, int nfi,
+                     int nbi,
                      const int32_t *fl_row, const int32_t *bl_row, double a[3], double sa[3], double *dr_out,
                      double *sdr_out)
 {
@@ -403,6 +412,7 @@ static int forces_of(const orc_params *p, const orc_grid *g, int i, const int32_
         const double Pi = orc_pressure(p, rhoi);
         const double pi = Pi / (rhoi * rhoi);
         const double ci = orc_sound_speed(p, rhoi);
+        const int central_fluid = (info[i] >> 30) == 0u;
         const int total = nfi + nbi;
         for (int k = 0; k < total; ++k) {
             const int j = k < nfi ? fl_row[k] : bl_row[k - nfi];
@@ -425,6 +435,16 @@ static int forces_of(const orc_params *p, const orc_grid *g, int i, const int32_
             }
             dr += mj * ux * F;
             sdr += mj * uxabs * fabs(F);
+            if (p->delta != 0.0 && central_fluid && k < nfi) {
+                /* density diffusion between fluid particles (Molteni and
+                 * Colagrossi): delta h c0 sum_j psi_ij . grad_i W_ij V_j with
+                 * psi_ij = 2 (rho_j - rho_i) x_ji / (r^2 + eps h^2) and
+                 * grad_i W_ij = F x_ij, so psi . grad W = -2 (rho_j - rho_i) F r^2 / (r^2 + eps h^2) */
+                const double dd = -2.0 * p->delta * h * p->c0 * (rhoj - rhoi) * F * r2 /
+                                  (r2 + p->eps_visc * h2) * mj / rhoj;
+                dr += dd;
+                sdr += fabs(dd);
+            }
             const double cbar = 0.5 * (ci + orc_sound_speed(p, rhoj));
             const double rhobar = 0.5 * (rhoi + rhoj);
             const double visc_den = rhobar * (r2 + p->eps_visc * h2);
@@ -459,10 +479,9 @@ void orc_forces(const orc_params *p, const orc_grid *g, int n,
                 int64_t *n_inter)
 {
     int64_t inter = 0;
-    (void)info;
 #pragma omp parallel for schedule(static) reduction(+ : inter)
     for (int i = 0; i < n; ++i)
-        inter += forces_of(p, g, i, cell, off, mass, vel, rho, nf[i], nb[i], fl + (size_t)i * max_neibs,
+        inter += forces_of(p, g, i, cell, off, mass, vel, rho, info, nf[i], nb[i], fl + (size_t)i * max_neibs,
                            bl + (size_t)i * max_neibs, acc + 3 * (size_t)i, s_acc + 3 * (size_t)i, drho + i,
                            s_drho + i);
     if (n_inter) *n_inter = inter;
@@ -471,13 +490,14 @@ void orc_forces(const orc_params *p, const orc_grid *g, int n,
 /* The same for particles rows[0..nrows) with row-indexed lists (as produced
  * by orc_neighbors_rows) and row-indexed outputs. */
 void orc_forces_rows(const orc_params *p, const orc_grid *g, const int32_t *cell, const double *off,
-                     const double *mass, const double *vel, const double *rho, const int32_t *rows, int nrows,
+                     const double *mass, const double *vel, const double *rho, const uint32_t *info,
+                     const int32_t *rows, int nrows,
                      const int32_t *nf, const int32_t *nb, const int32_t *fl, const int32_t *bl, int max_neibs,
                      double *acc, double *drho, double *s_acc, double *s_drho)
 {
 #pragma omp parallel for schedule(static)
     for (int r = 0; r < nrows; ++r)
-        (void)forces_of(p, g, rows[r], cell, off, mass, vel, rho, nf[r], nb[r], fl + (size_t)r * max_neibs,
+        (void)forces_of(p, g, rows[r], cell, off, mass, vel, rho, info, nf[r], nb[r], fl + (size_t)r * max_neibs,
                         bl + (size_t)r * max_neibs, acc + 3 * (size_t)r, s_acc + 3 * (size_t)r, drho + r,
                         s_drho + r);
 }

@@ -61,6 +61,7 @@ class Params:
     g: tuple = (0.0, 0.0, -9.81)
     cfl: float = 0.3
     visc_model: int = 0         # 0 = artificial (Monaghan), 1 = laminar (Morris)
+    delta: float = 0.0          # density diffusion coefficient (0 = off)
 
 
 @dataclass
