@@ -122,12 +122,19 @@ typedef struct {
  *              sum_j 4 nu m_j / (rho_i + rho_j) F_ij u_ij, added when
  *              visc_model = 1 (visc_model 0: no laminar term)
  *   g          body acceleration added to fluid particles by the integrator
- *   cfl        time-step safety factor */
+ *   cfl        time-step safety factor
+ *   delta      density diffusion of Molteni and Colagrossi (the mass
+ *              dissipative term named in section "A lightning introduction
+ *              to the method", used by the paper's test cases), between
+ *              fluid particles only:
+ *              Drho_i/Dt += -2 delta h c0 sum_j (rho_j - rho_i) F_ij r^2 /
+ *                           (r^2 + eps h^2) m_j / rho_j;  0 disables it */
 typedef struct {
     float h, r_search, rho0, gamma, c0, alpha, eps_visc, nu;
     float g[3];
     float cfl;
     int32_t visc_model;
+    float delta;
 } sph_params;
 
 /* Particle arrays (device pointers), see the conventions above. */
@@ -213,6 +220,7 @@ sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
  *   Drho_i/Dt = sum_j m_j (u_ij . x_ij) F_ij
  *   a_i = -sum_j m_j (P_i/rho_i^2 + P_j/rho_j^2 + Pi_ij) x_ij F_ij
  *         [+ sum_j 4 nu m_j/(rho_i + rho_j) F_ij u_ij  for visc_model 1]
+ * [and the density diffusion term of sph_params.delta]
  * with F = (105 / (128 pi h^5)) (q - 2)^3, q = r/h.  Gravity is excluded.
  * forces: device float[capacity][4], xyz = a_i [m/s^2], w = Drho_i/Dt,
  * fully overwritten for i < n.  Particles are read in the order of the last
@@ -298,7 +306,8 @@ size_t sph_forces_backward_workspace_bytes(int32_t capacity, int32_t n_cells);
  * one lane per particle gathers from global memory.  The two agree to
  * rounding.  workspace: sph_forces_backward_workspace_bytes(capacity,
  * n_cells).  Errors: SPH_ERR_ARG (also for a grid with a per-cell alpha
- * table), SPH_ERR_WORKSPACE. */
+ * table and for params->delta != 0: the adjoint of the density diffusion
+ * is not implemented), SPH_ERR_WORKSPACE. */
 sph_status sph_forces_backward(const sph_grid *grid, const sph_params *params,
                                const sph_particles *parts, const uint32_t *neibs,
                                const uint32_t *neib_count, int32_t max_neibs,

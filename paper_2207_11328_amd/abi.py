@@ -40,7 +40,7 @@ class SphGrid(C.Structure):
 class SphParams(C.Structure):
     _fields_ = [("h", C.c_float), ("r_search", C.c_float), ("rho0", C.c_float), ("gamma", C.c_float),
                 ("c0", C.c_float), ("alpha", C.c_float), ("eps_visc", C.c_float), ("nu", C.c_float),
-                ("g", C.c_float * 3), ("cfl", C.c_float), ("visc_model", C.c_int32)]
+                ("g", C.c_float * 3), ("cfl", C.c_float), ("visc_model", C.c_int32), ("delta", C.c_float)]
 
 
 class SphParticles(C.Structure):
@@ -146,6 +146,7 @@ def params_struct(p, alpha=None) -> SphParams:
         q.g[d] = float(p.g[d])
     q.cfl = p.cfl
     q.visc_model = int(p.visc_model)
+    q.delta = float(getattr(p, "delta", 0.0))
     return q
 
 

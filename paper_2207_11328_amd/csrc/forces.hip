@@ -42,6 +42,7 @@ struct ForceConst {
     float alpha_h;   // alpha * h
     float eps_h2;    // eps * h^2
     float four_nu;   // 4 nu
+    float diff;      // 2 delta h c0 (density diffusion)
     int max_neibs;
 };
 
@@ -97,15 +98,20 @@ struct PairAcc {
     float ax, ay, az, dr;
 };
 
+// Model template parameter: bit 0 = Morris laminar viscosity, bit 1 =
+// density diffusion between fluid particles.
+constexpr int kLaminar = 1, kDiffusion = 2;
+
 // One pair (i, j) of the derivative sums, branch-free; contributes only when
 // `valid` (slot inside i's list) and r < 2h.  mfj = m_j times the Wendland
 // coefficient 105/(128 pi h^5); ai.y, aj.y = alpha h c / 2 (so the mean of
 // the sound speeds and the min(u.x, 0) of Monaghan's term come out of one
 // sum and one subtraction: (ai.y + aj.y)(w - |w|) = alpha h (c_i + c_j) min(w, 0)).
+// pair_fluid: both particles are fluid (density diffusion applies).
 template <int VISC>
 __device__ __forceinline__ void pair_core(PairAcc &A, float xx, float xy, float xz, const float4 &vi,
                                           const float2 &ai, float mfj, const float4 &vj, const float2 &aj,
-                                          bool valid, const ForceConst &C)
+                                          bool valid, bool pair_fluid, const ForceConst &C)
 {
     const float r2 = fmaf(xx, xx, fmaf(xy, xy, xz * xz));
     const bool inter = valid && (r2 < C.lim2);
@@ -124,24 +130,29 @@ __device__ __forceinline__ void pair_core(PairAcc &A, float xx, float xy, float 
     A.ax = fmaf(coef, xx, A.ax);
     A.ay = fmaf(coef, xy, A.ay);
     A.az = fmaf(coef, xz, A.az);
-    if (VISC == 1) {
+    if (VISC & kLaminar) {
         const float lam = inter ? C.four_nu * mF * __builtin_amdgcn_rcpf(vi.w + vj.w) : 0.0f;
         A.ax = fmaf(lam, ux, A.ax);
         A.ay = fmaf(lam, uy, A.ay);
         A.az = fmaf(lam, uz, A.az);
+    }
+    if (VISC & kDiffusion) {
+        // Molteni-Colagrossi: 2 delta h c0 (rho_i - rho_j) m_j F r^2 / ((r^2 + eps h^2) rho_j)
+        const float dd = C.diff * (vi.w - vj.w) * mF * r2 * __builtin_amdgcn_rcpf((r2 + C.eps_h2) * vj.w);
+        A.dr = (inter && pair_fluid) ? A.dr + dd : A.dr;
     }
 }
 
 template <int VISC>
 __device__ __forceinline__ void pair_terms(PairAcc &A, uint32_t e, const float4 &pi, const float4 &vi,
                                            const float2 &ai, const float4 &pj, const float4 &vj, const float2 &aj,
-                                           bool valid, const ForceConst &C)
+                                           bool valid, bool pair_fluid, const ForceConst &C)
 {
     // separation, bit-identical to the list predicate: x = k cs + (o_i - o_j)
     const float xx = fmaf(entry_k(e, 0), C.csx, pi.x - pj.x);
     const float xy = fmaf(entry_k(e, 1), C.csy, pi.y - pj.y);
     const float xz = fmaf(entry_k(e, 2), C.csz, pi.z - pj.z);
-    pair_core<VISC>(A, xx, xy, xz, vi, ai, pj.w * C.fcoeff, vj, aj, valid, C);
+    pair_core<VISC>(A, xx, xy, xz, vi, ai, pj.w * C.fcoeff, vj, aj, valid, pair_fluid, C);
 }
 
 // Pairs of one lane's list gathered from global memory, in list order.
@@ -155,7 +166,7 @@ __device__ __forceinline__ void gather_pairs(PairAcc &A, const uint32_t *tile, i
                                              uint32_t jmax, const float4 *__restrict__ pos,
                                              const float4 *__restrict__ vel, const float2 *__restrict__ aux,
                                              const float4 &pi, const float4 &vi, const float2 &ai,
-                                             const ForceConst &C)
+                                             bool central_fluid, const ForceConst &C)
 {
     const int last = max(nt - 1, 0);
     uint32_t e[D], en[D];
@@ -176,7 +187,7 @@ __device__ __forceinline__ void gather_pairs(PairAcc &A, const uint32_t *tile, i
     for (int k = 0; k < ntw; k += D) {
 #pragma unroll
         for (int s = 0; s < D; ++s) {
-            pair_terms<VISC>(A, e[s], pi, vi, ai, P[s], V[s], X[s], k + s < nt, C);
+            pair_terms<VISC>(A, e[s], pi, vi, ai, P[s], V[s], X[s], k + s < nt, central_fluid && k + s < nf, C);
             e[s] = en[s];
             const uint32_t j = min(e[s] & kIndexMask, jmax);
             P[s] = pos[j];
@@ -193,6 +204,7 @@ __global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__rest
                                                      const float2 *__restrict__ aux,
                                                      const uint32_t *__restrict__ neibs,
                                                      const uint32_t *__restrict__ count,
+                                                     const uint32_t *__restrict__ info,
                                                      float4 *__restrict__ out, ForceConst C)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
@@ -219,7 +231,8 @@ __global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__rest
     const float2 ai = aux[ii];
     PairAcc A = {0.0f, 0.0f, 0.0f, 0.0f};
 
-    gather_pairs<VISC, kDepth>(A, tile + lane, nf, nt, ntw, M, jmax, pos, vel, aux, pi, vi, ai, C);
+    const bool central_fluid = (VISC & kDiffusion) ? ptype(info[ii]) != kBoundary : true;
+    gather_pairs<VISC, kDepth>(A, tile + lane, nf, nt, ntw, M, jmax, pos, vel, aux, pi, vi, ai, central_fluid, C);
     if (i < n) out[i] = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
@@ -287,8 +300,9 @@ __device__ __forceinline__ void brick_pairs_lds(PairAcc &A, const uint4 *lg, int
 #pragma unroll
         for (int s = 0; s < kBrickGroup; ++s) {
             const int r = s % kRing;
-            pair_core<VISC>(A, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, vi, ai, P[r].w, V[r], X[r], k + s < nt,
-                            C);
+            // staged w = +-(m_j x Wendland coefficient), negative for boundary particles
+            pair_core<VISC>(A, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, vi, ai, fabsf(P[r].w), V[r], X[r],
+                            k + s < nt, pi.w > 0.0f && P[r].w > 0.0f, C);
             const int s2 = s + kRing;
             fetch(s2 < kBrickGroup ? group_entry(gc, s2) : group_entry(gn, s2 - kBrickGroup), P[r], V[r], X[r]);
         }
@@ -307,6 +321,7 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
                                                      const int32_t *__restrict__ cell_start,
                                                      const int32_t *__restrict__ cell_end,
                                                      const int32_t *__restrict__ active,
+                                                     const uint32_t *__restrict__ info,
                                                      float4 *__restrict__ out, ForceConst C, BrickGrid G)
 {
     using St = Staging<BX, BY, BZ>;
@@ -405,8 +420,11 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
                 const int j = s2 - cDelta[t0 + c];
                 const float4 p = pos[j];
                 const float sx = (float)(c - 2);
+                // w = m x Wendland coefficient, negated for boundary particles
+                // when the density diffusion needs the type
+                const float mf = p.w * C.fcoeff;
                 sP[s2] = make_float4(fmaf(sx, C.csx, p.x), fmaf(sy, C.csy, p.y), fmaf(sz, C.csz, p.z),
-                                     p.w * C.fcoeff);
+                                     ((VISC & kDiffusion) && ptype(info[j]) == kBoundary) ? -mf : mf);
                 sV[s2] = vel[j];
                 sA[s2] = aux[j];
             }
@@ -440,8 +458,9 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
             } else {
                 // (a shallow pipeline: this path shares the register budget of
                 // the LDS path and runs only where a halo overflows)
+                const bool central_fluid = (VISC & kDiffusion) ? ptype(info[i]) != kBoundary : true;
                 gather_pairs<VISC, 2>(A, neibs + toff, nf, nt, ntw, M, jmax, pos, vel, aux, pos[i], vel[i], aux[i],
-                                      C);
+                                      central_fluid, C);
             }
         }
         if (act) out[i] = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -482,6 +501,7 @@ bool make_const(const sph_grid *g, const sph_params *p, int max_neibs, ForceCons
 {
     if (!(p->h > 0.0f) || !(p->rho0 > 0.0f) || !(p->c0 > 0.0f) || p->gamma != 7.0f) return false;
     if (p->visc_model != 0 && p->visc_model != 1) return false;
+    if (!(p->delta >= 0.0f) || !(p->delta < 1e30f)) return false;
     for (int d = 0; d < 3; ++d)
         if (!(g->cell_size[d] > 0.0f)) return false;
     C.csx = g->cell_size[0];
@@ -499,6 +519,7 @@ bool make_const(const sph_grid *g, const sph_params *p, int max_neibs, ForceCons
     C.alpha_h = (float)((double)p->alpha * h);
     C.eps_h2 = (float)((double)p->eps_visc * h * h);
     C.four_nu = (float)(4.0 * (double)p->nu);
+    C.diff = (float)(2.0 * (double)p->delta * h * (double)p->c0);
     C.max_neibs = max_neibs;
     return true;
 }
@@ -536,8 +557,8 @@ constexpr int brick_cap(int BX, int BY, int BZ) { return BX * BY * BZ >= 36 ? 40
 template <int VISC>
 void launch_brick(const sph_grid *grid, int shape, int n, const float4 *pos, const float4 *vel, const float2 *aux,
                   const uint32_t *neibs, const uint16_t *neibs_brick, const uint32_t *count,
-                  const int32_t *cell_start, const int32_t *cell_end, int32_t *active, float4 *out,
-                  const ForceConst &C, hipStream_t s)
+                  const int32_t *cell_start, const int32_t *cell_end, int32_t *active, const uint32_t *info,
+                  float4 *out, const ForceConst &C, hipStream_t s)
 {
     with_shape(shape, [&]<int BX, int BY, int BZ>() {
         const BrickGrid G = brick_grid<BX, BY, BZ>(grid->ncell, grid->periodic);
@@ -546,7 +567,7 @@ void launch_brick(const sph_grid *grid, int shape, int n, const float4 *pos, con
         // (active[0] was zeroed by k_eos)
         k_active_bricks<BX, BY, BZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(cell_start, cell_end, G, active);
         k_forces_brick<VISC, BX, BY, BZ, NT, brick_cap(BX, BY, BZ)><<<blocks, NT, 0, s>>>(
-            n, pos, vel, aux, neibs, neibs_brick, count, cell_start, cell_end, active, out, C, G);
+            n, pos, vel, aux, neibs, neibs_brick, count, cell_start, cell_end, active, info, out, C, G);
     });
 }
 
@@ -580,20 +601,31 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
     k_eos<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, vel, aux, parts->cell, grid->cell_alpha, grid->cell_base,
                                                        params->h, C, bricks ? active : nullptr,
                                                        bricks ? out : nullptr);
+    if ((params->delta != 0.0f) && !parts->info) return SPH_ERR_ARG;
+    const int model = params->visc_model | (params->delta != 0.0f ? kDiffusion : 0);
+    const uint32_t *info = parts->info;
     if (bricks) {
         // cell ranges and brick-local lists of the last build: LDS cell-brick
         // kernel (it writes the derivatives of every particle that lies in a
-        // cell; particles dropped by the build have none)
-        if (params->visc_model == 0)
-            launch_brick<0>(grid, shape, n, pos, vel, aux, neibs, neibs_brick, neib_count, cell_start, cell_end,
-                            active, out, C, s);
-        else
-            launch_brick<1>(grid, shape, n, pos, vel, aux, neibs, neibs_brick, neib_count, cell_start, cell_end,
-                            active, out, C, s);
-    } else if (params->visc_model == 0) {
-        k_forces<0><<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, pos, vel, aux, neibs, neib_count, out, C);
+        // cell; particles dropped by the build were zeroed by k_eos)
+        switch (model) {
+        case 0: launch_brick<0>(grid, shape, n, pos, vel, aux, neibs, neibs_brick, neib_count, cell_start, cell_end,
+                                active, info, out, C, s); break;
+        case 1: launch_brick<1>(grid, shape, n, pos, vel, aux, neibs, neibs_brick, neib_count, cell_start, cell_end,
+                                active, info, out, C, s); break;
+        case 2: launch_brick<2>(grid, shape, n, pos, vel, aux, neibs, neibs_brick, neib_count, cell_start, cell_end,
+                                active, info, out, C, s); break;
+        default: launch_brick<3>(grid, shape, n, pos, vel, aux, neibs, neibs_brick, neib_count, cell_start,
+                                 cell_end, active, info, out, C, s); break;
+        }
     } else {
-        k_forces<1><<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, pos, vel, aux, neibs, neib_count, out, C);
+        const unsigned b = sph_blocks(n, kThreads);
+        switch (model) {
+        case 0: k_forces<0><<<b, kThreads, 0, s>>>(n, pos, vel, aux, neibs, neib_count, info, out, C); break;
+        case 1: k_forces<1><<<b, kThreads, 0, s>>>(n, pos, vel, aux, neibs, neib_count, info, out, C); break;
+        case 2: k_forces<2><<<b, kThreads, 0, s>>>(n, pos, vel, aux, neibs, neib_count, info, out, C); break;
+        default: k_forces<3><<<b, kThreads, 0, s>>>(n, pos, vel, aux, neibs, neib_count, info, out, C); break;
+        }
     }
     SPH_CHECK_LAUNCH();
     return SPH_OK;

@@ -633,6 +633,7 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
         return SPH_ERR_ARG;
     if (!(p->h > 0.0f) || !(p->rho0 > 0.0f) || !(p->c0 > 0.0f) || p->gamma != 7.0f) return SPH_ERR_ARG;
     if (p->visc_model != 0 && p->visc_model != 1) return SPH_ERR_ARG;
+    if (p->delta != 0.0f) return SPH_ERR_ARG;  // the adjoint of the density diffusion is not implemented
     const int64_t n_cells = (int64_t)grid->ncell[0] * grid->ncell[1] * grid->ncell[2];
     if (n_cells <= 0 || n_cells > INT32_MAX - 2) return SPH_ERR_ARG;
     const bool bricks = cell_start && cell_end && neibs_brick;
