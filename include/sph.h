@@ -305,9 +305,9 @@ size_t sph_forces_backward_workspace_bytes(int32_t capacity, int32_t n_cells);
  * by brick of cells from LDS (each brick in two halves along y); without them
  * one lane per particle gathers from global memory.  The two agree to
  * rounding.  workspace: sph_forces_backward_workspace_bytes(capacity,
- * n_cells).  Errors: SPH_ERR_ARG (also for a grid with a per-cell alpha
- * table and for params->delta != 0: the adjoint of the density diffusion
- * is not implemented), SPH_ERR_WORKSPACE. */
+ * n_cells).  The density diffusion term (params->delta) is differentiated
+ * too; its coefficient enters dL/dc0.  Errors: SPH_ERR_ARG (also for a grid
+ * with a per-cell alpha table), SPH_ERR_WORKSPACE. */
 sph_status sph_forces_backward(const sph_grid *grid, const sph_params *params,
                                const sph_particles *parts, const uint32_t *neibs,
                                const uint32_t *neib_count, int32_t max_neibs,

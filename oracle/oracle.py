@@ -390,8 +390,6 @@ class Adj:
 def forces_reverse(grid, params, st: State, lists: Lists, abar, dbar, into: Adj | None = None, alpha=None):
     """Adds the reverse of forces() for upstream (abar, dbar) to `into` (or a
     new zero adjoint).  Returns (adjoint, gparams[alpha, c0, nu])."""
-    if getattr(params, "delta", 0.0) != 0.0:
-        raise NotImplementedError("the reverse of the density diffusion term is not part of the oracle")
     L = _setup_reverse()
     adj = Adj.zeros(st.n) if into is None else into
     gp = np.zeros(3)

@@ -656,6 +656,7 @@ void orc_forces_reverse(const orc_params *p, const orc_grid *g, int n,
         const double *ab = abar + 3 * (size_t)c;
         const double db = dbar[c];
         const int total = nf[c] + nb[c];
+        const int central_fluid = ptype(info[c]) != ORC_BOUNDARY;
         (void)B;
         for (int k = 0; k < total; ++k) {
             const int m = k < nf[c] ? fl[(size_t)c * max_neibs + k]
@@ -717,6 +718,22 @@ void orc_forces_reverse(const orc_params *p, const orc_grid *g, int n,
             galpha += A * (-mn * F) * Pi_over_alpha;
             gc0 += A * (-mn * F) * (2.0 * pc + 2.0 * pn + Pi) / p->c0;
             if (p->visc_model == 1) gnu += Bu * 4.0 * mn * F / rs;
+            if (p->delta != 0.0 && central_fluid && k < nf[c]) {
+                /* density diffusion, term = cD m_n (rho_c - rho_n)/rho_n Gd(r),
+                 * Gd = F r^2 / (r^2 + eps h^2), cD = 2 delta h c0 */
+                const double cD = 2.0 * p->delta * h * p->c0;
+                const double Gd = F * r2 / dd;
+                const double dGd_r = dFdr / r * r2 / dd + 2.0 * F * eh2 / (dd * dd); /* Gd'(r) / r */
+                const double ratio = (rc - rn) / rn;
+                for (int d = 0; d < 3; ++d) {
+                    const double t = db * cD * mn * ratio * dGd_r * x[d];
+                    go[3 * (size_t)c + d] += t;
+                    go[3 * (size_t)m + d] -= t;
+                }
+                grho[c] += db * cD * mn * Gd / rn;
+                grho[m] += db * cD * mn * Gd * (-rc / (rn * rn));
+                gc0 += db * cD * mn * ratio * Gd / p->c0;
+            }
         }
     }
     gparams[0] += galpha;

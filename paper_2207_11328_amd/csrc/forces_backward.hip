@@ -38,6 +38,7 @@ struct BackConst {
     float rho0, inv_rho0, B, c0;
     float lim2, inv_h, fcoeff;
     float alpha_h, h, eps_h2, four_nu, inv_c0;
+    float diff;  // 2 delta h c0 (density diffusion)
     int max_neibs;
 };
 
@@ -79,11 +80,15 @@ struct BackAcc {
     float galpha, gc0, gnu;
 };
 
+// Model template parameter: bit 0 = Morris laminar viscosity, bit 1 =
+// density diffusion between fluid particles (pair_fluid: both are fluid).
+constexpr int kLaminar = 1, kDiffusion = 2;
+
 template <int VISC>
 __device__ __forceinline__ void pair_adjoint_core(BackAcc &G, float xx, float xy, float xz, float mi,
                                                   const float4 &vi, const float4 &xi, const float4 &gi, float mj,
                                                   const float4 &vj, const float2 &xj, const float4 &gj, bool valid,
-                                                  const BackConst &C)
+                                                  bool pair_fluid, const BackConst &C)
 {
     float r2;
     {
@@ -119,14 +124,14 @@ __device__ __forceinline__ void pair_adjoint_core(BackAcc &G, float xx, float xy
     float kx = -dA * cx + sD * w * Fp_r;  // coefficient of x
     float ku = -dA * cu + sD * F;         // coefficient of u
     const float ka = -S * F;              // coefficient of da
-    if (VISC == 1) kx = fmaf(C.four_nu * Fp_r * inv_rs, fmaf(dax, ux, fmaf(day, uy, daz * uz)), kx);
+    if (VISC & kLaminar) kx = fmaf(C.four_nu * Fp_r * inv_rs, fmaf(dax, ux, fmaf(day, uy, daz * uz)), kx);
     float ox = fmaf(ka, dax, fmaf(kx, xx, ku * ux));
     float oy = fmaf(ka, day, fmaf(kx, xy, ku * uy));
     float oz = fmaf(ka, daz, fmaf(kx, xz, ku * uz));
     // d/du_i
     const float lx = -dA * cu + sD * F;  // coefficient of x
     float vx = lx * xx, vy = lx * xy, vz = lx * xz;
-    if (VISC == 1) {
+    if (VISC & kLaminar) {
         const float la = C.four_nu * F * inv_rs;
         vx = fmaf(la, dax, vx);
         vy = fmaf(la, day, vy);
@@ -135,14 +140,34 @@ __device__ __forceinline__ void pair_adjoint_core(BackAcc &G, float xx, float xy
     // d/drho_i
     const float dPi_dri = w < 0.0f ? -C.alpha_h * mw * inv_d * (xi.w * inv_rs - csum * inv_rs * inv_rs) : 0.0f;
     float gr = -F * (xi.z + dPi_dri) * dA;
-    if (VISC == 1) gr = fmaf(-C.four_nu * F * inv_rs * inv_rs, fmaf(dax, ux, fmaf(day, uy, daz * uz)), gr);
+    if (VISC & kLaminar) gr = fmaf(-C.four_nu * F * inv_rs * inv_rs, fmaf(dax, ux, fmaf(day, uy, daz * uz)), gr);
     // parameters (central role)
     const float Axi = fmaf(gi.x, xx, fmaf(gi.y, xy, gi.z * xz));
     const float mF = -mj * F;
     float ga = Axi * mF * (-C.h * csum * inv_rs * mw * inv_d);
     float gc = Axi * mF * (2.0f * (xi.x + xj.x) + Pi) * C.inv_c0;
     float gn = 0.0f;
-    if (VISC == 1) gn = fmaf(gi.x, ux, fmaf(gi.y, uy, gi.z * uz)) * 4.0f * mj * F * inv_rs;
+    if (VISC & kLaminar) gn = fmaf(gi.x, ux, fmaf(gi.y, uy, gi.z * uz)) * 4.0f * mj * F * inv_rs;
+    if (VISC & kDiffusion) {
+        // density diffusion, term_ij = c m_j (rho_i - rho_j)/rho_j Gd(r) with
+        // Gd = F r^2/(r^2 + eps h^2), c = 2 delta h c0; both roles combined:
+        //   do_i   += c Gd'/r (rho_i - rho_j)(dbar_i m_j/rho_j - dbar_j m_i/rho_i) x
+        //   drho_i += c Gd (dbar_i m_j/rho_j - dbar_j m_i rho_j/rho_i^2)
+        //   dc0    += dbar_i term_ij / c0   (central role)
+        if (pair_fluid) {
+            const float inv_rj = __builtin_amdgcn_rcpf(vj.w), inv_ri = __builtin_amdgcn_rcpf(vi.w);
+            const float Gd = F * r2 * inv_d;
+            const float Gd_r = Fp_r * r2 * inv_d + 2.0f * F * C.eps_h2 * inv_d * inv_d;
+            const float w1 = gi.w * mj * inv_rj, w2 = gj.w * mi * inv_ri;
+            const float dr = vi.w - vj.w;
+            const float kd = C.diff * Gd_r * dr * (w1 - w2);
+            ox = fmaf(kd, xx, ox);
+            oy = fmaf(kd, xy, oy);
+            oz = fmaf(kd, xz, oz);
+            gr = fmaf(C.diff * Gd, w1 - w2 * vj.w * inv_ri, gr);
+            gc = fmaf(w1 * C.diff * dr * Gd, C.inv_c0, gc);
+        }
+    }
     if (inter) {
         G.ox += ox;
         G.oy += oy;
@@ -161,20 +186,21 @@ template <int VISC>
 __device__ __forceinline__ void pair_adjoint(BackAcc &G, uint32_t e, const float4 &pi, const float4 &vi,
                                              const float4 &xi, const float4 &gi, const float4 &pj,
                                              const float4 &vj, const float4 &xj, const float4 &gj, bool valid,
-                                             const BackConst &C)
+                                             bool pair_fluid, const BackConst &C)
 {
     const float xx = fmaf(entry_k(e, 0), C.csx, pi.x - pj.x);
     const float xy = fmaf(entry_k(e, 1), C.csy, pi.y - pj.y);
     const float xz = fmaf(entry_k(e, 2), C.csz, pi.z - pj.z);
-    pair_adjoint_core<VISC>(G, xx, xy, xz, pi.w, vi, xi, gi, pj.w, vj, make_float2(xj.x, xj.y), gj, valid, C);
+    pair_adjoint_core<VISC>(G, xx, xy, xz, pi.w, vi, xi, gi, pj.w, vj, make_float2(xj.x, xj.y), gj, valid,
+                            pair_fluid, C);
 }
 
 template <int VISC>
 __global__ __launch_bounds__(kThreads) void k_forces_backward(
     int n, const float4 *__restrict__ pos, const float4 *__restrict__ vel, const float4 *__restrict__ aux,
     const float4 *__restrict__ gforce, const uint32_t *__restrict__ neibs, const uint32_t *__restrict__ count,
-    float4 *__restrict__ gpos, float4 *__restrict__ gvel, double *__restrict__ partial, int accumulate,
-    BackConst C)
+    const uint32_t *__restrict__ info, float4 *__restrict__ gpos, float4 *__restrict__ gvel,
+    double *__restrict__ partial, int accumulate, BackConst C)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     const int lane = threadIdx.x % kWave;
@@ -191,6 +217,7 @@ __global__ __launch_bounds__(kThreads) void k_forces_backward(
         const int tile_id = __builtin_amdgcn_readfirstlane(i / kWave);
         const uint32_t *tile = neibs + (size_t)tile_id * (kWave * M);
         const float4 pi = pos[ii], vi = vel[ii], xi = aux[ii], gi = gforce[ii];
+        const bool central_fluid = (VISC & kDiffusion) ? ptype(info[ii]) != kBoundary : true;
         uint32_t eA = tile[list_slot(0, nf, last, M) * kWave + lane];
         uint32_t eNext = tile[list_slot(1, nf, last, M) * kWave + lane];
         uint32_t jA = min(eA & kIndexMask, jmax);
@@ -200,7 +227,7 @@ __global__ __launch_bounds__(kThreads) void k_forces_backward(
             const uint32_t eB = eNext;
             const uint32_t jB = min(eB & kIndexMask, jmax);
             const float4 pB = pos[jB], vB = vel[jB], xB = aux[jB], gB = gforce[jB];
-            pair_adjoint<VISC>(G, eA, pi, vi, xi, gi, pA, vA, xA, gA, k < nt, C);
+            pair_adjoint<VISC>(G, eA, pi, vi, xi, gi, pA, vA, xA, gA, k < nt, central_fluid && k < nf, C);
             eNext = tile[list_slot(k + 3, nf, last, M) * kWave + lane];
             eA = eN2;
             jA = min(eA & kIndexMask, jmax);
@@ -208,7 +235,8 @@ __global__ __launch_bounds__(kThreads) void k_forces_backward(
             vA = vel[jA];
             xA = aux[jA];
             gA = gforce[jA];
-            pair_adjoint<VISC>(G, eB, pi, vi, xi, gi, pB, vB, xB, gB, k + 1 < nt, C);
+            pair_adjoint<VISC>(G, eB, pi, vi, xi, gi, pB, vB, xB, gB, k + 1 < nt, central_fluid && k + 1 < nf,
+                               C);
         }
     }
     if (i < n) {
@@ -324,8 +352,10 @@ __device__ __forceinline__ void brick_adjoint_lds(BackAcc &G, const uint4 *lg, i
 #pragma unroll
         for (int s = 0; s < kBrickGroup; ++s) {
             const int r = s % R;
-            pair_adjoint_core<VISC>(G, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, pi.w, vi, xi, gi, P[r].w, V[r],
-                                    X[r], Gj[r], g0 * kBrickGroup + s < nt, C);
+            // staged w = +-m_j, negative for boundary particles
+            pair_adjoint_core<VISC>(G, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, fabsf(pi.w), vi, xi, gi,
+                                    fabsf(P[r].w), V[r], X[r], Gj[r], g0 * kBrickGroup + s < nt,
+                                    pi.w > 0.0f && P[r].w > 0.0f, C);
             const int s2 = s + R;
             fetch(s2 < kBrickGroup ? group_entry(gc, s2) : group_entry(gn, s2 - kBrickGroup), r);
         }
@@ -353,8 +383,8 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
     int n, const float4 *__restrict__ pos, const float4 *__restrict__ vel, const float4 *__restrict__ aux,
     const float4 *__restrict__ gforce, const uint32_t *__restrict__ neibs, const uint16_t *__restrict__ neibs_brick,
     const uint32_t *__restrict__ count, const int32_t *__restrict__ cell_start, const int32_t *__restrict__ cell_end,
-    const int32_t *__restrict__ active, float4 *__restrict__ gpos, float4 *__restrict__ gvel,
-    double *__restrict__ partial, int accumulate, BackConst C, BrickGrid G)
+    const int32_t *__restrict__ active, const uint32_t *__restrict__ info, float4 *__restrict__ gpos,
+    float4 *__restrict__ gvel, double *__restrict__ partial, int accumulate, BackConst C, BrickGrid G)
 {
     using St = Staging<BX, BY, BZ>;
     constexpr int SX = St::SX, SZ = St::SZ, S = St::S, NI = St::NI;
@@ -445,7 +475,10 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
                     const float sx = (float)(c - 2);
                     const float4 a4 = aux[j];
                     const int l = s2 - s_lo;
-                    sP[l] = make_float4(fmaf(sx, C.csx, p.x), fmaf(sy, C.csy, p.y), fmaf(sz, C.csz, p.z), p.w);
+                    // mass negated for boundary particles when the diffusion needs the type
+                    const bool bnd = (VISC & kDiffusion) && ptype(info[j]) == kBoundary;
+                    sP[l] = make_float4(fmaf(sx, C.csx, p.x), fmaf(sy, C.csy, p.y), fmaf(sz, C.csz, p.z),
+                                        bnd ? -p.w : p.w);
                     sV[l] = vel[j];
                     sX[l] = make_float2(a4.x, a4.y);
                     sG[l] = gforce[j];
@@ -487,11 +520,13 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
                     // the lane pair splits the list by parity of the entry
                     const uint32_t *tile = neibs + (size_t)(i / kWave) * (kWave * M) + (i % kWave);
                     const float4 pi = pos[i], vi = vel[i], gi = gforce[i];
+                    const bool central_fluid = (VISC & kDiffusion) ? ptype(info[i]) != kBoundary : true;
                     const int last = max(nt - 1, 0);
                     for (int k = h; k < ntw; k += 2) {
                         const uint32_t e = tile[list_slot(k, nf, last, M) * kWave];
                         const uint32_t j = min(e & kIndexMask, jmax);
-                        pair_adjoint<VISC>(A, e, pi, vi, xi, gi, pos[j], vel[j], aux[j], gforce[j], k < nt, C);
+                        pair_adjoint<VISC>(A, e, pi, vi, xi, gi, pos[j], vel[j], aux[j], gforce[j], k < nt,
+                                           central_fluid && k < nf, C);
                     }
                 }
             }
@@ -591,8 +626,9 @@ template <int VISC>
 void launch_backward_brick(const sph_grid *grid, int shape, int n, const float4 *pos, const float4 *vel,
                            const float4 *aux, const float4 *gforce, const uint32_t *neibs,
                            const uint16_t *neibs_brick, const uint32_t *count, const int32_t *cell_start,
-                           const int32_t *cell_end, int32_t *active, float4 *gpos, float4 *gvel, double *partial,
-                           int accumulate, const BackConst &C, hipStream_t s, int &n_bricks)
+                           const int32_t *cell_end, int32_t *active, const uint32_t *info, float4 *gpos,
+                           float4 *gvel, double *partial, int accumulate, const BackConst &C, hipStream_t s,
+                           int &n_bricks)
 {
     with_shape(shape, [&]<int BX, int BY, int BZ>() {
         const BrickGrid G = brick_grid<BX, BY, BZ>(grid->ncell, grid->periodic);
@@ -604,8 +640,8 @@ void launch_backward_brick(const sph_grid *grid, int shape, int n, const float4 
         k_active_bricks<BX, BY, BZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(cell_start, cell_end, G, active);
         k_forces_backward_brick<VISC, BX, BY, BZ, kBackBrickThreads, kBackBrickCap><<<blocks, kBackBrickThreads, 0,
                                                                                       s>>>(
-            n, pos, vel, aux, gforce, neibs, neibs_brick, count, cell_start, cell_end, active, gpos, gvel, partial,
-            accumulate, C, G);
+            n, pos, vel, aux, gforce, neibs, neibs_brick, count, cell_start, cell_end, active, info, gpos, gvel,
+            partial, accumulate, C, G);
     });
 }
 
@@ -633,7 +669,8 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
         return SPH_ERR_ARG;
     if (!(p->h > 0.0f) || !(p->rho0 > 0.0f) || !(p->c0 > 0.0f) || p->gamma != 7.0f) return SPH_ERR_ARG;
     if (p->visc_model != 0 && p->visc_model != 1) return SPH_ERR_ARG;
-    if (p->delta != 0.0f) return SPH_ERR_ARG;  // the adjoint of the density diffusion is not implemented
+    if (!(p->delta >= 0.0f) || !(p->delta < 1e30f)) return SPH_ERR_ARG;
+    if (p->delta != 0.0f && parts->n > 0 && !parts->info) return SPH_ERR_ARG;
     const int64_t n_cells = (int64_t)grid->ncell[0] * grid->ncell[1] * grid->ncell[2];
     if (n_cells <= 0 || n_cells > INT32_MAX - 2) return SPH_ERR_ARG;
     const bool bricks = cell_start && cell_end && neibs_brick;
@@ -660,6 +697,7 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
     C.eps_h2 = (float)((double)p->eps_visc * h * h);
     C.four_nu = (float)(4.0 * (double)p->nu);
     C.inv_c0 = (float)(1.0 / (double)p->c0);
+    C.diff = (float)(2.0 * (double)p->delta * h * (double)p->c0);
     C.max_neibs = max_neibs;
     const int n = parts->n;
     hipStream_t s = (hipStream_t)stream;
@@ -669,20 +707,29 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
     double *bpartial = (double *)((char *)workspace + aux_bytes(cap1) + partial_bytes(cap1));
     int32_t *active = (int32_t *)(bpartial + 3 * (n_cells + 1));
     const int nblocks = n > 0 ? (int)sph_blocks(n, kThreads) : 0;
+    const int model = p->visc_model | (p->delta != 0.0f ? kDiffusion : 0);
+    const uint32_t *info = parts->info;
     if (n > 0 && bricks) {
         // cell ranges and brick-local lists of the last build: LDS bricks
         int nb = 0;
         k_eos_grad<<<nblocks, kThreads, 0, s>>>(n, (const float4 *)parts->vel, aux, C);
-        if (p->visc_model == 0)
-            launch_backward_brick<0>(grid, shape, n, (const float4 *)parts->pos, (const float4 *)parts->vel, aux,
-                                     (const float4 *)grad_forces, neibs, neibs_brick, neib_count, cell_start,
-                                     cell_end, active, (float4 *)grad_pos, (float4 *)grad_vel, bpartial, accumulate,
-                                     C, s, nb);
-        else
-            launch_backward_brick<1>(grid, shape, n, (const float4 *)parts->pos, (const float4 *)parts->vel, aux,
-                                     (const float4 *)grad_forces, neibs, neibs_brick, neib_count, cell_start,
-                                     cell_end, active, (float4 *)grad_pos, (float4 *)grad_vel, bpartial, accumulate,
-                                     C, s, nb);
+        const float4 *pos = (const float4 *)parts->pos, *vel = (const float4 *)parts->vel;
+        const float4 *gf = (const float4 *)grad_forces;
+        float4 *gp = (float4 *)grad_pos, *gv = (float4 *)grad_vel;
+        switch (model) {
+        case 0: launch_backward_brick<0>(grid, shape, n, pos, vel, aux, gf, neibs, neibs_brick, neib_count,
+                                         cell_start, cell_end, active, info, gp, gv, bpartial, accumulate, C, s, nb);
+            break;
+        case 1: launch_backward_brick<1>(grid, shape, n, pos, vel, aux, gf, neibs, neibs_brick, neib_count,
+                                         cell_start, cell_end, active, info, gp, gv, bpartial, accumulate, C, s, nb);
+            break;
+        case 2: launch_backward_brick<2>(grid, shape, n, pos, vel, aux, gf, neibs, neibs_brick, neib_count,
+                                         cell_start, cell_end, active, info, gp, gv, bpartial, accumulate, C, s, nb);
+            break;
+        default: launch_backward_brick<3>(grid, shape, n, pos, vel, aux, gf, neibs, neibs_brick, neib_count,
+                                          cell_start, cell_end, active, info, gp, gv, bpartial, accumulate, C, s, nb);
+            break;
+        }
         if (!accumulate)
             k_zero_dropped_adjoint<<<nblocks, kThreads, 0, s>>>(n, parts->cell, (float4 *)grad_pos,
                                                                  (float4 *)grad_vel);
@@ -692,14 +739,19 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
     }
     if (n > 0) {
         k_eos_grad<<<nblocks, kThreads, 0, s>>>(n, (const float4 *)parts->vel, aux, C);
-        if (p->visc_model == 0)
-            k_forces_backward<0><<<nblocks, kThreads, 0, s>>>(
-                n, (const float4 *)parts->pos, (const float4 *)parts->vel, aux, (const float4 *)grad_forces, neibs,
-                neib_count, (float4 *)grad_pos, (float4 *)grad_vel, partial, accumulate, C);
-        else
-            k_forces_backward<1><<<nblocks, kThreads, 0, s>>>(
-                n, (const float4 *)parts->pos, (const float4 *)parts->vel, aux, (const float4 *)grad_forces, neibs,
-                neib_count, (float4 *)grad_pos, (float4 *)grad_vel, partial, accumulate, C);
+        const float4 *pos = (const float4 *)parts->pos, *vel = (const float4 *)parts->vel;
+        const float4 *gf = (const float4 *)grad_forces;
+        float4 *gp = (float4 *)grad_pos, *gv = (float4 *)grad_vel;
+        switch (model) {
+        case 0: k_forces_backward<0><<<nblocks, kThreads, 0, s>>>(n, pos, vel, aux, gf, neibs, neib_count, info, gp,
+                                                                  gv, partial, accumulate, C); break;
+        case 1: k_forces_backward<1><<<nblocks, kThreads, 0, s>>>(n, pos, vel, aux, gf, neibs, neib_count, info, gp,
+                                                                  gv, partial, accumulate, C); break;
+        case 2: k_forces_backward<2><<<nblocks, kThreads, 0, s>>>(n, pos, vel, aux, gf, neibs, neib_count, info, gp,
+                                                                  gv, partial, accumulate, C); break;
+        default: k_forces_backward<3><<<nblocks, kThreads, 0, s>>>(n, pos, vel, aux, gf, neibs, neib_count, info,
+                                                                   gp, gv, partial, accumulate, C); break;
+        }
     }
     k_param_reduce<<<1, kReduceThreads, 0, s>>>(nblocks, partial, grad_params, accumulate);
     SPH_CHECK_LAUNCH();

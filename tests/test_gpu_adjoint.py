@@ -53,20 +53,29 @@ SCENES = {
 }
 
 
-CASES = [(name, "bricks", None) for name in SCENES] + [(name, "gather", None) for name in SCENES] + \
-    [("cloud_laminar_periodic", "bricks", (3, 3, 3)), ("cloud_av", "bricks", (3, 2, 3))]
+CASES = [(name, "bricks", None, 0.0) for name in SCENES] + [(name, "gather", None, 0.0) for name in SCENES] + \
+    [("cloud_laminar_periodic", "bricks", (3, 3, 3), 0.0), ("cloud_av", "bricks", (3, 2, 3), 0.0)] + \
+    [("cloud_av", "bricks", None, 0.1), ("cloud_laminar_periodic", "gather", None, 0.1),
+     ("dam_break_64k", "bricks", None, 0.1)]
 
 
-@pytest.mark.parametrize("name,form,shape", CASES,
-                         ids=["%s-%s%s" % (c[0], c[1], "" if c[2] is None else "-" + "x".join(map(str, c[2])))
-                              for c in CASES])
-def test_forces_backward_parity(name, form, shape):
+def _case_id(c):
+    shape = "" if c[2] is None else "-" + "x".join(map(str, c[2]))
+    return "%s-%s%s%s" % (c[0], c[1], shape, "-diffusion" if c[3] else "")
+
+
+@pytest.mark.parametrize("name,form,shape,delta", CASES, ids=[_case_id(c) for c in CASES])
+def test_forces_backward_parity(name, form, shape, delta):
     """Both forms of the adjoint (LDS bricks in two halves along y, also for
-    odd brick heights; per-particle gather) against the FP64 oracle reverse."""
+    odd brick heights; per-particle gather) against the FP64 oracle reverse,
+    also with the density diffusion term."""
+    import dataclasses
     bricks = form == "bricks"
     make, M = SCENES[name]
     sc = make()
-    log("case %s n=%d bricks=%s shape=%s" % (name, sc.n, bricks, shape))
+    if delta:
+        sc = dataclasses.replace(sc, params=dataclasses.replace(sc.params, delta=delta))
+    log("case %s n=%d bricks=%s shape=%s delta=%s" % (name, sc.n, bricks, shape, delta))
     sim = make_sim(sc, max_neibs=M, brick=shape)
     sim.build()
     torch_sync()

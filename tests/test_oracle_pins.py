@@ -489,13 +489,14 @@ def _fd_dot(fun, st, vo, vu, vr, eps):
     return (fun(sp) - fun(sm)) / (2 * eps)
 
 
-@pytest.mark.parametrize("visc", [0, 1])
-def test_forces_reverse_matches_central_differences(visc):
+@pytest.mark.parametrize("visc,delta", [(0, 0.0), (1, 0.0), (0, 0.1), (1, 0.1)])
+def test_forces_reverse_matches_central_differences(visc, delta):
     """<J v, w> by central differences of the forward sums equals
     <v, J^T w> from the reverse, for random directions and upstream
-    adjoints, including the parameter derivatives (alpha, c0, nu)."""
+    adjoints, including the parameter derivatives (alpha, c0, nu), with and
+    without density diffusion."""
     sc = S.random_cloud(n=500, box=(0.16, 0.14, 0.14), dp=0.02, seed=41, boundary_frac=0.25, u_sigma=0.3,
-                        rho_sigma=0.01, alpha=0.3, visc_model=visc, nu=1e-3)
+                        rho_sigma=0.01, alpha=0.3, visc_model=visc, nu=1e-3, delta=delta)
     b = O.build_f32(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info)
     st = O.State.lift(b["cell"], b["pos"], b["vel"], b["info"])
     rng = np.random.default_rng(1)
