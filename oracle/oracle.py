@@ -31,7 +31,8 @@ class OrcParams(C.Structure):
     _fields_ = [("h", C.c_double), ("r_search", C.c_double), ("rho0", C.c_double),
                 ("gamma", C.c_double), ("c0", C.c_double), ("alpha", C.c_double),
                 ("eps_visc", C.c_double), ("nu", C.c_double), ("g", C.c_double * 3),
-                ("cfl", C.c_double), ("visc_model", C.c_int32), ("delta", C.c_double)]
+                ("cfl", C.c_double), ("visc_model", C.c_int32), ("delta", C.c_double),
+                ("kernel", C.c_int32), ("formulation", C.c_int32)]
 
 
 _lib = None
@@ -64,6 +65,9 @@ def lib():
         L.orc_integrate.restype = None
         L.orc_dt.argtypes = [P, i32, P, P, P, P]
         L.orc_dt.restype = C.c_double
+        for nm in ("orc_kernel_W", "orc_kernel_F", "orc_kernel_dF"):
+            getattr(L, nm).argtypes = [i32, C.c_double, C.c_double]
+            getattr(L, nm).restype = C.c_double
         L.orc_wendland_W.argtypes = [C.c_double, C.c_double]
         L.orc_wendland_W.restype = C.c_double
         L.orc_wendland_F.argtypes = [C.c_double, C.c_double]
@@ -119,6 +123,8 @@ def params_struct(p, alpha=None) -> OrcParams:
     q.cfl = rnd(p.cfl)
     q.visc_model = int(p.visc_model)
     q.delta = rnd(getattr(p, "delta", 0.0))
+    q.kernel = int(getattr(p, "kernel", 0))
+    q.formulation = int(getattr(p, "formulation", 0))
     return q
 
 
@@ -137,6 +143,25 @@ def wendland_W(r: float, h: float) -> float:
 
 def wendland_F(r: float, h: float) -> float:
     return lib().orc_wendland_F(float(r), float(h))
+
+
+# smoothing kernels of listing l:ktemplate (support 2h)
+WENDLAND, CUBIC_SPLINE, QUADRATIC, GAUSSIAN = 0, 1, 2, 3
+KERNELS = {"wendland": WENDLAND, "cubic_spline": CUBIC_SPLINE, "quadratic": QUADRATIC, "gaussian": GAUSSIAN}
+
+
+def kernel_W(kind: int, r: float, h: float) -> float:
+    return lib().orc_kernel_W(int(kind), float(r), float(h))
+
+
+def kernel_F(kind: int, r: float, h: float) -> float:
+    """F = (1/r) dW/dr."""
+    return lib().orc_kernel_F(int(kind), float(r), float(h))
+
+
+def kernel_dF(kind: int, r: float, h: float) -> float:
+    """dF/dr."""
+    return lib().orc_kernel_dF(int(kind), float(r), float(h))
 
 
 def pressure(params, rho: float) -> float:

@@ -51,9 +51,22 @@ typedef struct {
     double h, r_search, rho0, gamma, c0, alpha, eps_visc, nu;
     double g[3];
     double cfl;
-    int32_t visc_model; /* 0 artificial (Monaghan), 1 laminar (Morris) */
+    int32_t visc_model; /* laminar term added to Monaghan's artificial viscosity:
+                           0 none, 1 Morris, 2 Monaghan's K form */
     double delta;       /* Molteni-Colagrossi density diffusion coefficient (0: off) */
+    int32_t kernel;     /* smoothing kernel: 0 Wendland, 1 cubic spline, 2 quadratic, 3 Gaussian */
+    int32_t formulation; /* 0 golden rule (eq. mass-cont-sph1, ns-sph1), 1 Landrini-Morris
+                            (eq. mass-cont-sph2, ns-sph2) */
 } orc_params;
+
+enum { ORC_WENDLAND = 0, ORC_CUBIC_SPLINE = 1, ORC_QUADRATIC = 2, ORC_GAUSSIAN = 3 };
+
+/* K of Monaghan's laminar form in 3D (section "Minimizing complexity" leaves
+ * it open).  With the weight m_j/(rho_i rho_j) and the factor 2 mu_bar that
+ * the form carries, sum_j V_j (u_ij . x_ij) x_ij F_ij / r^2 tends to
+ * (lap u + 2 grad div u) / (2 (d + 2)), so the term reduces to nu lap u for a
+ * divergence-free flow when K = d + 2. */
+#define ORC_MONAGHAN_K 5.0
 
 #define ORC_TYPE_SHIFT 30
 #define ORC_BOUNDARY 1u
@@ -323,23 +336,97 @@ int orc_neighbors_rows(const orc_grid *g, float r_search, const int32_t *cell, c
  * Kernel and equation of state, double precision.
  * ------------------------------------------------------------------------ */
 
-/* 3D Wendland C2 with support 2h: W = aD (1 - q/2)^4 (2q + 1), aD = 21/(16 pi h^3)
- * (from unit integral).  F = (1/r) dW/dr = fD (q - 2)^3, fD = 105/(128 pi h^5). */
-double orc_wendland_W(double r, double h)
+/* Smoothing kernels of listing l:ktemplate, 3D, all with support 2h (the
+ * radius of the method), q = r/h, each normalised to unit integral (section
+ * "A lightning introduction to the method"); F = (1/r) dW/dr.
+ *   Wendland C2:  W = 21/(16 pi h^3) (1 - q/2)^4 (2q + 1)
+ *   cubic spline (Monaghan-Lattanzio M4):
+ *                 W = 1/(pi h^3) (1 - 3/2 q^2 + 3/4 q^3)   q < 1
+ *                                1/4 (2 - q)^3              1 <= q < 2
+ *   quadratic (Johnson, Stryk and Beissel):
+ *                 W = 5/(4 pi h^3) (3/16 q^2 - 3/4 q + 3/4)
+ *   Gaussian truncated at d = 2h (the listing's w(q) = exp(-q^2) - exp(-(d/h)^2)):
+ *                 W = C (exp(-q^2) - exp(-4)),
+ *                 1/C = 4 pi h^3 (sqrt(pi)/4 erf(2) - 11/3 exp(-4))
+ * The quadratic kernel's F = 15/(32 pi h^5) (1 - 2/q) is unbounded at r = 0;
+ * the Gaussian's F does not vanish at r = 2h (W does). */
+static double gaussian_norm(double h)
 {
-    const double q = r / h;
-    if (q >= 2.0) return 0.0;
-    const double a = 1.0 - 0.5 * q;
-    return 21.0 / (16.0 * M_PI * h * h * h) * a * a * a * a * (2.0 * q + 1.0);
+    const double e4 = exp(-4.0);
+    return 1.0 / (4.0 * M_PI * h * h * h * (0.25 * sqrt(M_PI) * erf(2.0) - 11.0 / 3.0 * e4));
 }
 
-double orc_wendland_F(double r, double h)
+double orc_kernel_W(int kind, double r, double h)
 {
     const double q = r / h;
     if (q >= 2.0) return 0.0;
-    const double b = q - 2.0;
-    return 105.0 / (128.0 * M_PI * h * h * h * h * h) * b * b * b;
+    const double h3 = h * h * h;
+    switch (kind) {
+    case ORC_WENDLAND: {
+        const double a = 1.0 - 0.5 * q;
+        return 21.0 / (16.0 * M_PI * h3) * a * a * a * a * (2.0 * q + 1.0);
+    }
+    case ORC_CUBIC_SPLINE:
+        if (q < 1.0) return (1.0 - 1.5 * q * q + 0.75 * q * q * q) / (M_PI * h3);
+        return 0.25 * (2.0 - q) * (2.0 - q) * (2.0 - q) / (M_PI * h3);
+    case ORC_QUADRATIC:
+        /* 3/16 q^2 - 3/4 q + 3/4 = 3/16 (2 - q)^2, factored for accuracy near q = 2 */
+        return 5.0 / (4.0 * M_PI * h3) * 0.1875 * (2.0 - q) * (2.0 - q);
+    case ORC_GAUSSIAN:
+        return gaussian_norm(h) * (exp(-q * q) - exp(-4.0));
+    }
+    return NAN;
 }
+
+/* F = (1/r) dW/dr, derived from W above. */
+double orc_kernel_F(int kind, double r, double h)
+{
+    const double q = r / h;
+    if (q >= 2.0) return 0.0;
+    const double h5 = h * h * h * h * h;
+    switch (kind) {
+    case ORC_WENDLAND: {
+        const double b = q - 2.0;
+        return 105.0 / (128.0 * M_PI * h5) * b * b * b;
+    }
+    case ORC_CUBIC_SPLINE:
+        /* dW/dq = (-3q + 9/4 q^2) and -3/4 (2 - q)^2, over pi h^3; F = dW/dq / (q h^2) */
+        if (q < 1.0) return (-3.0 + 2.25 * q) / (M_PI * h5);
+        return -0.75 * (2.0 - q) * (2.0 - q) / (q * M_PI * h5);
+    case ORC_QUADRATIC:
+        /* dW/dq = 5/(4 pi h^3) (3/8 q - 3/4) */
+        return 15.0 / (32.0 * M_PI * h5) * (1.0 - 2.0 / q);
+    case ORC_GAUSSIAN:
+        return -2.0 * gaussian_norm(h) / (h * h) * exp(-q * q);
+    }
+    return NAN;
+}
+
+/* dF/dr, the derivative of the function above (for the reverse pass). */
+double orc_kernel_dF(int kind, double r, double h)
+{
+    const double q = r / h;
+    if (q >= 2.0) return 0.0;
+    const double h6 = h * h * h * h * h * h;
+    switch (kind) {
+    case ORC_WENDLAND: {
+        const double b = q - 2.0;
+        return 3.0 * 105.0 / (128.0 * M_PI * h6) * b * b;
+    }
+    case ORC_CUBIC_SPLINE:
+        if (q < 1.0) return 2.25 / (M_PI * h6);
+        return 0.75 * (4.0 - q * q) / (q * q * M_PI * h6);
+    case ORC_QUADRATIC:
+        return 15.0 / (16.0 * M_PI * h6) / (q * q);
+    case ORC_GAUSSIAN:
+        return 4.0 * gaussian_norm(h) / (h * h * h) * q * exp(-q * q);
+    }
+    return NAN;
+}
+
+double orc_wendland_W(double r, double h) { return orc_kernel_W(ORC_WENDLAND, r, h); }
+
+double orc_wendland_F(double r, double h) { return orc_kernel_F(ORC_WENDLAND, r, h); }
 
 /* Cole's equation of state P = B ((rho/rho0)^gamma - 1), B = rho0 c0^2 / gamma,
  * and the sound speed c = sqrt(dP/drho) = c0 (rho/rho0)^((gamma-1)/2). */
@@ -374,11 +461,20 @@ static inline void separation(const orc_grid *g, int32_t cell_i, int32_t cell_j,
 
 /* ------------------------------------------------------------------------
  * Time derivatives (the "forces").  For central particle i and every
- * listed neighbour j with r_ij < 2h:
+ * listed neighbour j with r_ij < 2h, golden-rule formulation (eq.
+ * mass-cont-sph1, eq. ns-sph1):
  *   Drho_i/Dt = sum_j m_j (u_ij . x_ij) F_ij
- *   a_i       = -sum_j m_j (P_i/rho_i^2 + P_j/rho_j^2 + Pi_ij) x_ij F_ij
- *               [+ sum_j 4 nu m_j / (rho_i + rho_j) F_ij u_ij   (laminar)]
+ *   a_i       = -sum_j m_j (P_i/rho_i^2 + P_j/rho_j^2 + Pi_ij) x_ij F_ij + L_i
+ * or the Landrini-Morris formulation (eq. mass-cont-sph2, eq. ns-sph2):
+ *   Drho_i/Dt = sum_j (rho_i/rho_j) m_j (u_ij . x_ij) F_ij
+ *   a_i       = -sum_j m_j ((P_i + P_j)/(rho_i rho_j) + Pi_ij) x_ij F_ij + L_i
+ * with Monaghan's artificial viscosity
  *   Pi_ij     = -alpha h cbar (u_ij . x_ij) / (rhobar (r^2 + eps h^2)) if u_ij.x_ij < 0
+ * and the laminar term L_i of section "Minimizing complexity", weight
+ * m_j/(rho_i rho_j) and mu_bar = 2 rho_i rho_j nu/(rho_i + rho_j) (the
+ * harmonic mean of mu = rho nu):
+ *   Morris:     L_i = sum_j 4 nu m_j / (rho_i + rho_j) F_ij u_ij
+ *   Monaghan K: L_i = K sum_j 4 nu m_j / (rho_i + rho_j) F_ij (u_ij . x_ij) / (r^2 + eps h^2) x_ij
  * and, with delta > 0, for a fluid i and fluid j the density diffusion of
  * Molteni and Colagrossi (named among the dissipative terms of section "A
  * lightning introduction to the method" and the options of "The SPH in
@@ -387,6 +483,8 @@ static inline void separation(const orc_grid *g, int32_t cell_i, int32_t cell_j,
  * publication's, the paper does not print it):
  *   Drho_i/Dt += -2 delta h c0 sum_j (rho_j - rho_i) F_ij r^2 / (r^2 + eps h^2) m_j / rho_j
  * Gravity is not included (the integrator adds it to fluid particles).
+ * With the quadratic kernel a pair at r = 0 contributes nothing (its F is
+ * unbounded there).
  *
  * Also returned, per particle and component, the sum of the magnitudes of
  * the pair terms (every signed factor replaced by its absolute value, the dot
@@ -422,19 +520,30 @@ static int forces_of(const orc_params *p, const orc_grid *g, int i, const int32_
             const double r = sqrt(r2);
             if (!(r < two_h)) continue;
             ++inter;
-            const double F = orc_wendland_F(r, h);
+            if (p->kernel == ORC_QUADRATIC && r == 0.0) continue;
+            const double F = orc_kernel_F(p->kernel, r, h);
             const double mj = mass[j];
             const double rhoj = rho[j];
             const double Pj = orc_pressure(p, rhoj);
-            const double pj = Pj / (rhoj * rhoj);
             double u[3], ux = 0.0, uxabs = 0.0;
             for (int d = 0; d < 3; ++d) {
                 u[d] = vel[3 * (size_t)i + d] - vel[3 * (size_t)j + d];
                 ux += u[d] * x[d];
                 uxabs += fabs(u[d] * x[d]);
             }
-            dr += mj * ux * F;
-            sdr += mj * uxabs * fabs(F);
+            /* pressure factor and continuity weight of the formulation */
+            double pres, spres, wc;
+            if (p->formulation == 1) {
+                pres = (Pi + Pj) / (rhoi * rhoj);
+                spres = (fabs(Pi) + fabs(Pj)) / (rhoi * rhoj);
+                wc = rhoi / rhoj;
+            } else {
+                pres = pi + Pj / (rhoj * rhoj);
+                spres = fabs(pi) + fabs(Pj / (rhoj * rhoj));
+                wc = 1.0;
+            }
+            dr += wc * mj * ux * F;
+            sdr += wc * mj * uxabs * fabs(F);
             if (p->delta != 0.0 && central_fluid && k < nfi) {
                 /* density diffusion between fluid particles (Molteni and
                  * Colagrossi): delta h c0 sum_j psi_ij . grad_i W_ij V_j with
@@ -451,8 +560,8 @@ static int forces_of(const orc_params *p, const orc_grid *g, int i, const int32_
             double Pi_ij = 0.0;
             if (ux < 0.0) Pi_ij = -p->alpha * h * cbar * ux / visc_den;
             const double Pi_abs = p->alpha * h * cbar * uxabs / visc_den;
-            const double coef = -mj * (pi + pj + Pi_ij) * F;
-            const double scoef = mj * (fabs(pi) + fabs(pj) + Pi_abs) * fabs(F);
+            const double coef = -mj * (pres + Pi_ij) * F;
+            const double scoef = mj * (spres + Pi_abs) * fabs(F);
             for (int d = 0; d < 3; ++d) {
                 a[d] += coef * x[d];
                 sa[d] += scoef * fabs(x[d]);
@@ -462,6 +571,12 @@ static int forces_of(const orc_params *p, const orc_grid *g, int i, const int32_
                 for (int d = 0; d < 3; ++d) {
                     a[d] += lam * u[d];
                     sa[d] += fabs(lam * u[d]);
+                }
+            } else if (p->visc_model == 2) {
+                const double lk = ORC_MONAGHAN_K * 4.0 * p->nu * mj / (rhoi + rhoj) * F / (r2 + p->eps_visc * h2);
+                for (int d = 0; d < 3; ++d) {
+                    a[d] += lk * ux * x[d];
+                    sa[d] += fabs(lk) * uxabs * fabs(x[d]);
                 }
             }
         }
@@ -622,15 +737,21 @@ double orc_dt(const orc_params *p, int n, const int32_t *cell, const uint32_t *i
 /* ------------------------------------------------------------------------
  * Reverse (adjoint) of orc_forces with the lists held fixed.
  *
- * Forward pair term of central c and neighbour n (r < 2h):
- *   a_c += G x + Lm u,   Drho_c += m_n F w,
- *   G = -m_n (p_c + p_n + Pi) F,  Lm = 4 nu m_n F / (rho_c + rho_n) (laminar),
- *   w = u . x,  Pi = K min(w, 0) / (r^2 + eps h^2),  K = -alpha h (c_c + c_n)/(rho_c + rho_n).
- * Given the upstream adjoints abar_c (3) and dbar_c of every central, the
- * derivative of T = abar_c . (G x + Lm u) + dbar_c m_n F w with respect to
- * x = x_c - x_n, u = u_c - u_n, rho_c, rho_n and (alpha, c0, nu) is formed and
- * scattered: +x/+u to the central, -x/-u to the neighbour.  The switch of Pi at
- * w = 0 takes the derivative of the active branch (zero at w = 0).
+ * Forward pair term of central c and neighbour n (r < 2h), x = x_c - x_n,
+ * u = u_c - u_n, w = u . x:
+ *   a_c += G x + Lm u + Lk x,   Drho_c += Wc m_n F w,
+ *   G  = -m_n (S_p + Pi) F,
+ *   S_p = P_c/rho_c^2 + P_n/rho_n^2, Wc = 1              (golden rule)
+ *   S_p = (P_c + P_n)/(rho_c rho_n), Wc = rho_c/rho_n    (Landrini-Morris)
+ *   Pi = K_a min(w, 0) / (r^2 + eps h^2),  K_a = -alpha h (c_c + c_n)/(rho_c + rho_n),
+ *   Lm = 4 nu m_n F/(rho_c + rho_n)                        (Morris)
+ *   Lk = K 4 nu m_n F w/((rho_c + rho_n)(r^2 + eps h^2))  (Monaghan K form),
+ * plus the density diffusion of orc_forces.  Given the upstream adjoints
+ * abar_c (3) and dbar_c of every central, the derivative of
+ * T = abar_c . a_pair + dbar_c Drho_pair with respect to x, u, rho_c, rho_n
+ * and (alpha, c0, nu) is formed and scattered: +x/+u to the central, -x/-u
+ * to the neighbour.  The switch of Pi at w = 0 takes the derivative of the
+ * active branch (zero at w = 0).
  * Results are ADDED to go [n,3], gu [n,3], grho [n] and gparams[3].
  * ------------------------------------------------------------------------ */
 void orc_forces_reverse(const orc_params *p, const orc_grid *g, int n,
@@ -641,8 +762,7 @@ void orc_forces_reverse(const orc_params *p, const orc_grid *g, int n,
                         double *go, double *gu, double *grho, double *gparams)
 {
     const double h = p->h, two_h = 2.0 * h, eh2 = p->eps_visc * h * h;
-    const double fD = 105.0 / (128.0 * M_PI * h * h * h * h * h);
-    const double B = p->rho0 * p->c0 * p->c0 / p->gamma;
+    const int form2 = p->formulation == 1;
     double galpha = 0.0, gc0 = 0.0, gnu = 0.0;
     for (int c = 0; c < n; ++c) {
         if (cell[c] < 0) continue;
@@ -657,7 +777,6 @@ void orc_forces_reverse(const orc_params *p, const orc_grid *g, int n,
         const double db = dbar[c];
         const int total = nf[c] + nb[c];
         const int central_fluid = ptype(info[c]) != ORC_BOUNDARY;
-        (void)B;
         for (int k = 0; k < total; ++k) {
             const int m = k < nf[c] ? fl[(size_t)c * max_neibs + k]
                                     : bl[(size_t)c * max_neibs + (k - nf[c])];
@@ -666,11 +785,11 @@ void orc_forces_reverse(const orc_params *p, const orc_grid *g, int n,
             const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
             const double r = sqrt(r2);
             if (!(r < two_h)) continue;
+            if (p->kernel == ORC_QUADRATIC && r == 0.0) continue;
             for (int d = 0; d < 3; ++d) u[d] = vel[3 * (size_t)c + d] - vel[3 * (size_t)m + d];
             const double w = u[0] * x[0] + u[1] * x[1] + u[2] * x[2];
-            const double q = r / h;
-            const double F = fD * (q - 2.0) * (q - 2.0) * (q - 2.0);
-            const double dFdr = 3.0 * fD * (q - 2.0) * (q - 2.0) / h;
+            const double F = orc_kernel_F(p->kernel, r, h);
+            const double dFdr = orc_kernel_dF(p->kernel, r, h);
             const double mn = mass[m];
             const double rn = rho[m];
             const double Pn = orc_pressure(p, rn);
@@ -684,9 +803,27 @@ void orc_forces_reverse(const orc_params *p, const orc_grid *g, int n,
             const double mw = act ? w : 0.0;
             const double K = -p->alpha * h * (cc + cn) / rs;
             const double Pi = K * mw / dd;
-            const double S = pc + pn + Pi;
+            /* pressure factor, its rho derivatives, continuity weight */
+            double Sp, dSp_drc, dSp_drn, Wc, dWc_drc, dWc_drn;
+            if (form2) {
+                Sp = (Pc + Pn) / (rc * rn);
+                dSp_drc = cc * cc / (rc * rn) - Sp / rc;
+                dSp_drn = cn * cn / (rc * rn) - Sp / rn;
+                Wc = rc / rn;
+                dWc_drc = 1.0 / rn;
+                dWc_drn = -rc / (rn * rn);
+            } else {
+                Sp = pc + pn;
+                dSp_drc = dpc;
+                dSp_drn = dpn;
+                Wc = 1.0;
+                dWc_drc = dWc_drn = 0.0;
+            }
+            const double S = Sp + Pi;
             const double G = -mn * S * F;
             const double Lm = p->visc_model == 1 ? 4.0 * p->nu * mn * F / rs : 0.0;
+            const double kk = p->visc_model == 2 ? ORC_MONAGHAN_K * 4.0 * p->nu * mn / rs : 0.0;
+            const double Lk = kk * F * w / dd;
             const double A = ab[0] * x[0] + ab[1] * x[1] + ab[2] * x[2];
             const double Bu = ab[0] * u[0] + ab[1] * u[1] + ab[2] * u[2];
             double gx[3], gv[3];
@@ -697,14 +834,19 @@ void orc_forces_reverse(const orc_params *p, const orc_grid *g, int n,
                 const double dGdx = -mn * (S * dFdx + F * dPidx);
                 const double dGdu = -mn * F * dPidu;
                 const double dLdx = p->visc_model == 1 ? 4.0 * p->nu * mn * dFdx / rs : 0.0;
-                gx[d] = G * ab[d] + A * dGdx + Bu * dLdx + db * mn * (F * u[d] + w * dFdx);
-                gv[d] = Lm * ab[d] + A * dGdu + db * mn * F * x[d];
+                const double dLkdx = kk * (dFdx * w / dd + F * u[d] / dd - 2.0 * F * w * x[d] / (dd * dd));
+                const double dLkdu = kk * F * x[d] / dd;
+                gx[d] = (G + Lk) * ab[d] + A * (dGdx + dLkdx) + Bu * dLdx + db * Wc * mn * (F * u[d] + w * dFdx);
+                gv[d] = Lm * ab[d] + A * (dGdu + dLkdu) + db * Wc * mn * F * x[d];
             }
             const double dPi_drc = act ? -p->alpha * h * mw / dd * (dcc / rs - (cc + cn) / (rs * rs)) : 0.0;
             const double dPi_drn = act ? -p->alpha * h * mw / dd * (dcn / rs - (cc + cn) / (rs * rs)) : 0.0;
             const double dL_drho = p->visc_model == 1 ? -4.0 * p->nu * mn * F / (rs * rs) : 0.0;
-            const double grc = A * (-mn * F * (dpc + dPi_drc)) + Bu * dL_drho;
-            const double grn = A * (-mn * F * (dpn + dPi_drn)) + Bu * dL_drho;
+            const double dLk_drho = -Lk / rs;
+            const double grc = A * (-mn * F * (dSp_drc + dPi_drc) + dLk_drho) + Bu * dL_drho +
+                               db * dWc_drc * mn * w * F;
+            const double grn = A * (-mn * F * (dSp_drn + dPi_drn) + dLk_drho) + Bu * dL_drho +
+                               db * dWc_drn * mn * w * F;
             for (int d = 0; d < 3; ++d) {
                 go[3 * (size_t)c + d] += gx[d];
                 go[3 * (size_t)m + d] -= gx[d];
@@ -713,11 +855,12 @@ void orc_forces_reverse(const orc_params *p, const orc_grid *g, int n,
             }
             grho[c] += grc;
             grho[m] += grn;
-            /* Pi is proportional to alpha and to c0; P/rho^2 to c0^2 */
+            /* Pi is proportional to alpha and to c0; the pressure factor to c0^2 */
             const double Pi_over_alpha = -h * (cc + cn) / rs * mw / dd;
             galpha += A * (-mn * F) * Pi_over_alpha;
-            gc0 += A * (-mn * F) * (2.0 * pc + 2.0 * pn + Pi) / p->c0;
+            gc0 += A * (-mn * F) * (2.0 * Sp + Pi) / p->c0;
             if (p->visc_model == 1) gnu += Bu * 4.0 * mn * F / rs;
+            if (p->visc_model == 2) gnu += A * ORC_MONAGHAN_K * 4.0 * mn / rs * F * w / dd;
             if (p->delta != 0.0 && central_fluid && k < nf[c]) {
                 /* density diffusion, term = cD m_n (rho_c - rho_n)/rho_n Gd(r),
                  * Gd = F r^2 / (r^2 + eps h^2), cD = 2 delta h c0 */

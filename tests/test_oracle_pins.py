@@ -263,12 +263,13 @@ def _forces(sc):
     return b, st, acc, drho, sa, sd, ni
 
 
-@pytest.mark.parametrize("visc", [0, 1])
-def test_momentum_antisymmetry(visc):
+@pytest.mark.parametrize("visc,kernel,form", [(0, 0, 0), (1, 0, 0), (2, 0, 0), (2, 1, 1), (1, 3, 1), (0, 2, 1)])
+def test_momentum_antisymmetry(visc, kernel, form):
     """Pair forces are antisymmetric: sum_i m_i a_i = 0 (fluid-boundary pairs
-    counted from both sides, boundary-boundary pairs from neither)."""
+    counted from both sides, boundary-boundary pairs from neither), for every
+    laminar form, kernel and formulation."""
     sc = S.random_cloud(n=1200, box=(0.25, 0.2, 0.2), dp=0.02, seed=21, boundary_frac=0.3,
-                        visc_model=visc, nu=1e-3)
+                        visc_model=visc, nu=1e-3, kernel=kernel, formulation=form)
     b, st, acc, drho, sa, sd, ni = _forces(sc)
     m = st.mass[:, None]
     tot = np.abs((m * acc).sum(axis=0))
@@ -287,7 +288,7 @@ def test_angular_momentum_of_central_forces():
     assert np.all(np.abs(L) <= 1e-13 * scale)
 
 
-@pytest.mark.parametrize("visc", [0, 1])
+@pytest.mark.parametrize("visc", [0, 1, 2])
 def test_viscous_dissipation(visc):
     """With pressure off (uniform rest density), viscosity never adds kinetic
     energy: sum_i m_i u_i . a_i <= 0, and it is strictly negative here."""
@@ -358,14 +359,17 @@ def test_small_g_hydrostatic_lattice():
     assert np.all(np.abs(acc[bulk, :2]) < 1e-5 * g)
 
 
-@pytest.mark.parametrize("visc,lam", [(0, 2.0), (0, 0.25), (1, 4.0)])
-def test_change_of_length_unit(visc, lam):
+@pytest.mark.parametrize("visc,lam,kernel,form", [(0, 2.0, 0, 0), (0, 0.25, 0, 0), (1, 4.0, 0, 0),
+                                                   (2, 2.0, 1, 0), (1, 0.5, 2, 1), (2, 4.0, 3, 1)])
+def test_change_of_length_unit(visc, lam, kernel, form):
     """Dimensional consistency: measuring lengths in a unit lam times smaller
     (positions, h, r_s, cell sizes, u, c0, g scale by lam, masses by lam^3,
     nu by lam^2) multiplies accelerations by lam and leaves Drho/Dt unchanged.
-    lam is a power of two, so the float32 encoding scales exactly."""
+    lam is a power of two, so the float32 encoding scales exactly.  Pins the
+    powers of h in every kernel's normalisation."""
     sc = S.random_cloud(n=800, box=(0.2, 0.2, 0.2), dp=0.02, seed=31, boundary_frac=0.25,
-                        u_sigma=0.2, rho_sigma=0.01, visc_model=visc, nu=2e-3, alpha=0.3)
+                        u_sigma=0.2, rho_sigma=0.01, visc_model=visc, nu=2e-3, alpha=0.3, kernel=kernel,
+                        formulation=form)
     b, st, acc, drho, sa, sd, ni = _forces(sc)
     import copy
     g2 = copy.deepcopy(sc.grid)
@@ -489,14 +493,18 @@ def _fd_dot(fun, st, vo, vu, vr, eps):
     return (fun(sp) - fun(sm)) / (2 * eps)
 
 
-@pytest.mark.parametrize("visc,delta", [(0, 0.0), (1, 0.0), (0, 0.1), (1, 0.1)])
-def test_forces_reverse_matches_central_differences(visc, delta):
+@pytest.mark.parametrize("visc,delta,kernel,form", [(0, 0.0, 0, 0), (1, 0.0, 0, 0), (0, 0.1, 0, 0), (1, 0.1, 0, 0),
+                                                     (2, 0.0, 0, 0), (0, 0.0, 1, 0), (0, 0.0, 2, 0), (0, 0.0, 3, 0),
+                                                     (0, 0.0, 0, 1), (1, 0.1, 1, 1), (2, 0.1, 3, 1), (2, 0.0, 2, 1)])
+def test_forces_reverse_matches_central_differences(visc, delta, kernel, form):
     """<J v, w> by central differences of the forward sums equals
     <v, J^T w> from the reverse, for random directions and upstream
     adjoints, including the parameter derivatives (alpha, c0, nu), with and
-    without density diffusion."""
+    without density diffusion, for the laminar forms, kernels and
+    formulations."""
     sc = S.random_cloud(n=500, box=(0.16, 0.14, 0.14), dp=0.02, seed=41, boundary_frac=0.25, u_sigma=0.3,
-                        rho_sigma=0.01, alpha=0.3, visc_model=visc, nu=1e-3, delta=delta)
+                        rho_sigma=0.01, alpha=0.3, visc_model=visc, nu=1e-3, delta=delta, kernel=kernel,
+                        formulation=form)
     b = O.build_f32(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info)
     st = O.State.lift(b["cell"], b["pos"], b["vel"], b["info"])
     rng = np.random.default_rng(1)

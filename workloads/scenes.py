@@ -60,8 +60,10 @@ class Params:
     nu: float = 0.0
     g: tuple = (0.0, 0.0, -9.81)
     cfl: float = 0.3
-    visc_model: int = 0         # 0 = artificial (Monaghan), 1 = laminar (Morris)
+    visc_model: int = 0         # laminar term: 0 none (artificial only), 1 Morris, 2 Monaghan K form
     delta: float = 0.0          # density diffusion coefficient (0 = off)
+    kernel: int = 0             # 0 Wendland, 1 cubic spline, 2 quadratic, 3 Gaussian
+    formulation: int = 0        # 0 golden rule, 1 Landrini-Morris
 
 
 @dataclass
