@@ -5,8 +5,10 @@
  * arXiv:2207.11328 (section "From theory to implementation"): a neighbour
  * search (re-bin, sort by cell, cell ranges, per-particle neighbour list), the
  * time derivatives ("forces": continuity, Cole equation of state, golden-rule
- * pressure gradient plus artificial or laminar viscosity, Wendland kernel) and
- * a predictor/corrector integrator; plus the adjoint of the derivatives.
+ * or Landrini-Morris pressure gradient plus artificial and optional laminar
+ * viscosity, density diffusion, Wendland, cubic-spline, quadratic or Gaussian
+ * kernel) and a predictor/corrector integrator; plus the adjoint of the
+ * derivatives.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -108,8 +110,27 @@ typedef struct {
     int32_t brick[3];
 } sph_grid;
 
+/* Smoothing kernels (listing l:ktemplate), all of support 2h, q = r/h,
+ * normalised to unit integral in 3D, F = (1/r) dW/dr:
+ *   SPH_KERNEL_WENDLAND      W = 21/(16 pi h^3) (1 - q/2)^4 (2q + 1)
+ *   SPH_KERNEL_CUBIC_SPLINE  W = 1/(pi h^3) (1 - 3/2 q^2 + 3/4 q^3) for q < 1,
+ *                                1/(4 pi h^3) (2 - q)^3 for 1 <= q < 2
+ *   SPH_KERNEL_QUADRATIC     W = 15/(64 pi h^3) (2 - q)^2 (pairs at r = 0,
+ *                                where its F is unbounded, contribute nothing)
+ *   SPH_KERNEL_GAUSSIAN      W = C (exp(-q^2) - exp(-4)), the Gaussian
+ *                                truncated at d = 2h, 1/C = 4 pi h^3
+ *                                (sqrt(pi)/4 erf(2) - 11/3 exp(-4)) */
+enum { SPH_KERNEL_WENDLAND = 0, SPH_KERNEL_CUBIC_SPLINE = 1, SPH_KERNEL_QUADRATIC = 2, SPH_KERNEL_GAUSSIAN = 3 };
+
+/* Laminar viscosity term (section "Minimizing complexity"), added to the
+ * artificial viscosity: none, Morris, or Monaghan's K form with K = 5. */
+enum { SPH_VISC_ARTIFICIAL = 0, SPH_VISC_MORRIS = 1, SPH_VISC_MONAGHAN_K = 2 };
+
+/* Formulation of the continuity and momentum sums. */
+enum { SPH_FORM_GOLDEN_RULE = 0, SPH_FORM_LANDRINI_MORRIS = 1 };
+
 /* Physical and numerical parameters.
- *   h          smoothing length; the Wendland kernel has support 2h
+ *   h          smoothing length; every kernel has support 2h
  *   r_search   neighbour search radius (>= 2h; the excess is the skin that
  *              lets the list be reused for several steps)
  *   rho0, gamma, c0   Cole equation of state P = B((rho/rho0)^gamma - 1),
@@ -118,9 +139,14 @@ typedef struct {
  *              Pi_ij = -alpha h cbar (u_ij.x_ij) / (rhobar (r^2 + eps h^2))
  *              for approaching pairs, cbar and rhobar arithmetic means
  *              (always applied; alpha = 0 disables it)
- *   nu         kinematic viscosity of the Morris laminar term
- *              sum_j 4 nu m_j / (rho_i + rho_j) F_ij u_ij, added when
- *              visc_model = 1 (visc_model 0: no laminar term)
+ *   nu, visc_model   kinematic viscosity and laminar term, weight
+ *              m_j/(rho_i rho_j) and mu_bar the harmonic mean of rho nu:
+ *              SPH_VISC_MORRIS:     sum_j 4 nu m_j / (rho_i + rho_j) F_ij u_ij
+ *              SPH_VISC_MONAGHAN_K: K sum_j 4 nu m_j / (rho_i + rho_j) F_ij
+ *                                   (u_ij.x_ij) / (r^2 + eps h^2) x_ij, K = 5
+ *                                   (d + 2: the term tends to nu lap u for
+ *                                   a divergence-free flow)
+ *              SPH_VISC_ARTIFICIAL: no laminar term
  *   g          body acceleration added to fluid particles by the integrator
  *   cfl        time-step safety factor
  *   delta      density diffusion of Molteni and Colagrossi (the mass
@@ -128,13 +154,18 @@ typedef struct {
  *              to the method", used by the paper's test cases), between
  *              fluid particles only:
  *              Drho_i/Dt += -2 delta h c0 sum_j (rho_j - rho_i) F_ij r^2 /
- *                           (r^2 + eps h^2) m_j / rho_j;  0 disables it */
+ *                           (r^2 + eps h^2) m_j / rho_j;  0 disables it
+ *   kernel     SPH_KERNEL_* (0, Wendland, for a zero-initialised struct)
+ *   formulation  SPH_FORM_GOLDEN_RULE (eq. mass-cont-sph1, eq. ns-sph1) or
+ *              SPH_FORM_LANDRINI_MORRIS (eq. mass-cont-sph2, eq. ns-sph2) */
 typedef struct {
     float h, r_search, rho0, gamma, c0, alpha, eps_visc, nu;
     float g[3];
     float cfl;
     int32_t visc_model;
     float delta;
+    int32_t kernel;
+    int32_t formulation;
 } sph_params;
 
 /* Particle arrays (device pointers), see the conventions above. */
@@ -215,13 +246,18 @@ sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
                                void *workspace, size_t workspace_bytes, void *stream);
 
 /* Time derivatives (eq. mass-cont-sph1 and eq. ns-sph1 with the readings of
- * the design notes; Wendland kernel of listing l:ktemplate).  For every
- * particle i < parts->n and every listed neighbour j with r_ij < 2h:
+ * the design notes, or eq. mass-cont-sph2 and eq. ns-sph2; kernels of
+ * listing l:ktemplate).  For every particle i < parts->n and every listed
+ * neighbour j with r_ij < 2h, golden rule:
  *   Drho_i/Dt = sum_j m_j (u_ij . x_ij) F_ij
  *   a_i = -sum_j m_j (P_i/rho_i^2 + P_j/rho_j^2 + Pi_ij) x_ij F_ij
- *         [+ sum_j 4 nu m_j/(rho_i + rho_j) F_ij u_ij  for visc_model 1]
- * [and the density diffusion term of sph_params.delta]
- * with F = (105 / (128 pi h^5)) (q - 2)^3, q = r/h.  Gravity is excluded.
+ * Landrini-Morris:
+ *   Drho_i/Dt = sum_j (rho_i/rho_j) m_j (u_ij . x_ij) F_ij
+ *   a_i = -sum_j m_j ((P_i + P_j)/(rho_i rho_j) + Pi_ij) x_ij F_ij
+ * plus the laminar term of visc_model and the density diffusion term of
+ * delta, with F of params->kernel (Wendland: F = 105/(128 pi h^5) (q - 2)^3).
+ * Every combination of kernel, formulation, laminar term and diffusion is a
+ * compiled instance of its own.  Gravity is excluded.
  * forces: device float[capacity][4], xyz = a_i [m/s^2], w = Drho_i/Dt,
  * fully overwritten for i < n.  Particles are read in the order of the last
  * build; positions may have drifted since (lists are reused).
@@ -238,7 +274,9 @@ sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
  * workspace: device buffer of sph_forces_workspace_bytes(capacity, n_cells)
  * bytes (per-particle equation-of-state terms and the list of bricks that
  * hold particles, both recomputed by every call).
- * Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
+ * Errors: SPH_ERR_ARG (also for an unknown kernel, formulation or
+ * visc_model, a negative or non-finite delta, or delta > 0 without
+ * parts->info), SPH_ERR_WORKSPACE. */
 sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
                       const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
                       const int32_t *cell_start, const int32_t *cell_end,
@@ -305,9 +343,11 @@ size_t sph_forces_backward_workspace_bytes(int32_t capacity, int32_t n_cells);
  * by brick of cells from LDS (each brick in two halves along y); without them
  * one lane per particle gathers from global memory.  The two agree to
  * rounding.  workspace: sph_forces_backward_workspace_bytes(capacity,
- * n_cells).  The density diffusion term (params->delta) is differentiated
- * too; its coefficient enters dL/dc0.  Errors: SPH_ERR_ARG (also for a grid
- * with a per-cell alpha table), SPH_ERR_WORKSPACE. */
+ * n_cells).  Every kernel, formulation and laminar term of sph_forces is
+ * differentiated, and the density diffusion term (params->delta) too; its
+ * coefficient enters dL/dc0, the laminar terms dL/dnu.  Errors: SPH_ERR_ARG
+ * (as for sph_forces, and for a grid with a per-cell alpha table),
+ * SPH_ERR_WORKSPACE. */
 sph_status sph_forces_backward(const sph_grid *grid, const sph_params *params,
                                const sph_particles *parts, const uint32_t *neibs,
                                const uint32_t *neib_count, int32_t max_neibs,

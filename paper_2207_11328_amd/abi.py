@@ -40,7 +40,14 @@ class SphGrid(C.Structure):
 class SphParams(C.Structure):
     _fields_ = [("h", C.c_float), ("r_search", C.c_float), ("rho0", C.c_float), ("gamma", C.c_float),
                 ("c0", C.c_float), ("alpha", C.c_float), ("eps_visc", C.c_float), ("nu", C.c_float),
-                ("g", C.c_float * 3), ("cfl", C.c_float), ("visc_model", C.c_int32), ("delta", C.c_float)]
+                ("g", C.c_float * 3), ("cfl", C.c_float), ("visc_model", C.c_int32), ("delta", C.c_float),
+                ("kernel", C.c_int32), ("formulation", C.c_int32)]
+
+
+# sph_params.kernel / visc_model / formulation values (include/sph.h)
+KERNEL_WENDLAND, KERNEL_CUBIC_SPLINE, KERNEL_QUADRATIC, KERNEL_GAUSSIAN = 0, 1, 2, 3
+VISC_ARTIFICIAL, VISC_MORRIS, VISC_MONAGHAN_K = 0, 1, 2
+FORM_GOLDEN_RULE, FORM_LANDRINI_MORRIS = 0, 1
 
 
 class SphParticles(C.Structure):
@@ -147,6 +154,8 @@ def params_struct(p, alpha=None) -> SphParams:
     q.cfl = p.cfl
     q.visc_model = int(p.visc_model)
     q.delta = float(getattr(p, "delta", 0.0))
+    q.kernel = int(getattr(p, "kernel", KERNEL_WENDLAND))
+    q.formulation = int(getattr(p, "formulation", FORM_GOLDEN_RULE))
     return q
 
 

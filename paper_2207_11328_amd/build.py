@@ -14,7 +14,12 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libsph.so")
-SOURCES = ["neighbors.hip", "forces.hip", "forces_backward.hip", "integrate.hip"]
+# (source, object, extra defines): the pair loops are compiled once per
+# smoothing kernel so the instances of the four kernels build in parallel
+PAIR_SOURCES = ["forces_pairs.hip", "forces_backward_pairs.hip"]
+SOURCES = ([(s, s.replace(".hip", ".o"), []) for s in
+            ["neighbors.hip", "forces.hip", "forces_backward.hip", "integrate.hip"]] +
+           [(s, s.replace(".hip", "_k%d.o" % k), ["-DSPH_KERNEL_KIND=%d" % k]) for s in PAIR_SOURCES for k in range(4)])
 ARCH = "gfx950"
 
 
@@ -35,15 +40,16 @@ def flags() -> list:
     ]
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 0) -> str:
     cc = hipcc()
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
+    jobs = jobs or max(1, min(len(SOURCES), os.cpu_count() or 1, 16))
     procs = []
     objs = []
-    for src in SOURCES:
-        obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [cc] + flags() + ["-c", os.path.join(CSRC, src), "-o", obj]
+    for src, oname, defs in SOURCES:
+        obj = os.path.join(objdir, oname)
+        cmd = [cc] + flags() + defs + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))

@@ -1,0 +1,459 @@
+// Pair loops of the time derivatives ("forces"): continuity, pressure
+// gradient, artificial and laminar viscosity, density diffusion, for the
+// smoothing kernel SPH_KERNEL_KIND (arXiv:2207.11328, eq. mass-cont-sph1,
+// eq. ns-sph1, eq. mass-cont-sph2, eq. ns-sph2, section "Minimizing
+// complexity", listing l:ktemplate).  This file is compiled once per kernel;
+// each object holds every formulation / laminar term / diffusion instance of
+// its kernel, in both kernel forms (global gather and LDS brick).
+//
+// Layout of the work on gfx950:
+// * One lane per central particle; the list is neighbour-major inside tiles
+//   of 64 particles, so slot k of a wave is one contiguous 256-byte row and
+//   its address is one 32-bit offset from the lane's tile base.
+// * The trip count is the wave's largest list (a scalar), lanes past their
+//   own count are masked, and fluid and boundary segments are walked in one
+//   loop (slot k < nf from the front, the rest from the back), so there is
+//   no divergent control flow in the pair loop.
+// * Loads are software-pipelined: list entries two pairs ahead, neighbour
+//   data one pair ahead, so each wave keeps several gathers in flight.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "forces_common.h"
+
+#ifndef SPH_KERNEL_KIND
+#error "compile with SPH_KERNEL_KIND set to one of the SPH_KERNEL_* values"
+#endif
+
+using namespace sph;
+
+namespace {
+
+constexpr int kThreads = 256;
+// pairs in flight per lane in the derivative loop
+#ifndef SPH_FORCES_DEPTH
+#define SPH_FORCES_DEPTH 4
+#endif
+constexpr int kDepth = SPH_FORCES_DEPTH;
+
+struct PairAcc {
+    float ax, ay, az, dr;
+};
+
+// One pair (i, j) of the derivative sums, branch-free; contributes only when
+// `valid` (slot inside i's list) and r < 2h.  mcj = m_j times the kernel
+// coefficient c of F = c f(q); ai.y, aj.y = alpha h c / 2 (so the mean of
+// the sound speeds and the min(u.x, 0) of Monaghan's term come out of one
+// sum and one subtraction: (ai.y + aj.y)(w - |w|) = alpha h (c_i + c_j) min(w, 0));
+// ai.x, aj.x = P/rho^2 (golden rule) or P (Landrini-Morris).
+// pair_fluid: both particles are fluid (density diffusion applies).
+template <int MODEL>
+__device__ __forceinline__ void pair_core(PairAcc &A, float xx, float xy, float xz, const float4 &vi,
+                                          const float2 &ai, float mcj, const float4 &vj, const float2 &aj,
+                                          bool valid, bool pair_fluid, const ForceConst &C)
+{
+    constexpr int KER = model_kernel(MODEL);
+    const float r2 = fmaf(xx, xx, fmaf(xy, xy, xz * xz));
+    bool inter = valid && (r2 < C.lim2);
+    if constexpr (KER == SPH_KERNEL_QUADRATIC) inter = inter && r2 > 0.0f;  // its F is unbounded at r = 0
+    const float r = __builtin_amdgcn_sqrtf(r2);
+    const float mF = kernel_mF<KER>(mcj, r, r2, C.inv_h, C.inv_h2);  // m_j F_ij
+    const float ux = vi.x - vj.x;
+    const float uy = vi.y - vj.y;
+    const float uz = vi.z - vj.z;
+    const float udx = fmaf(ux, xx, fmaf(uy, xy, uz * xz));
+    float pres;
+    if constexpr (MODEL & kLandrini) {
+        // (P_i + P_j)/(rho_i rho_j) and the continuity weight rho_i/rho_j
+        const float inv_rj = __builtin_amdgcn_rcpf(vj.w);
+        pres = (ai.x + aj.x) * (inv_rj * __builtin_amdgcn_rcpf(vi.w));
+        A.dr = inter ? fmaf(mF * (vi.w * inv_rj), udx, A.dr) : A.dr;
+    } else {
+        pres = ai.x + aj.x;
+        A.dr = inter ? fmaf(mF, udx, A.dr) : A.dr;
+    }
+    // Monaghan: Pi = -alpha h (c_i + c_j)/2 min(u.x, 0) / ((rho_i + rho_j)/2 (r^2 + eps h^2))
+    const float den = (vi.w + vj.w) * (r2 + C.eps_h2);
+    float vnum = -(ai.y + aj.y) * (udx - fabsf(udx));
+    // laminar K form: + 4 K nu m_j F (u.x) / ((rho_i + rho_j)(r^2 + eps h^2)) x, the same denominator
+    if constexpr (model_visc(MODEL) == kMonaghanK) vnum = fmaf(-C.k_four_nu, udx, vnum);
+    const float visc = vnum * __builtin_amdgcn_rcpf(den);
+    const float coef = inter ? -mF * (pres + visc) : 0.0f;
+    A.ax = fmaf(coef, xx, A.ax);
+    A.ay = fmaf(coef, xy, A.ay);
+    A.az = fmaf(coef, xz, A.az);
+    if constexpr (model_visc(MODEL) == kMorris) {
+        const float lam = inter ? C.four_nu * mF * __builtin_amdgcn_rcpf(vi.w + vj.w) : 0.0f;
+        A.ax = fmaf(lam, ux, A.ax);
+        A.ay = fmaf(lam, uy, A.ay);
+        A.az = fmaf(lam, uz, A.az);
+    }
+    if constexpr (MODEL & kDiffusion) {
+        // Molteni-Colagrossi: 2 delta h c0 (rho_i - rho_j) m_j F r^2 / ((r^2 + eps h^2) rho_j)
+        const float dd = C.diff * (vi.w - vj.w) * mF * r2 * __builtin_amdgcn_rcpf((r2 + C.eps_h2) * vj.w);
+        A.dr = (inter && pair_fluid) ? A.dr + dd : A.dr;
+    }
+}
+
+template <int MODEL>
+__device__ __forceinline__ void pair_terms(PairAcc &A, uint32_t e, const float4 &pi, const float4 &vi,
+                                           const float2 &ai, const float4 &pj, const float4 &vj, const float2 &aj,
+                                           bool valid, bool pair_fluid, const ForceConst &C)
+{
+    // separation, bit-identical to the list predicate: x = k cs + (o_i - o_j)
+    const float xx = fmaf(entry_k(e, 0), C.csx, pi.x - pj.x);
+    const float xy = fmaf(entry_k(e, 1), C.csy, pi.y - pj.y);
+    const float xz = fmaf(entry_k(e, 2), C.csz, pi.z - pj.z);
+    pair_core<MODEL>(A, xx, xy, xz, vi, ai, pj.w * C.fcoeff, vj, aj, valid, pair_fluid, C);
+}
+
+// Pairs of one lane's list gathered from global memory, in list order.
+// Software pipeline over a ring of D pair slots, unrolled by D: slot s holds
+// the neighbour data of pair k + s (requested D pairs before it is used) and
+// the list entry of pair k + s + D (requested 2 D pairs ahead).  Neighbour
+// data registers are only ever written by loads, so the loop carries no copy
+// of an in-flight value.
+template <int MODEL, int D>
+__device__ __forceinline__ void gather_pairs(PairAcc &A, const uint32_t *tile, int nf, int nt, int ntw, int M,
+                                             uint32_t jmax, const float4 *__restrict__ pos,
+                                             const float4 *__restrict__ vel, const float2 *__restrict__ aux,
+                                             const float4 &pi, const float4 &vi, const float2 &ai,
+                                             bool central_fluid, const ForceConst &C)
+{
+    const int last = max(nt - 1, 0);
+    uint32_t e[D], en[D];
+    float4 P[D], V[D];
+    float2 X[D];
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+        e[s] = tile[list_slot(s, nf, last, M) * kWave];
+        en[s] = tile[list_slot(s + D, nf, last, M) * kWave];
+    }
+#pragma unroll
+    for (int s = 0; s < D; ++s) {
+        const uint32_t j = min(e[s] & kIndexMask, jmax);
+        P[s] = pos[j];
+        V[s] = vel[j];
+        X[s] = aux[j];
+    }
+    for (int k = 0; k < ntw; k += D) {
+#pragma unroll
+        for (int s = 0; s < D; ++s) {
+            pair_terms<MODEL>(A, e[s], pi, vi, ai, P[s], V[s], X[s], k + s < nt, central_fluid && k + s < nf, C);
+            e[s] = en[s];
+            const uint32_t j = min(e[s] & kIndexMask, jmax);
+            P[s] = pos[j];
+            V[s] = vel[j];
+            X[s] = aux[j];
+            en[s] = tile[list_slot(k + s + 2 * D, nf, last, M) * kWave];
+        }
+    }
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__restrict__ pos,
+                                                     const float4 *__restrict__ vel,
+                                                     const float2 *__restrict__ aux,
+                                                     const uint32_t *__restrict__ neibs,
+                                                     const uint32_t *__restrict__ count,
+                                                     const uint32_t *__restrict__ info,
+                                                     float4 *__restrict__ out, ForceConst C)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    const int lane = threadIdx.x % kWave;
+    const int ii = min(i, n - 1);  // lanes past the end load in bounds and store nothing
+    const int M = C.max_neibs;
+    const uint32_t cnt = i < n ? count[i] : 0u;
+    // counts and indices are clamped: a stale or foreign list gives wrong
+    // numbers but never an out-of-bounds access
+    const int nf = min((int)(cnt & 0xFFFFu), M);
+    const int nt = min(nf + (int)(cnt >> 16), M);
+    const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
+    if (ntw == 0) {
+        if (i < n) out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        return;
+    }
+    // a wave is exactly one 64-particle tile of the list (wave-uniform base)
+    const int tile_id = __builtin_amdgcn_readfirstlane(i / kWave);
+    const uint32_t *tile = neibs + (size_t)tile_id * (kWave * M);
+    const uint32_t jmax = (uint32_t)(n - 1);
+
+    const float4 pi = pos[ii];
+    const float4 vi = vel[ii];
+    const float2 ai = aux[ii];
+    PairAcc A = {0.0f, 0.0f, 0.0f, 0.0f};
+
+    const bool central_fluid = (MODEL & kDiffusion) ? ptype(info[ii]) != kBoundary : true;
+    gather_pairs<MODEL, kDepth>(A, tile + lane, nf, nt, ntw, M, jmax, pos, vel, aux, pi, vi, ai, central_fluid, C);
+    if (i < n) out[i] = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// ---------------------------------------------------------------------------
+// Cell-brick variant of the derivative kernel (the cell perspective of section
+// "Changing perspective: from the particle to the cell" applied to the
+// derivatives).  A workgroup owns a brick of cells; it first copies
+// the particles of the brick and of its one-cell halo (every possible
+// neighbour of its particles) from HBM/L2 into LDS with coalesced loads, one
+// contiguous cell range after another, then each lane walks the list of one
+// central particle of the brick and reads the neighbour data from LDS.  The
+// 64 lanes of a wave read neighbours scattered over dozens of cache lines,
+// which the global-gather kernel pays in L1/L2 request throughput.
+//
+// The lists are the brick-local ones of the build: entry k is the
+// neighbour's LDS slot itself (uint16, fluid then boundary contiguous), so a
+// pair costs no index decoding.  Staged positions are relative to the centre
+// cell of the brick, o + s cs with s in {-2, ..., 2} per axis, so the
+// separation is one subtraction: its rounding error is a few ulp of 2.5 cs,
+// not of cs (the list predicate, which must be exact, is not evaluated here;
+// the r < 2h mask only differs from the exact one where the kernel weight is
+// of order 1e-20).  A brick whose halo does not fit in LDS reads the global
+// lists and the global state with the arithmetic of k_forces.
+
+// Pairs of one lane's brick-local list, read from LDS.  The list arrives in
+// 16-byte groups of 8 entries (one load per 8 pairs), requested two groups
+// ahead; the staged data of pair k + R is requested while pair k is computed
+// (a ring of R slots, R dividing 8 so the ring phase is the same in every
+// group).
+#ifndef SPH_BRICK_RING
+#define SPH_BRICK_RING 2
+#endif
+constexpr int kRing = SPH_BRICK_RING;
+static_assert(kBrickGroup % kRing == 0, "ring must divide the group");
+
+template <int MODEL, int NT>
+__device__ __forceinline__ void brick_pairs_lds(PairAcc &A, const uint4 *lg, int nt, int ntw, int total,
+                                                const float4 *__restrict__ sP, const float4 *__restrict__ sV,
+                                                const float2 *__restrict__ sA, const float4 &pi, const float4 &vi,
+                                                const float2 &ai, const ForceConst &C)
+{
+    constexpr int GS = kWave;  // uint4 stride between groups of one lane
+    const int lastg = max(nt - 1, 0) / kBrickGroup;
+    const uint32_t smax = (uint32_t)(total - 1);
+    float4 P[kRing], V[kRing];
+    float2 X[kRing];
+    auto fetch = [&](uint32_t slot, float4 &p, float4 &v, float2 &x) {
+        const uint32_t sl = min(slot, smax);  // a stale list stays inside the staged range
+        p = sP[sl];
+        v = sV[sl];
+        x = sA[sl];
+    };
+    uint4 gc = lg[0];
+    uint4 gn = lg[min(1, lastg) * GS];
+#pragma unroll
+    for (int r = 0; r < kRing; ++r) fetch(group_entry(gc, r), P[r], V[r], X[r]);
+    for (int k = 0; k < ntw; k += kBrickGroup) {
+        const uint4 gnn = lg[min(k / kBrickGroup + 2, lastg) * GS];
+#pragma unroll
+        for (int s = 0; s < kBrickGroup; ++s) {
+            const int r = s % kRing;
+            // staged w = +-(m_j x kernel coefficient), negative for boundary particles
+            pair_core<MODEL>(A, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, vi, ai, fabsf(P[r].w), V[r], X[r],
+                            k + s < nt, pi.w > 0.0f && P[r].w > 0.0f, C);
+            const int s2 = s + kRing;
+            fetch(s2 < kBrickGroup ? group_entry(gc, s2) : group_entry(gn, s2 - kBrickGroup), P[r], V[r], X[r]);
+        }
+        gc = gn;
+        gn = gnn;
+    }
+}
+
+template <int MODEL, int BX, int BY, int BZ, int NT, int CAP>
+__global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__restrict__ pos,
+                                                     const float4 *__restrict__ vel,
+                                                     const float2 *__restrict__ aux,
+                                                     const uint32_t *__restrict__ neibs,
+                                                     const uint16_t *__restrict__ neibs_brick,
+                                                     const uint32_t *__restrict__ count,
+                                                     const int32_t *__restrict__ cell_start,
+                                                     const int32_t *__restrict__ cell_end,
+                                                     const int32_t *__restrict__ active,
+                                                     const uint32_t *__restrict__ info,
+                                                     float4 *__restrict__ out, ForceConst C, BrickGrid G)
+{
+    using St = Staging<BX, BY, BZ>;
+    constexpr int SX = BX + 2, SY = BY + 2, SZ = BZ + 2;
+    constexpr int S = SX * SY * SZ;  // staged cells
+    constexpr int NI = BX * BY * BZ; // inner cells
+    static_assert(S <= NT && NI <= NT, "one thread per cell");
+    __shared__ float4 sP[CAP];  // brick-relative offset, mass x kernel coefficient
+    __shared__ float4 sV[CAP];
+    __shared__ float2 sA[CAP];
+    __shared__ int cBase[S + 1];
+    __shared__ int cDelta[S];
+    __shared__ int iBase[NI + 1];
+    __shared__ int iStart[NI];
+    __shared__ int wsum[NT / kWave];
+
+    const int tid = threadIdx.x;
+    // active[0] = number of bricks holding particles, active[1 + k] = brick id
+    if ((int)blockIdx.x >= active[0]) return;
+    const int b = active[1 + blockIdx.x];
+    const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
+
+    // 1. ranges of the staged cells and their LDS bases (the staging order of
+    //    the list build)
+    int st = 0, cnt = 0;
+    if (tid < S) {
+        int gx = cx0 - 1 + St::sx_of(tid), gy = cy0 - 1 + St::sy_of(tid), gz = cz0 - 1 + St::sz_of(tid);
+        const bool ok = wrap_axis(gx, G.nx, G.periodic & 1u) && wrap_axis(gy, G.ny, (G.periodic >> 1) & 1u) &&
+                        wrap_axis(gz, G.nz, (G.periodic >> 2) & 1u);
+        if (ok) {
+            const int lin = gx + G.nx * (gy + G.ny * gz);
+            st = cell_start[lin];
+            cnt = cell_end[lin] - st;
+        }
+    }
+    int total;
+    const int ex = block_scan<NT>(cnt, total, wsum);
+    if (tid < S) {
+        cBase[tid] = ex;
+        cDelta[tid] = ex - st;
+    }
+    if (tid == 0) cBase[S] = total;
+    __syncthreads();
+    // inner cells (x fastest: each inner row is one contiguous particle range)
+    int icnt = 0, ist = 0;
+    // inner cells past the grid edge hold no centrals (on a periodic axis the
+    // staged copy would be the wrapped cell, owned by another brick)
+    if (tid < NI && cx0 + St::ix_of(tid) < G.nx && cy0 + St::iy_of(tid) < G.ny && cz0 + St::iz_of(tid) < G.nz) {
+        const int t = St::inner(tid);
+        icnt = cBase[t + 1] - cBase[t];
+        ist = cBase[t] - cDelta[t];
+    }
+    int nc;
+    const int iex = block_scan<NT>(icnt, nc, wsum);
+    if (tid < NI) {
+        iBase[tid] = iex;
+        iStart[tid] = ist;
+    }
+    if (tid == 0) iBase[NI] = nc;
+    if (nc == 0) return;  // uniform: no particle in the brick
+    __syncthreads();
+    const bool use_lds = total <= CAP;
+    // central particle of lane q (binary search over the inner cells)
+    auto central = [&](int q, int &u, int &i) {
+        int lo = 0, hi = NI - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (iBase[mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        u = lo;
+        i = iStart[u] + (q - iBase[u]);
+    };
+    // the list count of the first pass is requested before the staging loads
+    // so the two latencies overlap
+    int u0, i0;
+    central(min(tid, nc - 1), u0, i0);
+    const uint32_t cnt0 = tid < nc ? count[i0] : 0u;
+    if (use_lds) {
+        // 2. stage the brick and its halo: one wave per row of SX staged
+        //    cells (x-consecutive, so one contiguous LDS range and, away from
+        //    a periodic seam, one contiguous global range), lanes over the
+        //    row's particles
+        const int wave = tid / kWave, lane = tid % kWave;
+        for (int r = wave; r < SY * SZ; r += NT / kWave) {
+            const int t0 = r * SX;
+            const int b0 = cBase[t0], b1 = cBase[t0 + SX];
+            int e[SX - 1];
+#pragma unroll
+            for (int c = 0; c < SX - 1; ++c) e[c] = cBase[t0 + 1 + c];
+            const float sy = (float)(r / SZ - 2), sz = (float)(r % SZ - 2);
+            for (int s2 = b0 + lane; s2 < b1; s2 += kWave) {
+                int c = 0;
+#pragma unroll
+                for (int k = 0; k < SX - 1; ++k) c += s2 >= e[k] ? 1 : 0;
+                const int j = s2 - cDelta[t0 + c];
+                const float4 p = pos[j];
+                const float sx = (float)(c - 2);
+                // w = m x kernel coefficient, negated for boundary particles
+                // when the density diffusion needs the type
+                const float mf = p.w * C.fcoeff;
+                sP[s2] = make_float4(fmaf(sx, C.csx, p.x), fmaf(sy, C.csy, p.y), fmaf(sz, C.csz, p.z),
+                                     ((MODEL & kDiffusion) && ptype(info[j]) == kBoundary) ? -mf : mf);
+                sV[s2] = vel[j];
+                sA[s2] = aux[j];
+            }
+        }
+    }
+    __syncthreads();
+
+    // 3. one lane per central particle of the brick
+    const int M = C.max_neibs;
+    const uint32_t jmax = (uint32_t)(n - 1);
+    for (int q0 = 0; q0 < nc; q0 += NT) {
+        const int q = q0 + tid;
+        const bool act = q < nc;
+        int u = u0, i = i0;
+        uint32_t cntw = cnt0;
+        if (q0 > 0) {
+            central(act ? q : nc - 1, u, i);
+            cntw = act ? count[i] : 0u;
+        }
+        const int nf = min((int)(cntw & 0xFFFFu), M);
+        const int nt = min(nf + (int)(cntw >> 16), M);
+        const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
+        PairAcc A = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (ntw > 0) {
+            const size_t toff = (size_t)(i / kWave) * (kWave * M) + (i % kWave);
+            if (use_lds) {
+                const int tc = St::inner(u);
+                const int si = i + cDelta[tc];
+                const uint4 *lg = (const uint4 *)(neibs_brick + brick_entry(i, 0, brick_groups(M)));
+                brick_pairs_lds<MODEL, NT>(A, lg, nt, ntw, total, sP, sV, sA, sP[si], sV[si], sA[si], C);
+            } else {
+                // (a shallow pipeline: this path shares the register budget of
+                // the LDS path and runs only where a halo overflows)
+                const bool central_fluid = (MODEL & kDiffusion) ? ptype(info[i]) != kBoundary : true;
+                gather_pairs<MODEL, 2>(A, neibs + toff, nf, nt, ntw, M, jmax, pos, vel, aux, pos[i], vel[i], aux[i],
+                                      central_fluid, C);
+            }
+        }
+        if (act) out[i] = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+}
+
+// LDS capacity (staged particles, 40 bytes each) per brick shape: the halo
+// of a brick at the h = 1.3 dp, r_s = 2.86 dp lattice density holds up to
+// about 27 particles per staged cell (3 x 4 x 3: 150 cells, 3825 at most in
+// the 1.62M dam break; 3 x 3 x 3: 125 cells, 3375; 3 x 2 x 3: 100 cells).
+// Measured on the 1.62M dam break (one workgroup per CU in every case):
+// 3 x 4 x 3 277 us, 3 x 3 x 3 357 us, 4 x 3 x 3 425 us (1% of its bricks
+// overflow the LDS there).
+constexpr int brick_cap(int BX, int BY, int BZ) { return BX * BY * BZ >= 36 ? 4000 : (BX * BY * BZ >= 27 ? 3400 : 2750); }
+
+template <int MODEL>
+void launch_brick(const ForceArgs &a, const ForceConst &C, hipStream_t s)
+{
+    with_shape(a.shape, [&]<int BX, int BY, int BZ>() {
+        const BrickGrid G = brick_grid<BX, BY, BZ>(a.grid->ncell, a.grid->periodic);
+        const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
+        constexpr int NT = brick_threads(BX * BY * BZ);
+        // (active[0] was zeroed by the equation-of-state prologue)
+        k_active_bricks<BX, BY, BZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(a.cell_start, a.cell_end, G, a.active);
+        k_forces_brick<MODEL, BX, BY, BZ, NT, brick_cap(BX, BY, BZ)><<<blocks, NT, 0, s>>>(
+            a.n, a.pos, a.vel, a.aux, a.neibs, a.neibs_brick, a.count, a.cell_start, a.cell_end, a.active, a.info,
+            a.out, C, G);
+    });
+}
+
+}  // namespace
+
+#define SPH_PAIRS_FN_(k) forces_pairs_kernel##k
+#define SPH_PAIRS_FN(k) SPH_PAIRS_FN_(k)
+
+bool sph::SPH_PAIRS_FN(SPH_KERNEL_KIND)(int model, const ForceArgs &a, const ForceConst &C, hipStream_t s)
+{
+    if (model < 0 || model_kernel(model) != SPH_KERNEL_KIND) return false;
+    return with_model<SPH_KERNEL_KIND>(model & kModelLowBits, [&]<int M>() {
+        if (a.bricks) {
+            // cell ranges and brick-local lists of the last build: LDS cell-brick
+            // kernel (it writes the derivatives of every particle that lies in a
+            // cell; particles dropped by the build were zeroed by the prologue)
+            launch_brick<M>(a, C, s);
+        } else {
+            k_forces<M><<<sph_blocks(a.n, kThreads), kThreads, 0, s>>>(a.n, a.pos, a.vel, a.aux, a.neibs, a.count,
+                                                                       a.info, a.out, C);
+        }
+    });
+}

@@ -76,6 +76,21 @@ __device__ __forceinline__ T wave_sum(T v)
     return v;
 }
 
+// Cell difference k_d in {-1, 0, 1} of axis d, stored as a two's-complement
+// 2-bit field at bit 26 + 2d of a list entry.
+__device__ __forceinline__ float entry_k(uint32_t e, int axis)
+{
+    return (float)((int32_t)(e << (4 - 2 * axis)) >> 30);
+}
+
+// Storage slot of the k-th pair of a list with nf fluid entries (front) and
+// the boundary ones (back), k clamped to last = count - 1.
+__device__ __forceinline__ int list_slot(int k, int nf, int last, int M)
+{
+    const int kk = min(k, last);
+    return kk < nf ? kk : M - 1 + nf - kk;
+}
+
 // ---------------------------------------------------------------------------
 // Cell bricks: blocks of cells processed by one workgroup with the particles
 // of the brick and of its one-cell halo staged in LDS (used by the list build
@@ -162,6 +177,13 @@ inline BrickGrid brick_grid(const int32_t ncell[3], uint32_t periodic)
     G.nby = (G.ny + BY - 1) / BY;
     G.nbz = (G.nz + BZ - 1) / BZ;
     return G;
+}
+
+// Entry s (0..7) of a 16-byte group of brick-local list entries.
+__device__ __forceinline__ uint32_t group_entry(const uint4 &g, int s)
+{
+    const uint32_t w = (s >> 1) == 0 ? g.x : (s >> 1) == 1 ? g.y : (s >> 1) == 2 ? g.z : g.w;
+    return (s & 1) ? (w >> 16) : (w & 0xFFFFu);
 }
 
 __device__ __forceinline__ bool wrap_axis(int &c, int n, uint32_t periodic)

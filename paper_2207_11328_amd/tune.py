@@ -12,8 +12,9 @@ picks the smallest cost per step,
     t_build / rebuild_every + 2 t_forces    (two derivative calls per step).
 
 Choices are cached in a JSON file keyed by the device and the workload's
-shape (particle count, grid, spacing, periodicity, viscosity model, list
-size, per-cell alpha), so a workload is timed once per device.
+shape (particle count, grid, spacing, periodicity, viscosity model, kernel,
+formulation, diffusion, list size, per-cell alpha), so a workload is timed
+once per device.
 """
 from __future__ import annotations
 
@@ -41,7 +42,9 @@ def workload_key(grid, params, n, max_neibs, cell_alpha, device) -> str:
     name = torch.cuda.get_device_name(torch.device(device))
     parts = [name, "n=%d" % n, "ncell=%s" % ",".join(str(int(v)) for v in grid.ncell),
              "periodic=%d" % int(grid.periodic), "rs=%.6g" % float(params.r_search), "h=%.6g" % float(params.h),
-             "visc=%d" % int(params.visc_model), "M=%d" % int(max_neibs), "alpha_table=%d" % int(cell_alpha is not None)]
+             "visc=%d" % int(params.visc_model), "kernel=%d" % int(getattr(params, "kernel", 0)),
+             "form=%d" % int(getattr(params, "formulation", 0)), "diff=%d" % int(getattr(params, "delta", 0.0) != 0.0),
+             "M=%d" % int(max_neibs), "alpha_table=%d" % int(cell_alpha is not None)]
     return "|".join(parts)
 
 

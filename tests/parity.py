@@ -171,8 +171,42 @@ def oracle_forces_of(sc, ob, state_pos=None, state_vel=None, alpha=None):
     return st, O.forces(sc.grid, sc.params, st, ob["lists"], alpha)
 
 
-def check_forces(gpu_f, acc, drho, s_acc, s_drho, tol=FORCE_TOL, label=""):
-    """Returns the max normalised errors (acc, drho); asserts <= tol."""
+def support_edge_rows(sc, ob, rel=1e-5):
+    """Mask of the particles with a listed neighbour at |r - 2h| <= rel 2h.
+    A kernel whose F does not vanish at the edge of its support (the
+    truncated Gaussian) gives such a pair a finite weight, and the float32
+    interaction decision of the GPU and the FP64 one of the oracle may then
+    differ, both being correct to rounding: these particles are left out of
+    the element-wise comparison for that kernel."""
+    L = ob["lists"]
+    cell = ob["cell"].astype(np.int64) - int(sc.grid.cell_base)
+    off = ob["pos"][:, :3].astype(np.float64)
+    nx, ny, nz = (int(v) for v in sc.grid.ncell)
+    c = np.stack([cell % nx, (cell // nx) % ny, cell // (nx * ny)], axis=1)
+    cs = [float(v) for v in sc.grid.cell_size]
+    two_h = 2.0 * O.f32(sc.params.h)
+    rows = np.zeros(cell.shape[0], bool)
+    for idx, cnt in ((L.fl, L.nf), (L.bl, L.nb)):
+        valid = np.arange(idx.shape[1])[None, :] < cnt[:, None]
+        j = np.where(valid, idx, 0)
+        r2 = np.zeros(idx.shape)
+        for d, nd in enumerate((nx, ny, nz)):
+            k = c[:, d][:, None] - c[:, d][j]
+            if (sc.grid.periodic >> d) & 1:
+                k = np.where(k > 1, k - nd, k)
+                k = np.where(k < -1, k + nd, k)
+            x = k * cs[d] + (off[:, d][:, None] - off[:, d][j])
+            r2 += x * x
+        rows |= np.any(valid & (np.abs(np.sqrt(r2) - two_h) <= rel * two_h), axis=1)
+    return rows
+
+
+def check_forces(gpu_f, acc, drho, s_acc, s_drho, tol=FORCE_TOL, label="", exclude=None):
+    """Returns the max normalised errors (acc, drho); asserts <= tol.
+    exclude: optional mask of particles left out (see support_edge_rows)."""
+    if exclude is not None:
+        keep = ~np.asarray(exclude, bool)
+        gpu_f, acc, drho, s_acc, s_drho = gpu_f[keep], acc[keep], drho[keep], s_acc[keep], s_drho[keep]
     ga = gpu_f[:, :3].astype(np.float64)
     gd = gpu_f[:, 3].astype(np.float64)
     ea = np.abs(ga - acc)

@@ -40,7 +40,8 @@ def test_struct_layout_matches_header(abi, tmp_path):
 #include "sph.h"
 int main(void) {
   printf("%zu %zu %zu %zu %zu\\n", sizeof(sph_grid), offsetof(sph_grid, cell_size), offsetof(sph_grid, periodic), offsetof(sph_grid, cell_base), offsetof(sph_grid, cell_alpha));
-  printf("%zu %zu %zu\\n", sizeof(sph_params), offsetof(sph_params, g), offsetof(sph_params, visc_model));
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(sph_params), offsetof(sph_params, g), offsetof(sph_params, visc_model),
+         offsetof(sph_params, delta), offsetof(sph_params, kernel), offsetof(sph_params, formulation));
   printf("%zu %zu %zu %zu\\n", sizeof(sph_particles), offsetof(sph_particles, cell), offsetof(sph_particles, vel), offsetof(sph_particles, info));
   return 0;
 }
@@ -52,7 +53,8 @@ int main(void) {
     assert g == [C.sizeof(abi.SphGrid), abi.SphGrid.cell_size.offset, abi.SphGrid.periodic.offset,
                  abi.SphGrid.cell_base.offset, abi.SphGrid.cell_alpha.offset]
     p = [int(v) for v in out[1].split()]
-    assert p == [C.sizeof(abi.SphParams), abi.SphParams.g.offset, abi.SphParams.visc_model.offset]
+    assert p == [C.sizeof(abi.SphParams), abi.SphParams.g.offset, abi.SphParams.visc_model.offset,
+                 abi.SphParams.delta.offset, abi.SphParams.kernel.offset, abi.SphParams.formulation.offset]
     q = [int(v) for v in out[2].split()]
     assert q == [C.sizeof(abi.SphParticles), abi.SphParticles.cell.offset, abi.SphParticles.vel.offset,
                  abi.SphParticles.info.offset]
@@ -97,3 +99,39 @@ def test_argument_errors_return_before_any_launch(abi):
     assert abi.lib.sph_integrate(C.byref(p), 2, None, None, None, None, None, None, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_step_dt(None, None, None, None, None, 0, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_count_interactions(None, None, None, None, None, 128, None, None) == abi.SPH_ERR_ARG
+
+
+def test_unknown_model_switches_are_rejected(abi):
+    """An unknown kernel, laminar form or formulation is an argument error of
+    sph_forces and sph_forces_backward; every known combination passes the
+    parameter checks (and stops at the missing workspace, before any launch)."""
+    g = abi.SphGrid()
+    for d in range(3):
+        g.cell_size[d] = 0.06
+        g.ncell[d] = 4
+    g.brick[:] = abi.sph_brick_shapes()[0]
+    parts = abi.SphParticles(0, 0, None, None, None, None)
+    gp = (C.c_double * 3)()
+
+    def both(p):
+        a = abi.lib.sph_forces(C.byref(g), C.byref(p), C.byref(parts), None, None, 128, None, None, None, None,
+                               None, 0, None)
+        b = abi.lib.sph_forces_backward(C.byref(g), C.byref(p), C.byref(parts), None, None, 128, None, None, None,
+                                        None, None, None, gp, 0, None, 0, None)
+        return a, b
+
+    def params(**kw):
+        p = abi.SphParams()
+        p.h, p.r_search, p.rho0, p.gamma, p.c0 = 0.026, 0.06, 1000.0, 7.0, 20.0
+        for k, v in kw.items():
+            setattr(p, k, v)
+        return p
+
+    for kernel in range(4):
+        for visc in range(3):
+            for form in range(2):
+                for delta in (0.0, 0.1):
+                    assert both(params(kernel=kernel, visc_model=visc, formulation=form, delta=delta)) == \
+                        (abi.SPH_ERR_WORKSPACE, abi.SPH_ERR_WORKSPACE)
+    for bad in (dict(kernel=4), dict(kernel=-1), dict(visc_model=3), dict(formulation=2), dict(delta=-0.1)):
+        assert both(params(**bad)) == (abi.SPH_ERR_ARG, abi.SPH_ERR_ARG), bad

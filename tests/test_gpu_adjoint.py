@@ -15,7 +15,7 @@ import pytest
 from oracle import oracle as O
 from workloads import scenes as S
 
-from parity import compare_build, log, make_sim, torch_sync
+from parity import compare_build, log, make_sim, support_edge_rows, torch_sync
 
 pytestmark = pytest.mark.gpu
 
@@ -70,12 +70,15 @@ def test_forces_backward_parity(name, form, shape, delta):
     odd brick heights; per-particle gather) against the FP64 oracle reverse,
     also with the density diffusion term."""
     import dataclasses
-    bricks = form == "bricks"
     make, M = SCENES[name]
     sc = make()
     if delta:
         sc = dataclasses.replace(sc, params=dataclasses.replace(sc.params, delta=delta))
-    log("case %s n=%d bricks=%s shape=%s delta=%s" % (name, sc.n, bricks, shape, delta))
+    log("case %s n=%d bricks=%s shape=%s delta=%s" % (name, sc.n, form == "bricks", shape, delta))
+    _backward_parity(sc, M, form == "bricks", shape, name)
+
+
+def _backward_parity(sc, M, bricks, shape, name):
     sim = make_sim(sc, max_neibs=M, brick=shape)
     sim.build()
     torch_sync()
@@ -103,9 +106,15 @@ def test_forces_backward_parity(name, form, shape, delta):
     gp_gpu = gpos[: sc.n].cpu().numpy()
     gv_gpu = gvel[: sc.n].cpu().numpy()
     assert np.all(gp_gpu[:, 3] == 7.0), "w of grad_pos must be left untouched"
-    _cmp(name + " dL/do", gp_gpu[:, :3], adj.go)
-    _cmp(name + " dL/du", gv_gpu[:, :3], adj.gu)
-    _cmp(name + " dL/drho", gv_gpu[:, 3], adj.grho)
+    keep = slice(None)
+    if int(getattr(sc.params, "kernel", 0)) == O.GAUSSIAN:
+        # pairs at the edge of the truncated Gaussian's support (see support_edge_rows)
+        edge = support_edge_rows(sc, ob)
+        assert edge.mean() < 0.01
+        keep = ~edge
+    _cmp(name + " dL/do", gp_gpu[keep, :3], adj.go[keep])
+    _cmp(name + " dL/du", gv_gpu[keep, :3], adj.gu[keep])
+    _cmp(name + " dL/drho", gv_gpu[keep, 3], adj.grho[keep])
     g = gparams.cpu().numpy()
     log("%s params gpu %s oracle %s" % (name, g, gp))
     for k in range(3):
@@ -123,6 +132,52 @@ def test_forces_backward_parity(name, form, shape, delta):
                             gvel2, gparams2, False, ws, **bk)
     torch_sync()
     assert torch.equal(gvel2, gvel) and torch.equal(gparams2, gparams)
+
+
+# every compiled model: kernel x laminar term x formulation x diffusion
+VARIANTS = [(k, v, f, d) for k in range(4) for v in range(3) for f in range(2) for d in (0.0, 0.1)]
+
+
+def _variant_id(v):
+    return "%s-%s-%s%s" % (["wendland", "cubic", "quadratic", "gaussian"][v[0]], ["av", "morris", "monaghan_k"][v[1]],
+                           ["golden", "landrini"][v[2]], "-diffusion" if v[3] else "")
+
+
+def _variant_case(name, variant, bricks):
+    import dataclasses
+    kernel, visc, form, delta = variant
+    make, M = SCENES[name]
+    sc = make()
+    sc = dataclasses.replace(sc, params=dataclasses.replace(sc.params, kernel=kernel, visc_model=visc, nu=2e-3,
+                                                              formulation=form, delta=delta))
+    log("case %s %s bricks=%s n=%d" % (name, _variant_id(variant), bricks, sc.n))
+    _backward_parity(sc, M, bricks, None, name + " " + _variant_id(variant))
+
+
+@pytest.mark.parametrize("variant", VARIANTS, ids=[_variant_id(v) for v in VARIANTS])
+def test_model_variants_backward_bricks(variant):
+    """The adjoint of every compiled model (kernel, formulation, laminar
+    term, diffusion) in the LDS brick form against the oracle reverse,
+    parameter derivatives included."""
+    _variant_case("cloud_av", variant, True)
+
+
+BACK_GATHER = [(1, 1, 1, 0.1), (2, 2, 0, 0.0), (3, 2, 1, 0.1), (0, 2, 1, 0.0), (3, 1, 0, 0.0)]
+
+
+@pytest.mark.parametrize("variant", BACK_GATHER, ids=[_variant_id(v) for v in BACK_GATHER])
+def test_model_variants_backward_gather(variant):
+    """A spread of the models in the per-particle gather form of the adjoint,
+    on the periodic cloud."""
+    _variant_case("cloud_laminar_periodic", variant, False)
+
+
+BACK_DAM = [(1, 2, 1, 0.1), (3, 1, 0, 0.0)]
+
+
+@pytest.mark.parametrize("variant", BACK_DAM, ids=[_variant_id(v) for v in BACK_DAM])
+def test_model_variants_backward_dam_break(variant):
+    _variant_case("dam_break_64k", variant, True)
 
 
 def test_integrate_backward_parity():
