@@ -39,7 +39,8 @@ FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 # acceleration 6 = 43; the Morris laminar term adds 9.
 FLOP_PER_INTERACTION = {0: 43, 1: 52}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forces_traffic_dam_break_1m.json")
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2207_11328_amd", "csrc", f) for f in ("forces.hip", "sph_device.h")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2207_11328_amd", "csrc", f)
+                  for f in ("forces.hip", "forces_pairs.hip", "forces_common.h", "sph_model.h", "sph_device.h")]
 
 
 def sources_sha256():
@@ -73,6 +74,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fwd-bwd", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (calibrates the HBM "
@@ -200,6 +202,60 @@ def batched(units=5, warm_units=1):
             "fluid_particle_steps_per_s": st.n_fluid * steps / t, "graph_units": units,
             "tuned": {"brick": list(choice["brick"]), "bricks": choice["bricks"],
                       "per_step_ms": {k: v * 1e3 for k, v in choice["per_step_s"].items()}}}
+
+
+# models timed by the variants leg: (label, kernel, visc_model, formulation, delta)
+VARIANTS = [
+    ("wendland", 0, 0, 0, 0.0), ("cubic_spline", 1, 0, 0, 0.0), ("quadratic", 2, 0, 0, 0.0),
+    ("gaussian", 3, 0, 0, 0.0), ("wendland_landrini", 0, 0, 1, 0.0), ("wendland_morris", 0, 1, 0, 0.0),
+    ("wendland_monaghan_k", 0, 2, 0, 0.0), ("wendland_diffusion", 0, 0, 0, 0.1),
+    ("gaussian_landrini_monaghan_k_diffusion", 3, 2, 1, 0.1),
+]
+
+
+def variants(sim, sc, inter_per_call, reps=20):
+    """sph_forces and sph_forces_backward of every model in VARIANTS on the
+    same state and lists (the timed run's last), HIP events on the launch
+    stream; laminar models at nu = 1e-6 m^2/s."""
+    import dataclasses
+    import torch
+    from paper_2207_11328_amd import abi
+    dev = sim.device
+    cap = sim.capacity
+    gforce = torch.randn((cap, 4), device=dev)
+    gpos = torch.zeros((cap, 4), device=dev)
+    gvel = torch.zeros((cap, 4), device=dev)
+    gpar = torch.zeros(3, dtype=torch.float64, device=dev)
+    ws = torch.zeros(abi.sph_forces_backward_workspace_bytes(cap, sim.n_cells), dtype=torch.uint8, device=dev)
+    cs, ce, nb = sim.brick_args()
+    stream = torch.cuda.current_stream()
+    out = {}
+    for label, kernel, visc, form, delta in VARIANTS:
+        p = abi.params_struct(dataclasses.replace(sc.params, kernel=kernel, visc_model=visc, formulation=form,
+                                                  delta=delta, nu=1e-6 if visc else sc.params.nu))
+
+        def fwd():
+            abi.sph_forces(sim.g, p, sim.parts, sim.neibs, sim.neib_count, sim.max_neibs, sim.forces_n,
+                           sim.ws_forces, None, cs, ce, nb)
+
+        def bwd():
+            abi.sph_forces_backward(sim.g, p, sim.parts, sim.neibs, sim.neib_count, sim.max_neibs, gforce, gpos,
+                                    gvel, gpar, False, ws, None, cs, ce, nb)
+
+        row = {}
+        for name, fn in (("forces", fwd), ("backward", bwd)):
+            fn()
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            for _ in range(reps):
+                fn()
+            b.record(stream)
+            torch.cuda.synchronize()
+            row[name + "_ms"] = a.elapsed_time(b) / reps
+        row["forces_interactions_per_s"] = inter_per_call / (row["forces_ms"] * 1e-3)
+        out[label] = row
+    return out
 
 
 def main():
@@ -348,6 +404,8 @@ def main():
                     "traffic_frac": None if traffic is None else traffic / t_forces_avg / 1e9 / HBM_PEAK_GBS},
         },
     }
+    if not args.no_variants:
+        out["variants"] = variants(sim, sc, inter / calls)
     if not args.no_batched:
         out["batched"] = batched()
     if not args.no_fwd_bwd:
