@@ -24,7 +24,8 @@ struct BackArgs {
     const uint32_t *neibs, *count, *info;
     const uint16_t *neibs_brick;
     const int32_t *cell_start, *cell_end;
-    int32_t *active;
+    int32_t *active;  // bricks holding particles: count, then ids
+    int32_t *next;    // brick counter of the persistent workgroups
     float4 *gpos, *gvel;
     double *partial;  // per-block (gather) or per-brick parameter partials
     int accumulate;

@@ -25,16 +25,20 @@ constexpr int kThreads = 256;
 // (1 + d)^7 - 1, full relative accuracy near rho0).  aux = (P/rho^2,
 // alpha h c / 2) with c = c0 (1 + d)^3 (aux.x = P for the Landrini-Morris
 // formulation).
-// Also (brick form): zeroes the active-brick counter and the derivatives of
-// particles the last build dropped (cell < 0), which no brick visits.
+// Also (brick form): zeroes the active-brick count, the brick counter of the
+// persistent brick kernel and the derivatives of particles the last build
+// dropped (cell < 0), which no brick visits.
 __global__ __launch_bounds__(kThreads) void k_eos(int n, const float4 *__restrict__ vel, float2 *__restrict__ aux,
                                                   const int32_t *__restrict__ cell,
                                                   const float *__restrict__ cell_alpha, int cell_base, float h,
                                                   ForceConst C, int32_t *__restrict__ active,
-                                                  float4 *__restrict__ out)
+                                                  int32_t *__restrict__ next, float4 *__restrict__ out)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (active && i == 0) active[0] = 0;
+    if (active && i == 0) {
+        active[0] = 0;
+        next[0] = 0;
+    }
     if (i >= n) return;
     float alpha_h = C.alpha_h;
     if (cell_alpha || out) {
@@ -133,8 +137,9 @@ size_t aux_bytes(int64_t capacity) { return (size_t)((sizeof(float2) * capacity 
 extern "C" size_t sph_forces_workspace_bytes(int32_t capacity, int32_t n_cells)
 {
     if (capacity < 0 || n_cells < 0) return 0;
-    // per-particle EOS terms, then the active-brick list (at most one brick per cell)
-    return aux_bytes(capacity > 0 ? capacity : 1) + sizeof(int32_t) * ((size_t)n_cells + 1) + 256;
+    // per-particle EOS terms, then the active-brick list (at most one brick per
+    // cell) and the brick counter
+    return aux_bytes(capacity > 0 ? capacity : 1) + sizeof(int32_t) * ((size_t)n_cells + 2) + 256;
 }
 
 extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
@@ -167,7 +172,7 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
     if ((params->delta != 0.0f) && !parts->info) return SPH_ERR_ARG;
     k_eos<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, vel, aux, parts->cell, grid->cell_alpha, grid->cell_base,
                                                        params->h, C, bricks ? active : nullptr,
-                                                       bricks ? out : nullptr);
+                                                       active + n_cells + 1, bricks ? out : nullptr);
     ForceArgs a;
     a.grid = grid;
     a.shape = shape;
@@ -182,6 +187,7 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
     a.cell_start = cell_start;
     a.cell_end = cell_end;
     a.active = active;
+    a.next = active + n_cells + 1;
     a.out = out;
     a.bricks = bricks;
     static bool (*const pairs[4])(int, const ForceArgs &, const ForceConst &, hipStream_t) = {

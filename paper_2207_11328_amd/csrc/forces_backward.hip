@@ -182,6 +182,7 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
         a.cell_start = cell_start;
         a.cell_end = cell_end;
         a.active = active;
+        a.next = active + n_cells + 1;
         a.gpos = (float4 *)grad_pos;
         a.gvel = (float4 *)grad_vel;
         a.partial = bricks ? bpartial : partial;

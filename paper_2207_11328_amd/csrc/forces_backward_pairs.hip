@@ -382,8 +382,9 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
     int n, const float4 *__restrict__ pos, const float4 *__restrict__ vel, const float4 *__restrict__ aux,
     const float4 *__restrict__ gforce, const uint32_t *__restrict__ neibs, const uint16_t *__restrict__ neibs_brick,
     const uint32_t *__restrict__ count, const int32_t *__restrict__ cell_start, const int32_t *__restrict__ cell_end,
-    const int32_t *__restrict__ active, const uint32_t *__restrict__ info, float4 *__restrict__ gpos,
-    float4 *__restrict__ gvel, double *__restrict__ partial, int accumulate, BackConst C, BrickGrid G)
+    const int32_t *__restrict__ active, int32_t *__restrict__ next, const uint32_t *__restrict__ info,
+    float4 *__restrict__ gpos, float4 *__restrict__ gvel, double *__restrict__ partial, int accumulate, BackConst C,
+    BrickGrid G)
 {
     using St = Staging<BX, BY, BZ>;
     constexpr int SX = St::SX, SZ = St::SZ, S = St::S, NI = St::NI;
@@ -402,164 +403,181 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
     __shared__ int wsum[NT / kWave];
     __shared__ double red[3][NT / kWave];
 
-    const int tid = threadIdx.x;
-    if ((int)blockIdx.x >= active[0]) return;
-    const int b = active[1 + blockIdx.x];
-    const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
-
-    // 1. staged cell ranges and LDS bases, inner cells and their centrals
-    int st = 0, cnt = 0;
-    if (tid < S) {
-        int gx = cx0 - 1 + St::sx_of(tid), gy = cy0 - 1 + St::sy_of(tid), gz = cz0 - 1 + St::sz_of(tid);
-        const bool ok = wrap_axis(gx, G.nx, G.periodic & 1u) && wrap_axis(gy, G.ny, (G.periodic >> 1) & 1u) &&
-                        wrap_axis(gz, G.nz, (G.periodic >> 2) & 1u);
-        if (ok) {
-            const int lin = gx + G.nx * (gy + G.ny * gz);
-            st = cell_start[lin];
-            cnt = cell_end[lin] - st;
-        }
-    }
-    int total;
-    const int ex = block_scan<NT>(cnt, total, wsum);
-    if (tid < S) {
-        cBase[tid] = ex;
-        cDelta[tid] = ex - st;
-    }
-    if (tid == 0) cBase[S] = total;
-    __syncthreads();
-    int icnt = 0, ist = 0;
-    if (tid < NI && cx0 + St::ix_of(tid) < G.nx && cy0 + St::iy_of(tid) < G.ny && cz0 + St::iz_of(tid) < G.nz) {
-        const int t = St::inner(tid);
-        icnt = cBase[t + 1] - cBase[t];
-        ist = cBase[t] - cDelta[t];
-    }
-    int nc;
-    const int iex = block_scan<NT>(icnt, nc, wsum);
-    if (tid < NI) {
-        iBase[tid] = iex;
-        iStart[tid] = ist;
-    }
-    if (tid == 0) iBase[NI] = nc;
-    __syncthreads();
-
-    const int M = C.max_neibs;
-    const int groups = brick_groups(M);
-    const uint32_t jmax = (uint32_t)(n - 1);
-    double pa = 0.0, pc = 0.0, pn = 0.0;
-    for (int half = 0; half < 2; ++half) {
-        // inner rows [y0, y1), staged rows [y0, y1 + 2)
-        const int y0 = half ? HALF : 0, y1 = half ? BY : HALF;
-        const int s_lo = cBase[y0 * ROW];
-        const int s_hi = cBase[(y1 + 2) * ROW];
-        const int q_lo = iBase[y0 * IROW];
-        const int q_hi = iBase[y1 * IROW];
-        const int span = s_hi - s_lo;
-        const bool use_lds = span <= CAP;
-        if (use_lds && q_hi > q_lo) {
-            // stage the half: one wave per row of SX cells (contiguous in LDS)
-            const int wave = tid / kWave, lane = tid % kWave;
-            for (int r = y0 * SZ + wave; r < (y1 + 2) * SZ; r += NT / kWave) {
-                const int t0 = r * SX;
-                const int b0 = cBase[t0], b1 = cBase[t0 + SX];
-                int e[SX - 1];
-#pragma unroll
-                for (int c = 0; c < SX - 1; ++c) e[c] = cBase[t0 + 1 + c];
-                const float sy = (float)(r / SZ - 2), sz = (float)(r % SZ - 2);
-                for (int s2 = b0 + lane; s2 < b1; s2 += kWave) {
-                    int c = 0;
-#pragma unroll
-                    for (int kk = 0; kk < SX - 1; ++kk) c += s2 >= e[kk] ? 1 : 0;
-                    const int j = s2 - cDelta[t0 + c];
-                    const float4 p = pos[j];
-                    const float sx = (float)(c - 2);
-                    const float4 a4 = aux[j];
-                    const int l = s2 - s_lo;
-                    // mass negated for boundary particles when the diffusion needs the type
-                    const bool bnd = (MODEL & kDiffusion) && ptype(info[j]) == kBoundary;
-                    sP[l] = make_float4(fmaf(sx, C.csx, p.x), fmaf(sy, C.csy, p.y), fmaf(sz, C.csz, p.z),
-                                        bnd ? -p.w : p.w);
-                    sV[l] = vel[j];
-                    sX[l] = make_float2(a4.x, a4.y);
-                    sG[l] = gforce[j];
-                }
-            }
-        }
+    __shared__ int sNext;
+    // One resident workgroup per CU takes the bricks that hold particles
+    // (active[0] of them, ids in active[1..]) one at a time from the counter
+    // `next` (no workgroup for an empty brick; costs even out across CUs).
+    for (;;) {
+        // the thread index is re-read per brick (an empty asm hides that it is the
+        // same), so nothing derived from it is kept live across the pair loop
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        if (tid == 0) sNext = atomicAdd(next, 1);
         __syncthreads();
-        // two lanes per central particle of the half (lane pairs 2q', 2q'+1)
-        const int h = tid & 1;
-        if (q_hi == q_lo) continue;  // uniform
-        for (int q0 = q_lo; q0 < q_hi; q0 += NT / 2) {
-            const int q = q0 + tid / 2;
-            const bool act = q < q_hi;
-            int u;
-            {
-                int lo = 0, hi = NI - 1;
-                const int qq = act ? q : q_hi - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (iBase[mid] <= qq) lo = mid;
-                    else hi = mid - 1;
-                }
-                u = lo;
+        const int kb = sNext;
+        if (kb >= active[0]) break;  // uniform
+        const int b = active[1 + kb];
+        const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
+
+        // 1. staged cell ranges and LDS bases, inner cells and their centrals
+        int st = 0, cnt = 0;
+        if (tid < S) {
+            int gx = cx0 - 1 + St::sx_of(tid), gy = cy0 - 1 + St::sy_of(tid), gz = cz0 - 1 + St::sz_of(tid);
+            const bool ok = wrap_axis(gx, G.nx, G.periodic & 1u) && wrap_axis(gy, G.ny, (G.periodic >> 1) & 1u) &&
+                            wrap_axis(gz, G.nz, (G.periodic >> 2) & 1u);
+            if (ok) {
+                const int lin = gx + G.nx * (gy + G.ny * gz);
+                st = cell_start[lin];
+                cnt = cell_end[lin] - st;
             }
-            const int i = iStart[u] + ((act ? q : q_hi - 1) - iBase[u]);
-            const uint32_t cntw = act ? count[i] : 0u;
-            const int nf = min((int)(cntw & 0xFFFFu), M);
-            const int nt = min(nf + (int)(cntw >> 16), M);
-            const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
-            BackAcc A = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-            if (ntw > 0) {
-                const float4 xi = aux[i];
-                if (use_lds) {
-                    const int si = i + cDelta[St::inner(u)] - s_lo;
-                    const uint4 *lg = (const uint4 *)(neibs_brick + brick_entry(i, 0, groups));
-                    brick_adjoint_lds<MODEL>(A, lg, h, nt, ntw, s_lo, span, sP, sV, sX, sG, sP[si], sV[si], xi,
-                                            sG[si], C);
-                } else {
-                    // the lane pair splits the list by parity of the entry
-                    const uint32_t *tile = neibs + (size_t)(i / kWave) * (kWave * M) + (i % kWave);
-                    const float4 pi = pos[i], vi = vel[i], gi = gforce[i];
-                    const bool central_fluid = (MODEL & kDiffusion) ? ptype(info[i]) != kBoundary : true;
-                    const int last = max(nt - 1, 0);
-                    for (int k = h; k < ntw; k += 2) {
-                        const uint32_t e = tile[list_slot(k, nf, last, M) * kWave];
-                        const uint32_t j = min(e & kIndexMask, jmax);
-                        pair_adjoint<MODEL>(A, e, pi, vi, xi, gi, pos[j], vel[j], aux[j], gforce[j], k < nt,
-                                           central_fluid && k < nf, C);
+        }
+        int total;
+        const int ex = block_scan<NT>(cnt, total, wsum);
+        if (tid < S) {
+            cBase[tid] = ex;
+            cDelta[tid] = ex - st;
+        }
+        if (tid == 0) cBase[S] = total;
+        __syncthreads();
+        int icnt = 0, ist = 0;
+        if (tid < NI && cx0 + St::ix_of(tid) < G.nx && cy0 + St::iy_of(tid) < G.ny && cz0 + St::iz_of(tid) < G.nz) {
+            const int t = St::inner(tid);
+            icnt = cBase[t + 1] - cBase[t];
+            ist = cBase[t] - cDelta[t];
+        }
+        int nc;
+        const int iex = block_scan<NT>(icnt, nc, wsum);
+        if (tid < NI) {
+            iBase[tid] = iex;
+            iStart[tid] = ist;
+        }
+        if (tid == 0) iBase[NI] = nc;
+        __syncthreads();
+
+        const int M = C.max_neibs;
+        const int groups = brick_groups(M);
+        const uint32_t jmax = (uint32_t)(n - 1);
+        double pa = 0.0, pc = 0.0, pn = 0.0;
+        for (int half = 0; half < 2; ++half) {
+            // inner rows [y0, y1), staged rows [y0, y1 + 2)
+            const int y0 = half ? HALF : 0, y1 = half ? BY : HALF;
+            const int s_lo = cBase[y0 * ROW];
+            const int s_hi = cBase[(y1 + 2) * ROW];
+            const int q_lo = iBase[y0 * IROW];
+            const int q_hi = iBase[y1 * IROW];
+            const int span = s_hi - s_lo;
+            const bool use_lds = span <= CAP;
+            if (use_lds && q_hi > q_lo) {
+                // stage the half: one wave per row of SX cells (contiguous in LDS)
+                const int wave = tid / kWave, lane = tid % kWave;
+                for (int r = y0 * SZ + wave; r < (y1 + 2) * SZ; r += NT / kWave) {
+                    const int t0 = r * SX;
+                    const int b0 = cBase[t0], b1 = cBase[t0 + SX];
+                    int e[SX - 1];
+#pragma unroll
+                    for (int c = 0; c < SX - 1; ++c) e[c] = cBase[t0 + 1 + c];
+                    const float sy = (float)(r / SZ - 2), sz = (float)(r % SZ - 2);
+                    for (int s2 = b0 + lane; s2 < b1; s2 += kWave) {
+                        int c = 0;
+#pragma unroll
+                        for (int kk = 0; kk < SX - 1; ++kk) c += s2 >= e[kk] ? 1 : 0;
+                        const int j = s2 - cDelta[t0 + c];
+                        const float4 p = pos[j];
+                        const float sx = (float)(c - 2);
+                        const float4 a4 = aux[j];
+                        const int l = s2 - s_lo;
+                        // mass negated for boundary particles when the diffusion needs the type
+                        const bool bnd = (MODEL & kDiffusion) && ptype(info[j]) == kBoundary;
+                        sP[l] = make_float4(fmaf(sx, C.csx, p.x), fmaf(sy, C.csy, p.y), fmaf(sz, C.csz, p.z),
+                                            bnd ? -p.w : p.w);
+                        sV[l] = vel[j];
+                        sX[l] = make_float2(a4.x, a4.y);
+                        sG[l] = gforce[j];
                     }
                 }
             }
-            add_partner(A);
-            if (act && h == 0) {
-                store_adjoint(i, nt, A, gpos, gvel, accumulate);
-                if (nt > 0) {
-                    pa += (double)A.galpha;
-                    pc += (double)A.gc0;
-                    pn += (double)A.gnu;
+            __syncthreads();
+            // two lanes per central particle of the half (lane pairs 2q', 2q'+1)
+            const int h = tid & 1;
+            if (q_hi == q_lo) continue;  // uniform
+            for (int q0 = q_lo; q0 < q_hi; q0 += NT / 2) {
+                const int q = q0 + tid / 2;
+                const bool act = q < q_hi;
+                int u;
+                {
+                    int lo = 0, hi = NI - 1;
+                    const int qq = act ? q : q_hi - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (iBase[mid] <= qq) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    u = lo;
+                }
+                const int i = iStart[u] + ((act ? q : q_hi - 1) - iBase[u]);
+                const uint32_t cntw = act ? count[i] : 0u;
+                const int nf = min((int)(cntw & 0xFFFFu), M);
+                const int nt = min(nf + (int)(cntw >> 16), M);
+                const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
+                BackAcc A = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+                if (ntw > 0) {
+                    const float4 xi = aux[i];
+                    if (use_lds) {
+                        const int si = i + cDelta[St::inner(u)] - s_lo;
+                        const uint4 *lg = (const uint4 *)(neibs_brick + brick_entry(i, 0, groups));
+                        brick_adjoint_lds<MODEL>(A, lg, h, nt, ntw, s_lo, span, sP, sV, sX, sG, sP[si], sV[si], xi,
+                                                sG[si], C);
+                    } else {
+                        // the lane pair splits the list by parity of the entry
+                        const uint32_t *tile = neibs + (size_t)(i / kWave) * (kWave * M) + (i % kWave);
+                        const float4 pi = pos[i], vi = vel[i], gi = gforce[i];
+                        const bool central_fluid = (MODEL & kDiffusion) ? ptype(info[i]) != kBoundary : true;
+                        const int last = max(nt - 1, 0);
+                        for (int k = h; k < ntw; k += 2) {
+                            const uint32_t e = tile[list_slot(k, nf, last, M) * kWave];
+                            const uint32_t j = min(e & kIndexMask, jmax);
+                            pair_adjoint<MODEL>(A, e, pi, vi, xi, gi, pos[j], vel[j], aux[j], gforce[j], k < nt,
+                                               central_fluid && k < nf, C);
+                        }
+                    }
+                }
+                add_partner(A);
+                if (act && h == 0) {
+                    store_adjoint(i, nt, A, gpos, gvel, accumulate);
+                    if (nt > 0) {
+                        pa += (double)A.galpha;
+                        pc += (double)A.gc0;
+                        pn += (double)A.gnu;
+                    }
                 }
             }
+            __syncthreads();  // the next half reuses LDS
         }
-        __syncthreads();  // the next half reuses LDS
-    }
-    // parameter partial sums of the brick, fixed order, stored by brick id
-    pa = wave_sum(pa);
-    pc = wave_sum(pc);
-    pn = wave_sum(pn);
-    const int lane = tid % kWave, w = tid / kWave;
-    if (lane == 0) {
-        red[0][w] = pa;
-        red[1][w] = pc;
-        red[2][w] = pn;
-    }
-    __syncthreads();
-    if (tid < 3) {
-        double sum = 0.0;
-        for (int k = 0; k < NT / kWave; ++k) sum += red[tid][k];
-        partial[3 * (size_t)b + tid] = sum;
+        // parameter partial sums of the brick, fixed order, stored by brick id
+        pa = wave_sum(pa);
+        pc = wave_sum(pc);
+        pn = wave_sum(pn);
+        const int lane = tid % kWave, w = tid / kWave;
+        if (lane == 0) {
+            red[0][w] = pa;
+            red[1][w] = pc;
+            red[2][w] = pn;
+        }
+        __syncthreads();
+        if (tid < 3) {
+            double sum = 0.0;
+            for (int k = 0; k < NT / kWave; ++k) sum += red[tid][k];
+            partial[3 * (size_t)b + tid] = sum;
+        }
+        __syncthreads();  // the next brick reuses the LDS
     }
 }
 
-__global__ void k_zero_i32(int32_t *p) { *p = 0; }
+__global__ void k_zero_counters(int32_t *a, int32_t *b)
+{
+    *a = 0;
+    *b = 0;
+}
 
 __global__ __launch_bounds__(kThreads) void k_zero_f64(int n, double *__restrict__ p)
 {
@@ -573,14 +591,15 @@ void launch_backward_brick(const BackArgs &a, const BackConst &C, hipStream_t s,
         const BrickGrid G = brick_grid<BX, BY, BZ>(a.grid->ncell, a.grid->periodic);
         const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
         n_bricks = (int)blocks;
-        k_zero_i32<<<1, 1, 0, s>>>(a.active);
+        k_zero_counters<<<1, 1, 0, s>>>(a.active, a.next);
         k_zero_f64<<<sph_blocks(3 * blocks, kThreads) < 1024u ? sph_blocks(3 * blocks, kThreads) : 1024u, kThreads,
                      0, s>>>(3 * (int)blocks, a.partial);
         k_active_bricks<BX, BY, BZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(a.cell_start, a.cell_end, G, a.active);
+        const unsigned wgs = blocks < (unsigned)sph_device_cus() ? blocks : (unsigned)sph_device_cus();
         k_forces_backward_brick<MODEL, BX, BY, BZ, kBackBrickThreads, kBackBrickCap>
-            <<<blocks, kBackBrickThreads, 0, s>>>(a.n, a.pos, a.vel, a.aux, a.gforce, a.neibs, a.neibs_brick,
-                                                 a.count, a.cell_start, a.cell_end, a.active, a.info, a.gpos,
-                                                 a.gvel, a.partial, a.accumulate, C, G);
+            <<<wgs, kBackBrickThreads, 0, s>>>(a.n, a.pos, a.vel, a.aux, a.gforce, a.neibs, a.neibs_brick,
+                                              a.count, a.cell_start, a.cell_end, a.active, a.next, a.info, a.gpos,
+                                              a.gvel, a.partial, a.accumulate, C, G);
     });
 }
 

@@ -31,7 +31,8 @@ struct ForceArgs {
     const uint32_t *neibs, *count, *info;
     const uint16_t *neibs_brick;
     const int32_t *cell_start, *cell_end;
-    int32_t *active;
+    int32_t *active;  // bricks holding particles: count, then ids
+    int32_t *next;    // brick counter of the persistent workgroups
     float4 *out;
     bool bricks;
 };

@@ -209,11 +209,12 @@ __global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__rest
 // of order 1e-20).  A brick whose halo does not fit in LDS reads the global
 // lists and the global state with the arithmetic of k_forces.
 
-// Pairs of one lane's brick-local list, read from LDS.  The list arrives in
-// 16-byte groups of 8 entries (one load per 8 pairs), requested two groups
-// ahead; the staged data of pair k + R is requested while pair k is computed
-// (a ring of R slots, R dividing 8 so the ring phase is the same in every
-// group).
+// Pairs of one central's brick-local list, read from LDS, shared by two
+// lanes: lane h of the pair takes the groups of 8 entries h, h + 2, h + 4, ...
+// The list arrives in 16-byte groups (one load per 8 pairs), requested two
+// iterations ahead; the staged data of pair k + R is requested while pair k
+// is computed (a ring of R slots, R dividing 8 so the ring phase is the same
+// in every group).
 #ifndef SPH_BRICK_RING
 #define SPH_BRICK_RING 2
 #endif
@@ -221,12 +222,12 @@ constexpr int kRing = SPH_BRICK_RING;
 static_assert(kBrickGroup % kRing == 0, "ring must divide the group");
 
 template <int MODEL, int NT>
-__device__ __forceinline__ void brick_pairs_lds(PairAcc &A, const uint4 *lg, int nt, int ntw, int total,
+__device__ __forceinline__ void brick_pairs_lds(PairAcc &A, const uint4 *lg, int h, int nt, int ntw, int total,
                                                 const float4 *__restrict__ sP, const float4 *__restrict__ sV,
                                                 const float2 *__restrict__ sA, const float4 &pi, const float4 &vi,
                                                 const float2 &ai, const ForceConst &C)
 {
-    constexpr int GS = kWave;  // uint4 stride between groups of one lane
+    constexpr int GS = kWave;  // uint4 stride between groups of one central
     const int lastg = max(nt - 1, 0) / kBrickGroup;
     const uint32_t smax = (uint32_t)(total - 1);
     float4 P[kRing], V[kRing];
@@ -237,18 +238,19 @@ __device__ __forceinline__ void brick_pairs_lds(PairAcc &A, const uint4 *lg, int
         v = sV[sl];
         x = sA[sl];
     };
-    uint4 gc = lg[0];
-    uint4 gn = lg[min(1, lastg) * GS];
+    uint4 gc = lg[min(h, lastg) * GS];
+    uint4 gn = lg[min(h + 2, lastg) * GS];
 #pragma unroll
     for (int r = 0; r < kRing; ++r) fetch(group_entry(gc, r), P[r], V[r], X[r]);
-    for (int k = 0; k < ntw; k += kBrickGroup) {
-        const uint4 gnn = lg[min(k / kBrickGroup + 2, lastg) * GS];
+    for (int k = 0; k < ntw; k += 2 * kBrickGroup) {
+        const int g0 = k / kBrickGroup + h;  // this lane's group
+        const uint4 gnn = lg[min(g0 + 4, lastg) * GS];
 #pragma unroll
         for (int s = 0; s < kBrickGroup; ++s) {
             const int r = s % kRing;
             // staged w = +-(m_j x kernel coefficient), negative for boundary particles
             pair_core<MODEL>(A, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, vi, ai, fabsf(P[r].w), V[r], X[r],
-                            k + s < nt, pi.w > 0.0f && P[r].w > 0.0f, C);
+                            g0 * kBrickGroup + s < nt, pi.w > 0.0f && P[r].w > 0.0f, C);
             const int s2 = s + kRing;
             fetch(s2 < kBrickGroup ? group_entry(gc, s2) : group_entry(gn, s2 - kBrickGroup), P[r], V[r], X[r]);
         }
@@ -267,6 +269,7 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
                                                      const int32_t *__restrict__ cell_start,
                                                      const int32_t *__restrict__ cell_end,
                                                      const int32_t *__restrict__ active,
+                                                     int32_t *__restrict__ next,
                                                      const uint32_t *__restrict__ info,
                                                      float4 *__restrict__ out, ForceConst C, BrickGrid G)
 {
@@ -283,133 +286,158 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     __shared__ int iBase[NI + 1];
     __shared__ int iStart[NI];
     __shared__ int wsum[NT / kWave];
+    __shared__ int sNext;
 
-    const int tid = threadIdx.x;
-    // active[0] = number of bricks holding particles, active[1 + k] = brick id
-    if ((int)blockIdx.x >= active[0]) return;
-    const int b = active[1 + blockIdx.x];
-    const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
+    // One resident workgroup per CU takes the bricks that hold particles
+    // (active[0] of them, ids in active[1..]) one at a time from the counter
+    // `next`: no workgroup is launched for an empty brick, and the bricks'
+    // different costs even out across CUs.
+    for (;;) {
+        // the thread index is re-read per brick (an empty asm hides that it is
+        // the same), so nothing derived from it is kept live across the pair loop
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        if (tid == 0) sNext = atomicAdd(next, 1);
+        __syncthreads();
+        const int kb = sNext;
+        if (kb >= active[0]) break;  // uniform
+        const int b = active[1 + kb];
+        const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
 
-    // 1. ranges of the staged cells and their LDS bases (the staging order of
-    //    the list build)
-    int st = 0, cnt = 0;
-    if (tid < S) {
-        int gx = cx0 - 1 + St::sx_of(tid), gy = cy0 - 1 + St::sy_of(tid), gz = cz0 - 1 + St::sz_of(tid);
-        const bool ok = wrap_axis(gx, G.nx, G.periodic & 1u) && wrap_axis(gy, G.ny, (G.periodic >> 1) & 1u) &&
-                        wrap_axis(gz, G.nz, (G.periodic >> 2) & 1u);
-        if (ok) {
-            const int lin = gx + G.nx * (gy + G.ny * gz);
-            st = cell_start[lin];
-            cnt = cell_end[lin] - st;
-        }
-    }
-    int total;
-    const int ex = block_scan<NT>(cnt, total, wsum);
-    if (tid < S) {
-        cBase[tid] = ex;
-        cDelta[tid] = ex - st;
-    }
-    if (tid == 0) cBase[S] = total;
-    __syncthreads();
-    // inner cells (x fastest: each inner row is one contiguous particle range)
-    int icnt = 0, ist = 0;
-    // inner cells past the grid edge hold no centrals (on a periodic axis the
-    // staged copy would be the wrapped cell, owned by another brick)
-    if (tid < NI && cx0 + St::ix_of(tid) < G.nx && cy0 + St::iy_of(tid) < G.ny && cz0 + St::iz_of(tid) < G.nz) {
-        const int t = St::inner(tid);
-        icnt = cBase[t + 1] - cBase[t];
-        ist = cBase[t] - cDelta[t];
-    }
-    int nc;
-    const int iex = block_scan<NT>(icnt, nc, wsum);
-    if (tid < NI) {
-        iBase[tid] = iex;
-        iStart[tid] = ist;
-    }
-    if (tid == 0) iBase[NI] = nc;
-    if (nc == 0) return;  // uniform: no particle in the brick
-    __syncthreads();
-    const bool use_lds = total <= CAP;
-    // central particle of lane q (binary search over the inner cells)
-    auto central = [&](int q, int &u, int &i) {
-        int lo = 0, hi = NI - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (iBase[mid] <= q) lo = mid;
-            else hi = mid - 1;
-        }
-        u = lo;
-        i = iStart[u] + (q - iBase[u]);
-    };
-    // the list count of the first pass is requested before the staging loads
-    // so the two latencies overlap
-    int u0, i0;
-    central(min(tid, nc - 1), u0, i0);
-    const uint32_t cnt0 = tid < nc ? count[i0] : 0u;
-    if (use_lds) {
-        // 2. stage the brick and its halo: one wave per row of SX staged
-        //    cells (x-consecutive, so one contiguous LDS range and, away from
-        //    a periodic seam, one contiguous global range), lanes over the
-        //    row's particles
-        const int wave = tid / kWave, lane = tid % kWave;
-        for (int r = wave; r < SY * SZ; r += NT / kWave) {
-            const int t0 = r * SX;
-            const int b0 = cBase[t0], b1 = cBase[t0 + SX];
-            int e[SX - 1];
-#pragma unroll
-            for (int c = 0; c < SX - 1; ++c) e[c] = cBase[t0 + 1 + c];
-            const float sy = (float)(r / SZ - 2), sz = (float)(r % SZ - 2);
-            for (int s2 = b0 + lane; s2 < b1; s2 += kWave) {
-                int c = 0;
-#pragma unroll
-                for (int k = 0; k < SX - 1; ++k) c += s2 >= e[k] ? 1 : 0;
-                const int j = s2 - cDelta[t0 + c];
-                const float4 p = pos[j];
-                const float sx = (float)(c - 2);
-                // w = m x kernel coefficient, negated for boundary particles
-                // when the density diffusion needs the type
-                const float mf = p.w * C.fcoeff;
-                sP[s2] = make_float4(fmaf(sx, C.csx, p.x), fmaf(sy, C.csy, p.y), fmaf(sz, C.csz, p.z),
-                                     ((MODEL & kDiffusion) && ptype(info[j]) == kBoundary) ? -mf : mf);
-                sV[s2] = vel[j];
-                sA[s2] = aux[j];
+        // 1. ranges of the staged cells and their LDS bases (the staging order of
+        //    the list build)
+        int st = 0, cnt = 0;
+        if (tid < S) {
+            int gx = cx0 - 1 + St::sx_of(tid), gy = cy0 - 1 + St::sy_of(tid), gz = cz0 - 1 + St::sz_of(tid);
+            const bool ok = wrap_axis(gx, G.nx, G.periodic & 1u) && wrap_axis(gy, G.ny, (G.periodic >> 1) & 1u) &&
+                            wrap_axis(gz, G.nz, (G.periodic >> 2) & 1u);
+            if (ok) {
+                const int lin = gx + G.nx * (gy + G.ny * gz);
+                st = cell_start[lin];
+                cnt = cell_end[lin] - st;
             }
         }
-    }
-    __syncthreads();
-
-    // 3. one lane per central particle of the brick
-    const int M = C.max_neibs;
-    const uint32_t jmax = (uint32_t)(n - 1);
-    for (int q0 = 0; q0 < nc; q0 += NT) {
-        const int q = q0 + tid;
-        const bool act = q < nc;
-        int u = u0, i = i0;
-        uint32_t cntw = cnt0;
-        if (q0 > 0) {
-            central(act ? q : nc - 1, u, i);
-            cntw = act ? count[i] : 0u;
+        int total;
+        const int ex = block_scan<NT>(cnt, total, wsum);
+        if (tid < S) {
+            cBase[tid] = ex;
+            cDelta[tid] = ex - st;
         }
-        const int nf = min((int)(cntw & 0xFFFFu), M);
-        const int nt = min(nf + (int)(cntw >> 16), M);
-        const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
-        PairAcc A = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (ntw > 0) {
-            const size_t toff = (size_t)(i / kWave) * (kWave * M) + (i % kWave);
-            if (use_lds) {
-                const int tc = St::inner(u);
-                const int si = i + cDelta[tc];
-                const uint4 *lg = (const uint4 *)(neibs_brick + brick_entry(i, 0, brick_groups(M)));
-                brick_pairs_lds<MODEL, NT>(A, lg, nt, ntw, total, sP, sV, sA, sP[si], sV[si], sA[si], C);
-            } else {
-                // (a shallow pipeline: this path shares the register budget of
-                // the LDS path and runs only where a halo overflows)
-                const bool central_fluid = (MODEL & kDiffusion) ? ptype(info[i]) != kBoundary : true;
-                gather_pairs<MODEL, 2>(A, neibs + toff, nf, nt, ntw, M, jmax, pos, vel, aux, pos[i], vel[i], aux[i],
-                                      central_fluid, C);
+        if (tid == 0) cBase[S] = total;
+        __syncthreads();
+        // inner cells (x fastest: each inner row is one contiguous particle range)
+        int icnt = 0, ist = 0;
+        // inner cells past the grid edge hold no centrals (on a periodic axis the
+        // staged copy would be the wrapped cell, owned by another brick)
+        if (tid < NI && cx0 + St::ix_of(tid) < G.nx && cy0 + St::iy_of(tid) < G.ny && cz0 + St::iz_of(tid) < G.nz) {
+            const int t = St::inner(tid);
+            icnt = cBase[t + 1] - cBase[t];
+            ist = cBase[t] - cDelta[t];
+        }
+        int nc;
+        const int iex = block_scan<NT>(icnt, nc, wsum);
+        if (tid < NI) {
+            iBase[tid] = iex;
+            iStart[tid] = ist;
+        }
+        if (tid == 0) iBase[NI] = nc;
+        if (nc == 0) continue;  // uniform: no particle in the brick
+        __syncthreads();
+        const bool use_lds = total <= CAP;
+        // central particle of lane q (binary search over the inner cells)
+        auto central = [&](int q, int &u, int &i) {
+            int lo = 0, hi = NI - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (iBase[mid] <= q) lo = mid;
+                else hi = mid - 1;
+            }
+            u = lo;
+            i = iStart[u] + (q - iBase[u]);
+        };
+        // two lanes per central particle (lanes 2q', 2q' + 1): a brick holds
+        // fewer centrals than the workgroup has lanes (about 840 at lattice
+        // density), and half lists spread the work over all 16 waves
+        constexpr int QP = NT / 2;  // centrals per pass
+        const int h = tid & 1;
+        // the list count of the first pass is requested before the staging loads
+        // so the two latencies overlap (consecutive centrals stay on consecutive
+        // lanes: their list groups are contiguous, one coalesced load per wave)
+        int u0, i0;
+        central(min(tid / 2, nc - 1), u0, i0);
+        const uint32_t cnt0 = tid / 2 < nc ? count[i0] : 0u;
+        if (use_lds) {
+            // 2. stage the brick and its halo: one wave per row of SX staged
+            //    cells (x-consecutive, so one contiguous LDS range and, away from
+            //    a periodic seam, one contiguous global range), lanes over the
+            //    row's particles
+            const int wave = tid / kWave, lane = tid % kWave;
+            for (int r = wave; r < SY * SZ; r += NT / kWave) {
+                const int t0 = r * SX;
+                const int b0 = cBase[t0], b1 = cBase[t0 + SX];
+                int e[SX - 1];
+#pragma unroll
+                for (int c = 0; c < SX - 1; ++c) e[c] = cBase[t0 + 1 + c];
+                const float sy = (float)(r / SZ - 2), sz = (float)(r % SZ - 2);
+                for (int s2 = b0 + lane; s2 < b1; s2 += kWave) {
+                    int c = 0;
+#pragma unroll
+                    for (int k = 0; k < SX - 1; ++k) c += s2 >= e[k] ? 1 : 0;
+                    const int j = s2 - cDelta[t0 + c];
+                    const float4 p = pos[j];
+                    const float sx = (float)(c - 2);
+                    // w = m x kernel coefficient, negated for boundary particles
+                    // when the density diffusion needs the type
+                    const float mf = p.w * C.fcoeff;
+                    sP[s2] = make_float4(fmaf(sx, C.csx, p.x), fmaf(sy, C.csy, p.y), fmaf(sz, C.csz, p.z),
+                                         ((MODEL & kDiffusion) && ptype(info[j]) == kBoundary) ? -mf : mf);
+                    sV[s2] = vel[j];
+                    sA[s2] = aux[j];
+                }
             }
         }
-        if (act) out[i] = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        __syncthreads();
+
+        // 3. two lanes per central particle of the brick
+        const int M = C.max_neibs;
+        const uint32_t jmax = (uint32_t)(n - 1);
+        for (int q0 = 0; q0 < nc; q0 += QP) {
+            const int q = q0 + tid / 2;
+            const bool act = q < nc;
+            int u = u0, i = i0;
+            uint32_t cntw = cnt0;
+            if (q0 > 0) {
+                central(act ? q : nc - 1, u, i);
+                cntw = act ? count[i] : 0u;
+            }
+            const int nf = min((int)(cntw & 0xFFFFu), M);
+            const int nt = min(nf + (int)(cntw >> 16), M);
+            const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
+            PairAcc A = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (ntw > 0) {
+                const size_t toff = (size_t)(i / kWave) * (kWave * M) + (i % kWave);
+                if (use_lds) {
+                    const int tc = St::inner(u);
+                    const int si = i + cDelta[tc];
+                    const uint4 *lg = (const uint4 *)(neibs_brick + brick_entry(i, 0, brick_groups(M)));
+                    brick_pairs_lds<MODEL, NT>(A, lg, h, nt, ntw, total, sP, sV, sA, sP[si], sV[si], sA[si], C);
+                    A.ax += __shfl_xor(A.ax, 1);
+                    A.ay += __shfl_xor(A.ay, 1);
+                    A.az += __shfl_xor(A.az, 1);
+                    A.dr += __shfl_xor(A.dr, 1);
+                } else {
+                    // the first lane of the pair walks the whole list (a shallow
+                    // pipeline: this path shares the register budget of the LDS
+                    // path and runs only where a halo overflows)
+                    const bool central_fluid = (MODEL & kDiffusion) ? ptype(info[i]) != kBoundary : true;
+                    gather_pairs<MODEL, 2>(A, neibs + toff, nf, h == 0 ? nt : 0, ntw, M, jmax, pos, vel, aux, pos[i],
+                                           vel[i], aux[i], central_fluid, C);
+                }
+            }
+            if (act && h == 0)
+                out[i] = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+        __syncthreads();  // the next brick reuses the LDS
     }
 }
 
@@ -429,11 +457,12 @@ void launch_brick(const ForceArgs &a, const ForceConst &C, hipStream_t s)
         const BrickGrid G = brick_grid<BX, BY, BZ>(a.grid->ncell, a.grid->periodic);
         const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
         constexpr int NT = brick_threads(BX * BY * BZ);
-        // (active[0] was zeroed by the equation-of-state prologue)
+        // (active[0] and the brick counter were zeroed by the equation-of-state prologue)
         k_active_bricks<BX, BY, BZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(a.cell_start, a.cell_end, G, a.active);
-        k_forces_brick<MODEL, BX, BY, BZ, NT, brick_cap(BX, BY, BZ)><<<blocks, NT, 0, s>>>(
-            a.n, a.pos, a.vel, a.aux, a.neibs, a.neibs_brick, a.count, a.cell_start, a.cell_end, a.active, a.info,
-            a.out, C, G);
+        const unsigned wgs = blocks < (unsigned)sph_device_cus() ? blocks : (unsigned)sph_device_cus();
+        k_forces_brick<MODEL, BX, BY, BZ, NT, brick_cap(BX, BY, BZ)><<<wgs, NT, 0, s>>>(
+            a.n, a.pos, a.vel, a.aux, a.neibs, a.neibs_brick, a.count, a.cell_start, a.cell_end, a.active,
+            a.next, a.info, a.out, C, G);
     });
 }
 

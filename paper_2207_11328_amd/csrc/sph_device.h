@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "sph.h"
 
 namespace sph {
@@ -265,6 +267,22 @@ __global__ void k_zero_one(T *p)
     do {                                                    \
         if (hipGetLastError() != hipSuccess) return SPH_ERR_HIP; \
     } while (0)
+
+// Compute units of the current device, queried once per device and kept
+// (the only state the library holds between calls): persistent brick kernels
+// launch one workgroup per CU.
+static inline int sph_device_cus()
+{
+    static std::atomic<int> cus[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    int v = cus[dev].load(std::memory_order_relaxed);
+    if (v <= 0) {
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        cus[dev].store(v, std::memory_order_relaxed);
+    }
+    return v;
+}
 
 static inline unsigned sph_blocks(long long n, int threads)
 {
