@@ -15,7 +15,8 @@
  * - All particle arrays, lists and scalars marked "device" are device
  *   pointers on the current HIP device; the caller allocates and owns them.
  *   The library never allocates on these paths and keeps no state between
- *   calls.
+ *   calls except the compute-unit count of each device it has run on (queried
+ *   once; it sizes the grids of the persistent brick kernels).
  * - `stream` is a hipStream_t passed as void*; NULL means the default
  *   stream.  Every call only enqueues work on that stream (asynchronous);
  *   calls on distinct streams with distinct buffers may overlap.
@@ -272,8 +273,9 @@ sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
  * an error of a few ulp of 2.5 cell sizes instead of one ulp of a cell size);
  * neither is bit-exact against the other.
  * workspace: device buffer of sph_forces_workspace_bytes(capacity, n_cells)
- * bytes (per-particle equation-of-state terms and the list of bricks that
- * hold particles, both recomputed by every call).
+ * bytes (per-particle equation-of-state terms, the list of bricks that hold
+ * particles and the brick counter of the persistent brick kernel, all
+ * recomputed by every call).  Calls that share a workspace must not overlap.
  * Errors: SPH_ERR_ARG (also for an unknown kernel, formulation or
  * visc_model, a negative or non-finite delta, or delta > 0 without
  * parts->info), SPH_ERR_WORKSPACE. */
