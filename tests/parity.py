@@ -171,34 +171,38 @@ def oracle_forces_of(sc, ob, state_pos=None, state_vel=None, alpha=None):
     return st, O.forces(sc.grid, sc.params, st, ob["lists"], alpha)
 
 
-def support_edge_rows(sc, ob, rel=1e-5):
+def support_edge_rows(sc, ob, rel=1e-5, rows=None, lists=None):
     """Mask of the particles with a listed neighbour at |r - 2h| <= rel 2h.
     A kernel whose F does not vanish at the edge of its support (the
     truncated Gaussian) gives such a pair a finite weight, and the float32
     interaction decision of the GPU and the FP64 one of the oracle may then
     differ, both being correct to rounding: these particles are left out of
-    the element-wise comparison for that kernel."""
-    L = ob["lists"]
-    cell = ob["cell"].astype(np.int64) - int(sc.grid.cell_base)
-    off = ob["pos"][:, :3].astype(np.float64)
+    the element-wise comparison for that kernel.  rows/lists: a subset of
+    particles and their row-indexed lists (otherwise all, from ob)."""
+    L = ob["lists"] if lists is None else lists
+    cell_all = ob["cell"].astype(np.int64) - int(sc.grid.cell_base)
+    off_all = ob["pos"][:, :3].astype(np.float64)
+    sel = slice(None) if rows is None else np.asarray(rows)
+    cell, off = cell_all[sel], off_all[sel]
     nx, ny, nz = (int(v) for v in sc.grid.ncell)
     c = np.stack([cell % nx, (cell // nx) % ny, cell // (nx * ny)], axis=1)
     cs = [float(v) for v in sc.grid.cell_size]
     two_h = 2.0 * O.f32(sc.params.h)
-    rows = np.zeros(cell.shape[0], bool)
+    ca = np.stack([cell_all % nx, (cell_all // nx) % ny, cell_all // (nx * ny)], axis=1)
+    mask = np.zeros(cell.shape[0], bool)
     for idx, cnt in ((L.fl, L.nf), (L.bl, L.nb)):
         valid = np.arange(idx.shape[1])[None, :] < cnt[:, None]
         j = np.where(valid, idx, 0)
         r2 = np.zeros(idx.shape)
         for d, nd in enumerate((nx, ny, nz)):
-            k = c[:, d][:, None] - c[:, d][j]
+            k = c[:, d][:, None] - ca[:, d][j]
             if (sc.grid.periodic >> d) & 1:
                 k = np.where(k > 1, k - nd, k)
                 k = np.where(k < -1, k + nd, k)
-            x = k * cs[d] + (off[:, d][:, None] - off[:, d][j])
+            x = k * cs[d] + (off[:, d][:, None] - off_all[:, d][j])
             r2 += x * x
-        rows |= np.any(valid & (np.abs(np.sqrt(r2) - two_h) <= rel * two_h), axis=1)
-    return rows
+        mask |= np.any(valid & (np.abs(np.sqrt(r2) - two_h) <= rel * two_h), axis=1)
+    return mask
 
 
 def check_forces(gpu_f, acc, drho, s_acc, s_drho, tol=FORCE_TOL, label="", exclude=None):

@@ -11,7 +11,8 @@ import pytest
 from oracle import oracle as O
 from workloads import scenes as S
 
-from parity import SENT, check_forces, expected_codes_rows, gpu_lists_rows, log, make_sim, torch_sync
+from parity import (SENT, check_forces, expected_codes_rows, gpu_lists_rows, log, make_sim, support_edge_rows,
+                    torch_sync)
 
 pytestmark = pytest.mark.gpu
 
@@ -69,6 +70,42 @@ def _full_size_case(sc, n_rows, seed):
 
 def test_full_size_dam_break_1m():
     _full_size_case(S.dam_break_1m(), n_rows=20000, seed=1)
+
+
+@pytest.mark.parametrize("variant", [(3, 2, 1, 0.1), (1, 1, 0, 0.0)],
+                         ids=["gaussian-monaghan_k-landrini-diffusion", "cubic-morris-golden"])
+def test_full_size_model_variants(variant):
+    """Two compiled models on the 1.62M dam break (velocities N(0, 0.2 m/s)
+    and densities 0.5% noisy, so every viscous and diffusive term is active),
+    the LDS brick form the benchmark times, against the oracle on a seeded
+    sample of particles."""
+    import dataclasses
+    kernel, visc, form, delta = variant
+    sc = S.dam_break_1m()
+    rng = np.random.default_rng(91)
+    sc.vel[: sc.n_fluid, :3] = rng.normal(0.0, 0.2, size=(sc.n_fluid, 3)).astype(np.float32)
+    sc.vel[:, 3] *= (1.0 + 0.005 * rng.standard_normal(sc.n)).astype(np.float32)
+    sc = dataclasses.replace(sc, params=dataclasses.replace(sc.params, kernel=kernel, visc_model=visc, nu=1e-3,
+                                                              formulation=form, delta=delta))
+    log("full size variant %s: n=%d" % (variant, sc.n))
+    sim = make_sim(sc)
+    sim.build()
+    sim.forces()
+    torch_sync()
+    ss = O.sorted_f32(sc.grid, sc.cell, sc.pos, sc.vel, sc.info)
+    assert np.array_equal(sim.state_host()["info"], ss["info"]), "sort order"
+    rows = np.sort(rng.choice(sc.n, size=6000, replace=False)).astype(np.int32)
+    lists = O.neighbors_rows(sc.grid, sc.params, ss, rows)
+    assert lists.overflow == 0
+    sto = O.State.lift(ss["cell"], ss["pos"], ss["vel"], ss["info"])
+    acc, drho, sa, sd = O.forces_rows(sc.grid, sc.params, sto, rows, lists)
+    exclude = None
+    if kernel == O.GAUSSIAN:
+        exclude = support_edge_rows(sc, ss, rows=rows, lists=lists)
+        log("  %d sampled particles with a pair at the support edge left out" % int(exclude.sum()))
+        assert exclude.mean() < 0.01
+    check_forces(sim.forces_n[: sc.n].cpu().numpy()[rows], acc, drho, sa, sd, label="dam break 1m %s" % (variant,),
+                 exclude=exclude)
 
 
 @pytest.mark.slow
