@@ -75,6 +75,8 @@ def parse():
     ap.add_argument("--no-fwd-bwd", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-m1", action="store_true")
+    ap.add_argument("--no-channel", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (calibrates the HBM "
@@ -122,6 +124,89 @@ def cpu_baseline(sc, budget_s):
         "sample": "%d FP64 oracle derivative call(s) on the full step-0 state (%d particles, %d interactions "
                   "per call; oracle list build %.1f s not included)" % (calls, sc.n, inter // calls, t_build),
     }
+
+
+def cpu_baseline_one_core(sc):
+    """The same FP64 oracle derivative call on one host thread (one call)."""
+    from oracle import oracle as O
+    ob = O.build_f32(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info)
+    st = O.State.lift(ob["cell"], ob["pos"], ob["vel"], ob["info"])
+    t_all = O.threads()
+    O.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        _, _, _, _, ni = O.forces(sc.grid, sc.params, st, ob["lists"])
+        t = time.perf_counter() - t0
+    finally:
+        O.set_threads(t_all)
+    return {"value": ni / t, "unit": "interactions/s", "cores": 1, "kind": "oracle",
+            "sample": "1 FP64 oracle derivative call on the full step-0 state (%d interactions)" % ni}
+
+
+def m1_forces(sc, choice, warm=10, calls=50, late_step=500):
+    """sph_forces alone: the median of `calls` HIP-event-timed calls after
+    `warm` warm-up calls, on the step-0 state (lattice) and again after
+    `late_step` steps (disordered), each on freshly built lists; the
+    interactions of the timed state counted by sph_count_interactions."""
+    import torch
+    from paper_2207_11328_amd import abi
+    from paper_2207_11328_amd.sim import Simulation
+    sim = Simulation(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0", brick=choice["brick"],
+                     use_bricks=choice["bricks"])
+    stream = torch.cuda.current_stream()
+    out = {}
+
+    def measure():
+        sim.build()
+        for _ in range(warm):
+            sim.forces()
+        ev = []
+        for _ in range(calls):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            sim.forces()
+            b.record(stream)
+            ev.append((a, b))
+        torch.cuda.synchronize()
+        sim.check_status()
+        t = sorted(x.elapsed_time(y) for x, y in ev)[calls // 2] * 1e-3
+        abi.sph_count_interactions(sim.g, sim.p, sim.parts, sim.neibs, sim.neib_count, sim.max_neibs, sim.count)
+        inter = int(sim.count.item())
+        return {"step": sim.steps_done, "forces_ms_median": t * 1e3, "interactions": inter,
+                "interactions_per_s": inter / t}
+
+    out["step_0"] = measure()
+    for _ in range(late_step):
+        sim.step()
+    torch.cuda.synchronize()
+    sim.check_status()
+    out["step_%d" % late_step] = measure()
+    return out
+
+
+def channel(steps=10, warm=3):
+    """The 16.6M-particle channel (periodic in y): whole steps (build every
+    10 steps) with the autotuned brick shape; MIPPS = particles x steps/s / 1e6."""
+    import torch
+    from paper_2207_11328_amd import tune
+    from paper_2207_11328_amd.sim import Simulation
+    sc = make_scene("channel_16m")
+    choice = tune.autotune(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0")
+    sim = Simulation(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0", brick=choice["brick"],
+                     use_bricks=choice["bricks"])
+    for _ in range(warm):
+        sim.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sim.step()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    sim.check_status()
+    return {"workload": "channel_16m", "particles": sc.n, "fluid": sc.n_fluid, "steps": steps,
+            "ms_per_step": t / steps * 1e3, "steps_per_s": steps / t, "mipps": sc.n * steps / t / 1e6,
+            "brick": list(choice["brick"]), "bricks": choice["bricks"]}
 
 
 def fwd_bwd(sc, dt, K=10, reps=3, brick=None, use_bricks=True):
@@ -198,7 +283,7 @@ def batched(units=5, warm_units=1):
     sim.check_status()
     steps = units * sim.rebuild_every
     return {"scenes": len(tanks), "particles": st.n, "fluid": st.n_fluid, "steps": steps,
-            "ms_per_step": t / steps * 1e3, "particle_steps_per_s": st.n * steps / t,
+            "ms_per_step": t / steps * 1e3, "particle_steps_per_s": st.n * steps / t, "mipps": st.n * steps / t / 1e6,
             "fluid_particle_steps_per_s": st.n_fluid * steps / t, "graph_units": units,
             "tuned": {"brick": list(choice["brick"]), "bricks": choice["bricks"],
                       "per_step_ms": {k: v * 1e3 for k, v in choice["per_step_s"].items()}}}
@@ -384,6 +469,7 @@ def main():
         "interactions_per_forces_call": inter / calls,
         "listed_per_forces_call": listed / calls,
         "steps_per_s": K / t_total,
+        "mipps": n * K / t_total / 1e6,
         "replay_bitwise_identical": bool(same),
         # the derivative call: its algorithmic intensity (on the dam break
         # about 13 FLOP per algorithmic byte) is above the FP32/HBM ridge
@@ -406,6 +492,8 @@ def main():
     }
     if not args.no_variants:
         out["variants"] = variants(sim, sc, inter / calls)
+    if not args.no_m1:
+        out["m1"] = m1_forces(sc, choice)
     if not args.no_batched:
         out["batched"] = batched()
     if not args.no_fwd_bwd:
@@ -424,8 +512,13 @@ def main():
         dt64 = float(s64.d_dt.item())
         del s64
         out["adjoint_64k"] = fwd_bwd(sc64, dt64, brick=c64["brick"], use_bricks=c64["bricks"])
+    if not args.no_channel:
+        del sim
+        torch.cuda.empty_cache()
+        out["channel"] = channel()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+        out["cpu_baseline_1core"] = cpu_baseline_one_core(sc)
     print(json.dumps(out), flush=True)
 
 
