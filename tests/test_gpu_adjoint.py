@@ -254,12 +254,20 @@ def _front(sc, steps, dt):
     return ids[fl][np.argsort(-x[fl, 0])[:k]], st0
 
 
-def test_rollout_gradient_matches_oracle_reverse():
+@pytest.mark.parametrize("variant", [None, (1, 2, 1, 0.1)], ids=["default", "cubic-monaghan_k-landrini-diffusion"])
+def test_rollout_gradient_matches_oracle_reverse(variant):
     """Differentiable dam break (reduced size), 24 fixed-dt steps, rebuild
     every 10, checkpoint every 20: dL/d(alpha, c0, u0) of L = mean x of the
-    front particles, through torch.autograd, against the FP64 oracle."""
+    front particles, through torch.autograd, against the FP64 oracle; for the
+    default model and for a variant (cubic spline, Landrini-Morris, Monaghan
+    K laminar term, density diffusion)."""
+    import dataclasses
     from paper_2207_11328_amd.adjoint import AdjointRollout, SPHRollout
     sc = S.dam_break(dp=0.04, u0_sigma=0.01, seed=2)
+    if variant is not None:
+        kernel, visc, form, delta = variant
+        sc = dataclasses.replace(sc, params=dataclasses.replace(sc.params, kernel=kernel, visc_model=visc, nu=1e-3,
+                                                                  formulation=form, delta=delta))
     steps, dt = 24, 1.5e-4
     front, st0 = _front(sc, steps, dt)
     L_o, adj_o, gp_o, _ = O.rollout_adjoint(sc.grid, sc.params, st0, steps, dt, O.front_loss(sc.grid, front))
