@@ -235,11 +235,19 @@ __global__ __launch_bounds__(256) void k_active_bricks(const int32_t *__restrict
     if (b < nb) {
         const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
         const int cx1 = min(cx0 + BX, G.nx) - 1;
-        for (int z = cz0; z < min(cz0 + BZ, G.nz); ++z)
-            for (int y = cy0; y < min(cy0 + BY, G.ny); ++y) {
-                const int row = G.nx * (y + G.ny * z);
-                cnt += cell_end[row + cx1] - cell_start[row + cx0];
-            }
+        // every row's loads are independent: all issued first (rows past the
+        // grid edge read a valid row), then masked and summed
+        int e[BY * BZ], s0[BY * BZ];
+#pragma unroll
+        for (int k = 0; k < BY * BZ; ++k) {
+            const int y = min(cy0 + k % BY, G.ny - 1), z = min(cz0 + k / BY, G.nz - 1);
+            const int row = G.nx * (y + G.ny * z);
+            e[k] = cell_end[row + cx1];
+            s0[k] = cell_start[row + cx0];
+        }
+#pragma unroll
+        for (int k = 0; k < BY * BZ; ++k)
+            cnt += (cy0 + k % BY < G.ny && cz0 + k / BY < G.nz) ? e[k] - s0[k] : 0;
     }
     const bool has = cnt > 0;
     // wave-aggregated append
