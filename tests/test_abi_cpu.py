@@ -135,3 +135,18 @@ def test_unknown_model_switches_are_rejected(abi):
                         (abi.SPH_ERR_WORKSPACE, abi.SPH_ERR_WORKSPACE)
     for bad in (dict(kernel=4), dict(kernel=-1), dict(visc_model=3), dict(formulation=2), dict(delta=-0.1)):
         assert both(params(**bad)) == (abi.SPH_ERR_ARG, abi.SPH_ERR_ARG), bad
+
+
+def test_weak_compressibility_check():
+    """c0 >= 10 U with U the free-fall speed of the water height: the dam
+    break's c0 = 20 m/s is below 10 sqrt(2 g 0.3) = 24.3 m/s (expected density
+    variation about 1.5%); c0 = 30 m/s passes."""
+    from paper_2207_11328_amd.checks import weak_compressibility
+    from workloads import scenes as S
+    p = S.sph_params(0.0043)
+    r = weak_compressibility(p, 0.3)
+    assert abs(r["U"] - (2 * 9.81 * 0.3) ** 0.5) < 1e-12
+    assert not r["ok"] and 0.014 < r["density_variation"] < 0.015
+    import dataclasses
+    assert weak_compressibility(dataclasses.replace(p, c0=30.0), 0.3)["ok"]
+    assert weak_compressibility(p, 0.0, u_max=3.0)["U"] == 3.0
