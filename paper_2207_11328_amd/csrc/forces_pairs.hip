@@ -47,7 +47,12 @@ struct PairAcc {
 // sum and one subtraction: (ai.y + aj.y)(w - |w|) = alpha h (c_i + c_j) min(w, 0));
 // ai.x, aj.x = P/rho^2 (golden rule) or P (Landrini-Morris).
 // pair_fluid: both particles are fluid (density diffusion applies).
-template <int MODEL>
+// LDS: the form of the LDS brick loop, where a pair outside the support or
+// past the list has m_j F set to zero and every term is computed (no branch,
+// fewer registers); the global-gather loop keeps per-term selects, which the
+// compiler turns into a branch that skips the term arithmetic and keeps more
+// gathers in flight.  Both give the same values (the zeroed terms add +-0).
+template <int MODEL, bool LDS>
 __device__ __forceinline__ void pair_core(PairAcc &A, float xx, float xy, float xz, const float4 &vi,
                                           const float2 &ai, float mcj, const float4 &vj, const float2 &aj,
                                           bool valid, bool pair_fluid, const ForceConst &C)
@@ -57,7 +62,10 @@ __device__ __forceinline__ void pair_core(PairAcc &A, float xx, float xy, float 
     bool inter = valid && (r2 < C.lim2);
     if constexpr (KER == SPH_KERNEL_QUADRATIC) inter = inter && r2 > 0.0f;  // its F is unbounded at r = 0
     const float r = __builtin_amdgcn_sqrtf(r2);
-    const float mF = kernel_mF<KER>(mcj, r, r2, C.inv_h, C.inv_h2);  // m_j F_ij
+    // m_j F_ij; in the LDS form zero for a pair outside the support or past
+    // the list (every term below is a finite factor times mF)
+    const float mF0 = kernel_mF<KER>(mcj, r, r2, C.inv_h, C.inv_h2);
+    const float mF = LDS ? (inter ? mF0 : 0.0f) : mF0;
     const float ux = vi.x - vj.x;
     const float uy = vi.y - vj.y;
     const float uz = vi.z - vj.z;
@@ -67,10 +75,10 @@ __device__ __forceinline__ void pair_core(PairAcc &A, float xx, float xy, float 
         // (P_i + P_j)/(rho_i rho_j) and the continuity weight rho_i/rho_j
         const float inv_rj = __builtin_amdgcn_rcpf(vj.w);
         pres = (ai.x + aj.x) * (inv_rj * __builtin_amdgcn_rcpf(vi.w));
-        A.dr = inter ? fmaf(mF * (vi.w * inv_rj), udx, A.dr) : A.dr;
+        A.dr = (LDS || inter) ? fmaf(mF * (vi.w * inv_rj), udx, A.dr) : A.dr;
     } else {
         pres = ai.x + aj.x;
-        A.dr = inter ? fmaf(mF, udx, A.dr) : A.dr;
+        A.dr = (LDS || inter) ? fmaf(mF, udx, A.dr) : A.dr;
     }
     // Monaghan: Pi = -alpha h (c_i + c_j)/2 min(u.x, 0) / ((rho_i + rho_j)/2 (r^2 + eps h^2))
     const float den = (vi.w + vj.w) * (r2 + C.eps_h2);
@@ -78,12 +86,12 @@ __device__ __forceinline__ void pair_core(PairAcc &A, float xx, float xy, float 
     // laminar K form: + 4 K nu m_j F (u.x) / ((rho_i + rho_j)(r^2 + eps h^2)) x, the same denominator
     if constexpr (model_visc(MODEL) == kMonaghanK) vnum = fmaf(-C.k_four_nu, udx, vnum);
     const float visc = vnum * __builtin_amdgcn_rcpf(den);
-    const float coef = inter ? -mF * (pres + visc) : 0.0f;
+    const float coef = (LDS || inter) ? -mF * (pres + visc) : 0.0f;
     A.ax = fmaf(coef, xx, A.ax);
     A.ay = fmaf(coef, xy, A.ay);
     A.az = fmaf(coef, xz, A.az);
     if constexpr (model_visc(MODEL) == kMorris) {
-        const float lam = inter ? C.four_nu * mF * __builtin_amdgcn_rcpf(vi.w + vj.w) : 0.0f;
+        const float lam = (LDS || inter) ? C.four_nu * mF * __builtin_amdgcn_rcpf(vi.w + vj.w) : 0.0f;
         A.ax = fmaf(lam, ux, A.ax);
         A.ay = fmaf(lam, uy, A.ay);
         A.az = fmaf(lam, uz, A.az);
@@ -91,7 +99,7 @@ __device__ __forceinline__ void pair_core(PairAcc &A, float xx, float xy, float 
     if constexpr (MODEL & kDiffusion) {
         // Molteni-Colagrossi: 2 delta h c0 (rho_i - rho_j) m_j F r^2 / ((r^2 + eps h^2) rho_j)
         const float dd = C.diff * (vi.w - vj.w) * mF * r2 * __builtin_amdgcn_rcpf((r2 + C.eps_h2) * vj.w);
-        A.dr = (inter && pair_fluid) ? A.dr + dd : A.dr;
+        A.dr = ((LDS || inter) && pair_fluid) ? A.dr + dd : A.dr;
     }
 }
 
@@ -104,7 +112,7 @@ __device__ __forceinline__ void pair_terms(PairAcc &A, uint32_t e, const float4 
     const float xx = fmaf(entry_k(e, 0), C.csx, pi.x - pj.x);
     const float xy = fmaf(entry_k(e, 1), C.csy, pi.y - pj.y);
     const float xz = fmaf(entry_k(e, 2), C.csz, pi.z - pj.z);
-    pair_core<MODEL>(A, xx, xy, xz, vi, ai, pj.w * C.fcoeff, vj, aj, valid, pair_fluid, C);
+    pair_core<MODEL, false>(A, xx, xy, xz, vi, ai, pj.w * C.fcoeff, vj, aj, valid, pair_fluid, C);
 }
 
 // Pairs of one lane's list gathered from global memory, in list order.
@@ -249,7 +257,7 @@ __device__ __forceinline__ void brick_pairs_lds(PairAcc &A, const uint4 *lg, int
         for (int s = 0; s < kBrickGroup; ++s) {
             const int r = s % kRing;
             // staged w = +-(m_j x kernel coefficient), negative for boundary particles
-            pair_core<MODEL>(A, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, vi, ai, fabsf(P[r].w), V[r], X[r],
+            pair_core<MODEL, true>(A, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, vi, ai, fabsf(P[r].w), V[r], X[r],
                             g0 * kBrickGroup + s < nt, pi.w > 0.0f && P[r].w > 0.0f, C);
             const int s2 = s + kRing;
             fetch(s2 < kBrickGroup ? group_entry(gc, s2) : group_entry(gn, s2 - kBrickGroup), P[r], V[r], X[r]);
