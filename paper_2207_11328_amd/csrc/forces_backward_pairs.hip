@@ -54,7 +54,13 @@ struct BackAcc {
 
 // aux: xi = (p or P, c, dp/drho or dP/drho, dc/drho) of the central; xj = (p
 // or P, c) of the neighbour.  pair_fluid: both are fluid (density diffusion).
-template <int MODEL>
+// MASKED: a pair outside the support or past the list has F and F'/r set to
+// zero and is accumulated anyway (every term is a finite factor times one of
+// them, so it adds +-0; the LDS loop only stages real particles, so every
+// factor is finite); otherwise a branch skips it.  The LDS loop takes the
+// masked form except with density diffusion, whose longer pair body spills
+// when it runs for every slot.
+template <int MODEL, bool MASKED>
 __device__ __forceinline__ void pair_adjoint_core(BackAcc &G, float xx, float xy, float xz, float mi,
                                                   const float4 &vi, const float4 &xi, const float4 &gi, float mj,
                                                   const float4 &vj, const float2 &xj, const float4 &gj, bool valid,
@@ -72,6 +78,10 @@ __device__ __forceinline__ void pair_adjoint_core(BackAcc &G, float xx, float xy
     const float inv_r = __builtin_amdgcn_rcpf(r);
     float F, Fp_r;  // F and F'(r)/r
     kernel_F_dF<KER>(C.fcoeff, r, r2, inv_r, C.inv_h, C.inv_h2, F, Fp_r);
+    if (MASKED) {
+        F = inter ? F : 0.0f;
+        Fp_r = inter ? Fp_r : 0.0f;
+    }
     const float ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
     const float w = fmaf(ux, xx, fmaf(uy, xy, uz * xz));
     const float rs = vi.w + vj.w;
@@ -173,7 +183,7 @@ __device__ __forceinline__ void pair_adjoint_core(BackAcc &G, float xx, float xy
             gc = fmaf(w1 * C.diff * dr * Gd, C.inv_c0, gc);
         }
     }
-    if (inter) {
+    if (MASKED || inter) {
         G.ox += ox;
         G.oy += oy;
         G.oz += oz;
@@ -196,7 +206,7 @@ __device__ __forceinline__ void pair_adjoint(BackAcc &G, uint32_t e, const float
     const float xx = fmaf(entry_k(e, 0), C.csx, pi.x - pj.x);
     const float xy = fmaf(entry_k(e, 1), C.csy, pi.y - pj.y);
     const float xz = fmaf(entry_k(e, 2), C.csz, pi.z - pj.z);
-    pair_adjoint_core<MODEL>(G, xx, xy, xz, pi.w, vi, xi, gi, pj.w, vj, make_float2(xj.x, xj.y), gj, valid,
+    pair_adjoint_core<MODEL, false>(G, xx, xy, xz, pi.w, vi, xi, gi, pj.w, vj, make_float2(xj.x, xj.y), gj, valid,
                             pair_fluid, C);
 }
 
@@ -352,7 +362,7 @@ __device__ __forceinline__ void brick_adjoint_lds(BackAcc &G, const uint4 *lg, i
         for (int s = 0; s < kBrickGroup; ++s) {
             const int r = s % R;
             // staged w = +-m_j, negative for boundary particles
-            pair_adjoint_core<MODEL>(G, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, fabsf(pi.w), vi, xi, gi,
+            pair_adjoint_core<MODEL, !(MODEL & kDiffusion)>(G, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, fabsf(pi.w), vi, xi, gi,
                                     fabsf(P[r].w), V[r], X[r], Gj[r], g0 * kBrickGroup + s < nt,
                                     pi.w > 0.0f && P[r].w > 0.0f, C);
             const int s2 = s + R;
