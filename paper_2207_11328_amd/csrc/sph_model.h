@@ -61,6 +61,12 @@ inline double kernel_coeff(int kind, double h)
 // Shape factors f(q) of F = c f(q):
 //   Wendland (q - 2)^3;  cubic spline 9/4 q - 3 (q < 1), -3/4 (2 - q)^2 / q;
 //   quadratic 1 - 2/q;  Gaussian -exp(-q^2).
+// The cubic spline is evaluated without a select on q < 1 (one there makes the
+// compiler split the unrolled pair loop and spill): with b = max(q, 1),
+// f = 9/4 min(q - 1, 0) - 3/4 (2 - b)^2 / b takes the inner branch for q < 1
+// (the second term is -3/4) and the outer one, to its own relative rounding,
+// for q >= 1 (the first is 0), and f'(q) = 3/4 (2 - b)(2 + b) / b^2, which is
+// 9/4 for q <= 1.  No term cancels and b >= 1, so F stays finite at r = 0.
 // kernel_mF returns m_j F given mc = m_j c, r = sqrt(r2) (unused by the
 // Gaussian, which needs only r2).
 template <int KER>
@@ -71,9 +77,8 @@ __device__ __forceinline__ float kernel_mF(float mc, float r, float r2, float in
         return (qm2 * qm2) * (qm2 * mc);
     } else if constexpr (KER == SPH_KERNEL_CUBIC_SPLINE) {
         const float q = r * inv_h;
-        const float t = 2.0f - q;
-        const float outer = -0.75f * (t * t) * __builtin_amdgcn_rcpf(q);
-        return mc * (q < 1.0f ? fmaf(2.25f, q, -3.0f) : outer);
+        const float b = fmaxf(q, 1.0f), tb = 2.0f - b;
+        return mc * fmaf(2.25f, fminf(q - 1.0f, 0.0f), -0.75f * tb * (tb * __builtin_amdgcn_rcpf(b)));
     } else if constexpr (KER == SPH_KERNEL_QUADRATIC) {
         const float q = r * inv_h;
         return mc * fmaf(-2.0f, __builtin_amdgcn_rcpf(q), 1.0f);
@@ -93,12 +98,11 @@ __device__ __forceinline__ void kernel_F_dF(float c, float r, float r2, float in
         Fp_r = 3.0f * c * qm2 * qm2 * inv_h * inv_r;
     } else if constexpr (KER == SPH_KERNEL_CUBIC_SPLINE) {
         const float q = r * inv_h;
-        const float iq = __builtin_amdgcn_rcpf(q);
-        const float t = 2.0f - q;
-        const bool in = q < 1.0f;
-        F = c * (in ? fmaf(2.25f, q, -3.0f) : -0.75f * t * t * iq);
-        // dF/dr = c/h (9/4) inside, c/h (3/4)(4 - q^2)/q^2 outside
-        Fp_r = c * inv_h * inv_r * (in ? 2.25f : 0.75f * (4.0f - q * q) * iq * iq);
+        const float b = fmaxf(q, 1.0f), tb = 2.0f - b;
+        const float ib = __builtin_amdgcn_rcpf(b);
+        F = c * fmaf(2.25f, fminf(q - 1.0f, 0.0f), -0.75f * tb * (tb * ib));
+        // dF/dr = (c/h) f'(q)
+        Fp_r = c * inv_h * inv_r * (0.75f * tb * (2.0f + b) * ib * ib);
     } else if constexpr (KER == SPH_KERNEL_QUADRATIC) {
         const float q = r * inv_h;
         const float iq = __builtin_amdgcn_rcpf(q);
