@@ -272,10 +272,14 @@ sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
  * The two differ by rounding only (the separation of the brick form carries
  * an error of a few ulp of 2.5 cell sizes instead of one ulp of a cell size);
  * neither is bit-exact against the other.
+ * In the brick form only bricks where some particle has a non-empty list are
+ * staged; the zero derivatives of particles with an empty list are written
+ * without it.
  * workspace: device buffer of sph_forces_workspace_bytes(capacity, n_cells)
- * bytes (per-particle equation-of-state terms, the list of bricks that hold
- * particles and the brick counter of the persistent brick kernel, all
- * recomputed by every call).  Calls that share a workspace must not overlap.
+ * bytes (per-particle equation-of-state terms, the list of bricks with a
+ * pair, the brick counter of the persistent brick kernel and one flag byte
+ * per cell, set and cleared within every call; its contents on entry do not
+ * change any result).  Calls that share a workspace must not overlap.
  * Errors: SPH_ERR_ARG (also for an unknown kernel, formulation or
  * visc_model, a negative or non-finite delta, or delta > 0 without
  * parts->info), SPH_ERR_WORKSPACE. */
@@ -344,8 +348,9 @@ size_t sph_forces_backward_workspace_bytes(int32_t capacity, int32_t n_cells);
  * build of the lists, or all NULL).  With them the adjoint is computed brick
  * by brick of cells from LDS (each brick in two halves along y); without them
  * one lane per particle gathers from global memory.  The two agree to
- * rounding.  workspace: sph_forces_backward_workspace_bytes(capacity,
- * n_cells).  Every kernel, formulation and laminar term of sph_forces is
+ * rounding; the brick form skips the bricks without a pair as sph_forces
+ * does.  workspace: sph_forces_backward_workspace_bytes(capacity, n_cells)
+ * (its contents on entry do not change any result).  Every kernel, formulation and laminar term of sph_forces is
  * differentiated, and the density diffusion term (params->delta) too; its
  * coefficient enters dL/dc0, the laminar terms dL/dnu.  Errors: SPH_ERR_ARG
  * (as for sph_forces, and for a grid with a per-cell alpha table),

@@ -25,14 +25,18 @@ constexpr int kThreads = 256;
 // (1 + d)^7 - 1, full relative accuracy near rho0).  aux = (P/rho^2,
 // alpha h c / 2) with c = c0 (1 + d)^3 (aux.x = P for the Landrini-Morris
 // formulation).
-// Also (brick form): zeroes the active-brick count, the brick counter of the
-// persistent brick kernel and the derivatives of particles the last build
-// dropped (cell < 0), which no brick visits.
+// Also (brick form): zeroes the active-brick count and the brick counter of
+// the persistent brick kernel, writes the (zero) derivatives of particles
+// with an empty list or dropped by the last build (cell < 0), and flags the
+// cells that hold a particle with a non-empty list, so that only bricks with
+// a pair are staged.
 __global__ __launch_bounds__(kThreads) void k_eos(int n, const float4 *__restrict__ vel, float2 *__restrict__ aux,
                                                   const int32_t *__restrict__ cell,
                                                   const float *__restrict__ cell_alpha, int cell_base, float h,
                                                   ForceConst C, int32_t *__restrict__ active,
-                                                  int32_t *__restrict__ next, float4 *__restrict__ out)
+                                                  int32_t *__restrict__ next, float4 *__restrict__ out,
+                                                  const uint32_t *__restrict__ count, uint8_t *__restrict__ cell_flags,
+                                                  int n_cells)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (active && i == 0) {
@@ -44,7 +48,13 @@ __global__ __launch_bounds__(kThreads) void k_eos(int n, const float4 *__restric
     if (cell_alpha || out) {
         const int c = cell[i];
         if (cell_alpha && c >= 0) alpha_h = cell_alpha[c - cell_base] * h;
-        if (out && c < 0) out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (out) {
+            const int lc = c - cell_base;
+            if (c < 0 || count[i] == 0u || (unsigned)lc >= (unsigned)n_cells)
+                out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            else
+                cell_flags[lc] = 1;
+        }
     }
     const float rho = vel[i].w;
     const float d = (rho - C.rho0) * C.inv_rho0;
@@ -138,8 +148,9 @@ extern "C" size_t sph_forces_workspace_bytes(int32_t capacity, int32_t n_cells)
 {
     if (capacity < 0 || n_cells < 0) return 0;
     // per-particle EOS terms, then the active-brick list (at most one brick per
-    // cell) and the brick counter
-    return aux_bytes(capacity > 0 ? capacity : 1) + sizeof(int32_t) * ((size_t)n_cells + 2) + 256;
+    // cell), the brick counter and one flag byte per cell
+    return aux_bytes(capacity > 0 ? capacity : 1) + sizeof(int32_t) * ((size_t)n_cells + 2) +
+           (((size_t)n_cells + 255) & ~(size_t)255) + 256;
 }
 
 extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
@@ -170,9 +181,11 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
     const bool bricks = cell_start && cell_end && neibs_brick;
     if (bricks && !parts->cell) return SPH_ERR_ARG;
     if ((params->delta != 0.0f) && !parts->info) return SPH_ERR_ARG;
+    uint8_t *cell_flags = (uint8_t *)(active + n_cells + 2);
     k_eos<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, vel, aux, parts->cell, grid->cell_alpha, grid->cell_base,
                                                        params->h, C, bricks ? active : nullptr,
-                                                       active + n_cells + 1, bricks ? out : nullptr);
+                                                       active + n_cells + 1, bricks ? out : nullptr, neib_count,
+                                                       cell_flags, (int)n_cells);
     ForceArgs a;
     a.grid = grid;
     a.shape = shape;
@@ -188,6 +201,7 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
     a.cell_end = cell_end;
     a.active = active;
     a.next = active + n_cells + 1;
+    a.cell_flags = cell_flags;
     a.out = out;
     a.bricks = bricks;
     static bool (*const pairs[4])(int, const ForceArgs &, const ForceConst &, hipStream_t) = {

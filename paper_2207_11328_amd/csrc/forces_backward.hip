@@ -17,11 +17,31 @@ constexpr int kThreads = 256;
 
 // aux = (P/rho^2, c, d(P/rho^2)/drho, dc/drho) for gamma = 7, or
 // (P, c, dP/drho = c^2, dc/drho) for the Landrini-Morris formulation
+// Also (brick form): flags the cells that hold a particle with a non-empty
+// list (only bricks with a pair are staged) and, unless the call accumulates,
+// writes the (zero) adjoint of particles with an empty list or dropped by the
+// last build (cell < 0; grad_pos.w is kept).
 __global__ __launch_bounds__(kThreads) void k_eos_grad(int n, const float4 *__restrict__ vel,
-                                                       float4 *__restrict__ aux, BackConst C)
+                                                       float4 *__restrict__ aux, BackConst C,
+                                                       const int32_t *__restrict__ cell, int cell_base,
+                                                       const uint32_t *__restrict__ count,
+                                                       uint8_t *__restrict__ cell_flags, int n_cells,
+                                                       float4 *__restrict__ gpos, float4 *__restrict__ gvel)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
+    if (cell_flags) {
+        const int c = cell[i];
+        const int lc = c - cell_base;
+        if (c < 0 || count[i] == 0u || (unsigned)lc >= (unsigned)n_cells) {
+            if (gpos) {
+                gpos[i] = make_float4(0.0f, 0.0f, 0.0f, gpos[i].w);
+                gvel[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
+        } else {
+            cell_flags[lc] = 1;
+        }
+    }
     const float rho = vel[i].w;
     const float d = (rho - C.rho0) * C.inv_rho0;
     float poly = 7.0f + d;
@@ -82,18 +102,11 @@ __global__ __launch_bounds__(kThreads) void k_unpermute(int n, const uint32_t *_
 
 size_t aux_bytes(int64_t cap) { return (size_t)((16 * cap + 255) & ~(int64_t)255); }
 size_t partial_bytes(int64_t cap) { return (size_t)(3 * 8 * ((cap + kThreads - 1) / kThreads) + 256); }
-// per-brick parameter partials (at most one brick per cell) and the active-brick list
-size_t brick_bytes(int64_t n_cells) { return (size_t)(3 * 8 * (n_cells + 1) + 4 * (n_cells + 2) + 256); }
-
-__global__ __launch_bounds__(kThreads) void k_zero_dropped_adjoint(int n, const int32_t *__restrict__ cell,
-                                                                   float4 *__restrict__ gpos,
-                                                                   float4 *__restrict__ gvel)
+// per-brick parameter partials (at most one brick per cell), the active-brick
+// list and one flag byte per cell
+size_t brick_bytes(int64_t n_cells)
 {
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i < n && cell[i] < 0) {
-        gpos[i] = make_float4(0.0f, 0.0f, 0.0f, gpos[i].w);
-        gvel[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    }
+    return (size_t)(3 * 8 * (n_cells + 1) + 4 * (n_cells + 2) + ((n_cells + 255) & ~(int64_t)255) + 256);
 }
 
 }  // namespace
@@ -166,7 +179,11 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
     const int model = model_of(p);
     int n_partials = 0;
     if (n > 0) {
-        k_eos_grad<<<nblocks, kThreads, 0, s>>>(n, (const float4 *)parts->vel, aux, C);
+        uint8_t *cell_flags = (uint8_t *)(active + n_cells + 2);
+        k_eos_grad<<<nblocks, kThreads, 0, s>>>(n, (const float4 *)parts->vel, aux, C, parts->cell,
+                                                grid->cell_base, neib_count, bricks ? cell_flags : nullptr,
+                                                (int)n_cells, bricks && !accumulate ? (float4 *)grad_pos : nullptr,
+                                                (float4 *)grad_vel);
         BackArgs a;
         a.grid = grid;
         a.shape = shape;
@@ -183,16 +200,13 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
         a.cell_end = cell_end;
         a.active = active;
         a.next = active + n_cells + 1;
+        a.cell_flags = cell_flags;
         a.gpos = (float4 *)grad_pos;
         a.gvel = (float4 *)grad_vel;
         a.partial = bricks ? bpartial : partial;
         a.accumulate = accumulate;
         a.bricks = bricks;
         if (!pairs[model_kernel(model)](model, a, C, s, n_partials)) return SPH_ERR_ARG;
-        // particles dropped by the build lie in no brick
-        if (bricks && !accumulate)
-            k_zero_dropped_adjoint<<<nblocks, kThreads, 0, s>>>(n, parts->cell, (float4 *)grad_pos,
-                                                                 (float4 *)grad_vel);
     }
     k_param_reduce<<<1, kReduceThreads, 0, s>>>(n_partials, bricks ? bpartial : partial, grad_params, accumulate);
     SPH_CHECK_LAUNCH();

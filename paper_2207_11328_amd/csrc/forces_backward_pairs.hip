@@ -553,7 +553,8 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
                 }
                 add_partner(A);
                 if (act && h == 0) {
-                    store_adjoint(i, nt, A, gpos, gvel, accumulate);
+                    // (a particle with an empty list was written by the prologue)
+                    if (nt > 0) store_adjoint(i, nt, A, gpos, gvel, accumulate);
                     if (nt > 0) {
                         pa += (double)A.galpha;
                         pc += (double)A.gc0;
@@ -604,7 +605,8 @@ void launch_backward_brick(const BackArgs &a, const BackConst &C, hipStream_t s,
         k_zero_counters<<<1, 1, 0, s>>>(a.active, a.next);
         k_zero_f64<<<sph_blocks(3 * blocks, kThreads) < 1024u ? sph_blocks(3 * blocks, kThreads) : 1024u, kThreads,
                      0, s>>>(3 * (int)blocks, a.partial);
-        k_active_bricks<BX, BY, BZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(a.cell_start, a.cell_end, G, a.active);
+        k_active_bricks<BX, BY, BZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(a.cell_start, a.cell_end, G, a.active,
+                                                                             a.cell_flags);
         const unsigned wgs = blocks < (unsigned)sph_device_cus() ? blocks : (unsigned)sph_device_cus();
         k_forces_backward_brick<MODEL, BX, BY, BZ, kBackBrickThreads, kBackBrickCap>
             <<<wgs, kBackBrickThreads, 0, s>>>(a.n, a.pos, a.vel, a.aux, a.gforce, a.neibs, a.neibs_brick,

@@ -442,8 +442,8 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
                                            vel[i], aux[i], central_fluid, C);
                 }
             }
-            if (act && h == 0)
-                out[i] = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            // (a particle with an empty list was written by the prologue)
+            if (act && h == 0 && nt > 0) out[i] = make_float4(A.ax, A.ay, A.az, A.dr);
         }
         __syncthreads();  // the next brick reuses the LDS
     }
@@ -466,7 +466,8 @@ void launch_brick(const ForceArgs &a, const ForceConst &C, hipStream_t s)
         const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
         constexpr int NT = brick_threads(BX * BY * BZ);
         // (active[0] and the brick counter were zeroed by the equation-of-state prologue)
-        k_active_bricks<BX, BY, BZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(a.cell_start, a.cell_end, G, a.active);
+        k_active_bricks<BX, BY, BZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(a.cell_start, a.cell_end, G, a.active,
+                                                                             a.cell_flags);
         const unsigned wgs = blocks < (unsigned)sph_device_cus() ? blocks : (unsigned)sph_device_cus();
         k_forces_brick<MODEL, BX, BY, BZ, NT, brick_cap(BX, BY, BZ)><<<wgs, NT, 0, s>>>(
             a.n, a.pos, a.vel, a.aux, a.neibs, a.neibs_brick, a.count, a.cell_start, a.cell_end, a.active,

@@ -609,7 +609,7 @@ extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params
             constexpr int NT = brick_threads(BX * BY * BZ);
             k_zero_one<int32_t><<<1, 1, 0, s>>>(active);
             // brick activity from the (exclusive-scan) cell starts: start[c + 1] is the end of cell c
-            k_active_bricks<BX, BY, BZ><<<sph_blocks(bricks, 256), 256, 0, s>>>(start, start + 1, G, active);
+            k_active_bricks<BX, BY, BZ><<<sph_blocks(bricks, 256), 256, 0, s>>>(start, start + 1, G, active, nullptr);
             k_build_brick<BX, BY, BZ, NT, kBuildCap><<<bricks, NT, 0, s>>>(
                 n, max_neibs, t_pos, t_info, start, G, grid->cell_size[0], grid->cell_size[1], grid->cell_size[2],
                 rs2, active, neibs, neibs_brick, neib_count, d_status);

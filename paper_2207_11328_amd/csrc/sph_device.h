@@ -224,14 +224,22 @@ __device__ __forceinline__ int block_scan(int v, int &total, int *wsum)
 
 // List the bricks that hold at least one particle (order is irrelevant: each
 // brick writes only its own particles).  active[0] must be zero on entry.
+// With cell_flags (one byte per cell, set by the call's prologue for every
+// cell that holds a particle with a non-empty list), a brick is listed only if
+// one of its inner cells is flagged: the outputs of particles with empty lists
+// were written by the prologue, so a brick of such particles (a wall away
+// from the fluid) needs no staging.  The flags of the brick's inner cells are
+// cleared for the next call; a stale flag only lists a brick that then finds
+// no pair.
 template <int BX, int BY, int BZ>
 __global__ __launch_bounds__(256) void k_active_bricks(const int32_t *__restrict__ cell_start,
                                                        const int32_t *__restrict__ cell_end, BrickGrid G,
-                                                       int32_t *__restrict__ active)
+                                                       int32_t *__restrict__ active, uint8_t *__restrict__ cell_flags)
 {
     const int b = blockIdx.x * 256 + threadIdx.x;
     const int nb = G.nbx * G.nby * G.nbz;
     int cnt = 0;
+    bool flagged = cell_flags == nullptr;
     if (b < nb) {
         const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
         const int cx1 = min(cx0 + BX, G.nx) - 1;
@@ -245,11 +253,36 @@ __global__ __launch_bounds__(256) void k_active_bricks(const int32_t *__restrict
             e[k] = cell_end[row + cx1];
             s0[k] = cell_start[row + cx0];
         }
+        if (cell_flags) {
+            uint8_t f[BY * BZ][BX];
+#pragma unroll
+            for (int k = 0; k < BY * BZ; ++k) {
+                const int y = min(cy0 + k % BY, G.ny - 1), z = min(cz0 + k / BY, G.nz - 1);
+                const int row = G.nx * (y + G.ny * z);
+#pragma unroll
+                for (int x = 0; x < BX; ++x) f[k][x] = cell_flags[row + min(cx0 + x, cx1)];
+            }
+            int any = 0;
+#pragma unroll
+            for (int k = 0; k < BY * BZ; ++k) {
+                const int y = cy0 + k % BY, z = cz0 + k / BY;
+                const int row = G.nx * (y + G.ny * z);
+#pragma unroll
+                for (int x = 0; x < BX; ++x) {
+                    const bool in = y < G.ny && z < G.nz && cx0 + x <= cx1;
+                    if (in && f[k][x]) {
+                        any = 1;
+                        cell_flags[row + cx0 + x] = 0;
+                    }
+                }
+            }
+            flagged = any != 0;
+        }
 #pragma unroll
         for (int k = 0; k < BY * BZ; ++k)
             cnt += (cy0 + k % BY < G.ny && cz0 + k / BY < G.nz) ? e[k] - s0[k] : 0;
     }
-    const bool has = cnt > 0;
+    const bool has = cnt > 0 && flagged;
     // wave-aggregated append
     const unsigned long long ballot = __ballot(has);
     const int lane = threadIdx.x % kWave;
@@ -259,7 +292,6 @@ __global__ __launch_bounds__(256) void k_active_bricks(const int32_t *__restrict
     base = __shfl(base, 0);
     if (has) active[1 + base + before] = b;
 }
-
 
 // A counter zeroed by a kernel (graph-capturable, no memset node).
 template <typename T>

@@ -180,6 +180,52 @@ def test_model_variants_backward_dam_break(variant):
     _variant_case("dam_break_64k", variant, True)
 
 
+def test_backward_brick_skip_any_workspace_contents():
+    """The adjoint skips the bricks whose particles all have empty lists as the
+    derivative kernel does (its prologue writes their zero adjoint unless the
+    call accumulates): bit-identical results whatever the workspace held,
+    in both modes, on the 64k dam break."""
+    from paper_2207_11328_amd import abi
+    sc = S.dam_break_64k()
+    sim = make_sim(sc, max_neibs=128)
+    sim.build()
+    torch_sync()
+    dev = sim.device
+    assert int((sim.neib_count[: sc.n] == 0).sum()) > 1000
+    g = torch.Generator(device=dev).manual_seed(5)
+    gforce = torch.randn((sim.capacity, 4), device=dev, generator=g)
+    bk = dict(cell_start=sim.cell_start, cell_end=sim.cell_end, neibs_brick=sim.neibs_brick)
+    nbytes = abi.sph_forces_backward_workspace_bytes(sim.capacity, sim.n_cells)
+
+    def run(fill, accumulate, base):
+        ws = torch.full((nbytes,), fill, dtype=torch.uint8, device=dev)
+        gpos = base[0].clone()
+        gvel = base[1].clone()
+        gpar = torch.zeros(3, dtype=torch.float64, device=dev)
+        abi.sph_forces_backward(sim.g, sim.p, sim.parts, sim.neibs, sim.neib_count, sim.max_neibs, gforce, gpos,
+                                gvel, gpar, accumulate, ws, **bk)
+        torch_sync()
+        return gpos, gvel, gpar
+
+    start = (torch.full((sim.capacity, 4), float("nan"), device=dev), torch.full((sim.capacity, 4), float("nan"),
+                                                                                  device=dev))
+    start[0][:, 3] = 3.0
+    ref = run(0, False, start)
+    assert torch.isfinite(ref[0][: sc.n]).all() and torch.isfinite(ref[1][: sc.n]).all()
+    assert (ref[0][: sc.n, 3] == 3.0).all()
+    for fill in (0xFF, 0x01):
+        got = run(fill, False, start)
+        for x, y in zip(ref, got):
+            assert torch.equal(x[: sc.n] if x.dim() == 2 else x, y[: sc.n] if y.dim() == 2 else y), fill
+    acc0 = run(0, True, ref[:2])
+    acc1 = run(0xFF, True, ref[:2])
+    for x, y in zip(acc0, acc1):
+        assert torch.equal(x, y)
+    empty = sim.neib_count[: sc.n] == 0
+    assert torch.equal(acc0[0][: sc.n][empty], ref[0][: sc.n][empty])
+    assert torch.equal(acc0[1][: sc.n][empty], ref[1][: sc.n][empty])
+
+
 def test_integrate_backward_parity():
     sc = S.random_cloud(n=800, box=(0.2, 0.2, 0.2), dp=0.02, seed=53, boundary_frac=0.3, u_sigma=0.2)
     sim = make_sim(sc, max_neibs=192)

@@ -304,6 +304,40 @@ def test_brick_kernel_matches_gather_kernel(name):
     assert float(rel.max(initial=0.0)) <= FORCE_TOL, name
 
 
+def test_brick_skip_any_workspace_contents():
+    """Bricks whose particles all have empty lists (walls away from the fluid)
+    are not staged: the prologue writes those particles' zero derivatives and
+    flags the cells with a pair.  The results do not depend on what the
+    workspace held before the call (flags left by another call, or garbage),
+    and every particle's derivative is written, checked on the 64k dam break
+    (empty-list wall particles) against the oracle and bit for bit across
+    workspace contents and repeated calls."""
+    sc = S.dam_break_64k()
+    sim = make_sim(sc, max_neibs=128)
+    sim.build()
+    torch_sync()
+    cnt = sim.neib_count[: sc.n]
+    n_empty = int((cnt == 0).sum())
+    log("dam_break_64k: %d of %d particles with an empty list" % (n_empty, sc.n))
+    assert n_empty > 1000
+    sim.forces_n.fill_(float("nan"))
+    a = sim.forces(bricks=True).clone()
+    torch_sync()
+    assert torch.isfinite(a[: sc.n]).all()
+    assert (a[: sc.n][cnt == 0] == 0).all()
+    for fill in (0xFF, 0x01, 0x00):
+        sim.ws_forces.fill_(fill)
+        sim.forces_n.fill_(float("nan"))
+        b = sim.forces(bricks=True).clone()
+        c = sim.forces(bricks=True).clone()
+        torch_sync()
+        assert torch.equal(a[: sc.n], b[: sc.n]), fill
+        assert torch.equal(a[: sc.n], c[: sc.n]), fill
+    ob = compare_build(sc, sim, max_neibs=128)
+    st, (acc, drho, sa, sd, ni) = oracle_forces_of(sc, ob)
+    check_forces(a[: sc.n].cpu().numpy(), acc, drho, sa, sd, label="dam_break_64k skip")
+
+
 @pytest.mark.parametrize("shape", [(3, 4, 3), (3, 3, 3), (3, 2, 3)], ids=lambda s: "x".join(map(str, s)))
 @pytest.mark.parametrize("name", ["still_water", "cloud_periodic_xyz", "channel_small"])
 def test_brick_shapes(name, shape):
