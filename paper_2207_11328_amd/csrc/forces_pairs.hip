@@ -375,32 +375,76 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
         central(min(tid / 2, nc - 1), u0, i0);
         const uint32_t cnt0 = tid / 2 < nc ? count[i0] : 0u;
         if (use_lds) {
-            // 2. stage the brick and its halo: one wave per row of SX staged
-            //    cells (x-consecutive, so one contiguous LDS range and, away from
-            //    a periodic seam, one contiguous global range), lanes over the
-            //    row's particles
+            // 2. stage the brick and its halo.  Wave w takes the staged rows w,
+            //    w + NW, ... (a row is SX x-consecutive cells: one contiguous
+            //    LDS range and, away from a periodic seam, one contiguous
+            //    global range); the wave walks its rows as one range in chunks
+            //    of 64 particles, the loads of SB chunks issued before their
+            //    LDS stores so that their latencies overlap
+            constexpr int NW = NT / kWave, NR = SY * SZ, RPW = (NR + NW - 1) / NW, SB = 4;
             const int wave = tid / kWave, lane = tid % kWave;
-            for (int r = wave; r < SY * SZ; r += NT / kWave) {
-                const int t0 = r * SX;
-                const int b0 = cBase[t0], b1 = cBase[t0 + SX];
-                int e[SX - 1];
+            int dlt[RPW], off[RPW + 1], e[RPW][SX - 1];
+            off[0] = 0;
 #pragma unroll
-                for (int c = 0; c < SX - 1; ++c) e[c] = cBase[t0 + 1 + c];
-                const float sy = (float)(r / SZ - 2), sz = (float)(r % SZ - 2);
-                for (int s2 = b0 + lane; s2 < b1; s2 += kWave) {
+            for (int k = 0; k < RPW; ++k) {
+                const int r = wave + k * NW, rr = min(r, NR - 1);
+                const int b0 = cBase[rr * SX];
+                dlt[k] = b0 - off[k];
+                off[k + 1] = off[k] + (r < NR ? cBase[rr * SX + SX] - b0 : 0);
+#pragma unroll
+                for (int m = 0; m < SX - 1; ++m) e[k][m] = cBase[rr * SX + 1 + m];
+            }
+            const int L = off[RPW];
+            for (int tb = 0; tb < L; tb += SB * kWave) {
+                int slot[SB], cc[SB], rw[SB];
+                float4 p[SB], v[SB];
+                float2 x[SB];
+                bool bnd[SB];
+#pragma unroll
+                for (int u = 0; u < SB; ++u) {
+                    const int t = tb + u * kWave + lane;
+                    int k = 0;
+#pragma unroll
+                    for (int m = 1; m < RPW; ++m) k += t >= off[m] ? 1 : 0;
+                    int d = dlt[0], ee[SX - 1];
+#pragma unroll
+                    for (int m = 0; m < SX - 1; ++m) ee[m] = e[0][m];
+#pragma unroll
+                    for (int q = 1; q < RPW; ++q)
+                        if (k == q) {
+                            d = dlt[q];
+#pragma unroll
+                            for (int m = 0; m < SX - 1; ++m) ee[m] = e[q][m];
+                        }
+                    const int s2 = t + d;
                     int c = 0;
 #pragma unroll
-                    for (int k = 0; k < SX - 1; ++k) c += s2 >= e[k] ? 1 : 0;
-                    const int j = s2 - cDelta[t0 + c];
-                    const float4 p = pos[j];
-                    const float sx = (float)(c - 2);
-                    // w = m x kernel coefficient, negated for boundary particles
-                    // when the density diffusion needs the type
-                    const float mf = p.w * C.fcoeff;
-                    sP[s2] = make_float4(fmaf(sx, C.csx, p.x), fmaf(sy, C.csy, p.y), fmaf(sz, C.csz, p.z),
-                                         ((MODEL & kDiffusion) && ptype(info[j]) == kBoundary) ? -mf : mf);
-                    sV[s2] = vel[j];
-                    sA[s2] = aux[j];
+                    for (int m = 0; m < SX - 1; ++m) c += s2 >= ee[m] ? 1 : 0;
+                    const int r = min(wave + k * NW, NR - 1);
+                    slot[u] = t < L ? s2 : -1;
+                    cc[u] = c;
+                    rw[u] = r;
+                    // past the wave's range a lane loads particle 0 (loads stay
+                    // unconditional, so the chunk buffers stay in registers)
+                    const int j = t < L ? s2 - cDelta[r * SX + c] : 0;
+                    p[u] = pos[j];
+                    v[u] = vel[j];
+                    x[u] = aux[j];
+                    bnd[u] = (MODEL & kDiffusion) ? ptype(info[j]) == kBoundary : false;
+                }
+#pragma unroll
+                for (int u = 0; u < SB; ++u) {
+                    if (slot[u] >= 0) {
+                        const float sx = (float)(cc[u] - 2), sy = (float)(rw[u] / SZ - 2),
+                                    sz = (float)(rw[u] % SZ - 2);
+                        // w = m x kernel coefficient, negated for boundary particles
+                        // when the density diffusion needs the type
+                        const float mf = p[u].w * C.fcoeff;
+                        sP[slot[u]] = make_float4(fmaf(sx, C.csx, p[u].x), fmaf(sy, C.csy, p[u].y),
+                                                  fmaf(sz, C.csz, p[u].z), bnd[u] ? -mf : mf);
+                        sV[slot[u]] = v[u];
+                        sA[slot[u]] = x[u];
+                    }
                 }
             }
         }
