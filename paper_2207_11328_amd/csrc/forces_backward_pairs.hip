@@ -478,31 +478,76 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
             const int span = s_hi - s_lo;
             const bool use_lds = span <= CAP;
             if (use_lds && q_hi > q_lo) {
-                // stage the half: one wave per row of SX cells (contiguous in LDS)
+                // stage the half.  Wave w takes the staged rows R0 + w, R0 + w +
+                // NW, ... (SX x-consecutive cells: contiguous in LDS) and walks
+                // them as one range in chunks of 64 particles, the loads of SB
+                // chunks issued before their LDS stores so that their
+                // latencies overlap; lanes past the range load particle 0
+                constexpr int NW = NT / kWave, RPW = ((BY - HALF + 2) * SZ + NW - 1) / NW, SB = 4;
                 const int wave = tid / kWave, lane = tid % kWave;
-                for (int r = y0 * SZ + wave; r < (y1 + 2) * SZ; r += NT / kWave) {
-                    const int t0 = r * SX;
-                    const int b0 = cBase[t0], b1 = cBase[t0 + SX];
-                    int e[SX - 1];
+                const int R0 = y0 * SZ, R1 = (y1 + 2) * SZ;
+                int dlt[RPW], off[RPW + 1], e[RPW][SX - 1];
+                off[0] = 0;
 #pragma unroll
-                    for (int c = 0; c < SX - 1; ++c) e[c] = cBase[t0 + 1 + c];
-                    const float sy = (float)(r / SZ - 2), sz = (float)(r % SZ - 2);
-                    for (int s2 = b0 + lane; s2 < b1; s2 += kWave) {
+                for (int k = 0; k < RPW; ++k) {
+                    const int r = R0 + wave + k * NW, rr = min(r, R1 - 1);
+                    const int b0 = cBase[rr * SX];
+                    dlt[k] = b0 - off[k];
+                    off[k + 1] = off[k] + (r < R1 ? cBase[rr * SX + SX] - b0 : 0);
+#pragma unroll
+                    for (int m = 0; m < SX - 1; ++m) e[k][m] = cBase[rr * SX + 1 + m];
+                }
+                const int L = off[RPW];
+                const float2 *aux2 = (const float2 *)aux;
+                for (int tb = 0; tb < L; tb += SB * kWave) {
+                    int slot[SB], cc[SB], rw[SB];
+                    float4 p[SB], v[SB], g[SB];
+                    float2 x[SB];
+                    bool bnd[SB];
+#pragma unroll
+                    for (int u = 0; u < SB; ++u) {
+                        const int t = tb + u * kWave + lane;
+                        int k = 0;
+#pragma unroll
+                        for (int m = 1; m < RPW; ++m) k += t >= off[m] ? 1 : 0;
+                        int d = dlt[0], ee[SX - 1];
+#pragma unroll
+                        for (int m = 0; m < SX - 1; ++m) ee[m] = e[0][m];
+#pragma unroll
+                        for (int q = 1; q < RPW; ++q)
+                            if (k == q) {
+                                d = dlt[q];
+#pragma unroll
+                                for (int m = 0; m < SX - 1; ++m) ee[m] = e[q][m];
+                            }
+                        const int s2 = t + d;
                         int c = 0;
 #pragma unroll
-                        for (int kk = 0; kk < SX - 1; ++kk) c += s2 >= e[kk] ? 1 : 0;
-                        const int j = s2 - cDelta[t0 + c];
-                        const float4 p = pos[j];
-                        const float sx = (float)(c - 2);
-                        const float4 a4 = aux[j];
-                        const int l = s2 - s_lo;
+                        for (int m = 0; m < SX - 1; ++m) c += s2 >= ee[m] ? 1 : 0;
+                        const int r = min(R0 + wave + k * NW, R1 - 1);
+                        slot[u] = t < L ? s2 : -1;
+                        cc[u] = c;
+                        rw[u] = r;
+                        const int j = t < L ? s2 - cDelta[r * SX + c] : 0;
+                        p[u] = pos[j];
+                        v[u] = vel[j];
+                        x[u] = aux2[2 * (size_t)j];
+                        g[u] = gforce[j];
                         // mass negated for boundary particles when the diffusion needs the type
-                        const bool bnd = (MODEL & kDiffusion) && ptype(info[j]) == kBoundary;
-                        sP[l] = make_float4(fmaf(sx, C.csx, p.x), fmaf(sy, C.csy, p.y), fmaf(sz, C.csz, p.z),
-                                            bnd ? -p.w : p.w);
-                        sV[l] = vel[j];
-                        sX[l] = make_float2(a4.x, a4.y);
-                        sG[l] = gforce[j];
+                        bnd[u] = (MODEL & kDiffusion) ? ptype(info[j]) == kBoundary : false;
+                    }
+#pragma unroll
+                    for (int u = 0; u < SB; ++u) {
+                        if (slot[u] >= 0) {
+                            const float sx = (float)(cc[u] - 2), sy = (float)(rw[u] / SZ - 2),
+                                        sz = (float)(rw[u] % SZ - 2);
+                            const int l = slot[u] - s_lo;
+                            sP[l] = make_float4(fmaf(sx, C.csx, p[u].x), fmaf(sy, C.csy, p[u].y),
+                                                fmaf(sz, C.csz, p[u].z), bnd[u] ? -p[u].w : p[u].w);
+                            sV[l] = v[u];
+                            sX[l] = x[u];
+                            sG[l] = g[u];
+                        }
                     }
                 }
             }
