@@ -36,12 +36,13 @@ __global__ __launch_bounds__(kThreads) void k_eos(int n, const float4 *__restric
                                                   ForceConst C, int32_t *__restrict__ active,
                                                   int32_t *__restrict__ next, float4 *__restrict__ out,
                                                   const uint32_t *__restrict__ count, uint8_t *__restrict__ cell_flags,
-                                                  int n_cells)
+                                                  int n_cells, int32_t *__restrict__ light)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (active && i == 0) {
         active[0] = 0;
         next[0] = 0;
+        light[0] = 0;
     }
     if (i >= n) return;
     float alpha_h = C.alpha_h;
@@ -147,9 +148,10 @@ size_t aux_bytes(int64_t capacity) { return (size_t)((sizeof(float2) * capacity 
 extern "C" size_t sph_forces_workspace_bytes(int32_t capacity, int32_t n_cells)
 {
     if (capacity < 0 || n_cells < 0) return 0;
-    // per-particle EOS terms, then the active-brick list (at most one brick per
-    // cell), the brick counter and one flag byte per cell
-    return aux_bytes(capacity > 0 ? capacity : 1) + sizeof(int32_t) * ((size_t)n_cells + 2) +
+    // per-particle EOS terms, then the active-brick list (the heavy count, ids
+    // of at most one brick per cell, the brick counter, the light count) and
+    // one flag byte per cell
+    return aux_bytes(capacity > 0 ? capacity : 1) + sizeof(int32_t) * ((size_t)n_cells + 3) +
            (((size_t)n_cells + 255) & ~(size_t)255) + 256;
 }
 
@@ -181,11 +183,11 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
     const bool bricks = cell_start && cell_end && neibs_brick;
     if (bricks && !parts->cell) return SPH_ERR_ARG;
     if ((params->delta != 0.0f) && !parts->info) return SPH_ERR_ARG;
-    uint8_t *cell_flags = (uint8_t *)(active + n_cells + 2);
+    uint8_t *cell_flags = (uint8_t *)(active + n_cells + 3);
     k_eos<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, vel, aux, parts->cell, grid->cell_alpha, grid->cell_base,
                                                        params->h, C, bricks ? active : nullptr,
                                                        active + n_cells + 1, bricks ? out : nullptr, neib_count,
-                                                       cell_flags, (int)n_cells);
+                                                       cell_flags, (int)n_cells, active + n_cells + 2);
     ForceArgs a;
     a.grid = grid;
     a.shape = shape;
@@ -201,6 +203,7 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
     a.cell_end = cell_end;
     a.active = active;
     a.next = active + n_cells + 1;
+    a.light = active + n_cells + 2;
     a.cell_flags = cell_flags;
     a.out = out;
     a.bricks = bricks;

@@ -106,7 +106,7 @@ size_t partial_bytes(int64_t cap) { return (size_t)(3 * 8 * ((cap + kThreads - 1
 // list and one flag byte per cell
 size_t brick_bytes(int64_t n_cells)
 {
-    return (size_t)(3 * 8 * (n_cells + 1) + 4 * (n_cells + 2) + ((n_cells + 255) & ~(int64_t)255) + 256);
+    return (size_t)(3 * 8 * (n_cells + 1) + 4 * (n_cells + 3) + ((n_cells + 255) & ~(int64_t)255) + 256);
 }
 
 }  // namespace
@@ -179,7 +179,7 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
     const int model = model_of(p);
     int n_partials = 0;
     if (n > 0) {
-        uint8_t *cell_flags = (uint8_t *)(active + n_cells + 2);
+        uint8_t *cell_flags = (uint8_t *)(active + n_cells + 3);
         k_eos_grad<<<nblocks, kThreads, 0, s>>>(n, (const float4 *)parts->vel, aux, C, parts->cell,
                                                 grid->cell_base, neib_count, bricks ? cell_flags : nullptr,
                                                 (int)n_cells, bricks && !accumulate ? (float4 *)grad_pos : nullptr,
@@ -200,6 +200,7 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
         a.cell_end = cell_end;
         a.active = active;
         a.next = active + n_cells + 1;
+        a.light = active + n_cells + 2;
         a.cell_flags = cell_flags;
         a.gpos = (float4 *)grad_pos;
         a.gvel = (float4 *)grad_vel;

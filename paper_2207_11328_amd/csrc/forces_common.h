@@ -33,6 +33,7 @@ struct ForceArgs {
     const int32_t *cell_start, *cell_end;
     int32_t *active;  // bricks holding particles: count, then ids
     int32_t *next;    // brick counter of the persistent workgroups
+    int32_t *light;   // count of the light bricks, listed from the back of active
     uint8_t *cell_flags;  // cells holding a particle with a non-empty list (set by the prologue)
     float4 *out;
     bool bricks;

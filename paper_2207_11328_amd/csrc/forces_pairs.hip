@@ -278,6 +278,7 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
                                                      const int32_t *__restrict__ cell_end,
                                                      const int32_t *__restrict__ active,
                                                      int32_t *__restrict__ next,
+                                                     const int32_t *__restrict__ light,
                                                      const uint32_t *__restrict__ info,
                                                      float4 *__restrict__ out, ForceConst C, BrickGrid G)
 {
@@ -296,10 +297,11 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     __shared__ int wsum[NT / kWave];
     __shared__ int sNext;
 
-    // One resident workgroup per CU takes the bricks that hold particles
-    // (active[0] of them, ids in active[1..]) one at a time from the counter
-    // `next`: no workgroup is launched for an empty brick, and the bricks'
-    // different costs even out across CUs.
+    // One resident workgroup per CU takes the bricks with a pair one at a time
+    // from the counter `next`, heavy ones first (brick_at order): no workgroup
+    // is launched for an empty brick, the bricks' different costs even out
+    // across CUs, and the cheap bricks come last, where they fill the gaps.
+    const int n_listed = bricks_listed(active, light), cap_ids = G.nx * G.ny * G.nz;
     for (;;) {
         // the thread index is re-read per brick (an empty asm hides that it is
         // the same), so nothing derived from it is kept live across the pair loop
@@ -308,8 +310,8 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
         if (tid == 0) sNext = atomicAdd(next, 1);
         __syncthreads();
         const int kb = sNext;
-        if (kb >= active[0]) break;  // uniform
-        const int b = active[1 + kb];
+        if (kb >= n_listed) break;  // uniform
+        const int b = brick_at(active, cap_ids, kb);
         const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
 
         // 1. ranges of the staged cells and their LDS bases (the staging order of
@@ -509,13 +511,15 @@ void launch_brick(const ForceArgs &a, const ForceConst &C, hipStream_t s)
         const BrickGrid G = brick_grid<BX, BY, BZ>(a.grid->ncell, a.grid->periodic);
         const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
         constexpr int NT = brick_threads(BX * BY * BZ);
-        // (active[0] and the brick counter were zeroed by the equation-of-state prologue)
-        k_active_bricks<BX, BY, BZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(a.cell_start, a.cell_end, G, a.active,
-                                                                             a.cell_flags);
+        // (active[0], the brick counter and the light count were zeroed by the
+        // equation-of-state prologue; a brick with fewer than 12 particles per
+        // inner cell is light)
+        k_active_bricks<BX, BY, BZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(
+            a.cell_start, a.cell_end, G, a.active, a.cell_flags, a.light, 12 * BX * BY * BZ, G.nx * G.ny * G.nz);
         const unsigned wgs = blocks < (unsigned)sph_device_cus() ? blocks : (unsigned)sph_device_cus();
         k_forces_brick<MODEL, BX, BY, BZ, NT, brick_cap(BX, BY, BZ)><<<wgs, NT, 0, s>>>(
             a.n, a.pos, a.vel, a.aux, a.neibs, a.neibs_brick, a.count, a.cell_start, a.cell_end, a.active,
-            a.next, a.info, a.out, C, G);
+            a.next, a.light, a.info, a.out, C, G);
     });
 }
 

@@ -231,10 +231,16 @@ __device__ __forceinline__ int block_scan(int v, int &total, int *wsum)
 // from the fluid) needs no staging.  The flags of the brick's inner cells are
 // cleared for the next call; a stale flag only lists a brick that then finds
 // no pair.
+// With light (a second counter, zero on entry), bricks with fewer than
+// light_min particles are listed from the back of the id region instead
+// (active[cap_ids], active[cap_ids - 1], ...; light[0] of them), so that a
+// consumer taking the bricks in brick_at order ends with the cheap ones.
 template <int BX, int BY, int BZ>
 __global__ __launch_bounds__(256) void k_active_bricks(const int32_t *__restrict__ cell_start,
                                                        const int32_t *__restrict__ cell_end, BrickGrid G,
-                                                       int32_t *__restrict__ active, uint8_t *__restrict__ cell_flags)
+                                                       int32_t *__restrict__ active, uint8_t *__restrict__ cell_flags,
+                                                       int32_t *__restrict__ light = nullptr, int light_min = 0,
+                                                       int cap_ids = 0)
 {
     const int b = blockIdx.x * 256 + threadIdx.x;
     const int nb = G.nbx * G.nby * G.nbz;
@@ -283,14 +289,30 @@ __global__ __launch_bounds__(256) void k_active_bricks(const int32_t *__restrict
             cnt += (cy0 + k % BY < G.ny && cz0 + k / BY < G.nz) ? e[k] - s0[k] : 0;
     }
     const bool has = cnt > 0 && flagged;
-    // wave-aggregated append
-    const unsigned long long ballot = __ballot(has);
+    const bool lt = has && light && cnt < light_min;
+    // wave-aggregated appends
+    const unsigned long long ballot = __ballot(has && !lt), lballot = __ballot(lt);
     const int lane = threadIdx.x % kWave;
-    const int before = __popcll(ballot & ((1ull << lane) - 1ull));
-    int base = 0;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int base = 0, lbase = 0;
     if (lane == 0 && ballot) base = atomicAdd(&active[0], (int)__popcll(ballot));
+    if (lane == 0 && lballot) lbase = atomicAdd(light, (int)__popcll(lballot));
     base = __shfl(base, 0);
-    if (has) active[1 + base + before] = b;
+    lbase = __shfl(lbase, 0);
+    if (has && !lt) active[1 + base + __popcll(ballot & below)] = b;
+    if (lt) active[cap_ids - (lbase + __popcll(lballot & below))] = b;
+}
+
+// Bricks listed by k_active_bricks: their number, and the kb-th in the order
+// heavy (from the front) then light (from the back).
+__device__ __forceinline__ int bricks_listed(const int32_t *active, const int32_t *light)
+{
+    return active[0] + light[0];
+}
+__device__ __forceinline__ int brick_at(const int32_t *active, int cap_ids, int kb)
+{
+    const int nh = active[0];
+    return kb < nh ? active[1 + kb] : active[cap_ids - (kb - nh)];
 }
 
 // A counter zeroed by a kernel (graph-capturable, no memset node).
