@@ -57,6 +57,31 @@ __global__ void k_fill(int32_t *__restrict__ p, int64_t n, int32_t v)
         p[i] = v;
 }
 
+// atomicAdd(&cnt[key], 1) for every valid lane of a wave, combined over runs
+// of consecutive lanes with the same key (particles come in the order of the
+// last build, sorted by cell, so a run is typically a whole cell's part of
+// the wave): one atomic per run.  Returns the value the lane's own atomic
+// could have returned (the run's base plus the lane's rank in the run).
+// Every lane of the wave must call it.
+__device__ __forceinline__ int run_atomic_inc(int32_t *cnt, int key, bool valid)
+{
+    const int lane = threadIdx.x % kWave;
+    const int prev = __shfl(key, lane > 0 ? lane - 1 : 0);
+    const unsigned long long vmask = __ballot(valid);
+    const bool prev_valid = lane > 0 && ((vmask >> (lane - 1)) & 1ull);
+    const bool first = valid && (!prev_valid || prev != key);
+    // run boundaries: run starts and invalid lanes
+    const unsigned long long bounds = __ballot(first) | ~vmask;
+    const unsigned long long upto = bounds & (~0ull >> (kWave - 1 - lane));  // bits <= lane
+    const int rs = kWave - 1 - __clzll(upto | 1ull);
+    const unsigned long long above = lane == kWave - 1 ? 0ull : bounds & (~0ull << (lane + 1));
+    const int re = above ? __ffsll((long long)above) - 1 : kWave;
+    int base = 0;
+    if (first) base = atomicAdd(&cnt[key], re - rs);
+    base = __shfl(base, rs);
+    return base + (lane - rs);
+}
+
 // Re-bin offsets into [-cs/2, cs/2) (float32, at most 4 cells per axis) and
 // count particles per cell.  Particles that leave a non-periodic axis, or
 // whose offsets are not finite, become dropped (cell = -1, last bucket).
@@ -65,10 +90,10 @@ __global__ __launch_bounds__(kThreads) void k_rebin_count(
     float csz, int cell_base, int n_cells, int32_t *__restrict__ cnt)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
-    int c = cell[i];
+    const bool valid = i < n;
+    int c = valid ? cell[i] : -1;
     int bucket = n_cells;
-    if (c >= 0) {
+    if (valid && c >= 0) {
         int cc[3];
         cell_coords(c - cell_base, dims, cc[0], cc[1], cc[2]);
         float4 p = pos[i];
@@ -103,7 +128,7 @@ __global__ __launch_bounds__(kThreads) void k_rebin_count(
             cell[i] = -1;
         }
     }
-    atomicAdd(&cnt[bucket], 1);
+    run_atomic_inc(cnt, bucket, valid);
 }
 
 // ---- exclusive scan of cnt[0..m) into start[0..m], start[m] = total --------
@@ -189,11 +214,11 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int n, const int32_t *__re
                                                       uint32_t *__restrict__ perm)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i >= n) return;
-    const int c = cell[i];
+    const bool valid = i < n;
+    const int c = valid ? cell[i] : -1;
     const int b = c >= 0 ? c - cell_base : n_cells;
-    const int slot = start[b] + atomicAdd(&cursor[b], 1);
-    perm[slot] = (uint32_t)i;
+    const int r = run_atomic_inc(cursor, b, valid);
+    if (valid) perm[start[b] + r] = (uint32_t)i;
 }
 
 // One wave per bucket: rank each particle of the bucket by its info word
