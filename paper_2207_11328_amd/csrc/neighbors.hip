@@ -340,7 +340,11 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
                                                const uint32_t *__restrict__ ginfo, float csx, float csy, float csz,
                                                float rs2, uint32_t *tile, uint16_t *ltile, int &total_found)
 {
-    int nf = 0, nb = 0, wf = 0, wb = 0;
+    // Each neighbour cell is scanned in chunks of up to 64 candidates in two
+    // phases: the predicate alone, one bit per hit in a 64-bit mask, then the
+    // hits in slot order, written as before.  Only about one candidate in six
+    // is a hit, so the writing work runs per hit instead of per candidate.
+    int found = 0, wf = 0, wb = 0;
     for (int dz = -1; dz <= 1; ++dz) {
         const float t2z = cell_shift(-dz, csz);
         for (int dy = -1; dy <= 1; ++dy) {
@@ -352,42 +356,42 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
                 const int s1 = central_boundary ? cFluidEnd[t] : cBase[t + 1];
                 const int delta = cDelta[t];
                 const uint32_t code = pack_neib(0u, -dx, -dy, -dz);
-                // two candidates in flight per lane (the LDS read latency)
+                for (int c0 = s0; c0 < s1; c0 += 64) {
+                    const int m = min(s1 - c0, 64);
+                    uint64_t hits = 0;
+                    // two candidates in flight per lane (the LDS read latency)
 #pragma unroll 2
-                for (int sl = s0; sl < s1; ++sl) {
-                    const int j = sl - delta;
-                    float4 pj;
-                    uint32_t inf;
-                    if (LDS) {
-                        pj = sPos[sl];
-                        inf = __float_as_uint(pj.w);
-                    } else {
-                        pj = gpos[j];
-                        inf = ginfo[j];
+                    for (int k = 0; k < m; ++k) {
+                        const int sl = c0 + k;
+                        const float4 pj = LDS ? sPos[sl] : gpos[sl - delta];
+                        const float r2 = predicate_r2(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, t2x, t2y, t2z);
+                        const bool hit = (r2 < rs2) & (sl - delta != i);
+                        hits |= (uint64_t)hit << k;
                     }
-                    const bool nb_boundary = ptype(inf) == kBoundary;
-                    const float r2 = predicate_r2(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, t2x, t2y, t2z);
-                    const bool hit = (r2 < rs2) & (j != i);
-                    const bool keep = hit & (wf + wb < M);
-                    const int slot = nb_boundary ? M - 1 - wb : wf;
-                    if (keep) {
-                        tile[slot * kWave] = (uint32_t)j | code;
-                        if (ltile) {
-                            const int p = wf + wb;
-                            ltile[(p / kBrickGroup) * (kWave * kBrickGroup) + p % kBrickGroup] =
-                                (uint16_t)min(sl, 0xFFFF);
+                    found += __popcll(hits);
+                    while (hits) {
+                        const int k = __ffsll((long long)hits) - 1;
+                        hits &= hits - 1;
+                        if (wf + wb < M) {
+                            const int sl = c0 + k;
+                            const int j = sl - delta;
+                            const uint32_t inf = LDS ? __float_as_uint(sPos[sl].w) : ginfo[j];
+                            const bool nb_boundary = ptype(inf) == kBoundary;
+                            tile[(nb_boundary ? M - 1 - wb : wf) * kWave] = (uint32_t)j | code;
+                            if (ltile) {
+                                const int p = wf + wb;
+                                ltile[(p / kBrickGroup) * (kWave * kBrickGroup) + p % kBrickGroup] =
+                                    (uint16_t)min(sl, 0xFFFF);
+                            }
+                            wb += nb_boundary ? 1 : 0;
+                            wf += nb_boundary ? 0 : 1;
                         }
                     }
-                    const int kb = (int)(keep & nb_boundary), hb = (int)(hit & nb_boundary);
-                    wb += kb;
-                    wf += (int)keep - kb;
-                    nb += hb;
-                    nf += (int)hit - hb;
                 }
             }
         }
     }
-    total_found = nf + nb;
+    total_found = found;
     return (uint32_t)wf | (uint32_t)wb << 16;
 }
 
