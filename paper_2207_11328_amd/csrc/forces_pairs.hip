@@ -296,6 +296,7 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     __shared__ int iStart[NI];
     __shared__ int wsum[NT / kWave];
     __shared__ int sNext;
+    __shared__ int sGroup;  // groups of centrals claimed in the brick, past the first NT / kWave
 
     // One resident workgroup per CU takes the bricks with a pair one at a time
     // from the counter `next`, heavy ones first (brick_at order): no workgroup
@@ -368,9 +369,9 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
         // two lanes per central particle (lanes 2q', 2q' + 1): a brick holds
         // fewer centrals than the workgroup has lanes (about 840 at lattice
         // density), and half lists spread the work over all 16 waves
-        constexpr int QP = NT / 2;  // centrals per pass
         const int h = tid & 1;
-        // the list count of the first pass is requested before the staging loads
+        if (tid == 0) sGroup = 0;  // read after the staging barrier
+        // the list count of each wave's first group is requested before the staging loads
         // so the two latencies overlap (consecutive centrals stay on consecutive
         // lanes: their list groups are contiguous, one coalesced load per wave)
         int u0, i0;
@@ -452,15 +453,21 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
         }
         __syncthreads();
 
-        // 3. two lanes per central particle of the brick
+        // 3. two lanes per central particle of the brick, a wave taking
+        //    kWave / 2 consecutive centrals at a time: wave w takes group w
+        //    first (its counts were requested before the staging), then claims
+        //    the next unclaimed group as it finishes one, so that waves that
+        //    drew cheap groups (short lists) take more of the brick
         const int M = C.max_neibs;
         const uint32_t jmax = (uint32_t)(n - 1);
-        for (int q0 = 0; q0 < nc; q0 += QP) {
-            const int q = q0 + tid / 2;
+        constexpr int NW = NT / kWave, QG = kWave / 2;
+        int g = tid / kWave;
+        for (bool first = true; g * QG < nc; first = false) {  // wave-uniform
+            const int q = g * QG + (tid % kWave) / 2;
             const bool act = q < nc;
             int u = u0, i = i0;
             uint32_t cntw = cnt0;
-            if (q0 > 0) {
+            if (!first) {
                 central(act ? q : nc - 1, u, i);
                 cntw = act ? count[i] : 0u;
             }
@@ -490,6 +497,9 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
             }
             // (a particle with an empty list was written by the prologue)
             if (act && h == 0 && nt > 0) out[i] = make_float4(A.ax, A.ay, A.az, A.dr);
+            int gn = 0;
+            if (tid % kWave == 0) gn = atomicAdd(&sGroup, 1) + NW;
+            g = __builtin_amdgcn_readfirstlane(__shfl(gn, 0));
         }
         __syncthreads();  // the next brick reuses the LDS
     }
