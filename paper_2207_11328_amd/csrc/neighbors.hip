@@ -344,7 +344,12 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
     // phases: the predicate alone, one bit per hit in a 64-bit mask, then the
     // hits in slot order, written as before.  Only about one candidate in six
     // is a hit, so the writing work runs per hit instead of per candidate.
-    int found = 0, wf = 0, wb = 0;
+    int found = 0, w = 0;
+    // write positions: the next fluid slot from the front, the next boundary
+    // slot from the back, the next brick-local entry (groups of 8 contiguous
+    // entries, kWave x 8 entries apart)
+    uint32_t *tf = tile, *tb = tile + (size_t)(M - 1) * kWave;
+    uint16_t *lp = ltile;
     for (int dz = -1; dz <= 1; ++dz) {
         const float t2z = cell_shift(-dz, csz);
         for (int dy = -1; dy <= 1; ++dy) {
@@ -372,25 +377,26 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
                     while (hits) {
                         const int k = __ffsll((long long)hits) - 1;
                         hits &= hits - 1;
-                        if (wf + wb < M) {
+                        if (w < M) {
                             const int sl = c0 + k;
                             const int j = sl - delta;
                             const uint32_t inf = LDS ? __float_as_uint(sPos[sl].w) : ginfo[j];
                             const bool nb_boundary = ptype(inf) == kBoundary;
-                            tile[(nb_boundary ? M - 1 - wb : wf) * kWave] = (uint32_t)j | code;
+                            *(nb_boundary ? tb : tf) = (uint32_t)j | code;
+                            tf += nb_boundary ? 0 : kWave;
+                            tb -= nb_boundary ? kWave : 0;
                             if (ltile) {
-                                const int p = wf + wb;
-                                ltile[(p / kBrickGroup) * (kWave * kBrickGroup) + p % kBrickGroup] =
-                                    (uint16_t)min(sl, 0xFFFF);
+                                *lp = (uint16_t)min(sl, 0xFFFF);
+                                lp += (w & (kBrickGroup - 1)) == kBrickGroup - 1 ? kWave * kBrickGroup - (kBrickGroup - 1) : 1;
                             }
-                            wb += nb_boundary ? 1 : 0;
-                            wf += nb_boundary ? 0 : 1;
+                            ++w;
                         }
                     }
                 }
             }
         }
     }
+    const int wf = (int)((tf - tile) / kWave), wb = w - wf;
     total_found = found;
     return (uint32_t)wf | (uint32_t)wb << 16;
 }
