@@ -222,7 +222,8 @@ size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells);
  *      adjoint of the rebuild is dL/dy_before[perm_out[k]] = dL/dy_after[k]
  *      (sph_unpermute), since re-binning does not move a particle;
  *   7. if neibs_brick (device uint16[sph_neib_brick_entries(capacity,
- *      max_neibs)]) is not NULL, the same lists in brick-local form for
+ *      max_neibs)], 16-byte aligned: it is written and read in 16-byte
+ *      groups; SPH_ERR_ARG otherwise) is not NULL, the same lists in brick-local form for
  *      sph_forces: entry k of particle i (k < nf + nb, neighbours in scan
  *      order, fluid and boundary interleaved as found) is stored at
  *        ((i / 64) * G + k / 8) * 512 + (i % 64) * 8 + k % 8,

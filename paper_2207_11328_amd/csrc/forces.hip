@@ -182,6 +182,7 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
     if (grid->cell_alpha && !parts->cell) return SPH_ERR_ARG;
     const bool bricks = cell_start && cell_end && neibs_brick;
     if (bricks && !parts->cell) return SPH_ERR_ARG;
+    if (bricks && ((uintptr_t)neibs_brick & 15u)) return SPH_ERR_ARG;  // read in 16-byte groups
     if ((params->delta != 0.0f) && !parts->info) return SPH_ERR_ARG;
     uint8_t *cell_flags = (uint8_t *)(active + n_cells + 3);
     k_eos<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, vel, aux, parts->cell, grid->cell_alpha, grid->cell_base,

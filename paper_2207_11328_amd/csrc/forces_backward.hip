@@ -141,6 +141,7 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
     const int shape = brick_shape_index(grid->brick);
     if (shape < 0) return SPH_ERR_ARG;
     if (bricks && parts->n > 0 && !parts->cell) return SPH_ERR_ARG;
+    if (bricks && ((uintptr_t)neibs_brick & 15u)) return SPH_ERR_ARG;  // read in 16-byte groups
     if (!workspace || workspace_bytes < sph_forces_backward_workspace_bytes(parts->capacity, (int32_t)n_cells))
         return SPH_ERR_WORKSPACE;
     BackConst C;

@@ -346,10 +346,12 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
     // is a hit, so the writing work runs per hit instead of per candidate.
     int found = 0, w = 0;
     // write positions: the next fluid slot from the front, the next boundary
-    // slot from the back, the next brick-local entry (groups of 8 contiguous
-    // entries, kWave x 8 entries apart)
+    // slot from the back; the brick-local entries of the current group of 8
+    // are collected in registers and stored as one 16-byte group when it is
+    // full (groups are kWave x 8 entries apart), the last one at the end
     uint32_t *tf = tile, *tb = tile + (size_t)(M - 1) * kWave;
-    uint16_t *lp = ltile;
+    uint4 *lg = (uint4 *)ltile;
+    uint4 grp = make_uint4(0u, 0u, 0u, 0u);
     for (int dz = -1; dz <= 1; ++dz) {
         const float t2z = cell_shift(-dz, csz);
         for (int dy = -1; dy <= 1; ++dy) {
@@ -386,8 +388,16 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
                             tf += nb_boundary ? 0 : kWave;
                             tb -= nb_boundary ? kWave : 0;
                             if (ltile) {
-                                *lp = (uint16_t)min(sl, 0xFFFF);
-                                lp += (w & (kBrickGroup - 1)) == kBrickGroup - 1 ? kWave * kBrickGroup - (kBrickGroup - 1) : 1;
+                                const int e = w & (kBrickGroup - 1);
+                                const uint32_t v = (uint32_t)min(sl, 0xFFFF) << ((e & 1) * 16);
+                                grp.x |= (e >> 1) == 0 ? v : 0u;
+                                grp.y |= (e >> 1) == 1 ? v : 0u;
+                                grp.z |= (e >> 1) == 2 ? v : 0u;
+                                grp.w |= (e >> 1) == 3 ? v : 0u;
+                                if (e == kBrickGroup - 1) {
+                                    lg[(size_t)(w / kBrickGroup) * kWave] = grp;
+                                    grp = make_uint4(0u, 0u, 0u, 0u);
+                                }
                             }
                             ++w;
                         }
@@ -396,13 +406,14 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
             }
         }
     }
+    if (ltile && (w & (kBrickGroup - 1)) != 0) lg[(size_t)(w / kBrickGroup) * kWave] = grp;
     const int wf = (int)((tf - tile) / kWave), wb = w - wf;
     total_found = found;
     return (uint32_t)wf | (uint32_t)wb << 16;
 }
 
 template <int BX, int BY, int BZ, int NT, int CAP>
-__global__ __launch_bounds__(NT) void k_build_brick(int n, int max_neibs, const float4 *__restrict__ pos,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) void k_build_brick(int n, int max_neibs, const float4 *__restrict__ pos,
                                                     const uint32_t *__restrict__ info,
                                                     const int32_t *__restrict__ start, BrickGrid G, float csx,
                                                     float csy, float csz, float rs2,
@@ -582,6 +593,7 @@ extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params
     if (parts->n < 0 || parts->capacity < parts->n || parts->capacity > SPH_MAX_CAPACITY) return SPH_ERR_ARG;
     if (parts->capacity > 0 && (!parts->cell || !parts->pos || !parts->vel || !parts->info)) return SPH_ERR_ARG;
     if (max_neibs < 1 || max_neibs > 65535) return SPH_ERR_ARG;
+    if (neibs_brick && ((uintptr_t)neibs_brick & 15u)) return SPH_ERR_ARG;  // written in 16-byte groups
     if (!(params->r_search > 0.0f) || !grid_ok(grid, params->r_search)) return SPH_ERR_ARG;
     const int shape = brick_shape_index(grid->brick);
     if (shape < 0) return SPH_ERR_ARG;

@@ -137,6 +137,35 @@ def test_unknown_model_switches_are_rejected(abi):
         assert both(params(**bad)) == (abi.SPH_ERR_ARG, abi.SPH_ERR_ARG), bad
 
 
+def test_misaligned_brick_lists_are_rejected(abi):
+    """The brick-local lists are written and read in 16-byte groups: a
+    neibs_brick pointer that is not 16-byte aligned is an argument error of
+    the build, the derivatives and the adjoint, returned before any launch
+    (the device pointers below are placeholders that are never dereferenced)."""
+    g = abi.SphGrid()
+    for d in range(3):
+        g.cell_size[d] = 0.06
+        g.ncell[d] = 4
+    g.brick[:] = abi.sph_brick_shapes()[0]
+    p = abi.SphParams()
+    p.h, p.r_search, p.rho0, p.gamma, p.c0 = 0.026, 0.06, 1000.0, 7.0, 20.0
+    dev = C.c_void_p(0x100000)
+    parts = abi.SphParticles(1, 1, dev, dev, dev, dev)
+    gp = C.c_void_p(0x100000)
+    big = C.c_size_t(1 << 40)
+    # the same build call with no brick lists gets as far as the workspace check
+    assert abi.lib.sph_build_neighbors(C.byref(g), C.byref(p), C.byref(parts), dev, dev, 128, dev, dev, dev,
+                                       None, None, dev, C.c_size_t(0), None) == abi.SPH_ERR_WORKSPACE
+    for nb in (0x100002, 0x100008):
+        nbp = C.c_void_p(nb)
+        assert abi.lib.sph_build_neighbors(C.byref(g), C.byref(p), C.byref(parts), dev, dev, 128, dev, dev, dev,
+                                           None, nbp, dev, big, None) == abi.SPH_ERR_ARG
+        assert abi.lib.sph_forces(C.byref(g), C.byref(p), C.byref(parts), dev, dev, 128, dev, dev, nbp, dev, dev,
+                                  big, None) == abi.SPH_ERR_ARG
+        assert abi.lib.sph_forces_backward(C.byref(g), C.byref(p), C.byref(parts), dev, dev, 128, dev, dev, nbp,
+                                           dev, dev, dev, gp, 0, dev, big, None) == abi.SPH_ERR_ARG
+
+
 def test_weak_compressibility_check():
     """c0 >= 10 U with U the free-fall speed of the water height: the dam
     break's c0 = 20 m/s is below 10 sqrt(2 g 0.3) = 24.3 m/s (expected density
