@@ -290,36 +290,31 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     __shared__ float4 sP[CAP];  // brick-relative offset, mass x kernel coefficient
     __shared__ float4 sV[CAP];
     __shared__ float2 sA[CAP];
-    __shared__ int cBase[S + 1];
-    __shared__ int cDelta[S];
-    __shared__ int iBase[NI + 1];
-    __shared__ int iStart[NI];
+    // cell scans of the brick (two buffers: the next brick's are computed
+    // ahead into the other one, see below)
+    __shared__ int cBaseB[2][S + 1];
+    __shared__ int cDeltaB[2][S];
+    __shared__ int iBaseB[2][NI + 1];
+    __shared__ int iStartB[2][NI];
     __shared__ int wsum[NT / kWave];
     __shared__ int sNext;
     __shared__ int sGroup;  // groups of centrals claimed in the brick, past the first NT / kWave
+    __shared__ int sPre[4]; // scan ahead: claimed, next brick's list index, total, centrals
+    static_assert(NI <= kWave, "one lane per inner cell in the scan ahead");
 
     // One resident workgroup per CU takes the bricks with a pair one at a time
     // from the counter `next`, heavy ones first (brick_at order): no workgroup
     // is launched for an empty brick, the bricks' different costs even out
     // across CUs, and the cheap bricks come last, where they fill the gaps.
     const int n_listed = bricks_listed(active, light), cap_ids = G.nx * G.ny * G.nz;
-    for (;;) {
-        // the thread index is re-read per brick (an empty asm hides that it is
-        // the same), so nothing derived from it is kept live across the pair loop
-        int tid = threadIdx.x;
-        asm volatile("" : "+v"(tid));
-        if (tid == 0) sNext = atomicAdd(next, 1);
-        __syncthreads();
-        const int kb = sNext;
-        if (kb >= n_listed) break;  // uniform
-        const int b = brick_at(active, cap_ids, kb);
+    // cell range (start, count) of staged cell t < S of brick b (count 0 for a
+    // cell outside a non-periodic grid edge)
+    auto ranges = [&](int b, int t, int &st, int &cnt) {
         const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
-
-        // 1. ranges of the staged cells and their LDS bases (the staging order of
-        //    the list build)
-        int st = 0, cnt = 0;
-        if (tid < S) {
-            int gx = cx0 - 1 + St::sx_of(tid), gy = cy0 - 1 + St::sy_of(tid), gz = cz0 - 1 + St::sz_of(tid);
+        st = 0;
+        cnt = 0;
+        if (t < S) {
+            int gx = cx0 - 1 + St::sx_of(t), gy = cy0 - 1 + St::sy_of(t), gz = cz0 - 1 + St::sz_of(t);
             const bool ok = wrap_axis(gx, G.nx, G.periodic & 1u) && wrap_axis(gy, G.ny, (G.periodic >> 1) & 1u) &&
                             wrap_axis(gz, G.nz, (G.periodic >> 2) & 1u);
             if (ok) {
@@ -328,31 +323,131 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
                 cnt = cell_end[lin] - st;
             }
         }
-        int total;
-        const int ex = block_scan<NT>(cnt, total, wsum);
-        if (tid < S) {
-            cBase[tid] = ex;
-            cDelta[tid] = ex - st;
+    };
+    // inner cell u of brick b holds centrals (inner cells past the grid edge
+    // hold none: on a periodic axis the staged copy would be the wrapped cell,
+    // owned by another brick)
+    auto inner_in_grid = [&](int b, int u) {
+        const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
+        return cx0 + St::ix_of(u) < G.nx && cy0 + St::iy_of(u) < G.ny && cz0 + St::iz_of(u) < G.nz;
+    };
+    // Scan ahead, by one wave: claim the next brick and write its cell scans
+    // (the same values as the workgroup's block scans below) into buffer buf,
+    // with wave operations only, while the other waves finish the current
+    // brick's pairs.
+    auto scan_ahead = [&](int lane, int buf) {
+        int kb2 = 0;
+        if (lane == 0) kb2 = atomicAdd(next, 1);
+        kb2 = __shfl(kb2, 0);
+        int total2 = 0, nc2 = 0;
+        if (kb2 < n_listed) {
+            const int b2 = brick_at(active, cap_ids, kb2);
+            constexpr int NCH = (S + kWave - 1) / kWave;
+            int st[NCH], ct[NCH], ex[NCH];
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) ranges(b2, c * kWave + lane, st[c], ct[c]);
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                int inc = ct[c];
+#pragma unroll
+                for (int o = 1; o < kWave; o <<= 1) {
+                    const int v = __shfl_up(inc, o);
+                    if (lane >= o) inc += v;
+                }
+                ex[c] = total2 + inc - ct[c];
+                const int t = c * kWave + lane;
+                if (t < S) {
+                    cBaseB[buf][t] = ex[c];
+                    cDeltaB[buf][t] = ex[c] - st[c];
+                }
+                total2 += __shfl(inc, kWave - 1);
+            }
+            if (lane == 0) cBaseB[buf][S] = total2;
+            // inner cell `lane`: the count and start of its staged cell, taken
+            // from the lane that scanned it
+            const int t = St::inner(min(lane, NI - 1));
+            int vct = 0, vst = 0;
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                const int a = __shfl(ct[c], t % kWave), s2 = __shfl(st[c], t % kWave);
+                if (t / kWave == c) {
+                    vct = a;
+                    vst = s2;
+                }
+            }
+            const int icnt = lane < NI && inner_in_grid(b2, lane) ? vct : 0;
+            int inc = icnt;
+#pragma unroll
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int v = __shfl_up(inc, o);
+                if (lane >= o) inc += v;
+            }
+            nc2 = __shfl(inc, kWave - 1);
+            if (lane < NI) {
+                iBaseB[buf][lane] = inc - icnt;
+                iStartB[buf][lane] = vst;
+            }
+            if (lane == 0) iBaseB[buf][NI] = nc2;
         }
-        if (tid == 0) cBase[S] = total;
-        __syncthreads();
-        // inner cells (x fastest: each inner row is one contiguous particle range)
-        int icnt = 0, ist = 0;
-        // inner cells past the grid edge hold no centrals (on a periodic axis the
-        // staged copy would be the wrapped cell, owned by another brick)
-        if (tid < NI && cx0 + St::ix_of(tid) < G.nx && cy0 + St::iy_of(tid) < G.ny && cz0 + St::iz_of(tid) < G.nz) {
-            const int t = St::inner(tid);
-            icnt = cBase[t + 1] - cBase[t];
-            ist = cBase[t] - cDelta[t];
+        if (lane == 0) {
+            sPre[1] = kb2;
+            sPre[2] = total2;
+            sPre[3] = nc2;
         }
-        int nc;
-        const int iex = block_scan<NT>(icnt, nc, wsum);
-        if (tid < NI) {
-            iBase[tid] = iex;
-            iStart[tid] = ist;
+    };
+    int cur = 0;       // buffer of the current brick's scans
+    bool pre = false;  // uniform: they were scanned ahead
+    for (;;) {
+        // the thread index is re-read per brick (an empty asm hides that it is
+        // the same), so nothing derived from it is kept live across the pair loop
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        int kb, total, nc;
+        if (pre) {
+            kb = sPre[1];
+            total = sPre[2];
+            nc = sPre[3];
+        } else {
+            if (tid == 0) sNext = atomicAdd(next, 1);
+            __syncthreads();
+            kb = sNext;
         }
-        if (tid == 0) iBase[NI] = nc;
-        if (nc == 0) continue;  // uniform: no particle in the brick
+        if (kb >= n_listed) break;  // uniform
+        const int b = brick_at(active, cap_ids, kb);
+        const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
+        int *cBase = cBaseB[cur], *cDelta = cDeltaB[cur], *iBase = iBaseB[cur], *iStart = iStartB[cur];
+
+        if (!pre) {
+            // 1. ranges of the staged cells and their LDS bases (the staging
+            //    order of the list build)
+            int st, cnt;
+            ranges(b, tid, st, cnt);
+            const int ex = block_scan<NT>(cnt, total, wsum);
+            if (tid < S) {
+                cBase[tid] = ex;
+                cDelta[tid] = ex - st;
+            }
+            if (tid == 0) cBase[S] = total;
+            __syncthreads();
+            // inner cells (x fastest: each inner row is one contiguous particle range)
+            int icnt = 0, ist = 0;
+            if (tid < NI && inner_in_grid(b, tid)) {
+                const int t = St::inner(tid);
+                icnt = cBase[t + 1] - cBase[t];
+                ist = cBase[t] - cDelta[t];
+            }
+            const int iex = block_scan<NT>(icnt, nc, wsum);
+            if (tid < NI) {
+                iBase[tid] = iex;
+                iStart[tid] = ist;
+            }
+            if (tid == 0) iBase[NI] = nc;
+        }
+        if (nc == 0) {  // uniform: no particle in the brick
+            pre = false;
+            __syncthreads();
+            continue;
+        }
         __syncthreads();
         const bool use_lds = total <= CAP;
         // central particle of lane q (binary search over the inner cells)
@@ -452,6 +547,8 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
             }
         }
         __syncthreads();
+        // (every thread read sPre at the top of this brick)
+        if (tid == 0) sPre[0] = 0;
 
         // 3. two lanes per central particle of the brick, a wave taking
         //    kWave / 2 consecutive centrals at a time: wave w takes group w
@@ -501,7 +598,13 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
             if (tid % kWave == 0) gn = atomicAdd(&sGroup, 1) + NW;
             g = __builtin_amdgcn_readfirstlane(__shfl(gn, 0));
         }
+        // the first wave left without a group scans the next brick ahead
+        int won = 0;
+        if (tid % kWave == 0) won = atomicCAS(&sPre[0], 0, 1) == 0;
+        if (__builtin_amdgcn_readfirstlane(__shfl(won, 0))) scan_ahead(tid % kWave, cur ^ 1);
         __syncthreads();  // the next brick reuses the LDS
+        pre = sPre[0] != 0;
+        if (pre) cur ^= 1;
     }
 }
 
