@@ -348,7 +348,13 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
     // write positions: the next fluid slot from the front, the next boundary
     // slot from the back; the brick-local entries of the current group of 8
     // are collected in registers and stored as one 16-byte group when it is
-    // full (groups are kWave x 8 entries apart), the last one at the end
+    // full (groups are kWave x 8 entries apart), the last one at the end.
+    // With the brick staged in LDS and brick-local lists asked for, the
+    // global entries are written after the scan from the brick-local ones
+    // (deferred): the lanes of a wave then write entry k of their lists in
+    // one store, where during the scan each lane writes at its own pace and
+    // the tile rows leave the L2 cache partly filled, several times over.
+    const bool deferred = LDS && ltile != nullptr;
     uint32_t *tf = tile, *tb = tile + (size_t)(M - 1) * kWave;
     uint4 *lg = (uint4 *)ltile;
     uint4 grp = make_uint4(0u, 0u, 0u, 0u);
@@ -382,11 +388,13 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
                         if (w < M) {
                             const int sl = c0 + k;
                             const int j = sl - delta;
-                            const uint32_t inf = LDS ? __float_as_uint(sPos[sl].w) : ginfo[j];
-                            const bool nb_boundary = ptype(inf) == kBoundary;
-                            *(nb_boundary ? tb : tf) = (uint32_t)j | code;
-                            tf += nb_boundary ? 0 : kWave;
-                            tb -= nb_boundary ? kWave : 0;
+                            if (!deferred) {
+                                const uint32_t inf = LDS ? __float_as_uint(sPos[sl].w) : ginfo[j];
+                                const bool nb_boundary = ptype(inf) == kBoundary;
+                                *(nb_boundary ? tb : tf) = (uint32_t)j | code;
+                                tf += nb_boundary ? 0 : kWave;
+                                tb -= nb_boundary ? kWave : 0;
+                            }
                             if (ltile) {
                                 const int e = w & (kBrickGroup - 1);
                                 const uint32_t v = (uint32_t)min(sl, 0xFFFF) << ((e & 1) * 16);
@@ -407,6 +415,40 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
         }
     }
     if (ltile && (w & (kBrickGroup - 1)) != 0) lg[(size_t)(w / kBrickGroup) * kWave] = grp;
+    if (deferred) {
+        // Entries are in scan order, neighbour cell by neighbour cell, and the
+        // 27 cells hold disjoint slot ranges: a cursor over the cells in scan
+        // order, moved on until the entry's slot is in its cell's range, finds
+        // each entry's cell (and so its particle index and image code).
+        int dx = -1, dy = -1, dz = -1;
+        int t = tc + Staging<BX, BY, BZ>::step(dx, dy, dz);
+        int lo = cBase[t], hi = cBase[t + 1], delta = cDelta[t];
+        for (int e = 0; e < w; ++e) {
+            if ((e & (kBrickGroup - 1)) == 0) grp = lg[(size_t)(e / kBrickGroup) * kWave];
+            const int word = e >> 1 & 3;
+            const uint32_t pair = word == 0 ? grp.x : word == 1 ? grp.y : word == 2 ? grp.z : grp.w;
+            const int sl = (int)(pair >> ((e & 1) * 16) & 0xFFFFu);
+            const uint32_t inf = __float_as_uint(sPos[sl].w);  // read before the cursor moves
+            while (sl < lo || sl >= hi) {
+                if (++dx > 1) {
+                    dx = -1;
+                    if (++dy > 1) {
+                        dy = -1;
+                        ++dz;
+                    }
+                }
+                if (dz > 1) break;  // not reached: every entry lies in one of the 27 cells
+                t = tc + Staging<BX, BY, BZ>::step(dx, dy, dz);
+                lo = cBase[t];
+                hi = cBase[t + 1];
+                delta = cDelta[t];
+            }
+            const bool nb_boundary = ptype(inf) == kBoundary;
+            *(nb_boundary ? tb : tf) = (uint32_t)(sl - delta) | pack_neib(0u, -dx, -dy, -dz);
+            tf += nb_boundary ? 0 : kWave;
+            tb -= nb_boundary ? kWave : 0;
+        }
+    }
     const int wf = (int)((tf - tile) / kWave), wb = w - wf;
     total_found = found;
     return (uint32_t)wf | (uint32_t)wb << 16;
