@@ -369,18 +369,32 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
                 const int s1 = central_boundary ? cFluidEnd[t] : cBase[t + 1];
                 const int delta = cDelta[t];
                 const uint32_t code = pack_neib(0u, -dx, -dy, -dz);
+                // the central itself can only be met in its own cell (the 27
+                // cells are distinct grid cells), at slot i + delta there
+                const int self_sl = (dx | dy | dz) == 0 ? i + delta : -1;
                 for (int c0 = s0; c0 < s1; c0 += 64) {
                     const int m = min(s1 - c0, 64);
-                    uint64_t hits = 0;
+                    // hit bits of the chunk, candidates 0..31 and 32..63 in a
+                    // 32-bit word each (the bit of candidate k is uniform)
+                    uint32_t hlo = 0u, hhi = 0u;
                     // two candidates in flight per lane (the LDS read latency)
 #pragma unroll 2
-                    for (int k = 0; k < m; ++k) {
+                    for (int k = 0; k < min(m, 32); ++k) {
                         const int sl = c0 + k;
                         const float4 pj = LDS ? sPos[sl] : gpos[sl - delta];
                         const float r2 = predicate_r2(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, t2x, t2y, t2z);
-                        const bool hit = (r2 < rs2) & (sl - delta != i);
-                        hits |= (uint64_t)hit << k;
+                        hlo = r2 < rs2 ? hlo | 1u << k : hlo;
                     }
+#pragma unroll 2
+                    for (int k = 32; k < m; ++k) {
+                        const int sl = c0 + k;
+                        const float4 pj = LDS ? sPos[sl] : gpos[sl - delta];
+                        const float r2 = predicate_r2(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, t2x, t2y, t2z);
+                        hhi = r2 < rs2 ? hhi | 1u << (k - 32) : hhi;
+                    }
+                    uint64_t hits = (uint64_t)hhi << 32 | hlo;
+                    const int sk = self_sl - c0;
+                    if ((unsigned)sk < 64u) hits &= ~(1ull << sk);
                     found += __popcll(hits);
                     while (hits) {
                         const int k = __ffsll((long long)hits) - 1;
