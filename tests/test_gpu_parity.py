@@ -187,6 +187,22 @@ def test_neighbour_overflow_reported():
         sim.check_status()
 
 
+def test_truncated_lists_with_walls():
+    """Lists cut at max_neibs on a scene with walls: the fluid entries (from
+    the front) and the wall entries (from the back), each in scan order, match
+    the oracle's lists, and the brick-local lists keep the documented layout."""
+    sc = S.dam_break(dp=0.03)
+    log("case truncated dam break: n=%d max_neibs=40" % sc.n)
+    sim = make_sim(sc, max_neibs=40)
+    sim.build()
+    torch_sync()
+    ob = compare_build(sc, sim, max_neibs=40)
+    assert ob["lists"].overflow > 0
+    assert sim.status_host()["overflow"] == ob["lists"].overflow
+    exp, tot = expected_brick_lists(sim, sc.grid)
+    assert np.array_equal(gpu_brick_lists(sim), exp), "brick-local lists"
+
+
 def test_deterministic_rebuild_and_forces():
     sc = S.shuffled(S.dam_break(dp=0.02), seed=9)
     a = make_sim(sc)
