@@ -21,7 +21,8 @@ def _coords(grid, cell):
 
 
 def pair_r2(grid, cell, pos, fp64=False):
-    """[N,N] squared separations x_i - x_j of a float32 encoded state."""
+    """[N,N] squared separations x_i - x_j of a float32 encoded state (with
+    fp64, of float32 or double offsets, in double)."""
     c = _coords(grid, cell)
     k = c[:, None, :] - c[None, :, :]
     for d in range(3):
@@ -29,11 +30,12 @@ def pair_r2(grid, cell, pos, fp64=False):
             n = int(grid.ncell[d])
             k[:, :, d] = (k[:, :, d] + n // 2) % n - n // 2
     cs = np.asarray(grid.cell_size, dtype=np.float32)
-    o = np.asarray(pos, dtype=np.float32)[:, :3]
     if fp64:
-        x = k.astype(np.float64) * cs.astype(np.float64)[None, None, :] + (
-            o.astype(np.float64)[:, None, :] - o.astype(np.float64)[None, :, :])
+        # double offsets are taken as given (float32 ones lift exactly)
+        o64 = np.asarray(pos)[:, :3].astype(np.float64)
+        x = k.astype(np.float64) * cs.astype(np.float64)[None, None, :] + (o64[:, None, :] - o64[None, :, :])
         return (x * x).sum(axis=2)
+    o = np.asarray(pos, dtype=np.float32)[:, :3]
     t1 = (o[:, None, :] - o[None, :, :]).astype(np.float32)
     t2 = (k.astype(np.float32) * cs[None, None, :]).astype(np.float32)
     x = (t2 + t1).astype(np.float32)
