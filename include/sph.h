@@ -77,12 +77,15 @@ typedef enum {
     SPH_ERR_HIP = 3         /* a HIP runtime call or launch failed */
 } sph_status;
 
-/* Device status word written by sph_build_neighbors: int32[4]. */
+/* Device status word written by sph_build_neighbors: int32[SPH_STATUS_WORDS]. */
 enum {
     SPH_STATUS_N_ACTIVE = 0,   /* particles inside the grid (sorted first)  */
     SPH_STATUS_MAX_NEIBS = 1,  /* largest n_fluid + n_boundary found        */
     SPH_STATUS_OVERFLOW = 2,   /* particles whose list did not fit          */
-    SPH_STATUS_DROPPED = 3     /* particles that left the grid (sorted last) */
+    SPH_STATUS_DROPPED = 3,    /* particles that left the grid (sorted last) */
+    SPH_STATUS_NONFINITE = 4,  /* particles with a non-finite offset, mass,
+                                  velocity or density when the build ran    */
+    SPH_STATUS_WORDS = 8       /* words 5..7 are reserved and written 0     */
 };
 
 #define SPH_NEIB_INDEX_BITS 26
@@ -182,7 +185,8 @@ typedef struct {
 /* Human-readable name of a status code (static storage). */
 const char *sph_status_string(sph_status s);
 
-/* ABI revision of this header (incremented on incompatible changes). */
+/* ABI revision of this header (incremented on incompatible changes; 2: the
+ * status word grew to SPH_STATUS_WORDS). */
 int32_t sph_abi_version(void);
 
 /* Number of uint32 entries of a neighbour list for `capacity` particles:
@@ -216,7 +220,11 @@ size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells);
  *   4. build the split neighbour list described above into
  *      neibs (device uint32[sph_neib_list_entries(capacity, max_neibs)]) and
  *      neib_count (device uint32[capacity]); dropped particles get count 0;
- *   5. d_status (device int32[4], see SPH_STATUS_*) is overwritten;
+ *   5. d_status (device int32[SPH_STATUS_WORDS], see SPH_STATUS_*) is
+ *      overwritten; a particle whose offset, mass, velocity or density is
+ *      not finite is counted in SPH_STATUS_NONFINITE (a non-finite offset
+ *      also drops it), so that a state that blew up is reported at the next
+ *      rebuild instead of propagating silently;
  *   6. if perm_out (device uint32[capacity]) is not NULL, perm_out[k] is the
  *      index before the call of the particle now stored at k (k < n); the
  *      adjoint of the rebuild is dL/dy_before[perm_out[k]] = dL/dy_after[k]
@@ -407,6 +415,31 @@ sph_status sph_count_interactions(const sph_grid *grid, const sph_params *params
                                   const sph_particles *parts, const uint32_t *neibs,
                                   const uint32_t *neib_count, int32_t max_neibs,
                                   unsigned long long *d_count, void *stream);
+
+/* Pairs missed by reused lists (section "Optimizing the neighbors search":
+ * the list is built with a search radius above the kernel support so that
+ * it can serve several steps; section "Too much of a good thing?": rebuilt
+ * every 10 steps).  A pair that came within 2h while the lists were reused,
+ * but was not listed, was left out of the derivatives.  Counted at each
+ * rebuild, in two calls on the same state:
+ *   phase 0, just before sph_build_neighbors, with the lists about to be
+ *            replaced: d_missed[0] = their pairs with r < 2h at the current
+ *            positions (as sph_count_interactions);
+ *   phase 1, just after it, with the new lists: d_missed[1] = their pairs
+ *            with r < 2h, which are all the pairs within 2h when no list
+ *            overflowed; d_missed[2] = d_missed[1] - d_missed[0], the pairs
+ *            within 2h the previous lists did not hold; d_missed[3] +=
+ *            d_missed[2] (a running total the caller zeroes).
+ * Both counts evaluate the separation as the neighbour predicate does, each
+ * on its own encoding (the re-binning moves offsets by whole cells), so a
+ * pair within rounding of 2h may be counted by one and not the other;
+ * particles dropped by the rebuild lose their pairs, which can make
+ * d_missed[2] negative.  d_missed: device int64[4].
+ * Errors: SPH_ERR_ARG (also for a phase other than 0 or 1). */
+sph_status sph_count_missed_pairs(const sph_grid *grid, const sph_params *params,
+                                  const sph_particles *parts, const uint32_t *neibs,
+                                  const uint32_t *neib_count, int32_t max_neibs, int32_t phase,
+                                  long long *d_missed, void *stream);
 
 #ifdef __cplusplus
 }

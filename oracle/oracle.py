@@ -285,7 +285,30 @@ def build_f32(grid, params, cell, pos, vel, info, max_neibs=128):
     lists = neighbors(grid, params, cell, info, start, end, max_neibs, pos=pos)
     return dict(cell=np.ascontiguousarray(cell), pos=np.ascontiguousarray(pos),
                 vel=np.ascontiguousarray(vel), info=np.ascontiguousarray(info), perm=perm,
-                start=start, end=end, lists=lists, n_active=n_active, dropped=dropped)
+                start=start, end=end, lists=lists, n_active=n_active, dropped=dropped,
+                nonfinite=nonfinite_count(pos, vel))
+
+
+def nonfinite_count(pos, vel) -> int:
+    """Particles with a non-finite offset, mass, velocity or density."""
+    pos = np.asarray(pos, dtype=np.float32)
+    vel = np.asarray(vel, dtype=np.float32)
+    return int((~np.isfinite(pos).all(axis=1) | ~np.isfinite(vel).all(axis=1)).sum())
+
+
+def missed_pairs(grid, params, old, pos_now, max_neibs=128):
+    """Pairs within 2h that the lists of a previous build missed (section
+    "Optimizing the neighbors search": lists built with an enlarged radius
+    are reused for several steps).  old: a build_f32 result; pos_now: the
+    float32 state [n, 4] at the next rebuild, in old's sorted order, offsets
+    relative to old's cells.  Returns (interactions of old's lists at
+    pos_now, interactions of the fresh lists, their difference): the fresh
+    lists hold every pair within the search radius, so the difference counts
+    the pairs within 2h missing from the old lists."""
+    i_old = count_interactions_f32(grid, params, old["cell"], pos_now, old["lists"])
+    new = build_f32(grid, params, old["cell"], pos_now, old["vel"], old["info"], max_neibs)
+    i_new = count_interactions_f32(grid, params, new["cell"], new["pos"], new["lists"])
+    return i_old, i_new, i_new - i_old
 
 
 def rebuild_f64(grid, params, st: State, max_neibs=128):

@@ -14,11 +14,12 @@ import os
 import torch
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-# SPH_LIB may name another build of the same library (e.g. a tuning variant)
-LIB_PATH = os.environ.get("SPH_LIB") or os.path.join(PKG, "libsph.so")
+# the in-tree build, and only that one
+LIB_PATH = os.path.join(PKG, "libsph.so")
 
 SPH_OK, SPH_ERR_ARG, SPH_ERR_WORKSPACE, SPH_ERR_HIP = 0, 1, 2, 3
-STATUS_N_ACTIVE, STATUS_MAX_NEIBS, STATUS_OVERFLOW, STATUS_DROPPED = 0, 1, 2, 3
+STATUS_N_ACTIVE, STATUS_MAX_NEIBS, STATUS_OVERFLOW, STATUS_DROPPED, STATUS_NONFINITE = 0, 1, 2, 3, 4
+STATUS_WORDS = 8
 NEIB_INDEX_BITS = 26
 MAX_CAPACITY = 1 << NEIB_INDEX_BITS
 
@@ -27,7 +28,7 @@ EXPORTS = [
     "sph_brick_shapes", "sph_neib_brick_entries", "sph_build_neighbors", "sph_forces", "sph_forces_workspace_bytes", "sph_integrate",
     "sph_dt_workspace_bytes", "sph_step_dt", "sph_count_interactions", "sph_integrate_backward",
     "sph_forces_backward_workspace_bytes", "sph_forces_backward", "sph_unpermute",
-    "sph_diagnostics_workspace_bytes", "sph_reduce_diagnostics",
+    "sph_diagnostics_workspace_bytes", "sph_reduce_diagnostics", "sph_count_missed_pairs",
 ]
 
 
@@ -92,6 +93,8 @@ def _load():
     L.sph_step_dt.restype = st
     L.sph_count_interactions.argtypes = [P, P, P, P, P, i32, P, P]
     L.sph_count_interactions.restype = st
+    L.sph_count_missed_pairs.argtypes = [P, P, P, P, P, i32, i32, P, P]
+    L.sph_count_missed_pairs.restype = st
     L.sph_integrate_backward.argtypes = [P, i32, P, P, P, P, P, P, P, P]
     L.sph_integrate_backward.restype = st
     L.sph_forces_backward_workspace_bytes.argtypes = [i32, i32]
@@ -228,6 +231,13 @@ def sph_count_interactions(grid: SphGrid, params: SphParams, parts: SphParticles
     check(lib.sph_count_interactions(C.byref(grid), C.byref(params), C.byref(parts), ptr(neibs),
                                      ptr(neib_count), int(max_neibs), ptr(d_count), stream_ptr(stream)),
           "sph_count_interactions")
+
+
+def sph_count_missed_pairs(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count,
+                           max_neibs: int, phase: int, d_missed, stream=None):
+    check(lib.sph_count_missed_pairs(C.byref(grid), C.byref(params), C.byref(parts), ptr(neibs),
+                                     ptr(neib_count), int(max_neibs), int(phase), ptr(d_missed),
+                                     stream_ptr(stream)), "sph_count_missed_pairs")
 
 
 def sph_forces_backward_workspace_bytes(capacity: int, n_cells: int) -> int:

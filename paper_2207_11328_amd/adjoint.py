@@ -53,6 +53,11 @@ class AdjointRollout:
         self.perm = z(cap, torch.int32)
         self.ws_back = z(abi.sph_forces_backward_workspace_bytes(cap, s.n_cells), torch.uint8)
         self.grad_params = z(3, torch.float64)
+        # status word of every build of the forward and of the reverse (the
+        # reverse rebuilds each block's lists); checked once at the end of each
+        n_builds = max(1, (self.steps + self.K - 1) // self.K)
+        self.fwd_status = z((n_builds, abi.STATUS_WORDS), torch.int32)
+        self.bwd_status = z((n_builds, abi.STATUS_WORDS), torch.int32)
         self.initial = self._snapshot()
         self.checkpoints = {}
         self.n = n
@@ -60,12 +65,19 @@ class AdjointRollout:
     # ------------------------------------------------------------ state helpers
     def _snapshot(self):
         s = self.sim
-        return tuple(t.clone() for t in (s.cell, s.pos, s.vel, s.info))
+        return tuple(t.clone() for t in (s.cell, s.pos, s.vel, s.info, s.d_time))
 
     def _restore(self, snap):
         s = self.sim
-        for dst, src in zip((s.cell, s.pos, s.vel, s.info), snap):
+        for dst, src in zip((s.cell, s.pos, s.vel, s.info, s.d_time), snap):
             dst.copy_(src)
+
+    def _check_builds(self, status, n_builds):
+        """Raise SphError if any build overflowed its lists (a truncated list
+        is not symmetric, and the gather adjoint assumes it is) or met a
+        non-finite state."""
+        for row in status[:n_builds].cpu().numpy():
+            self.sim.raise_on_status(self.sim.status_dict(row))
 
     def _advance(self, store=None):
         """One predictor/corrector step on the current lists (no rebuild)."""
@@ -99,12 +111,14 @@ class AdjointRollout:
     # ------------------------------------------------------------ forward
     def forward(self):
         s = self.sim
+        self.fwd_status.zero_()
         for k in range(self.steps):
             if k % self.C == 0:
                 self.checkpoints[k] = self._snapshot()
             if k % self.K == 0:
-                s.build()
+                s.build(status=self.fwd_status[k // self.K])
             self._advance()
+        self._check_builds(self.fwd_status, (self.steps + self.K - 1) // self.K)
         return s
 
     # ------------------------------------------------------------ reverse
@@ -133,6 +147,8 @@ class AdjointRollout:
         dL/d(alpha, c0, nu) (device double[3])."""
         s = self.sim
         n = s.n
+        t_end = s.d_time.clone()
+        self.bwd_status.zero_()
         self.gpos.zero_()
         self.gvel.zero_()
         self.gpos[:n] = gpos_final
@@ -146,12 +162,12 @@ class AdjointRollout:
             for b in blocks:
                 pre[b] = self._snapshot()
                 if b != blocks[-1]:
-                    s.build()
+                    s.build(status=self.bwd_status[b // self.K])
                     for _ in range(self.K):
                         self._advance()
             for b in reversed(blocks):
                 self._restore(pre[b])
-                s.build(perm_out=self.perm)
+                s.build(perm_out=self.perm, status=self.bwd_status[b // self.K])
                 stored = []
                 for _ in range(b, min(b + self.K, end)):
                     self._advance(stored)
@@ -160,6 +176,8 @@ class AdjointRollout:
                 abi.sph_unpermute(n, self.perm, self.gvel, self.tmp_v)
                 self.gpos, self.tmp_p = self.tmp_p, self.gpos
                 self.gvel, self.tmp_v = self.tmp_v, self.gvel
+        s.d_time.copy_(t_end)
+        self._check_builds(self.bwd_status, (self.steps + self.K - 1) // self.K)
         return self.gpos[:n], self.gvel[:n], self.grad_params
 
     # ------------------------------------------------------------ outputs

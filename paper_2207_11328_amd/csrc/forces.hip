@@ -101,6 +101,13 @@ __global__ __launch_bounds__(kThreads) void k_count_interactions(int n, const fl
 
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
 
+// missed pairs of a rebuild: the difference of the two counts, and its running total
+__global__ void k_missed_finish(long long *m)
+{
+    m[2] = m[1] - m[0];
+    m[3] += m[2];
+}
+
 bool make_const(const sph_grid *g, const sph_params *p, int max_neibs, ForceConst &C)
 {
     if (!(p->h > 0.0f) || !(p->rho0 > 0.0f) || !(p->c0 > 0.0f) || p->gamma != 7.0f) return false;
@@ -231,6 +238,30 @@ extern "C" sph_status sph_count_interactions(const sph_grid *grid, const sph_par
     if (n == 0) return SPH_OK;
     k_count_interactions<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, (const float4 *)parts->pos, neibs,
                                                                       neib_count, C, d_count);
+    SPH_CHECK_LAUNCH();
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_count_missed_pairs(const sph_grid *grid, const sph_params *params,
+                                             const sph_particles *parts, const uint32_t *neibs,
+                                             const uint32_t *neib_count, int32_t max_neibs, int32_t phase,
+                                             long long *d_missed, void *stream)
+{
+    if (!common_args(grid, params, parts, neibs, neib_count, max_neibs) || !d_missed) return SPH_ERR_ARG;
+    if (phase != 0 && phase != 1) return SPH_ERR_ARG;
+    ForceConst C;
+    if (!make_const(grid, params, max_neibs, C)) return SPH_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    // phase 0 counts into slot 0, phase 1 into slot 1 (both non-negative
+    // counts, accumulated as unsigned)
+    unsigned long long *slot = (unsigned long long *)(d_missed + phase);
+    k_zero_u64<<<1, 1, 0, s>>>(slot);
+    SPH_CHECK_LAUNCH();
+    const int n = parts->n;
+    if (n > 0)
+        k_count_interactions<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, (const float4 *)parts->pos, neibs,
+                                                                          neib_count, C, slot);
+    if (phase == 1) k_missed_finish<<<1, 1, 0, s>>>(d_missed);
     SPH_CHECK_LAUNCH();
     return SPH_OK;
 }

@@ -108,7 +108,10 @@ __device__ __forceinline__ void pair_terms(PairAcc &A, uint32_t e, const float4 
                                            const float2 &ai, const float4 &pj, const float4 &vj, const float2 &aj,
                                            bool valid, bool pair_fluid, const ForceConst &C)
 {
-    // separation, bit-identical to the list predicate: x = k cs + (o_i - o_j)
+    // separation x = k cs + (o_i - o_j), each component bit-identical to the
+    // list predicate's; r^2 is then formed with fused multiply-adds, so the
+    // r < 2h decision can differ from an exactly rounded one by a rounding
+    // of r^2
     const float xx = fmaf(entry_k(e, 0), C.csx, pi.x - pj.x);
     const float xy = fmaf(entry_k(e, 1), C.csy, pi.y - pj.y);
     const float xz = fmaf(entry_k(e, 2), C.csz, pi.z - pj.z);
@@ -212,9 +215,13 @@ __global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__rest
 // pair costs no index decoding.  Staged positions are relative to the centre
 // cell of the brick, o + s cs with s in {-2, ..., 2} per axis, so the
 // separation is one subtraction: its rounding error is a few ulp of 2.5 cs,
-// not of cs (the list predicate, which must be exact, is not evaluated here;
-// the r < 2h mask only differs from the exact one where the kernel weight is
-// of order 1e-20).  A brick whose halo does not fit in LDS reads the global
+// not of cs (the list predicate, which must be exact, is not evaluated here).
+// The r < 2h mask may therefore differ from an exactly rounded one for a
+// pair within that error of the support edge: for the Wendland, cubic-spline
+// and quadratic kernels such a pair weighs ~(q - 2)^2 or less, i.e. nothing
+// in float32; the truncated Gaussian's F does not vanish at r = 2h, so there
+// such a pair carries a finite weight and is counted by one side and not
+// the other.  A brick whose halo does not fit in LDS reads the global
 // lists and the global state with the arithmetic of k_forces.
 
 // Pairs of one central's brick-local list, read from LDS, shared by two

@@ -330,4 +330,4 @@ extern "C" const char *sph_status_string(sph_status st)
     return "SPH: unknown status";
 }
 
-extern "C" int32_t sph_abi_version(void) { return 1; }
+extern "C" int32_t sph_abi_version(void) { return 2; }

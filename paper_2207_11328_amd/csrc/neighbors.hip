@@ -254,6 +254,9 @@ __global__ __launch_bounds__(kThreads) void k_cell_sort(int n_buckets, const int
     }
 }
 
+// Reorder by the sort permutation.  Also counts the particles whose offset,
+// mass, velocity or density is not finite (one atomic per wave), so that a
+// state that blew up is reported by the build's status word.
 __global__ __launch_bounds__(kThreads) void k_gather(int n, const uint32_t *__restrict__ perm,
                                                      const int32_t *__restrict__ cell,
                                                      const float4 *__restrict__ pos,
@@ -263,16 +266,25 @@ __global__ __launch_bounds__(kThreads) void k_gather(int n, const uint32_t *__re
                                                      float4 *__restrict__ o_pos,
                                                      float4 *__restrict__ o_vel,
                                                      uint32_t *__restrict__ o_info,
-                                                     uint32_t *__restrict__ perm_out)
+                                                     uint32_t *__restrict__ perm_out,
+                                                     int32_t *__restrict__ status)
 {
     const int k = blockIdx.x * kThreads + threadIdx.x;
-    if (k >= n) return;
-    const uint32_t src = perm[k];
-    if (perm_out) perm_out[k] = src;
-    o_cell[k] = cell[src];
-    o_pos[k] = pos[src];
-    o_vel[k] = vel[src];
-    o_info[k] = info[src];
+    bool bad = false;
+    if (k < n) {
+        const uint32_t src = perm[k];
+        if (perm_out) perm_out[k] = src;
+        const float4 p = pos[src];
+        const float4 v = vel[src];
+        o_cell[k] = cell[src];
+        o_pos[k] = p;
+        o_vel[k] = v;
+        o_info[k] = info[src];
+        bad = !(isfinite(p.x) && isfinite(p.y) && isfinite(p.z) && isfinite(p.w) && isfinite(v.x) &&
+                isfinite(v.y) && isfinite(v.z) && isfinite(v.w));
+    }
+    const unsigned long long m = __ballot(bad);
+    if (m && (threadIdx.x % kWave) == 0) atomicAdd(&status[SPH_STATUS_NONFINITE], (int)__popcll(m));
 }
 
 __global__ __launch_bounds__(kThreads) void k_copy_state(int n, const int32_t *__restrict__ cell,
@@ -680,7 +692,7 @@ extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params
     const unsigned fill_blocks = sph_blocks(nbk, kThreads) < 4096u ? sph_blocks(nbk, kThreads) : 4096u;
     k_fill<<<fill_blocks, kThreads, 0, s>>>(cnt, nbk, 0);
     k_fill<<<fill_blocks, kThreads, 0, s>>>(cursor, nbk, 0);
-    k_fill<<<1, 64, 0, s>>>(d_status, 4, 0);
+    k_fill<<<1, 64, 0, s>>>(d_status, SPH_STATUS_WORDS, 0);
     SPH_CHECK_LAUNCH();
     if (n > 0) {
         k_rebin_count<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(
@@ -702,7 +714,7 @@ extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params
         k_cell_sort<<<sph_blocks(nbk, kThreads / kWave), kThreads, 0, s>>>(nbk, start, perm_a, parts->info,
                                                                               perm_b);
         k_gather<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, perm_b, parts->cell, pos, vel, parts->info,
-                                                               t_cell, t_pos, t_vel, t_info, perm_out);
+                                                               t_cell, t_pos, t_vel, t_info, perm_out, d_status);
         SPH_CHECK_LAUNCH();
         const float rs2 = params->r_search * params->r_search;
         int32_t *active = (int32_t *)(ws + L.active);

@@ -61,7 +61,11 @@ class Simulation:
         self.neib_count = z(cap, torch.int32)
         self.cell_start = z(max(self.n_cells, 1), torch.int32)
         self.cell_end = z(max(self.n_cells, 1), torch.int32)
-        self.status = z(4, torch.int32)
+        self.status = z(abi.STATUS_WORDS, torch.int32)
+        # missed pairs at rebuilds (sph_count_missed_pairs): previous lists'
+        # interactions, new lists' interactions, their difference, running total
+        self.missed = z(4, torch.int64)
+        self.track_missed = False
         self.ws_build = z(abi.sph_build_workspace_bytes(cap, self.n_cells), torch.uint8)
         self.ws_dt = z(abi.sph_dt_workspace_bytes(), torch.uint8)
         self.ws_forces = z(abi.sph_forces_workspace_bytes(cap, self.n_cells), torch.uint8)
@@ -90,12 +94,26 @@ class Simulation:
         self.parts = abi.particles_struct(n, self.cell, self.pos, self.vel, self.info)
         self.parts_star = abi.particles_struct(n, self.cell, self.pos_star, self.vel_star, self.info)
         self.steps_done = 0
+        self._built = False
 
     # ------------------------------------------------------------ primitives
-    def build(self, stream=None, perm_out=None):
+    def build(self, stream=None, perm_out=None, status=None):
+        """Neighbour search (re-bin, sort, lists).  status: an int32 device
+        tensor of STATUS_WORDS words to receive the build's status word
+        instead of self.status.  With track_missed set, every rebuild after
+        the first also counts the pairs within 2h that the replaced lists
+        missed (self.missed)."""
+        count = self.track_missed and self._built
+        if count:
+            abi.sph_count_missed_pairs(self.g, self.p, self.parts, self.neibs, self.neib_count, self.max_neibs,
+                                       0, self.missed, stream)
         abi.sph_build_neighbors(self.g, self.p, self.parts, self.neibs, self.neib_count, self.max_neibs,
-                                self.cell_start, self.cell_end, self.status, self.ws_build, stream, perm_out,
-                                self.neibs_brick)
+                                self.cell_start, self.cell_end, self.status if status is None else status,
+                                self.ws_build, stream, perm_out, self.neibs_brick)
+        if count:
+            abi.sph_count_missed_pairs(self.g, self.p, self.parts, self.neibs, self.neib_count, self.max_neibs,
+                                       1, self.missed, stream)
+        self._built = True
 
     def set_brick(self, brick):
         """Change the brick shape of the LDS kernels; the lists must be
@@ -209,16 +227,34 @@ class Simulation:
             self.steps_done += self.rebuild_every
 
     # ------------------------------------------------------------ host views
-    def status_host(self) -> dict:
-        s = self.status.cpu().numpy()
-        return {"n_active": int(s[0]), "max_neibs": int(s[1]), "overflow": int(s[2]), "dropped": int(s[3])}
+    @staticmethod
+    def status_dict(words) -> dict:
+        s = np.asarray(words)
+        return {"n_active": int(s[abi.STATUS_N_ACTIVE]), "max_neibs": int(s[abi.STATUS_MAX_NEIBS]),
+                "overflow": int(s[abi.STATUS_OVERFLOW]), "dropped": int(s[abi.STATUS_DROPPED]),
+                "nonfinite": int(s[abi.STATUS_NONFINITE])}
 
-    def check_status(self):
-        st = self.status_host()
+    def status_host(self) -> dict:
+        return self.status_dict(self.status.cpu().numpy())
+
+    def raise_on_status(self, st: dict):
+        """SphError for a build whose lists overflowed or whose state held
+        non-finite values (particles that left the grid are not an error)."""
+        if st["nonfinite"] > 0:
+            raise abi.SphError("non-finite state: %d particles have a non-finite offset, mass, velocity or "
+                               "density" % st["nonfinite"])
         if st["overflow"] > 0:
             raise abi.SphError("neighbour list overflow: %d particles need more than %d slots (max %d)"
                                % (st["overflow"], self.max_neibs, st["max_neibs"]))
+
+    def check_status(self):
+        st = self.status_host()
+        self.raise_on_status(st)
         return st
+
+    def missed_host(self) -> dict:
+        m = self.missed.cpu().numpy()
+        return {"previous_lists": int(m[0]), "new_lists": int(m[1]), "missed": int(m[2]), "missed_total": int(m[3])}
 
     def state_host(self) -> dict:
         n = self.n

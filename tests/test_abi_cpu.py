@@ -61,7 +61,7 @@ int main(void) {
 
 
 def test_host_only_entry_points(abi):
-    assert abi.lib.sph_abi_version() == 1
+    assert abi.lib.sph_abi_version() == 2
     for code in range(4):
         assert abi.lib.sph_status_string(code)
     a = abi.sph_build_workspace_bytes(1000, 500)
@@ -99,6 +99,21 @@ def test_argument_errors_return_before_any_launch(abi):
     assert abi.lib.sph_integrate(C.byref(p), 2, None, None, None, None, None, None, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_step_dt(None, None, None, None, None, 0, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_count_interactions(None, None, None, None, None, 128, None, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_count_missed_pairs(None, None, None, None, None, 128, 0, None, None) == abi.SPH_ERR_ARG
+    # a phase other than 0 or 1, and a missing output, on otherwise valid arguments
+    g2 = abi.SphGrid()
+    for d in range(3):
+        g2.cell_size[d] = 0.06
+        g2.ncell[d] = 4
+    p2 = abi.SphParams()
+    p2.h, p2.r_search, p2.rho0, p2.gamma, p2.c0 = 0.026, 0.06, 1000.0, 7.0, 20.0
+    empty = abi.SphParticles(0, 0, None, None, None, None)
+    out = (C.c_longlong * 4)()
+    for phase in (-1, 2):
+        assert abi.lib.sph_count_missed_pairs(C.byref(g2), C.byref(p2), C.byref(empty), None, None, 128, phase,
+                                              out, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_count_missed_pairs(C.byref(g2), C.byref(p2), C.byref(empty), None, None, 128, 0, None,
+                                          None) == abi.SPH_ERR_ARG
 
 
 def test_unknown_model_switches_are_rejected(abi):

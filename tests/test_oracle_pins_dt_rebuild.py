@@ -298,3 +298,71 @@ def test_double_and_float_predicates_differ_only_near_the_radius():
         c = set(l64.fluid(i).tolist()) | set(l64.boundary(i).tolist())
         for j in a ^ c:
             assert abs(r2[i, j] - rs * rs) < 2.0 ** -20 * rs * rs
+
+
+# ------------------------------------------------------------------ missed pairs
+M_CLOUD = 256   # list slots for the random clouds, which cluster (no overflow)
+
+def _moved(sc, amp, seed):
+    """The oracle's sorted build of a scene and, in its order, the float32
+    offsets after a seeded displacement of up to amp dp per axis (fluid
+    particles only; boundary particles are fixed)."""
+    b = O.build_f32(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, max_neibs=M_CLOUD)
+    assert b["lists"].overflow == 0
+    rng = np.random.default_rng(seed)
+    fluid = (b["info"] >> TYPE_SHIFT) == 0
+    d = rng.uniform(-amp, amp, size=(sc.n, 3)) * sc.params.dp * fluid[:, None]
+    # no particle leaves a closed axis (none is dropped by the rebuild)
+    x = S.decode_positions(sc.grid, b["cell"], b["pos"][:, :3].astype(np.float64) + d)
+    L = sc.grid.ncell * sc.grid.cell_size.astype(np.float64)
+    for a in range(3):
+        if not (sc.grid.periodic >> a) & 1:
+            d[(x[:, a] < 0.0) | (x[:, a] >= L[a]), a] = 0.0
+    pos = b["pos"].copy()
+    pos[:, :3] = (pos[:, :3].astype(np.float64) + d).astype(np.float32)
+    return b, pos
+
+
+@pytest.mark.parametrize("amp,periodic", [(0.05, 0), (0.4, 0), (0.9, 0b011)])
+def test_missed_pairs_are_the_pairs_within_2h_absent_from_the_old_lists(amp, periodic):
+    """The oracle's missed-pair count equals the brute-force count of pairs
+    (i, j) with float32 r < 2h at the rebuild (after re-binning, boundary-
+    boundary pairs excluded) whose j is not in i's previous list; its two
+    parts are the brute-force counts of those pairs and of the old lists'
+    pairs within 2h."""
+    sc = S.random_cloud(n=1500, box=(0.3, 0.26, 0.24), dp=0.02, periodic=periodic, seed=31, boundary_frac=0.25)
+    old, pos = _moved(sc, amp, seed=40)
+    i_old, i_new, missed = O.missed_pairs(sc.grid, sc.params, old, pos, max_neibs=M_CLOUD)
+    # brute force at the rebuild on the re-binned encoding
+    cell, pos2, dropped = O.rebin_f32(sc.grid, old["cell"], pos)
+    assert dropped == 0
+    r2 = B.pair_r2(sc.grid, cell, pos2)
+    two_h = np.float32(2.0 * np.float32(sc.params.h))
+    within = r2 < np.float32(two_h * two_h)
+    np.fill_diagonal(within, False)
+    typ = old["info"] >> TYPE_SHIFT
+    within &= ~((typ[:, None] == 1) & (typ[None, :] == 1))
+    in_old = np.zeros_like(within)
+    L = old["lists"]
+    for i in range(sc.n):
+        in_old[i, L.fluid(i)] = True
+        in_old[i, L.boundary(i)] = True
+    assert i_new == int(within.sum())
+    assert missed == int((within & ~in_old).sum())
+    assert i_old == int((within & in_old).sum())
+    if amp <= 0.05:
+        assert missed == 0      # well inside the skin (0.1 x 2h = 0.26 dp)
+    else:
+        assert missed > 0
+
+
+def test_nonfinite_count_of_the_build():
+    sc = S.random_cloud(n=300, box=(0.2, 0.2, 0.2), dp=0.02, seed=3)
+    pos, vel = sc.pos.copy(), sc.vel.copy()
+    vel[5, 3] = np.nan       # density
+    vel[9, 0] = np.inf       # velocity
+    pos[11, 3] = -np.inf     # mass
+    pos[17, 1] = np.nan      # offset (also dropped by the re-binning)
+    vel[17, 2] = np.nan      # the same particle counts once
+    b = O.build_f32(sc.grid, sc.params, sc.cell, pos, vel, sc.info)
+    assert b["nonfinite"] == 4 and b["dropped"] == 1
