@@ -136,7 +136,7 @@ def test_edge_empty_and_single():
     sim.step()
     torch_sync()
     st = sim.status_host()
-    assert st == {"n_active": 1, "max_neibs": 0, "overflow": 0, "dropped": 0}
+    assert st == {"n_active": 1, "max_neibs": 0, "overflow": 0, "dropped": 0, "nonfinite": 0}
     # free fall of the lone particle: midpoint is exact for constant g
     sc0 = S.random_cloud(n=1, box=(0.2, 0.2, 0.2), dp=0.02, seed=1, boundary_frac=0.0)
     dt = sim.time
@@ -152,7 +152,7 @@ def test_edge_empty_and_single():
     sim2.build()
     sim2.forces()
     torch_sync()
-    assert sim2.status_host() == {"n_active": 0, "max_neibs": 0, "overflow": 0, "dropped": 0}
+    assert sim2.status_host() == {"n_active": 0, "max_neibs": 0, "overflow": 0, "dropped": 0, "nonfinite": 0}
 
 
 def test_dropped_particles_and_ragged_capacity():
