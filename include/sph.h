@@ -74,7 +74,9 @@ typedef enum {
     SPH_OK = 0,
     SPH_ERR_ARG = 1,        /* invalid argument or shape; nothing launched */
     SPH_ERR_WORKSPACE = 2,  /* workspace missing or smaller than required */
-    SPH_ERR_HIP = 3         /* a HIP runtime call or launch failed */
+    SPH_ERR_HIP = 3,        /* a HIP runtime call or launch failed */
+    SPH_ERR_SCRATCH = 4     /* the problem needs more device scratch than the
+                               fixed maximum of sph_forces_noalloc */
 } sph_status;
 
 /* Device status word written by sph_build_neighbors: int32[SPH_STATUS_WORDS]. */
@@ -300,6 +302,29 @@ sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_
 
 /* Bytes of device workspace sph_forces needs (n_cells: cells of the grid). */
 size_t sph_forces_workspace_bytes(int32_t capacity, int32_t n_cells);
+
+/* Bytes of the fixed device scratch of sph_forces_noalloc (64 MiB). */
+#define SPH_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* sph_forces for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same derivatives, from the same kernels, with the workspace taken from a
+ * fixed scratch array of SPH_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each device it runs on (from module load to the end of the process).
+ * Arguments are those of sph_forces without the workspace; the caller still
+ * passes inputs and outputs.  The call allocates nothing: no hipMalloc, no
+ * hipFree, no allocating library routine; the first call on a device looks
+ * up the scratch array's device address (hipGetSymbolAddress) and keeps it.
+ * Every call on a device shares that device's scratch, which keeps the last
+ * call's contents (no result depends on them); calls that overlap on one
+ * device, on different streams, race and must not be issued.
+ * Errors: those of sph_forces, and SPH_ERR_SCRATCH, before any device call,
+ * when sph_forces_workspace_bytes(parts->capacity, cells of the grid)
+ * exceeds SPH_NOALLOC_SCRATCH_BYTES (about 7.7M particles at 1M cells). */
+sph_status sph_forces_noalloc(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
+                              const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
+                              const int32_t *cell_start, const int32_t *cell_end,
+                              const uint16_t *neibs_brick, float *forces, void *stream);
 
 /* Explicit midpoint predictor/corrector (section "Code structure": phases
  * with dt/2 and dt).  d_dt: device double, the step.

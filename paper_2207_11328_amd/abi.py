@@ -17,7 +17,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 # the in-tree build, and only that one
 LIB_PATH = os.path.join(PKG, "libsph.so")
 
-SPH_OK, SPH_ERR_ARG, SPH_ERR_WORKSPACE, SPH_ERR_HIP = 0, 1, 2, 3
+SPH_OK, SPH_ERR_ARG, SPH_ERR_WORKSPACE, SPH_ERR_HIP, SPH_ERR_SCRATCH = 0, 1, 2, 3, 4
+NOALLOC_SCRATCH_BYTES = 64 << 20
 STATUS_N_ACTIVE, STATUS_MAX_NEIBS, STATUS_OVERFLOW, STATUS_DROPPED, STATUS_NONFINITE = 0, 1, 2, 3, 4
 STATUS_WORDS = 8
 NEIB_INDEX_BITS = 26
@@ -29,6 +30,7 @@ EXPORTS = [
     "sph_dt_workspace_bytes", "sph_step_dt", "sph_count_interactions", "sph_integrate_backward",
     "sph_forces_backward_workspace_bytes", "sph_forces_backward", "sph_unpermute",
     "sph_diagnostics_workspace_bytes", "sph_reduce_diagnostics", "sph_count_missed_pairs",
+    "sph_forces_noalloc",
 ]
 
 
@@ -95,6 +97,8 @@ def _load():
     L.sph_count_interactions.restype = st
     L.sph_count_missed_pairs.argtypes = [P, P, P, P, P, i32, i32, P, P]
     L.sph_count_missed_pairs.restype = st
+    L.sph_forces_noalloc.argtypes = [P, P, P, P, P, i32, P, P, P, P, P]
+    L.sph_forces_noalloc.restype = st
     L.sph_integrate_backward.argtypes = [P, i32, P, P, P, P, P, P, P, P]
     L.sph_integrate_backward.restype = st
     L.sph_forces_backward_workspace_bytes.argtypes = [i32, i32]
@@ -213,6 +217,13 @@ def sph_forces(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, nei
                          int(max_neibs), ptr(cell_start), ptr(cell_end), ptr(neibs_brick), ptr(forces),
                          ptr(workspace), workspace.numel() * workspace.element_size(), stream_ptr(stream)),
           "sph_forces")
+
+
+def sph_forces_noalloc(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count, max_neibs: int,
+                       forces, stream=None, cell_start=None, cell_end=None, neibs_brick=None):
+    check(lib.sph_forces_noalloc(C.byref(grid), C.byref(params), C.byref(parts), ptr(neibs), ptr(neib_count),
+                                 int(max_neibs), ptr(cell_start), ptr(cell_end), ptr(neibs_brick), ptr(forces),
+                                 stream_ptr(stream)), "sph_forces_noalloc")
 
 
 def sph_integrate(params: SphParams, stage: int, d_dt, state_n: SphParticles, vel_star, forces,

@@ -12,9 +12,20 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <mutex>
+
 #include "forces_common.h"
 
 using namespace sph;
+
+// Device scratch of the allocation-free entry point sph_forces_noalloc: it
+// holds the workspace of sph_forces (equation-of-state terms, brick list and
+// counters, cell flags) for problems whose sph_forces_workspace_bytes is at
+// most SPH_NOALLOC_SCRATCH_BYTES.  Each device the library runs on holds its
+// own copy from module load to the end of the process.  Host code never uses
+// this name as an address: the device address comes from
+// hipGetSymbolAddress, once per device (noalloc_scratch below).
+static __device__ __align__(256) unsigned char scratch[SPH_NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -150,6 +161,26 @@ bool common_args(const sph_grid *g, const sph_params *p, const sph_particles *pa
 
 size_t aux_bytes(int64_t capacity) { return (size_t)((sizeof(float2) * capacity + 255) & ~(int64_t)255); }
 
+// Device address of `scratch` on the current device, looked up on the first
+// call on that device (with it current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+sph_status noalloc_scratch(void **out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return SPH_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SPH_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SPH_OK;
+}
+
 }  // namespace
 
 extern "C" size_t sph_forces_workspace_bytes(int32_t capacity, int32_t n_cells)
@@ -264,4 +295,24 @@ extern "C" sph_status sph_count_missed_pairs(const sph_grid *grid, const sph_par
     if (phase == 1) k_missed_finish<<<1, 1, 0, s>>>(d_missed);
     SPH_CHECK_LAUNCH();
     return SPH_OK;
+}
+
+extern "C" sph_status sph_forces_noalloc(const sph_grid *grid, const sph_params *params,
+                                         const sph_particles *parts, const uint32_t *neibs,
+                                         const uint32_t *neib_count, int32_t max_neibs, const int32_t *cell_start,
+                                         const int32_t *cell_end, const uint16_t *neibs_brick, float *forces,
+                                         void *stream)
+{
+    if (!grid || !params || !parts) return SPH_ERR_ARG;
+    if (parts->capacity < 0 || parts->capacity > SPH_MAX_CAPACITY) return SPH_ERR_ARG;
+    const int64_t n_cells = (int64_t)grid->ncell[0] * grid->ncell[1] * grid->ncell[2];
+    if (n_cells <= 0 || n_cells > INT32_MAX - 1) return SPH_ERR_ARG;
+    // the size check comes before any device call
+    if (sph_forces_workspace_bytes(parts->capacity, (int32_t)n_cells) > (size_t)SPH_NOALLOC_SCRATCH_BYTES)
+        return SPH_ERR_SCRATCH;
+    void *ws = nullptr;
+    const sph_status st = noalloc_scratch(&ws);
+    if (st != SPH_OK) return st;
+    return sph_forces(grid, params, parts, neibs, neib_count, max_neibs, cell_start, cell_end, neibs_brick, forces,
+                      ws, (size_t)SPH_NOALLOC_SCRATCH_BYTES, stream);
 }

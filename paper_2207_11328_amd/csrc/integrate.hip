@@ -326,6 +326,9 @@ extern "C" const char *sph_status_string(sph_status st)
     case SPH_ERR_ARG: return "SPH_ERR_ARG: invalid argument or shape";
     case SPH_ERR_WORKSPACE: return "SPH_ERR_WORKSPACE: workspace missing or too small";
     case SPH_ERR_HIP: return "SPH_ERR_HIP: HIP launch or runtime failure";
+    case SPH_ERR_SCRATCH:
+        return "SPH_ERR_SCRATCH: the problem needs more than the fixed device scratch of sph_forces_noalloc "
+               "(SPH_NOALLOC_SCRATCH_BYTES)";
     }
     return "SPH: unknown status";
 }
