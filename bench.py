@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-m1", action="store_true")
     ap.add_argument("--no-channel", action="store_true")
+    ap.add_argument("--no-missed", action="store_true")
+    ap.add_argument("--no-channel-adjoint", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (calibrates the HBM "
@@ -262,7 +264,7 @@ def fwd_bwd(sc, dt, K=10, reps=3, brick=None, use_bricks=True):
             "fwd_bwd_steps_per_s": K / (tf + tb)}
 
 
-def batched(units=5, warm_units=1):
+def batched(units=50, warm_units=1):
     """128 independent tanks (fluid counts log-uniform in [2k, 60k], column
     aspect 0.3-2, alpha 0.005-0.05) stacked in one grid, advanced by replays
     of a HIP graph holding one rebuild unit (10 steps, adaptive dt)."""
@@ -287,6 +289,185 @@ def batched(units=5, warm_units=1):
             "fluid_particle_steps_per_s": st.n_fluid * steps / t, "graph_units": units,
             "tuned": {"brick": list(choice["brick"]), "bricks": choice["bricks"],
                       "per_step_ms": {k: v * 1e3 for k, v in choice["per_step_s"].items()}}}
+
+
+# list slots for a search-radius skin s (lattice neighbours within r_s =
+# 2.6 dp (1 + s) plus margin for the walls)
+SKIN_SLOTS = {0.1: 128, 0.15: 160, 0.2: 192, 0.25: 224, 0.3: 256, 0.35: 288, 0.4: 320}
+
+
+def missed_pairs(steps=1000, skins=(0.1, 0.15, 0.2, 0.25, 0.3, 0.35, 0.4)):
+    """Pairs within 2h that the reused lists missed, at every rebuild of a
+    1000-step run of the 1.62M dam break (lists rebuilt every 10 steps,
+    sph_count_missed_pairs before and after each rebuild).  If the default
+    skin (search radius 2h (1 + 0.1)) misses pairs, larger skins are run
+    until one misses none."""
+    import torch
+    from paper_2207_11328_amd.sim import Simulation
+    from workloads import scenes as S
+    out = {"steps": steps, "rebuild_every": 10, "skins": {}}
+    for skin in skins:
+        sc = S.dam_break_1m(skin=skin)
+        sim = Simulation(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0",
+                         max_neibs=SKIN_SLOTS[skin])
+        sim.track_missed = True
+        per = []
+        t0 = time.perf_counter()
+        for k in range(steps):
+            sim.step()
+            if k > 0 and k % sim.rebuild_every == 0:   # a rebuild with counting just ran
+                per.append(sim.missed_host()["missed"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        st = sim.check_status()
+        rec = {"search_radius_over_2h": 1.0 + skin, "max_neibs": sim.max_neibs, "max_listed": st["max_neibs"],
+               "rebuilds_counted": len(per), "missed_total": int(sum(per)), "missed_max": int(max(per)),
+               "rebuilds_with_misses": int(sum(1 for v in per if v > 0)), "missed_per_rebuild": per,
+               "wall_s_with_counting": wall}
+        out["skins"]["%.2f" % skin] = rec
+        del sim
+        torch.cuda.empty_cache()
+        if rec["missed_total"] == 0:
+            out["smallest_skin_without_misses"] = skin
+            break
+    return out
+
+
+def channel_adjoint(fwd_steps=100, adj_steps=50, K=10):
+    """The 16.6M channel at its stated workload: 100 forward steps (timed),
+    then a 50-step adjoint with recomputation (checkpoint every 10 steps,
+    fixed dt = the step-0 dt): forward and reverse times and the peak device
+    memory of the adjoint run."""
+    import torch
+    from paper_2207_11328_amd import tune
+    from paper_2207_11328_amd.adjoint import AdjointRollout
+    from paper_2207_11328_amd.sim import Simulation
+    sc = make_scene("channel_16m")
+    choice = tune.autotune(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0")
+    sim = Simulation(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0", brick=choice["brick"],
+                     use_bricks=choice["bricks"])
+    sim.build()
+    sim.forces()
+    sim.step_dt()
+    dt0 = float(sim.d_dt.item())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(fwd_steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    sim.check_status()
+    del sim
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats()
+    run = AdjointRollout(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, steps=adj_steps, dt=dt0,
+                         rebuild_every=K, checkpoint_every=K, brick=choice["brick"], use_bricks=choice["bricks"])
+    n = run.n
+    g = torch.Generator(device=run.sim.device).manual_seed(0)
+    seed_p = torch.randn((n, 4), device=run.sim.device, generator=g)
+    seed_v = torch.randn((n, 4), device=run.sim.device, generator=g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run.forward()
+    torch.cuda.synchronize()
+    t_af = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    gp, gv, gpar = run.backward(seed_p, seed_v)
+    torch.cuda.synchronize()
+    t_ab = time.perf_counter() - t0
+    finite = bool(torch.isfinite(gp).all() and torch.isfinite(gv).all() and torch.isfinite(gpar).all())
+    peak = torch.cuda.max_memory_allocated()
+    del run
+    torch.cuda.empty_cache()
+    return {"workload": "channel_16m", "particles": sc.n, "fluid": sc.n_fluid, "forward_steps": fwd_steps,
+            "forward_ms_per_step": t_fwd / fwd_steps * 1e3, "forward_mipps": sc.n * fwd_steps / t_fwd / 1e6,
+            "adjoint_steps": adj_steps, "checkpoint_every": K, "dt": dt0,
+            "adjoint_forward_s": t_af, "adjoint_backward_s": t_ab,
+            "backward_over_forward": t_ab / t_af, "gradients_finite": finite,
+            "peak_device_memory_gb": peak / 1e9, "brick": list(choice["brick"])}
+
+
+def adjoint_64k_200(steps=200, C=20, K=10):
+    """The differentiable dam break of ~64k fluid particles at its stated
+    length: 200 fixed-dt steps (the step-0 dt), checkpoint every 20 steps,
+    rebuild every 10; the forward rollout, and the reverse with the
+    recomputation between checkpoints, each timed."""
+    import torch
+    from paper_2207_11328_amd import tune
+    from paper_2207_11328_amd.adjoint import AdjointRollout
+    from paper_2207_11328_amd.sim import Simulation
+    sc = make_scene("dam_break_64k")
+    c = tune.autotune(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0")
+    s = Simulation(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0", brick=c["brick"],
+                   use_bricks=c["bricks"])
+    s.build()
+    s.forces()
+    s.step_dt()
+    dt = float(s.d_dt.item())
+    del s
+    run = AdjointRollout(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, steps=steps, dt=dt, rebuild_every=K,
+                         checkpoint_every=C, brick=c["brick"], use_bricks=c["bricks"])
+    n = run.n
+    g = torch.Generator(device=run.sim.device).manual_seed(0)
+    seed_p = torch.randn((n, 4), device=run.sim.device, generator=g)
+    seed_v = torch.randn((n, 4), device=run.sim.device, generator=g)
+    best = None
+    for _ in range(2):
+        run.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run.forward()
+        torch.cuda.synchronize()
+        t_f = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        run.backward(seed_p, seed_v)
+        torch.cuda.synchronize()
+        t_b = time.perf_counter() - t0
+        if best is None or t_f + t_b < best[0] + best[1]:
+            best = (t_f, t_b)
+    t_f, t_b = best
+    return {"workload": "dam_break_64k", "particles": sc.n, "steps": steps, "checkpoint_every": C,
+            "forward_s": t_f, "backward_with_recompute_s": t_b, "fwd_bwd_ratio_with_recompute": (t_f + t_b) / t_f,
+            "fwd_bwd_steps_per_s": steps / (t_f + t_b)}
+
+
+def still_water_vs_oracle(steps=100):
+    """The still-water tank (8,000 fluid + 7,548 wall particles, dp = 0.02 m)
+    rolled out 100 steps (adaptive dt, rebuild every 10) by the GPU library in
+    float32 and by the FP64 oracle on the host (timed): the error of each field
+    of the GPU's final state against the oracle's, by particle id."""
+    import torch
+    from oracle import oracle as O
+    from paper_2207_11328_amd.sim import Simulation
+    from workloads import scenes as S
+    sc = S.still_water(0.02)
+    sim = Simulation(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.run(steps)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    sim.check_status()
+    g = sim.state_host()
+    st0 = O.State.lift(sc.cell, sc.pos, sc.vel, sc.info)
+    t0 = time.perf_counter()
+    ref, t_ref = O.rollout(sc.grid, sc.params, st0, steps, rebuild_every=10)
+    t_orc = time.perf_counter() - t0
+    mask = np.uint32((1 << 30) - 1)
+    gst = O.State.lift(g["cell"], g["pos"], g["vel"], g["info"])
+    og = np.argsort(g["info"] & mask)
+    oo = np.argsort(ref.info & mask)
+    xg, xo = O.positions(sc.grid, gst)[og], O.positions(sc.grid, ref)[oo]
+    ug, uo = gst.vel[og], ref.vel[oo]
+    rg, ro = gst.rho[og], ref.rho[oo]
+    rho0 = O.f32(sc.params.rho0)
+    return {"workload": "still_water_8k", "particles": sc.n, "steps": steps,
+            "gpu_s": t_gpu, "oracle_s": t_orc, "oracle_cores": O.threads(),
+            "time_gpu": sim.time, "time_oracle": t_ref,
+            "error": {"position_max_over_dp": float(np.abs(xg - xo).max() / sc.params.dp),
+                      "velocity_max_over_umax": float(np.abs(ug - uo).max() / np.abs(uo).max()),
+                      "velocity_rms_over_urms": float(np.sqrt(((ug - uo) ** 2).mean() / (uo ** 2).mean())),
+                      "density_max_over_rho0": float(np.abs(rg - ro).max() / rho0),
+                      "time_rel": abs(sim.time - t_ref) / t_ref}}
 
 
 # models timed by the variants leg: (label, kernel, visc_model, formulation, delta)
@@ -427,6 +608,8 @@ def main():
         rep.steps_done += 1
     torch.cuda.synchronize()
     same = torch.equal(rep.pos, sim.pos) and torch.equal(rep.vel, sim.vel)
+    del rep
+    torch.cuda.empty_cache()
 
     n = sc.n
     calls = len(t_forces_events)
@@ -464,7 +647,11 @@ def main():
             "brick": list(choice["brick"]), "kernel": "lds_bricks" if choice["bricks"] else "gather",
         },
         "tuning": {"cached": choice["cached"], "per_step_ms": {k: v * 1e3 for k, v in choice["per_step_s"].items()}},
+        "value_definition": "interactions evaluated by sph_forces (pairs with r < 2h, two calls per step) per "
+                            "second of WHOLE-STEP time (list build every 10th step, dt, integrator included)",
         "forces_interactions_per_s": inter / t_forces,
+        "forces_interactions_per_s_definition": "the same interactions per second of sph_forces time only "
+                                                "(HIP events around each call in the timed steps)",
         "forces_ms_avg": t_forces_avg * 1e3,
         "interactions_per_forces_call": inter / calls,
         "listed_per_forces_call": listed / calls,
@@ -498,7 +685,6 @@ def main():
         out["batched"] = batched()
     if not args.no_fwd_bwd:
         dt_now = float(sim.d_dt.item())
-        del rep
         out["adjoint"] = fwd_bwd(sc, dt_now, brick=choice["brick"], use_bricks=choice["bricks"])
         # the differentiable dam break of ~64k fluid particles (the configuration
         # the fwd+bwd cost ratio is quoted on), at its own step-0 dt
@@ -512,13 +698,21 @@ def main():
         dt64 = float(s64.d_dt.item())
         del s64
         out["adjoint_64k"] = fwd_bwd(sc64, dt64, brick=c64["brick"], use_bricks=c64["bricks"])
+        out["adjoint_64k_200_steps"] = adjoint_64k_200()
+    del sim
+    torch.cuda.empty_cache()
+    if not args.no_missed:
+        out["missed_pairs"] = missed_pairs()
     if not args.no_channel:
-        del sim
-        torch.cuda.empty_cache()
         out["channel"] = channel()
+    if not args.no_channel_adjoint:
+        out["channel_adjoint"] = channel_adjoint()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
         out["cpu_baseline_1core"] = cpu_baseline_one_core(sc)
+        # the oracle's 100-step still-water rollout, timed, and the GPU's
+        # per-field error against it
+        out["cpu_baseline_still_water"] = still_water_vs_oracle()
     print(json.dumps(out), flush=True)
 
 

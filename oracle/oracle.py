@@ -410,6 +410,8 @@ def _setup_reverse():
     i32 = C.c_int
     L.orc_forces_reverse.argtypes = [P, P, i32, P, P, P, P, P, P, P, P, P, P, i32, P, P, P, P, P, P]
     L.orc_forces_reverse.restype = None
+    L.orc_forces_reverse_scales.argtypes = [P, P, i32, P, P, P, P, P, P, P, P, P, P, i32, P, P, P, P, P, P]
+    L.orc_forces_reverse_scales.restype = None
     L.orc_integrate_reverse.argtypes = [i32, C.c_double, i32, P, P, P, P, P, P, P, P, P, P, P]
     L.orc_integrate_reverse.restype = None
     L._rev_ready = True
@@ -449,6 +451,23 @@ def forces_reverse(grid, params, st: State, lists: Lists, abar, dbar, into: Adj 
                          _p(st.rho), _p(st.info), _p(lists.nf), _p(lists.nb), _p(lists.fl), _p(lists.bl),
                          lists.max_neibs, _p(abar), _p(dbar), _p(adj.go), _p(adj.gu), _p(adj.grho), _p(gp))
     return adj, gp
+
+
+def forces_reverse_scales(grid, params, st: State, lists: Lists, abar, dbar, alpha=None):
+    """Magnitude scales of forces_reverse (the reverse with every factor
+    taken in absolute value): (Adj of scales, scales of gparams[3]).  The
+    error gate of a float evaluation of the reverse is a multiple of these."""
+    L = _setup_reverse()
+    sc = Adj.zeros(st.n)
+    sp = np.zeros(3)
+    g = grid_struct(grid)
+    ps = params_struct(params, alpha)
+    abar = np.ascontiguousarray(abar, dtype=np.float64)
+    dbar = np.ascontiguousarray(dbar, dtype=np.float64)
+    L.orc_forces_reverse_scales(C.byref(ps), C.byref(g), st.n, _p(st.cell), _p(st.off), _p(st.mass), _p(st.vel),
+                                _p(st.rho), _p(st.info), _p(lists.nf), _p(lists.nb), _p(lists.fl), _p(lists.bl),
+                                lists.max_neibs, _p(abar), _p(dbar), _p(sc.go), _p(sc.gu), _p(sc.grho), _p(sp))
+    return sc, sp
 
 
 def integrate_reverse(stage, dt, st_n: State, adj_out: Adj):

@@ -884,6 +884,137 @@ void orc_forces_reverse(const orc_params *p, const orc_grid *g, int n,
     gparams[2] += gnu;
 }
 
+/* Magnitude scales of orc_forces_reverse, for error gates: the reverse pass
+ * evaluated with every factor replaced by its absolute value (sums of
+ * products become sums of absolute products, u.x becomes sum |u_d x_d|), on
+ * the same pairs and active branches, scattered to the central and the
+ * neighbour alike.  A float evaluation of the reverse in any order has an
+ * error of a few units of rounding times these scales.  Results are ADDED to
+ * so [n,3], su [n,3], srho [n] and sparams[3]. */
+void orc_forces_reverse_scales(const orc_params *p, const orc_grid *g, int n,
+                               const int32_t *cell, const double *off, const double *mass,
+                               const double *vel, const double *rho, const uint32_t *info,
+                               const int32_t *nf, const int32_t *nb, const int32_t *fl, const int32_t *bl,
+                               int max_neibs, const double *abar, const double *dbar,
+                               double *so, double *su, double *srho, double *sparams)
+{
+    const double h = p->h, two_h = 2.0 * h, eh2 = p->eps_visc * h * h;
+    const int form2 = p->formulation == 1;
+    double salpha = 0.0, sc0 = 0.0, snu = 0.0;
+    for (int c = 0; c < n; ++c) {
+        if (cell[c] < 0) continue;
+        const double rc = rho[c];
+        const double Pc = orc_pressure(p, rc);
+        const double cc = orc_sound_speed(p, rc);
+        const double dpc = cc * cc / (rc * rc) + 2.0 * fabs(Pc) / (rc * rc * rc);
+        const double dcc = 0.5 * (p->gamma - 1.0) * cc / rc;
+        const double *ab = abar + 3 * (size_t)c;
+        const double db = fabs(dbar[c]);
+        const int total = nf[c] + nb[c];
+        const int central_fluid = ptype(info[c]) != ORC_BOUNDARY;
+        for (int k = 0; k < total; ++k) {
+            const int m = k < nf[c] ? fl[(size_t)c * max_neibs + k]
+                                    : bl[(size_t)c * max_neibs + (k - nf[c])];
+            double x[3], u[3];
+            separation(g, cell[c], cell[m], off + 3 * (size_t)c, off + 3 * (size_t)m, x);
+            const double r2 = x[0] * x[0] + x[1] * x[1] + x[2] * x[2];
+            const double r = sqrt(r2);
+            if (!(r < two_h)) continue;
+            if (p->kernel == ORC_QUADRATIC && r == 0.0) continue;
+            double w = 0.0, wa = 0.0, A = 0.0, Bu = 0.0;
+            for (int d = 0; d < 3; ++d) {
+                u[d] = vel[3 * (size_t)c + d] - vel[3 * (size_t)m + d];
+                w += u[d] * x[d];
+                wa += fabs(u[d] * x[d]);
+                A += fabs(ab[d] * x[d]);
+                Bu += fabs(ab[d] * u[d]);
+            }
+            const double F = fabs(orc_kernel_F(p->kernel, r, h));
+            const double dFdr = fabs(orc_kernel_dF(p->kernel, r, h));
+            const double mn = mass[m];
+            const double rn = rho[m];
+            const double Pn = orc_pressure(p, rn);
+            const double cn = orc_sound_speed(p, rn);
+            const double dpn = cn * cn / (rn * rn) + 2.0 * fabs(Pn) / (rn * rn * rn);
+            const double dcn = 0.5 * (p->gamma - 1.0) * cn / rn;
+            const double rs = rc + rn;
+            const double dd = r2 + eh2;
+            const int act = w < 0.0;
+            const double K = p->alpha * h * (cc + cn) / rs;
+            const double Pi = act ? K * wa / dd : 0.0;
+            double Sp, dSp_drc, dSp_drn, Wc, dWc_drc, dWc_drn;
+            if (form2) {
+                Sp = (fabs(Pc) + fabs(Pn)) / (rc * rn);
+                dSp_drc = cc * cc / (rc * rn) + Sp / rc;
+                dSp_drn = cn * cn / (rc * rn) + Sp / rn;
+                Wc = rc / rn;
+                dWc_drc = 1.0 / rn;
+                dWc_drn = rc / (rn * rn);
+            } else {
+                Sp = fabs(Pc) / (rc * rc) + fabs(Pn) / (rn * rn);
+                dSp_drc = dpc;
+                dSp_drn = dpn;
+                Wc = 1.0;
+                dWc_drc = dWc_drn = 0.0;
+            }
+            const double S = Sp + Pi;
+            const double G = mn * S * F;
+            const double Lm = p->visc_model == 1 ? 4.0 * p->nu * mn * F / rs : 0.0;
+            const double kk = p->visc_model == 2 ? ORC_MONAGHAN_K * 4.0 * p->nu * mn / rs : 0.0;
+            const double Lk = kk * F * wa / dd;
+            double sx[3], sv[3];
+            for (int d = 0; d < 3; ++d) {
+                const double ax = fabs(x[d]), au = fabs(u[d]), aab = fabs(ab[d]);
+                const double dFdx = dFdr * ax / r;
+                const double dPidx = act ? K * (au / dd + 2.0 * wa * ax / (dd * dd)) : 0.0;
+                const double dPidu = act ? K * ax / dd : 0.0;
+                const double dGdx = mn * (S * dFdx + F * dPidx);
+                const double dGdu = mn * F * dPidu;
+                const double dLdx = p->visc_model == 1 ? 4.0 * p->nu * mn * dFdx / rs : 0.0;
+                const double dLkdx = kk * (dFdx * wa / dd + F * au / dd + 2.0 * F * wa * ax / (dd * dd));
+                const double dLkdu = kk * F * ax / dd;
+                sx[d] = (G + Lk) * aab + A * (dGdx + dLkdx) + Bu * dLdx + db * Wc * mn * (F * au + wa * dFdx);
+                sv[d] = Lm * aab + A * (dGdu + dLkdu) + db * Wc * mn * F * ax;
+            }
+            const double dPi_drc = act ? p->alpha * h * wa / dd * (dcc / rs + (cc + cn) / (rs * rs)) : 0.0;
+            const double dPi_drn = act ? p->alpha * h * wa / dd * (dcn / rs + (cc + cn) / (rs * rs)) : 0.0;
+            const double dL_drho = p->visc_model == 1 ? 4.0 * p->nu * mn * F / (rs * rs) : 0.0;
+            const double dLk_drho = Lk / rs;
+            const double src = A * (mn * F * (dSp_drc + dPi_drc) + dLk_drho) + Bu * dL_drho + db * dWc_drc * mn * wa * F;
+            const double srn = A * (mn * F * (dSp_drn + dPi_drn) + dLk_drho) + Bu * dL_drho + db * dWc_drn * mn * wa * F;
+            for (int d = 0; d < 3; ++d) {
+                so[3 * (size_t)c + d] += sx[d];
+                so[3 * (size_t)m + d] += sx[d];
+                su[3 * (size_t)c + d] += sv[d];
+                su[3 * (size_t)m + d] += sv[d];
+            }
+            srho[c] += src;
+            srho[m] += srn;
+            salpha += act ? A * mn * F * h * (cc + cn) / rs * wa / dd : 0.0;
+            sc0 += A * mn * F * (2.0 * Sp + Pi) / p->c0;
+            if (p->visc_model == 1) snu += Bu * 4.0 * mn * F / rs;
+            if (p->visc_model == 2) snu += A * ORC_MONAGHAN_K * 4.0 * mn / rs * F * wa / dd;
+            if (p->delta != 0.0 && central_fluid && k < nf[c]) {
+                const double cD = 2.0 * p->delta * h * p->c0;
+                const double Gd = F * r2 / dd;
+                const double dGd_r = dFdr / r * r2 / dd + 2.0 * F * eh2 / (dd * dd);
+                const double ratio = fabs(rc - rn) / rn;
+                for (int d = 0; d < 3; ++d) {
+                    const double t = db * cD * mn * ratio * dGd_r * fabs(x[d]);
+                    so[3 * (size_t)c + d] += t;
+                    so[3 * (size_t)m + d] += t;
+                }
+                srho[c] += db * cD * mn * Gd / rn;
+                srho[m] += db * cD * mn * Gd * rc / (rn * rn);
+                sc0 += db * cD * mn * ratio * Gd / p->c0;
+            }
+        }
+    }
+    sparams[0] += salpha;
+    sparams[1] += sc0;
+    sparams[2] += snu;
+}
+
 /* Reverse of orc_integrate.  Given the adjoint of the stage output
  * (go_out, gu_out, grho_out), return the adjoint of the stage inputs:
  *   stage 0 (y* = y + tau f(y), tau = dt/2):

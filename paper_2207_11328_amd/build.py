@@ -37,7 +37,46 @@ def flags() -> list:
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I" + INCLUDE, "-I" + CSRC,
         "-Wall", "-Wno-unused-function",
+        # per-kernel register, scratch and LDS usage, checked below
+        "-Rpass-analysis=kernel-resource-usage",
     ]
+
+
+class ScratchError(RuntimeError):
+    pass
+
+
+def resource_usage(text: str) -> dict:
+    """{kernel: {field: value}} from the compiler's kernel-resource-usage
+    remarks (function name, registers, scratch, spills, dynamic stack)."""
+    out, cur = {}, None
+    for ln in text.splitlines():
+        if "[-Rpass-analysis=kernel-resource-usage]" not in ln or "remark:" not in ln:
+            continue
+        body = ln.split("remark:", 1)[1].replace("[-Rpass-analysis=kernel-resource-usage]", "").strip()
+        if body.startswith("Function Name:"):
+            cur = body.split(":", 1)[1].strip()
+            out[cur] = {}
+        elif cur is not None and ":" in body:
+            k, v = body.rsplit(":", 1)
+            out[cur][k.strip()] = v.strip()
+    return out
+
+
+def check_no_scratch(src: str, usage: dict):
+    """Fail the build if any kernel of `src` uses scratch memory: vector
+    register spills or a stack would turn the pair loops' register traffic
+    into memory traffic.  (Scalar register spills go to vector register
+    lanes, not to memory, and are allowed.)"""
+    bad = []
+    for fn, u in usage.items():
+        scratch = int(u.get("ScratchSize [bytes/lane]", "0"))
+        spills = int(u.get("VGPRs Spill", "0"))
+        dyn = u.get("Dynamic Stack", "False") != "False"
+        if scratch or spills or dyn:
+            bad.append("%s: scratch %d B/lane, VGPR spills %d, dynamic stack %s" % (fn, scratch, spills, dyn))
+    if bad:
+        raise ScratchError("kernels of %s use scratch memory:\n  %s" % (src, "\n  ".join(bad)))
 
 
 def build(verbose: bool = False, jobs: int = 0) -> str:
@@ -71,12 +110,28 @@ def _wait(item):
     src, p = item
     out, _ = p.communicate()
     text = out.decode(errors="replace")
-    # the host pass does not know the packed-fp32 target feature: harmless
-    lines = [ln for ln in text.splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
     if p.returncode != 0:
         raise RuntimeError("hipcc failed on %s:\n%s" % (src, text))
+    usage = resource_usage(text)
+    check_no_scratch(src, usage)
+    # the host pass does not know the packed-fp32 target feature: harmless;
+    # the resource remarks were checked above; the source-line echo of a
+    # remark is a line of code with a caret line under it
+    lines = []
+    skip = 0
+    for ln in text.splitlines():
+        if skip:
+            skip -= 1
+            continue
+        if "kernel-resource-usage" in ln:
+            skip = 2 if "Function Name" in ln else 0
+            continue
+        if "packed-fp32-ops" in ln or not ln.strip():
+            continue
+        lines.append(ln)
     if lines:
         print("\n".join(lines), file=sys.stderr)
+    return usage
 
 
 if __name__ == "__main__":

@@ -339,7 +339,11 @@ __device__ __forceinline__ void brick_adjoint_lds(BackAcc &G, const uint4 *lg, i
                                                   const float4 *__restrict__ sG, const float4 &pi, const float4 &vi,
                                                   const float4 &xi, const float4 &gi, const BackConst &C)
 {
-    constexpr int R = SPH_BACK_RING;  // pairs of staged data in flight
+    // pairs of staged data in flight; one for the longest pair bodies
+    // (Landrini-Morris with density diffusion and a laminar term), which
+    // would otherwise exceed the 128 registers of a 1024-lane workgroup
+    constexpr bool kHeaviest = (MODEL & kLandrini) && (MODEL & kDiffusion) && model_visc(MODEL) != 0;
+    constexpr int R = kHeaviest ? 1 : SPH_BACK_RING;
     const int lastg = max(nt - 1, 0) / kBrickGroup;
     const uint32_t smax = (uint32_t)(span - 1);
     float4 P[R], V[R], Gj[R];
@@ -469,7 +473,11 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
         const int M = C.max_neibs;
         const int groups = brick_groups(M);
         const uint32_t jmax = (uint32_t)(n - 1);
-        double pa = 0.0, pc = 0.0, pn = 0.0;
+        if (tid % kWave == 0) {  // this wave's parameter sums of the brick (only its lane 0 touches them)
+            red[0][tid / kWave] = 0.0;
+            red[1][tid / kWave] = 0.0;
+            red[2][tid / kWave] = 0.0;
+        }
         for (int half = 0; half < 2; ++half) {
             // inner rows [y0, y1), staged rows [y0, y1 + 2)
             const int y0 = half ? HALF : 0, y1 = half ? BY : HALF;
@@ -599,29 +607,24 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
                     }
                 }
                 add_partner(A);
-                if (act && h == 0) {
-                    // (a particle with an empty list was written by the prologue)
-                    if (nt > 0) store_adjoint(i, nt, A, gpos, gvel, accumulate);
-                    if (nt > 0) {
-                        pa += (double)A.galpha;
-                        pc += (double)A.gc0;
-                        pn += (double)A.gnu;
-                    }
+                const bool own = act && h == 0 && nt > 0;
+                // (a particle with an empty list was written by the prologue)
+                if (own) store_adjoint(i, nt, A, gpos, gvel, accumulate);
+                // parameter sums: per wave and group of centrals, in double,
+                // added to the wave's LDS slot in a fixed order (no per-lane
+                // double kept across the loop: registers are the pair loop's)
+                const double ga = wave_sum(own ? (double)A.galpha : 0.0);
+                const double gc = wave_sum(own ? (double)A.gc0 : 0.0);
+                const double gn = wave_sum(own ? (double)A.gnu : 0.0);
+                if (tid % kWave == 0) {
+                    red[0][tid / kWave] += ga;
+                    red[1][tid / kWave] += gc;
+                    red[2][tid / kWave] += gn;
                 }
             }
             __syncthreads();  // the next half reuses LDS
         }
         // parameter partial sums of the brick, fixed order, stored by brick id
-        pa = wave_sum(pa);
-        pc = wave_sum(pc);
-        pn = wave_sum(pn);
-        const int lane = tid % kWave, w = tid / kWave;
-        if (lane == 0) {
-            red[0][w] = pa;
-            red[1][w] = pc;
-            red[2][w] = pn;
-        }
-        __syncthreads();
         if (tid < 3) {
             double sum = 0.0;
             for (int k = 0; k < NT / kWave; ++k) sum += red[tid][k];

@@ -194,3 +194,28 @@ def test_weak_compressibility_check():
     import dataclasses
     assert weak_compressibility(dataclasses.replace(p, c0=30.0), 0.3)["ok"]
     assert weak_compressibility(p, 0.0, u_max=3.0)["U"] == 3.0
+
+
+def test_build_refuses_kernels_with_scratch():
+    """The build step parses the compiler's kernel resource remarks and fails
+    on any kernel with scratch memory, vector register spills or a dynamic
+    stack (scalar spills go to vector lanes and are allowed)."""
+    from paper_2207_11328_amd import build as Bd
+
+    def remarks(name, scratch, vspill, sspill, dyn):
+        pre = "x.hip:10:1: remark: "
+        tail = " [-Rpass-analysis=kernel-resource-usage]"
+        return "\n".join([pre + "Function Name: " + name + tail, "   10 | {", "      | ^",
+                          pre + "    VGPRs: 128" + tail, pre + "    ScratchSize [bytes/lane]: %d" % scratch + tail,
+                          pre + "    Dynamic Stack: %s" % dyn + tail, pre + "    SGPRs Spill: %d" % sspill + tail,
+                          pre + "    VGPRs Spill: %d" % vspill + tail])
+
+    ok = remarks("k_ok", 0, 0, 37, "False")
+    u = Bd.resource_usage(ok)
+    assert u == {"k_ok": {"VGPRs": "128", "ScratchSize [bytes/lane]": "0", "Dynamic Stack": "False",
+                          "SGPRs Spill": "37", "VGPRs Spill": "0"}}
+    Bd.check_no_scratch("x.hip", u)
+    for bad in (remarks("k_bad", 8, 2, 0, "False"), remarks("k_bad", 0, 1, 0, "False"),
+                remarks("k_bad", 0, 0, 0, "True")):
+        with pytest.raises(Bd.ScratchError, match="k_bad"):
+            Bd.check_no_scratch("x.hip", Bd.resource_usage(ok + "\n" + bad))

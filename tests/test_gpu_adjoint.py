@@ -2,13 +2,16 @@
 sph_integrate_backward, sph_unpermute) and of the checkpointed rollout
 gradient against the FP64 oracle reverse.
 
-Tolerances: the adjoint sums are float32 gathers of both roles of every pair;
-they are compared normwise per field (|d| <= 2e-5 max|ref|) and element-wise
-where the reference is not small (|d| <= 1e-3 |ref| where |ref| > 1e-2 max|ref|);
-the parameter derivatives are float64 block sums of float32 terms (1e-4).
+Tolerance of sph_forces_backward: the same bar as the derivatives, 1e-5 of
+the condition scale, per particle and component: |g_gpu - g_oracle| <= 1e-5
+S, where S is the oracle reverse evaluated with every factor in absolute
+value (oracle.forces_reverse_scales: the sum over the pairs of both roles of
+the magnitudes of each term's factors); a float evaluation in any order errs
+by a few units of rounding (u = 6e-8) times about the number of terms, i.e.
+well inside 1e-5 S.  The parameter derivatives (float64 sums of float32
+terms) take the same bar against their own scales.
 The 24-step rollout gradient differs from the FP64 oracle's by the float32
-trajectory error (1e-3 for alpha and c0, 1e-2 normwise for the initial
-velocities)."""
+trajectory error (bounds set from the measured agreement, with margin)."""
 import numpy as np
 import pytest
 
@@ -28,17 +31,20 @@ def _gpu():
         pytest.skip("no GPU")
 
 
-def _cmp(name, got, ref, norm_tol=2e-5, elem_tol=1e-3):
+ADJ_TOL = 1e-5
+
+
+def _cmp(name, got, ref, scale, tol=ADJ_TOL):
+    """|got - ref| <= tol scale for every element (no element left out)."""
     got = np.asarray(got, np.float64)
     ref = np.asarray(ref, np.float64)
-    m = np.abs(ref).max()
+    scale = np.asarray(scale, np.float64)
     d = np.abs(got - ref)
-    big = np.abs(ref) > 1e-2 * m
-    worst_norm = d.max() / m if m > 0 else d.max()
-    worst_el = (d[big] / np.abs(ref[big])).max() if big.any() else 0.0
-    log("%s: normwise %.2e  elementwise %.2e" % (name, worst_norm, worst_el))
-    assert worst_norm <= norm_tol, (name, worst_norm)
-    assert worst_el <= elem_tol, (name, worst_el)
+    assert np.all(np.abs(ref) <= scale * (1 + 1e-12) + 1e-300), name + ": scale below the value"
+    e = np.where(scale > 0, d / np.where(scale > 0, scale, 1.0), np.where(d > 0, np.inf, 0.0))
+    m = np.abs(ref).max()
+    log("%s: max |d|/S %.2e  (normwise |d|/max|ref| %.2e)" % (name, e.max(), d.max() / m if m > 0 else d.max()))
+    assert e.max() <= tol, (name, e.max())
 
 
 # random clouds at about lattice density with 192 slots: the gather form of
@@ -91,6 +97,8 @@ def _backward_parity(sc, M, bricks, shape, name):
     gf[:, 3] = rng.normal(size=sc.n) * 1e-3
     adj, gp = O.forces_reverse(sc.grid, sc.params, st, ob["lists"], gf[:, :3].astype(np.float64),
                                gf[:, 3].astype(np.float64))
+    scl, sp = O.forces_reverse_scales(sc.grid, sc.params, st, ob["lists"], gf[:, :3].astype(np.float64),
+                                      gf[:, 3].astype(np.float64))
     from paper_2207_11328_amd import abi
     dev = sim.device
     gforce = torch.from_numpy(gf).to(dev)
@@ -110,15 +118,16 @@ def _backward_parity(sc, M, bricks, shape, name):
     if int(getattr(sc.params, "kernel", 0)) == O.GAUSSIAN:
         # pairs at the edge of the truncated Gaussian's support (see support_edge_rows)
         edge = support_edge_rows(sc, ob)
-        assert edge.mean() < 0.01
+        log("%s: %d of %d particles within 2e-6 of 2h of a neighbour left out" % (name, edge.sum(), sc.n))
+        assert edge.mean() < 0.005
         keep = ~edge
-    _cmp(name + " dL/do", gp_gpu[keep, :3], adj.go[keep])
-    _cmp(name + " dL/du", gv_gpu[keep, :3], adj.gu[keep])
-    _cmp(name + " dL/drho", gv_gpu[keep, 3], adj.grho[keep])
+    _cmp(name + " dL/do", gp_gpu[keep, :3], adj.go[keep], scl.go[keep])
+    _cmp(name + " dL/du", gv_gpu[keep, :3], adj.gu[keep], scl.gu[keep])
+    _cmp(name + " dL/drho", gv_gpu[keep, 3], adj.grho[keep], scl.grho[keep])
     g = gparams.cpu().numpy()
-    log("%s params gpu %s oracle %s" % (name, g, gp))
+    log("%s params gpu %s oracle %s |d|/S %s" % (name, g, gp, np.abs(g - gp) / np.where(sp > 0, sp, 1.0)))
     for k in range(3):
-        assert abs(g[k] - gp[k]) <= 1e-4 * abs(gp[k]) + 1e-30, (k, g[k], gp[k])
+        assert abs(g[k] - gp[k]) <= ADJ_TOL * sp[k], (k, g[k], gp[k], sp[k])
     # accumulate mode adds to what is there; deterministic bit for bit
     gpos2 = gpos.clone()
     gvel2 = gvel.clone()
@@ -332,9 +341,10 @@ def test_rollout_gradient_matches_oracle_reverse(variant):
     assert abs(L.item() - L_o) < 1e-6
     ga, gc = alpha.grad.item(), c0.grad.item()
     log("dL/dalpha gpu %.6e oracle %.6e ; dL/dc0 gpu %.6e oracle %.6e" % (ga, gp_o[0], gc, gp_o[1]))
-    assert abs(ga - gp_o[0]) <= 1e-3 * abs(gp_o[0])
-    assert abs(gc - gp_o[1]) <= 1e-3 * abs(gp_o[1])
+    # measured: 1.1e-6 and 2.9e-6 (alpha), <= 4e-7 (c0), 1.6e-7 (u0, normwise)
+    assert abs(ga - gp_o[0]) <= 2e-5 * abs(gp_o[0])
+    assert abs(gc - gp_o[1]) <= 2e-5 * abs(gp_o[1])
     gu = vel0.grad.cpu().numpy().astype(np.float64)
     rel = np.linalg.norm(gu - adj_o.gu) / np.linalg.norm(adj_o.gu)
     log("dL/du0 relative L2 error %.3e" % rel)
-    assert rel <= 1e-2
+    assert rel <= 2e-6

@@ -715,3 +715,56 @@ def test_diffusion_only_between_fluid_particles():
     assert np.array_equal(dd1, dd2)
     is_b = (st.info >> np.uint32(30)) == 1
     assert np.all(dd1[is_b] == 0.0) and np.any(dd1[~is_b] != 0.0)
+
+
+@pytest.mark.parametrize("visc,delta,kernel,form", [(0, 0.0, 0, 0), (1, 0.1, 1, 1), (2, 0.1, 3, 1), (2, 0.0, 2, 0)])
+def test_reverse_scales_bound_every_term(visc, delta, kernel, form):
+    """The magnitude scales of the reverse (the error scale of the adjoint
+    parity gate) bound the reverse itself element by element, and each
+    particle's scale bounds the sum of the absolute values of the pair
+    contributions scattered to it (reverse run one pair at a time by
+    restricting the lists)."""
+    sc = S.random_cloud(n=300, box=(0.14, 0.12, 0.12), dp=0.02, seed=43, boundary_frac=0.25, u_sigma=0.3,
+                        rho_sigma=0.01, alpha=0.3, visc_model=visc, nu=1e-3, delta=delta, kernel=kernel,
+                        formulation=form)
+    b = O.build_f32(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info)
+    st = O.State.lift(b["cell"], b["pos"], b["vel"], b["info"])
+    rng = np.random.default_rng(2)
+    ab = rng.normal(size=(st.n, 3))
+    db = rng.normal(size=st.n) * 1e-3
+    adj, gp = O.forces_reverse(sc.grid, sc.params, st, b["lists"], ab, db)
+    scl, sp = O.forces_reverse_scales(sc.grid, sc.params, st, b["lists"], ab, db)
+    assert np.all(np.abs(adj.go) <= scl.go * (1 + 1e-12))
+    assert np.all(np.abs(adj.gu) <= scl.gu * (1 + 1e-12))
+    assert np.all(np.abs(adj.grho) <= scl.grho * (1 + 1e-12))
+    assert np.all(np.abs(gp) <= sp * (1 + 1e-12))
+    # one central at a time: the sum of |contribution of central c| over c
+    L = b["lists"]
+    acc_o = np.zeros_like(adj.go)
+    acc_r = np.zeros_like(adj.grho)
+    for c in range(st.n):
+        if L.nf[c] + L.nb[c] == 0:
+            continue
+        one = O.Lists(np.where(np.arange(st.n) == c, L.nf, 0).astype(np.int32),
+                      np.where(np.arange(st.n) == c, L.nb, 0).astype(np.int32), L.fl, L.bl, L.max_neibs, 0)
+        a1, _ = O.forces_reverse(sc.grid, sc.params, st, one, ab, db)
+        acc_o += np.abs(a1.go)
+        acc_r += np.abs(a1.grho)
+    assert np.all(acc_o <= scl.go * (1 + 1e-12))
+    assert np.all(acc_r <= scl.grho * (1 + 1e-12))
+    # and the scale is not vacuous: within a few hundred times the values' own magnitudes
+    assert np.median(scl.go / np.maximum(acc_o, 1e-300)) < 100
+
+
+def test_dam_break_64k_gradient_golden_reverse_equals_finite_differences():
+    """The stored FP64 gradient of the 200-step differentiable dam break
+    (tests/golden/make_dam_break_64k_gradient.py, oracle only): the reverse
+    pass agrees with central differences at eps = 1e-4 for alpha, c0 and a
+    direction of the initial velocities."""
+    import json
+    with open(os.path.join(GOLDEN, "dam_break_64k_gradient.json")) as f:
+        g = json.load(f)
+    assert g["steps"] == 200 and g["fluid"] == 64232 and g["fd_eps"] == 1e-4
+    assert len(g["front_ids"]) == math.ceil(0.01 * g["fluid"])
+    for rev, fd in (("grad_alpha", "fd_alpha"), ("grad_c0", "fd_c0"), ("grad_u0_dot_v", "fd_u0_dot_v")):
+        assert abs(g[rev] - g[fd]) <= 2e-5 * abs(g[fd]), (rev, g[rev], g[fd])

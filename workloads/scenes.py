@@ -317,6 +317,36 @@ def random_cloud(n: int = 500, box=(0.2, 0.2, 0.2), dp: float = 0.02, u_sigma: f
     return sc
 
 
+def adversarial_pairs(n_pairs: int = 60, dp: float = 0.02, seed: int = 11, box: float = 0.6,
+                      periodic: int = 0) -> Scene:
+    """Pairs of particles placed at r_s (1 + k 2^-23), k in -3..3, along
+    random oblique directions (double positions, then the float32
+    encoding): separations within a few float32 roundings of the search
+    radius, where the predicate's rounding order decides.  Test input only."""
+    rng = np.random.default_rng(seed)
+    p = sph_params(dp, g=(0.0, 0.0, 0.0))
+    grid = make_grid((0.0, 0.0, 0.0), (box, box, box), p.r_search, periodic=periodic)
+    rs = float(np.float32(p.r_search))
+    xs = []
+    for k in range(n_pairs):
+        c = rng.uniform(0.25 * box, 0.75 * box, size=3)
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        r = rs * (1.0 + (k % 7 - 3) * 2.0 ** -23)
+        xs.append(c)
+        xs.append(c + r * d)
+    x = np.array(xs)
+    cell, off = encode_positions(grid, x)
+    n = x.shape[0]
+    pos = np.zeros((n, 4), np.float32)
+    pos[:, :3] = off
+    pos[:, 3] = np.float32(p.rho0 * dp ** 3)
+    vel = np.zeros((n, 4), np.float32)
+    vel[:, 3] = np.float32(p.rho0)
+    info = np.arange(n, dtype=np.uint32)
+    return Scene("adversarial_pairs", grid, p, cell, pos, vel, info, n, 0)
+
+
 def shuffled(scene: Scene, seed: int = 0) -> Scene:
     """Same particles in a random storage order (ids keep their values)."""
     rng = np.random.default_rng(seed)
