@@ -196,7 +196,9 @@ int32_t sph_abi_version(void);
 size_t sph_neib_list_entries(int32_t capacity, int32_t max_neibs);
 
 /* Entries (uint16) of a brick-local neighbour list for `capacity`
- * particles: ceil(capacity / 64) * 64 * 8 * ceil(max_neibs / 8). */
+ * particles: ceil(capacity / 64) * 64 * 8 * ceil(max_neibs / 8) list
+ * entries, then the table of the bricks with a pair (capacity + 4 int32
+ * words, i.e. 2 * (capacity + 4) entries; see sph_build_neighbors). */
 size_t sph_neib_brick_entries(int32_t capacity, int32_t max_neibs);
 
 /* Brick shapes the LDS kernels support: writes up to max_shapes triples
@@ -244,7 +246,15 @@ size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells);
  *      and its one-cell halo, x fastest, then z, then y, periodic axes
  *      wrapped, cells outside a closed axis empty, then particles of a cell
  *      in sorted order;
- *      saturated at 65535.
+ *      saturated at 65535.  Behind the lists (at entry ceil(capacity / 64)
+ *      * 64 * 8 * ceil(max_neibs / 8), as int32 words) the table of the
+ *      bricks that hold a particle with a non-empty list, for the brick
+ *      form of sph_forces: [0] the number of heavy bricks (at least 12
+ *      particles per inner cell), [1 .. capacity] brick ids bx + nbx (by +
+ *      nby bz) of the grid tiled by grid->brick from cell 0, the heavy ones
+ *      from the front and the light ones from the back, [capacity + 1] the
+ *      number of light bricks, [capacity + 2 ..] reserved (capacity is at
+ *      least 1 here);
  * A particle whose neighbours exceed max_neibs keeps the first max_neibs
  * found (scan order: cells z, y, x outer to inner, then sorted index) and is
  * counted in SPH_STATUS_OVERFLOW; the lists are then unusable for physics.
@@ -283,14 +293,15 @@ sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
  * The two differ by rounding only (the separation of the brick form carries
  * an error of a few ulp of 2.5 cell sizes instead of one ulp of a cell size);
  * neither is bit-exact against the other.
- * In the brick form only bricks where some particle has a non-empty list are
- * staged; the zero derivatives of particles with an empty list are written
- * without it.
+ * In the brick form only the bricks of the build's table (those where a
+ * particle has a non-empty list) are staged, the equation of state is
+ * evaluated as particles are staged, and the zero derivatives of particles
+ * with an empty list are written without staging: no pass over the particles
+ * precedes the brick kernel.
  * workspace: device buffer of sph_forces_workspace_bytes(capacity, n_cells)
- * bytes (per-particle equation-of-state terms, the list of bricks with a
- * pair, the brick counter of the persistent brick kernel and one flag byte
- * per cell, set and cleared within every call; its contents on entry do not
- * change any result).  Calls that share a workspace must not overlap.
+ * bytes (the per-particle equation-of-state terms of the gather form and
+ * the brick counter of the persistent brick kernel, set within every call;
+ * its contents on entry do not change any result).  Calls that share a workspace must not overlap.
  * Errors: SPH_ERR_ARG (also for an unknown kernel, formulation or
  * visc_model, a negative or non-finite delta, or delta > 0 without
  * parts->info), SPH_ERR_WORKSPACE. */
@@ -320,7 +331,7 @@ size_t sph_forces_workspace_bytes(int32_t capacity, int32_t n_cells);
  * device, on different streams, race and must not be issued.
  * Errors: those of sph_forces, and SPH_ERR_SCRATCH, before any device call,
  * when sph_forces_workspace_bytes(parts->capacity, cells of the grid)
- * exceeds SPH_NOALLOC_SCRATCH_BYTES (about 7.7M particles at 1M cells). */
+ * exceeds SPH_NOALLOC_SCRATCH_BYTES (about 8.3M particles). */
 sph_status sph_forces_noalloc(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
                               const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
                               const int32_t *cell_start, const int32_t *cell_end,

@@ -31,55 +31,16 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// Cole EOS for gamma = 7 in the expanded form P = B d (7 + 21d + 35d^2 +
-// 35d^3 + 21d^4 + 7d^5 + d^6), d = (rho - rho0)/rho0 (exact expansion of
-// (1 + d)^7 - 1, full relative accuracy near rho0).  aux = (P/rho^2,
-// alpha h c / 2) with c = c0 (1 + d)^3 (aux.x = P for the Landrini-Morris
-// formulation).
-// Also (brick form): zeroes the active-brick count and the brick counter of
-// the persistent brick kernel, writes the (zero) derivatives of particles
-// with an empty list or dropped by the last build (cell < 0), and flags the
-// cells that hold a particle with a non-empty list, so that only bricks with
-// a pair are staged.
+// Equation-of-state terms of the gather form (eos_terms): aux = (P/rho^2
+// or P, alpha h c / 2) per particle.  The brick form evaluates them while it
+// stages particles in LDS and needs no such pass.
 __global__ __launch_bounds__(kThreads) void k_eos(int n, const float4 *__restrict__ vel, float2 *__restrict__ aux,
-                                                  const int32_t *__restrict__ cell,
-                                                  const float *__restrict__ cell_alpha, int cell_base, float h,
-                                                  ForceConst C, int32_t *__restrict__ active,
-                                                  int32_t *__restrict__ next, float4 *__restrict__ out,
-                                                  const uint32_t *__restrict__ count, uint8_t *__restrict__ cell_flags,
-                                                  int n_cells, int32_t *__restrict__ light)
+                                                  const int32_t *__restrict__ cell, ForceConst C)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (active && i == 0) {
-        active[0] = 0;
-        next[0] = 0;
-        light[0] = 0;
-    }
     if (i >= n) return;
-    float alpha_h = C.alpha_h;
-    if (cell_alpha || out) {
-        const int c = cell[i];
-        if (cell_alpha && c >= 0) alpha_h = cell_alpha[c - cell_base] * h;
-        if (out) {
-            const int lc = c - cell_base;
-            if (c < 0 || count[i] == 0u || (unsigned)lc >= (unsigned)n_cells)
-                out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            else
-                cell_flags[lc] = 1;
-        }
-    }
-    const float rho = vel[i].w;
-    const float d = (rho - C.rho0) * C.inv_rho0;
-    float poly = 7.0f + d;
-    poly = fmaf(poly, d, 21.0f);
-    poly = fmaf(poly, d, 35.0f);
-    poly = fmaf(poly, d, 35.0f);
-    poly = fmaf(poly, d, 21.0f);
-    poly = fmaf(poly, d, 7.0f);
-    const float P = C.B * d * poly;
-    const float inv_rho = 1.0f / rho;
-    const float a = 1.0f + d;
-    aux[i] = make_float2(C.landrini ? P : P * inv_rho * inv_rho, 0.5f * alpha_h * (C.c0 * a * a * a));
+    const float alpha_h = C.cell_alpha && cell[i] >= 0 ? alpha_h_of(i, cell, C) : C.alpha_h;
+    aux[i] = eos_terms(vel[i].w, alpha_h, C);
 }
 
 __global__ __launch_bounds__(kThreads) void k_count_interactions(int n, const float4 *__restrict__ pos,
@@ -146,6 +107,9 @@ bool make_const(const sph_grid *g, const sph_params *p, int max_neibs, ForceCons
     C.diff = (float)(2.0 * (double)p->delta * h * (double)p->c0);
     C.max_neibs = max_neibs;
     C.landrini = p->formulation == SPH_FORM_LANDRINI_MORRIS;
+    C.h = p->h;
+    C.cell_alpha = g->cell_alpha;
+    C.cell_base = g->cell_base;
     return true;
 }
 
@@ -186,11 +150,10 @@ sph_status noalloc_scratch(void **out)
 extern "C" size_t sph_forces_workspace_bytes(int32_t capacity, int32_t n_cells)
 {
     if (capacity < 0 || n_cells < 0) return 0;
-    // per-particle EOS terms, then the active-brick list (the heavy count, ids
-    // of at most one brick per cell, the brick counter, the light count) and
-    // one flag byte per cell
-    return aux_bytes(capacity > 0 ? capacity : 1) + sizeof(int32_t) * ((size_t)n_cells + 3) +
-           (((size_t)n_cells + 255) & ~(size_t)255) + 256;
+    // per-particle equation-of-state terms (gather form), then the brick
+    // counter of the persistent brick kernel
+    (void)n_cells;
+    return aux_bytes(capacity > 0 ? capacity : 1) + 256;
 }
 
 extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
@@ -212,39 +175,36 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
     const int n = parts->n;
     if (n == 0) return SPH_OK;
     hipStream_t s = (hipStream_t)stream;
-    const float4 *pos = (const float4 *)parts->pos;
-    const float4 *vel = (const float4 *)parts->vel;
     float2 *aux = (float2 *)workspace;
-    int32_t *active = (int32_t *)((char *)workspace + aux_bytes(parts->capacity > 0 ? parts->capacity : 1));
-    float4 *out = (float4 *)forces;
+    int32_t *next = (int32_t *)((char *)workspace + aux_bytes(parts->capacity > 0 ? parts->capacity : 1));
     if (grid->cell_alpha && !parts->cell) return SPH_ERR_ARG;
     const bool bricks = cell_start && cell_end && neibs_brick;
     if (bricks && !parts->cell) return SPH_ERR_ARG;
     if (bricks && ((uintptr_t)neibs_brick & 15u)) return SPH_ERR_ARG;  // read in 16-byte groups
     if ((params->delta != 0.0f) && !parts->info) return SPH_ERR_ARG;
-    uint8_t *cell_flags = (uint8_t *)(active + n_cells + 3);
-    k_eos<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, vel, aux, parts->cell, grid->cell_alpha, grid->cell_base,
-                                                       params->h, C, bricks ? active : nullptr,
-                                                       active + n_cells + 1, bricks ? out : nullptr, neib_count,
-                                                       cell_flags, (int)n_cells, active + n_cells + 2);
+    if (bricks)
+        k_zero_one<int32_t><<<1, 1, 0, s>>>(next);
+    else
+        k_eos<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, (const float4 *)parts->vel, aux, parts->cell, C);
     ForceArgs a;
     a.grid = grid;
     a.shape = shape;
     a.n = n;
-    a.pos = pos;
-    a.vel = vel;
+    a.pos = (const float4 *)parts->pos;
+    a.vel = (const float4 *)parts->vel;
     a.aux = aux;
+    a.cell = parts->cell;
     a.neibs = neibs;
     a.count = neib_count;
     a.info = parts->info;
     a.neibs_brick = neibs_brick;
     a.cell_start = cell_start;
     a.cell_end = cell_end;
-    a.active = active;
-    a.next = active + n_cells + 1;
-    a.light = active + n_cells + 2;
-    a.cell_flags = cell_flags;
-    a.out = out;
+    a.cap_ids = brick_table_cap(parts->capacity);
+    a.table = bricks ? brick_table(reinterpret_cast<const int32_t *>(neibs_brick), parts->capacity, max_neibs)
+                     : nullptr;
+    a.next = next;
+    a.out = (float4 *)forces;
     a.bricks = bricks;
     static bool (*const pairs[4])(int, const ForceArgs &, const ForceConst &, hipStream_t) = {
         forces_pairs_kernel0, forces_pairs_kernel1, forces_pairs_kernel2, forces_pairs_kernel3};

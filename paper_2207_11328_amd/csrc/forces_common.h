@@ -19,22 +19,53 @@ struct ForceConst {
     float k_four_nu;  // 4 K nu (Monaghan K form)
     float diff;       // 2 delta h c0 (density diffusion)
     int max_neibs;
-    int landrini;     // the equation-of-state prologue stores P instead of P/rho^2
+    int landrini;     // the equation-of-state terms hold P instead of P/rho^2
+    float h;          // smoothing length (per-cell alpha times h)
+    const float *cell_alpha;  // per-cell artificial-viscosity coefficient, or null
+    int cell_base;
 };
+
+// Cole equation of state for gamma = 7 in the expanded form P = B d (7 + 21d
+// + 35d^2 + 35d^3 + 21d^4 + 7d^5 + d^6), d = (rho - rho0)/rho0 (exact
+// expansion of (1 + d)^7 - 1, full relative accuracy near rho0), as the pair
+// terms use it: (P/rho^2, or P for the Landrini-Morris formulation, and
+// alpha h c / 2 with c = c0 (1 + d)^3).  One definition for every kernel that
+// needs it, so both derivative forms see bit-identical values.
+__device__ __forceinline__ float2 eos_terms(float rho, float alpha_h, const ForceConst &C)
+{
+    const float d = (rho - C.rho0) * C.inv_rho0;
+    float poly = 7.0f + d;
+    poly = fmaf(poly, d, 21.0f);
+    poly = fmaf(poly, d, 35.0f);
+    poly = fmaf(poly, d, 35.0f);
+    poly = fmaf(poly, d, 21.0f);
+    poly = fmaf(poly, d, 7.0f);
+    const float P = C.B * d * poly;
+    const float inv_rho = 1.0f / rho;
+    const float a = 1.0f + d;
+    return make_float2(C.landrini ? P : P * inv_rho * inv_rho, 0.5f * alpha_h * (C.c0 * a * a * a));
+}
+
+// alpha h of particle j: the coefficient of its cell when a per-cell table is
+// given, else the global one
+__device__ __forceinline__ float alpha_h_of(int j, const int32_t *__restrict__ cell, const ForceConst &C)
+{
+    return C.cell_alpha ? C.cell_alpha[cell[j] - C.cell_base] * C.h : C.alpha_h;
+}
 
 struct ForceArgs {
     const sph_grid *grid;
     int shape;  // brick shape index
     int n;
     const float4 *pos, *vel;
-    const float2 *aux;  // (P/rho^2 or P, alpha h c / 2) per particle
+    const float2 *aux;  // (P/rho^2 or P, alpha h c / 2) per particle (gather form)
+    const int32_t *cell;
     const uint32_t *neibs, *count, *info;
     const uint16_t *neibs_brick;
     const int32_t *cell_start, *cell_end;
-    int32_t *active;  // bricks holding particles: count, then ids
-    int32_t *next;    // brick counter of the persistent workgroups
-    int32_t *light;   // count of the light bricks, listed from the back of active
-    uint8_t *cell_flags;  // cells holding a particle with a non-empty list (set by the prologue)
+    const int32_t *table;  // bricks with a pair (brick_table layout), from the build
+    int cap_ids;           // ids of the table
+    int32_t *next;         // brick counter of the persistent workgroups (zeroed before the launch)
     float4 *out;
     bool bricks;
 };

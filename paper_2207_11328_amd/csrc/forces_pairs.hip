@@ -124,17 +124,22 @@ __device__ __forceinline__ void pair_terms(PairAcc &A, uint32_t e, const float4 
 // the list entry of pair k + s + D (requested 2 D pairs ahead).  Neighbour
 // data registers are only ever written by loads, so the loop carries no copy
 // of an in-flight value.
+// aux == nullptr: the neighbours' equation-of-state terms are evaluated from
+// their densities (eos_terms, bit-identical to the gather form's prologue).
 template <int MODEL, int D>
 __device__ __forceinline__ void gather_pairs(PairAcc &A, const uint32_t *tile, int nf, int nt, int ntw, int M,
                                              uint32_t jmax, const float4 *__restrict__ pos,
                                              const float4 *__restrict__ vel, const float2 *__restrict__ aux,
-                                             const float4 &pi, const float4 &vi, const float2 &ai,
-                                             bool central_fluid, const ForceConst &C)
+                                             const int32_t *__restrict__ cell, const float4 &pi, const float4 &vi,
+                                             const float2 &ai, bool central_fluid, const ForceConst &C)
 {
     const int last = max(nt - 1, 0);
     uint32_t e[D], en[D];
     float4 P[D], V[D];
     float2 X[D];
+    auto terms = [&](uint32_t j, const float4 &v) {
+        return aux ? aux[j] : eos_terms(v.w, alpha_h_of((int)j, cell, C), C);
+    };
 #pragma unroll
     for (int s = 0; s < D; ++s) {
         e[s] = tile[list_slot(s, nf, last, M) * kWave];
@@ -145,7 +150,7 @@ __device__ __forceinline__ void gather_pairs(PairAcc &A, const uint32_t *tile, i
         const uint32_t j = min(e[s] & kIndexMask, jmax);
         P[s] = pos[j];
         V[s] = vel[j];
-        X[s] = aux[j];
+        X[s] = terms(j, V[s]);
     }
     for (int k = 0; k < ntw; k += D) {
 #pragma unroll
@@ -155,7 +160,7 @@ __device__ __forceinline__ void gather_pairs(PairAcc &A, const uint32_t *tile, i
             const uint32_t j = min(e[s] & kIndexMask, jmax);
             P[s] = pos[j];
             V[s] = vel[j];
-            X[s] = aux[j];
+            X[s] = terms(j, V[s]);
             en[s] = tile[list_slot(k + s + 2 * D, nf, last, M) * kWave];
         }
     }
@@ -195,7 +200,8 @@ __global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__rest
     PairAcc A = {0.0f, 0.0f, 0.0f, 0.0f};
 
     const bool central_fluid = (MODEL & kDiffusion) ? ptype(info[ii]) != kBoundary : true;
-    gather_pairs<MODEL, kDepth>(A, tile + lane, nf, nt, ntw, M, jmax, pos, vel, aux, pi, vi, ai, central_fluid, C);
+    gather_pairs<MODEL, kDepth>(A, tile + lane, nf, nt, ntw, M, jmax, pos, vel, aux, nullptr, pi, vi, ai,
+                                central_fluid, C);
     if (i < n) out[i] = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
@@ -277,15 +283,14 @@ __device__ __forceinline__ void brick_pairs_lds(PairAcc &A, const uint4 *lg, int
 template <int MODEL, int BX, int BY, int BZ, int NT, int CAP>
 __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__restrict__ pos,
                                                      const float4 *__restrict__ vel,
-                                                     const float2 *__restrict__ aux,
+                                                     const int32_t *__restrict__ cell,
                                                      const uint32_t *__restrict__ neibs,
                                                      const uint16_t *__restrict__ neibs_brick,
                                                      const uint32_t *__restrict__ count,
                                                      const int32_t *__restrict__ cell_start,
                                                      const int32_t *__restrict__ cell_end,
-                                                     const int32_t *__restrict__ active,
+                                                     const int32_t *__restrict__ table, int cap_ids,
                                                      int32_t *__restrict__ next,
-                                                     const int32_t *__restrict__ light,
                                                      const uint32_t *__restrict__ info,
                                                      float4 *__restrict__ out, ForceConst C, BrickGrid G)
 {
@@ -310,10 +315,11 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     static_assert(NI <= kWave, "one lane per inner cell in the scan ahead");
 
     // One resident workgroup per CU takes the bricks with a pair one at a time
-    // from the counter `next`, heavy ones first (brick_at order): no workgroup
-    // is launched for an empty brick, the bricks' different costs even out
-    // across CUs, and the cheap bricks come last, where they fill the gaps.
-    const int n_listed = bricks_listed(active, light), cap_ids = G.nx * G.ny * G.nz;
+    // from the counter `next`, heavy ones first (brick_at order; the build's
+    // table): no workgroup is launched for an empty brick, the bricks'
+    // different costs even out across CUs, and the cheap bricks come last,
+    // where they fill the gaps.
+    const int n_listed = table[0] + table[cap_ids + 1];
     // cell range (start, count) of staged cell t < S of brick b (count 0 for a
     // cell outside a non-periodic grid edge)
     auto ranges = [&](int b, int t, int &st, int &cnt) {
@@ -348,7 +354,7 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
         kb2 = __shfl(kb2, 0);
         int total2 = 0, nc2 = 0;
         if (kb2 < n_listed) {
-            const int b2 = brick_at(active, cap_ids, kb2);
+            const int b2 = brick_at(table, cap_ids, kb2);
             constexpr int NCH = (S + kWave - 1) / kWave;
             int st[NCH], ct[NCH], ex[NCH];
 #pragma unroll
@@ -420,7 +426,7 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
             kb = sNext;
         }
         if (kb >= n_listed) break;  // uniform
-        const int b = brick_at(active, cap_ids, kb);
+        const int b = brick_at(table, cap_ids, kb);
         const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
         int *cBase = cBaseB[cur], *cDelta = cDeltaB[cur], *iBase = iBaseB[cur], *iStart = iStartB[cur];
 
@@ -503,7 +509,7 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
             for (int tb = 0; tb < L; tb += SB * kWave) {
                 int slot[SB], cc[SB], rw[SB];
                 float4 p[SB], v[SB];
-                float2 x[SB];
+                float ah[SB];  // alpha h of each loaded particle
                 bool bnd[SB];
 #pragma unroll
                 for (int u = 0; u < SB; ++u) {
@@ -534,7 +540,7 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
                     const int j = t < L ? s2 - cDelta[r * SX + c] : 0;
                     p[u] = pos[j];
                     v[u] = vel[j];
-                    x[u] = aux[j];
+                    ah[u] = alpha_h_of(j, cell, C);
                     bnd[u] = (MODEL & kDiffusion) ? ptype(info[j]) == kBoundary : false;
                 }
 #pragma unroll
@@ -548,7 +554,8 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
                         sP[slot[u]] = make_float4(fmaf(sx, C.csx, p[u].x), fmaf(sy, C.csy, p[u].y),
                                                   fmaf(sz, C.csz, p[u].z), bnd[u] ? -mf : mf);
                         sV[slot[u]] = v[u];
-                        sA[slot[u]] = x[u];
+                        // equation-of-state terms from the staged density
+                        sA[slot[u]] = eos_terms(v[u].w, ah[u], C);
                     }
                 }
             }
@@ -595,11 +602,12 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
                     // pipeline: this path shares the register budget of the LDS
                     // path and runs only where a halo overflows)
                     const bool central_fluid = (MODEL & kDiffusion) ? ptype(info[i]) != kBoundary : true;
-                    gather_pairs<MODEL, 2>(A, neibs + toff, nf, h == 0 ? nt : 0, ntw, M, jmax, pos, vel, aux, pos[i],
-                                           vel[i], aux[i], central_fluid, C);
+                    const float4 vi = vel[i];
+                    gather_pairs<MODEL, 2>(A, neibs + toff, nf, h == 0 ? nt : 0, ntw, M, jmax, pos, vel, nullptr, cell,
+                                           pos[i], vi, eos_terms(vi.w, alpha_h_of(i, cell, C), C), central_fluid, C);
                 }
             }
-            // (a particle with an empty list was written by the prologue)
+            // (particles with an empty list are written after the last brick)
             if (act && h == 0 && nt > 0) out[i] = make_float4(A.ax, A.ay, A.az, A.dr);
             int gn = 0;
             if (tid % kWave == 0) gn = atomicAdd(&sGroup, 1) + NW;
@@ -613,6 +621,11 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
         pre = sPre[0] != 0;
         if (pre) cur ^= 1;
     }
+    // Particles with an empty list (none of their bricks' pairs; also those
+    // the build dropped) get zero derivatives, by all workgroups as they run
+    // out of bricks: no other lane writes them.
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
+        if (count[i] == 0u) out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 // LDS capacity (staged particles, 40 bytes each) per brick shape: the halo
@@ -631,15 +644,12 @@ void launch_brick(const ForceArgs &a, const ForceConst &C, hipStream_t s)
         const BrickGrid G = brick_grid<BX, BY, BZ>(a.grid->ncell, a.grid->periodic);
         const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
         constexpr int NT = brick_threads(BX * BY * BZ);
-        // (active[0], the brick counter and the light count were zeroed by the
-        // equation-of-state prologue; a brick with fewer than 12 particles per
-        // inner cell is light)
-        k_active_bricks<BX, BY, BZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(
-            a.cell_start, a.cell_end, G, a.active, a.cell_flags, a.light, 12 * BX * BY * BZ, G.nx * G.ny * G.nz);
+        // (the brick counter was zeroed before the launch; the table of
+        // bricks with a pair is the build's)
         const unsigned wgs = blocks < (unsigned)sph_device_cus() ? blocks : (unsigned)sph_device_cus();
         k_forces_brick<MODEL, BX, BY, BZ, NT, brick_cap(BX, BY, BZ)><<<wgs, NT, 0, s>>>(
-            a.n, a.pos, a.vel, a.aux, a.neibs, a.neibs_brick, a.count, a.cell_start, a.cell_end, a.active,
-            a.next, a.light, a.info, a.out, C, G);
+            a.n, a.pos, a.vel, a.cell, a.neibs, a.neibs_brick, a.count, a.cell_start, a.cell_end, a.table,
+            a.cap_ids, a.next, a.info, a.out, C, G);
     });
 }
 

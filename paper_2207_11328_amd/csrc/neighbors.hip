@@ -24,7 +24,7 @@ constexpr int kScanItems = 4;                       // per thread
 constexpr int kScanTile = kThreads * kScanItems;    // elements per block
 
 struct BuildLayout {
-    size_t cnt, cursor, start, partials, perm_a, perm_b, t_cell, t_pos, t_vel, t_info, active, total;
+    size_t cnt, cursor, start, partials, perm_a, perm_b, t_cell, t_pos, t_vel, t_info, active, flags, total;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
@@ -46,6 +46,7 @@ BuildLayout build_layout(int64_t capacity, int64_t n_cells)
     L.t_vel = o;    o = align_up(o + sizeof(float4) * capacity);
     L.t_info = o;   o = align_up(o + sizeof(uint32_t) * capacity);
     L.active = o;   o = align_up(o + sizeof(int32_t) * (n_cells + 1));
+    L.flags = o;    o = align_up(o + (size_t)n_cells + 4);
     L.total = o;
     return L;
 }
@@ -633,7 +634,8 @@ extern "C" size_t sph_neib_list_entries(int32_t capacity, int32_t max_neibs)
 extern "C" size_t sph_neib_brick_entries(int32_t capacity, int32_t max_neibs)
 {
     if (capacity < 0 || max_neibs < 0) return 0;
-    return (size_t)((capacity + kWave - 1) / kWave) * kWave * (size_t)brick_groups(max_neibs) * kBrickGroup;
+    // the lists, then the table of bricks with a pair (int32 words)
+    return brick_list_entries(capacity, max_neibs) + 2 * brick_table_words(capacity);
 }
 
 extern "C" size_t sph_build_workspace_bytes(int32_t capacity, int32_t n_cells)
@@ -732,6 +734,27 @@ extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params
         k_zero_dropped_counts<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, t_cell, neib_count);
         k_copy_state<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, t_cell, t_pos, t_vel, t_info, parts->cell,
                                                                    pos, vel, parts->info);
+        SPH_CHECK_LAUNCH();
+    }
+    if (neibs_brick) {
+        // the table of bricks with a pair behind the brick-local lists, for
+        // the derivative kernels (heavy bricks first: at least 12 particles
+        // per inner cell)
+        const int cap_ids = brick_table_cap(cap);
+        int32_t *table = brick_table(reinterpret_cast<int32_t *>(neibs_brick), cap, max_neibs);
+        uint8_t *flags = (uint8_t *)(ws + L.flags);
+        k_fill<<<fill_blocks, kThreads, 0, s>>>((int32_t *)flags, (n_cells + 3) / 4, 0);
+        k_zero_one<int32_t><<<1, 1, 0, s>>>(table);
+        k_zero_one<int32_t><<<1, 1, 0, s>>>(table + cap_ids + 1);
+        if (n > 0)
+            k_flag_cells<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, parts->cell, grid->cell_base, n_cells,
+                                                                       neib_count, flags);
+        with_shape(shape, [&]<int BX, int BY, int BZ>() {
+            const BrickGrid G = brick_grid<BX, BY, BZ>(grid->ncell, grid->periodic);
+            const unsigned bricks = (unsigned)G.nbx * G.nby * G.nbz;
+            k_active_bricks<BX, BY, BZ><<<sph_blocks(bricks, 256), 256, 0, s>>>(
+                start, start + 1, G, table, flags, table + cap_ids + 1, 12 * BX * BY * BZ, cap_ids);
+        });
         SPH_CHECK_LAUNCH();
     }
     return SPH_OK;

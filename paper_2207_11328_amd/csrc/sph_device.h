@@ -161,6 +161,26 @@ __host__ __device__ inline size_t brick_entry(int i, int p, int groups)
            (size_t)(i % kWave) * kBrickGroup + (size_t)(p % kBrickGroup);
 }
 
+// Table of the bricks with a pair, written by the list build behind the
+// brick-local lists of the same array (4-byte aligned: the lists take a
+// multiple of 512 entries): int32 words [0] heavy bricks, [1 .. capacity]
+// brick ids, heavy ones from the front and light ones from the back
+// (brick_at), [capacity + 1] light bricks, [capacity + 2 ..] reserved.  A
+// brick has a pair when one of its inner cells holds a particle with a
+// non-empty list; at most one brick per such particle, so capacity ids
+// suffice.
+__host__ __device__ inline size_t brick_list_entries(int capacity, int max_neibs)
+{
+    return (size_t)((capacity + kWave - 1) / kWave) * kWave * (size_t)brick_groups(max_neibs) * kBrickGroup;
+}
+__host__ __device__ inline size_t brick_table_words(int capacity) { return (size_t)(capacity > 0 ? capacity : 1) + 4; }
+__host__ __device__ inline int brick_table_cap(int capacity) { return capacity > 0 ? capacity : 1; }
+template <typename T>
+__host__ __device__ inline T *brick_table(T *neibs_brick, int capacity, int max_neibs)
+{
+    return (T *)((uint16_t *)neibs_brick + brick_list_entries(capacity, max_neibs));
+}
+
 struct BrickGrid {
     int nx, ny, nz;
     uint32_t periodic;
@@ -320,6 +340,19 @@ template <typename T>
 __global__ void k_zero_one(T *p)
 {
     *p = T(0);
+}
+
+// Flag the cells that hold a particle with a non-empty list (sorted state:
+// cell[i] - cell_base, count[i] = nf | nb << 16; dropped particles have cell
+// -1 and count 0).
+__global__ __launch_bounds__(256) inline void k_flag_cells(int n, const int32_t *__restrict__ cell, int cell_base,
+                                                           int n_cells, const uint32_t *__restrict__ count,
+                                                           uint8_t *__restrict__ flags)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n || count[i] == 0u) return;
+    const int lc = cell[i] - cell_base;
+    if ((unsigned)lc < (unsigned)n_cells) flags[lc] = 1;
 }
 
 }  // namespace sph

@@ -379,7 +379,8 @@ def gpu_brick_lists(sim):
     -1 past each list."""
     n, M = sim.n, sim.max_neibs
     G = -(-M // 8)
-    t = sim.neibs_brick.view(-1, G, 64, 8).cpu().numpy().view(np.uint16)  # [tile, group, lane, 8]
+    E = -(-sim.capacity // 64) * 64 * 8 * G   # the lists; the table of bricks with a pair follows
+    t = sim.neibs_brick[:E].view(-1, G, 64, 8).cpu().numpy().view(np.uint16)  # [tile, group, lane, 8]
     L = t.transpose(0, 2, 1, 3).reshape(-1, G * 8)[:n, :M].astype(np.int64)
     cnt = sim.neib_count[:n].cpu().numpy().view(np.uint32).astype(np.int64)
     tot = (cnt & 0xFFFF) + (cnt >> 16)

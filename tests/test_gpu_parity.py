@@ -555,3 +555,39 @@ def test_tiny_random_scenes():
             torch_sync()
             check_forces(f[:n].cpu().numpy(), acc, drho, sa, sd, label="tiny %d bricks=%s" % (case, bricks),
                          allowance=allow)
+
+
+@pytest.mark.parametrize("name", ["dam_break_64k", "cloud_periodic_xyz", "channel_small"])
+def test_brick_table_lists_the_bricks_with_a_pair(name):
+    """The build's table behind the brick-local lists holds exactly the
+    bricks (of the grid tiled by the brick shape from cell 0) where a particle
+    has a non-empty list, heavy ones (at least 12 particles per inner cell)
+    from the front and light ones from the back, each once."""
+    sc = SCENES[name]()
+    M = _slots(name)
+    sim = make_sim(sc, max_neibs=M)
+    sim.build()
+    torch_sync()
+    BX, BY, BZ = sim.brick_shape
+    nx, ny, nz = (int(v) for v in sc.grid.ncell)
+    nbx, nby = -(-nx // BX), -(-ny // BY)
+    cell = sim.cell[: sc.n].cpu().numpy().astype(np.int64) - int(sc.grid.cell_base)
+    cnt = sim.neib_count[: sc.n].cpu().numpy().view(np.uint32)
+    ok = cell >= 0
+    cx, cy, cz = cell % nx, (cell // nx) % ny, cell // (nx * ny)
+    bid = cx // BX + nbx * (cy // BY + nby * (cz // BZ))
+    has = np.zeros(nbx * nby * (-(-nz // BZ)), bool)
+    has[bid[ok & (cnt > 0)]] = True
+    load = np.bincount(bid[ok], minlength=has.size)
+    heavy = set(np.nonzero(has & (load >= 12 * BX * BY * BZ))[0].tolist())
+    light = set(np.nonzero(has & (load < 12 * BX * BY * BZ))[0].tolist())
+    G = -(-M // 8)
+    E = -(-sim.capacity // 64) * 64 * 8 * G
+    t = sim.neibs_brick[E:].view(torch.int32).cpu().numpy()
+    cap = sim.capacity
+    nh, nl = int(t[0]), int(t[cap + 1])
+    got_h = t[1:1 + nh].tolist()
+    got_l = t[cap + 1 - nl:cap + 1].tolist()
+    log("%s: %d heavy and %d light bricks with a pair of %d" % (name, nh, nl, has.size))
+    assert len(got_h) == len(set(got_h)) and len(got_l) == len(set(got_l))
+    assert set(got_h) == heavy and set(got_l) == light
