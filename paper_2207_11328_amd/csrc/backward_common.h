@@ -24,10 +24,9 @@ struct BackArgs {
     const uint32_t *neibs, *count, *info;
     const uint16_t *neibs_brick;
     const int32_t *cell_start, *cell_end;
-    int32_t *active;  // bricks holding particles: count, then ids
-    int32_t *next;    // brick counter of the persistent workgroups
-    int32_t *light;   // count of the light bricks, listed from the back of active
-    uint8_t *cell_flags;  // cells holding a particle with a non-empty list (set by the prologue)
+    const int32_t *table;  // bricks with a pair (brick_table layout), from the build
+    int cap_ids;           // ids of the table
+    int32_t *next;         // brick counter of the persistent workgroups
     float4 *gpos, *gvel;
     double *partial;  // per-block (gather) or per-brick parameter partials
     int accumulate;

@@ -17,30 +17,19 @@ constexpr int kThreads = 256;
 
 // aux = (P/rho^2, c, d(P/rho^2)/drho, dc/drho) for gamma = 7, or
 // (P, c, dP/drho = c^2, dc/drho) for the Landrini-Morris formulation
-// Also (brick form): flags the cells that hold a particle with a non-empty
-// list (only bricks with a pair are staged) and, unless the call accumulates,
-// writes the (zero) adjoint of particles with an empty list or dropped by the
-// last build (cell < 0; grad_pos.w is kept).
+// Also (brick form, when the call overwrites): writes the (zero) adjoint of
+// particles with an empty list, dropped ones included (grad_pos.w is kept);
+// only the bricks with a pair are staged.
 __global__ __launch_bounds__(kThreads) void k_eos_grad(int n, const float4 *__restrict__ vel,
                                                        float4 *__restrict__ aux, BackConst C,
-                                                       const int32_t *__restrict__ cell, int cell_base,
                                                        const uint32_t *__restrict__ count,
-                                                       uint8_t *__restrict__ cell_flags, int n_cells,
                                                        float4 *__restrict__ gpos, float4 *__restrict__ gvel)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
     if (i >= n) return;
-    if (cell_flags) {
-        const int c = cell[i];
-        const int lc = c - cell_base;
-        if (c < 0 || count[i] == 0u || (unsigned)lc >= (unsigned)n_cells) {
-            if (gpos) {
-                gpos[i] = make_float4(0.0f, 0.0f, 0.0f, gpos[i].w);
-                gvel[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            }
-        } else {
-            cell_flags[lc] = 1;
-        }
+    if (gpos && count[i] == 0u) {
+        gpos[i] = make_float4(0.0f, 0.0f, 0.0f, gpos[i].w);
+        gvel[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
     const float rho = vel[i].w;
     const float d = (rho - C.rho0) * C.inv_rho0;
@@ -102,12 +91,9 @@ __global__ __launch_bounds__(kThreads) void k_unpermute(int n, const uint32_t *_
 
 size_t aux_bytes(int64_t cap) { return (size_t)((16 * cap + 255) & ~(int64_t)255); }
 size_t partial_bytes(int64_t cap) { return (size_t)(3 * 8 * ((cap + kThreads - 1) / kThreads) + 256); }
-// per-brick parameter partials (at most one brick per cell), the active-brick
-// list and one flag byte per cell
-size_t brick_bytes(int64_t n_cells)
-{
-    return (size_t)(3 * 8 * (n_cells + 1) + 4 * (n_cells + 3) + ((n_cells + 255) & ~(int64_t)255) + 256);
-}
+// per-brick parameter partials (at most one brick per cell) and the brick
+// counter
+size_t brick_bytes(int64_t n_cells) { return (size_t)(3 * 8 * (n_cells + 1) + 256); }
 
 }  // namespace
 
@@ -173,17 +159,15 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
     float4 *aux = (float4 *)workspace;
     double *partial = (double *)((char *)workspace + aux_bytes(cap1));
     double *bpartial = (double *)((char *)workspace + aux_bytes(cap1) + partial_bytes(cap1));
-    int32_t *active = (int32_t *)(bpartial + 3 * (n_cells + 1));
+    int32_t *next = (int32_t *)(bpartial + 3 * (n_cells + 1));
     const int nblocks = n > 0 ? (int)sph_blocks(n, kThreads) : 0;
     static bool (*const pairs[4])(int, const BackArgs &, const BackConst &, hipStream_t, int &) = {
         backward_pairs_kernel0, backward_pairs_kernel1, backward_pairs_kernel2, backward_pairs_kernel3};
     const int model = model_of(p);
     int n_partials = 0;
     if (n > 0) {
-        uint8_t *cell_flags = (uint8_t *)(active + n_cells + 3);
-        k_eos_grad<<<nblocks, kThreads, 0, s>>>(n, (const float4 *)parts->vel, aux, C, parts->cell,
-                                                grid->cell_base, neib_count, bricks ? cell_flags : nullptr,
-                                                (int)n_cells, bricks && !accumulate ? (float4 *)grad_pos : nullptr,
+        k_eos_grad<<<nblocks, kThreads, 0, s>>>(n, (const float4 *)parts->vel, aux, C, neib_count,
+                                                bricks && !accumulate ? (float4 *)grad_pos : nullptr,
                                                 (float4 *)grad_vel);
         BackArgs a;
         a.grid = grid;
@@ -199,10 +183,10 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
         a.neibs_brick = neibs_brick;
         a.cell_start = cell_start;
         a.cell_end = cell_end;
-        a.active = active;
-        a.next = active + n_cells + 1;
-        a.light = active + n_cells + 2;
-        a.cell_flags = cell_flags;
+        a.cap_ids = brick_table_cap(parts->capacity);
+        a.table = bricks ? brick_table(reinterpret_cast<const int32_t *>(neibs_brick), parts->capacity, max_neibs)
+                         : nullptr;
+        a.next = next;
         a.gpos = (float4 *)grad_pos;
         a.gvel = (float4 *)grad_vel;
         a.partial = bricks ? bpartial : partial;

@@ -396,7 +396,7 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
     int n, const float4 *__restrict__ pos, const float4 *__restrict__ vel, const float4 *__restrict__ aux,
     const float4 *__restrict__ gforce, const uint32_t *__restrict__ neibs, const uint16_t *__restrict__ neibs_brick,
     const uint32_t *__restrict__ count, const int32_t *__restrict__ cell_start, const int32_t *__restrict__ cell_end,
-    const int32_t *__restrict__ active, int32_t *__restrict__ next, const int32_t *__restrict__ light,
+    const int32_t *__restrict__ table, int cap_ids, int32_t *__restrict__ next,
     const uint32_t *__restrict__ info,
     float4 *__restrict__ gpos, float4 *__restrict__ gvel, double *__restrict__ partial, int accumulate, BackConst C,
     BrickGrid G)
@@ -422,7 +422,7 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
     // One resident workgroup per CU takes the bricks with a pair one at a time
     // from the counter `next`, heavy ones first (brick_at order; no workgroup
     // for an empty brick; costs even out across CUs, cheap bricks come last).
-    const int n_listed = bricks_listed(active, light), cap_ids = G.nx * G.ny * G.nz;
+    const int n_listed = table[0] + table[cap_ids + 1];
     for (;;) {
         // the thread index is re-read per brick (an empty asm hides that it is the
         // same), so nothing derived from it is kept live across the pair loop
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
         __syncthreads();
         const int kb = sNext;
         if (kb >= n_listed) break;  // uniform
-        const int b = brick_at(active, cap_ids, kb);
+        const int b = brick_at(table, cap_ids, kb);
         const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
 
         // 1. staged cell ranges and LDS bases, inner cells and their centrals
@@ -634,13 +634,6 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
     }
 }
 
-__global__ void k_zero_counters(int32_t *a, int32_t *b, int32_t *c)
-{
-    *a = 0;
-    *b = 0;
-    *c = 0;
-}
-
 __global__ __launch_bounds__(kThreads) void k_zero_f64(int n, double *__restrict__ p)
 {
     for (int k = blockIdx.x * kThreads + threadIdx.x; k < n; k += gridDim.x * kThreads) p[k] = 0.0;
@@ -653,15 +646,16 @@ void launch_backward_brick(const BackArgs &a, const BackConst &C, hipStream_t s,
         const BrickGrid G = brick_grid<BX, BY, BZ>(a.grid->ncell, a.grid->periodic);
         const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
         n_bricks = (int)blocks;
-        k_zero_counters<<<1, 1, 0, s>>>(a.active, a.next, a.light);
+        // the brick counter and the per-brick parameter partials (a brick of
+        // the grid without a pair keeps a zero partial); the table of bricks
+        // with a pair is the build's
+        k_zero_one<int32_t><<<1, 1, 0, s>>>(a.next);
         k_zero_f64<<<sph_blocks(3 * blocks, kThreads) < 1024u ? sph_blocks(3 * blocks, kThreads) : 1024u, kThreads,
                      0, s>>>(3 * (int)blocks, a.partial);
-        k_active_bricks<BX, BY, BZ><<<sph_blocks(blocks, 256), 256, 0, s>>>(
-            a.cell_start, a.cell_end, G, a.active, a.cell_flags, a.light, 12 * BX * BY * BZ, G.nx * G.ny * G.nz);
         const unsigned wgs = blocks < (unsigned)sph_device_cus() ? blocks : (unsigned)sph_device_cus();
         k_forces_backward_brick<MODEL, BX, BY, BZ, kBackBrickThreads, kBackBrickCap>
             <<<wgs, kBackBrickThreads, 0, s>>>(a.n, a.pos, a.vel, a.aux, a.gforce, a.neibs, a.neibs_brick,
-                                              a.count, a.cell_start, a.cell_end, a.active, a.next, a.light, a.info,
+                                              a.count, a.cell_start, a.cell_end, a.table, a.cap_ids, a.next, a.info,
                                               a.gpos,
                                               a.gvel, a.partial, a.accumulate, C, G);
     });
