@@ -346,6 +346,52 @@ __global__ void k_status(int n, int n_cells, const int32_t *__restrict__ start, 
 // Staging order, particles of a cell in sorted order), uint16, in scan order with
 // fluid and boundary neighbours interleaved as found (entries 0 .. nf+nb-1),
 // stored in groups of 8 per particle (brick_entry).
+// The split j-list of one central particle written from its brick-local
+// list (w entries, already in global memory, in scan order), entry k of the
+// lanes of a wave in one store.  Entries are in scan order, neighbour cell by
+// neighbour cell, and the 27 cells hold disjoint slot ranges: a cursor over
+// the cells in scan order, moved on until the entry's slot is in its cell's
+// range, finds each entry's cell (and so its particle index and image code).
+// Returns n_fluid | n_boundary << 16.
+template <int BX, int BY, int BZ>
+__device__ __forceinline__ uint32_t brick_jlists(int tc, int M, int w, const int *cBase, const int *cDelta,
+                                                 const float4 *sPos, uint32_t *tile, const uint16_t *ltile)
+{
+    uint32_t *tf = tile, *tb = tile + (size_t)(M - 1) * kWave;
+    const uint4 *lg = (const uint4 *)ltile;
+    uint4 grp = make_uint4(0u, 0u, 0u, 0u);
+    int dx = -1, dy = -1, dz = -1;
+    int t = tc + Staging<BX, BY, BZ>::step(dx, dy, dz);
+    int lo = cBase[t], hi = cBase[t + 1], delta = cDelta[t];
+    for (int e = 0; e < w; ++e) {
+        if ((e & (kBrickGroup - 1)) == 0) grp = lg[(size_t)(e / kBrickGroup) * kWave];
+        const int word = e >> 1 & 3;
+        const uint32_t pair = word == 0 ? grp.x : word == 1 ? grp.y : word == 2 ? grp.z : grp.w;
+        const int sl = (int)(pair >> ((e & 1) * 16) & 0xFFFFu);
+        const uint32_t inf = __float_as_uint(sPos[sl].w);  // read before the cursor moves
+        while (sl < lo || sl >= hi) {
+            if (++dx > 1) {
+                dx = -1;
+                if (++dy > 1) {
+                    dy = -1;
+                    ++dz;
+                }
+            }
+            if (dz > 1) break;  // not reached: every entry lies in one of the 27 cells
+            t = tc + Staging<BX, BY, BZ>::step(dx, dy, dz);
+            lo = cBase[t];
+            hi = cBase[t + 1];
+            delta = cDelta[t];
+        }
+        const bool nb_boundary = ptype(inf) == kBoundary;
+        *(nb_boundary ? tb : tf) = (uint32_t)(sl - delta) | pack_neib(0u, -dx, -dy, -dz);
+        tf += nb_boundary ? 0 : kWave;
+        tb -= nb_boundary ? kWave : 0;
+    }
+    const int wf = (int)((tf - tile) / kWave), wb = w - wf;
+    return (uint32_t)wf | (uint32_t)wb << 16;
+}
+
 template <int BX, int BY, int BZ, bool LDS>
 __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float4 &pi, bool central_boundary,
                                                const int *cBase, const int *cDelta, const int *cFluidEnd,
@@ -443,42 +489,158 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
     }
     if (ltile && (w & (kBrickGroup - 1)) != 0) lg[(size_t)(w / kBrickGroup) * kWave] = grp;
     if (deferred) {
-        // Entries are in scan order, neighbour cell by neighbour cell, and the
-        // 27 cells hold disjoint slot ranges: a cursor over the cells in scan
-        // order, moved on until the entry's slot is in its cell's range, finds
-        // each entry's cell (and so its particle index and image code).
-        int dx = -1, dy = -1, dz = -1;
-        int t = tc + Staging<BX, BY, BZ>::step(dx, dy, dz);
-        int lo = cBase[t], hi = cBase[t + 1], delta = cDelta[t];
-        for (int e = 0; e < w; ++e) {
-            if ((e & (kBrickGroup - 1)) == 0) grp = lg[(size_t)(e / kBrickGroup) * kWave];
-            const int word = e >> 1 & 3;
-            const uint32_t pair = word == 0 ? grp.x : word == 1 ? grp.y : word == 2 ? grp.z : grp.w;
-            const int sl = (int)(pair >> ((e & 1) * 16) & 0xFFFFu);
-            const uint32_t inf = __float_as_uint(sPos[sl].w);  // read before the cursor moves
-            while (sl < lo || sl >= hi) {
-                if (++dx > 1) {
-                    dx = -1;
-                    if (++dy > 1) {
-                        dy = -1;
-                        ++dz;
-                    }
-                }
-                if (dz > 1) break;  // not reached: every entry lies in one of the 27 cells
-                t = tc + Staging<BX, BY, BZ>::step(dx, dy, dz);
-                lo = cBase[t];
-                hi = cBase[t + 1];
-                delta = cDelta[t];
-            }
-            const bool nb_boundary = ptype(inf) == kBoundary;
-            *(nb_boundary ? tb : tf) = (uint32_t)(sl - delta) | pack_neib(0u, -dx, -dy, -dz);
-            tf += nb_boundary ? 0 : kWave;
-            tb -= nb_boundary ? kWave : 0;
-        }
+        total_found = found;
+        return brick_jlists<BX, BY, BZ>(tc, M, w, cBase, cDelta, sPos, tile, ltile);
     }
     const int wf = (int)((tf - tile) / kWave), wb = w - wf;
     total_found = found;
     return (uint32_t)wf | (uint32_t)wb << 16;
+}
+
+// Scan of the list build, cell form (brick staged in LDS, brick-local lists
+// asked for).  The work items are the two halves of each inner cell's
+// central particles; a wave takes items from a counter.  For its item, the
+// wave lays the candidates of the cell's 27 neighbour cells, in scan order
+// (cells z, y, x from -1 to +1, each in slot order; only the fluid prefix of
+// each cell when the item's centrals are boundary particles), out over its
+// lanes in chunks of 64, one candidate per lane with its cell shift, and
+// tests every central of the item against each chunk: every lane busy on the
+// same central, no divergent trip counts.  The hits of a chunk are a ballot;
+// a hit's place in the central's list is the count of hits before it
+// (mbcnt), so the entries come out in scan order and the first max_neibs
+// found are kept, as in the lane-per-central form.  The brick-local entries
+// go straight to global memory (the groups of one central fill within the
+// item); the number found is kept in the low 30 bits of the central's staged
+// type word (its type bits stay: other waves read them); a candidate past
+// the cell set points at a dummy staged particle far away.
+constexpr int kItemChunks = 6;                 // candidate chunks held in registers per pass
+constexpr uint32_t kFoundMask = (1u << kTypeShift) - 1u;
+
+// Tests of one central (slot si, position pi) against the nch candidate
+// chunks of the item; found: entries so far.  MASK_B: the central is a
+// boundary particle among fluid candidates (boundary candidates are skipped;
+// mask_b is uniform).
+__device__ __forceinline__ int scan_central(bool mask_b, int found, int si, const float4 &pi, int nch, const int *sa,
+                                            const float *tx, const float *ty, const float *tz, const float4 *sPos,
+                                            float rs2, int M, uint16_t *__restrict__ lt)
+{
+#pragma unroll
+    for (int c = 0; c < kItemChunks; ++c) {
+        if (c < nch) {  // uniform (scalar)
+            const uint32_t slot = (uint32_t)sa[c];
+            const float4 pj = sPos[slot];
+            const float r2 = predicate_r2(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, tx[c], ty[c], tz[c]);
+            bool hit = (r2 < rs2) & (slot != (uint32_t)si);
+            if (mask_b) hit = hit & (ptype(__float_as_uint(pj.w)) != kBoundary);
+            const unsigned long long H = __ballot(hit);
+            if (H) {  // uniform
+                const uint32_t pos = (uint32_t)found + __builtin_amdgcn_mbcnt_hi(
+                                                           (uint32_t)(H >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)H, 0u));
+                if (hit & (pos < (uint32_t)M))
+                    lt[((pos >> 3) << 9) | (pos & 7u)] = (uint16_t)slot;  // brick_entry layout
+                found += (int)__popcll(H);
+            }
+        }
+    }
+    return found;
+}
+
+template <int BX, int BY, int BZ>
+__device__ __forceinline__ void brick_scan_items(int M, int *sItem, const int *cBase, const int *cDelta,
+                                                 const int *cFluidEnd, const int *iBase, const int *iStart,
+                                                 float4 *sPos, int dummy_slot, float csx, float csy, float csz,
+                                                 float rs2, uint16_t *__restrict__ neibs_brick)
+{
+    using St = Staging<BX, BY, BZ>;
+    constexpr int NI = St::NI;
+    const int lane = threadIdx.x % kWave;
+    const int G = brick_groups(M);
+    for (;;) {
+        int item = 0;
+        if (lane == 0) item = atomicAdd(sItem, 1);
+        item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
+        if (item >= 2 * NI) break;  // uniform
+        const int u = item >> 1;
+        const int n_u = iBase[u + 1] - iBase[u];
+        const int half = (n_u + 1) >> 1;
+        const int qa = (item & 1) ? half : 0, qb = (item & 1) ? n_u : half;
+        if (qa >= qb) continue;  // uniform
+        const int tc = St::inner(u);
+        const int i0 = iStart[u];
+        const int sdel = cDelta[tc];
+        // centrals are fluid first: a boundary one first means all are
+        const bool fluid_only = ptype(__float_as_uint(sPos[i0 + qa + sdel].w)) == kBoundary;
+        // candidate ranges of the 27 cells, lane k < 27 (k = 9 (dz+1) + 3 (dy+1) + dx+1)
+        int beg = 0, len = 0;
+        if (lane < 27) {
+            const int t = tc + St::step(lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1);
+            beg = cBase[t];
+            len = (fluid_only ? cFluidEnd[t] : cBase[t + 1]) - beg;
+        }
+        // inclusive scan over lanes 0..26; the lane id is read afresh (opaque
+        // to the compiler) so that the shuffle addresses are not kept live
+        // across the whole item loop
+        int incl = len, me;
+        asm volatile("v_mbcnt_lo_u32_b32 %0, -1, 0" : "=v"(me));
+#pragma unroll
+        for (int o = 1; o < 32; o <<= 1) {
+            const int v = __builtin_amdgcn_ds_bpermute((me - o) << 2, incl);
+            if (me >= o) incl += v;
+        }
+        const int ex = incl - len;
+        const int ncand = __builtin_amdgcn_readfirstlane(__shfl(incl, 26));
+        if (ncand == 0) {  // uniform: no candidate (boundary centrals far from the fluid)
+            for (int q = qa + lane; q < qb; q += kWave) {
+                uint32_t *wq = reinterpret_cast<uint32_t *>(&sPos[i0 + q + sdel]) + 3;
+                *wq &= ~kFoundMask;
+            }
+            continue;
+        }
+        for (int pg = 0; pg < ncand; pg += kItemChunks * kWave) {
+            int sa[kItemChunks];
+            float tx[kItemChunks], ty[kItemChunks], tz[kItemChunks];
+#pragma unroll
+            for (int c = 0; c < kItemChunks; ++c) {
+                const int idx = pg + c * kWave + lane;
+                int lo = 0, hi = 26;  // the last cell k with ex_k <= idx
+#pragma unroll
+                for (int st = 0; st < 5; ++st) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (__shfl(ex, mid) <= idx) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int b = __shfl(beg, lo), e = __shfl(ex, lo);
+                sa[c] = idx < ncand ? b + (idx - e) : dummy_slot;
+                // k_d = c_i - c_j = -(d) for the neighbour cell at offset d
+                tx[c] = cell_shift(1 - lo % 3, csx);
+                ty[c] = cell_shift(1 - (lo / 3) % 3, csy);
+                tz[c] = cell_shift(1 - lo / 9, csz);
+            }
+            const int nch = min(kItemChunks, (ncand - pg + kWave - 1) / kWave);
+            const bool last_page = pg + kItemChunks * kWave >= ncand;
+            for (int q = qa; q < qb; ++q) {  // uniform
+                const int i = __builtin_amdgcn_readfirstlane(i0 + q), si = i + sdel;
+                const float4 pi = sPos[si];
+                const uint32_t wi = __builtin_amdgcn_readfirstlane(__float_as_uint(pi.w));
+                int found = pg == 0 ? 0 : (int)(wi & kFoundMask);
+                uint16_t *lt = neibs_brick + brick_entry(i, 0, G);
+                // a boundary central among fluid ones takes fluid neighbours only
+                const bool mask_b = !fluid_only && ptype(wi) == kBoundary;
+                found = scan_central(mask_b, found, si, pi, nch, sa, tx, ty, tz, sPos, rs2, M, lt);
+                if (last_page) {
+                    // zero the rest of the last group, so the lists are the same bytes
+                    // whatever the array held
+                    const int w = min(found, M);
+                    const int wend = min((w + kBrickGroup - 1) & ~(kBrickGroup - 1), G * kBrickGroup);
+                    const int e = w + lane;
+                    if (e < wend) lt[((e >> 3) << 9) | (e & 7)] = 0;
+                }
+                if (lane == 0)
+                    reinterpret_cast<uint32_t *>(&sPos[si])[3] =
+                        (wi & ~kFoundMask) | (uint32_t)min(found, (int)kFoundMask);
+            }
+        }
+    }
 }
 
 template <int BX, int BY, int BZ, int NT, int CAP>
@@ -503,6 +665,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     __shared__ int iBase[NI + 1];
     __shared__ int iStart[NI];
     __shared__ int wsum[NT / kWave];
+    __shared__ int sItem;  // work items taken (cell form of the scan)
 
     const int tid = threadIdx.x;
     if ((int)blockIdx.x >= active[0]) return;
@@ -548,7 +711,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     }
     if (tid == 0) iBase[NI] = nc;
     if (nc == 0) return;  // uniform: no particle in the brick
-    const bool use_lds = total <= CAP;
+    // (one staged slot past the brick is the cell form's dummy candidate)
+    const bool use_lds = total < CAP;
+    // the cell form of the scan needs the brick-local lists (the j-lists are
+    // written from them)
+    const bool cells = use_lds && neibs_brick != nullptr;
 
     // 2. stage the brick and its halo (slot -> cell by binary search) and mark
     //    the first boundary particle of each cell
@@ -568,7 +735,41 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         }
         if (ptype(inf) == kBoundary && (s2 == cBase[lo] || ptype(info[j - 1]) != kBoundary)) cFluidEnd[lo] = s2;
     }
+    if (cells && tid == 0) {
+        sPos[total] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);  // no central is within r_s of it
+        sItem = 0;
+    }
     __syncthreads();
+
+    if (cells) {
+        // 3a. the cell form of the scan: brick-local lists and counts found
+        brick_scan_items<BX, BY, BZ>(max_neibs, &sItem, cBase, cDelta, cFluidEnd, iBase, iStart, sPos, total, csx,
+                                     csy, csz, rs2, neibs_brick);
+        __syncthreads();
+        // 3b. one lane per central: its j-list from its brick-local list
+        for (int q0 = 0; q0 < nc; q0 += NT) {
+            const int q = q0 + tid;
+            if (q >= nc) break;
+            int lo = 0, hi = NI - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (iBase[mid] <= q) lo = mid;
+                else hi = mid - 1;
+            }
+            const int u = lo;
+            const int i = iStart[u] + (q - iBase[u]);
+            const int tc = St::inner(u);
+            const int found = (int)(__float_as_uint(sPos[i + cDelta[tc]].w) & kFoundMask);
+            const size_t toff = (size_t)(i / kWave) * kWave * max_neibs + (i % kWave);
+            const uint32_t cw = brick_jlists<BX, BY, BZ>(tc, max_neibs, min(found, max_neibs), cBase, cDelta, sPos,
+                                                         neibs + toff,
+                                                         neibs_brick + brick_entry(i, 0, brick_groups(max_neibs)));
+            neib_count[i] = cw;
+            atomicMax(&status[SPH_STATUS_MAX_NEIBS], found);
+            if (found > max_neibs) atomicAdd(&status[SPH_STATUS_OVERFLOW], 1);
+        }
+        return;
+    }
 
     // 3. one lane per central particle of the brick
     for (int q0 = 0; q0 < nc; q0 += NT) {
