@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--no-missed", action="store_true")
     ap.add_argument("--no-channel-adjoint", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--gather-probe", type=int, default=0, metavar="MIB",
+                    help="only run a gather of MIB MiB in 128-byte rows taken in a random order, three times "
+                         "(checks the HBM byte counters' scale on a scattered pattern) and exit")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (calibrates the HBM "
                          "byte counters of a profiler run) and exit")
@@ -524,10 +527,28 @@ def variants(sim, sc, inter_per_call, reps=20):
     return out
 
 
+def gather_probe(mib):
+    import torch
+    rows = (mib << 20) // 128
+    src = torch.ones((rows, 32), dtype=torch.float32, device="cuda:0")
+    g = torch.Generator(device="cpu").manual_seed(7)
+    perm = torch.randperm(rows, generator=g).to("cuda:0")
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst = src.index_select(0, perm)
+    torch.cuda.synchronize()
+    # every 128-byte row is read once and written once; the index is 8 bytes a row
+    print(json.dumps({"gather_probe_rows": rows, "row_bytes": 128, "index_bytes": rows * 8,
+                      "gathers": 3, "checksum": float(dst[:4].sum())}), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.gather_probe:
+        gather_probe(args.gather_probe)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the step shards by slabs of "
@@ -668,7 +689,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": achieved_tflops / FP32_PEAK_TFLOPS,
             "traffic": traffic,
-            "kernel": ("sph_forces = k_eos + k_active_bricks + k_forces_brick" if choice["bricks"]
+            "kernel": ("sph_forces = k_zero_one (brick counter) + k_forces_brick" if choice["bricks"]
                        else "sph_forces = k_eos + k_forces"),
             "flop_per_launch": flop_per_launch,
             "launch_ms": t_forces_avg * 1e3,

@@ -266,12 +266,13 @@ __device__ __forceinline__ void brick_pairs_lds(PairAcc &A, const uint4 *lg, int
     for (int k = 0; k < ntw; k += 2 * kBrickGroup) {
         const int g0 = k / kBrickGroup + h;  // this lane's group
         const uint4 gnn = lg[min(g0 + 4, lastg) * GS];
+        const int rem = nt - g0 * kBrickGroup;  // entries of the list from this group on
 #pragma unroll
         for (int s = 0; s < kBrickGroup; ++s) {
             const int r = s % kRing;
             // staged w = +-(m_j x kernel coefficient), negative for boundary particles
             pair_core<MODEL, true>(A, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, vi, ai, fabsf(P[r].w), V[r], X[r],
-                            g0 * kBrickGroup + s < nt, pi.w > 0.0f && P[r].w > 0.0f, C);
+                            s < rem, pi.w > 0.0f && P[r].w > 0.0f, C);
             const int s2 = s + kRing;
             fetch(s2 < kBrickGroup ? group_entry(gc, s2) : group_entry(gn, s2 - kBrickGroup), P[r], V[r], X[r]);
         }
