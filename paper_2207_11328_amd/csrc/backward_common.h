@@ -26,12 +26,44 @@ struct BackArgs {
     const int32_t *cell_start, *cell_end;
     const int32_t *table;  // bricks with a pair (brick_table layout), from the build
     int cap_ids;           // ids of the table
-    int32_t *next;         // brick counter of the persistent workgroups
+    int32_t *next;         // brick counter and finished workgroups of the persistent workgroups (zeroed before)
     float4 *gpos, *gvel;
     double *partial;  // per-block (gather) or per-brick parameter partials
+    double *grad_params;  // (brick form) the last workgroup to finish sums the partials into it
     int accumulate;
     bool bricks;
 };
+
+// Sum of nparts parameter partials (3 doubles each) by the NT threads of one
+// workgroup (tid: the thread's index) in a fixed order: thread t adds
+// partials t, t + NT, ... in four
+// running sums combined in a fixed order, then the waves' sums in wave order
+// (red: 3 x NT/kWave doubles of LDS).  out = sum, or out + sum to accumulate.
+template <int NT>
+__device__ __forceinline__ void sum_partials(int tid, int nparts, const double *__restrict__ partial,
+                                             double *__restrict__ out, int accumulate, double (*red)[NT / kWave])
+{
+    double s[3][4] = {};
+    int b = tid;
+    for (; b + 3 * NT < nparts; b += 4 * NT)
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) s[k][u] += partial[3 * (size_t)(b + u * NT) + k];
+    for (; b < nparts; b += NT)
+        for (int k = 0; k < 3; ++k) s[k][0] += partial[3 * (size_t)b + k];
+    const int lane = tid % kWave, w = tid / kWave;
+    for (int k = 0; k < 3; ++k) {
+        const double t = wave_sum((s[k][0] + s[k][1]) + (s[k][2] + s[k][3]));
+        if (lane == 0) red[k][w] = t;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        double t = 0.0;
+        for (int k = 0; k < NT / kWave; ++k) t += red[tid][k];
+        out[tid] = accumulate ? out[tid] + t : t;
+    }
+}
 
 // Launch the adjoint pair kernel of `model` on stream s and return the number
 // of parameter partials it writes in n_partials; false if the model's kernel

@@ -19,13 +19,21 @@ constexpr int kThreads = 256;
 // (P, c, dP/drho = c^2, dc/drho) for the Landrini-Morris formulation
 // Also (brick form, when the call overwrites): writes the (zero) adjoint of
 // particles with an empty list, dropped ones included (grad_pos.w is kept);
-// only the bricks with a pair are staged.
+// only the bricks with a pair are staged.  And (brick form) clears what the
+// brick kernel counts and sums into: its two counters (next) and the nbp
+// per-brick parameter partials.
 __global__ __launch_bounds__(kThreads) void k_eos_grad(int n, const float4 *__restrict__ vel,
                                                        float4 *__restrict__ aux, BackConst C,
                                                        const uint32_t *__restrict__ count,
-                                                       float4 *__restrict__ gpos, float4 *__restrict__ gvel)
+                                                       float4 *__restrict__ gpos, float4 *__restrict__ gvel,
+                                                       int32_t *__restrict__ next, double *__restrict__ bpartial,
+                                                       int nbp)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (next) {
+        for (int k = i; k < nbp; k += gridDim.x * kThreads) bpartial[k] = 0.0;
+        if (i < 2) next[i] = 0;
+    }
     if (i >= n) return;
     if (gpos && count[i] == 0u) {
         gpos[i] = make_float4(0.0f, 0.0f, 0.0f, gpos[i].w);
@@ -57,27 +65,8 @@ constexpr int kReduceThreads = 1024;
 __global__ __launch_bounds__(kReduceThreads) void k_param_reduce(int nblocks, const double *__restrict__ partial,
                                                                  double *__restrict__ out, int accumulate)
 {
-    double s[3][4] = {};
-    int b = threadIdx.x;
-    for (; b + 3 * kReduceThreads < nblocks; b += 4 * kReduceThreads)
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-#pragma unroll
-            for (int k = 0; k < 3; ++k) s[k][u] += partial[3 * (size_t)(b + u * kReduceThreads) + k];
-    for (; b < nblocks; b += kReduceThreads)
-        for (int k = 0; k < 3; ++k) s[k][0] += partial[3 * (size_t)b + k];
     __shared__ double red[3][kReduceThreads / kWave];
-    const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
-    for (int k = 0; k < 3; ++k) {
-        const double t = wave_sum((s[k][0] + s[k][1]) + (s[k][2] + s[k][3]));
-        if (lane == 0) red[k][w] = t;
-    }
-    __syncthreads();
-    if (threadIdx.x < 3) {
-        double t = 0.0;
-        for (int k = 0; k < kReduceThreads / kWave; ++k) t += red[threadIdx.x][k];
-        out[threadIdx.x] = accumulate ? out[threadIdx.x] + t : t;
-    }
+    sum_partials<kReduceThreads>(threadIdx.x, nblocks, partial, out, accumulate, red);
 }
 
 __global__ __launch_bounds__(kThreads) void k_unpermute(int n, const uint32_t *__restrict__ perm,
@@ -166,9 +155,16 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
     const int model = model_of(p);
     int n_partials = 0;
     if (n > 0) {
+        // bricks of the grid (one parameter partial each)
+        int n_bricks = 0;
+        with_shape(shape, [&]<int BX, int BY, int BZ>() {
+            const BrickGrid G = brick_grid<BX, BY, BZ>(grid->ncell, grid->periodic);
+            n_bricks = G.nbx * G.nby * G.nbz;
+        });
         k_eos_grad<<<nblocks, kThreads, 0, s>>>(n, (const float4 *)parts->vel, aux, C, neib_count,
                                                 bricks && !accumulate ? (float4 *)grad_pos : nullptr,
-                                                (float4 *)grad_vel);
+                                                (float4 *)grad_vel, bricks ? next : nullptr, bpartial,
+                                                bricks ? 3 * n_bricks : 0);
         BackArgs a;
         a.grid = grid;
         a.shape = shape;
@@ -190,11 +186,14 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
         a.gpos = (float4 *)grad_pos;
         a.gvel = (float4 *)grad_vel;
         a.partial = bricks ? bpartial : partial;
+        a.grad_params = grad_params;
         a.accumulate = accumulate;
         a.bricks = bricks;
         if (!pairs[model_kernel(model)](model, a, C, s, n_partials)) return SPH_ERR_ARG;
     }
-    k_param_reduce<<<1, kReduceThreads, 0, s>>>(n_partials, bricks ? bpartial : partial, grad_params, accumulate);
+    // (the brick kernel's last workgroup has summed the partials itself)
+    if (!(bricks && n > 0))
+        k_param_reduce<<<1, kReduceThreads, 0, s>>>(n_partials, partial, grad_params, accumulate);
     SPH_CHECK_LAUNCH();
     return SPH_OK;
 }

@@ -74,8 +74,9 @@ __device__ __forceinline__ void pair_adjoint_core(BackAcc &G, float xx, float xy
     }
     bool inter = valid && (r2 < C.lim2);
     if constexpr (KER == SPH_KERNEL_QUADRATIC) inter = inter && r2 > 0.0f;  // its F is unbounded at r = 0
-    const float r = __builtin_amdgcn_sqrtf(r2);
-    const float inv_r = __builtin_amdgcn_rcpf(r);
+    // 1/r from one reciprocal square root, r = r^2/r
+    const float inv_r = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * inv_r;
     float F, Fp_r;  // F and F'(r)/r
     kernel_F_dF<KER>(C.fcoeff, r, r2, inv_r, C.inv_h, C.inv_h2, F, Fp_r);
     if (MASKED) {
@@ -89,9 +90,15 @@ __device__ __forceinline__ void pair_adjoint_core(BackAcc &G, float xx, float xy
     const float dd = r2 + C.eps_h2;
     const float inv_d = __builtin_amdgcn_rcpf(dd);
     const float csum = xi.y + xj.y;
-    const float mw = fminf(w, 0.0f);
-    const float actK = w < 0.0f ? -C.alpha_h * csum * inv_rs : 0.0f;
-    const float Pi = -C.alpha_h * csum * inv_rs * mw * inv_d;
+    // Pi = -alpha h min(w, 0)/d (c_i + c_j)/rs = A B with A = -alpha h min(w, 0)/d
+    // (zero for w >= 0, and so are Pi and its rho_i derivative) and B = csum/rs
+    const float mwd = fminf(w, 0.0f) * inv_d;
+    const float B = csum * inv_rs;
+    const float A = -C.alpha_h * mwd;
+    const float Pi = A * B;
+    const float actK = w < 0.0f ? -C.alpha_h * B : 0.0f;
+    // dPi/drho_i = A (dc_i/drho_i - B)/rs
+    const float dPi_dri = A * (xi.w - B) * inv_rs;
     // pressure factor S_p and dS_p/drho_i
     float Sp, dSp;
     if constexpr (MODEL & kLandrini) {
@@ -118,51 +125,38 @@ __device__ __forceinline__ void pair_adjoint_core(BackAcc &G, float xx, float xy
     } else {
         sD = fmaf(mj, gi.w, mi * gj.w);
     }
-    // d/do_i
-    const float cx = S * Fp_r + F * actK * (-2.0f * w * inv_d * inv_d);
+    // d/do_i = ka da + kx x + ku u, d/du_i = ku x (+ the laminar terms)
+    const float t = w * inv_d;
     const float cu = F * actK * inv_d;
-    float kx = -dA * cx + sD * w * Fp_r;  // coefficient of x
-    float ku = -dA * cu + sD * F;         // coefficient of u
-    float ka = -S * F;                    // coefficient of da
-    [[maybe_unused]] float kr = 0.0f, Q = 0.0f;
+    const float cx = fmaf(-2.0f * t, cu, S * Fp_r);  // S F'/r - 2 F actK w/d^2
+    float kx = fmaf(-dA, cx, sD * w * Fp_r);
+    float ku = fmaf(-dA, cu, sD * F);
+    float ka = -S * F;
+    [[maybe_unused]] float kr = 0.0f, Q = 0.0f, duu = 0.0f;
     if constexpr (model_visc(MODEL) == kMonaghanK) {
         kr = C.k_four_nu * inv_rs * inv_d;
         Q = kr * F * w;
         ka += Q;
-        kx = fmaf(dA * kr, fmaf(Fp_r, w, -2.0f * F * w * inv_d), kx);
+        kx = fmaf(dA * kr, fmaf(Fp_r, w, -2.0f * F * t), kx);
         ku = fmaf(dA * kr, F, ku);
     }
-    if constexpr (model_visc(MODEL) == kMorris)
-        kx = fmaf(C.four_nu * Fp_r * inv_rs, fmaf(dax, ux, fmaf(day, uy, daz * uz)), kx);
-    float ox = fmaf(ka, dax, fmaf(kx, xx, ku * ux));
-    float oy = fmaf(ka, day, fmaf(kx, xy, ku * uy));
-    float oz = fmaf(ka, daz, fmaf(kx, xz, ku * uz));
-    // d/du_i
-    float lx = -dA * cu + sD * F;  // coefficient of x
-    if constexpr (model_visc(MODEL) == kMonaghanK) lx = fmaf(dA * kr, F, lx);
-    float vx = lx * xx, vy = lx * xy, vz = lx * xz;
     if constexpr (model_visc(MODEL) == kMorris) {
-        const float la = C.four_nu * F * inv_rs;
-        vx = fmaf(la, dax, vx);
-        vy = fmaf(la, day, vy);
-        vz = fmaf(la, daz, vz);
+        duu = fmaf(dax, ux, fmaf(day, uy, daz * uz));
+        kx = fmaf(C.four_nu * Fp_r * inv_rs, duu, kx);
     }
     // d/drho_i
-    const float dPi_dri = w < 0.0f ? -C.alpha_h * mw * inv_d * (xi.w * inv_rs - csum * inv_rs * inv_rs) : 0.0f;
-    float gr = -F * (dSp + dPi_dri) * dA;
-    if constexpr (model_visc(MODEL) == kMorris)
-        gr = fmaf(-C.four_nu * F * inv_rs * inv_rs, fmaf(dax, ux, fmaf(day, uy, daz * uz)), gr);
+    float gr = F * (dSp + dPi_dri) * -dA;
+    if constexpr (model_visc(MODEL) == kMorris) gr = fmaf(-C.four_nu * F * inv_rs * inv_rs, duu, gr);
     if constexpr (model_visc(MODEL) == kMonaghanK) gr = fmaf(-Q * inv_rs, dA, gr);
     if constexpr (MODEL & kLandrini) gr = fmaf(w * F, fmaf(gi.w * mj, inv_rj, -gj.w * mi * wj * inv_ri), gr);
     // parameters (central role)
-    const float Axi = fmaf(gi.x, xx, fmaf(gi.y, xy, gi.z * xz));
-    const float mF = -mj * F;
-    float ga = Axi * mF * (-C.h * csum * inv_rs * mw * inv_d);
-    float gc = Axi * mF * (2.0f * Sp + Pi) * C.inv_c0;
+    const float AmF = fmaf(gi.x, xx, fmaf(gi.y, xy, gi.z * xz)) * (-mj * F);
+    float ga = AmF * (-C.h * mwd * B);
+    float gc = AmF * fmaf(2.0f, Sp, Pi) * C.inv_c0;
     float gn = 0.0f;
     if constexpr (model_visc(MODEL) == kMorris) gn = fmaf(gi.x, ux, fmaf(gi.y, uy, gi.z * uz)) * 4.0f * mj * F * inv_rs;
     if constexpr (model_visc(MODEL) == kMonaghanK)
-        gn = Axi * (4.0f * kMonaghanKFactor) * mj * F * w * inv_rs * inv_d;
+        gn = fmaf(gi.x, xx, fmaf(gi.y, xy, gi.z * xz)) * (4.0f * kMonaghanKFactor) * mj * F * w * inv_rs * inv_d;
     if constexpr (MODEL & kDiffusion) {
         // density diffusion, term_ij = c m_j (rho_i - rho_j)/rho_j Gd(r) with
         // Gd = F r^2/(r^2 + eps h^2), c = 2 delta h c0; both roles combined:
@@ -175,21 +169,24 @@ __device__ __forceinline__ void pair_adjoint_core(BackAcc &G, float xx, float xy
             const float Gd_r = Fp_r * r2 * inv_d + 2.0f * F * C.eps_h2 * inv_d * inv_d;
             const float w1 = gi.w * mj * irj, w2 = gj.w * mi * iri;
             const float dr = vi.w - vj.w;
-            const float kd = C.diff * Gd_r * dr * (w1 - w2);
-            ox = fmaf(kd, xx, ox);
-            oy = fmaf(kd, xy, oy);
-            oz = fmaf(kd, xz, oz);
+            kx = fmaf(C.diff * Gd_r * dr, w1 - w2, kx);
             gr = fmaf(C.diff * Gd, w1 - w2 * vj.w * iri, gr);
             gc = fmaf(w1 * C.diff * dr * Gd, C.inv_c0, gc);
         }
     }
     if (MASKED || inter) {
-        G.ox += ox;
-        G.oy += oy;
-        G.oz += oz;
-        G.ux += vx;
-        G.uy += vy;
-        G.uz += vz;
+        G.ox = fmaf(ka, dax, fmaf(kx, xx, fmaf(ku, ux, G.ox)));
+        G.oy = fmaf(ka, day, fmaf(kx, xy, fmaf(ku, uy, G.oy)));
+        G.oz = fmaf(ka, daz, fmaf(kx, xz, fmaf(ku, uz, G.oz)));
+        G.ux = fmaf(ku, xx, G.ux);
+        G.uy = fmaf(ku, xy, G.uy);
+        G.uz = fmaf(ku, xz, G.uz);
+        if constexpr (model_visc(MODEL) == kMorris) {
+            const float la = C.four_nu * F * inv_rs;
+            G.ux = fmaf(la, dax, G.ux);
+            G.uy = fmaf(la, day, G.uy);
+            G.uz = fmaf(la, daz, G.uz);
+        }
         G.r += gr;
         G.galpha += ga;
         G.gc0 += gc;
@@ -362,12 +359,13 @@ __device__ __forceinline__ void brick_adjoint_lds(BackAcc &G, const uint4 *lg, i
     for (int k = 0; k < ntw; k += 2 * kBrickGroup) {
         const int g0 = k / kBrickGroup + h;  // this lane's group
         const uint4 gnn = lg[min(g0 + 4, lastg) * kWave];
+        const int rem = nt - g0 * kBrickGroup;  // entries of the list from this group on
 #pragma unroll
         for (int s = 0; s < kBrickGroup; ++s) {
             const int r = s % R;
             // staged w = +-m_j, negative for boundary particles
             pair_adjoint_core<MODEL, !(MODEL & kDiffusion)>(G, pi.x - P[r].x, pi.y - P[r].y, pi.z - P[r].z, fabsf(pi.w), vi, xi, gi,
-                                    fabsf(P[r].w), V[r], X[r], Gj[r], g0 * kBrickGroup + s < nt,
+                                    fabsf(P[r].w), V[r], X[r], Gj[r], s < rem,
                                     pi.w > 0.0f && P[r].w > 0.0f, C);
             const int s2 = s + R;
             fetch(s2 < kBrickGroup ? group_entry(gc, s2) : group_entry(gn, s2 - kBrickGroup), r);
@@ -398,8 +396,8 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
     const uint32_t *__restrict__ count, const int32_t *__restrict__ cell_start, const int32_t *__restrict__ cell_end,
     const int32_t *__restrict__ table, int cap_ids, int32_t *__restrict__ next,
     const uint32_t *__restrict__ info,
-    float4 *__restrict__ gpos, float4 *__restrict__ gvel, double *__restrict__ partial, int accumulate, BackConst C,
-    BrickGrid G)
+    float4 *__restrict__ gpos, float4 *__restrict__ gvel, double *__restrict__ partial,
+    double *__restrict__ grad_params, int accumulate, BackConst C, BrickGrid G)
 {
     using St = Staging<BX, BY, BZ>;
     constexpr int SX = St::SX, SZ = St::SZ, S = St::S, NI = St::NI;
@@ -419,6 +417,7 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
     __shared__ double red[3][NT / kWave];
 
     __shared__ int sNext;
+    __shared__ int sLast;
     // One resident workgroup per CU takes the bricks with a pair one at a time
     // from the counter `next`, heavy ones first (brick_at order; no workgroup
     // for an empty brick; costs even out across CUs, cheap bricks come last).
@@ -632,11 +631,24 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
         }
         __syncthreads();  // the next brick reuses the LDS
     }
-}
-
-__global__ __launch_bounds__(kThreads) void k_zero_f64(int n, double *__restrict__ p)
-{
-    for (int k = blockIdx.x * kThreads + threadIdx.x; k < n; k += gridDim.x * kThreads) p[k] = 0.0;
+    // The last workgroup to finish sums the partials of every brick of the
+    // grid (bricks without a pair hold the zero written before the launch)
+    // in a fixed order: each workgroup makes its partials visible device-wide
+    // before it counts itself finished (next[1]), and the last one takes that
+    // count's view of memory before it reads them.
+    // (the thread index is hidden from the compiler here as in the loop, so
+    // that nothing derived from it is computed before the loop and kept live)
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    if (tid == 0) {
+        __threadfence();
+        sLast = atomicAdd(&next[1], 1) == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (sLast) {  // uniform
+        __threadfence();
+        sum_partials<NT>(tid, G.nbx * G.nby * G.nbz, partial, grad_params, accumulate, red);
+    }
 }
 
 template <int MODEL>
@@ -646,18 +658,15 @@ void launch_backward_brick(const BackArgs &a, const BackConst &C, hipStream_t s,
         const BrickGrid G = brick_grid<BX, BY, BZ>(a.grid->ncell, a.grid->periodic);
         const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
         n_bricks = (int)blocks;
-        // the brick counter and the per-brick parameter partials (a brick of
-        // the grid without a pair keeps a zero partial); the table of bricks
-        // with a pair is the build's
-        k_zero_one<int32_t><<<1, 1, 0, s>>>(a.next);
-        k_zero_f64<<<sph_blocks(3 * blocks, kThreads) < 1024u ? sph_blocks(3 * blocks, kThreads) : 1024u, kThreads,
-                     0, s>>>(3 * (int)blocks, a.partial);
+        // (the brick counters and the per-brick parameter partials were
+        // cleared by the equation-of-state pass before the launch; the table
+        // of bricks with a pair is the build's)
         const unsigned wgs = blocks < (unsigned)sph_device_cus() ? blocks : (unsigned)sph_device_cus();
         k_forces_backward_brick<MODEL, BX, BY, BZ, kBackBrickThreads, kBackBrickCap>
             <<<wgs, kBackBrickThreads, 0, s>>>(a.n, a.pos, a.vel, a.aux, a.gforce, a.neibs, a.neibs_brick,
                                               a.count, a.cell_start, a.cell_end, a.table, a.cap_ids, a.next, a.info,
                                               a.gpos,
-                                              a.gvel, a.partial, a.accumulate, C, G);
+                                              a.gvel, a.partial, a.grad_params, a.accumulate, C, G);
     });
 }
 

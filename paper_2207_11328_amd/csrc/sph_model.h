@@ -94,8 +94,9 @@ __device__ __forceinline__ void kernel_F_dF(float c, float r, float r2, float in
 {
     if constexpr (KER == SPH_KERNEL_WENDLAND) {
         const float qm2 = fmaf(r, inv_h, -2.0f);
-        F = c * qm2 * qm2 * qm2;
-        Fp_r = 3.0f * c * qm2 * qm2 * inv_h * inv_r;
+        const float cq = c * (qm2 * qm2);
+        F = cq * qm2;
+        Fp_r = cq * (3.0f * inv_h) * inv_r;
     } else if constexpr (KER == SPH_KERNEL_CUBIC_SPLINE) {
         const float q = r * inv_h;
         const float b = fmaxf(q, 1.0f), tb = 2.0f - b;
