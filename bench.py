@@ -219,17 +219,21 @@ def fwd_bwd(sc, dt, K=10, reps=3, brick=None, use_bricks=True):
     same workload (fixed dt): t_fwd = K plain steps (one rebuild); t_bwd = the
     reverse of those K steps from stored stage states (sph_integrate_backward
     and sph_forces_backward twice per step, plus the rebuild permutation).
-    Also the end-to-end ratio with the checkpoint recomputation included."""
+    Also the end-to-end ratios: forward + backward of the rollout with the
+    block taped (the default: lists and stage states kept from the forward),
+    and with the checkpoint recomputation (no tape)."""
     import torch
     from paper_2207_11328_amd import abi
     from paper_2207_11328_amd.adjoint import AdjointRollout
     run = AdjointRollout(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, steps=K, dt=dt, rebuild_every=K,
-                         checkpoint_every=K, brick=brick, use_bricks=use_bricks)
+                         checkpoint_every=K, brick=brick, use_bricks=use_bricks, tape_bytes=0)
+    taped = AdjointRollout(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, steps=K, dt=dt, rebuild_every=K,
+                           checkpoint_every=K, brick=brick, use_bricks=use_bricks)
     n = run.n
     g = torch.Generator(device=run.sim.device).manual_seed(0)
     seed_p = torch.randn((n, 4), device=run.sim.device, generator=g)
     seed_v = torch.randn((n, 4), device=run.sim.device, generator=g)
-    t_f, t_b, t_e2e = [], [], []
+    t_f, t_b, t_e2e, t_tape = [], [], [], []
     for _ in range(reps):
         run.reset()
         torch.cuda.synchronize()
@@ -261,10 +265,21 @@ def fwd_bwd(sc, dt, K=10, reps=3, brick=None, use_bricks=True):
         run.backward(seed_p, seed_v)
         torch.cuda.synchronize()
         t_e2e.append(time.perf_counter() - t0)
-    tf, tb, te = min(t_f), min(t_b), min(t_e2e)
-    return {"workload": sc.name, "particles": sc.n, "block_steps": K, "fwd_ms": tf * 1e3, "bwd_ms": tb * 1e3,
-            "fwd_bwd_ratio": (tf + tb) / tf, "fwd_bwd_ratio_with_recompute": te / tf,
-            "fwd_bwd_steps_per_s": K / (tf + tb)}
+        taped.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        taped.forward()
+        taped.backward(seed_p, seed_v)
+        torch.cuda.synchronize()
+        t_tape.append(time.perf_counter() - t0)
+    tf, tb, te, tt = min(t_f), min(t_b), min(t_e2e), min(t_tape)
+    out = {"workload": sc.name, "particles": sc.n, "block_steps": K, "fwd_ms": tf * 1e3, "bwd_ms": tb * 1e3,
+           "fwd_bwd_ratio": (tf + tb) / tf, "fwd_bwd_ratio_end_to_end": tt / tf,
+           "fwd_bwd_ratio_with_recompute": te / tf, "taped_blocks": taped.n_taped,
+           "tape_bytes_per_block": taped.tape_block_bytes(), "fwd_bwd_steps_per_s": K / (tf + tb)}
+    del run, taped
+    torch.cuda.empty_cache()
+    return out
 
 
 def batched(units=50, warm_units=1):
@@ -392,8 +407,9 @@ def channel_adjoint(fwd_steps=100, adj_steps=50, K=10):
 def adjoint_64k_200(steps=200, C=20, K=10):
     """The differentiable dam break of ~64k fluid particles at its stated
     length: 200 fixed-dt steps (the step-0 dt), checkpoint every 20 steps,
-    rebuild every 10; the forward rollout, and the reverse with the
-    recomputation between checkpoints, each timed."""
+    rebuild every 10; the forward rollout and the reverse, each timed, with
+    the blocks taped (the default, device memory permitting) and with the
+    recomputation between checkpoints."""
     import torch
     from paper_2207_11328_amd import tune
     from paper_2207_11328_amd.adjoint import AdjointRollout
@@ -407,30 +423,35 @@ def adjoint_64k_200(steps=200, C=20, K=10):
     s.step_dt()
     dt = float(s.d_dt.item())
     del s
-    run = AdjointRollout(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, steps=steps, dt=dt, rebuild_every=K,
-                         checkpoint_every=C, brick=c["brick"], use_bricks=c["bricks"])
-    n = run.n
-    g = torch.Generator(device=run.sim.device).manual_seed(0)
-    seed_p = torch.randn((n, 4), device=run.sim.device, generator=g)
-    seed_v = torch.randn((n, 4), device=run.sim.device, generator=g)
-    best = None
-    for _ in range(2):
-        run.reset()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        run.forward()
-        torch.cuda.synchronize()
-        t_f = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        run.backward(seed_p, seed_v)
-        torch.cuda.synchronize()
-        t_b = time.perf_counter() - t0
-        if best is None or t_f + t_b < best[0] + best[1]:
-            best = (t_f, t_b)
-    t_f, t_b = best
-    return {"workload": "dam_break_64k", "particles": sc.n, "steps": steps, "checkpoint_every": C,
-            "forward_s": t_f, "backward_with_recompute_s": t_b, "fwd_bwd_ratio_with_recompute": (t_f + t_b) / t_f,
-            "fwd_bwd_steps_per_s": steps / (t_f + t_b)}
+    out = {"workload": "dam_break_64k", "particles": sc.n, "steps": steps, "checkpoint_every": C}
+    for mode, budget in (("taped", None), ("recompute", 0)):
+        run = AdjointRollout(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, steps=steps, dt=dt,
+                             rebuild_every=K, checkpoint_every=C, brick=c["brick"], use_bricks=c["bricks"],
+                             tape_bytes=budget)
+        n = run.n
+        g = torch.Generator(device=run.sim.device).manual_seed(0)
+        seed_p = torch.randn((n, 4), device=run.sim.device, generator=g)
+        seed_v = torch.randn((n, 4), device=run.sim.device, generator=g)
+        best = None
+        for _ in range(2):
+            run.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run.forward()
+            torch.cuda.synchronize()
+            t_f = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            run.backward(seed_p, seed_v)
+            torch.cuda.synchronize()
+            t_b = time.perf_counter() - t0
+            if best is None or t_f + t_b < best[0] + best[1]:
+                best = (t_f, t_b)
+        t_f, t_b = best
+        out[mode] = {"taped_blocks": run.n_taped, "forward_s": t_f, "backward_s": t_b,
+                     "fwd_bwd_ratio": (t_f + t_b) / t_f, "fwd_bwd_steps_per_s": steps / (t_f + t_b)}
+        del run
+        torch.cuda.empty_cache()
+    return out
 
 
 def still_water_vs_oracle(steps=100):

@@ -1,13 +1,18 @@
 """Differentiable fixed-dt rollouts over the C ABI.
 
-The forward rollout keeps a checkpoint of the full particle state every
-`checkpoint_every` steps (a multiple of the rebuild interval K).  The reverse
-walks the checkpoint segments backwards; inside a segment it re-runs the
-forward once to recover the state before each rebuild, then for every K-step
-block (last to first): restores the pre-rebuild state, rebuilds (the same
-lists and the same sort permutation as the forward, the build being
-deterministic), re-runs the K steps keeping the stage states y^n and y*, and
-applies the reverse step
+The last K-step blocks of the rollout, as many as a device-memory budget
+allows (`tape_bytes`; by default half of the free device memory), are taped:
+their build writes its lists into buffers of their own and the forward keeps
+their sort permutation, particle order and stage states y^n and y*, so the
+reverse replays them without rebuilding or re-running anything.  For the
+blocks before them the forward keeps a checkpoint of the full particle state
+every `checkpoint_every` steps (a multiple of the rebuild interval K); the
+reverse walks those checkpoint segments backwards; inside a segment it
+re-runs the forward once to recover the state before each rebuild, then for
+every block (last to first): restores the pre-rebuild state, rebuilds (the
+same lists and the same sort permutation as the forward, the build being
+deterministic), re-runs the K steps keeping the stage states, and applies
+the reverse step
 
     sph_integrate_backward(1) -> sph_forces_backward(y*) ->
     sph_integrate_backward(0) -> sph_forces_backward(y^n)
@@ -31,7 +36,7 @@ from .sim import Simulation
 class AdjointRollout:
     def __init__(self, grid, params, cell, pos, vel, info, steps: int, dt: float, rebuild_every: int = 10,
                  checkpoint_every: int = 20, max_neibs: int = 128, device: str = "cuda", brick=None,
-                 use_bricks: bool = True):
+                 use_bricks: bool = True, tape_bytes: int | None = None):
         if checkpoint_every % rebuild_every != 0:
             raise ValueError("checkpoint_every must be a multiple of rebuild_every")
         self.steps = int(steps)
@@ -61,6 +66,44 @@ class AdjointRollout:
         self.initial = self._snapshot()
         self.checkpoints = {}
         self.n = n
+        # the tape: the last n_taped blocks (buffers allocated once, reused
+        # by every forward)
+        n_blocks = (self.steps + self.K - 1) // self.K
+        if tape_bytes is None:
+            free, _total = torch.cuda.mem_get_info(torch.device(dev))
+            tape_bytes = free // 2
+        per_block = self.tape_block_bytes()
+        self.n_taped = int(min(n_blocks, max(0, int(tape_bytes) // per_block)))
+        self.first_taped = n_blocks - self.n_taped  # block index
+        self.tape = {}
+        for b in range(self.first_taped, n_blocks):
+            self.tape[b] = {
+                "neibs": torch.empty_like(s.neibs), "neib_count": torch.empty_like(s.neib_count),
+                "neibs_brick": torch.empty_like(s.neibs_brick), "cell_start": torch.empty_like(s.cell_start),
+                "cell_end": torch.empty_like(s.cell_end), "perm": torch.empty_like(self.perm),
+                "cell": torch.empty_like(s.cell), "info": torch.empty_like(s.info), "stored": None,
+            }
+        self._own_lists = (s.neibs, s.neib_count, s.neibs_brick, s.cell_start, s.cell_end)
+
+    def tape_block_bytes(self) -> int:
+        """Device bytes of one taped block: its lists, cell ranges,
+        permutation and particle order, and the K steps' stage states."""
+        s = self.sim
+        lists = sum(t.numel() * t.element_size()
+                    for t in (s.neibs, s.neib_count, s.neibs_brick, s.cell_start, s.cell_end))
+        order = 3 * s.cell.numel() * s.cell.element_size()
+        stages = self.K * 4 * s.pos.numel() * s.pos.element_size()
+        return lists + order + stages
+
+    def _use_lists(self, bufs):
+        """Point the simulation's list buffers at bufs (neibs, neib_count,
+        neibs_brick, cell_start, cell_end): every call reads them from there."""
+        s = self.sim
+        s.neibs, s.neib_count, s.neibs_brick, s.cell_start, s.cell_end = bufs
+
+    def _tape_lists(self, b):
+        t = self.tape[b]
+        return (t["neibs"], t["neib_count"], t["neibs_brick"], t["cell_start"], t["cell_end"])
 
     # ------------------------------------------------------------ state helpers
     def _snapshot(self):
@@ -112,12 +155,24 @@ class AdjointRollout:
     def forward(self):
         s = self.sim
         self.fwd_status.zero_()
+        self._use_lists(self._own_lists)
+        stored = None
         for k in range(self.steps):
-            if k % self.C == 0:
+            b = k // self.K
+            if k % self.C == 0 and b < self.first_taped:
                 self.checkpoints[k] = self._snapshot()
             if k % self.K == 0:
-                s.build(status=self.fwd_status[k // self.K])
-            self._advance()
+                if b < self.first_taped:
+                    s.build(status=self.fwd_status[b])
+                    stored = None
+                else:
+                    t = self.tape[b]
+                    self._use_lists(self._tape_lists(b))
+                    s.build(perm_out=t["perm"], status=self.fwd_status[b])
+                    t["cell"].copy_(s.cell)
+                    t["info"].copy_(s.info)
+                    stored = t["stored"] = []
+            self._advance(stored)
         self._check_builds(self.fwd_status, (self.steps + self.K - 1) // self.K)
         return s
 
@@ -135,6 +190,15 @@ class AdjointRollout:
         abi.sph_forces_backward(s.g, s.p, pn, s.neibs, s.neib_count, s.max_neibs, self.gforce, self.gpos,
                                 self.gvel, self.grad_params, True, self.ws_back, **bk)
 
+    def _carry_back(self, perm):
+        """Adjoint across a rebuild: from the sorted order it made back to
+        the order before it."""
+        n = self.n
+        abi.sph_unpermute(n, perm, self.gpos, self.tmp_p)
+        abi.sph_unpermute(n, perm, self.gvel, self.tmp_v)
+        self.gpos, self.tmp_p = self.tmp_p, self.gpos
+        self.gvel, self.tmp_v = self.tmp_v, self.gvel
+
     def reverse_block(self, stored):
         """Reverse the steps of one block given their stored stage states."""
         for pos_n, vel_n, pos_s, vel_s in reversed(stored):
@@ -147,15 +211,27 @@ class AdjointRollout:
         dL/d(alpha, c0, nu) (device double[3])."""
         s = self.sim
         n = s.n
-        t_end = s.d_time.clone()
+        final = self._snapshot()  # the final state, put back at the end
         self.bwd_status.zero_()
         self.gpos.zero_()
         self.gvel.zero_()
         self.gpos[:n] = gpos_final
         self.gvel[:n] = gvel_final
         self.grad_params.zero_()
+        # the taped blocks, last to first: their lists, order and stage states
+        # as the forward left them
+        for b in sorted(self.tape, reverse=True):
+            t = self.tape[b]
+            self._use_lists(self._tape_lists(b))
+            s.cell.copy_(t["cell"])
+            s.info.copy_(t["info"])
+            self.reverse_block(t["stored"])
+            self._carry_back(t["perm"])
+        self._use_lists(self._own_lists)
+        # the blocks before them from the checkpoints
+        taped_from = self.first_taped * self.K
         for c in sorted(self.checkpoints, reverse=True):
-            end = min(c + self.C, self.steps)
+            end = min(c + self.C, self.steps, taped_from)
             blocks = list(range(c, end, self.K))
             self._restore(self.checkpoints[c])
             pre = {}
@@ -172,11 +248,10 @@ class AdjointRollout:
                 for _ in range(b, min(b + self.K, end)):
                     self._advance(stored)
                 self.reverse_block(stored)
-                abi.sph_unpermute(n, self.perm, self.gpos, self.tmp_p)
-                abi.sph_unpermute(n, self.perm, self.gvel, self.tmp_v)
-                self.gpos, self.tmp_p = self.tmp_p, self.gpos
-                self.gvel, self.tmp_v = self.tmp_v, self.gvel
-        s.d_time.copy_(t_end)
+                self._carry_back(self.perm)
+        self._restore(final)
+        if self.tape:
+            self._use_lists(self._tape_lists(max(self.tape)))
         self._check_builds(self.bwd_status, (self.steps + self.K - 1) // self.K)
         return self.gpos[:n], self.gvel[:n], self.grad_params
 
