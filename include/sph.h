@@ -188,7 +188,7 @@ typedef struct {
 const char *sph_status_string(sph_status s);
 
 /* ABI revision of this header (incremented on incompatible changes; 2: the
- * status word grew to SPH_STATUS_WORDS). */
+ * status word grew to SPH_STATUS_WORDS; 3: per-scene time steps). */
 int32_t sph_abi_version(void);
 
 /* Number of uint32 entries of a neighbour list for `capacity` particles:
@@ -442,6 +442,39 @@ size_t sph_dt_workspace_bytes(void);
  * Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
 sph_status sph_step_dt(const sph_params *params, const sph_particles *parts, const float *forces,
                        double *d_dt, void *workspace, size_t workspace_bytes, void *stream);
+
+/* Scenes that share one grid (see sph_grid) advance with time steps of their
+ * own, so that each evolves as it would alone.  cell_scene: device
+ * int32[n_cells], the scene of each cell (indexed by cell - cell_base);
+ * n_scenes in [1, SPH_MAX_SCENES].  A particle outside the grid, or in a
+ * cell whose entry is outside [0, n_scenes), belongs to no scene: it counts
+ * in no scene's step and sph_integrate_scenes leaves it as it is. */
+#define SPH_MAX_SCENES (1 << 20)
+
+/* Bytes of device workspace sph_step_dt_scenes needs (0 for an invalid
+ * n_scenes). */
+size_t sph_dt_scenes_workspace_bytes(int32_t n_scenes);
+
+/* sph_step_dt for each scene (section "The GPU in GPUSPH": the step is a
+ * device reduction, here one per scene): d_dt[s] (device double[n_scenes])
+ * = cfl * min(h / max c_i, sqrt(h / max |a_i + g|) [, 0.125 h^2 / nu]) over
+ * the fluid particles i of scene s, the maxima taken in float32 as in
+ * sph_step_dt (equal, bit for bit, to sph_step_dt on the scene alone); a
+ * scene with no fluid particle gets cfl * 0.125 h^2 / nu, or +inf.
+ * Errors: SPH_ERR_ARG, SPH_ERR_WORKSPACE. */
+sph_status sph_step_dt_scenes(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
+                              const float *forces, const int32_t *cell_scene, int32_t n_scenes,
+                              double *d_dt, void *workspace, size_t workspace_bytes, void *stream);
+
+/* sph_integrate with a step per scene: a particle advances with d_dt[s] of
+ * its scene s (d_dt: device double[n_scenes]); the corrector adds d_dt[s]
+ * to d_time[s] (device double[n_scenes]) when d_time is not NULL.
+ * Otherwise as sph_integrate.  Errors: SPH_ERR_ARG. */
+sph_status sph_integrate_scenes(const sph_grid *grid, const sph_params *params, int32_t stage,
+                                const double *d_dt, const int32_t *cell_scene, int32_t n_scenes,
+                                const sph_particles *state_n, const float *vel_star,
+                                const float *forces, sph_particles *out, double *d_time,
+                                void *stream);
 
 /* Number of listed pairs (i, j), i < n, whose float32 squared separation
  * (evaluated as in the neighbour predicate) is below (2h)^2 in float32:

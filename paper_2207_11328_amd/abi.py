@@ -30,8 +30,9 @@ EXPORTS = [
     "sph_dt_workspace_bytes", "sph_step_dt", "sph_count_interactions", "sph_integrate_backward",
     "sph_forces_backward_workspace_bytes", "sph_forces_backward", "sph_unpermute",
     "sph_diagnostics_workspace_bytes", "sph_reduce_diagnostics", "sph_count_missed_pairs",
-    "sph_forces_noalloc",
+    "sph_forces_noalloc", "sph_dt_scenes_workspace_bytes", "sph_step_dt_scenes", "sph_integrate_scenes",
 ]
+MAX_SCENES = 1 << 20
 
 
 class SphGrid(C.Structure):
@@ -93,6 +94,12 @@ def _load():
     L.sph_dt_workspace_bytes.restype = C.c_size_t
     L.sph_step_dt.argtypes = [P, P, P, P, P, C.c_size_t, P]
     L.sph_step_dt.restype = st
+    L.sph_dt_scenes_workspace_bytes.argtypes = [i32]
+    L.sph_dt_scenes_workspace_bytes.restype = C.c_size_t
+    L.sph_step_dt_scenes.argtypes = [P, P, P, P, P, i32, P, P, C.c_size_t, P]
+    L.sph_step_dt_scenes.restype = st
+    L.sph_integrate_scenes.argtypes = [P, P, i32, P, P, i32, P, P, P, P, P, P]
+    L.sph_integrate_scenes.restype = st
     L.sph_count_interactions.argtypes = [P, P, P, P, P, i32, P, P]
     L.sph_count_interactions.restype = st
     L.sph_count_missed_pairs.argtypes = [P, P, P, P, P, i32, i32, P, P]
@@ -235,6 +242,25 @@ def sph_integrate(params: SphParams, stage: int, d_dt, state_n: SphParticles, ve
 def sph_step_dt(params: SphParams, parts: SphParticles, forces, d_dt, workspace, stream=None):
     check(lib.sph_step_dt(C.byref(params), C.byref(parts), ptr(forces), ptr(d_dt), ptr(workspace),
                           workspace.numel() * workspace.element_size(), stream_ptr(stream)), "sph_step_dt")
+
+
+def sph_dt_scenes_workspace_bytes(n_scenes: int) -> int:
+    return int(lib.sph_dt_scenes_workspace_bytes(int(n_scenes)))
+
+
+def sph_step_dt_scenes(grid: SphGrid, params: SphParams, parts: SphParticles, forces, cell_scene, n_scenes: int,
+                       d_dt, workspace, stream=None):
+    check(lib.sph_step_dt_scenes(C.byref(grid), C.byref(params), C.byref(parts), ptr(forces), ptr(cell_scene),
+                                 int(n_scenes), ptr(d_dt), ptr(workspace),
+                                 workspace.numel() * workspace.element_size(), stream_ptr(stream)),
+          "sph_step_dt_scenes")
+
+
+def sph_integrate_scenes(grid: SphGrid, params: SphParams, stage: int, d_dt, cell_scene, n_scenes: int,
+                         state_n: SphParticles, vel_star, forces, out: SphParticles, d_time=None, stream=None):
+    check(lib.sph_integrate_scenes(C.byref(grid), C.byref(params), int(stage), ptr(d_dt), ptr(cell_scene),
+                                   int(n_scenes), C.byref(state_n), ptr(vel_star), ptr(forces), C.byref(out),
+                                   ptr(d_time), stream_ptr(stream)), "sph_integrate_scenes")
 
 
 def sph_count_interactions(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count,

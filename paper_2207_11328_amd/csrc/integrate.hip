@@ -272,6 +272,107 @@ extern "C" sph_status sph_integrate_backward(const sph_params *params, int32_t s
     return SPH_OK;
 }
 
+// Scenes sharing one grid (batching): scene of a particle in cell c is
+// cell_scene[c - cell_base]; particles outside the grid, and cells whose
+// entry is not in [0, n_scenes), have none.
+
+// The predictor/corrector with the step of each particle's scene; thread k <
+// n_scenes of the corrector also advances scene k's clock.
+__global__ __launch_bounds__(kThreads) void k_integrate_scenes(
+    int n, int stage, const double *__restrict__ d_dt, const int32_t *__restrict__ cell_scene, int cell_base,
+    int n_scenes, const int32_t *__restrict__ cell, const uint32_t *__restrict__ info, const float4 *pos_n,
+    const float4 *vel_n, const float4 *__restrict__ vel_star, const float4 *__restrict__ forces, float4 *pos_out,
+    float4 *vel_out, float gx, float gy, float gz, double *__restrict__ d_time)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (stage == 1 && d_time && i < n_scenes) d_time[i] += d_dt[i];
+    if (i >= n) return;
+    float4 p = pos_n[i];
+    float4 v = vel_n[i];
+    const int c = cell[i];
+    const int sc = c >= 0 ? cell_scene[c - cell_base] : -1;
+    if ((unsigned)sc < (unsigned)n_scenes) {  // (a cell of no scene: left as it is)
+        const double dt = d_dt[sc];
+        const float tau = (float)(stage == 0 ? 0.5 * dt : dt);
+        const float4 f = forces[i];
+        if (ptype(info[i]) != kBoundary) {
+            const float4 ua = stage == 0 ? v : vel_star[i];
+            p.x = fmaf(tau, ua.x, p.x);
+            p.y = fmaf(tau, ua.y, p.y);
+            p.z = fmaf(tau, ua.z, p.z);
+            v.x = fmaf(tau, f.x + gx, v.x);
+            v.y = fmaf(tau, f.y + gy, v.y);
+            v.z = fmaf(tau, f.z + gz, v.z);
+        }
+        v.w = fmaf(tau, f.w, v.w);
+    }
+    pos_out[i] = p;
+    vel_out[i] = v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_zero_u32(int n, uint32_t *__restrict__ p)
+{
+    for (int k = blockIdx.x * kThreads + threadIdx.x; k < n; k += gridDim.x * kThreads) p[k] = 0u;
+}
+
+// Per-scene maxima of the sound speed and of |a + g| over fluid particles,
+// as float32 bit patterns (non-negative floats order as their bits), in
+// m[2 s] and m[2 s + 1]: the lanes of a wave that share a scene are reduced
+// together and one of them takes the atomic maximum (particles are sorted
+// by cell, so a wave seldom holds more than one scene).  A maximum does not
+// depend on the order of the updates.
+__global__ __launch_bounds__(kThreads) void k_dt_scenes_partial(
+    int n, const int32_t *__restrict__ cell, const uint32_t *__restrict__ info, const float4 *__restrict__ vel,
+    const float4 *__restrict__ forces, const int32_t *__restrict__ cell_scene, int cell_base, int n_scenes,
+    float rho0, float inv_rho0, float c0, float gx, float gy, float gz, uint32_t *__restrict__ m)
+{
+    const int lane = threadIdx.x % kWave;
+    // (every lane runs the same number of iterations: the wave operations below need them all)
+    const int stride = gridDim.x * kThreads;
+    for (int i0 = blockIdx.x * kThreads; i0 < n; i0 += stride) {
+        const int i = i0 + threadIdx.x;
+        int sc = -1;
+        float c = 0.0f, a = 0.0f;
+        if (i < n && cell[i] >= 0 && ptype(info[i]) != kBoundary) sc = cell_scene[cell[i] - cell_base];
+        if ((unsigned)sc >= (unsigned)n_scenes) sc = -1;  // a cell of no scene counts in none
+        if (sc >= 0) {
+            const float d = (vel[i].w - rho0) * inv_rho0;
+            const float b = 1.0f + d;
+            c = fmaxf(c0 * b * b * b, 0.0f);
+            const float4 f = forces[i];
+            const float fx = f.x + gx, fy = f.y + gy, fz = f.z + gz;
+            a = fmaxf(__builtin_sqrtf(fx * fx + fy * fy + fz * fz), 0.0f);
+        }
+        uint64_t pending = __builtin_amdgcn_ballot_w64(sc >= 0);
+        while (pending) {  // uniform
+            const int leader = __builtin_ffsll((long long)pending) - 1;
+            const int s = __shfl(sc, leader);
+            const bool mine = sc == s;
+            const float cm = wave_max(mine ? c : 0.0f), am = wave_max(mine ? a : 0.0f);
+            if (lane == leader) {
+                atomicMax(&m[2 * s], __float_as_uint(cm));
+                atomicMax(&m[2 * s + 1], __float_as_uint(am));
+            }
+            pending &= ~__builtin_amdgcn_ballot_w64(mine);
+        }
+    }
+}
+
+// dt of each scene from its maxima, as k_dt_final does for one scene.
+__global__ __launch_bounds__(kThreads) void k_dt_scenes_final(int n_scenes, const uint32_t *__restrict__ m,
+                                                              double h, double nu, double cfl,
+                                                              double *__restrict__ d_dt)
+{
+    const int s = blockIdx.x * kThreads + threadIdx.x;
+    if (s >= n_scenes) return;
+    const double c = (double)__uint_as_float(m[2 * s]), a = (double)__uint_as_float(m[2 * s + 1]);
+    double dt = INFINITY;
+    if (c > 0.0) dt = h / c;
+    if (a > 0.0) dt = fmin(dt, sqrt(h / a));
+    if (nu > 0.0) dt = fmin(dt, 0.125 * h * h / nu);
+    d_dt[s] = cfl * dt;
+}
+
 extern "C" sph_status sph_integrate(const sph_params *params, int32_t stage, const double *d_dt,
                                     const sph_particles *state_n, const float *vel_star, const float *forces,
                                     sph_particles *out, double *d_time, void *stream)
@@ -319,6 +420,73 @@ extern "C" sph_status sph_step_dt(const sph_params *params, const sph_particles 
     return SPH_OK;
 }
 
+extern "C" size_t sph_dt_scenes_workspace_bytes(int32_t n_scenes)
+{
+    if (n_scenes < 1 || n_scenes > SPH_MAX_SCENES) return 0;
+    return (size_t)(2 * sizeof(uint32_t) * (size_t)n_scenes + 256);
+}
+
+static bool scene_table_ok(const sph_grid *grid, const int32_t *cell_scene, int32_t n_scenes)
+{
+    if (!grid || !cell_scene || n_scenes < 1 || n_scenes > SPH_MAX_SCENES) return false;
+    const int64_t n_cells = (int64_t)grid->ncell[0] * grid->ncell[1] * grid->ncell[2];
+    return n_cells > 0 && n_cells <= INT32_MAX;
+}
+
+extern "C" sph_status sph_step_dt_scenes(const sph_grid *grid, const sph_params *params,
+                                         const sph_particles *parts, const float *forces,
+                                         const int32_t *cell_scene, int32_t n_scenes, double *d_dt,
+                                         void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!params || !parts || !d_dt || !scene_table_ok(grid, cell_scene, n_scenes)) return SPH_ERR_ARG;
+    const int n = parts->n;
+    if (n < 0 || parts->capacity < n) return SPH_ERR_ARG;
+    if (n > 0 && (!parts->cell || !parts->vel || !parts->info || !forces)) return SPH_ERR_ARG;
+    if (!(params->h > 0.0f) || !(params->rho0 > 0.0f) || params->gamma != 7.0f) return SPH_ERR_ARG;
+    if (!workspace || workspace_bytes < sph_dt_scenes_workspace_bytes(n_scenes)) return SPH_ERR_WORKSPACE;
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t *m = (uint32_t *)workspace;
+    const unsigned zb = sph_blocks(2 * n_scenes, kThreads);
+    k_zero_u32<<<zb, kThreads, 0, s>>>(2 * n_scenes, m);
+    if (n > 0) {
+        const unsigned want = sph_blocks(n, kThreads);
+        const unsigned blocks = want < (unsigned)kDtBlocks ? want : (unsigned)kDtBlocks;
+        k_dt_scenes_partial<<<blocks, kThreads, 0, s>>>(n, parts->cell, parts->info, (const float4 *)parts->vel,
+                                                         (const float4 *)forces, cell_scene, grid->cell_base,
+                                                         n_scenes, params->rho0, (float)(1.0 / (double)params->rho0),
+                                                         params->c0, params->g[0], params->g[1], params->g[2], m);
+    }
+    k_dt_scenes_final<<<sph_blocks(n_scenes, kThreads), kThreads, 0, s>>>(n_scenes, m, params->h, params->nu,
+                                                                          params->cfl, d_dt);
+    SPH_CHECK_LAUNCH();
+    return SPH_OK;
+}
+
+extern "C" sph_status sph_integrate_scenes(const sph_grid *grid, const sph_params *params, int32_t stage,
+                                           const double *d_dt, const int32_t *cell_scene, int32_t n_scenes,
+                                           const sph_particles *state_n, const float *vel_star,
+                                           const float *forces, sph_particles *out, double *d_time, void *stream)
+{
+    if (!params || !d_dt || !state_n || !out || (stage != 0 && stage != 1)) return SPH_ERR_ARG;
+    if (!scene_table_ok(grid, cell_scene, n_scenes)) return SPH_ERR_ARG;
+    const int n = state_n->n;
+    if (n < 0 || state_n->capacity < n || out->capacity < n) return SPH_ERR_ARG;
+    if (n > 0) {
+        if (!state_n->cell || !state_n->pos || !state_n->vel || !state_n->info || !forces) return SPH_ERR_ARG;
+        if (!out->pos || !out->vel) return SPH_ERR_ARG;
+        if (stage == 1 && !vel_star) return SPH_ERR_ARG;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int threads = n > n_scenes ? n : n_scenes;
+    k_integrate_scenes<<<sph_blocks(threads, kThreads), kThreads, 0, s>>>(
+        n, stage, d_dt, cell_scene, grid->cell_base, n_scenes, state_n->cell, state_n->info,
+        (const float4 *)state_n->pos, (const float4 *)state_n->vel, (const float4 *)vel_star,
+        (const float4 *)forces, (float4 *)out->pos, (float4 *)out->vel, params->g[0], params->g[1], params->g[2],
+        d_time);
+    SPH_CHECK_LAUNCH();
+    return SPH_OK;
+}
+
 extern "C" const char *sph_status_string(sph_status st)
 {
     switch (st) {
@@ -333,4 +501,4 @@ extern "C" const char *sph_status_string(sph_status st)
     return "SPH: unknown status";
 }
 
-extern "C" int32_t sph_abi_version(void) { return 2; }
+extern "C" int32_t sph_abi_version(void) { return 3; }

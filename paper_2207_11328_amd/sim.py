@@ -30,7 +30,7 @@ class Simulation:
 
     def __init__(self, grid, params, cell, pos, vel, info, max_neibs: int = 128, capacity: int | None = None,
                  rebuild_every: int = 10, device: str = "cuda", dt_fixed: float | None = None, cell_alpha=None,
-                 brick=None, use_bricks: bool = True):
+                 brick=None, use_bricks: bool = True, cell_scene=None):
         n = int(np.asarray(cell).shape[0])
         cap = int(capacity or n)
         if cap < n or cap > abi.MAX_CAPACITY:
@@ -67,10 +67,22 @@ class Simulation:
         self.missed = z(4, torch.int64)
         self.track_missed = False
         self.ws_build = z(abi.sph_build_workspace_bytes(cap, self.n_cells), torch.uint8)
-        self.ws_dt = z(abi.sph_dt_workspace_bytes(), torch.uint8)
+        # scenes sharing the grid, each with its own time step and clock
+        # (cell_scene: int32 per cell), or one scene
+        self.cell_scene = None
+        self.n_scenes = 1
+        if cell_scene is not None:
+            cs_np = np.ascontiguousarray(cell_scene, np.int32)
+            if cs_np.shape != (self.n_cells,):
+                raise ValueError("cell_scene must hold one scene index per cell")
+            self.n_scenes = int(cs_np.max()) + 1
+            self.cell_scene = torch.from_numpy(cs_np).to(dev)
+            self.ws_dt = z(abi.sph_dt_scenes_workspace_bytes(self.n_scenes), torch.uint8)
+        else:
+            self.ws_dt = z(abi.sph_dt_workspace_bytes(), torch.uint8)
         self.ws_forces = z(abi.sph_forces_workspace_bytes(cap, self.n_cells), torch.uint8)
-        self.d_dt = z(1, torch.float64)
-        self.d_time = z(1, torch.float64)
+        self.d_dt = z(self.n_scenes, torch.float64)
+        self.d_time = z(self.n_scenes, torch.float64)
         self.count = z(1, torch.int64)
         self.dt_fixed = dt_fixed
         if dt_fixed is not None:
@@ -150,10 +162,21 @@ class Simulation:
         return out
 
     def step_dt(self, stream=None):
-        abi.sph_step_dt(self.p, self.parts, self.forces_n, self.d_dt, self.ws_dt, stream)
+        if self.cell_scene is not None:
+            abi.sph_step_dt_scenes(self.g, self.p, self.parts, self.forces_n, self.cell_scene, self.n_scenes,
+                                   self.d_dt, self.ws_dt, stream)
+        else:
+            abi.sph_step_dt(self.p, self.parts, self.forces_n, self.d_dt, self.ws_dt, stream)
 
     def integrate(self, stage: int, stream=None):
-        if stage == 0:
+        if self.cell_scene is not None:
+            if stage == 0:
+                abi.sph_integrate_scenes(self.g, self.p, 0, self.d_dt, self.cell_scene, self.n_scenes, self.parts,
+                                         None, self.forces_n, self.parts_star, None, stream)
+            else:
+                abi.sph_integrate_scenes(self.g, self.p, 1, self.d_dt, self.cell_scene, self.n_scenes, self.parts,
+                                         self.vel_star, self.forces_star, self.parts, self.d_time, stream)
+        elif stage == 0:
             abi.sph_integrate(self.p, 0, self.d_dt, self.parts, None, self.forces_n, self.parts_star,
                               None, stream)
         else:
@@ -274,5 +297,8 @@ class Simulation:
         return np.ascontiguousarray(nb), cnt
 
     @property
-    def time(self) -> float:
+    def time(self):
+        """Simulated time (host; syncs): a float, or one per scene."""
+        if self.cell_scene is not None:
+            return self.d_time.cpu().numpy()
         return float(self.d_time.item())

@@ -61,7 +61,7 @@ int main(void) {
 
 
 def test_host_only_entry_points(abi):
-    assert abi.lib.sph_abi_version() == 2
+    assert abi.lib.sph_abi_version() == 3
     for code in range(4):
         assert abi.lib.sph_status_string(code)
     a = abi.sph_build_workspace_bytes(1000, 500)
@@ -70,6 +70,9 @@ def test_host_only_entry_points(abi):
     assert 0 < a < b and a < c
     assert a % 256 == 0
     assert abi.sph_dt_workspace_bytes() > 0
+    assert abi.sph_dt_scenes_workspace_bytes(0) == 0
+    assert abi.sph_dt_scenes_workspace_bytes(abi.MAX_SCENES + 1) == 0
+    assert 0 < abi.sph_dt_scenes_workspace_bytes(1) < abi.sph_dt_scenes_workspace_bytes(128)
 
 
 def test_brick_shapes(abi):
@@ -98,6 +101,10 @@ def test_argument_errors_return_before_any_launch(abi):
     assert abi.lib.sph_integrate(None, 0, None, None, None, None, None, None, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_integrate(C.byref(p), 2, None, None, None, None, None, None, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_step_dt(None, None, None, None, None, 0, None) == abi.SPH_ERR_ARG
+    # per-scene steps: no table, or a scene count outside [1, SPH_MAX_SCENES]
+    assert abi.lib.sph_step_dt_scenes(None, None, None, None, None, 1, None, None, 0, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_integrate_scenes(None, None, 0, None, None, 1, None, None, None, None, None,
+                                        None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_count_interactions(None, None, None, None, None, 128, None, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_count_missed_pairs(None, None, None, None, None, 128, 0, None, None) == abi.SPH_ERR_ARG
     # a phase other than 0 or 1, and a missing output, on otherwise valid arguments
@@ -108,6 +115,18 @@ def test_argument_errors_return_before_any_launch(abi):
     p2 = abi.SphParams()
     p2.h, p2.r_search, p2.rho0, p2.gamma, p2.c0 = 0.026, 0.06, 1000.0, 7.0, 20.0
     empty = abi.SphParticles(0, 0, None, None, None, None)
+    table = (C.c_int32 * 64)()
+    dts = (C.c_double * 2)()
+    ws = (C.c_uint8 * 4096)()
+    for bad in (0, abi.MAX_SCENES + 1):
+        assert abi.lib.sph_step_dt_scenes(C.byref(g2), C.byref(p2), C.byref(empty), None, table, bad, dts, ws,
+                                          4096, None) == abi.SPH_ERR_ARG
+        assert abi.lib.sph_integrate_scenes(C.byref(g2), C.byref(p2), 0, dts, table, bad, C.byref(empty), None,
+                                            None, C.byref(empty), None, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_step_dt_scenes(C.byref(g2), C.byref(p2), C.byref(empty), None, table, 2, dts, ws, 8,
+                                      None) == abi.SPH_ERR_WORKSPACE
+    assert abi.lib.sph_integrate_scenes(C.byref(g2), C.byref(p2), 2, dts, table, 2, C.byref(empty), None, None,
+                                        C.byref(empty), None, None) == abi.SPH_ERR_ARG
     out = (C.c_longlong * 4)()
     for phase in (-1, 2):
         assert abi.lib.sph_count_missed_pairs(C.byref(g2), C.byref(p2), C.byref(empty), None, None, 128, phase,

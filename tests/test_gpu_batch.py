@@ -5,8 +5,11 @@ and the HIP-graph capture of a rebuild unit.
 * parity: each scene's batched derivatives against the FP64 oracle run on
   that scene alone, with its own alpha (1e-5 of the pair-term scale);
 * batched == single: 20 fixed-dt steps of the batch equal, bit for bit, the
-  same 20 steps of each scene run alone on its own grid;
-* independence: perturbing one scene leaves every other scene bit-identical;
+  same 20 steps of each scene run alone on its own grid, and so do 30 steps
+  with each scene's own adaptive dt (per-scene time steps and clocks);
+* per-scene dt against the oracle's dt of each scene alone;
+* independence: perturbing one scene leaves every other scene bit-identical,
+  with fixed and with adaptive dt;
 * graph: replays of a captured 10-step unit equal the eager steps bit for bit,
   with eager work and synchronisations between replays."""
 import numpy as np
@@ -32,10 +35,10 @@ def _tanks(n=6, seed=9):
     return S.batched_tanks(n_scenes=n, seed=seed, n_min=400, n_max=3000)
 
 
-def _batch_sim(stacked, alpha, dt=None):
+def _batch_sim(stacked, alpha, dt=None, scenes=True):
     from paper_2207_11328_amd.sim import Simulation
     return Simulation(stacked.grid, stacked.params, stacked.cell, stacked.pos, stacked.vel, stacked.info,
-                      cell_alpha=alpha, dt_fixed=dt)
+                      cell_alpha=alpha, dt_fixed=dt, cell_scene=S.scene_cells(stacked) if scenes else None)
 
 
 def _by_id(sim):
@@ -112,7 +115,7 @@ def test_graph_replay_equals_eager():
     graph.capture_unit()
     torch_sync()
     # capturing ran nothing
-    assert graph.steps_done == 0 and float(graph.d_time.item()) == 0.0
+    assert graph.steps_done == 0 and bool(torch.all(graph.d_time == 0.0))
     for unit in range(3):
         eager.run(10)
         graph.replay_units(1)
@@ -122,4 +125,79 @@ def test_graph_replay_equals_eager():
         assert torch.equal(eager.d_time, graph.d_time)
         assert torch.equal(eager.neibs, graph.neibs)
         del junk
-    log("graph replay == eager over 3 units, t = %.6e s" % graph.time)
+    log("graph replay == eager over 3 units, t = %s s" % np.array2string(graph.time, precision=6))
+
+
+def test_per_scene_dt_matches_oracle():
+    """sph_step_dt_scenes: each tank's step from its own particles, against
+    the oracle's dt of that tank alone (1e-5), and equal to the single-scene
+    step of the tank on its own grid bit for bit."""
+    from paper_2207_11328_amd.sim import Simulation
+    tanks = _tanks()
+    stacked, alpha, subs, ranges = S.stack_scenes(tanks)
+    sim = _batch_sim(stacked, alpha)
+    sim.build()
+    sim.forces()
+    sim.step_dt()
+    torch_sync()
+    dts = sim.d_dt.cpu().numpy()
+    assert dts.shape == (len(tanks),)
+    for k, (t, sub, rng) in enumerate(zip(tanks, subs, ranges)):
+        one = S.scene_on_subgrid(stacked, sub, rng)
+        ob = O.build_f32(one.grid, t.params, one.cell, one.pos, one.vel, one.info)
+        sto = O.State.lift(ob["cell"], ob["pos"], ob["vel"], ob["info"])
+        acc, _, _, _, _ = O.forces(one.grid, t.params, sto, ob["lists"])
+        dt_o = O.dt(t.params, sto, acc)
+        s1 = Simulation(one.grid, t.params, one.cell, one.pos, one.vel, one.info)
+        s1.build()
+        s1.forces()
+        s1.step_dt()
+        torch_sync()
+        dt_1 = float(s1.d_dt.item())
+        log("scene %d: dt batched %.9e alone %.9e oracle %.9e" % (k, dts[k], dt_1, dt_o))
+        assert abs(dts[k] - dt_o) <= 1e-5 * dt_o
+        assert dts[k] == dt_1
+    # the tanks' steps differ: one shared step would couple them
+    assert len(set(dts.tolist())) > 1
+
+
+def test_adaptive_dt_batched_equals_single_and_independent():
+    """30 steps with each tank's own adaptive dt (per-scene steps and clocks):
+    every tank equals, bit for bit, the same tank run alone with its own
+    adaptive dt, and perturbing one tank leaves the others' bits and clocks
+    unchanged."""
+    from paper_2207_11328_amd.sim import Simulation
+    tanks = _tanks()
+    stacked, alpha, subs, ranges = S.stack_scenes(tanks)
+    steps = 30
+    sim = _batch_sim(stacked, alpha)
+    sim.run(steps)
+    torch_sync()
+    clocks = sim.time
+    ids_b, pos_b, vel_b = _by_id(sim)
+    for k, (t, sub, rng) in enumerate(zip(tanks, subs, ranges)):
+        one = S.scene_on_subgrid(stacked, sub, rng)
+        s1 = Simulation(one.grid, t.params, one.cell, one.pos, one.vel, one.info)
+        s1.run(steps)
+        torch_sync()
+        ids_1, pos_1, vel_1 = _by_id(s1)
+        first, count = rng
+        sel = slice(first, first + count)
+        assert np.array_equal(ids_b[sel], ids_1)
+        assert np.array_equal(pos_b[sel].view(np.uint32), pos_1.view(np.uint32)), k
+        assert np.array_equal(vel_b[sel].view(np.uint32), vel_1.view(np.uint32)), k
+        assert clocks[k] == s1.time, k
+    log("per-scene clocks after %d steps: %s" % (steps, np.array2string(clocks, precision=6)))
+    pert = stacked.copy()
+    first, count = ranges[2]
+    pert.vel[first:first + count, :3] += np.float32(0.05)
+    sim2 = _batch_sim(pert, alpha)
+    sim2.run(steps)
+    torch_sync()
+    clocks2 = sim2.time
+    ids_p, pos_p, vel_p = _by_id(sim2)
+    for k, (first, count) in enumerate(ranges):
+        sel = slice(first, first + count)
+        same = np.array_equal(pos_p[sel].view(np.uint32), pos_b[sel].view(np.uint32)) and \
+            np.array_equal(vel_p[sel].view(np.uint32), vel_b[sel].view(np.uint32)) and clocks2[k] == clocks[k]
+        assert same == (k != 2), k

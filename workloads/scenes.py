@@ -481,6 +481,18 @@ def stack_scenes(scenes, gap_cells: int = 2):
     return sc, alpha, sub_grids, ranges
 
 
+def scene_cells(stacked: Scene) -> np.ndarray:
+    """Scene index of every cell of a grid made by stack_scenes: scene k
+    owns the cell layers from its first one up to the next scene's (its gap
+    layers included), the last scene up to the top."""
+    z0 = list(stacked.meta["z0"])
+    nx, ny, nz = (int(v) for v in stacked.grid.ncell)
+    layer = np.zeros(nz, np.int32)
+    for k, z in enumerate(z0):
+        layer[z:] = k
+    return np.repeat(layer, nx * ny).astype(np.int32)
+
+
 def scene_on_subgrid(stacked: Scene, sub_grid: Grid, rng):
     """The particles [first, first + count) of a stacked scene re-encoded on
     their own sub-grid (same offsets, local cells), with their own ids."""
