@@ -59,12 +59,11 @@ __global__ __launch_bounds__(kThreads) void k_dt_partial(int n, const int32_t *_
     float cmax = 0.0f, amax = 0.0f;
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) {
         if (cell[i] < 0 || ptype(info[i]) == kBoundary) continue;
-        const float d = (vel[i].w - rho0) * inv_rho0;
-        const float a = 1.0f + d;
-        cmax = fmaxf(cmax, c0 * a * a * a);
         const float4 f = forces[i];
-        const float fx = f.x + gx, fy = f.y + gy, fz = f.z + gz;
-        amax = fmaxf(amax, __builtin_sqrtf(fx * fx + fy * fy + fz * fz));
+        float c, a;
+        dt_speeds(vel[i].w, f.x, f.y, f.z, rho0, inv_rho0, c0, gx, gy, gz, c, a);
+        cmax = fmaxf(cmax, c);
+        amax = fmaxf(amax, a);
     }
     cmax = wave_max(cmax);
     amax = wave_max(amax);
@@ -100,11 +99,7 @@ __global__ __launch_bounds__(kThreads) void k_dt_final(int np, const float2 *__r
             c = fmax(c, (double)w[k].x);
             a = fmax(a, (double)w[k].y);
         }
-        double dt = INFINITY;
-        if (c > 0.0) dt = h / c;
-        if (a > 0.0) dt = fmin(dt, sqrt(h / a));
-        if (nu > 0.0) dt = fmin(dt, 0.125 * h * h / nu);
-        *d_dt = cfl * dt;
+        *d_dt = dt_from_maxima(c, a, h, nu, cfl);
     }
 }
 
@@ -317,31 +312,35 @@ __global__ __launch_bounds__(kThreads) void k_zero_u32(int n, uint32_t *__restri
 
 // Per-scene maxima of the sound speed and of |a + g| over fluid particles,
 // as float32 bit patterns (non-negative floats order as their bits), in
-// m[2 s] and m[2 s + 1]: the lanes of a wave that share a scene are reduced
-// together and one of them takes the atomic maximum (particles are sorted
-// by cell, so a wave seldom holds more than one scene).  A maximum does not
-// depend on the order of the updates.
+// m[2 s] and m[2 s + 1].  A wave takes kDtChunk consecutive particles: they
+// are sorted by cell, and a scene is a run of cells, so the chunk meets its
+// scenes one after the other.  The lanes that share a scene are reduced
+// together, the wave keeps the running maxima of its current scene, and it
+// takes the device-wide maximum once per scene it leaves (a few atomics per
+// chunk, spread over the scenes).  A maximum does not depend on the order of
+// the updates.
+constexpr int kDtChunk = 8 * kWave;
 __global__ __launch_bounds__(kThreads) void k_dt_scenes_partial(
     int n, const int32_t *__restrict__ cell, const uint32_t *__restrict__ info, const float4 *__restrict__ vel,
     const float4 *__restrict__ forces, const int32_t *__restrict__ cell_scene, int cell_base, int n_scenes,
     float rho0, float inv_rho0, float c0, float gx, float gy, float gz, uint32_t *__restrict__ m)
 {
     const int lane = threadIdx.x % kWave;
-    // (every lane runs the same number of iterations: the wave operations below need them all)
-    const int stride = gridDim.x * kThreads;
-    for (int i0 = blockIdx.x * kThreads; i0 < n; i0 += stride) {
-        const int i = i0 + threadIdx.x;
+    const int wave = (int)((blockIdx.x * kThreads + threadIdx.x) / kWave);
+    const int begin = wave * kDtChunk, end = min(begin + kDtChunk, n);
+    int cur = -1;  // the wave's current scene and its running maxima (uniform)
+    float cc = 0.0f, ca = 0.0f;
+    for (int i0 = begin; i0 < end; i0 += kWave) {  // uniform
+        const int i = i0 + lane;
         int sc = -1;
         float c = 0.0f, a = 0.0f;
-        if (i < n && cell[i] >= 0 && ptype(info[i]) != kBoundary) sc = cell_scene[cell[i] - cell_base];
+        if (i < end && cell[i] >= 0 && ptype(info[i]) != kBoundary) sc = cell_scene[cell[i] - cell_base];
         if ((unsigned)sc >= (unsigned)n_scenes) sc = -1;  // a cell of no scene counts in none
         if (sc >= 0) {
-            const float d = (vel[i].w - rho0) * inv_rho0;
-            const float b = 1.0f + d;
-            c = fmaxf(c0 * b * b * b, 0.0f);
             const float4 f = forces[i];
-            const float fx = f.x + gx, fy = f.y + gy, fz = f.z + gz;
-            a = fmaxf(__builtin_sqrtf(fx * fx + fy * fy + fz * fz), 0.0f);
+            dt_speeds(vel[i].w, f.x, f.y, f.z, rho0, inv_rho0, c0, gx, gy, gz, c, a);
+            c = fmaxf(c, 0.0f);  // (NaN or negative: no bound, as in the one-scene maxima)
+            a = fmaxf(a, 0.0f);
         }
         uint64_t pending = __builtin_amdgcn_ballot_w64(sc >= 0);
         while (pending) {  // uniform
@@ -349,12 +348,24 @@ __global__ __launch_bounds__(kThreads) void k_dt_scenes_partial(
             const int s = __shfl(sc, leader);
             const bool mine = sc == s;
             const float cm = wave_max(mine ? c : 0.0f), am = wave_max(mine ? a : 0.0f);
-            if (lane == leader) {
-                atomicMax(&m[2 * s], __float_as_uint(cm));
-                atomicMax(&m[2 * s + 1], __float_as_uint(am));
+            if (s != cur) {
+                if (cur >= 0 && lane == 0) {
+                    atomicMax(&m[2 * cur], __float_as_uint(cc));
+                    atomicMax(&m[2 * cur + 1], __float_as_uint(ca));
+                }
+                cur = s;
+                cc = cm;
+                ca = am;
+            } else {
+                cc = fmaxf(cc, cm);
+                ca = fmaxf(ca, am);
             }
             pending &= ~__builtin_amdgcn_ballot_w64(mine);
         }
+    }
+    if (cur >= 0 && lane == 0) {
+        atomicMax(&m[2 * cur], __float_as_uint(cc));
+        atomicMax(&m[2 * cur + 1], __float_as_uint(ca));
     }
 }
 
@@ -366,11 +377,7 @@ __global__ __launch_bounds__(kThreads) void k_dt_scenes_final(int n_scenes, cons
     const int s = blockIdx.x * kThreads + threadIdx.x;
     if (s >= n_scenes) return;
     const double c = (double)__uint_as_float(m[2 * s]), a = (double)__uint_as_float(m[2 * s + 1]);
-    double dt = INFINITY;
-    if (c > 0.0) dt = h / c;
-    if (a > 0.0) dt = fmin(dt, sqrt(h / a));
-    if (nu > 0.0) dt = fmin(dt, 0.125 * h * h / nu);
-    d_dt[s] = cfl * dt;
+    d_dt[s] = dt_from_maxima(c, a, h, nu, cfl);
 }
 
 extern "C" sph_status sph_integrate(const sph_params *params, int32_t stage, const double *d_dt,
@@ -449,8 +456,8 @@ extern "C" sph_status sph_step_dt_scenes(const sph_grid *grid, const sph_params 
     const unsigned zb = sph_blocks(2 * n_scenes, kThreads);
     k_zero_u32<<<zb, kThreads, 0, s>>>(2 * n_scenes, m);
     if (n > 0) {
-        const unsigned want = sph_blocks(n, kThreads);
-        const unsigned blocks = want < (unsigned)kDtBlocks ? want : (unsigned)kDtBlocks;
+        const int waves = (n + kDtChunk - 1) / kDtChunk;
+        const unsigned blocks = sph_blocks(waves * kWave, kThreads);
         k_dt_scenes_partial<<<blocks, kThreads, 0, s>>>(n, parts->cell, parts->info, (const float4 *)parts->vel,
                                                          (const float4 *)forces, cell_scene, grid->cell_base,
                                                          n_scenes, params->rho0, (float)(1.0 / (double)params->rho0),

@@ -335,11 +335,47 @@ __device__ __forceinline__ int brick_at(const int32_t *active, int cap_ids, int 
     return kb < nh ? active[1 + kb] : active[cap_ids - (kb - nh)];
 }
 
+// The two speeds of the adaptive time step of one fluid particle: its sound
+// speed c = c0 (rho/rho0)^3 (gamma = 7) and |a + g| from its derivatives,
+// in float32 with a fixed operation order (every kernel that takes the
+// step's maxima evaluates them with this one definition, so they agree bit
+// for bit).
+__device__ __forceinline__ void dt_speeds(float rho, float fx, float fy, float fz, float rho0, float inv_rho0,
+                                          float c0, float gx, float gy, float gz, float &c, float &a)
+{
+#pragma clang fp contract(off)
+    const float d = (rho - rho0) * inv_rho0;
+    const float b = 1.0f + d;
+    c = c0 * b * b * b;
+    const float x = fx + gx, y = fy + gy, z = fz + gz;
+    a = __builtin_sqrtf(x * x + y * y + z * z);
+}
+
+// The adaptive step from the maxima of dt_speeds over the fluid particles
+// (float32 maxima, taken to double): cfl min(h / c, sqrt(h / a)
+// [, 0.125 h^2 / nu]); +inf scaled by cfl when nothing bounds it.
+__device__ __forceinline__ double dt_from_maxima(double c, double a, double h, double nu, double cfl)
+{
+    double dt = INFINITY;
+    if (c > 0.0) dt = h / c;
+    if (a > 0.0) dt = fmin(dt, sqrt(h / a));
+    if (nu > 0.0) dt = fmin(dt, 0.125 * h * h / nu);
+    return cfl * dt;
+}
+
 // A counter zeroed by a kernel (graph-capturable, no memset node).
 template <typename T>
 __global__ void k_zero_one(T *p)
 {
     *p = T(0);
+}
+
+// A few words zeroed by one thread (graph-capturable, no memset node).
+template <typename T, int N>
+__global__ void k_zero_few(T *p)
+{
+#pragma unroll
+    for (int k = 0; k < N; ++k) p[k] = T(0);
 }
 
 // Flag the cells that hold a particle with a non-empty list (sorted state:
