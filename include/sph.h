@@ -299,10 +299,9 @@ sph_status sph_build_neighbors(const sph_grid *grid, const sph_params *params,
  * with an empty list are written without staging: no pass over the particles
  * precedes the brick kernel.
  * workspace: device buffer of sph_forces_workspace_bytes(capacity, n_cells)
- * bytes (the per-particle equation-of-state terms of the gather form, the
- * brick counter of the persistent brick kernel and the time step's maxima of
- * sph_forces_dt, set within every call; its contents on entry do not change
- * any result).  Calls that share a workspace must not overlap.
+ * bytes (the per-particle equation-of-state terms of the gather form and
+ * the brick counter of the persistent brick kernel, set within every call;
+ * its contents on entry do not change any result).  Calls that share a workspace must not overlap.
  * Errors: SPH_ERR_ARG (also for an unknown kernel, formulation or
  * visc_model, a negative or non-finite delta, or delta > 0 without
  * parts->info), SPH_ERR_WORKSPACE. */
@@ -311,21 +310,6 @@ sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_
                       const int32_t *cell_start, const int32_t *cell_end,
                       const uint16_t *neibs_brick, float *forces, void *workspace,
                       size_t workspace_bytes, void *stream);
-
-/* sph_forces, and the adaptive time step of sph_step_dt from the derivatives
- * it computes, written to d_dt (device double): the same value, bit for bit
- * (the same float32 maxima of the sound speed and of |a + g| over the fluid
- * particles with cell >= 0; section "The GPU in GPUSPH": the step is a
- * device reduction).  In the brick form the maxima are taken as each
- * particle's derivatives are finished and the last workgroup computes the
- * step, so no pass over the particles follows; the gather form runs
- * sph_step_dt's reduction after its kernel.  parts->info and parts->cell are
- * required.  Errors: as sph_forces (SPH_ERR_ARG also for a NULL d_dt). */
-sph_status sph_forces_dt(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
-                         const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
-                         const int32_t *cell_start, const int32_t *cell_end, const uint16_t *neibs_brick,
-                         float *forces, void *workspace, size_t workspace_bytes, double *d_dt,
-                         void *stream);
 
 /* Bytes of device workspace sph_forces needs (n_cells: cells of the grid). */
 size_t sph_forces_workspace_bytes(int32_t capacity, int32_t n_cells);

@@ -31,7 +31,6 @@ EXPORTS = [
     "sph_forces_backward_workspace_bytes", "sph_forces_backward", "sph_unpermute",
     "sph_diagnostics_workspace_bytes", "sph_reduce_diagnostics", "sph_count_missed_pairs",
     "sph_forces_noalloc", "sph_dt_scenes_workspace_bytes", "sph_step_dt_scenes", "sph_integrate_scenes",
-    "sph_forces_dt",
 ]
 MAX_SCENES = 1 << 20
 
@@ -89,8 +88,6 @@ def _load():
     L.sph_build_neighbors.restype = st
     L.sph_forces.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, C.c_size_t, P]
     L.sph_forces.restype = st
-    L.sph_forces_dt.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, C.c_size_t, P, P]
-    L.sph_forces_dt.restype = st
     L.sph_integrate.argtypes = [P, i32, P, P, P, P, P, P, P]
     L.sph_integrate.restype = st
     L.sph_dt_workspace_bytes.argtypes = []
@@ -227,14 +224,6 @@ def sph_forces(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, nei
                          int(max_neibs), ptr(cell_start), ptr(cell_end), ptr(neibs_brick), ptr(forces),
                          ptr(workspace), workspace.numel() * workspace.element_size(), stream_ptr(stream)),
           "sph_forces")
-
-
-def sph_forces_dt(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count, max_neibs: int,
-                  forces, workspace, d_dt, stream=None, cell_start=None, cell_end=None, neibs_brick=None):
-    check(lib.sph_forces_dt(C.byref(grid), C.byref(params), C.byref(parts), ptr(neibs), ptr(neib_count),
-                            int(max_neibs), ptr(cell_start), ptr(cell_end), ptr(neibs_brick), ptr(forces),
-                            ptr(workspace), workspace.numel() * workspace.element_size(), ptr(d_dt),
-                            stream_ptr(stream)), "sph_forces_dt")
 
 
 def sph_forces_noalloc(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count, max_neibs: int,

@@ -110,12 +110,6 @@ bool make_const(const sph_grid *g, const sph_params *p, int max_neibs, ForceCons
     C.h = p->h;
     C.cell_alpha = g->cell_alpha;
     C.cell_base = g->cell_base;
-    C.gx = p->g[0];
-    C.gy = p->g[1];
-    C.gz = p->g[2];
-    C.dt_h = p->h;
-    C.dt_nu = p->nu;
-    C.dt_cfl = p->cfl;
     return true;
 }
 
@@ -157,21 +151,16 @@ extern "C" size_t sph_forces_workspace_bytes(int32_t capacity, int32_t n_cells)
 {
     if (capacity < 0 || n_cells < 0) return 0;
     // per-particle equation-of-state terms (gather form), then the brick
-    // counter of the persistent brick kernel and the time step's maxima,
-    // then the time step's workspace of the gather form
+    // counter of the persistent brick kernel
     (void)n_cells;
-    return aux_bytes(capacity > 0 ? capacity : 1) + 256 + ((sph_dt_workspace_bytes() + 255) & ~(size_t)255);
+    return aux_bytes(capacity > 0 ? capacity : 1) + 256;
 }
 
-namespace {
-
-// sph_forces, and with d_dt the time step of sph_step_dt from the
-// derivatives it computes (fused into the brick kernel; the gather form runs
-// the step's reduction after it).
-sph_status forces_impl(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
-                       const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
-                       const int32_t *cell_start, const int32_t *cell_end, const uint16_t *neibs_brick,
-                       float *forces, void *workspace, size_t workspace_bytes, double *d_dt, void *stream)
+extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
+                                 const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
+                                 const int32_t *cell_start, const int32_t *cell_end,
+                                 const uint16_t *neibs_brick, float *forces, void *workspace,
+                                 size_t workspace_bytes, void *stream)
 {
     if (!common_args(grid, params, parts, neibs, neib_count, max_neibs)) return SPH_ERR_ARG;
     if (parts->n > 0 && !forces) return SPH_ERR_ARG;
@@ -184,21 +173,17 @@ sph_status forces_impl(const sph_grid *grid, const sph_params *params, const sph
     if (!workspace || workspace_bytes < sph_forces_workspace_bytes(parts->capacity, (int32_t)n_cells))
         return SPH_ERR_WORKSPACE;
     const int n = parts->n;
+    if (n == 0) return SPH_OK;
     hipStream_t s = (hipStream_t)stream;
     float2 *aux = (float2 *)workspace;
-    char *tail = (char *)workspace + aux_bytes(parts->capacity > 0 ? parts->capacity : 1);
-    int32_t *next = (int32_t *)tail;
-    void *ws_dt = tail + 256;
-    const size_t ws_dt_bytes = workspace_bytes - (aux_bytes(parts->capacity > 0 ? parts->capacity : 1) + 256);
-    if (n == 0) return d_dt ? sph_step_dt(params, parts, forces, d_dt, ws_dt, ws_dt_bytes, stream) : SPH_OK;
+    int32_t *next = (int32_t *)((char *)workspace + aux_bytes(parts->capacity > 0 ? parts->capacity : 1));
     if (grid->cell_alpha && !parts->cell) return SPH_ERR_ARG;
     const bool bricks = cell_start && cell_end && neibs_brick;
     if (bricks && !parts->cell) return SPH_ERR_ARG;
     if (bricks && ((uintptr_t)neibs_brick & 15u)) return SPH_ERR_ARG;  // read in 16-byte groups
-    if ((params->delta != 0.0f || d_dt) && !parts->info) return SPH_ERR_ARG;
-    if (d_dt && !parts->cell) return SPH_ERR_ARG;
-    if (bricks)  // the brick counter, and the step's maxima and finished workgroups
-        k_zero_few<int32_t, 4><<<1, 1, 0, s>>>(next);
+    if ((params->delta != 0.0f) && !parts->info) return SPH_ERR_ARG;
+    if (bricks)
+        k_zero_one<int32_t><<<1, 1, 0, s>>>(next);
     else
         k_eos<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, (const float4 *)parts->vel, aux, parts->cell, C);
     ForceArgs a;
@@ -219,8 +204,6 @@ sph_status forces_impl(const sph_grid *grid, const sph_params *params, const sph
     a.table = bricks ? brick_table(reinterpret_cast<const int32_t *>(neibs_brick), parts->capacity, max_neibs)
                      : nullptr;
     a.next = next;
-    a.dtm = bricks && d_dt ? reinterpret_cast<uint32_t *>(next + 1) : nullptr;
-    a.d_dt = d_dt;
     a.out = (float4 *)forces;
     a.bricks = bricks;
     static bool (*const pairs[4])(int, const ForceArgs &, const ForceConst &, hipStream_t) = {
@@ -228,31 +211,7 @@ sph_status forces_impl(const sph_grid *grid, const sph_params *params, const sph
     const int model = model_of(params);
     if (!pairs[model_kernel(model)](model, a, C, s)) return SPH_ERR_ARG;
     SPH_CHECK_LAUNCH();
-    if (d_dt && !bricks) return sph_step_dt(params, parts, forces, d_dt, ws_dt, ws_dt_bytes, stream);
     return SPH_OK;
-}
-
-}  // namespace
-
-extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
-                                 const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
-                                 const int32_t *cell_start, const int32_t *cell_end,
-                                 const uint16_t *neibs_brick, float *forces, void *workspace,
-                                 size_t workspace_bytes, void *stream)
-{
-    return forces_impl(grid, params, parts, neibs, neib_count, max_neibs, cell_start, cell_end, neibs_brick,
-                       forces, workspace, workspace_bytes, nullptr, stream);
-}
-
-extern "C" sph_status sph_forces_dt(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
-                                    const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
-                                    const int32_t *cell_start, const int32_t *cell_end,
-                                    const uint16_t *neibs_brick, float *forces, void *workspace,
-                                    size_t workspace_bytes, double *d_dt, void *stream)
-{
-    if (!d_dt) return SPH_ERR_ARG;
-    return forces_impl(grid, params, parts, neibs, neib_count, max_neibs, cell_start, cell_end, neibs_brick,
-                       forces, workspace, workspace_bytes, d_dt, stream);
 }
 
 extern "C" sph_status sph_count_interactions(const sph_grid *grid, const sph_params *params,

@@ -23,10 +23,7 @@ struct ForceConst {
     float h;          // smoothing length (per-cell alpha times h)
     const float *cell_alpha;  // per-cell artificial-viscosity coefficient, or null
     int cell_base;
-    float gx, gy, gz;               // gravity (the time step's |a + g|)
-    double dt_h, dt_nu, dt_cfl;     // the time step's h, nu and CFL factor
 };
-
 
 // Cole equation of state for gamma = 7 in the expanded form P = B d (7 + 21d
 // + 35d^2 + 35d^3 + 21d^4 + 7d^5 + d^6), d = (rho - rho0)/rho0 (exact
@@ -69,8 +66,6 @@ struct ForceArgs {
     const int32_t *table;  // bricks with a pair (brick_table layout), from the build
     int cap_ids;           // ids of the table
     int32_t *next;         // brick counter of the persistent workgroups (zeroed before the launch)
-    uint32_t *dtm;         // the step's maxima (c, |a + g| bits) and finished workgroups (zeroed), or null
-    double *d_dt;          // the step, written by the last workgroup when dtm is given
     float4 *out;
     bool bricks;
 };

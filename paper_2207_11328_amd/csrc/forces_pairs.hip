@@ -293,8 +293,7 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
                                                      const int32_t *__restrict__ table, int cap_ids,
                                                      int32_t *__restrict__ next,
                                                      const uint32_t *__restrict__ info,
-                                                     float4 *__restrict__ out, uint32_t *__restrict__ dtm,
-                                                     double *__restrict__ d_dt, ForceConst C, BrickGrid G)
+                                                     float4 *__restrict__ out, ForceConst C, BrickGrid G)
 {
     using St = Staging<BX, BY, BZ>;
     constexpr int SX = BX + 2, SY = BY + 2, SZ = BZ + 2;
@@ -314,7 +313,6 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     __shared__ int sNext;
     __shared__ int sGroup;  // groups of centrals claimed in the brick, past the first NT / kWave
     __shared__ int sPre[4]; // scan ahead: claimed, next brick's list index, total, centrals
-    __shared__ uint32_t sDt[2];  // the workgroup's maxima of the step's speeds (float bits)
     static_assert(NI <= kWave, "one lane per inner cell in the scan ahead");
 
     // One resident workgroup per CU takes the bricks with a pair one at a time
@@ -413,23 +411,6 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     };
     int cur = 0;       // buffer of the current brick's scans
     bool pre = false;  // uniform: they were scanned ahead
-    if (threadIdx.x < 2) sDt[threadIdx.x] = 0u;  // (read after the first barrier)
-    // The time step's maxima over the fluid particles (when asked for): each
-    // wave reduces its lanes' speeds and takes the workgroup's LDS maximum.
-    auto dt_take = [&](bool fluid, float rho, float fx, float fy, float fz, bool lead) {
-        float c = 0.0f, a = 0.0f;
-        if (fluid) {
-            dt_speeds(rho, fx, fy, fz, C.rho0, C.inv_rho0, C.c0, C.gx, C.gy, C.gz, c, a);
-            c = fmaxf(c, 0.0f);  // (NaN or negative: no bound, as in sph_step_dt's maxima)
-            a = fmaxf(a, 0.0f);
-        }
-        c = wave_max(c);
-        a = wave_max(a);
-        if (lead) {
-            atomicMax(&sDt[0], __float_as_uint(c));
-            atomicMax(&sDt[1], __float_as_uint(a));
-        }
-    };
     for (;;) {
         // the thread index is re-read per brick (an empty asm hides that it is
         // the same), so nothing derived from it is kept live across the pair loop
@@ -629,10 +610,6 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
             }
             // (particles with an empty list are written after the last brick)
             if (act && h == 0 && nt > 0) out[i] = make_float4(A.ax, A.ay, A.az, A.dr);
-            if (dtm) {  // uniform
-                const bool take = act && h == 0 && nt > 0 && ptype(info[i]) != kBoundary;
-                dt_take(take, take ? vel[i].w : 0.0f, A.ax, A.ay, A.az, tid % kWave == 0);
-            }
             int gn = 0;
             if (tid % kWave == 0) gn = atomicAdd(&sGroup, 1) + NW;
             g = __builtin_amdgcn_readfirstlane(__shfl(gn, 0));
@@ -647,34 +624,9 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     }
     // Particles with an empty list (none of their bricks' pairs; also those
     // the build dropped) get zero derivatives, by all workgroups as they run
-    // out of bricks: no other lane writes them.  (Every lane of a wave runs
-    // the same iterations: the step's maxima take wave operations.)
-    for (int i0 = blockIdx.x * NT; i0 < n; i0 += gridDim.x * NT) {
-        const int i = i0 + (int)threadIdx.x;
-        const bool empty = i < n && count[i] == 0u;
-        if (empty) out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (dtm) {  // uniform
-            const bool take = empty && cell[i] >= 0 && ptype(info[i]) != kBoundary;
-            dt_take(take, take ? vel[i].w : 0.0f, 0.0f, 0.0f, 0.0f, threadIdx.x % kWave == 0);
-        }
-    }
-    // The last workgroup to finish turns the maxima into the step: each
-    // takes the device-wide maximum of its own and counts itself finished
-    // after a device-scope fence; the last one reads the maxima after one.
-    if (dtm) {  // uniform
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            atomicMax(&dtm[0], sDt[0]);
-            atomicMax(&dtm[1], sDt[1]);
-            __threadfence();
-            if (atomicAdd(&dtm[2], 1u) == gridDim.x - 1) {
-                __threadfence();
-                const float c = __uint_as_float(atomicMax(&dtm[0], 0u));
-                const float a = __uint_as_float(atomicMax(&dtm[1], 0u));
-                *d_dt = dt_from_maxima((double)c, (double)a, C.dt_h, C.dt_nu, C.dt_cfl);
-            }
-        }
-    }
+    // out of bricks: no other lane writes them.
+    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
+        if (count[i] == 0u) out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 // LDS capacity (staged particles, 40 bytes each) per brick shape: the halo
@@ -698,7 +650,7 @@ void launch_brick(const ForceArgs &a, const ForceConst &C, hipStream_t s)
         const unsigned wgs = blocks < (unsigned)sph_device_cus() ? blocks : (unsigned)sph_device_cus();
         k_forces_brick<MODEL, BX, BY, BZ, NT, brick_cap(BX, BY, BZ)><<<wgs, NT, 0, s>>>(
             a.n, a.pos, a.vel, a.cell, a.neibs, a.neibs_brick, a.count, a.cell_start, a.cell_end, a.table,
-            a.cap_ids, a.next, a.info, a.out, a.dtm, a.d_dt, C, G);
+            a.cap_ids, a.next, a.info, a.out, C, G);
     });
 }
 

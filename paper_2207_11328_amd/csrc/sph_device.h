@@ -370,14 +370,6 @@ __global__ void k_zero_one(T *p)
     *p = T(0);
 }
 
-// A few words zeroed by one thread (graph-capturable, no memset node).
-template <typename T, int N>
-__global__ void k_zero_few(T *p)
-{
-#pragma unroll
-    for (int k = 0; k < N; ++k) p[k] = T(0);
-}
-
 // Flag the cells that hold a particle with a non-empty list (sorted state:
 // cell[i] - cell_base, count[i] = nf | nb << 16; dropped particles have cell
 // -1 and count 0).

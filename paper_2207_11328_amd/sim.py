@@ -149,24 +149,16 @@ class Simulation:
         use = self.use_bricks if bricks is None else bricks
         return (self.cell_start, self.cell_end, self.neibs_brick) if use else (None, None, None)
 
-    def forces(self, star: bool = False, stream=None, bricks: bool | None = None, with_dt: bool = False):
+    def forces(self, star: bool = False, stream=None, bricks: bool | None = None):
         """Derivatives of the state n (or *).  bricks: the LDS cell-brick
         kernel (uses the cell ranges and brick-local lists of the last
         build); False: the per-particle global-gather kernel; None: the
-        simulation's choice (use_bricks).  The two agree to rounding.
-        with_dt: also the adaptive step from these derivatives into d_dt
-        (sph_forces_dt; the value step_dt gives, one scene only)."""
+        simulation's choice (use_bricks).  The two agree to rounding."""
         parts = self.parts_star if star else self.parts
         out = self.forces_star if star else self.forces_n
         cs, ce, nb = self.brick_args(bricks)
-        if with_dt:
-            if self.cell_scene is not None:
-                raise ValueError("with_dt takes one step for the whole grid; scenes use step_dt")
-            abi.sph_forces_dt(self.g, self.p, parts, self.neibs, self.neib_count, self.max_neibs, out,
-                              self.ws_forces, self.d_dt, stream, cs, ce, nb)
-        else:
-            abi.sph_forces(self.g, self.p, parts, self.neibs, self.neib_count, self.max_neibs, out, self.ws_forces,
-                           stream, cs, ce, nb)
+        abi.sph_forces(self.g, self.p, parts, self.neibs, self.neib_count, self.max_neibs, out, self.ws_forces,
+                       stream, cs, ce, nb)
         return out
 
     def step_dt(self, stream=None):
@@ -210,18 +202,12 @@ class Simulation:
         return self.count
 
     # ------------------------------------------------------------ step
-    def _forces_and_dt(self, stream=None):
-        """Derivatives of state n and, unless dt is fixed, the step from them
-        (fused for one scene, a reduction per scene otherwise)."""
-        fuse = self.dt_fixed is None and self.cell_scene is None
-        self.forces(False, stream, with_dt=fuse)
-        if self.dt_fixed is None and not fuse:
-            self.step_dt(stream)
-
     def step(self, stream=None):
         if self.steps_done % self.rebuild_every == 0:
             self.build(stream)
-        self._forces_and_dt(stream)
+        self.forces(False, stream)
+        if self.dt_fixed is None:
+            self.step_dt(stream)
         self.integrate(0, stream)
         self.forces(True, stream)
         self.integrate(1, stream)
@@ -248,7 +234,9 @@ class Simulation:
             with torch.cuda.graph(graph, stream=side):
                 self.build()
                 for _ in range(self.rebuild_every):
-                    self._forces_and_dt()
+                    self.forces(False)
+                    if self.dt_fixed is None:
+                        self.step_dt()
                     self.integrate(0)
                     self.forces(True)
                     self.integrate(1)

@@ -592,32 +592,3 @@ def test_brick_table_lists_the_bricks_with_a_pair(name):
     assert len(got_h) == len(set(got_h)) and len(got_l) == len(set(got_l))
     assert set(got_h) == heavy and set(got_l) == light
 
-
-@pytest.mark.parametrize("name", ["still_water", "cloud_open", "laminar_cloud", "dam_break_64k", "dense_overflow"])
-@pytest.mark.parametrize("bricks", [True, False], ids=["bricks", "gather"])
-def test_fused_time_step_equals_step_dt(name, bricks):
-    """sph_forces_dt: the same derivatives as sph_forces and the same step as
-    sph_step_dt on them, bit for bit, in the brick form (maxima taken as the
-    derivatives are finished, the step by the last workgroup; with and
-    without bricks past the LDS capacity) and in the gather form."""
-    if name == "dense_overflow":
-        sc = S.random_cloud(n=24000, box=(0.4, 0.4, 0.4), dp=0.02, seed=21, boundary_frac=0.2, u_sigma=0.2)
-        M = 416
-    else:
-        sc = SCENES[name]()
-        M = _slots(name)
-    log("case %s fused dt (%s): n=%d" % (name, "bricks" if bricks else "gather", sc.n))
-    sim = make_sim(sc, max_neibs=M)
-    sim.build()
-    plain = sim.forces(bricks=bricks).clone()
-    sim.step_dt()
-    torch_sync()
-    dt_ref = sim.d_dt.clone()
-    for rep in range(2):  # the second call on the workspace the first one left
-        sim.d_dt.fill_(float("nan"))
-        sim.forces_n.fill_(float("nan"))
-        fused = sim.forces(bricks=bricks, with_dt=True)
-        torch_sync()
-        assert torch.equal(fused[: sc.n], plain[: sc.n]), rep
-        log("dt step_dt %.17g fused %.17g" % (dt_ref.item(), sim.d_dt.item()))
-        assert torch.equal(sim.d_dt, dt_ref), rep
