@@ -514,6 +514,7 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
 // type word (its type bits stay: other waves read them); a candidate past
 // the cell set points at a dummy staged particle far away.
 constexpr int kItemChunks = 6;                 // candidate chunks held in registers per pass
+constexpr int kItemParts = 2;                  // work items per inner cell (its centrals split evenly)
 constexpr uint32_t kFoundMask = (1u << kTypeShift) - 1u;
 
 // Tests of one central (slot si, position pi) against the nch candidate
@@ -559,11 +560,10 @@ __device__ __forceinline__ void brick_scan_items(int M, int *sItem, const int *c
         int item = 0;
         if (lane == 0) item = atomicAdd(sItem, 1);
         item = __builtin_amdgcn_readfirstlane(__shfl(item, 0));
-        if (item >= 2 * NI) break;  // uniform
-        const int u = item >> 1;
+        if (item >= kItemParts * NI) break;  // uniform
+        const int u = item / kItemParts, part = item % kItemParts;
         const int n_u = iBase[u + 1] - iBase[u];
-        const int half = (n_u + 1) >> 1;
-        const int qa = (item & 1) ? half : 0, qb = (item & 1) ? n_u : half;
+        const int qa = part * n_u / kItemParts, qb = (part + 1) * n_u / kItemParts;
         if (qa >= qb) continue;  // uniform
         const int tc = St::inner(u);
         const int i0 = iStart[u];
