@@ -594,64 +594,66 @@ def main():
     sim = new_sim()
     for _ in range(W):
         sim.step()
+    # the timed steps start on a rebuild step (their first step rebuilds, as
+    # every 10th does), so that they can be replayed as 10-step graph units
+    align = -W % sim.rebuild_every
+    for _ in range(align):
+        sim.step()
     torch.cuda.synchronize()
     sim.check_status()
 
-    ev = []  # (start, end) around each sph_forces launch
-    t_forces_events = []
-
-    def timed_step():
-        rebuild = sim.steps_done % sim.rebuild_every == 0
-        if rebuild:
-            sim.build()
-        for star in (False, True):
-            if star:
-                sim.integrate(0)
-            a = torch.cuda.Event(enable_timing=True)
-            b = torch.cuda.Event(enable_timing=True)
-            a.record()
-            sim.forces(star)
-            b.record()
-            ev.append((a, b))
-            if not star and sim.dt_fixed is None:
-                sim.step_dt()
-        sim.integrate(1)
-        sim.steps_done += 1
-
+    # The timed steps: replays of a HIP graph holding one rebuild unit (the
+    # neighbour search and 10 steps, no host launch per kernel) when K is a
+    # whole number of units, else launched one by one.
+    use_graph = K % sim.rebuild_every == 0
+    if use_graph:
+        sim.capture_unit()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(K):
-        timed_step()
+    if use_graph:
+        sim.replay_units(K // sim.rebuild_every)
+    else:
+        sim.run(K)
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
-    for a, b in ev:
-        t_forces_events.append(a.elapsed_time(b) * 1e-3)
     sim.check_status()
 
-    # replay the same deterministic trajectory to count interactions per call
+    # The same trajectory again, launched one by one: HIP events around each
+    # sph_forces call (the derivative call's own time, for the roofline) and
+    # the interactions each call evaluates; its final state must equal the
+    # timed run's bit for bit.
+    from paper_2207_11328_amd import abi
     rep = new_sim()
-    for _ in range(W):
+    for _ in range(W + align):
         rep.step()
-    inter = 0
-    listed = 0
+    ev = []  # (start, end) around each sph_forces launch
+    inter_dev = torch.zeros(1, dtype=torch.int64, device="cuda:0")
+    listed_dev = torch.zeros(1, dtype=torch.int64, device="cuda:0")
     for _ in range(K):
         if rep.steps_done % rep.rebuild_every == 0:
             rep.build()
         for star in (False, True):
             if star:
                 rep.integrate(0)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
             rep.forces(star)
+            b.record()
+            ev.append((a, b))
             parts_n = rep.parts_star if star else rep.parts
-            from paper_2207_11328_amd import abi
             abi.sph_count_interactions(rep.g, rep.p, parts_n, rep.neibs, rep.neib_count, rep.max_neibs, rep.count)
-            inter += int(rep.count.item())
-            if not star:
+            inter_dev += rep.count
+            if not star and rep.dt_fixed is None:
                 rep.step_dt()
-        cnt = rep.neib_count[: rep.n]
-        listed += 2 * int(((cnt & 0xFFFF) + (cnt >> 16)).sum().item())
+        cnt = rep.neib_count[: rep.n].long()
+        listed_dev += 2 * ((cnt & 0xFFFF) + (cnt >> 16)).sum()
         rep.integrate(1)
         rep.steps_done += 1
     torch.cuda.synchronize()
+    t_forces_events = [a.elapsed_time(b) * 1e-3 for a, b in ev]
+    inter = int(inter_dev.item())
+    listed = int(listed_dev.item())
     same = torch.equal(rep.pos, sim.pos) and torch.equal(rep.vel, sim.vel)
     del rep
     torch.cuda.empty_cache()
@@ -703,6 +705,8 @@ def main():
         "steps_per_s": K / t_total,
         "mipps": n * K / t_total / 1e6,
         "replay_bitwise_identical": bool(same),
+        "timing": ("HIP graph replays of %d-step units (neighbour search + steps)" % sim.rebuild_every
+                   if use_graph else "steps launched one by one"),
         # the derivative call: its algorithmic intensity (on the dam break
         # about 13 FLOP per algorithmic byte) is above the FP32/HBM ridge
         # (9.8), so the FP32 vector roof bounds it; HBM figures beside it
