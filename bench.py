@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--no-missed", action="store_true")
     ap.add_argument("--no-channel-adjoint", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--brick", default=None, metavar="BX,BY,BZ",
+                    help="use this brick shape for the 1.62M dam break and the batched tanks instead of the "
+                         "autotuner's choice (profiling runs: counters distort the tuner's timings)")
     ap.add_argument("--gather-probe", type=int, default=0, metavar="MIB",
                     help="only run a gather of MIB MiB in 128-byte rows taken in a random order, three times "
                          "(checks the HBM byte counters' scale on a scattered pattern) and exit")
@@ -282,7 +285,13 @@ def fwd_bwd(sc, dt, K=10, reps=3, brick=None, use_bricks=True):
     return out
 
 
-def batched(units=50, warm_units=1):
+def fixed_choice(brick):
+    """The tuner's result format for a given brick shape (LDS brick kernels)."""
+    return {"brick": tuple(int(v) for v in brick), "bricks": True, "per_step_s": {}, "cached": False,
+            "fixed": True}
+
+
+def batched(units=50, warm_units=1, brick=None):
     """128 independent tanks (fluid counts log-uniform in [2k, 60k], column
     aspect 0.3-2, alpha 0.005-0.05) stacked in one grid, advanced by replays
     of a HIP graph holding one rebuild unit (10 steps, each tank with its
@@ -292,8 +301,14 @@ def batched(units=50, warm_units=1):
     from workloads import scenes as S
     tanks = S.batched_tanks()
     st, alpha, _, _ = S.stack_scenes(tanks)
-    sim, choice = tune.tuned_simulation(st.grid, st.params, st.cell, st.pos, st.vel, st.info, cell_alpha=alpha,
-                                        device="cuda:0", cell_scene=S.scene_cells(st))
+    if brick is None:
+        sim, choice = tune.tuned_simulation(st.grid, st.params, st.cell, st.pos, st.vel, st.info, cell_alpha=alpha,
+                                            device="cuda:0", cell_scene=S.scene_cells(st))
+    else:
+        from paper_2207_11328_amd.sim import Simulation
+        choice = fixed_choice(brick)
+        sim = Simulation(st.grid, st.params, st.cell, st.pos, st.vel, st.info, cell_alpha=alpha, device="cuda:0",
+                         cell_scene=S.scene_cells(st), brick=choice["brick"])
     sim.capture_unit()
     sim.replay_units(warm_units)
     torch.cuda.synchronize()
@@ -585,7 +600,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     sc = make_scene(args.workload)
     K, W = args.steps, args.warmup
-    choice = tune.autotune(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0")
+    brick = tuple(int(v) for v in args.brick.split(",")) if args.brick else None
+    choice = (fixed_choice(brick) if brick else
+              tune.autotune(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0"))
 
     def new_sim():
         return Simulation(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0",
@@ -693,7 +710,8 @@ def main():
             "dp": sc.params.dp, "h_over_dp": 1.3, "max_neibs": sim.max_neibs, "rebuild_every": sim.rebuild_every,
             "brick": list(choice["brick"]), "kernel": "lds_bricks" if choice["bricks"] else "gather",
         },
-        "tuning": {"cached": choice["cached"], "per_step_ms": {k: v * 1e3 for k, v in choice["per_step_s"].items()}},
+        "tuning": {"cached": choice["cached"], "fixed_by_flag": bool(choice.get("fixed")),
+                   "per_step_ms": {k: v * 1e3 for k, v in choice["per_step_s"].items()}},
         "value_definition": "interactions evaluated by sph_forces (pairs with r < 2h, two calls per step) per "
                             "second of WHOLE-STEP time (list build every 10th step, dt, integrator included)",
         "forces_interactions_per_s": inter / t_forces,
@@ -731,7 +749,7 @@ def main():
     if not args.no_m1:
         out["m1"] = m1_forces(sc, choice)
     if not args.no_batched:
-        out["batched"] = batched()
+        out["batched"] = batched(brick=brick)
     if not args.no_fwd_bwd:
         dt_now = float(sim.d_dt.item())
         out["adjoint"] = fwd_bwd(sc, dt_now, brick=choice["brick"], use_bricks=choice["bricks"])
