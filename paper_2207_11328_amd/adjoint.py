@@ -222,6 +222,8 @@ class AdjointRollout:
         # as the forward left them
         for b in sorted(self.tape, reverse=True):
             t = self.tape[b]
+            if t["stored"] is None:
+                raise RuntimeError("backward() needs a forward() of the rollout first")
             self._use_lists(self._tape_lists(b))
             s.cell.copy_(t["cell"])
             s.info.copy_(t["info"])

@@ -76,6 +76,8 @@ class Simulation:
             if cs_np.shape != (self.n_cells,):
                 raise ValueError("cell_scene must hold one scene index per cell")
             self.n_scenes = int(cs_np.max()) + 1
+            if self.n_scenes < 1 or self.n_scenes > abi.MAX_SCENES:
+                raise ValueError("cell_scene must name between 1 and %d scenes" % abi.MAX_SCENES)
             self.cell_scene = torch.from_numpy(cs_np).to(dev)
             self.ws_dt = z(abi.sph_dt_scenes_workspace_bytes(self.n_scenes), torch.uint8)
         else:
