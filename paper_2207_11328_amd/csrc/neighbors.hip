@@ -498,8 +498,8 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
 }
 
 // Scan of the list build, cell form (brick staged in LDS, brick-local lists
-// asked for).  The work items are the two halves of each inner cell's
-// central particles; a wave takes items from a counter.  For its item, the
+// asked for).  The work items are the kItemParts parts of each inner cell's
+// central particles (consecutive runs); a wave takes items from a counter.  For its item, the
 // wave lays the candidates of the cell's 27 neighbour cells, in scan order
 // (cells z, y, x from -1 to +1, each in slot order; only the fluid prefix of
 // each cell when the item's centrals are boundary particles), out over its
