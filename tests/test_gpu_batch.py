@@ -201,3 +201,45 @@ def test_adaptive_dt_batched_equals_single_and_independent():
         same = np.array_equal(pos_p[sel].view(np.uint32), pos_b[sel].view(np.uint32)) and \
             np.array_equal(vel_p[sel].view(np.uint32), vel_b[sel].view(np.uint32)) and clocks2[k] == clocks[k]
         assert same == (k != 2), k
+
+
+def test_cells_of_no_scene_are_left_alone():
+    """A cell whose scene entry is outside [0, n_scenes) belongs to no scene:
+    its particles keep their state through sph_integrate_scenes and count in
+    no scene's step (the other tanks step exactly as with the full table)."""
+    from paper_2207_11328_amd.sim import Simulation
+    tanks = _tanks(n=4, seed=13)
+    stacked, alpha, subs, ranges = S.stack_scenes(tanks)
+    table = S.scene_cells(stacked)
+    cut = table.copy()
+    cut[cut == 1] = -1  # tank 1's cells: no scene
+    full = Simulation(stacked.grid, stacked.params, stacked.cell, stacked.pos, stacked.vel, stacked.info,
+                      cell_alpha=alpha, cell_scene=table)
+    part = Simulation(stacked.grid, stacked.params, stacked.cell, stacked.pos, stacked.vel, stacked.info,
+                      cell_alpha=alpha, cell_scene=cut)
+    assert part.n_scenes == len(tanks)
+    for s in (full, part):
+        s.build()
+        s.forces()
+        s.step_dt()
+    torch_sync()
+    dt_full = full.d_dt.cpu().numpy()
+    dt_part = part.d_dt.cpu().numpy()
+    assert np.array_equal(dt_part[[0, 2, 3]], dt_full[[0, 2, 3]])
+    # scene 1 now holds no particle: only the laminar limit, if any, bounds it
+    p = stacked.params
+    h, nu, cfl = float(np.float32(p.h)), float(np.float32(p.nu)), float(np.float32(p.cfl))
+    assert dt_part[1] == (cfl * (0.125 * h * h / nu) if nu > 0 else np.inf)
+    before = part.state_host()
+    part.d_dt[1] = 1e-4  # any step: the tank's particles must still stay put
+    part.integrate(0)
+    part.integrate(1)
+    torch_sync()
+    after = part.state_host()
+    first, count = ranges[1]
+    ids = (before["info"] & np.uint32((1 << 30) - 1)).astype(np.int64)
+    sel = (ids >= first) & (ids < first + count)
+    assert sel.sum() == count
+    assert np.array_equal(after["pos"][sel].view(np.uint32), before["pos"][sel].view(np.uint32))
+    assert np.array_equal(after["vel"][sel].view(np.uint32), before["vel"][sel].view(np.uint32))
+    assert not np.array_equal(after["pos"][~sel].view(np.uint32), before["pos"][~sel].view(np.uint32))
