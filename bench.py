@@ -104,6 +104,33 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes": n, "copies": 3}), flush=True)
 
 
+def hbm_probe(mib=1024, reps=5):
+    """Achievable HBM bandwidth: a plain device-to-device copy of MIB MiB
+    (read + write = 2 x MIB MiB moved), timed with HIP events, median of
+    REPS copies after one warm-up copy.  The denominator of the derivative
+    call's achievable-HBM fraction, beside the 8 TB/s data-sheet peak."""
+    import torch
+    n = mib << 20
+    src = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) * 1e-3)
+    t = float(np.median(ts))
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"copy_GBps": 2 * n / t / 1e9, "bytes_moved": 2 * n, "copies": reps, "copy_ms_median": t * 1e3,
+            "kind": "device-to-device copy of %d MiB (torch copy_), median of %d" % (mib, reps)}
+
+
 def make_scene(name):
     from workloads import scenes as S
     return S.CONFIGS[name]()
@@ -689,6 +716,7 @@ def main():
     flop_per_launch = FLOP_PER_INTERACTION[int(sc.params.visc_model)] * inter / calls
     achieved_tflops = flop_per_launch / t_forces_avg / 1e12
     traffic = measured_traffic(args.workload) if choice["bricks"] else None
+    probe = hbm_probe()
     ms_per_step = t_total / K * 1e3
     value = inter / t_total
     out = {
@@ -741,7 +769,13 @@ def main():
             "launch_ms": t_forces_avg * 1e3,
             "hbm": {"achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved_gbs / HBM_PEAK_GBS, "bytes_per_launch": bytes_per_launch,
-                    "traffic_frac": None if traffic is None else traffic / t_forces_avg / 1e9 / HBM_PEAK_GBS},
+                    "traffic_frac": None if traffic is None else traffic / t_forces_avg / 1e9 / HBM_PEAK_GBS,
+                    # the achievable peak measured on this GPU (stream copy)
+                    "achievable": probe["copy_GBps"],
+                    "frac_of_achievable": achieved_gbs / probe["copy_GBps"],
+                    "traffic_frac_of_achievable": (None if traffic is None else
+                                                   traffic / t_forces_avg / 1e9 / probe["copy_GBps"]),
+                    "probe": probe},
         },
     }
     if not args.no_variants:

@@ -517,11 +517,15 @@ constexpr int kItemChunks = 6;                 // candidate chunks held in regis
 constexpr int kItemParts = 2;                  // work items per inner cell (its centrals split evenly)
 constexpr uint32_t kFoundMask = (1u << kTypeShift) - 1u;
 
-// Tests of one central (slot si, position pi) against the nch candidate
+// Tests of one central (LDS slot si, position pi) against the nch candidate
 // chunks of the item; found: entries so far.  MASK_B: the central is a
-// boundary particle among fluid candidates (boundary candidates are skipped;
-// mask_b is uniform).
-__device__ __forceinline__ int scan_central(bool mask_b, int found, int si, const float4 &pi, int nch, const int *sa,
+// boundary particle among fluid candidates (boundary candidates are skipped).
+// The hit mask of a chunk is formed from ballots of plain compares combined on
+// the scalar unit (a ballot of a combined lane predicate would first be turned
+// into a vector of 0/1 and compared again); a hit's entry is stored at its
+// byte offset from the central's (uniform) group base.
+template <bool MASK_B>
+__device__ __forceinline__ int scan_central(int found, uint32_t si, const float4 &pi, int nch, const int *sa,
                                             const float *tx, const float *ty, const float *tz, const float4 *sPos,
                                             float rs2, int M, uint16_t *__restrict__ lt)
 {
@@ -531,14 +535,20 @@ __device__ __forceinline__ int scan_central(bool mask_b, int found, int si, cons
             const uint32_t slot = (uint32_t)sa[c];
             const float4 pj = sPos[slot];
             const float r2 = predicate_r2(pi.x, pi.y, pi.z, pj.x, pj.y, pj.z, tx[c], ty[c], tz[c]);
-            bool hit = (r2 < rs2) & (slot != (uint32_t)si);
-            if (mask_b) hit = hit & (ptype(__float_as_uint(pj.w)) != kBoundary);
-            const unsigned long long H = __ballot(hit);
+            const bool in = r2 < rs2, other = slot != si;
+            unsigned long long H = __builtin_amdgcn_ballot_w64(in) & __builtin_amdgcn_ballot_w64(other);
+            bool fluid = true;
+            if constexpr (MASK_B) {
+                fluid = ptype(__float_as_uint(pj.w)) != kBoundary;
+                H &= __builtin_amdgcn_ballot_w64(fluid);
+            }
             if (H) {  // uniform
-                const uint32_t pos = (uint32_t)found + __builtin_amdgcn_mbcnt_hi(
-                                                           (uint32_t)(H >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)H, 0u));
-                if (hit & (pos < (uint32_t)M))
-                    lt[((pos >> 3) << 9) | (pos & 7u)] = (uint16_t)slot;  // brick_entry layout
+                const uint32_t pos = __builtin_amdgcn_mbcnt_hi((uint32_t)(H >> 32),
+                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)H, (uint32_t)found));
+                // brick_entry layout: group pos / 8 at 1024-byte stride, entry pos % 8
+                const uint32_t boff = ((pos >> 3) << 10) | ((pos & 7u) << 1);
+                if (in && other && fluid && pos < (uint32_t)M)
+                    *reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(lt) + boff) = (uint16_t)slot;
                 found += (int)__popcll(H);
             }
         }
@@ -625,8 +635,10 @@ __device__ __forceinline__ void brick_scan_items(int M, int *sItem, const int *c
                 int found = pg == 0 ? 0 : (int)(wi & kFoundMask);
                 uint16_t *lt = neibs_brick + brick_entry(i, 0, G);
                 // a boundary central among fluid ones takes fluid neighbours only
-                const bool mask_b = !fluid_only && ptype(wi) == kBoundary;
-                found = scan_central(mask_b, found, si, pi, nch, sa, tx, ty, tz, sPos, rs2, M, lt);
+                if (!fluid_only && ptype(wi) == kBoundary)
+                    found = scan_central<true>(found, si, pi, nch, sa, tx, ty, tz, sPos, rs2, M, lt);
+                else
+                    found = scan_central<false>(found, si, pi, nch, sa, tx, ty, tz, sPos, rs2, M, lt);
                 if (last_page) {
                     // zero the rest of the last group, so the lists are the same bytes
                     // whatever the array held
