@@ -346,45 +346,38 @@ __global__ void k_status(int n, int n_cells, const int32_t *__restrict__ start, 
 // Staging order, particles of a cell in sorted order), uint16, in scan order with
 // fluid and boundary neighbours interleaved as found (entries 0 .. nf+nb-1),
 // stored in groups of 8 per particle (brick_entry).
+// The staged word of a particle (w of its float4 in LDS): its type in the
+// type bits, its staged cell in bits kCellShift.., and for a central the
+// number of neighbours found so far in the low bits (kFoundMask; a count
+// saturates there, far above any list length).
+constexpr uint32_t kFoundMask = 0xFFFFu;
+constexpr int kCellShift = 16;
+constexpr uint32_t kCellMask = 0xFFu;
+
 // The split j-list of one central particle written from its brick-local
 // list (w entries, already in global memory, in scan order), entry k of the
-// lanes of a wave in one store.  Entries are in scan order, neighbour cell by
-// neighbour cell, and the 27 cells hold disjoint slot ranges: a cursor over
-// the cells in scan order, moved on until the entry's slot is in its cell's
-// range, finds each entry's cell (and so its particle index and image code).
-// Returns n_fluid | n_boundary << 16.
+// lanes of a wave in one store.  The staged word of each entry's particle
+// holds its staged cell t (kCellShift); the cell gives the particle index
+// (slot - cDelta[t]) and, from the offset t - tc to the central's cell, the
+// image code (sCode[t - tc + S - 1]).  Returns n_fluid | n_boundary << 16.
 template <int BX, int BY, int BZ>
-__device__ __forceinline__ uint32_t brick_jlists(int tc, int M, int w, const int *cBase, const int *cDelta,
+__device__ __forceinline__ uint32_t brick_jlists(int tc, int M, int w, const int *cDelta, const uint32_t *sCode,
                                                  const float4 *sPos, uint32_t *tile, const uint16_t *ltile)
 {
+    constexpr int S = Staging<BX, BY, BZ>::S;
     uint32_t *tf = tile, *tb = tile + (size_t)(M - 1) * kWave;
     const uint4 *lg = (const uint4 *)ltile;
     uint4 grp = make_uint4(0u, 0u, 0u, 0u);
-    int dx = -1, dy = -1, dz = -1;
-    int t = tc + Staging<BX, BY, BZ>::step(dx, dy, dz);
-    int lo = cBase[t], hi = cBase[t + 1], delta = cDelta[t];
+    const uint32_t *code = sCode + (S - 1 - tc);
     for (int e = 0; e < w; ++e) {
         if ((e & (kBrickGroup - 1)) == 0) grp = lg[(size_t)(e / kBrickGroup) * kWave];
         const int word = e >> 1 & 3;
         const uint32_t pair = word == 0 ? grp.x : word == 1 ? grp.y : word == 2 ? grp.z : grp.w;
         const int sl = (int)(pair >> ((e & 1) * 16) & 0xFFFFu);
-        const uint32_t inf = __float_as_uint(sPos[sl].w);  // read before the cursor moves
-        while (sl < lo || sl >= hi) {
-            if (++dx > 1) {
-                dx = -1;
-                if (++dy > 1) {
-                    dy = -1;
-                    ++dz;
-                }
-            }
-            if (dz > 1) break;  // not reached: every entry lies in one of the 27 cells
-            t = tc + Staging<BX, BY, BZ>::step(dx, dy, dz);
-            lo = cBase[t];
-            hi = cBase[t + 1];
-            delta = cDelta[t];
-        }
-        const bool nb_boundary = ptype(inf) == kBoundary;
-        *(nb_boundary ? tb : tf) = (uint32_t)(sl - delta) | pack_neib(0u, -dx, -dy, -dz);
+        const uint32_t ws = __float_as_uint(sPos[sl].w);
+        const int t = (int)(ws >> kCellShift & kCellMask);
+        const bool nb_boundary = ptype(ws) == kBoundary;
+        *(nb_boundary ? tb : tf) = (uint32_t)(sl - cDelta[t]) | code[t];
         tf += nb_boundary ? 0 : kWave;
         tb -= nb_boundary ? kWave : 0;
     }
@@ -408,12 +401,8 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
     // slot from the back; the brick-local entries of the current group of 8
     // are collected in registers and stored as one 16-byte group when it is
     // full (groups are kWave x 8 entries apart), the last one at the end.
-    // With the brick staged in LDS and brick-local lists asked for, the
-    // global entries are written after the scan from the brick-local ones
-    // (deferred): the lanes of a wave then write entry k of their lists in
-    // one store, where during the scan each lane writes at its own pace and
-    // the tile rows leave the L2 cache partly filled, several times over.
-    const bool deferred = LDS && ltile != nullptr;
+    // (With the brick staged in LDS and brick-local lists asked for, the
+    // cell form of the scan runs instead.)
     uint32_t *tf = tile, *tb = tile + (size_t)(M - 1) * kWave;
     uint4 *lg = (uint4 *)ltile;
     uint4 grp = make_uint4(0u, 0u, 0u, 0u);
@@ -461,7 +450,7 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
                         if (w < M) {
                             const int sl = c0 + k;
                             const int j = sl - delta;
-                            if (!deferred) {
+                            {
                                 const uint32_t inf = LDS ? __float_as_uint(sPos[sl].w) : ginfo[j];
                                 const bool nb_boundary = ptype(inf) == kBoundary;
                                 *(nb_boundary ? tb : tf) = (uint32_t)j | code;
@@ -488,10 +477,6 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
         }
     }
     if (ltile && (w & (kBrickGroup - 1)) != 0) lg[(size_t)(w / kBrickGroup) * kWave] = grp;
-    if (deferred) {
-        total_found = found;
-        return brick_jlists<BX, BY, BZ>(tc, M, w, cBase, cDelta, sPos, tile, ltile);
-    }
     const int wf = (int)((tf - tile) / kWave), wb = w - wf;
     total_found = found;
     return (uint32_t)wf | (uint32_t)wb << 16;
@@ -515,7 +500,6 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
 // the cell set points at a dummy staged particle far away.
 constexpr int kItemChunks = 6;                 // candidate chunks held in registers per pass
 constexpr int kItemParts = 2;                  // work items per inner cell (its centrals split evenly)
-constexpr uint32_t kFoundMask = (1u << kTypeShift) - 1u;
 
 // Tests of one central (LDS slot si, position pi) against the nch candidate
 // chunks of the item; found: entries so far.  MASK_B: the central is a
@@ -678,9 +662,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     __shared__ int iStart[NI];
     __shared__ int wsum[NT / kWave];
     __shared__ int sItem;  // work items taken (cell form of the scan)
+    // image code of the neighbour cell at staged offset d = t - tc from the
+    // central's cell, at index d + S - 1 (offsets that are no neighbour: 0)
+    __shared__ uint32_t sCode[2 * S - 1];
+    static_assert(S - 1 <= (int)kCellMask, "the staged cell fits its field of the staged word");
 
     const int tid = threadIdx.x;
     if ((int)blockIdx.x >= active[0]) return;
+    for (int k = tid; k < 2 * S - 1; k += NT) {  // (read after the staging barrier)
+        // d = dx + SX (dz + SZ dy) with dx, dy, dz in {-1, 0, 1}, d + S - 1 = k
+        const int e = k - (S - 1) + 1 + SX + SX * SZ;
+        const int ex = e % SX, ez = (e / SX) % SZ, ey = e / (SX * SZ);
+        const bool nb = e >= 0 && ex <= 2 && ez <= 2 && ey <= 2;
+        sCode[k] = nb ? pack_neib(0u, 1 - ex, 1 - ey, 1 - ez) : 0u;
+    }
     const int b = active[1 + blockIdx.x];
     const int cx0 = (b % G.nbx) * BX, cy0 = ((b / G.nbx) % G.nby) * BY, cz0 = (b / (G.nbx * G.nby)) * BZ;
 
@@ -742,7 +737,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
         const uint32_t inf = info[j];
         if (use_lds) {
             float4 p = pos[j];
-            p.w = __uint_as_float(inf);
+            p.w = __uint_as_float((inf & ~((1u << kTypeShift) - 1u)) | (uint32_t)lo << kCellShift);
             sPos[s2] = p;
         }
         if (ptype(inf) == kBoundary && (s2 == cBase[lo] || ptype(info[j - 1]) != kBoundary)) cFluidEnd[lo] = s2;
@@ -773,7 +768,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
             const int tc = St::inner(u);
             const int found = (int)(__float_as_uint(sPos[i + cDelta[tc]].w) & kFoundMask);
             const size_t toff = (size_t)(i / kWave) * kWave * max_neibs + (i % kWave);
-            const uint32_t cw = brick_jlists<BX, BY, BZ>(tc, max_neibs, min(found, max_neibs), cBase, cDelta, sPos,
+            const uint32_t cw = brick_jlists<BX, BY, BZ>(tc, max_neibs, min(found, max_neibs), cDelta, sCode, sPos,
                                                          neibs + toff,
                                                          neibs_brick + brick_entry(i, 0, brick_groups(max_neibs)));
             neib_count[i] = cw;
