@@ -499,7 +499,7 @@ __device__ __forceinline__ uint32_t brick_scan(int i, int tc, int M, const float
 // type word (its type bits stay: other waves read them); a candidate past
 // the cell set points at a dummy staged particle far away.
 constexpr int kItemChunks = 6;                 // candidate chunks held in registers per pass
-constexpr int kItemParts = 2;                  // work items per inner cell (its centrals split evenly)
+constexpr int kItemParts = 1;                  // work items per inner cell (its centrals split evenly)
 
 // Tests of one central (LDS slot si, position pi) against the nch candidate
 // chunks of the item; found: entries so far.  MASK_B: the central is a
