@@ -510,6 +510,15 @@ sph_status sph_count_missed_pairs(const sph_grid *grid, const sph_params *params
                                   const uint32_t *neib_count, int32_t max_neibs, int32_t phase,
                                   long long *d_missed, void *stream);
 
+/* Stream copy of `bytes` bytes from src to dst (device, 16-byte aligned,
+ * bytes a multiple of 16, not overlapping), blocks_per_cu workgroups of 256
+ * lanes per compute unit (1..64), each lane moving 16-byte vectors with
+ * four loads in flight and nontemporal stores.  A measurement aid, no part
+ * of the method: the bench times it to report the HBM bandwidth a plain
+ * stream achieves on the GPU beside the data-sheet peak.
+ * Errors: SPH_ERR_ARG. */
+sph_status sph_stream_copy(const void *src, void *dst, size_t bytes, int32_t blocks_per_cu, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,6 +31,7 @@ EXPORTS = [
     "sph_forces_backward_workspace_bytes", "sph_forces_backward", "sph_unpermute",
     "sph_diagnostics_workspace_bytes", "sph_reduce_diagnostics", "sph_count_missed_pairs",
     "sph_forces_noalloc", "sph_dt_scenes_workspace_bytes", "sph_step_dt_scenes", "sph_integrate_scenes",
+    "sph_stream_copy",
 ]
 MAX_SCENES = 1 << 20
 
@@ -106,6 +107,8 @@ def _load():
     L.sph_count_missed_pairs.restype = st
     L.sph_forces_noalloc.argtypes = [P, P, P, P, P, i32, P, P, P, P, P]
     L.sph_forces_noalloc.restype = st
+    L.sph_stream_copy.argtypes = [P, P, C.c_size_t, i32, P]
+    L.sph_stream_copy.restype = st
     L.sph_integrate_backward.argtypes = [P, i32, P, P, P, P, P, P, P, P]
     L.sph_integrate_backward.restype = st
     L.sph_forces_backward_workspace_bytes.argtypes = [i32, i32]
@@ -268,6 +271,11 @@ def sph_count_interactions(grid: SphGrid, params: SphParams, parts: SphParticles
     check(lib.sph_count_interactions(C.byref(grid), C.byref(params), C.byref(parts), ptr(neibs),
                                      ptr(neib_count), int(max_neibs), ptr(d_count), stream_ptr(stream)),
           "sph_count_interactions")
+
+
+def sph_stream_copy(src, dst, nbytes: int, blocks_per_cu: int = 8, stream=None):
+    check(lib.sph_stream_copy(ptr(src), ptr(dst), int(nbytes), int(blocks_per_cu), stream_ptr(stream)),
+          "sph_stream_copy")
 
 
 def sph_count_missed_pairs(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count,

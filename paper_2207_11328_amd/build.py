@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libsph.so")
 # smoothing kernel so the instances of the four kernels build in parallel
 PAIR_SOURCES = ["forces_pairs.hip", "forces_backward_pairs.hip"]
 SOURCES = ([(s, s.replace(".hip", ".o"), []) for s in
-            ["neighbors.hip", "forces.hip", "forces_backward.hip", "integrate.hip"]] +
+            ["neighbors.hip", "forces.hip", "forces_backward.hip", "integrate.hip", "probe.hip"]] +
            [(s, s.replace(".hip", "_k%d.o" % k), ["-DSPH_KERNEL_KIND=%d" % k]) for s in PAIR_SOURCES for k in range(4)])
 ARCH = "gfx950"
 

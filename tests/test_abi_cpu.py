@@ -133,6 +133,16 @@ def test_argument_errors_return_before_any_launch(abi):
                                               out, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_count_missed_pairs(C.byref(g2), C.byref(p2), C.byref(empty), None, None, 128, 0, None,
                                           None) == abi.SPH_ERR_ARG
+    # the stream-copy probe: sizes and addresses off 16 bytes, missing
+    # buffers, workgroups per CU outside 1..64; an empty copy launches nothing
+    buf = (C.c_uint8 * 64)()
+    al = (C.addressof(buf) + 15) & ~15
+    assert abi.lib.sph_stream_copy(al, al + 16, 8, 8, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_stream_copy(al + 1, al + 16, 16, 8, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_stream_copy(None, al, 16, 8, None) == abi.SPH_ERR_ARG
+    for bad in (0, 65):
+        assert abi.lib.sph_stream_copy(al, al + 16, 16, bad, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_stream_copy(None, None, 0, 8, None) == abi.SPH_OK
 
 
 def test_unknown_model_switches_are_rejected(abi):
