@@ -222,36 +222,55 @@ __global__ __launch_bounds__(kThreads) void k_scatter(int n, const int32_t *__re
     if (valid) perm[start[b] + r] = (uint32_t)i;
 }
 
-// One wave per bucket: rank each particle of the bucket by its info word
-// (type << 30 | id) and write it to its final position.  Ids are unique;
-// equal words (invalid input) are ranked by their slot so the result is a
-// permutation in every case.
-__global__ __launch_bounds__(kThreads) void k_cell_sort(int n_buckets, const int32_t *__restrict__ start,
+// Rank each particle of a bucket by its info word (type << 30 | id) and
+// write it to its final position.  Ids are unique; equal words (invalid
+// input) are ranked by their slot so the result is a permutation in every
+// case.  One wave per window of kWave consecutive positions of the scattered
+// order (which is grouped by bucket): the wave ranks the buckets that start
+// in its window, one after the other.  Most buckets of a grid can be empty
+// (the air above a dam break); waves over positions visit only buckets that
+// hold particles, where a wave per bucket would be dispatched for each.
+__global__ __launch_bounds__(kThreads) void k_cell_sort(int n, const int32_t *__restrict__ cell, int cell_base,
+                                                        int n_cells, const int32_t *__restrict__ start,
                                                         const uint32_t *__restrict__ perm_in,
                                                         const uint32_t *__restrict__ info,
                                                         uint32_t *__restrict__ perm_out)
 {
-    const int b = blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
-    if (b >= n_buckets) return;
+    const int w0 = (blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave) * kWave;
+    if (w0 >= n) return;  // uniform
     const int lane = threadIdx.x % kWave;
-    const int s = start[b];
-    const int m = start[b + 1] - s;
-    for (int mb = 0; mb < m; mb += kWave) {
-        const int me = mb + lane;
-        const bool valid = me < m;
-        const uint32_t idx = valid ? perm_in[s + me] : 0u;
-        const uint32_t key = valid ? info[idx] : 0xFFFFFFFFu;
-        int rank = 0;
-        for (int tb = 0; tb < m; tb += kWave) {
-            const int t = tb + lane;
-            const uint32_t kt_lane = t < m ? info[perm_in[s + t]] : 0xFFFFFFFFu;
-            const int cnt = min(kWave, m - tb);
-            for (int u = 0; u < cnt; ++u) {
-                const uint32_t kt = __shfl(kt_lane, u);
-                rank += (kt < key || (kt == key && tb + u < me)) ? 1 : 0;
+    const int p = w0 + lane;
+    int b = 0;  // bucket of position p
+    bool first = false;
+    if (p < n) {
+        const int c = cell[perm_in[p]];
+        b = c >= 0 ? c - cell_base : n_cells;
+        first = start[b] == p;
+    }
+    unsigned long long F = __ballot(first);
+    while (F) {  // uniform: the buckets that start in the window
+        const int k = __ffsll((long long)F) - 1;
+        F &= F - 1;
+        const int bk = __shfl(b, k);
+        const int s = w0 + k;
+        const int m = start[bk + 1] - s;
+        for (int mb = 0; mb < m; mb += kWave) {
+            const int me = mb + lane;
+            const bool valid = me < m;
+            const uint32_t idx = valid ? perm_in[s + me] : 0u;
+            const uint32_t key = valid ? info[idx] : 0xFFFFFFFFu;
+            int rank = 0;
+            for (int tb = 0; tb < m; tb += kWave) {
+                const int t = tb + lane;
+                const uint32_t kt_lane = t < m ? info[perm_in[s + t]] : 0xFFFFFFFFu;
+                const int cnt = min(kWave, m - tb);
+                for (int u = 0; u < cnt; ++u) {
+                    const uint32_t kt = __shfl(kt_lane, u);
+                    rank += (kt < key || (kt == key && tb + u < me)) ? 1 : 0;
+                }
             }
+            if (valid) perm_out[s + rank] = idx;
         }
-        if (valid) perm_out[s + rank] = idx;
     }
 }
 
@@ -921,8 +940,8 @@ extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params
     if (n > 0) {
         k_scatter<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, parts->cell, grid->cell_base, n_cells,
                                                                 start, cursor, perm_a);
-        k_cell_sort<<<sph_blocks(nbk, kThreads / kWave), kThreads, 0, s>>>(nbk, start, perm_a, parts->info,
-                                                                              perm_b);
+        k_cell_sort<<<sph_blocks((n + kWave - 1) / kWave, kThreads / kWave), kThreads, 0, s>>>(
+            n, parts->cell, grid->cell_base, n_cells, start, perm_a, parts->info, perm_b);
         k_gather<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, perm_b, parts->cell, pos, vel, parts->info,
                                                                t_cell, t_pos, t_vel, t_info, perm_out, d_status);
         SPH_CHECK_LAUNCH();
