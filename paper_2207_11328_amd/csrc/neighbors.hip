@@ -51,11 +51,30 @@ BuildLayout build_layout(int64_t capacity, int64_t n_cells)
     return L;
 }
 
-__global__ void k_fill(int32_t *__restrict__ p, int64_t n, int32_t v)
+// Everything the build counts into starts at zero, in one launch (a kernel,
+// not a memset, so that a captured graph holds no memset node): the bucket
+// counts and cursors (nb each), the status words, the cell flags of the
+// table of bricks with a pair (flag_words int32 words, none without brick
+// lists) and the counters of the active-brick list and of that table.
+__global__ void k_build_zero(int64_t nb, int32_t *__restrict__ cnt, int32_t *__restrict__ cursor,
+                             int32_t *__restrict__ status, int64_t flag_words, int32_t *__restrict__ flags,
+                             int32_t *__restrict__ active, int32_t *__restrict__ table_heavy,
+                             int32_t *__restrict__ table_light)
 {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = v;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x, stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = t; i < nb; i += stride) {
+        cnt[i] = 0;
+        cursor[i] = 0;
+    }
+    for (int64_t i = t; i < flag_words; i += stride) flags[i] = 0;
+    if (t < SPH_STATUS_WORDS) status[t] = 0;
+    if (t == 0) {
+        *active = 0;
+        if (table_heavy) {
+            *table_heavy = 0;
+            *table_light = 0;
+        }
+    }
 }
 
 // atomicAdd(&cnt[key], 1) for every valid lane of a wave, combined over runs
@@ -307,6 +326,10 @@ __global__ __launch_bounds__(kThreads) void k_gather(int n, const uint32_t *__re
     if (m && (threadIdx.x % kWave) == 0) atomicAdd(&status[SPH_STATUS_NONFINITE], (int)__popcll(m));
 }
 
+// The sorted state back into the caller's arrays.  Also: particles dropped
+// by the build are in no brick and get no neighbours (count 0), and, when
+// flags is not null, the cells that hold a particle with a non-empty list
+// are flagged (for the table of bricks with a pair).
 __global__ __launch_bounds__(kThreads) void k_copy_state(int n, const int32_t *__restrict__ cell,
                                                          const float4 *__restrict__ pos,
                                                          const float4 *__restrict__ vel,
@@ -314,31 +337,41 @@ __global__ __launch_bounds__(kThreads) void k_copy_state(int n, const int32_t *_
                                                          int32_t *__restrict__ o_cell,
                                                          float4 *__restrict__ o_pos,
                                                          float4 *__restrict__ o_vel,
-                                                         uint32_t *__restrict__ o_info)
+                                                         uint32_t *__restrict__ o_info,
+                                                         uint32_t *__restrict__ neib_count, int cell_base,
+                                                         int n_cells, uint8_t *__restrict__ flags)
 {
     const int k = blockIdx.x * kThreads + threadIdx.x;
     if (k >= n) return;
-    o_cell[k] = cell[k];
+    const int c = cell[k];
+    o_cell[k] = c;
     o_pos[k] = pos[k];
     o_vel[k] = vel[k];
     o_info[k] = info[k];
+    if (c < 0) {
+        neib_count[k] = 0u;
+    } else if (flags && neib_count[k] != 0u) {
+        const int lc = c - cell_base;
+        if ((unsigned)lc < (unsigned)n_cells) flags[lc] = 1;
+    }
 }
 
+// Cell ranges from the bucket starts; thread 0 also writes the particles in
+// cells and the dropped ones (the last bucket) to the status words.
 __global__ __launch_bounds__(kThreads) void k_cell_ranges(int n_cells, const int32_t *__restrict__ start,
                                                           int32_t *__restrict__ cell_start,
-                                                          int32_t *__restrict__ cell_end)
+                                                          int32_t *__restrict__ cell_end, int n,
+                                                          int32_t *__restrict__ status)
 {
     const int c = blockIdx.x * kThreads + threadIdx.x;
+    if (c == 0) {
+        const int n_active = start[n_cells];
+        status[SPH_STATUS_N_ACTIVE] = n_active;
+        status[SPH_STATUS_DROPPED] = n - n_active;
+    }
     if (c >= n_cells) return;
     cell_start[c] = start[c];
     cell_end[c] = start[c + 1];
-}
-
-__global__ void k_status(int n, int n_cells, const int32_t *__restrict__ start, int32_t *__restrict__ status)
-{
-    const int n_active = start[n_cells];
-    status[SPH_STATUS_N_ACTIVE] = n_active;
-    status[SPH_STATUS_DROPPED] = n - n_active;
 }
 
 // Neighbour lists, cell-brick form (section "Changing perspective: from the
@@ -828,14 +861,6 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
     }
 }
 
-// particles dropped by the build are in no brick: no neighbours
-__global__ __launch_bounds__(kThreads) void k_zero_dropped_counts(int n, const int32_t *__restrict__ cell,
-                                                                  uint32_t *__restrict__ neib_count)
-{
-    const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (i < n && cell[i] < 0) neib_count[i] = 0u;
-}
-
 constexpr int kBuildCap = 4800;  // 75 KB of LDS for the halo: two workgroups per CU
 
 bool grid_ok(const sph_grid *g, float r_search)
@@ -918,10 +943,15 @@ extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params
     const CellDims dims{grid->ncell[0], grid->ncell[1], grid->ncell[2], grid->periodic};
     const int nbk = n_cells + 1;
 
-    const unsigned fill_blocks = sph_blocks(nbk, kThreads) < 4096u ? sph_blocks(nbk, kThreads) : 4096u;
-    k_fill<<<fill_blocks, kThreads, 0, s>>>(cnt, nbk, 0);
-    k_fill<<<fill_blocks, kThreads, 0, s>>>(cursor, nbk, 0);
-    k_fill<<<1, 64, 0, s>>>(d_status, SPH_STATUS_WORDS, 0);
+    const int cap_ids = brick_table_cap(cap);
+    int32_t *table = neibs_brick ? brick_table(reinterpret_cast<int32_t *>(neibs_brick), cap, max_neibs) : nullptr;
+    uint8_t *flags = neibs_brick ? (uint8_t *)(ws + L.flags) : nullptr;
+    int32_t *active = (int32_t *)(ws + L.active);
+    const int64_t flag_words = neibs_brick ? (n_cells + 3) / 4 : 0;
+    const int64_t zero_items = nbk > flag_words ? nbk : flag_words;
+    const unsigned fill_blocks = sph_blocks(zero_items, kThreads) < 4096u ? sph_blocks(zero_items, kThreads) : 4096u;
+    k_build_zero<<<fill_blocks, kThreads, 0, s>>>(nbk, cnt, cursor, d_status, flag_words, (int32_t *)flags, active,
+                                                  table, table ? table + cap_ids + 1 : nullptr);
     SPH_CHECK_LAUNCH();
     if (n > 0) {
         k_rebin_count<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(
@@ -934,8 +964,8 @@ extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params
     k_scan_partials<<<1, kThreads, 0, s>>>(partials, np, start + nbk);
     k_scan_apply<<<np, kThreads, 0, s>>>(cnt, nbk, partials, start);
     SPH_CHECK_LAUNCH();
-    k_status<<<1, 1, 0, s>>>(n, n_cells, start, d_status);
-    k_cell_ranges<<<sph_blocks(n_cells, kThreads), kThreads, 0, s>>>(n_cells, start, cell_start, cell_end);
+    k_cell_ranges<<<sph_blocks(n_cells, kThreads), kThreads, 0, s>>>(n_cells, start, cell_start, cell_end, n,
+                                                                     d_status);
     SPH_CHECK_LAUNCH();
     if (n > 0) {
         k_scatter<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, parts->cell, grid->cell_base, n_cells,
@@ -946,36 +976,25 @@ extern "C" sph_status sph_build_neighbors(const sph_grid *grid, const sph_params
                                                                t_cell, t_pos, t_vel, t_info, perm_out, d_status);
         SPH_CHECK_LAUNCH();
         const float rs2 = params->r_search * params->r_search;
-        int32_t *active = (int32_t *)(ws + L.active);
         with_shape(shape, [&]<int BX, int BY, int BZ>() {
             const BrickGrid G = brick_grid<BX, BY, BZ>(grid->ncell, grid->periodic);
             const unsigned bricks = (unsigned)G.nbx * G.nby * G.nbz;
             constexpr int NT = brick_threads(BX * BY * BZ);
-            k_zero_one<int32_t><<<1, 1, 0, s>>>(active);
             // brick activity from the (exclusive-scan) cell starts: start[c + 1] is the end of cell c
             k_active_bricks<BX, BY, BZ><<<sph_blocks(bricks, 256), 256, 0, s>>>(start, start + 1, G, active, nullptr);
             k_build_brick<BX, BY, BZ, NT, kBuildCap><<<bricks, NT, 0, s>>>(
                 n, max_neibs, t_pos, t_info, start, G, grid->cell_size[0], grid->cell_size[1], grid->cell_size[2],
                 rs2, active, neibs, neibs_brick, neib_count, d_status);
         });
-        k_zero_dropped_counts<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, t_cell, neib_count);
         k_copy_state<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, t_cell, t_pos, t_vel, t_info, parts->cell,
-                                                                   pos, vel, parts->info);
+                                                                   pos, vel, parts->info, neib_count,
+                                                                   grid->cell_base, n_cells, flags);
         SPH_CHECK_LAUNCH();
     }
     if (neibs_brick) {
         // the table of bricks with a pair behind the brick-local lists, for
         // the derivative kernels (heavy bricks first: at least 12 particles
-        // per inner cell)
-        const int cap_ids = brick_table_cap(cap);
-        int32_t *table = brick_table(reinterpret_cast<int32_t *>(neibs_brick), cap, max_neibs);
-        uint8_t *flags = (uint8_t *)(ws + L.flags);
-        k_fill<<<fill_blocks, kThreads, 0, s>>>((int32_t *)flags, (n_cells + 3) / 4, 0);
-        k_zero_one<int32_t><<<1, 1, 0, s>>>(table);
-        k_zero_one<int32_t><<<1, 1, 0, s>>>(table + cap_ids + 1);
-        if (n > 0)
-            k_flag_cells<<<sph_blocks(n, kThreads), kThreads, 0, s>>>(n, parts->cell, grid->cell_base, n_cells,
-                                                                       neib_count, flags);
+        // per inner cell), from the cell flags k_copy_state set
         with_shape(shape, [&]<int BX, int BY, int BZ>() {
             const BrickGrid G = brick_grid<BX, BY, BZ>(grid->ncell, grid->periodic);
             const unsigned bricks = (unsigned)G.nbx * G.nby * G.nbz;

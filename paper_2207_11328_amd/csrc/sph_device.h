@@ -370,19 +370,6 @@ __global__ void k_zero_one(T *p)
     *p = T(0);
 }
 
-// Flag the cells that hold a particle with a non-empty list (sorted state:
-// cell[i] - cell_base, count[i] = nf | nb << 16; dropped particles have cell
-// -1 and count 0).
-__global__ __launch_bounds__(256) inline void k_flag_cells(int n, const int32_t *__restrict__ cell, int cell_base,
-                                                           int n_cells, const uint32_t *__restrict__ count,
-                                                           uint8_t *__restrict__ flags)
-{
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n || count[i] == 0u) return;
-    const int lc = cell[i] - cell_base;
-    if ((unsigned)lc < (unsigned)n_cells) flags[lc] = 1;
-}
-
 }  // namespace sph
 
 // Host-side launch helpers.
