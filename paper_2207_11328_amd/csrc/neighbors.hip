@@ -400,8 +400,8 @@ __global__ __launch_bounds__(kThreads) void k_cell_ranges(int n_cells, const int
 // stored in groups of 8 per particle (brick_entry).
 // The staged word of a particle (w of its float4 in LDS): its type in the
 // type bits, its staged cell in bits kCellShift.., and for a central the
-// number of neighbours found so far in the low bits (kFoundMask; a count
-// saturates there, far above any list length).
+// number of neighbours found so far in the low bits (kFoundMask; the count is
+// below the brick's staged particles, fewer than kBuildCap).
 constexpr uint32_t kFoundMask = 0xFFFFu;
 constexpr int kCellShift = 16;
 constexpr uint32_t kCellMask = 0xFFu;
@@ -862,6 +862,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(NT / 128))) 
 }
 
 constexpr int kBuildCap = 4800;  // 75 KB of LDS for the halo: two workgroups per CU
+static_assert(kBuildCap <= (int)kFoundMask, "a central's count of found neighbours fits its field");
 
 bool grid_ok(const sph_grid *g, float r_search)
 {
