@@ -83,6 +83,10 @@ def parse():
     ap.add_argument("--brick", default=None, metavar="BX,BY,BZ",
                     help="use this brick shape for the 1.62M dam break and the batched tanks instead of the "
                          "autotuner's choice (profiling runs: counters distort the tuner's timings)")
+    ap.add_argument("--no-fuse", action="store_true",
+                    help="take the corrector's derivatives and update as two calls (sph_forces, sph_integrate) "
+                         "instead of one (sph_forces_corrector): every k_forces_brick dispatch is then a plain "
+                         "sph_forces call (counter passes of that call)")
     ap.add_argument("--gather-probe", type=int, default=0, metavar="MIB",
                     help="only run a gather of MIB MiB in 128-byte rows taken in a random order, three times "
                          "(checks the HBM byte counters' scale on a scattered pattern) and exit")
@@ -642,8 +646,11 @@ def main():
               tune.autotune(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0"))
 
     def new_sim():
-        return Simulation(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0",
-                          brick=choice["brick"], use_bricks=choice["bricks"])
+        s = Simulation(sc.grid, sc.params, sc.cell, sc.pos, sc.vel, sc.info, device="cuda:0",
+                       brick=choice["brick"], use_bricks=choice["bricks"])
+        if args.no_fuse:
+            s.fuse_corrector = False
+        return s
 
     sim = new_sim()
     for _ in range(W):

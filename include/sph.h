@@ -353,6 +353,34 @@ sph_status sph_integrate(const sph_params *params, int32_t stage, const double *
                          const float *forces, sph_particles *out, double *d_time,
                          void *stream);
 
+/* The corrector half of the step in one pass (section "Code structure": the
+ * corrector's derivatives at the predicted state, then its update with dt):
+ * the derivatives of `star` exactly as sph_forces computes them (same
+ * lists, kernels and rounding), and, for each particle as soon as its
+ * derivatives are finished, sph_integrate stage 1 applied to state_n in
+ * place with vel_star = star->vel.  The result is bit for bit that of
+ *   sph_forces(star) -> forces;  sph_integrate(1, state_n, star->vel, forces,
+ *                                              out = state_n, d_time)
+ * without the round trip of the derivatives through device memory.
+ * d_dt: device double, the step; d_time: device double advanced by dt, or
+ * NULL; forces: device float[capacity][4] that also receives the
+ * derivatives, or NULL.  state_n->cell and ->info give each particle's
+ * cell (dropped particles, cell < 0, are left unchanged) and type; only
+ * state_n->pos and ->vel are written.  state_n and star hold the same
+ * particles in the same order (those of the last build) and must not share
+ * pos or vel storage: the kernel reads the staged state of other particles
+ * while it rewrites state n.
+ * Every other argument is that of sph_forces.  One scene per call (one dt).
+ * Errors: those of sph_forces; SPH_ERR_ARG for a null d_dt, star or
+ * state_n, state_n->n != star->n, missing state_n arrays, or shared
+ * pos / vel storage. */
+sph_status sph_forces_corrector(const sph_grid *grid, const sph_params *params, const sph_particles *star,
+                                const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
+                                const int32_t *cell_start, const int32_t *cell_end,
+                                const uint16_t *neibs_brick, const double *d_dt, sph_particles *state_n,
+                                double *d_time, float *forces, void *workspace, size_t workspace_bytes,
+                                void *stream);
+
 /* Reverse of sph_integrate (the transpose of its linear update; dt is held
  * fixed).  All grad arrays are device float[capacity][4] laid out like the
  * state: grad_pos xyz = dL/d(offset), grad_vel xyz = dL/du, w = dL/drho;

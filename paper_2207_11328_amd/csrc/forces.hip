@@ -73,6 +73,8 @@ __global__ __launch_bounds__(kThreads) void k_count_interactions(int n, const fl
 
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
 
+__global__ void k_add_time(double *d_time, const double *d_dt) { *d_time += *d_dt; }
+
 // missed pairs of a rebuild: the difference of the two counts, and its running total
 __global__ void k_missed_finish(long long *m)
 {
@@ -156,14 +158,16 @@ extern "C" size_t sph_forces_workspace_bytes(int32_t capacity, int32_t n_cells)
     return aux_bytes(capacity > 0 ? capacity : 1) + 256;
 }
 
-extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
-                                 const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
-                                 const int32_t *cell_start, const int32_t *cell_end,
-                                 const uint16_t *neibs_brick, float *forces, void *workspace,
-                                 size_t workspace_bytes, void *stream)
+namespace {
+
+// sph_forces, and with K.d_dt set sph_forces_corrector (forces may then be null)
+sph_status forces_impl(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
+                       const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
+                       const int32_t *cell_start, const int32_t *cell_end, const uint16_t *neibs_brick,
+                       float *forces, void *workspace, size_t workspace_bytes, void *stream, const Corrector &K)
 {
     if (!common_args(grid, params, parts, neibs, neib_count, max_neibs)) return SPH_ERR_ARG;
-    if (parts->n > 0 && !forces) return SPH_ERR_ARG;
+    if (parts->n > 0 && !forces && !K.d_dt) return SPH_ERR_ARG;
     ForceConst C;
     if (!make_const(grid, params, max_neibs, C)) return SPH_ERR_ARG;
     const int shape = brick_shape_index(grid->brick);
@@ -173,8 +177,13 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
     if (!workspace || workspace_bytes < sph_forces_workspace_bytes(parts->capacity, (int32_t)n_cells))
         return SPH_ERR_WORKSPACE;
     const int n = parts->n;
-    if (n == 0) return SPH_OK;
     hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        // the corrector's clock still advances, as the separate stage's does
+        if (K.d_dt && K.d_time) k_add_time<<<1, 1, 0, s>>>(K.d_time, K.d_dt);
+        SPH_CHECK_LAUNCH();
+        return SPH_OK;
+    }
     float2 *aux = (float2 *)workspace;
     int32_t *next = (int32_t *)((char *)workspace + aux_bytes(parts->capacity > 0 ? parts->capacity : 1));
     if (grid->cell_alpha && !parts->cell) return SPH_ERR_ARG;
@@ -206,12 +215,56 @@ extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params,
     a.next = next;
     a.out = (float4 *)forces;
     a.bricks = bricks;
+    a.K = K;
     static bool (*const pairs[4])(int, const ForceArgs &, const ForceConst &, hipStream_t) = {
         forces_pairs_kernel0, forces_pairs_kernel1, forces_pairs_kernel2, forces_pairs_kernel3};
     const int model = model_of(params);
     if (!pairs[model_kernel(model)](model, a, C, s)) return SPH_ERR_ARG;
     SPH_CHECK_LAUNCH();
     return SPH_OK;
+}
+
+}  // namespace
+
+extern "C" sph_status sph_forces(const sph_grid *grid, const sph_params *params, const sph_particles *parts,
+                                 const uint32_t *neibs, const uint32_t *neib_count, int32_t max_neibs,
+                                 const int32_t *cell_start, const int32_t *cell_end,
+                                 const uint16_t *neibs_brick, float *forces, void *workspace,
+                                 size_t workspace_bytes, void *stream)
+{
+    const Corrector none = {};
+    return forces_impl(grid, params, parts, neibs, neib_count, max_neibs, cell_start, cell_end, neibs_brick, forces,
+                       workspace, workspace_bytes, stream, none);
+}
+
+extern "C" sph_status sph_forces_corrector(const sph_grid *grid, const sph_params *params,
+                                           const sph_particles *star, const uint32_t *neibs,
+                                           const uint32_t *neib_count, int32_t max_neibs,
+                                           const int32_t *cell_start, const int32_t *cell_end,
+                                           const uint16_t *neibs_brick, const double *d_dt,
+                                           sph_particles *state_n, double *d_time, float *forces,
+                                           void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!star || !state_n || !d_dt) return SPH_ERR_ARG;
+    if (state_n->n != star->n || state_n->capacity < star->n) return SPH_ERR_ARG;
+    if (star->n > 0) {
+        if (!state_n->pos || !state_n->vel || !state_n->cell || !state_n->info) return SPH_ERR_ARG;
+        // state n is rewritten while the kernel still reads state * of other
+        // particles: the two must not share storage
+        if (state_n->pos == star->pos || state_n->vel == star->vel) return SPH_ERR_ARG;
+    }
+    Corrector K;
+    K.d_dt = d_dt;
+    K.pos = (float4 *)state_n->pos;
+    K.vel = (float4 *)state_n->vel;
+    K.cell = state_n->cell;
+    K.info = state_n->info;
+    K.d_time = d_time;
+    K.gx = params ? params->g[0] : 0.0f;
+    K.gy = params ? params->g[1] : 0.0f;
+    K.gz = params ? params->g[2] : 0.0f;
+    return forces_impl(grid, params, star, neibs, neib_count, max_neibs, cell_start, cell_end, neibs_brick, forces,
+                       workspace, workspace_bytes, stream, K);
 }
 
 extern "C" sph_status sph_count_interactions(const sph_grid *grid, const sph_params *params,

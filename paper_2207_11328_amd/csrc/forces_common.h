@@ -53,6 +53,31 @@ __device__ __forceinline__ float alpha_h_of(int j, const int32_t *__restrict__ c
     return C.cell_alpha ? C.cell_alpha[cell[j] - C.cell_base] * C.h : C.alpha_h;
 }
 
+// The corrector stage taken inside the derivative kernel
+// (sph_forces_corrector): as the derivatives f of a particle of state * are
+// finished, its state n is advanced in place by dt (midpoint_stage with the
+// stage velocity u*).  d_dt == nullptr: derivatives only.
+struct Corrector {
+    const double *d_dt;
+    float4 *pos, *vel;  // state n, overwritten by state n+1
+    const int32_t *cell;
+    const uint32_t *info;
+    double *d_time;     // advanced by dt once per call, or null
+    float gx, gy, gz;
+};
+
+// The update of particle i, which lies in a cell (a particle the build
+// dropped, cell < 0, is never passed here: it stays as it is); tau = (float)
+// dt, read once per kernel.  Its loads do not wait on one another.
+__device__ __forceinline__ void corrector_at(int i, const float4 &f, const float4 &ustar, float tau,
+                                             const Corrector &K)
+{
+    float4 p = K.pos[i], v = K.vel[i];
+    midpoint_stage(p, v, ustar, f, ptype(K.info[i]) == kBoundary, tau, K.gx, K.gy, K.gz);
+    K.pos[i] = p;
+    K.vel[i] = v;
+}
+
 struct ForceArgs {
     const sph_grid *grid;
     int shape;  // brick shape index
@@ -66,8 +91,9 @@ struct ForceArgs {
     const int32_t *table;  // bricks with a pair (brick_table layout), from the build
     int cap_ids;           // ids of the table
     int32_t *next;         // brick counter of the persistent workgroups (zeroed before the launch)
-    float4 *out;
+    float4 *out;  // may be null when K.d_dt is set
     bool bricks;
+    Corrector K;
 };
 
 // Launch the pair kernel of `model` (sph_model.h bits) on stream s; false if

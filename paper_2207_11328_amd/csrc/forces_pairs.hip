@@ -173,9 +173,11 @@ __global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__rest
                                                      const uint32_t *__restrict__ neibs,
                                                      const uint32_t *__restrict__ count,
                                                      const uint32_t *__restrict__ info,
-                                                     float4 *__restrict__ out, ForceConst C)
+                                                     float4 *__restrict__ out, ForceConst C, Corrector K)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
+    const float tau = K.d_dt ? (float)*K.d_dt : 0.0f;  // (the corrector's step)
+    if (K.d_dt && K.d_time && i == 0) *K.d_time += *K.d_dt;
     const int lane = threadIdx.x % kWave;
     const int ii = min(i, n - 1);  // lanes past the end load in bounds and store nothing
     const int M = C.max_neibs;
@@ -186,7 +188,11 @@ __global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__rest
     const int nt = min(nf + (int)(cnt >> 16), M);
     const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
     if (ntw == 0) {
-        if (i < n) out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (i < n) {
+            const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (out) out[i] = z;
+            if (K.d_dt && K.cell[i] >= 0) corrector_at(i, z, vel[i], tau, K);
+        }
         return;
     }
     // a wave is exactly one 64-particle tile of the list (wave-uniform base)
@@ -202,7 +208,11 @@ __global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__rest
     const bool central_fluid = (MODEL & kDiffusion) ? ptype(info[ii]) != kBoundary : true;
     gather_pairs<MODEL, kDepth>(A, tile + lane, nf, nt, ntw, M, jmax, pos, vel, aux, nullptr, pi, vi, ai,
                                 central_fluid, C);
-    if (i < n) out[i] = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (i < n) {
+        const float4 f = nt > 0 ? make_float4(A.ax, A.ay, A.az, A.dr) : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (out) out[i] = f;
+        if (K.d_dt && K.cell[i] >= 0) corrector_at(i, f, vi, tau, K);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -293,7 +303,8 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
                                                      const int32_t *__restrict__ table, int cap_ids,
                                                      int32_t *__restrict__ next,
                                                      const uint32_t *__restrict__ info,
-                                                     float4 *__restrict__ out, ForceConst C, BrickGrid G)
+                                                     float4 *__restrict__ out, ForceConst C, BrickGrid G,
+                                                     Corrector K)
 {
     using St = Staging<BX, BY, BZ>;
     constexpr int SX = BX + 2, SY = BY + 2, SZ = BZ + 2;
@@ -321,6 +332,8 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     // different costs even out across CUs, and the cheap bricks come last,
     // where they fill the gaps.
     const int n_listed = table[0] + table[cap_ids + 1];
+    const float tau = K.d_dt ? (float)*K.d_dt : 0.0f;  // (the corrector's step)
+    if (K.d_dt && K.d_time && blockIdx.x == 0 && threadIdx.x == 0) *K.d_time += *K.d_dt;
     // cell range (start, count) of staged cell t < S of brick b (count 0 for a
     // cell outside a non-periodic grid edge)
     auto ranges = [&](int b, int t, int &st, int &cnt) {
@@ -587,6 +600,7 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
             const int nt = min(nf + (int)(cntw >> 16), M);
             const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
             PairAcc A = {0.0f, 0.0f, 0.0f, 0.0f};
+            float4 ustar;  // the central's own velocity (corrector stage)
             if (ntw > 0) {
                 const size_t toff = (size_t)(i / kWave) * (kWave * M) + (i % kWave);
                 if (use_lds) {
@@ -598,6 +612,7 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
                     A.ay += __shfl_xor(A.ay, 1);
                     A.az += __shfl_xor(A.az, 1);
                     A.dr += __shfl_xor(A.dr, 1);
+                    if (K.d_dt) ustar = sV[i + cDelta[St::inner(u)]];
                 } else {
                     // the first lane of the pair walks the whole list (a shallow
                     // pipeline: this path shares the register budget of the LDS
@@ -606,10 +621,16 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
                     const float4 vi = vel[i];
                     gather_pairs<MODEL, 2>(A, neibs + toff, nf, h == 0 ? nt : 0, ntw, M, jmax, pos, vel, nullptr, cell,
                                            pos[i], vi, eos_terms(vi.w, alpha_h_of(i, cell, C), C), central_fluid, C);
+                    ustar = vi;
                 }
             }
             // (particles with an empty list are written after the last brick)
-            if (act && h == 0 && nt > 0) out[i] = make_float4(A.ax, A.ay, A.az, A.dr);
+            if (act && h == 0 && nt > 0) {
+                const float4 f = make_float4(A.ax, A.ay, A.az, A.dr);
+                if (out) out[i] = f;
+                // (a central lies in one of the brick's cells)
+                if (K.d_dt) corrector_at(i, f, ustar, tau, K);
+            }
             int gn = 0;
             if (tid % kWave == 0) gn = atomicAdd(&sGroup, 1) + NW;
             g = __builtin_amdgcn_readfirstlane(__shfl(gn, 0));
@@ -626,7 +647,11 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     // the build dropped) get zero derivatives, by all workgroups as they run
     // out of bricks: no other lane writes them.
     for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT)
-        if (count[i] == 0u) out[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (count[i] == 0u) {
+            const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (out) out[i] = z;
+            if (K.d_dt && K.cell[i] >= 0) corrector_at(i, z, vel[i], tau, K);
+        }
 }
 
 // LDS capacity (staged particles, 40 bytes each) per brick shape: the halo
@@ -650,7 +675,7 @@ void launch_brick(const ForceArgs &a, const ForceConst &C, hipStream_t s)
         const unsigned wgs = blocks < (unsigned)sph_device_cus() ? blocks : (unsigned)sph_device_cus();
         k_forces_brick<MODEL, BX, BY, BZ, NT, brick_cap(BX, BY, BZ)><<<wgs, NT, 0, s>>>(
             a.n, a.pos, a.vel, a.cell, a.neibs, a.neibs_brick, a.count, a.cell_start, a.cell_end, a.table,
-            a.cap_ids, a.next, a.info, a.out, C, G);
+            a.cap_ids, a.next, a.info, a.out, C, G, a.K);
     });
 }
 
@@ -670,7 +695,7 @@ bool sph::SPH_PAIRS_FN(SPH_KERNEL_KIND)(int model, const ForceArgs &a, const For
             launch_brick<M>(a, C, s);
         } else {
             k_forces<M><<<sph_blocks(a.n, kThreads), kThreads, 0, s>>>(a.n, a.pos, a.vel, a.aux, a.neibs, a.count,
-                                                                       a.info, a.out, C);
+                                                                       a.info, a.out, C, a.K);
         }
     });
 }

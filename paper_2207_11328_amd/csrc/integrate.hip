@@ -32,17 +32,9 @@ __global__ __launch_bounds__(kThreads) void k_integrate(int n, int stage, const 
     float4 p = pos_n[i];
     float4 v = vel_n[i];
     if (cell[i] >= 0) {
-        const float4 f = forces[i];
-        if (ptype(info[i]) != kBoundary) {
-            const float4 ua = stage == 0 ? v : vel_star[i];
-            p.x = fmaf(tau, ua.x, p.x);
-            p.y = fmaf(tau, ua.y, p.y);
-            p.z = fmaf(tau, ua.z, p.z);
-            v.x = fmaf(tau, f.x + gx, v.x);
-            v.y = fmaf(tau, f.y + gy, v.y);
-            v.z = fmaf(tau, f.z + gz, v.z);
-        }
-        v.w = fmaf(tau, f.w, v.w);
+        const bool boundary = ptype(info[i]) == kBoundary;
+        const float4 ua = stage == 0 || boundary ? v : vel_star[i];
+        midpoint_stage(p, v, ua, forces[i], boundary, tau, gx, gy, gz);
     }
     pos_out[i] = p;
     vel_out[i] = v;
@@ -289,17 +281,9 @@ __global__ __launch_bounds__(kThreads) void k_integrate_scenes(
     if ((unsigned)sc < (unsigned)n_scenes) {  // (a cell of no scene: left as it is)
         const double dt = d_dt[sc];
         const float tau = (float)(stage == 0 ? 0.5 * dt : dt);
-        const float4 f = forces[i];
-        if (ptype(info[i]) != kBoundary) {
-            const float4 ua = stage == 0 ? v : vel_star[i];
-            p.x = fmaf(tau, ua.x, p.x);
-            p.y = fmaf(tau, ua.y, p.y);
-            p.z = fmaf(tau, ua.z, p.z);
-            v.x = fmaf(tau, f.x + gx, v.x);
-            v.y = fmaf(tau, f.y + gy, v.y);
-            v.z = fmaf(tau, f.z + gz, v.z);
-        }
-        v.w = fmaf(tau, f.w, v.w);
+        const bool boundary = ptype(info[i]) == kBoundary;
+        const float4 ua = stage == 0 || boundary ? v : vel_star[i];
+        midpoint_stage(p, v, ua, forces[i], boundary, tau, gx, gy, gz);
     }
     pos_out[i] = p;
     vel_out[i] = v;

@@ -363,6 +363,26 @@ __device__ __forceinline__ double dt_from_maxima(double c, double a, double h, d
     return cfl * dt;
 }
 
+// One stage of the explicit midpoint integrator for one particle (section
+// "Code structure": predictor with dt/2, corrector with dt): the state (p, v)
+// advances by tau along the stage velocity ua, the derivatives f plus gravity
+// g and the density rate f.w; a boundary particle advances its density only.
+// Every kernel that integrates goes through this one definition, so the
+// fused and the separate forms of a stage agree bit for bit.
+__device__ __forceinline__ void midpoint_stage(float4 &p, float4 &v, const float4 &ua, const float4 &f,
+                                               bool boundary, float tau, float gx, float gy, float gz)
+{
+    if (!boundary) {
+        p.x = fmaf(tau, ua.x, p.x);
+        p.y = fmaf(tau, ua.y, p.y);
+        p.z = fmaf(tau, ua.z, p.z);
+        v.x = fmaf(tau, f.x + gx, v.x);
+        v.y = fmaf(tau, f.y + gy, v.y);
+        v.z = fmaf(tau, f.z + gz, v.z);
+    }
+    v.w = fmaf(tau, f.w, v.w);
+}
+
 // A counter zeroed by a kernel (graph-capturable, no memset node).
 template <typename T>
 __global__ void k_zero_one(T *p)

@@ -11,7 +11,10 @@ of a good thing?": lists rebuilt every 10 steps by default):
     sph_forces(state *)      -> forces_*
     sph_integrate(stage 1)   -> state n+1 (in place), t += dt
 
-Nothing is synchronised with the host inside a step.
+For one scene the last two calls are one, sph_forces_corrector (the
+corrector's derivatives and update in the same kernel, bit for bit the same
+state n+1; forces_* is then not written).  Nothing is synchronised with the
+host inside a step.
 """
 from __future__ import annotations
 
@@ -109,6 +112,9 @@ class Simulation:
         self.parts_star = abi.particles_struct(n, self.cell, self.pos_star, self.vel_star, self.info)
         self.steps_done = 0
         self._built = False
+        # the corrector's derivatives and update in one kernel (one scene:
+        # the per-scene steps of batched scenes take the separate stage)
+        self.fuse_corrector = self.cell_scene is None
 
     # ------------------------------------------------------------ primitives
     def build(self, stream=None, perm_out=None, status=None):
@@ -163,6 +169,22 @@ class Simulation:
                        stream, cs, ce, nb)
         return out
 
+    def corrector(self, stream=None, bricks: bool | None = None, forces=None):
+        """The corrector half of the step in one kernel: the derivatives of
+        state * and sph_integrate stage 1 (state n -> n+1 in place, t += dt),
+        bit for bit forces(True) followed by integrate(1).  forces: a
+        [capacity, 4] tensor that also receives the derivatives, or None."""
+        cs, ce, nb = self.brick_args(bricks)
+        abi.sph_forces_corrector(self.g, self.p, self.parts_star, self.neibs, self.neib_count, self.max_neibs,
+                                 self.d_dt, self.parts, self.ws_forces, self.d_time, forces, stream, cs, ce, nb)
+
+    def _second_half(self, stream=None):
+        if self.fuse_corrector:
+            self.corrector(stream)
+        else:
+            self.forces(True, stream)
+            self.integrate(1, stream)
+
     def step_dt(self, stream=None):
         if self.cell_scene is not None:
             abi.sph_step_dt_scenes(self.g, self.p, self.parts, self.forces_n, self.cell_scene, self.n_scenes,
@@ -211,8 +233,7 @@ class Simulation:
         if self.dt_fixed is None:
             self.step_dt(stream)
         self.integrate(0, stream)
-        self.forces(True, stream)
-        self.integrate(1, stream)
+        self._second_half(stream)
         self.steps_done += 1
 
     def run(self, steps: int, stream=None):
@@ -240,8 +261,7 @@ class Simulation:
                     if self.dt_fixed is None:
                         self.step_dt()
                     self.integrate(0)
-                    self.forces(True)
-                    self.integrate(1)
+                    self._second_half()
         torch.cuda.current_stream(self.device).wait_stream(side)
         self.graph = graph
         return graph

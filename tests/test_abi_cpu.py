@@ -96,6 +96,8 @@ def test_argument_errors_return_before_any_launch(abi):
                                        0, None, 0, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_integrate_backward(None, 0, None, None, None, None, None, None, None,
                                           None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_forces_corrector(None, None, None, None, None, 128, None, None, None, None, None, None,
+                                        None, None, 0, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_unpermute(-1, None, None, None, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_unpermute(0, None, None, None, None) == abi.SPH_OK
     assert abi.lib.sph_integrate(None, 0, None, None, None, None, None, None, None) == abi.SPH_ERR_ARG
@@ -200,6 +202,17 @@ def test_misaligned_brick_lists_are_rejected(abi):
     # the same build call with no brick lists gets as far as the workspace check
     assert abi.lib.sph_build_neighbors(C.byref(g), C.byref(p), C.byref(parts), dev, dev, 128, dev, dev, dev,
                                        None, None, dev, C.c_size_t(0), None) == abi.SPH_ERR_WORKSPACE
+    # the fused corrector: no step, or state n sharing storage with state *
+    other = abi.SphParticles(1, 1, C.c_void_p(0x200000), C.c_void_p(0x200000), C.c_void_p(0x300000),
+                             C.c_void_p(0x300000))
+    assert abi.lib.sph_forces_corrector(C.byref(g), C.byref(p), C.byref(parts), dev, dev, 128, None, None, None,
+                                        None, C.byref(other), None, None, dev, big, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_forces_corrector(C.byref(g), C.byref(p), C.byref(parts), dev, dev, 128, None, None, None,
+                                        dev, C.byref(parts), None, None, dev, big, None) == abi.SPH_ERR_ARG
+    short = abi.SphParticles(0, 1, C.c_void_p(0x200000), C.c_void_p(0x200000), C.c_void_p(0x300000),
+                             C.c_void_p(0x300000))
+    assert abi.lib.sph_forces_corrector(C.byref(g), C.byref(p), C.byref(parts), dev, dev, 128, None, None, None,
+                                        dev, C.byref(short), None, None, dev, big, None) == abi.SPH_ERR_ARG
     for nb in (0x100002, 0x100008):
         nbp = C.c_void_p(nb)
         assert abi.lib.sph_build_neighbors(C.byref(g), C.byref(p), C.byref(parts), dev, dev, 128, dev, dev, dev,
