@@ -40,6 +40,21 @@ def _dropped_cloud():
     return sc
 
 
+def _isolated_dam_break():
+    # a small dam break with a few fluid particles alone in the empty part of
+    # the tank: no neighbour, so the corrector reaches them in the pass over
+    # the particles with an empty list
+    sc = S.dam_break(dp=0.02, box=(0.8, 0.3, 0.4), column=(0.2, 0.3, 0.2))
+    x = S.decode_positions(sc.grid, sc.cell, sc.pos[:, :3])
+    k = np.arange(5)
+    x[k] = np.array([[0.5 + 0.06 * j, 0.15, 0.25] for j in range(5)])
+    cell, off = S.encode_positions(sc.grid, x)
+    sc.cell[:] = cell
+    sc.pos[:, :3] = off
+    sc.vel[k, 0] = np.float32(0.3)
+    return sc
+
+
 def _variant(sc, kernel, visc, form, delta):
     return dataclasses.replace(sc, params=dataclasses.replace(sc.params, kernel=kernel, visc_model=visc, nu=2e-3,
                                                               formulation=form, delta=delta))
@@ -53,6 +68,7 @@ SCENES = {
     "cloud_cubic_morris_landrini_diffusion": (lambda: _variant(_moving_cloud(35), 1, 1, 1, 0.1), 192),
     "cloud_gaussian_monaghan_k": (lambda: _variant(_moving_cloud(37), 3, 2, 0, 0.0), 192),
     "dam_break_64k": (lambda: S.dam_break_64k(), 128),
+    "isolated_fluid": (_isolated_dam_break, 128),
 }
 
 
@@ -81,6 +97,10 @@ def test_corrector_equals_separate_calls(name, bricks):
     assert st["overflow"] == 0
     if name == "cloud_dropped":
         assert st["dropped"] > 0
+    if name == "isolated_fluid":
+        cnt = sim.neib_count[: sc.n].cpu().numpy()
+        info = sim.info[: sc.n].cpu().numpy().view(np.uint32)
+        assert ((cnt == 0) & ((info >> 30) == 0)).sum() >= 5, "fluid particles with an empty list"
     sim.forces(False)
     sim.step_dt()
     sim.integrate(0)
