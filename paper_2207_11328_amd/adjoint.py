@@ -123,7 +123,9 @@ class AdjointRollout:
             self.sim.raise_on_status(self.sim.status_dict(row))
 
     def _advance(self, store=None):
-        """One predictor/corrector step on the current lists (no rebuild)."""
+        """One predictor/corrector step on the current lists (no rebuild),
+        the corrector as the simulation's step takes it (one fused call for
+        one scene, bit for bit the separate calls)."""
         s = self.sim
         if store is not None:
             store.append([s.pos.clone(), s.vel.clone(), None, None])
@@ -132,8 +134,7 @@ class AdjointRollout:
         if store is not None:
             store[-1][2] = s.pos_star.clone()
             store[-1][3] = s.vel_star.clone()
-        s.forces(True)
-        s.integrate(1)
+        s.corrector_half()
 
     def reset(self, vel0=None, alpha=None, c0=None):
         """Back to the initial state, optionally with new initial velocities

@@ -178,7 +178,9 @@ class Simulation:
         abi.sph_forces_corrector(self.g, self.p, self.parts_star, self.neibs, self.neib_count, self.max_neibs,
                                  self.d_dt, self.parts, self.ws_forces, self.d_time, forces, stream, cs, ce, nb)
 
-    def _second_half(self, stream=None):
+    def corrector_half(self, stream=None):
+        """The derivatives of state * and the corrector stage: one call
+        (corrector) for one scene, else the two separate calls."""
         if self.fuse_corrector:
             self.corrector(stream)
         else:
@@ -233,7 +235,7 @@ class Simulation:
         if self.dt_fixed is None:
             self.step_dt(stream)
         self.integrate(0, stream)
-        self._second_half(stream)
+        self.corrector_half(stream)
         self.steps_done += 1
 
     def run(self, steps: int, stream=None):
@@ -261,7 +263,7 @@ class Simulation:
                     if self.dt_fixed is None:
                         self.step_dt()
                     self.integrate(0)
-                    self._second_half()
+                    self.corrector_half()
         torch.cuda.current_stream(self.device).wait_stream(side)
         self.graph = graph
         return graph
