@@ -17,6 +17,28 @@ struct BackConst {
     int landrini;  // aux holds (P, c, c^2, dc/drho) instead of (P/rho^2, c, d(P/rho^2)/drho, dc/drho)
 };
 
+// Equation-of-state terms of the adjoint for gamma = 7 in the expanded Cole
+// form: (P/rho^2, c, d(P/rho^2)/drho, dc/drho), or (P, c, dP/drho = c^2,
+// dc/drho) for the Landrini-Morris formulation.  One definition for the
+// gather form's prologue and the brick form's staging.
+__device__ __forceinline__ float4 eos_grad_terms(float rho, const BackConst &C)
+{
+    const float d = (rho - C.rho0) * C.inv_rho0;
+    float poly = 7.0f + d;
+    poly = fmaf(poly, d, 21.0f);
+    poly = fmaf(poly, d, 35.0f);
+    poly = fmaf(poly, d, 35.0f);
+    poly = fmaf(poly, d, 21.0f);
+    poly = fmaf(poly, d, 7.0f);
+    const float P = C.B * d * poly;
+    const float inv_rho = 1.0f / rho;
+    const float a = 1.0f + d;
+    const float c = C.c0 * a * a * a;
+    const float p = P * inv_rho * inv_rho;
+    if (C.landrini) return make_float4(P, c, c * c, 3.0f * c * inv_rho);
+    return make_float4(p, c, (c * c * inv_rho - 2.0f * P * inv_rho * inv_rho) * inv_rho, 3.0f * c * inv_rho);
+}
+
 struct BackArgs {
     const sph_grid *grid;
     int shape, n;

@@ -7,6 +7,8 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
+
 #include "backward_common.h"
 
 using namespace sph;
@@ -15,47 +17,24 @@ namespace {
 
 constexpr int kThreads = 256;
 
-// aux = (P/rho^2, c, d(P/rho^2)/drho, dc/drho) for gamma = 7, or
-// (P, c, dP/drho = c^2, dc/drho) for the Landrini-Morris formulation
-// Also (brick form, when the call overwrites): writes the (zero) adjoint of
-// particles with an empty list, dropped ones included (grad_pos.w is kept);
-// only the bricks with a pair are staged.  And (brick form) clears what the
-// brick kernel counts and sums into: its two counters (next) and the nbp
-// per-brick parameter partials.
+// Gather form: the equation-of-state terms of every particle, aux =
+// eos_grad_terms(rho).  (The brick form evaluates them as it stages
+// particles.)
 __global__ __launch_bounds__(kThreads) void k_eos_grad(int n, const float4 *__restrict__ vel,
-                                                       float4 *__restrict__ aux, BackConst C,
-                                                       const uint32_t *__restrict__ count,
-                                                       float4 *__restrict__ gpos, float4 *__restrict__ gvel,
-                                                       int32_t *__restrict__ next, double *__restrict__ bpartial,
-                                                       int nbp)
+                                                       float4 *__restrict__ aux, BackConst C)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
-    if (next) {
-        for (int k = i; k < nbp; k += gridDim.x * kThreads) bpartial[k] = 0.0;
-        if (i < 2) next[i] = 0;
-    }
-    if (i >= n) return;
-    if (gpos && count[i] == 0u) {
-        gpos[i] = make_float4(0.0f, 0.0f, 0.0f, gpos[i].w);
-        gvel[i] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    }
-    const float rho = vel[i].w;
-    const float d = (rho - C.rho0) * C.inv_rho0;
-    float poly = 7.0f + d;
-    poly = fmaf(poly, d, 21.0f);
-    poly = fmaf(poly, d, 35.0f);
-    poly = fmaf(poly, d, 35.0f);
-    poly = fmaf(poly, d, 21.0f);
-    poly = fmaf(poly, d, 7.0f);
-    const float P = C.B * d * poly;
-    const float inv_rho = 1.0f / rho;
-    const float a = 1.0f + d;
-    const float c = C.c0 * a * a * a;
-    const float p = P * inv_rho * inv_rho;
-    if (C.landrini)
-        aux[i] = make_float4(P, c, c * c, 3.0f * c * inv_rho);
-    else
-        aux[i] = make_float4(p, c, (c * c * inv_rho - 2.0f * P * inv_rho * inv_rho) * inv_rho, 3.0f * c * inv_rho);
+    if (i < n) aux[i] = eos_grad_terms(vel[i].w, C);
+}
+
+// Brick form: clears what the brick kernel counts and sums into, its two
+// counters (next) and the nbp per-brick parameter partials.
+__global__ __launch_bounds__(kThreads) void k_back_clear(int32_t *__restrict__ next, double *__restrict__ bpartial,
+                                                         int nbp)
+{
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    for (int k = i; k < nbp; k += gridDim.x * kThreads) bpartial[k] = 0.0;
+    if (i < 2) next[i] = 0;
 }
 
 // Sum of the per-block (or per-brick) parameter partials in a fixed order:
@@ -161,10 +140,13 @@ extern "C" sph_status sph_forces_backward(const sph_grid *grid, const sph_params
             const BrickGrid G = brick_grid<BX, BY, BZ>(grid->ncell, grid->periodic);
             n_bricks = G.nbx * G.nby * G.nbz;
         });
-        k_eos_grad<<<nblocks, kThreads, 0, s>>>(n, (const float4 *)parts->vel, aux, C, neib_count,
-                                                bricks && !accumulate ? (float4 *)grad_pos : nullptr,
-                                                (float4 *)grad_vel, bricks ? next : nullptr, bpartial,
-                                                bricks ? 3 * n_bricks : 0);
+        if (bricks) {
+            const int nbp = 3 * n_bricks;
+            const unsigned cb = (unsigned)std::min(std::max((nbp + kThreads - 1) / kThreads, 1), 256);
+            k_back_clear<<<cb, kThreads, 0, s>>>(next, bpartial, nbp);
+        } else {
+            k_eos_grad<<<nblocks, kThreads, 0, s>>>(n, (const float4 *)parts->vel, aux, C);
+        }
         BackArgs a;
         a.grid = grid;
         a.shape = shape;

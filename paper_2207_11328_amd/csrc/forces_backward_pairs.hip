@@ -391,7 +391,7 @@ __device__ __forceinline__ void add_partner(BackAcc &A)
 
 template <int MODEL, int BX, int BY, int BZ, int NT, int CAP>
 __global__ __launch_bounds__(NT) void k_forces_backward_brick(
-    int n, const float4 *__restrict__ pos, const float4 *__restrict__ vel, const float4 *__restrict__ aux,
+    int n, const float4 *__restrict__ pos, const float4 *__restrict__ vel,
     const float4 *__restrict__ gforce, const uint32_t *__restrict__ neibs, const uint16_t *__restrict__ neibs_brick,
     const uint32_t *__restrict__ count, const int32_t *__restrict__ cell_start, const int32_t *__restrict__ cell_end,
     const int32_t *__restrict__ table, int cap_ids, int32_t *__restrict__ next,
@@ -507,11 +507,9 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
                     for (int m = 0; m < SX - 1; ++m) e[k][m] = cBase[rr * SX + 1 + m];
                 }
                 const int L = off[RPW];
-                const float2 *aux2 = (const float2 *)aux;
                 for (int tb = 0; tb < L; tb += SB * kWave) {
                     int slot[SB], cc[SB], rw[SB];
                     float4 p[SB], v[SB], g[SB];
-                    float2 x[SB];
                     bool bnd[SB];
 #pragma unroll
                     for (int u = 0; u < SB; ++u) {
@@ -540,7 +538,6 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
                         const int j = t < L ? s2 - cDelta[r * SX + c] : 0;
                         p[u] = pos[j];
                         v[u] = vel[j];
-                        x[u] = aux2[2 * (size_t)j];
                         g[u] = gforce[j];
                         // mass negated for boundary particles when the diffusion needs the type
                         bnd[u] = (MODEL & kDiffusion) ? ptype(info[j]) == kBoundary : false;
@@ -554,7 +551,9 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
                             sP[l] = make_float4(fmaf(sx, C.csx, p[u].x), fmaf(sy, C.csy, p[u].y),
                                                 fmaf(sz, C.csz, p[u].z), bnd[u] ? -p[u].w : p[u].w);
                             sV[l] = v[u];
-                            sX[l] = x[u];
+                            // equation-of-state terms (P/rho^2 or P, c) from the staged density
+                            const float4 x = eos_grad_terms(v[u].w, C);
+                            sX[l] = make_float2(x.x, x.y);
                             sG[l] = g[u];
                         }
                     }
@@ -585,29 +584,31 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
                 const int ntw = __builtin_amdgcn_readfirstlane(wave_max(nt));
                 BackAcc A = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
                 if (ntw > 0) {
-                    const float4 xi = aux[i];
                     if (use_lds) {
                         const int si = i + cDelta[St::inner(u)] - s_lo;
                         const uint4 *lg = (const uint4 *)(neibs_brick + brick_entry(i, 0, groups));
-                        brick_adjoint_lds<MODEL>(A, lg, h, nt, ntw, s_lo, span, sP, sV, sX, sG, sP[si], sV[si], xi,
-                                                sG[si], C);
+                        const float4 vi = sV[si];
+                        brick_adjoint_lds<MODEL>(A, lg, h, nt, ntw, s_lo, span, sP, sV, sX, sG, sP[si], vi,
+                                                eos_grad_terms(vi.w, C), sG[si], C);
                     } else {
                         // the lane pair splits the list by parity of the entry
                         const uint32_t *tile = neibs + (size_t)(i / kWave) * (kWave * M) + (i % kWave);
                         const float4 pi = pos[i], vi = vel[i], gi = gforce[i];
+                        const float4 xi = eos_grad_terms(vi.w, C);
                         const bool central_fluid = (MODEL & kDiffusion) ? ptype(info[i]) != kBoundary : true;
                         const int last = max(nt - 1, 0);
                         for (int k = h; k < ntw; k += 2) {
                             const uint32_t e = tile[list_slot(k, nf, last, M) * kWave];
                             const uint32_t j = min(e & kIndexMask, jmax);
-                            pair_adjoint<MODEL>(A, e, pi, vi, xi, gi, pos[j], vel[j], aux[j], gforce[j], k < nt,
-                                               central_fluid && k < nf, C);
+                            const float4 vj = vel[j];
+                            pair_adjoint<MODEL>(A, e, pi, vi, xi, gi, pos[j], vj, eos_grad_terms(vj.w, C),
+                                               gforce[j], k < nt, central_fluid && k < nf, C);
                         }
                     }
                 }
                 add_partner(A);
                 const bool own = act && h == 0 && nt > 0;
-                // (a particle with an empty list was written by the prologue)
+                // (a particle with an empty list is written after the last brick)
                 if (own) store_adjoint(i, nt, A, gpos, gvel, accumulate);
                 // parameter sums: per wave and group of centrals, in double,
                 // added to the wave's LDS slot in a fixed order (no per-lane
@@ -631,6 +632,16 @@ __global__ __launch_bounds__(NT) void k_forces_backward_brick(
         }
         __syncthreads();  // the next brick reuses the LDS
     }
+    // Particles with an empty list (none of their bricks' pairs; also those
+    // the build dropped) get a zero adjoint when the call overwrites
+    // (grad_pos.w is kept), by all workgroups as they run out of bricks: no
+    // other lane writes them.
+    if (!accumulate)
+        for (int k = blockIdx.x * NT + threadIdx.x; k < n; k += gridDim.x * NT)
+            if (count[k] == 0u) {
+                gpos[k] = make_float4(0.0f, 0.0f, 0.0f, gpos[k].w);
+                gvel[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            }
     // The last workgroup to finish sums the partials of every brick of the
     // grid (bricks without a pair hold the zero written before the launch)
     // in a fixed order: each workgroup makes its partials visible device-wide
@@ -659,11 +670,11 @@ void launch_backward_brick(const BackArgs &a, const BackConst &C, hipStream_t s,
         const unsigned blocks = (unsigned)G.nbx * G.nby * G.nbz;
         n_bricks = (int)blocks;
         // (the brick counters and the per-brick parameter partials were
-        // cleared by the equation-of-state pass before the launch; the table
-        // of bricks with a pair is the build's)
+        // cleared before the launch; the table of bricks with a pair is the
+        // build's)
         const unsigned wgs = blocks < (unsigned)sph_device_cus() ? blocks : (unsigned)sph_device_cus();
         k_forces_backward_brick<MODEL, BX, BY, BZ, kBackBrickThreads, kBackBrickCap>
-            <<<wgs, kBackBrickThreads, 0, s>>>(a.n, a.pos, a.vel, a.aux, a.gforce, a.neibs, a.neibs_brick,
+            <<<wgs, kBackBrickThreads, 0, s>>>(a.n, a.pos, a.vel, a.gforce, a.neibs, a.neibs_brick,
                                               a.count, a.cell_start, a.cell_end, a.table, a.cap_ids, a.next, a.info,
                                               a.gpos,
                                               a.gvel, a.partial, a.grad_params, a.accumulate, C, G);
