@@ -31,7 +31,7 @@ __device__ __forceinline__ float4 eos_grad_terms(float rho, const BackConst &C)
     poly = fmaf(poly, d, 21.0f);
     poly = fmaf(poly, d, 7.0f);
     const float P = C.B * d * poly;
-    const float inv_rho = 1.0f / rho;
+    const float inv_rho = __builtin_amdgcn_rcpf(rho);  // (hardware reciprocal, 1 ulp; no division sequence)
     const float a = 1.0f + d;
     const float c = C.c0 * a * a * a;
     const float p = P * inv_rho * inv_rho;

@@ -41,7 +41,7 @@ __device__ __forceinline__ float2 eos_terms(float rho, float alpha_h, const Forc
     poly = fmaf(poly, d, 21.0f);
     poly = fmaf(poly, d, 7.0f);
     const float P = C.B * d * poly;
-    const float inv_rho = 1.0f / rho;
+    const float inv_rho = __builtin_amdgcn_rcpf(rho);  // (hardware reciprocal, 1 ulp; no division sequence)
     const float a = 1.0f + d;
     return make_float2(C.landrini ? P : P * inv_rho * inv_rho, 0.5f * alpha_h * (C.c0 * a * a * a));
 }
