@@ -86,9 +86,12 @@ __device__ __forceinline__ void pair_adjoint_core(BackAcc &G, float xx, float xy
     const float ux = vi.x - vj.x, uy = vi.y - vj.y, uz = vi.z - vj.z;
     const float w = fmaf(ux, xx, fmaf(uy, xy, uz * xz));
     const float rs = vi.w + vj.w;
-    const float inv_rs = __builtin_amdgcn_rcpf(rs);
     const float dd = r2 + C.eps_h2;
-    const float inv_d = __builtin_amdgcn_rcpf(dd);
+    // 1/rs and 1/d from one reciprocal (a quarter-rate operation) of their
+    // product (rs d >= 2 rho eps h^2, far from the float range's ends)
+    const float inv_rsd = __builtin_amdgcn_rcpf(rs * dd);
+    const float inv_rs = dd * inv_rsd;
+    const float inv_d = rs * inv_rsd;
     const float csum = xi.y + xj.y;
     // Pi = -alpha h min(w, 0)/d (c_i + c_j)/rs = A B with A = -alpha h min(w, 0)/d
     // (zero for w >= 0, and so are Pi and its rho_i derivative) and B = csum/rs
