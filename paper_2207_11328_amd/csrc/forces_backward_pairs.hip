@@ -102,10 +102,17 @@ __device__ __forceinline__ void pair_adjoint_core(BackAcc &G, float xx, float xy
     const float actK = w < 0.0f ? -C.alpha_h * B : 0.0f;
     // dPi/drho_i = A (dc_i/drho_i - B)/rs
     const float dPi_dri = A * (xi.w - B) * inv_rs;
+    // 1/(rho_i rho_j), 1/rho_i and 1/rho_j from one reciprocal (Landrini-Morris;
+    // the density diffusion alone takes them in its branch)
+    [[maybe_unused]] float inv_rr = 0.0f, iri = 0.0f, irj = 0.0f;
+    if constexpr (MODEL & kLandrini) {
+        inv_rr = __builtin_amdgcn_rcpf(vi.w * vj.w);
+        iri = vj.w * inv_rr;
+        irj = vi.w * inv_rr;
+    }
     // pressure factor S_p and dS_p/drho_i
     float Sp, dSp;
     if constexpr (MODEL & kLandrini) {
-        const float inv_rr = __builtin_amdgcn_rcpf(vi.w * vj.w);
         Sp = (xi.x + xj.x) * inv_rr;
         dSp = (xi.z - Sp * vj.w) * inv_rr;  // (c_i^2 - S_p rho_j)/(rho_i rho_j)
     } else {
@@ -121,8 +128,8 @@ __device__ __forceinline__ void pair_adjoint_core(BackAcc &G, float xx, float xy
     float sD;
     [[maybe_unused]] float inv_ri = 0.0f, inv_rj = 0.0f, wj = 0.0f;
     if constexpr (MODEL & kLandrini) {
-        inv_ri = __builtin_amdgcn_rcpf(vi.w);
-        inv_rj = __builtin_amdgcn_rcpf(vj.w);
+        inv_ri = iri;
+        inv_rj = irj;
         wj = vj.w * inv_ri;
         sD = fmaf(mj * gi.w, vi.w * inv_rj, mi * gj.w * wj);
     } else {
@@ -167,7 +174,11 @@ __device__ __forceinline__ void pair_adjoint_core(BackAcc &G, float xx, float xy
         //   drho_i += c Gd (dbar_i m_j/rho_j - dbar_j m_i rho_j/rho_i^2)
         //   dc0    += dbar_i term_ij / c0   (central role)
         if (pair_fluid) {
-            const float irj = __builtin_amdgcn_rcpf(vj.w), iri = __builtin_amdgcn_rcpf(vi.w);
+            if constexpr (!(MODEL & kLandrini)) {
+                inv_rr = __builtin_amdgcn_rcpf(vi.w * vj.w);
+                iri = vj.w * inv_rr;
+                irj = vi.w * inv_rr;
+            }
             const float Gd = F * r2 * inv_d;
             const float Gd_r = Fp_r * r2 * inv_d + 2.0f * F * C.eps_h2 * inv_d * inv_d;
             const float w1 = gi.w * mj * irj, w2 = gj.w * mi * iri;

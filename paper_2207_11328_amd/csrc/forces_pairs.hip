@@ -81,17 +81,20 @@ __device__ __forceinline__ void pair_core(PairAcc &A, float xx, float xy, float 
         A.dr = (LDS || inter) ? fmaf(mF, udx, A.dr) : A.dr;
     }
     // Monaghan: Pi = -alpha h (c_i + c_j)/2 min(u.x, 0) / ((rho_i + rho_j)/2 (r^2 + eps h^2))
-    const float den = (vi.w + vj.w) * (r2 + C.eps_h2);
+    const float d2 = r2 + C.eps_h2;
+    const float den = (vi.w + vj.w) * d2;
     float vnum = -(ai.y + aj.y) * (udx - fabsf(udx));
     // laminar K form: + 4 K nu m_j F (u.x) / ((rho_i + rho_j)(r^2 + eps h^2)) x, the same denominator
     if constexpr (model_visc(MODEL) == kMonaghanK) vnum = fmaf(-C.k_four_nu, udx, vnum);
-    const float visc = vnum * __builtin_amdgcn_rcpf(den);
+    const float inv_den = __builtin_amdgcn_rcpf(den);
+    const float visc = vnum * inv_den;
     const float coef = (LDS || inter) ? -mF * (pres + visc) : 0.0f;
     A.ax = fmaf(coef, xx, A.ax);
     A.ay = fmaf(coef, xy, A.ay);
     A.az = fmaf(coef, xz, A.az);
     if constexpr (model_visc(MODEL) == kMorris) {
-        const float lam = (LDS || inter) ? C.four_nu * mF * __builtin_amdgcn_rcpf(vi.w + vj.w) : 0.0f;
+        // 1/(rho_i + rho_j) = (r^2 + eps h^2)/den: no second reciprocal
+        const float lam = (LDS || inter) ? C.four_nu * mF * (d2 * inv_den) : 0.0f;
         A.ax = fmaf(lam, ux, A.ax);
         A.ay = fmaf(lam, uy, A.ay);
         A.az = fmaf(lam, uz, A.az);
