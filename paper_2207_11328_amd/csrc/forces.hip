@@ -1,14 +1,15 @@
 // Time derivatives of the WCSPH step ("forces"), entry points: argument
-// checks, the equation-of-state prologue, and the dispatch to the pair
-// kernels of the model (arXiv:2207.11328, eq. mass-cont-sph1, eq. ns-sph1,
+// checks, the equation-of-state prologue of the gather form, and the
+// dispatch to the pair kernels of the model (arXiv:2207.11328, eq. mass-cont-sph1, eq. ns-sph1,
 // eq. mass-cont-sph2, eq. ns-sph2, section "Minimizing complexity", listing
 // l:ktemplate).  The pair loops live in forces_pairs.hip, one object per
 // smoothing kernel.
 //
-// The prologue evaluates the equation of state once per particle (P/rho^2,
-// or P for the Landrini-Morris formulation, and alpha h c), so the pair loop
-// gathers 8 bytes instead of recomputing a 6th-order polynomial and a
-// reciprocal per pair.
+// The gather form's prologue evaluates the equation of state once per
+// particle (P/rho^2, or P for the Landrini-Morris formulation, and alpha h
+// c), so its pair loop gathers 8 bytes instead of recomputing a 6th-order
+// polynomial and a reciprocal per pair; the brick form evaluates the same
+// terms as it stages particles in LDS.
 #include <hip/hip_runtime.h>
 #include <math.h>
 

@@ -1,5 +1,6 @@
 // Adjoint of the derivative sums (sph_forces) with the neighbour lists held
-// fixed, entry points: argument checks, the equation-of-state prologue, the
+// fixed, entry points: argument checks, the equation-of-state prologue of the
+// gather form (the brick form takes the terms at staging), the
 // dispatch to the pair kernels of the model (forces_backward_pairs.hip, one
 // object per smoothing kernel), the fixed-order reduction of the parameter
 // derivatives, and the permutation helper used to carry adjoints across a

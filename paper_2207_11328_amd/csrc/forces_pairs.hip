@@ -693,8 +693,8 @@ bool sph::SPH_PAIRS_FN(SPH_KERNEL_KIND)(int model, const ForceArgs &a, const For
     return with_model<SPH_KERNEL_KIND>(model & kModelLowBits, [&]<int M>() {
         if (a.bricks) {
             // cell ranges and brick-local lists of the last build: LDS cell-brick
-            // kernel (it writes the derivatives of every particle that lies in a
-            // cell; particles dropped by the build were zeroed by the prologue)
+            // kernel (it writes the derivatives of every particle, those with an
+            // empty list and those dropped by the build after its last brick)
             launch_brick<M>(a, C, s);
         } else {
             k_forces<M><<<sph_blocks(a.n, kThreads), kThreads, 0, s>>>(a.n, a.pos, a.vel, a.aux, a.neibs, a.count,

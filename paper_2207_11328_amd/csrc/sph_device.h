@@ -244,11 +244,11 @@ __device__ __forceinline__ int block_scan(int v, int &total, int *wsum)
 
 // List the bricks that hold at least one particle (order is irrelevant: each
 // brick writes only its own particles).  active[0] must be zero on entry.
-// With cell_flags (one byte per cell, set by the call's prologue for every
-// cell that holds a particle with a non-empty list), a brick is listed only if
-// one of its inner cells is flagged: the outputs of particles with empty lists
-// were written by the prologue, so a brick of such particles (a wall away
-// from the fluid) needs no staging.  The flags of the brick's inner cells are
+// With cell_flags (one byte per cell, set by the list build for every cell
+// that holds a particle with a non-empty list), a brick is listed only if one
+// of its inner cells is flagged: the kernels that take the list write the
+// outputs of particles with empty lists without staging, so a brick of such
+// particles (a wall away from the fluid) needs none.  The flags of the brick's inner cells are
 // cleared for the next call; a stale flag only lists a brick that then finds
 // no pair.
 // With light (a second counter, zero on entry), bricks with fewer than
