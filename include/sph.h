@@ -381,6 +381,23 @@ sph_status sph_forces_corrector(const sph_grid *grid, const sph_params *params, 
                                 double *d_time, float *forces, void *workspace, size_t workspace_bytes,
                                 void *stream);
 
+/* sph_forces_corrector with a step per scene (scenes sharing one grid, see
+ * sph_step_dt_scenes): a particle advances with d_dt[s] of its cell's scene
+ * s (d_dt: device double[n_scenes]) and d_time[s] (device double[n_scenes],
+ * or NULL) advances by d_dt[s]; a particle in a cell of no scene is left
+ * as it is.  Bit for bit sph_forces followed by sph_integrate_scenes(stage
+ * 1).  cell_scene, n_scenes: as for sph_integrate_scenes.  Errors: those of
+ * sph_forces_corrector, and SPH_ERR_ARG for a missing scene table or
+ * n_scenes outside [1, SPH_MAX_SCENES]. */
+sph_status sph_forces_corrector_scenes(const sph_grid *grid, const sph_params *params,
+                                       const sph_particles *star, const uint32_t *neibs,
+                                       const uint32_t *neib_count, int32_t max_neibs,
+                                       const int32_t *cell_start, const int32_t *cell_end,
+                                       const uint16_t *neibs_brick, const double *d_dt,
+                                       const int32_t *cell_scene, int32_t n_scenes, sph_particles *state_n,
+                                       double *d_time, float *forces, void *workspace, size_t workspace_bytes,
+                                       void *stream);
+
 /* Reverse of sph_integrate (the transpose of its linear update; dt is held
  * fixed).  All grad arrays are device float[capacity][4] laid out like the
  * state: grad_pos xyz = dL/d(offset), grad_vel xyz = dL/du, w = dL/drho;

@@ -31,7 +31,7 @@ EXPORTS = [
     "sph_forces_backward_workspace_bytes", "sph_forces_backward", "sph_unpermute",
     "sph_diagnostics_workspace_bytes", "sph_reduce_diagnostics", "sph_count_missed_pairs",
     "sph_forces_noalloc", "sph_dt_scenes_workspace_bytes", "sph_step_dt_scenes", "sph_integrate_scenes",
-    "sph_stream_copy", "sph_forces_corrector",
+    "sph_stream_copy", "sph_forces_corrector", "sph_forces_corrector_scenes",
 ]
 MAX_SCENES = 1 << 20
 
@@ -91,6 +91,8 @@ def _load():
     L.sph_forces.restype = st
     L.sph_forces_corrector.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, P, P, P, C.c_size_t, P]
     L.sph_forces_corrector.restype = st
+    L.sph_forces_corrector_scenes.argtypes = [P, P, P, P, P, i32, P, P, P, P, P, i32, P, P, P, P, C.c_size_t, P]
+    L.sph_forces_corrector_scenes.restype = st
     L.sph_integrate.argtypes = [P, i32, P, P, P, P, P, P, P]
     L.sph_integrate.restype = st
     L.sph_dt_workspace_bytes.argtypes = []
@@ -239,6 +241,18 @@ def sph_forces_corrector(grid: SphGrid, params: SphParams, star: SphParticles, n
                                    C.byref(state_n), ptr(d_time), ptr(forces), ptr(workspace),
                                    workspace.numel() * workspace.element_size(), stream_ptr(stream)),
           "sph_forces_corrector")
+
+
+def sph_forces_corrector_scenes(grid: SphGrid, params: SphParams, star: SphParticles, neibs, neib_count,
+                                max_neibs: int, d_dt, cell_scene, n_scenes: int, state_n: SphParticles, workspace,
+                                d_time=None, forces=None, stream=None, cell_start=None, cell_end=None,
+                                neibs_brick=None):
+    check(lib.sph_forces_corrector_scenes(C.byref(grid), C.byref(params), C.byref(star), ptr(neibs),
+                                          ptr(neib_count), int(max_neibs), ptr(cell_start), ptr(cell_end),
+                                          ptr(neibs_brick), ptr(d_dt), ptr(cell_scene), int(n_scenes),
+                                          C.byref(state_n), ptr(d_time), ptr(forces), ptr(workspace),
+                                          workspace.numel() * workspace.element_size(), stream_ptr(stream)),
+          "sph_forces_corrector_scenes")
 
 
 def sph_forces_noalloc(grid: SphGrid, params: SphParams, parts: SphParticles, neibs, neib_count, max_neibs: int,

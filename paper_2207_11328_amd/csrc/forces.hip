@@ -74,7 +74,11 @@ __global__ __launch_bounds__(kThreads) void k_count_interactions(int n, const fl
 
 __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
 
-__global__ void k_add_time(double *d_time, const double *d_dt) { *d_time += *d_dt; }
+// the clocks advance by their steps (one per scene)
+__global__ void k_add_time(double *d_time, const double *d_dt, int n_clocks)
+{
+    for (int k = threadIdx.x; k < n_clocks; k += blockDim.x) d_time[k] += d_dt[k];
+}
 
 // missed pairs of a rebuild: the difference of the two counts, and its running total
 __global__ void k_missed_finish(long long *m)
@@ -181,7 +185,8 @@ sph_status forces_impl(const sph_grid *grid, const sph_params *params, const sph
     hipStream_t s = (hipStream_t)stream;
     if (n == 0) {
         // the corrector's clock still advances, as the separate stage's does
-        if (K.d_dt && K.d_time) k_add_time<<<1, 1, 0, s>>>(K.d_time, K.d_dt);
+        if (K.d_dt && K.d_time)
+            k_add_time<<<1, 256, 0, s>>>(K.d_time, K.d_dt, K.cell_scene ? K.n_scenes : 1);
         SPH_CHECK_LAUNCH();
         return SPH_OK;
     }
@@ -254,7 +259,7 @@ extern "C" sph_status sph_forces_corrector(const sph_grid *grid, const sph_param
         // particles: the two must not share storage
         if (state_n->pos == star->pos || state_n->vel == star->vel) return SPH_ERR_ARG;
     }
-    Corrector K;
+    Corrector K = {};
     K.d_dt = d_dt;
     K.pos = (float4 *)state_n->pos;
     K.vel = (float4 *)state_n->vel;
@@ -264,6 +269,39 @@ extern "C" sph_status sph_forces_corrector(const sph_grid *grid, const sph_param
     K.gx = params ? params->g[0] : 0.0f;
     K.gy = params ? params->g[1] : 0.0f;
     K.gz = params ? params->g[2] : 0.0f;
+    return forces_impl(grid, params, star, neibs, neib_count, max_neibs, cell_start, cell_end, neibs_brick, forces,
+                       workspace, workspace_bytes, stream, K);
+}
+
+extern "C" sph_status sph_forces_corrector_scenes(const sph_grid *grid, const sph_params *params,
+                                                  const sph_particles *star, const uint32_t *neibs,
+                                                  const uint32_t *neib_count, int32_t max_neibs,
+                                                  const int32_t *cell_start, const int32_t *cell_end,
+                                                  const uint16_t *neibs_brick, const double *d_dt,
+                                                  const int32_t *cell_scene, int32_t n_scenes,
+                                                  sph_particles *state_n, double *d_time, float *forces,
+                                                  void *workspace, size_t workspace_bytes, void *stream)
+{
+    if (!star || !state_n || !d_dt || !grid || !cell_scene || n_scenes < 1 || n_scenes > SPH_MAX_SCENES)
+        return SPH_ERR_ARG;
+    if (state_n->n != star->n || state_n->capacity < star->n) return SPH_ERR_ARG;
+    if (star->n > 0) {
+        if (!state_n->pos || !state_n->vel || !state_n->cell || !state_n->info) return SPH_ERR_ARG;
+        if (state_n->pos == star->pos || state_n->vel == star->vel) return SPH_ERR_ARG;
+    }
+    Corrector K = {};
+    K.d_dt = d_dt;
+    K.pos = (float4 *)state_n->pos;
+    K.vel = (float4 *)state_n->vel;
+    K.cell = state_n->cell;
+    K.info = state_n->info;
+    K.d_time = d_time;
+    K.gx = params ? params->g[0] : 0.0f;
+    K.gy = params ? params->g[1] : 0.0f;
+    K.gz = params ? params->g[2] : 0.0f;
+    K.cell_scene = cell_scene;
+    K.cell_base = grid->cell_base;
+    K.n_scenes = n_scenes;
     return forces_impl(grid, params, star, neibs, neib_count, max_neibs, cell_start, cell_end, neibs_brick, forces,
                        workspace, workspace_bytes, stream, K);
 }

@@ -54,28 +54,56 @@ __device__ __forceinline__ float alpha_h_of(int j, const int32_t *__restrict__ c
 }
 
 // The corrector stage taken inside the derivative kernel
-// (sph_forces_corrector): as the derivatives f of a particle of state * are
-// finished, its state n is advanced in place by dt (midpoint_stage with the
-// stage velocity u*).  d_dt == nullptr: derivatives only.
+// (sph_forces_corrector, sph_forces_corrector_scenes): as the derivatives f
+// of a particle of state * are finished, its state n is advanced in place by
+// dt (midpoint_stage with the stage velocity u*).  d_dt == nullptr:
+// derivatives only.  With cell_scene, d_dt and d_time hold one step and one
+// clock per scene and a particle takes its cell's scene's step.
 struct Corrector {
     const double *d_dt;
     float4 *pos, *vel;  // state n, overwritten by state n+1
     const int32_t *cell;
     const uint32_t *info;
-    double *d_time;     // advanced by dt once per call, or null
+    double *d_time;     // advanced by dt once per call (per scene), or null
     float gx, gy, gz;
+    const int32_t *cell_scene;  // scene of each cell (index cell - cell_base), or null
+    int cell_base, n_scenes;
 };
 
 // The update of particle i, which lies in a cell (a particle the build
 // dropped, cell < 0, is never passed here: it stays as it is); tau = (float)
-// dt, read once per kernel.  Its loads do not wait on one another.
-__device__ __forceinline__ void corrector_at(int i, const float4 &f, const float4 &ustar, float tau,
-                                             const Corrector &K)
+// dt, read once per kernel for one scene; with scenes the step of the
+// particle's scene (a cell of no scene: the particle stays as it is).  Its
+// loads do not wait on one another except for the scene's step.
+__device__ __forceinline__ void corrector_apply(int i, const float4 &f, const float4 &ustar, float tau,
+                                                const Corrector &K)
 {
     float4 p = K.pos[i], v = K.vel[i];
     midpoint_stage(p, v, ustar, f, ptype(K.info[i]) == kBoundary, tau, K.gx, K.gy, K.gz);
     K.pos[i] = p;
     K.vel[i] = v;
+}
+
+__device__ __forceinline__ void corrector_at(int i, const float4 &f, const float4 &ustar, float tau,
+                                             const Corrector &K)
+{
+    if (K.cell_scene) {
+        const int sc = K.cell_scene[K.cell[i] - K.cell_base];
+        if ((unsigned)sc >= (unsigned)K.n_scenes) return;
+        tau = (float)K.d_dt[sc];
+    }
+    corrector_apply(i, f, ustar, tau, K);
+}
+
+// The clocks the corrector advances: by block 0 at the start of the kernel.
+__device__ __forceinline__ void corrector_clock(const Corrector &K)
+{
+    if (!K.d_dt || !K.d_time || blockIdx.x != 0) return;
+    if (K.cell_scene) {
+        for (int k = threadIdx.x; k < K.n_scenes; k += blockDim.x) K.d_time[k] += K.d_dt[k];
+    } else if (threadIdx.x == 0) {
+        *K.d_time += *K.d_dt;
+    }
 }
 
 struct ForceArgs {

@@ -179,8 +179,8 @@ __global__ __launch_bounds__(kThreads) void k_forces(int n, const float4 *__rest
                                                      float4 *__restrict__ out, ForceConst C, Corrector K)
 {
     const int i = blockIdx.x * kThreads + threadIdx.x;
-    const float tau = K.d_dt ? (float)*K.d_dt : 0.0f;  // (the corrector's step)
-    if (K.d_dt && K.d_time && i == 0) *K.d_time += *K.d_dt;
+    const float tau = K.d_dt && !K.cell_scene ? (float)*K.d_dt : 0.0f;  // (the corrector's step)
+    corrector_clock(K);
     const int lane = threadIdx.x % kWave;
     const int ii = min(i, n - 1);  // lanes past the end load in bounds and store nothing
     const int M = C.max_neibs;
@@ -327,6 +327,9 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     __shared__ int sNext;
     __shared__ int sGroup;  // groups of centrals claimed in the brick, past the first NT / kWave
     __shared__ int sPre[4]; // scan ahead: claimed, next brick's list index, total, centrals
+    // (corrector with a step per scene) each inner cell's scene (-1: none) and step
+    __shared__ int sSc[NI];
+    __shared__ float sTau[NI];
     static_assert(NI <= kWave, "one lane per inner cell in the scan ahead");
 
     // One resident workgroup per CU takes the bricks with a pair one at a time
@@ -335,8 +338,8 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
     // different costs even out across CUs, and the cheap bricks come last,
     // where they fill the gaps.
     const int n_listed = table[0] + table[cap_ids + 1];
-    const float tau = K.d_dt ? (float)*K.d_dt : 0.0f;  // (the corrector's step)
-    if (K.d_dt && K.d_time && blockIdx.x == 0 && threadIdx.x == 0) *K.d_time += *K.d_dt;
+    const float tau = K.d_dt && !K.cell_scene ? (float)*K.d_dt : 0.0f;  // (the corrector's step)
+    corrector_clock(K);
     // cell range (start, count) of staged cell t < S of brick b (count 0 for a
     // cell outside a non-periodic grid edge)
     auto ranges = [&](int b, int t, int &st, int &cnt) {
@@ -480,6 +483,19 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
         }
         __syncthreads();
         const bool use_lds = total <= CAP;
+        if (K.cell_scene && tid < NI) {
+            // the step of each inner cell's scene, for the corrector of its
+            // centrals (read after the staging barrier)
+            int sc = -1;
+            if (inner_in_grid(b, tid)) {
+                const int lin = (cx0 + St::ix_of(tid)) +
+                                G.nx * ((cy0 + St::iy_of(tid)) + G.ny * (cz0 + St::iz_of(tid)));
+                sc = K.cell_scene[lin];
+                if ((unsigned)sc >= (unsigned)K.n_scenes) sc = -1;
+            }
+            sSc[tid] = sc;
+            sTau[tid] = sc >= 0 ? (float)K.d_dt[sc] : 0.0f;
+        }
         // central particle of lane q (binary search over the inner cells)
         auto central = [&](int q, int &u, int &i) {
             int lo = 0, hi = NI - 1;
@@ -631,8 +647,13 @@ __global__ __launch_bounds__(NT) void k_forces_brick(int n, const float4 *__rest
             if (act && h == 0 && nt > 0) {
                 const float4 f = make_float4(A.ax, A.ay, A.az, A.dr);
                 if (out) out[i] = f;
-                // (a central lies in one of the brick's cells)
-                if (K.d_dt) corrector_at(i, f, ustar, tau, K);
+                // (a central lies in one of the brick's cells: inner cell u)
+                if (K.d_dt) {
+                    if (!K.cell_scene)
+                        corrector_apply(i, f, ustar, tau, K);
+                    else if (sSc[u] >= 0)
+                        corrector_apply(i, f, ustar, sTau[u], K);
+                }
             }
             int gn = 0;
             if (tid % kWave == 0) gn = atomicAdd(&sGroup, 1) + NW;

@@ -11,9 +11,10 @@ of a good thing?": lists rebuilt every 10 steps by default):
     sph_forces(state *)      -> forces_*
     sph_integrate(stage 1)   -> state n+1 (in place), t += dt
 
-For one scene the last two calls are one, sph_forces_corrector (the
-corrector's derivatives and update in the same kernel, bit for bit the same
-state n+1; forces_* is then not written).  Nothing is synchronised with the
+The last two calls are one, sph_forces_corrector (the corrector's
+derivatives and update in the same kernel, bit for bit the same state n+1;
+forces_* is then not written), or sph_forces_corrector_scenes with a step
+per scene.  Nothing is synchronised with the
 host inside a step.
 """
 from __future__ import annotations
@@ -112,9 +113,9 @@ class Simulation:
         self.parts_star = abi.particles_struct(n, self.cell, self.pos_star, self.vel_star, self.info)
         self.steps_done = 0
         self._built = False
-        # the corrector's derivatives and update in one kernel (one scene:
-        # the per-scene steps of batched scenes take the separate stage)
-        self.fuse_corrector = self.cell_scene is None
+        # the corrector's derivatives and update in one kernel (with a step
+        # per scene for batched scenes)
+        self.fuse_corrector = True
 
     # ------------------------------------------------------------ primitives
     def build(self, stream=None, perm_out=None, status=None):
@@ -175,8 +176,13 @@ class Simulation:
         bit for bit forces(True) followed by integrate(1).  forces: a
         [capacity, 4] tensor that also receives the derivatives, or None."""
         cs, ce, nb = self.brick_args(bricks)
-        abi.sph_forces_corrector(self.g, self.p, self.parts_star, self.neibs, self.neib_count, self.max_neibs,
-                                 self.d_dt, self.parts, self.ws_forces, self.d_time, forces, stream, cs, ce, nb)
+        if self.cell_scene is not None:
+            abi.sph_forces_corrector_scenes(self.g, self.p, self.parts_star, self.neibs, self.neib_count,
+                                            self.max_neibs, self.d_dt, self.cell_scene, self.n_scenes, self.parts,
+                                            self.ws_forces, self.d_time, forces, stream, cs, ce, nb)
+        else:
+            abi.sph_forces_corrector(self.g, self.p, self.parts_star, self.neibs, self.neib_count, self.max_neibs,
+                                     self.d_dt, self.parts, self.ws_forces, self.d_time, forces, stream, cs, ce, nb)
 
     def corrector_half(self, stream=None):
         """The derivatives of state * and the corrector stage: one call

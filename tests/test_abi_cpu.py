@@ -98,6 +98,8 @@ def test_argument_errors_return_before_any_launch(abi):
                                           None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_forces_corrector(None, None, None, None, None, 128, None, None, None, None, None, None,
                                         None, None, 0, None) == abi.SPH_ERR_ARG
+    assert abi.lib.sph_forces_corrector_scenes(None, None, None, None, None, 128, None, None, None, None, None, 1,
+                                               None, None, None, None, 0, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_unpermute(-1, None, None, None, None) == abi.SPH_ERR_ARG
     assert abi.lib.sph_unpermute(0, None, None, None, None) == abi.SPH_OK
     assert abi.lib.sph_integrate(None, 0, None, None, None, None, None, None, None) == abi.SPH_ERR_ARG

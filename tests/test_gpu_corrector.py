@@ -195,3 +195,75 @@ def test_corrector_rejects_shared_state():
         abi.sph_forces_corrector(sim.g, sim.p, sim.parts, sim.neibs, sim.neib_count, sim.max_neibs, sim.d_dt,
                                  sim.parts, sim.ws_forces, cell_start=sim.cell_start, cell_end=sim.cell_end,
                                  neibs_brick=sim.neibs_brick)
+
+
+def _stacked(cut_scene=None):
+    from paper_2207_11328_amd.sim import Simulation
+    tanks = S.batched_tanks(n_scenes=5, seed=21, n_min=400, n_max=3000)
+    stacked, alpha, subs, ranges = S.stack_scenes(tanks)
+    table = S.scene_cells(stacked)
+    if cut_scene is not None:
+        table = table.copy()
+        table[table == cut_scene] = -1  # that tank's cells: no scene
+
+    def make():
+        return Simulation(stacked.grid, stacked.params, stacked.cell, stacked.pos, stacked.vel, stacked.info,
+                          cell_alpha=alpha, cell_scene=table)
+    return stacked, make
+
+
+@pytest.mark.parametrize("cut", [None, 2], ids=["all_scenes", "a_tank_of_no_scene"])
+def test_corrector_scenes_equals_separate_calls(cut):
+    """Batched tanks, each with its own step: one corrector both ways
+    (sph_forces_corrector_scenes against sph_forces + sph_integrate_scenes),
+    bit for bit, clocks included; a tank whose cells belong to no scene keeps
+    its state."""
+    stacked, make = _stacked(cut)
+    sim = make()
+    sim.build()
+    sim.forces(False)
+    sim.step_dt()
+    sim.integrate(0)
+    torch_sync()
+    dts = sim.d_dt.cpu().numpy()
+    log("per-scene steps %s" % np.array2string(dts, precision=6))
+    sim.d_time.copy_(torch.arange(sim.n_scenes, dtype=torch.float64, device=sim.d_time.device) * 0.5)
+    before = _state(sim)
+    sim.forces(True)
+    sim.integrate(1)
+    torch_sync()
+    sep = _state(sim)
+    _restore(sim, before)
+    sim.corrector()
+    torch_sync()
+    fused = _state(sim)
+    assert all(torch.equal(a, b) for a, b in zip(fused, sep))
+    n = stacked.n
+    assert not torch.equal(fused[1][:n], before[1][:n])
+    if cut is not None:
+        sc = sim.cell_scene[(sim.cell[:n] - sim.g.cell_base).clamp(min=0).long()]
+        alone = (sc < 0) & (sim.cell[:n] >= 0)
+        assert int(alone.sum()) > 0
+        assert torch.equal(fused[0][:n][alone], before[0][:n][alone])
+        assert torch.equal(fused[1][:n][alone], before[1][:n][alone])
+
+
+def test_batched_rollout_fused_equals_separate():
+    """20 steps of batched tanks with per-scene adaptive steps, fused and
+    separate corrector, eagerly and as graph replays: identical bits and
+    clocks."""
+    stacked, make = _stacked()
+    a, b = make(), make()
+    b.fuse_corrector = False
+    a.run(20)
+    b.run(20)
+    torch_sync()
+    assert torch.equal(a.pos, b.pos) and torch.equal(a.vel, b.vel)
+    assert np.array_equal(a.time, b.time)
+    c = make()
+    c.capture_unit()
+    for rep in range(2):
+        c.replay_units(1)
+        torch_sync()
+    assert torch.equal(c.pos, b.pos) and torch.equal(c.vel, b.vel)
+    assert np.array_equal(c.time, b.time)
