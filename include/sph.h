@@ -370,7 +370,8 @@ sph_status sph_integrate(const sph_params *params, int32_t stage, const double *
  * particles in the same order (those of the last build) and must not share
  * pos or vel storage: the kernel reads the staged state of other particles
  * while it rewrites state n.
- * Every other argument is that of sph_forces.  One scene per call (one dt).
+ * Every other argument is that of sph_forces.  One step for every particle
+ * (sph_forces_corrector_scenes takes one per scene).
  * Errors: those of sph_forces; SPH_ERR_ARG for a null d_dt, star or
  * state_n, state_n->n != star->n, missing state_n arrays, or shared
  * pos / vel storage. */
